@@ -1,0 +1,193 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) library for the modified lattice
+ * Boltzmann method of dense dry polar active fluids (Nesbitt, Pruessner & Lee,
+ * arXiv:1902.00530).
+ *
+ * What it computes.  Populations f_i(t, r), i = 0..6, live on a periodic
+ * triangular (D2Q7) lattice of nx x ny sites (section "Dry polar active
+ * fluids").  One step is the algorithm of the appendix "Summary of modified
+ * lattice Boltzmann model algorithm": densities and velocities (eq.
+ * D2Q7macroscopic_u_disc), a target velocity u* (MIPS: eq. bu_mips with the
+ * U_max clamp and the isotropic gradient stencil; CIL: eq. bu_CIL with the
+ * speed law eq. U0; passive: u* = u), BGK relaxation towards the steady
+ * state xi(rho, u*) (eq. fssD2Q7, eq. fevolution2), zero-sum noise (eq.
+ * noiseDensityConservation), the negative-population correction (appendix
+ * "Negative Correction") and streaming.
+ *
+ * Conventions shared by every entry point.
+ *  - Lattice vectors e_i = (cos((i-1) pi/3), sin((i-1) pi/3)), weights
+ *    w_0 = 1/2, w_i = 1/12; opposite pairs 1-4, 2-5, 3-6.
+ *  - Storage is offset rows: site (x, y) sits at (x + (y mod 2)/2, y sqrt(3)/2);
+ *    ny must be even.  Neighbour along e_1: (x+1, y); e_2: (x+p, y+1);
+ *    e_3: (x-1+p, y+1); e_4: (x-1, y); e_5: (x-1+p, y-1); e_6: (x+p, y-1),
+ *    p = y mod 2, all indices periodic.
+ *  - A population buffer is [7][ny][pitch] elements of the storage type
+ *    (plane i, row y, column x), pitch >= nx elements.  The state kept
+ *    between steps is the post-streaming population f*.
+ *  - Noise: raw draws eta~_i = sigma (2 U_i - 1), U_i = (h_i + 1/2)/65536,
+ *    h_i = the i-th 16-bit half (low half first) of Philox4x32-10 with
+ *    key (seed lo, seed hi) and counter (y*nx + x, step lo, step hi, 0);
+ *    eta_i = eta~_i - mean_j eta~_j.  "step" is the absolute step index.
+ *  - Negative correction: a negative rest population is set to 0; an
+ *    opposite pair with a negative member becomes (max(d, 0), max(-d, 0)),
+ *    d = f_i - f_opp (the paper's rule (ii), in closed form); if either rule
+ *    fired, the site is rescaled to this step's density.
+ *
+ * Memory ownership.  The caller owns every device buffer passed in
+ * (population buffers, field outputs, batch buffers, workspaces, network
+ * tensors) and the HIP stream, and keeps them alive until the context that
+ * uses them is destroyed.  A context owns a host object, a small device
+ * scratch for reductions (allocated by lbm_create, freed by lbm_destroy) and
+ * any HIP graphs it captures.
+ *
+ * Errors.  Every entry point returns an int32_t status: LBM_OK (0) or a
+ * negative code.  The message of the last error on the calling thread is
+ * returned by lbm_last_error().  No C++ exception crosses this ABI.  Work is
+ * enqueued on the caller's stream; an entry point only synchronises the
+ * stream where its description says so.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_EINVAL (-1)       /* invalid argument (sizes, parameters, null pointers) */
+#define LBM_EHIP (-2)         /* HIP runtime error; message kept */
+#define LBM_ENONFINITE (-3)   /* a reduction saw a NaN or infinite population */
+#define LBM_EUNSUPPORTED (-4) /* valid request this build does not implement */
+#define LBM_ESTATE (-5)       /* call out of order (e.g. destroyed context) */
+
+/* Models: how u* is computed. */
+#define LBM_PASSIVE 0 /* u* = u: standard BGK lattice Boltzmann */
+#define LBM_MIPS 1    /* u* = C (1 - rho/rho*) grad rho for rho < rho*, |u*| <= U_max */
+#define LBM_CIL 2     /* u* = U0(rho) u/|u|, U0 = B - A rho^2 if B >= A rho^2, else 0 */
+
+/* Population storage. */
+#define LBM_F32 0      /* float32 populations */
+#define LBM_BF16_DEV 1 /* bfloat16 deviations d_i = f_i - w_i rho_ref (round to nearest even) */
+#define LBM_F16_DEV 2  /* IEEE half deviations d_i = f_i - w_i rho_ref (round to nearest even) */
+
+/* Initial states (appendix "CIL Model: General notes"). */
+#define LBM_INIT_NONE 0        /* caller has filled the first buffer */
+#define LBM_INIT_UNIFORM_DIR 1 /* direction uniform on [0, 2 pi), density uniform within +-spread */
+#define LBM_INIT_GAUSS_DIR 2   /* direction normal about +x with std angle_std */
+
+typedef struct lbm_params {
+    int32_t nx, ny;    /* lattice size; ny even, ny <= 65535; nx * ny < 2^32 */
+    int32_t model;     /* LBM_PASSIVE / LBM_MIPS / LBM_CIL */
+    int32_t storage;   /* LBM_F32 / LBM_BF16_DEV / LBM_F16_DEV */
+    double tau;        /* relaxation time, >= 1 (appendix "Negative Correction"); +inf = streaming only */
+    double sigma;      /* noise half-width, >= 0 */
+    double A, B;       /* CIL speed law */
+    double C, rho_star;/* MIPS gradient gain and cut-off density */
+    double u_max;      /* MIPS clamp */
+    double rho_ref;    /* reference density of the deviation storages */
+    uint64_t seed;     /* Philox key */
+} lbm_params;
+
+typedef struct lbm_init {
+    int32_t mode;      /* LBM_INIT_* */
+    int32_t reserved;
+    double rho_mean;   /* mean density */
+    double rho_spread; /* relative half-width of the density draw (paper: 0.1) */
+    double angle_std;  /* LBM_INIT_GAUSS_DIR: standard deviation of the angle */
+    double u_mag;      /* |u| of the initial state; < 0 means U0(rho) (CIL), 0 otherwise */
+    double pop_noise;  /* half-width of a uniform perturbation added to every f_i */
+} lbm_init;
+
+/* Observables of the stored state, accumulated in FP64 (section "Regime
+ * Categorisation in the phase diagram"). */
+typedef struct lbm_obs {
+    int64_t step;      /* absolute step index of the state */
+    double M;          /* sum rho */
+    double Jx, Jy;     /* sum rho u */
+    double phi;        /* |sum rho u| / sum rho (eq. phi) */
+    double mean_speed; /* sum rho |u| / sum rho */
+    double zeta;       /* sum rho (B - |u|) / sum rho */
+    double drho;       /* standard deviation over x of rho_y(x) = mean over y of rho(x, y) */
+    int64_t nonfinite; /* number of non-finite populations */
+} lbm_obs;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Create a lattice context on the current HIP device.
+ *   p       parameters (copied).
+ *   f_a,f_b two caller-owned device buffers [7][ny][pitch] of the storage
+ *           type; the state starts in f_a.
+ *   pitch   row pitch in elements, >= nx.
+ *   init    initial state written into f_a (NULL or LBM_INIT_NONE: the caller
+ *           has filled f_a).
+ *   stream  caller's hipStream_t (NULL: the null stream), cast to void*.
+ *   out     receives the context.
+ * Returns LBM_EINVAL for nx < 2, odd, < 2 or > 65535 ny, nx*ny >= 2^32, pitch < nx,
+ * tau < 1, sigma < 0, non-finite or negative model constants, null or equal
+ * buffers, unknown model/storage/init mode. */
+int32_t lbm_create(const lbm_params *p, void *f_a, void *f_b, int64_t pitch, const lbm_init *init,
+                   void *stream, lbm_ctx **out);
+
+/* Enqueue n >= 0 steps on the context's stream (no synchronisation).  The
+ * state alternates between the two buffers; lbm_current_buffer() tells which
+ * holds it afterwards. */
+int32_t lbm_step(lbm_ctx *c, int64_t n);
+
+/* Fields and observables of the stored state.  rho, ux, uy: caller-owned
+ * device arrays [ny][nx] of float, or NULL to skip (u = 0 where rho = 0).
+ * obs: host struct, or NULL.  With obs != NULL the call synchronises the
+ * stream and returns LBM_ENONFINITE (after filling obs) if a population is
+ * NaN or infinite. */
+int32_t lbm_moments(lbm_ctx *c, float *rho, float *ux, float *uy, lbm_obs *obs);
+
+/* 0 if the state is in f_a, 1 if in f_b; negative on error. */
+int32_t lbm_current_buffer(const lbm_ctx *c);
+
+/* Absolute step index of the stored state (the Philox counter of the next
+ * step); lbm_set_step sets it (checkpoint/resume). */
+int64_t lbm_get_step(const lbm_ctx *c);
+int32_t lbm_set_step(lbm_ctx *c, int64_t step);
+
+/* Add drho/7 to every population of the stored state (the adiabatic density
+ * change of the appendix "CIL Model: General notes").  Enqueued, no sync. */
+int32_t lbm_add_density(lbm_ctx *c, double drho);
+
+/* Release the context (waits for its stream first). */
+int32_t lbm_destroy(lbm_ctx *c);
+
+/* Message of the last error on this thread ("" if none). */
+const char *lbm_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Batched sweeps: n independent lattices of arbitrary sizes and parameters
+ * advanced together, one kernel launch per step for the whole batch, the
+ * step loop captured in a HIP graph.
+ * ---------------------------------------------------------------------- */
+typedef struct lbm_sweep_opts {
+    int64_t n_steps;      /* steps to run */
+    int64_t sample_every; /* observables every sample_every steps (0: only at the end) */
+    int64_t step0;        /* absolute step index of the first step */
+    int32_t tile_rows;    /* rows per work tile; 0 = autotuned / default */
+    int32_t use_graph;    /* 1: capture the step loop in a HIP graph */
+} lbm_sweep_opts;
+
+/* Workspace bytes lbm_sweep_batch needs for these n lattices. */
+size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n);
+
+/* Run a batch.  ps[n]: per-lattice parameters (F32 storage only); bufs[2n]:
+ * device buffers, lattice l uses bufs[2l] (holding its state, pitch = nx)
+ * and bufs[2l+1]; ws: device workspace of ws_bytes >=
+ * lbm_sweep_workspace_bytes(); out: host array of n * n_samples lbm_obs,
+ * n_samples = n_steps / sample_every (or 1 if sample_every == 0), sample s of
+ * lattice l at out[l * n_samples + s].  After the call lattice l's state is in
+ * bufs[2l + (n_steps & 1)].  Synchronises the stream at the end. */
+int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o, void *const *bufs, void *ws,
+                        size_t ws_bytes, void *stream, lbm_obs *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

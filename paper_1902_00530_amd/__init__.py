@@ -1,0 +1,223 @@
+"""MI355X-native library for the modified lattice Boltzmann method of dense dry
+polar active fluids (Nesbitt, Pruessner & Lee, arXiv:1902.00530).
+
+This module is a thin ctypes binding of the C ABI in ``include/lbm.h``: the
+functions below carry the same names and marshal arguments only.  Every step
+of the method runs in the HIP kernels of ``liblbm.so``; there is no CPU
+fallback, and importing this package fails if the library is not built.
+PyTorch tensors provide device memory and streams.
+"""
+import ctypes
+import math
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ENONFINITE, LBM_EUNSUPPORTED, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LBM_PASSIVE, LBM_MIPS, LBM_CIL = 0, 1, 2
+LBM_F32, LBM_BF16_DEV, LBM_F16_DEV = 0, 1, 2
+LBM_INIT_NONE, LBM_INIT_UNIFORM_DIR, LBM_INIT_GAUSS_DIR = 0, 1, 2
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("model", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("tau", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("A", ctypes.c_double), ("B", ctypes.c_double), ("C", ctypes.c_double),
+                ("rho_star", ctypes.c_double), ("u_max", ctypes.c_double), ("rho_ref", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class lbm_init(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("reserved", ctypes.c_int32), ("rho_mean", ctypes.c_double),
+                ("rho_spread", ctypes.c_double), ("angle_std", ctypes.c_double), ("u_mag", ctypes.c_double),
+                ("pop_noise", ctypes.c_double)]
+
+
+class lbm_obs(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("M", ctypes.c_double), ("Jx", ctypes.c_double),
+                ("Jy", ctypes.c_double), ("phi", ctypes.c_double), ("mean_speed", ctypes.c_double),
+                ("zeta", ctypes.c_double), ("drho", ctypes.c_double), ("nonfinite", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class lbm_sweep_opts(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int64), ("sample_every", ctypes.c_int64), ("step0", ctypes.c_int64),
+                ("tile_rows", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where} failed ({code}): {lbm_last_error()}")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp = ctypes.c_void_p
+_P = ctypes.POINTER
+
+_SIGS = {
+    "lbm_create": (ctypes.c_int32, [_P(lbm_params), _vp, _vp, ctypes.c_int64, _P(lbm_init), _vp, _P(_vp)]),
+    "lbm_step": (ctypes.c_int32, [_vp, ctypes.c_int64]),
+    "lbm_moments": (ctypes.c_int32, [_vp, _vp, _vp, _vp, _P(lbm_obs)]),
+    "lbm_current_buffer": (ctypes.c_int32, [_vp]),
+    "lbm_get_step": (ctypes.c_int64, [_vp]),
+    "lbm_set_step": (ctypes.c_int32, [_vp, ctypes.c_int64]),
+    "lbm_add_density": (ctypes.c_int32, [_vp, ctypes.c_double]),
+    "lbm_destroy": (ctypes.c_int32, [_vp]),
+    "lbm_last_error": (ctypes.c_char_p, []),
+    "lbm_sweep_workspace_bytes": (ctypes.c_size_t, [_P(lbm_params), ctypes.c_int32]),
+    "lbm_sweep_batch": (ctypes.c_int32, [_P(lbm_params), ctypes.c_int32, _P(lbm_sweep_opts), _P(_vp), _vp,
+                                         ctypes.c_size_t, _vp, _P(lbm_obs)]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+def lbm_last_error():
+    return _lib.lbm_last_error().decode()
+
+
+def _check(rc, where):
+    if rc != LBM_OK:
+        raise LbmError(rc, where)
+    return rc
+
+
+# ----------------------------------------------------------------- raw ABI
+
+def lbm_create(params, f_a, f_b, pitch, init, stream):
+    ctx = _vp()
+    _check(_lib.lbm_create(ctypes.byref(params), f_a, f_b, int(pitch),
+                           ctypes.byref(init) if init is not None else None, stream, ctypes.byref(ctx)),
+           "lbm_create")
+    return ctx
+
+
+def lbm_step(ctx, n):
+    return _check(_lib.lbm_step(ctx, int(n)), "lbm_step")
+
+
+def lbm_moments(ctx, rho=None, ux=None, uy=None, want_obs=True, check=True):
+    obs = lbm_obs() if want_obs else None
+    rc = _lib.lbm_moments(ctx, rho, ux, uy, ctypes.byref(obs) if obs is not None else None)
+    if check and rc not in (LBM_OK,):
+        raise LbmError(rc, "lbm_moments")
+    return obs, rc
+
+
+def lbm_current_buffer(ctx):
+    r = _lib.lbm_current_buffer(ctx)
+    if r < 0:
+        raise LbmError(r, "lbm_current_buffer")
+    return r
+
+
+def lbm_get_step(ctx):
+    return _lib.lbm_get_step(ctx)
+
+
+def lbm_set_step(ctx, step):
+    return _check(_lib.lbm_set_step(ctx, int(step)), "lbm_set_step")
+
+
+def lbm_add_density(ctx, drho):
+    return _check(_lib.lbm_add_density(ctx, float(drho)), "lbm_add_density")
+
+
+def lbm_destroy(ctx):
+    return _check(_lib.lbm_destroy(ctx), "lbm_destroy")
+
+
+def lbm_sweep_workspace_bytes(params_array, n):
+    return _lib.lbm_sweep_workspace_bytes(params_array, int(n))
+
+
+def lbm_sweep_batch(params_array, n, opts, bufs, ws, ws_bytes, stream, out):
+    return _check(_lib.lbm_sweep_batch(params_array, int(n), ctypes.byref(opts), bufs, ws, int(ws_bytes), stream,
+                                       out), "lbm_sweep_batch")
+
+
+# ----------------------------------------------------------------- helpers
+
+def make_params(nx, ny, model, tau=1.0, sigma=0.0, A=0.0, B=0.0, C=0.0, rho_star=1.0, u_max=1.0, seed=0,
+                storage=LBM_F32, rho_ref=0.0):
+    return lbm_params(int(nx), int(ny), int(model), int(storage), float(tau), float(sigma), float(A), float(B),
+                      float(C), float(rho_star), float(u_max), float(rho_ref), int(seed) & 0xFFFFFFFFFFFFFFFF)
+
+
+def make_init(mode=LBM_INIT_UNIFORM_DIR, rho_mean=1.0, rho_spread=0.1, angle_std=0.0, u_mag=-1.0, pop_noise=0.0):
+    return lbm_init(int(mode), 0, float(rho_mean), float(rho_spread), float(angle_std), float(u_mag),
+                    float(pop_noise))
+
+
+def storage_dtype(storage):
+    import torch
+    return {LBM_F32: torch.float32, LBM_BF16_DEV: torch.bfloat16, LBM_F16_DEV: torch.float16}[storage]
+
+
+class Lattice:
+    """One lattice with torch-owned population buffers [7, ny, pitch] on the
+    current device; every operation is a call of the C ABI."""
+
+    def __init__(self, params, init=None, pitch=None, stream=None, device="cuda"):
+        import torch
+        self.params = params
+        self.pitch = int(pitch or params.nx)
+        dt = storage_dtype(params.storage)
+        self.buffers = [torch.zeros((7, params.ny, self.pitch), dtype=dt, device=device) for _ in range(2)]
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.ctx = lbm_create(params, self.buffers[0].data_ptr(), self.buffers[1].data_ptr(), self.pitch, init,
+                              self.stream.cuda_stream)
+
+    def step(self, n=1):
+        lbm_step(self.ctx, n)
+
+    @property
+    def state(self):
+        return self.buffers[lbm_current_buffer(self.ctx)]
+
+    def set_state(self, f):
+        """Copy populations [7, ny, nx] (storage dtype) into the current buffer."""
+        self.state[:, :, : self.params.nx].copy_(f)
+
+    def fields(self):
+        import torch
+        dev = self.buffers[0].device
+        rho = torch.empty((self.params.ny, self.params.nx), dtype=torch.float32, device=dev)
+        ux = torch.empty_like(rho)
+        uy = torch.empty_like(rho)
+        obs, _ = lbm_moments(self.ctx, rho.data_ptr(), ux.data_ptr(), uy.data_ptr(), want_obs=True, check=False)
+        return rho, ux, uy, obs.as_dict()
+
+    def observables(self, check=True):
+        obs, rc = lbm_moments(self.ctx, None, None, None, want_obs=True, check=check)
+        return obs.as_dict()
+
+    @property
+    def step_index(self):
+        return lbm_get_step(self.ctx)
+
+    def set_step(self, t):
+        lbm_set_step(self.ctx, t)
+
+    def add_density(self, drho):
+        lbm_add_density(self.ctx, drho)
+
+    def close(self):
+        if self.ctx:
+            lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,264 @@
+// Device-side building blocks of the fused D2Q7 active-LBM step (gfx950).
+//
+// Everything here runs inside the kernels: the counter-based noise generator,
+// the population storage formats, and the per-site collision of the modified
+// lattice Boltzmann method (Nesbitt, Pruessner & Lee, arXiv:1902.00530).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum Model : int { kPassive = 0, kMips = 1, kCil = 2 };
+enum Storage : int { kF32 = 0, kBf16Dev = 1, kF16Dev = 2 };
+
+// Kernel-side copy of the parameters, with derived constants precomputed on
+// the host in double and rounded once to float.
+struct StepArgs {
+    int32_t nx, ny;
+    int64_t pitch;      // elements per row
+    int64_t plane;      // elements per population plane (ny * pitch)
+    float omega;        // 1 / tau (0 for tau = +inf)
+    float noise_scale;  // sigma / 229376: eta_i = (7 h_i - sum h) * noise_scale
+    float A, B;         // CIL
+    float C, rho_star, inv_rho_star, u_max;  // MIPS
+    float wr0, wr1;     // w_0 rho_ref, w_i rho_ref (deviation storages)
+    uint32_t key0, key1;
+    int32_t noisy;      // sigma != 0
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies with the Philox multipliers, a word permutation and a
+// key xor; the key advances by the Weyl increments between rounds.  The key
+// and the upper counter words are uniform across the launch, so the
+// compiler keeps the key schedule in scalar registers.
+// ---------------------------------------------------------------------------
+struct Philox4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                 uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = c0 * 0xD2511F53u;
+        const uint32_t hi0 = __umulhi(c0, 0xD2511F53u);
+        const uint32_t lo1 = c2 * 0xCD9E8D57u;
+        const uint32_t hi1 = __umulhi(c2, 0xCD9E8D57u);
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Philox4 o;
+    o.v[0] = c0;
+    o.v[1] = c1;
+    o.v[2] = c2;
+    o.v[3] = c3;
+    return o;
+}
+
+// Zero-sum noise of one site and step (eq. noiseDensityConservation with
+// uniform raw draws).  With 16-bit draws h_i the raw value is
+// sigma (2 h_i - 65535) / 65536; subtracting the mean over the seven
+// directions leaves sigma (7 h_i - H) / 229376 with H = sum h_i, an exact
+// integer times one constant.
+__device__ __forceinline__ void site_noise(const StepArgs &a, uint32_t site, uint32_t t_lo, uint32_t t_hi,
+                                           float eta[7])
+{
+    const Philox4 w = philox4x32_10(site, t_lo, t_hi, 0u, a.key0, a.key1);
+    int h[7];
+    h[0] = (int)(w.v[0] & 0xffffu);
+    h[1] = (int)(w.v[0] >> 16);
+    h[2] = (int)(w.v[1] & 0xffffu);
+    h[3] = (int)(w.v[1] >> 16);
+    h[4] = (int)(w.v[2] & 0xffffu);
+    h[5] = (int)(w.v[2] >> 16);
+    h[6] = (int)(w.v[3] & 0xffffu);
+    const int H = h[0] + h[1] + h[2] + h[3] + h[4] + h[5] + h[6];
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        eta[i] = (float)(7 * h[i] - H) * a.noise_scale;
+}
+
+// ---------------------------------------------------------------------------
+// Storage formats.  F32 holds f_i; the deviation formats hold
+// d_i = f_i - w_i rho_ref rounded to nearest even in bf16 / fp16, and are
+// widened to f32 on load.
+// ---------------------------------------------------------------------------
+template <int S>
+struct Store;
+
+template <>
+struct Store<kF32> {
+    using T = float;
+    __device__ __forceinline__ static float load(const T *p, int64_t i, float) { return p[i]; }
+    __device__ __forceinline__ static void store(T *p, int64_t i, float v, float) { p[i] = v; }
+};
+
+__device__ __forceinline__ float bf16_bits_to_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ uint16_t float_to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u)  // inf / nan: keep class, quiet NaN
+        return (uint16_t)((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <>
+struct Store<kBf16Dev> {
+    using T = uint16_t;
+    __device__ __forceinline__ static float load(const T *p, int64_t i, float wr) { return bf16_bits_to_float(p[i]) + wr; }
+    __device__ __forceinline__ static void store(T *p, int64_t i, float v, float wr) { p[i] = float_to_bf16_rne(v - wr); }
+};
+
+template <>
+struct Store<kF16Dev> {
+    using T = _Float16;
+    __device__ __forceinline__ static float load(const T *p, int64_t i, float wr) { return (float)p[i] + wr; }
+    __device__ __forceinline__ static void store(T *p, int64_t i, float v, float wr) { p[i] = (_Float16)(v - wr); }
+};
+
+// ---------------------------------------------------------------------------
+// Per-site arithmetic.
+// ---------------------------------------------------------------------------
+constexpr float kHalfSqrt3 = 0.86602540378443864676f;        // sqrt(3)/2
+constexpr float kInv2Sqrt3 = 0.28867513459481288225f;        // 1/(2 sqrt 3)
+
+// rho and j = sum f_i e_i, with the momentum taken over opposite pairs so
+// that a pairwise-symmetric site has exactly zero momentum.
+__device__ __forceinline__ void site_moments(const float f[7], float &rho, float &jx, float &jy)
+{
+    rho = f[0] + ((f[1] + f[4]) + ((f[2] + f[5]) + (f[3] + f[6])));
+    const float d1 = f[1] - f[4], d2 = f[2] - f[5], d3 = f[3] - f[6];
+    jx = d1 + 0.5f * (d2 - d3);
+    jy = kHalfSqrt3 * (d2 + d3);
+}
+
+// CIL target velocity: u* = U0(rho) j/|j|, U0 = max(B - A rho^2, 0); zero
+// where j = 0.  Passive: u* = j/rho (zero where rho = 0).
+template <int M>
+__device__ __forceinline__ void local_ustar(const StepArgs &a, float rho, float jx, float jy, float &ux, float &uy)
+{
+    if (M == kCil) {
+        const float u0 = fmaxf(a.B - a.A * rho * rho, 0.0f);
+        const float jn2 = jx * jx + jy * jy;
+        const float s = jn2 > 0.0f ? u0 / sqrtf(jn2) : 0.0f;
+        ux = s * jx;
+        uy = s * jy;
+    } else {
+        const float r = rho != 0.0f ? 1.0f / rho : 0.0f;
+        ux = jx * r;
+        uy = jy * r;
+    }
+}
+
+// MIPS target velocity from the six neighbour densities (isotropic stencil,
+// component form) with the U_max clamp that keeps the direction.
+__device__ __forceinline__ void mips_ustar(const StepArgs &a, float rho, const float nb[7], float &ux, float &uy)
+{
+    const float gx = (2.0f * (nb[1] - nb[4]) + (nb[2] + nb[6]) - (nb[3] + nb[5])) * (1.0f / 6.0f);
+    const float gy = ((nb[2] + nb[3]) - (nb[5] + nb[6])) * kInv2Sqrt3;
+    float k = 0.0f;
+    if (rho < a.rho_star)
+        k = a.C * (1.0f - rho * a.inv_rho_star);
+    ux = k * gx;
+    uy = k * gy;
+    const float un2 = ux * ux + uy * uy;
+    if (un2 > a.u_max * a.u_max) {
+        const float s = a.u_max / sqrtf(un2);
+        ux *= s;
+        uy *= s;
+    }
+}
+
+// BGK relaxation towards xi(rho, u*) (eq. fssD2Q7), zero-sum noise, and the
+// negative correction (pair form, rescale to rho where a rule fired).
+__device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], float rho, float ux, float uy,
+                                             uint32_t site, uint32_t t_lo, uint32_t t_hi)
+{
+    const float usq = ux * ux + uy * uy;
+    const float a1 = ux;
+    const float a2 = 0.5f * ux + kHalfSqrt3 * uy;
+    const float a3 = -0.5f * ux + kHalfSqrt3 * uy;
+    const float r12 = rho * (1.0f / 12.0f);
+    const float base = 1.0f - 2.0f * usq;
+    float eq[7];
+    eq[0] = 0.5f * rho * base;
+    {
+        const float b1 = base + 8.0f * a1 * a1, b2 = base + 8.0f * a2 * a2, b3 = base + 8.0f * a3 * a3;
+        eq[1] = r12 * (b1 + 4.0f * a1);
+        eq[4] = r12 * (b1 - 4.0f * a1);
+        eq[2] = r12 * (b2 + 4.0f * a2);
+        eq[5] = r12 * (b2 - 4.0f * a2);
+        eq[3] = r12 * (b3 + 4.0f * a3);
+        eq[6] = r12 * (b3 - 4.0f * a3);
+    }
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        f[i] = f[i] - (f[i] - eq[i]) * a.omega;
+    if (a.noisy) {
+        float eta[7];
+        site_noise(a, site, t_lo, t_hi, eta);
+#pragma unroll
+        for (int i = 0; i < 7; ++i)
+            f[i] += eta[i];
+    }
+    bool fired = false;
+    if (f[0] < 0.0f) {
+        f[0] = 0.0f;
+        fired = true;
+    }
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) {
+        if (f[k] < 0.0f || f[k + 3] < 0.0f) {
+            const float d = f[k] - f[k + 3];
+            f[k] = fmaxf(d, 0.0f);
+            f[k + 3] = fmaxf(-d, 0.0f);
+            fired = true;
+        }
+    }
+    if (fired) {
+        const float s = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6];
+        const float r = s > 0.0f ? rho / s : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 7; ++i)
+            f[i] = s > 0.0f ? f[i] * r : 0.0f;
+    }
+}
+
+// Offset-row neighbour columns: for direction i the target is
+// (x + dx_i(p), y + dy_i) with p = y & 1; xm = x-1, xp = x+1 wrapped.
+struct PushTargets {
+    int64_t idx[7];
+};
+
+__device__ __forceinline__ PushTargets push_targets(const StepArgs &a, int x, int y)
+{
+    const int p = y & 1;
+    const int xm = x == 0 ? a.nx - 1 : x - 1;
+    const int xp = x == a.nx - 1 ? 0 : x + 1;
+    const int yu = y == a.ny - 1 ? 0 : y + 1;
+    const int yd = y == 0 ? a.ny - 1 : y - 1;
+    const int xr = p ? xp : x;  // x + p
+    const int xl = p ? x : xm;  // x - 1 + p
+    const int64_t P = a.pitch;
+    PushTargets t;
+    t.idx[0] = (int64_t)y * P + x;
+    t.idx[1] = (int64_t)y * P + xp;
+    t.idx[2] = (int64_t)yu * P + xr;
+    t.idx[3] = (int64_t)yu * P + xl;
+    t.idx[4] = (int64_t)y * P + xm;
+    t.idx[5] = (int64_t)yd * P + xl;
+    t.idx[6] = (int64_t)yd * P + xr;
+    return t;
+}
+
+}  // namespace lbm

@@ -1,0 +1,60 @@
+// Host-side internals of the library: the context object and the kernel
+// launchers that the C ABI layer calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/lbm.h"
+#include "device.h"
+
+namespace lbm {
+
+void set_error(const std::string &msg);
+int32_t fail(int32_t code, const std::string &msg);
+int32_t hip_fail(hipError_t e, const char *what);
+
+#define LBM_HIP_TRY(expr)                                      \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return ::lbm::hip_fail(e_, #expr); \
+    } while (0)
+
+// Fill the kernel argument block from validated parameters.
+StepArgs make_step_args(const lbm_params &p, int64_t pitch);
+// Parameter validation shared by lbm_create and lbm_sweep_batch.
+int32_t validate_params(const lbm_params *p, int64_t pitch);
+
+// One fused step src -> dst at absolute step t.
+hipError_t launch_step(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
+                       hipStream_t s);
+// Initial state into dst.
+hipError_t launch_init(const lbm_params &p, const lbm_init &in, const StepArgs &a, void *dst, hipStream_t s);
+// f_i += drho / 7 in place.
+hipError_t launch_add_density(const lbm_params &p, const StepArgs &a, void *buf, double drho, hipStream_t s);
+
+// Moments and FP64 reductions.  scratch: device doubles of
+// moments_scratch_doubles(p); result: 8 device doubles
+// {M, Jx, Jy, sum |j|, nonfinite, mean_x rho_y, var_x rho_y, unused}.
+size_t moments_scratch_doubles(const lbm_params &p);
+hipError_t launch_moments(const lbm_params &p, const StepArgs &a, const void *src, float *rho, float *ux,
+                          float *uy, double *scratch, double *result, hipStream_t s);
+// Turn the 8 reduced doubles into an lbm_obs (host).
+void finish_obs(const lbm_params &p, const double *r, int64_t step, lbm_obs *o);
+
+}  // namespace lbm
+
+struct lbm_ctx {
+    lbm_params p;
+    lbm::StepArgs args;
+    int device;
+    hipStream_t stream;
+    void *buf[2];
+    int cur;
+    int64_t pitch;
+    int64_t step;
+    double *d_scratch;   // reductions
+    double *d_result;    // 8 doubles
+    double *h_result;    // pinned, 8 doubles
+};

@@ -1,0 +1,85 @@
+"""ABI contract checks that need no GPU: the library loads, exports every
+function that include/*.h declares, and rejects invalid arguments before any
+device work."""
+import ctypes
+import glob
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(lbm_[A-Za-z0-9_]+)\s*\(", text,
+                             flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("lbm_create", "lbm_step", "lbm_moments", "lbm_sweep_batch", "lbm_destroy", "lbm_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1902_00530_amd as L
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    missing = declared_functions() - exported
+    assert not missing, missing
+    lib = ctypes.CDLL(L.LIB_PATH)
+    for n in declared_functions():
+        assert getattr(lib, n) is not None
+
+
+def _create(L, p, pitch=None, a=1, b=2, init=None):
+    ctx = ctypes.c_void_p()
+    rc = L._lib.lbm_create(ctypes.byref(p), ctypes.c_void_p(a), ctypes.c_void_p(b),
+                           p.nx if pitch is None else pitch, init, None, ctypes.byref(ctx))
+    return rc, ctx
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("ny", 63, "even"), ("nx", 1, ">= 2"), ("ny", 0, ">= 2"), ("tau", 0.5, "tau"),
+    ("tau", float("nan"), "tau"), ("sigma", -0.1, "sigma"), ("sigma", float("inf"), "sigma"),
+    ("A", -1.0, "A, B"), ("B", float("nan"), "A, B"), ("model", 7, "model"), ("storage", 9, "storage"),
+])
+def test_create_rejects_invalid_parameters(field, value, msg):
+    import paper_1902_00530_amd as L
+    p = L.make_params(64, 64, L.LBM_CIL, A=0.1, B=0.3)
+    setattr(p, field, value)
+    rc, ctx = _create(L, p)
+    assert rc == L.LBM_EINVAL and not ctx.value
+    assert msg in L.lbm_last_error()
+
+
+def test_create_rejects_bad_buffers_and_pitch():
+    import paper_1902_00530_amd as L
+    p = L.make_params(64, 64, L.LBM_CIL)
+    assert _create(L, p, pitch=63)[0] == L.LBM_EINVAL
+    assert _create(L, p, a=0)[0] == L.LBM_EINVAL
+    assert _create(L, p, a=5, b=5)[0] == L.LBM_EINVAL
+    big = L.make_params(131072, 32768, L.LBM_CIL)
+    assert _create(L, big)[0] == L.LBM_EINVAL
+    mips = L.make_params(64, 64, L.LBM_MIPS, rho_star=0.0)
+    assert _create(L, mips)[0] == L.LBM_EINVAL
+    bad_init = L.make_init(mode=9)
+    assert L._lib.lbm_create(ctypes.byref(p), ctypes.c_void_p(1), ctypes.c_void_p(2), 64, ctypes.byref(bad_init),
+                             None, ctypes.byref(ctypes.c_void_p())) == L.LBM_EINVAL
+
+
+def test_null_context_is_a_state_error():
+    import paper_1902_00530_amd as L
+    assert L._lib.lbm_step(None, 1) == L.LBM_ESTATE
+    assert L._lib.lbm_moments(None, None, None, None, None) == L.LBM_ESTATE
+    assert L._lib.lbm_destroy(None) == L.LBM_ESTATE
+    assert L._lib.lbm_current_buffer(None) == L.LBM_ESTATE

@@ -1,0 +1,286 @@
+"""GPU parity of the fused FP32 step against the FP64 oracle, through the C ABI.
+
+Tolerances (derived from the arithmetic): one FP32 step is ~50 rounded
+operations per site with relative error <= 2^-24 each, so one step stays
+within 1e-6 of the population scale; 100 noisy steps accumulate at most
+linearly, within the 1e-5 target, as long as the state is linearly stable
+(passive, homogeneous ordered CIL with 2 A rho^2 < 1/2, MIPS outside the
+spinodal).  Streaming-only steps, symmetric states, translations and
+power-of-two rescalings are compared bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth_inputs as SI
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1902_00530_amd as lib
+    return lib
+
+
+def _oparams(orc, cfg):
+    return orc.make_params(cfg["nx"], cfg["ny"], cfg["model"], cfg["tau"], cfg["sigma"], cfg["A"], cfg["B"],
+                           cfg["C"], cfg["rho_star"], cfg["u_max"], cfg["seed"])
+
+
+def _gparams(L, cfg, storage=0, rho_ref=0.0):
+    return L.make_params(cfg["nx"], cfg["ny"], cfg["model"], cfg["tau"], cfg["sigma"], cfg["A"], cfg["B"],
+                         cfg["C"], cfg["rho_star"], cfg["u_max"], cfg["seed"], storage=storage, rho_ref=rho_ref)
+
+
+def _cfg(model, nx, ny, **kw):
+    base = dict(nx=nx, ny=ny, model=model, tau=1.0, sigma=0.0, A=0.0, B=0.0, C=0.0, rho_star=1.0, u_max=1.0,
+                seed=77)
+    base.update(kw)
+    return base
+
+
+def gpu_run(L, cfg, f0, steps, pitch=None, chunks=None):
+    """Run `steps` steps on the GPU from FP32 populations f0 [7, ny, nx]."""
+    lat = L.Lattice(_gparams(L, cfg), pitch=pitch)
+    lat.set_state(torch.from_numpy(np.ascontiguousarray(f0, dtype=np.float32)).cuda())
+    for n in (chunks or [steps]):
+        lat.step(n)
+    torch.cuda.synchronize()
+    out = lat.state[:, :, : cfg["nx"]].double().cpu().numpy()
+    lat.close()
+    return out
+
+
+def rel_err(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+CFGS = {
+    "cil_ho": _cfg(SI.CIL, 200, 70, tau=1.0, sigma=4 / 70, A=0.125, B=0.3),
+    "cil_rb": _cfg(SI.CIL, 300, 34, tau=1.0, sigma=4 / 70, A=0.125, B=0.3),
+    "mips": _cfg(SI.MIPS, 200, 70, tau=2.0, sigma=8 / 70, C=6.25, rho_star=1.6, u_max=0.3),
+    "passive": _cfg(SI.PASSIVE, 130, 66, tau=1.3, sigma=0.01),
+}
+INITS = {
+    "cil_ho": dict(mode=1, rho_mean=0.74, rho_spread=0.1),
+    "cil_rb": dict(mode=2, rho_mean=1.5, rho_spread=0.1, angle_std=0.05),
+    "mips": dict(mode=1, rho_mean=1.0, rho_spread=0.1, u_mag=0.1, pop_noise=1e-3),
+    "passive": dict(mode=1, rho_mean=1.0, rho_spread=0.1, u_mag=0.05),
+}
+
+
+def _init32(orc, cfg, ini):
+    f = orc.initialise(_oparams(orc, cfg), **ini)
+    return f.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("name", list(CFGS))
+def test_init_kernel_matches_oracle(L, orc, name):
+    cfg, ini = CFGS[name], INITS[name]
+    ref = orc.initialise(_oparams(orc, cfg), **ini)
+    lat = L.Lattice(_gparams(L, cfg), init=L.make_init(**{**dict(angle_std=0.0, u_mag=-1.0, pop_noise=0.0), **ini}))
+    torch.cuda.synchronize()
+    got = lat.state[:, :, : cfg["nx"]].double().cpu().numpy()
+    lat.close()
+    assert rel_err(got, ref) < 2e-7
+
+
+@pytest.mark.parametrize("name", list(CFGS))
+def test_one_step(L, orc, name):
+    cfg = CFGS[name]
+    f0 = _init32(orc, cfg, INITS[name])
+    got = gpu_run(L, cfg, f0, 1)
+    ref = orc.run(_oparams(orc, cfg), f0.copy(), 1)
+    assert rel_err(got, ref) < 1e-6
+
+
+@pytest.mark.parametrize("name", ["cil_ho", "passive"])
+def test_hundred_steps_stable_states(L, orc, name):
+    cfg = CFGS[name]
+    f0 = _init32(orc, cfg, INITS[name])
+    got = gpu_run(L, cfg, f0, 100, chunks=[1, 36, 63])
+    ref = orc.run(_oparams(orc, cfg), f0.copy(), 100)
+    assert rel_err(got, ref) < 1e-5
+
+
+def test_hundred_steps_mips_outside_spinodal(L, orc):
+    """MIPS with density above the spinodal (all modes decay): paper-scaled
+    C and rho* at mean density 1.56 of rho* = 1.6 (lambda = 8 of 0.195)."""
+    cfg = _cfg(SI.MIPS, 200, 70, tau=2.0, sigma=8 / 70, C=6.25, rho_star=1.6, u_max=0.3)
+    f0 = _init32(orc, cfg, dict(mode=1, rho_mean=1.56, rho_spread=0.01, u_mag=0.01, pop_noise=1e-3))
+    got = gpu_run(L, cfg, f0, 100)
+    ref = orc.run(_oparams(orc, cfg), f0.copy(), 100)
+    assert rel_err(got, ref) < 1e-5
+
+
+def test_negative_correction_fires(L, orc):
+    cfg = _cfg(SI.CIL, 130, 34, tau=1.0, sigma=0.05, A=2.0, B=0.3, seed=5)
+    f0 = SI.near_negative_populations(130, 34, seed=9).astype(np.float32).astype(np.float64)
+    got = gpu_run(L, cfg, f0, 3)
+    ref = orc.run(_oparams(orc, cfg), f0.copy(), 3)
+    assert (got >= 0).all()
+    assert rel_err(got, ref) < 2e-6
+
+
+@pytest.mark.parametrize("nx,ny", [(2, 2), (3, 4), (64, 2), (65, 6), (257, 10), (1000, 4)])
+def test_ragged_and_tiny_lattices(L, orc, nx, ny):
+    for model, kw in ((SI.CIL, dict(A=0.125, B=0.3, sigma=4 / 70)),
+                      (SI.MIPS, dict(tau=2.0, C=6.25, rho_star=1.6, u_max=0.3, sigma=8 / 70))):
+        cfg = _cfg(model, nx, ny, **kw)
+        f0 = SI.random_populations(nx, ny, seed=nx * 7 + ny).astype(np.float32).astype(np.float64)
+        got = gpu_run(L, cfg, f0, 2)
+        ref = orc.run(_oparams(orc, cfg), f0.copy(), 2)
+        assert rel_err(got, ref) < 2e-6, (model, nx, ny)
+
+
+@pytest.mark.parametrize("model", [SI.PASSIVE, SI.MIPS, SI.CIL])
+def test_stream_only_bitwise(L, orc, model):
+    """tau = +inf, sigma = 0: a step is a pure permutation of the FP32 values,
+    identical to the oracle bit for bit (pitch larger than nx too)."""
+    nx, ny = 75, 22
+    cfg = _cfg(model, nx, ny, tau=math.inf, rho_star=1.0, C=1.0, A=1.0, B=0.1)
+    f0 = SI.random_populations(nx, ny, seed=3).astype(np.float32).astype(np.float64)
+    got = gpu_run(L, cfg, f0, 9, pitch=80)
+    ref = orc.run(_oparams(orc, cfg), f0.copy(), 9)
+    assert (got == ref).all()
+
+
+@pytest.mark.parametrize("model", [SI.MIPS, SI.CIL])
+def test_translation_bitwise(L, model):
+    """sigma = 0: a state translated by a lattice vector gives the translated
+    output, bit for bit (catches tile and halo mistakes)."""
+    nx, ny = 192, 36
+    cfg = _cfg(model, nx, ny, tau=1.0, A=0.125, B=0.3, C=6.25, rho_star=1.6, u_max=0.3)
+    f0 = SI.random_populations(nx, ny, seed=8, lo=0.05, hi=0.2)
+    a = gpu_run(L, cfg, f0, 5)
+    # translation (x, y) -> (x + 1, y)
+    b = gpu_run(L, cfg, np.roll(f0, 1, axis=2), 5)
+    assert (np.roll(a, 1, axis=2) == b).all()
+    # translation by two rows (keeps row parity)
+    c = gpu_run(L, cfg, np.roll(f0, 2, axis=1), 5)
+    assert (np.roll(a, 2, axis=1) == c).all()
+
+
+def test_symmetric_state_keeps_zero_momentum(L):
+    """A uniform pairwise-symmetric state has exactly zero momentum at every
+    site after any number of steps (sigma = 0)."""
+    nx, ny = 64, 8
+    cfg = _cfg(SI.CIL, nx, ny, tau=1.0, A=0.125, B=0.3)
+    f0 = np.zeros((7, ny, nx))
+    f0[0] = 0.4
+    f0[1:] = 0.1
+    got = gpu_run(L, cfg, f0, 7)
+    for k in (1, 2, 3):
+        assert (got[k] == got[k + 3]).all()
+
+
+@pytest.mark.parametrize("model", [SI.MIPS, SI.CIL])
+def test_scale_covariance_bitwise(L, orc, model):
+    """(f, sigma, rho*, C, A) -> (4 f, 4 sigma, 4 rho*, C/4, A/16) scales the
+    result by exactly 4."""
+    nx, ny = 96, 20
+    kw = dict(tau=1.0, sigma=4 / 70, A=0.125, B=0.3) if model == SI.CIL else \
+        dict(tau=2.0, sigma=8 / 70, C=6.25, rho_star=1.6, u_max=0.3)
+    cfg = _cfg(model, nx, ny, **kw)
+    cfg4 = dict(cfg, sigma=cfg["sigma"] * 4, A=cfg["A"] / 16, C=cfg["C"] / 4, rho_star=cfg["rho_star"] * 4)
+    f0 = _init32(orc, cfg, dict(mode=1, rho_mean=0.74 if model == SI.CIL else 1.0, rho_spread=0.1,
+                                u_mag=-1.0 if model == SI.CIL else 0.1))
+    a = gpu_run(L, cfg, f0, 20)
+    b = gpu_run(L, cfg4, 4 * f0, 20)
+    assert (b == 4 * a).all()
+
+
+def test_resume_bitwise(L, orc):
+    cfg = CFGS["cil_ho"]
+    f0 = _init32(orc, cfg, INITS["cil_ho"])
+    a = gpu_run(L, cfg, f0, 30)
+    lat = L.Lattice(_gparams(L, cfg))
+    lat.set_state(torch.from_numpy(gpu_run(L, cfg, f0, 12).astype(np.float32)).cuda())
+    lat.set_step(12)
+    lat.step(18)
+    b = lat.state[:, :, : cfg["nx"]].double().cpu().numpy()
+    lat.close()
+    assert (a == b).all()
+
+
+def test_observables_and_fields(L, orc):
+    cfg = CFGS["cil_rb"]
+    f0 = _init32(orc, cfg, INITS["cil_rb"])
+    po = _oparams(orc, cfg)
+    lat = L.Lattice(_gparams(L, cfg))
+    lat.set_state(torch.from_numpy(f0.astype(np.float32)).cuda())
+    lat.step(10)
+    rho, ux, uy, obs = lat.fields()
+    state = lat.state[:, :, : cfg["nx"]].double().cpu().numpy()
+    lat.close()
+    o = orc.observables(po, state)
+    r_o, ux_o, uy_o = orc.fields(po, state)
+    assert rel_err(rho.double().cpu().numpy(), r_o) < 1e-6
+    assert np.abs(ux.double().cpu().numpy() - ux_o).max() < 1e-6
+    assert np.abs(uy.double().cpu().numpy() - uy_o).max() < 1e-6
+    assert abs(obs["M"] - o["M"]) < 1e-9 * o["M"]
+    for k in ("phi", "mean_speed", "zeta"):
+        assert abs(obs[k] - o[k]) < 1e-7, k
+    assert abs(obs["drho"] - o["drho"]) < 1e-7 * max(o["drho"], 1e-3)
+    assert obs["step"] == 10 and obs["nonfinite"] == 0
+
+
+def test_nonfinite_is_reported(L):
+    cfg = _cfg(SI.CIL, 64, 4, A=0.125, B=0.3)
+    f0 = SI.random_populations(64, 4, seed=1)
+    f0[3, 2, 5] = np.nan
+    lat = L.Lattice(_gparams(L, cfg))
+    lat.set_state(torch.from_numpy(f0.astype(np.float32)).cuda())
+    obs, rc = L.lbm_moments(lat.ctx, None, None, None, want_obs=True, check=False)
+    lat.close()
+    assert rc == L.LBM_ENONFINITE and obs.nonfinite == 1
+
+
+def test_mass_drift_long_run(L, orc):
+    """10^4 noisy CIL steps in FP32: the total mass drifts by rounding only."""
+    cfg = _cfg(SI.CIL, 256, 64, tau=1.0, sigma=4 / 70, A=0.125, B=0.3, seed=3)
+    lat = L.Lattice(_gparams(L, cfg), init=L.make_init(mode=1, rho_mean=0.74, rho_spread=0.1))
+    m0 = lat.observables()["M"]
+    lat.step(10000)
+    o = lat.observables()
+    lat.close()
+    assert abs(o["M"] - m0) / m0 < 1e-4
+    assert o["nonfinite"] == 0
+
+
+def test_zero_density_sites(L, orc):
+    """Empty sites stay empty and produce no NaN (u = 0 where rho = 0)."""
+    nx, ny = 64, 6
+    for model, kw in ((SI.CIL, dict(A=0.125, B=0.3)), (SI.MIPS, dict(tau=2.0, C=6.25, rho_star=1.6, u_max=0.3)),
+                      (SI.PASSIVE, {})):
+        cfg = _cfg(model, nx, ny, **kw)
+        f0 = SI.random_populations(nx, ny, seed=2)
+        f0[:, :, 10:30] = 0.0
+        got = gpu_run(L, cfg, f0, 1)
+        ref = orc.run(_oparams(orc, cfg), f0.astype(np.float32).astype(np.float64), 1)
+        assert np.isfinite(got).all() and rel_err(got, ref) < 1e-6
+
+
+def test_full_size_cil_1024(L, orc):
+    """The benchmark workload's lattice (1024 x 1024, CIL, FP32, launch
+    configuration of the benchmark): GPU init and 5 steps against the oracle on
+    the whole lattice."""
+    cfg = SI.cil_1024(1.0)
+    ini = cfg.pop("init")
+    po = _oparams(orc, cfg)
+    f0 = orc.initialise(po, **ini)
+    lat = L.Lattice(_gparams(L, cfg), init=L.make_init(**ini))
+    torch.cuda.synchronize()
+    g0 = lat.state[:, :, : cfg["nx"]].double().cpu().numpy()
+    assert rel_err(g0, f0) < 2e-7
+    lat.step(5)
+    got = lat.state[:, :, : cfg["nx"]].double().cpu().numpy()
+    lat.close()
+    ref = orc.run(po, g0.copy(), 5)
+    assert rel_err(got, ref) < 2e-6
