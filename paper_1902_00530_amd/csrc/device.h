@@ -131,6 +131,11 @@ struct Store<kF16Dev> {
 // ---------------------------------------------------------------------------
 constexpr float kHalfSqrt3 = 0.86602540378443864676f;        // sqrt(3)/2
 constexpr float kInv2Sqrt3 = 0.28867513459481288225f;        // 1/(2 sqrt 3)
+// 1/12 as an unevaluated float pair: float(1/12) is 3e-8 too large, which
+// would add a same-signed bias to the mass of every relaxed site; rho * hi +
+// rho * lo (one fma) is within an ulp of rho/12 with no systematic sign.
+constexpr float kTwelfthHi = (float)(1.0 / 12.0);
+constexpr float kTwelfthLo = (float)(1.0 / 12.0 - (double)(float)(1.0 / 12.0));
 
 // rho and j = sum f_i e_i, with the momentum taken over opposite pairs so
 // that a pairwise-symmetric site has exactly zero momentum.
@@ -188,7 +193,7 @@ __device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], floa
     const float a1 = ux;
     const float a2 = 0.5f * ux + kHalfSqrt3 * uy;
     const float a3 = -0.5f * ux + kHalfSqrt3 * uy;
-    const float r12 = rho * (1.0f / 12.0f);
+    const float r12 = fmaf(rho, kTwelfthHi, rho * kTwelfthLo);
     const float base = 1.0f - 2.0f * usq;
     float eq[7];
     eq[0] = 0.5f * rho * base;

@@ -100,22 +100,90 @@ def test_one_step(L, orc, name):
     assert rel_err(got, ref) < 1e-6
 
 
-@pytest.mark.parametrize("name", ["cil_ho", "passive"])
-def test_hundred_steps_stable_states(L, orc, name):
-    cfg = CFGS[name]
-    f0 = _init32(orc, cfg, INITS[name])
-    got = gpu_run(L, cfg, f0, 100, chunks=[1, 36, 63])
-    ref = orc.run(_oparams(orc, cfg), f0.copy(), 100)
+STABLE = {
+    # homogeneous ordered CIL started aligned (Gaussian angle about +x), weak noise
+    "cil_aligned": (_cfg(SI.CIL, 200, 70, tau=1.0, sigma=4 / 700, A=0.125, B=0.3),
+                    dict(mode=2, rho_mean=0.74, rho_spread=0.1, angle_std=0.05)),
+    # paper-scaled noise, slower relaxation (tau = 2) keeps the ordered state stable
+    "cil_noisy_tau2": (_cfg(SI.CIL, 200, 70, tau=2.0, sigma=4 / 70, A=0.125, B=0.3),
+                       dict(mode=2, rho_mean=0.74, rho_spread=0.1, angle_std=0.05)),
+    "passive": (CFGS["passive"], INITS["passive"]),
+}
+
+
+def _self_sensitivity(orc, po, f0, steps):
+    """Relative change of the oracle's own result after `steps` steps when the
+    initial populations are perturbed by 1e-7 relative: the linear horizon of
+    the configuration (field parity is only defined where this stays small)."""
+    r = np.random.default_rng(0)
+    f1 = f0 * (1 + 1e-7 * r.uniform(-1, 1, f0.shape))
+    return rel_err(orc.run(po, f1, steps), orc.run(po, f0.copy(), steps))
+
+
+@pytest.mark.parametrize("name,steps", [("cil_aligned", 100), ("cil_noisy_tau2", 100), ("passive", 100),
+                                        ("cil_aligned", 1000)])
+def test_long_runs_stable_states(L, orc, name, steps):
+    cfg, ini = STABLE[name]
+    f0 = _init32(orc, cfg, ini)
+    po = _oparams(orc, cfg)
+    assert _self_sensitivity(orc, po, f0, steps) < 1e-6
+    got = gpu_run(L, cfg, f0, steps, chunks=[1, steps // 3, steps - 1 - steps // 3])
+    ref = orc.run(po, f0.copy(), steps)
     assert rel_err(got, ref) < 1e-5
 
 
-def test_hundred_steps_mips_outside_spinodal(L, orc):
-    """MIPS with density above the spinodal (all modes decay): paper-scaled
-    C and rho* at mean density 1.56 of rho* = 1.6 (lambda = 8 of 0.195)."""
-    cfg = _cfg(SI.MIPS, 200, 70, tau=2.0, sigma=8 / 70, C=6.25, rho_star=1.6, u_max=0.3)
-    f0 = _init32(orc, cfg, dict(mode=1, rho_mean=1.56, rho_spread=0.01, u_mag=0.01, pop_noise=1e-3))
+def test_chaotic_state_statistics(L, orc):
+    """Paper-scaled CIL noise from a disordered start amplifies rounding (the
+    oracle's own 1e-7 perturbation reaches O(1) within ~100 steps), so here the
+    GPU and the oracle are compared on conserved and averaged quantities."""
+    cfg, ini = CFGS["cil_ho"], INITS["cil_ho"]
+    f0 = _init32(orc, cfg, ini)
+    po = _oparams(orc, cfg)
+    lat = L.Lattice(_gparams(L, cfg))
+    lat.set_state(torch.from_numpy(f0.astype(np.float32)).cuda())
+    f = f0.copy()
+    g_obs, o_obs = [], []
+    for t in range(0, 400, 20):
+        lat.step(20)
+        orc.run(po, f, 20, step0=t)
+        if t >= 200:
+            g_obs.append(lat.observables())
+            o_obs.append(orc.observables(po, f))
+    lat.close()
+    m0 = f0.sum()
+    for g, o in zip(g_obs, o_obs):
+        assert abs(g["M"] - m0) < 1e-5 * m0 and abs(o["M"] - m0) < 1e-12 * m0
+    # eight oracle runs 1e-7 apart spread by 0.58% (zeta) and 0.28% (mean
+    # speed) in these averages on this lattice: allow 4 standard deviations
+    # (phi and the banding measure fluctuate by ~20%, not compared)
+    for k, spread in (("mean_speed", 0.0028), ("zeta", 0.0058)):
+        gm = np.mean([g[k] for g in g_obs])
+        om = np.mean([o[k] for o in o_obs])
+        assert abs(gm - om) < 4 * spread * abs(om), (k, gm, om)
+    # the step map itself, on the developed noisy state (many corrections)
+    f32 = f.astype(np.float32).astype(np.float64)
+    assert (f32 == 0).mean() > 0.03
+    lat2 = L.Lattice(_gparams(L, cfg))
+    lat2.set_state(torch.from_numpy(f32.astype(np.float32)).cuda())
+    lat2.set_step(400)
+    lat2.step(1)
+    got = lat2.state[:, :, : cfg["nx"]].double().cpu().numpy()
+    lat2.close()
+    ref = orc.run(po, f32.copy(), 1, step0=400)
+    assert rel_err(got, ref) < 1e-6
+
+
+def test_hundred_steps_mips_stable(L, orc):
+    """MIPS with an active gradient term but below the instability (gamma
+    rho0 C (1 - rho0/rho*) <= c_s^2: C = 1 at rho0 = 1, rho* = 1.6), with
+    paper-scaled noise firing the negative correction at ~10% of populations."""
+    cfg = _cfg(SI.MIPS, 200, 70, tau=2.0, sigma=8 / 70, C=1.0, rho_star=1.6, u_max=0.3)
+    f0 = _init32(orc, cfg, dict(mode=1, rho_mean=1.0, rho_spread=0.1, u_mag=0.01, pop_noise=1e-3))
+    po = _oparams(orc, cfg)
+    assert _self_sensitivity(orc, po, f0, 100) < 1e-6
     got = gpu_run(L, cfg, f0, 100)
-    ref = orc.run(_oparams(orc, cfg), f0.copy(), 100)
+    ref = orc.run(po, f0.copy(), 100)
+    assert (ref == 0).mean() > 0.05
     assert rel_err(got, ref) < 1e-5
 
 
@@ -283,4 +351,6 @@ def test_full_size_cil_1024(L, orc):
     got = lat.state[:, :, : cfg["nx"]].double().cpu().numpy()
     lat.close()
     ref = orc.run(po, g0.copy(), 5)
-    assert rel_err(got, ref) < 2e-6
+    # paper-scaled noise: rounding is amplified ~2x over 5 steps (oracle
+    # self-sensitivity), on top of <= 1e-6 per step
+    assert rel_err(got, ref) < 1e-5
