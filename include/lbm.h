@@ -23,7 +23,11 @@
  *    p = y mod 2, all indices periodic.
  *  - A population buffer is [7][ny][pitch] elements of the storage type
  *    (plane i, row y, column x), pitch >= nx elements.  The state kept
- *    between steps is the post-streaming population f*.
+ *    between steps is the population after the last step of the algorithm
+ *    (the negative correction); a step streams it (population i of site r
+ *    comes from r - e_i), then collides.  An initial state f^SS is therefore
+ *    streamed by the first step, as in the paper.  Fields and observables of
+ *    a state are those of its streamed populations (the input of step (ii)).
  *  - Noise: raw draws eta~_i = sigma (2 U_i - 1), U_i = (h_i + 1/2)/65536,
  *    h_i = the i-th 16-bit half (low half first) of Philox4x32-10 with
  *    key (seed lo, seed hi) and counter (y*nx + x, step lo, step hi, 0);

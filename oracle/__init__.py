@@ -73,6 +73,9 @@ def lib():
         L.orc_initialise.restype = ctypes.c_int
         L.orc_observables.argtypes = [ctypes.POINTER(Params), dp, ctypes.POINTER(Obs)]
         L.orc_fields.argtypes = [ctypes.POINTER(Params), dp, dp, dp, dp]
+        L.orc_observables_of.argtypes = [ctypes.POINTER(Params), dp, ctypes.POINTER(Obs)]
+        L.orc_fields_of.argtypes = [ctypes.POINTER(Params), dp, dp, dp, dp]
+        L.orc_stream.argtypes = [ctypes.POINTER(Params), dp, dp]
         _lib = L
     return _lib
 
@@ -173,17 +176,31 @@ def initialise(p, mode=INIT_UNIFORM_DIR, rho_mean=1.0, rho_spread=0.1, angle_std
     return f
 
 
-def observables(p, f):
+def observables(p, f, streamed=True):
+    """Observables of a stored state (of its streamed populations), or with
+    streamed=False of the populations exactly as given."""
     f = np.ascontiguousarray(f, dtype=np.float64)
     o = Obs()
-    lib().orc_observables(ctypes.byref(p), _dp(f), ctypes.byref(o))
+    fn = lib().orc_observables if streamed else lib().orc_observables_of
+    fn(ctypes.byref(p), _dp(f), ctypes.byref(o))
     return {k: getattr(o, k) for k, _ in Obs._fields_}
 
 
-def fields(p, f):
+def fields(p, f, streamed=True):
+    """rho, ux, uy [ny, nx] of a stored state (of its streamed populations),
+    or with streamed=False of the populations exactly as given."""
     f = np.ascontiguousarray(f, dtype=np.float64)
     n = p.nx * p.ny
     rho, ux, uy = np.zeros(n), np.zeros(n), np.zeros(n)
-    lib().orc_fields(ctypes.byref(p), _dp(f), _dp(rho), _dp(ux), _dp(uy))
+    fn = lib().orc_fields if streamed else lib().orc_fields_of
+    fn(ctypes.byref(p), _dp(f), _dp(rho), _dp(ux), _dp(uy))
     sh = (p.ny, p.nx)
     return rho.reshape(sh), ux.reshape(sh), uy.reshape(sh)
+
+
+def stream(p, f):
+    """Streaming step (i) of a whole lattice: returns f*_i(r) = f_i(r - e_i)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.empty_like(f)
+    lib().orc_stream(ctypes.byref(p), _dp(f), _dp(out))
+    return out

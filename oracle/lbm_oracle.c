@@ -12,7 +12,11 @@
  *   - lattice vectors e_i = (cos((i-1) pi/3), sin((i-1) pi/3)) (the printed
  *     pi/6 cannot give a lattice whose opposite pairs are 1-4, 2-5, 3-6);
  *   - offset-row storage of the triangular lattice, odd rows shifted by +1/2;
- *   - the stored state between steps is the post-streaming population;
+ *   - the stored state between steps is the population after step (vi)
+ *     (correction), so a step is the algorithm's order (i)-(vi) verbatim, and
+ *     the initial state f^SS is streamed by the first step;
+ *   - observables and fields are those of the streamed populations, from
+ *     which step (ii) computes rho and u (eq. D2Q7macroscopic_u_disc);
  *   - the noise subtracts the mean of the raw draws over all seven directions;
  *   - the raw draws come from Philox4x32-10 keyed by the seed, with counter
  *     (site, step lo, step hi, 0), one 16-bit half-word per direction;
@@ -270,11 +274,25 @@ static int valid(const orc_params *p)
     return 1;
 }
 
+/* Streaming, step (i): f*_i(r) = f_i(r - e_i), taken as a pull from the
+ * neighbour along the opposite direction.  out must not alias in. */
+void orc_stream(const orc_params *p, const double *in, double *out)
+{
+    const int nx = p->nx, ny = p->ny;
+    const size_t n = plane(p);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            for (int i = 0; i < 7; ++i) {
+                int xs, ys;
+                orc_neighbour(nx, ny, x, y, opposite(i), &xs, &ys);
+                out[(size_t)i * n + (size_t)y * nx + x] = in[(size_t)i * n + (size_t)ys * nx + xs];
+            }
+}
+
 /* One step of the algorithm in the appendix "Summary of modified lattice
- * Boltzmann model algorithm", steps (ii)-(vi) at every site, then the
- * streaming step (i) that produces the next stored state.  Streaming is done
- * as a pull: f_i(r) <- g_i(r - e_i), with r - e_i the neighbour along the
- * opposite direction. */
+ * Boltzmann model algorithm", in its order: (i) streaming of the whole
+ * lattice, then at every site (ii) rho and u, (iii) u* and f^SS, (iv) BGK
+ * redistribution, (v) noise and (vi) the negative correction. */
 int orc_step(const orc_params *p, double *f, int64_t step)
 {
     if (!valid(p))
@@ -282,28 +300,30 @@ int orc_step(const orc_params *p, double *f, int64_t step)
     const int nx = p->nx, ny = p->ny;
     const size_t n = plane(p);
     double *rho = (double *)malloc(n * sizeof(double));
-    double *g = (double *)malloc(7 * n * sizeof(double));
-    if (!rho || !g) {
+    double *fs = (double *)malloc(7 * n * sizeof(double));
+    if (!rho || !fs) {
         free(rho);
-        free(g);
+        free(fs);
         return -2;
     }
-    /* (ii) densities of the whole lattice (the MIPS gradient needs them). */
+    /* (i) streaming */
+    orc_stream(p, f, fs);
+    /* (ii) densities of the whole streamed lattice (the MIPS gradient needs them) */
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
-            double fs[7], r, jx, jy;
+            double g[7], r, jx, jy;
             for (int i = 0; i < 7; ++i)
-                fs[i] = f[(size_t)i * n + (size_t)y * nx + x];
-            orc_moments(fs, &r, &jx, &jy);
+                g[i] = fs[(size_t)i * n + (size_t)y * nx + x];
+            orc_moments(g, &r, &jx, &jy);
             rho[(size_t)y * nx + x] = r;
         }
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t s = (size_t)y * nx + x;
-            double fs[7], r, jx, jy;
+            double g[7], r, jx, jy;
             for (int i = 0; i < 7; ++i)
-                fs[i] = f[(size_t)i * n + s];
-            orc_moments(fs, &r, &jx, &jy);
+                g[i] = fs[(size_t)i * n + s];
+            orc_moments(g, &r, &jx, &jy);
             /* (iii) u* and f^SS */
             double usx, usy;
             if (p->model == ORC_MIPS) {
@@ -325,7 +345,7 @@ int orc_step(const orc_params *p, double *f, int64_t step)
             /* (iv) BGK redistribution */
             double out[7];
             for (int i = 0; i < 7; ++i)
-                out[i] = fs[i] - (fs[i] - fss[i]) / p->tau;
+                out[i] = g[i] - (g[i] - fss[i]) / p->tau;
             /* (v) noise */
             double eta[7];
             orc_noise(p, (uint32_t)s, step, eta);
@@ -334,18 +354,10 @@ int orc_step(const orc_params *p, double *f, int64_t step)
             /* (vi) negative correction */
             orc_correct(out, r);
             for (int i = 0; i < 7; ++i)
-                g[(size_t)i * n + s] = out[i];
+                f[(size_t)i * n + s] = out[i];
         }
-    /* (i) streaming of the next step */
-    for (int y = 0; y < ny; ++y)
-        for (int x = 0; x < nx; ++x)
-            for (int i = 0; i < 7; ++i) {
-                int xs, ys;
-                orc_neighbour(nx, ny, x, y, opposite(i), &xs, &ys);
-                f[(size_t)i * n + (size_t)y * nx + x] = g[(size_t)i * n + (size_t)ys * nx + xs];
-            }
     free(rho);
-    free(g);
+    free(fs);
     return 0;
 }
 
@@ -417,7 +429,7 @@ int orc_initialise(const orc_params *p, const orc_init *in, double *f)
     return 0;
 }
 
-void orc_fields(const orc_params *p, const double *f, double *rho, double *ux, double *uy)
+void orc_fields_of(const orc_params *p, const double *f, double *rho, double *ux, double *uy)
 {
     const size_t n = plane(p);
     for (size_t s = 0; s < n; ++s) {
@@ -436,8 +448,9 @@ void orc_fields(const orc_params *p, const double *f, double *rho, double *ux, d
 
 /* Observables of the section "Regime Categorisation in the phase diagram":
  * phi (eq. phi), the banding measure (standard deviation over x of the
- * y-averaged density) and zeta; plus total mass and momentum. */
-void orc_observables(const orc_params *p, const double *f, orc_obs *out)
+ * y-averaged density) and zeta; plus total mass and momentum; of the given
+ * populations. */
+void orc_observables_of(const orc_params *p, const double *f, orc_obs *out)
 {
     const int nx = p->nx, ny = p->ny;
     const size_t n = plane(p);
@@ -480,4 +493,26 @@ void orc_observables(const orc_params *p, const double *f, orc_obs *out)
     out->zeta = (M != 0.0) ? zsum / M : 0.0;
     out->drho = sqrt(var);
     out->nonfinite = bad;
+}
+
+/* Fields and observables of a stored state: those of its streamed
+ * populations, from which step (ii) takes rho and u. */
+void orc_fields(const orc_params *p, const double *f, double *rho, double *ux, double *uy)
+{
+    double *fs = (double *)malloc(7 * plane(p) * sizeof(double));
+    if (!fs)
+        return;
+    orc_stream(p, f, fs);
+    orc_fields_of(p, fs, rho, ux, uy);
+    free(fs);
+}
+
+void orc_observables(const orc_params *p, const double *f, orc_obs *out)
+{
+    double *fs = (double *)malloc(7 * plane(p) * sizeof(double));
+    if (!fs)
+        return;
+    orc_stream(p, f, fs);
+    orc_observables_of(p, fs, out);
+    free(fs);
 }

@@ -9,10 +9,11 @@
  *
  * Layout: populations are f[i][y][x], i = 0..6, 0 <= x < nx, 0 <= y < ny,
  * contiguous (no pitch), FP64.  The stored state between steps is the
- * post-streaming population f* (step (i) of the algorithm in the appendix
- * "Summary of modified lattice Boltzmann model algorithm"), so one oracle step
- * is: moments -> u* -> f^SS -> collide -> noise -> negative correction ->
- * stream.
+ * population after the last step of the algorithm in the appendix "Summary
+ * of modified lattice Boltzmann model algorithm" (the negative correction),
+ * so one oracle step is that algorithm in order: stream -> moments -> u* ->
+ * f^SS -> collide -> noise -> negative correction.  Fields and observables
+ * of a stored state are those of its streamed populations.
  */
 #ifndef LBM_ORACLE_H
 #define LBM_ORACLE_H
@@ -83,9 +84,13 @@ int orc_step(const orc_params *p, double *f, int64_t step);
 int orc_run(const orc_params *p, double *f, int64_t step0, int64_t n);
 /* Initial populations (appendix "CIL Model: General notes"). */
 int orc_initialise(const orc_params *p, const orc_init *in, double *f);
-/* Observables of the stored state. */
+/* Streaming (step (i)) of a whole lattice, pull form; out must not alias in. */
+void orc_stream(const orc_params *p, const double *in, double *out);
+/* Observables and fields (arrays of ny*nx) of the given populations. */
+void orc_observables_of(const orc_params *p, const double *f, orc_obs *out);
+void orc_fields_of(const orc_params *p, const double *f, double *rho, double *ux, double *uy);
+/* Observables and fields of a stored state: those of its streamed populations. */
 void orc_observables(const orc_params *p, const double *f, orc_obs *out);
-/* Per-site fields rho, ux, uy of the stored state (arrays of ny*nx). */
 void orc_fields(const orc_params *p, const double *f, double *rho, double *ux, double *uy);
 
 #endif

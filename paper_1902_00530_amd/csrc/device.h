@@ -44,14 +44,13 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = c0 * 0xD2511F53u;
-        const uint32_t hi0 = __umulhi(c0, 0xD2511F53u);
-        const uint32_t lo1 = c2 * 0xCD9E8D57u;
-        const uint32_t hi1 = __umulhi(c2, 0xCD9E8D57u);
-        c0 = hi1 ^ c1 ^ k0;
-        c1 = lo1;
-        c2 = hi0 ^ c3 ^ k1;
-        c3 = lo0;
+        // one 32x32->64 product per multiplier (a single v_mad_u64_u32 each)
+        const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+        c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        c1 = (uint32_t)p1;
+        c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -99,6 +98,8 @@ struct Store<kF32> {
     using T = float;
     __device__ __forceinline__ static float load(const T *p, int64_t i, float) { return p[i]; }
     __device__ __forceinline__ static void store(T *p, int64_t i, float v, float) { p[i] = v; }
+    __device__ __forceinline__ static float widen(T v, float) { return v; }
+    __device__ __forceinline__ static T narrow(float v, float) { return v; }
 };
 
 __device__ __forceinline__ float bf16_bits_to_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
@@ -117,6 +118,8 @@ struct Store<kBf16Dev> {
     using T = uint16_t;
     __device__ __forceinline__ static float load(const T *p, int64_t i, float wr) { return bf16_bits_to_float(p[i]) + wr; }
     __device__ __forceinline__ static void store(T *p, int64_t i, float v, float wr) { p[i] = float_to_bf16_rne(v - wr); }
+    __device__ __forceinline__ static float widen(T v, float wr) { return bf16_bits_to_float(v) + wr; }
+    __device__ __forceinline__ static T narrow(float v, float wr) { return float_to_bf16_rne(v - wr); }
 };
 
 template <>
@@ -124,6 +127,8 @@ struct Store<kF16Dev> {
     using T = _Float16;
     __device__ __forceinline__ static float load(const T *p, int64_t i, float wr) { return (float)p[i] + wr; }
     __device__ __forceinline__ static void store(T *p, int64_t i, float v, float wr) { p[i] = (_Float16)(v - wr); }
+    __device__ __forceinline__ static float widen(T v, float wr) { return (float)v + wr; }
+    __device__ __forceinline__ static T narrow(float v, float wr) { return (_Float16)(v - wr); }
 };
 
 // ---------------------------------------------------------------------------
@@ -155,11 +160,11 @@ __device__ __forceinline__ void local_ustar(const StepArgs &a, float rho, float 
     if (M == kCil) {
         const float u0 = fmaxf(a.B - a.A * rho * rho, 0.0f);
         const float jn2 = jx * jx + jy * jy;
-        const float s = jn2 > 0.0f ? u0 / sqrtf(jn2) : 0.0f;
+        const float s = jn2 > 0.0f ? u0 * rsqrtf(jn2) : 0.0f;
         ux = s * jx;
         uy = s * jy;
     } else {
-        const float r = rho != 0.0f ? 1.0f / rho : 0.0f;
+        const float r = rho != 0.0f ? __builtin_amdgcn_rcpf(rho) : 0.0f;
         ux = jx * r;
         uy = jy * r;
     }
@@ -178,7 +183,7 @@ __device__ __forceinline__ void mips_ustar(const StepArgs &a, float rho, const f
     uy = k * gy;
     const float un2 = ux * ux + uy * uy;
     if (un2 > a.u_max * a.u_max) {
-        const float s = a.u_max / sqrtf(un2);
+        const float s = a.u_max * rsqrtf(un2);
         ux *= s;
         uy *= s;
     }
@@ -232,20 +237,22 @@ __device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], floa
     }
     if (fired) {
         const float s = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6];
-        const float r = s > 0.0f ? rho / s : 0.0f;
+        const float r = s > 0.0f ? rho * __builtin_amdgcn_rcpf(s) : 0.0f;
 #pragma unroll
         for (int i = 0; i < 7; ++i)
             f[i] = s > 0.0f ? f[i] * r : 0.0f;
     }
 }
 
-// Offset-row neighbour columns: for direction i the target is
-// (x + dx_i(p), y + dy_i) with p = y & 1; xm = x-1, xp = x+1 wrapped.
-struct PushTargets {
+// Streaming sources (step (i)): after streaming, population i at site r is
+// the one that sat at r - e_i.  On offset rows with p = y & 1 those sites are
+// e_1: (x-1, y), e_2: (x-1+p, y-1), e_3: (x+p, y-1), e_4: (x+1, y),
+// e_5: (x+p, y+1), e_6: (x-1+p, y+1), all periodic.
+struct PullSources {
     int64_t idx[7];
 };
 
-__device__ __forceinline__ PushTargets push_targets(const StepArgs &a, int x, int y)
+__device__ __forceinline__ PullSources pull_sources(const StepArgs &a, int x, int y)
 {
     const int p = y & 1;
     const int xm = x == 0 ? a.nx - 1 : x - 1;
@@ -255,15 +262,67 @@ __device__ __forceinline__ PushTargets push_targets(const StepArgs &a, int x, in
     const int xr = p ? xp : x;  // x + p
     const int xl = p ? x : xm;  // x - 1 + p
     const int64_t P = a.pitch;
-    PushTargets t;
+    PullSources t;
     t.idx[0] = (int64_t)y * P + x;
-    t.idx[1] = (int64_t)y * P + xp;
-    t.idx[2] = (int64_t)yu * P + xr;
-    t.idx[3] = (int64_t)yu * P + xl;
-    t.idx[4] = (int64_t)y * P + xm;
-    t.idx[5] = (int64_t)yd * P + xl;
-    t.idx[6] = (int64_t)yd * P + xr;
+    t.idx[1] = (int64_t)y * P + xm;
+    t.idx[2] = (int64_t)yd * P + xl;
+    t.idx[3] = (int64_t)yd * P + xr;
+    t.idx[4] = (int64_t)y * P + xp;
+    t.idx[5] = (int64_t)yu * P + xr;
+    t.idx[6] = (int64_t)yu * P + xl;
     return t;
+}
+
+// The same with 32-bit element offsets (buffers below 2^30 elements, checked
+// on the host).
+struct PullSources32 {
+    uint32_t idx[7];
+};
+
+__device__ __forceinline__ PullSources32 pull_sources32(const StepArgs &a, int x, int y)
+{
+    const int p = y & 1;
+    const uint32_t xm = x == 0 ? a.nx - 1 : x - 1;
+    const uint32_t xp = x == a.nx - 1 ? 0 : x + 1;
+    const uint32_t P = (uint32_t)a.pitch;
+    const uint32_t ry = (uint32_t)y * P;
+    const uint32_t ru = (y == a.ny - 1 ? 0u : (uint32_t)(y + 1)) * P;
+    const uint32_t rd = (y == 0 ? (uint32_t)(a.ny - 1) : (uint32_t)(y - 1)) * P;
+    const uint32_t xr = p ? xp : (uint32_t)x;  // x + p
+    const uint32_t xl = p ? (uint32_t)x : xm;  // x - 1 + p
+    PullSources32 t;
+    t.idx[0] = ry + x;
+    t.idx[1] = ry + xm;
+    t.idx[2] = rd + xl;
+    t.idx[3] = rd + xr;
+    t.idx[4] = ry + xp;
+    t.idx[5] = ru + xr;
+    t.idx[6] = ru + xl;
+    return t;
+}
+
+// Blocks are handed to the eight XCDs round-robin (block b runs on XCD
+// b mod 8).  Remapping b so that each XCD gets one contiguous run of tiles
+// keeps neighbouring tiles of a row on the same L2, so the partial cache
+// lines at tile edges are merged there instead of being fetched or written
+// back through two L2s.  The map is a bijection on [0, nb).
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, k = b & 7, s = b >> 3;
+    return k * q + (k < r ? k : r) + s;
+}
+
+// Element access through a uniform base pointer and a 32-bit byte offset,
+// which maps onto the scalar-base + vector-offset global addressing mode.
+template <typename T>
+__device__ __forceinline__ T ld32(const T *base, uint32_t elem)
+{
+    return *(const T *)((const char *)base + elem * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T *base, uint32_t elem, T v)
+{
+    *(T *)((char *)base + elem * (uint32_t)sizeof(T)) = v;
 }
 
 }  // namespace lbm

@@ -1,4 +1,5 @@
-// Fields and FP64 observables of the stored state: rho, u (eq.
+// Fields and FP64 observables of the stored state, taken (like step (ii) of
+// the algorithm) on its streamed populations: rho, u (eq.
 // D2Q7macroscopic_u_disc), the order parameter phi (eq. phi), the mean speed,
 // zeta and the banding measure (standard deviation over x of the y-averaged
 // density), section "Regime Categorisation in the phase diagram".
@@ -6,8 +7,10 @@
 // Pass 1: each block covers 256 columns x kRowsPerBlock rows; lanes hold
 // FP64 sums, reduced across the wavefront with shuffles and across the block
 // through LDS, one partial per block; per-column density sums go to a
-// [row-block][nx] array.  Pass 2 (one block) adds the partials in a fixed
-// order, so the result does not depend on scheduling.
+// [row-block][nx] array.  Pass 2 sums each column over the row blocks (one
+// thread per column) and pass 3 (one block) adds the block partials and the
+// column means in a fixed order, so the result does not depend on
+// scheduling.
 #include "internal.h"
 
 namespace lbm {
@@ -72,11 +75,11 @@ __global__ __launch_bounds__(kMomBX) void k_moments(const typename Store<S>::T *
     if (x < a.nx) {
         const int ye = min(yb + kRowsPerBlock, a.ny);
         for (int y = yb; y < ye; ++y) {
-            const int64_t own = (int64_t)y * a.pitch + x;
+            const PullSources g_src = pull_sources(a, x, y);
             float f[7];
 #pragma unroll
             for (int i = 0; i < 7; ++i)
-                f[i] = Store<S>::load(src, i * a.plane + own, i == 0 ? a.wr0 : a.wr1);
+                f[i] = Store<S>::load(src, i * a.plane + g_src.idx[i], i == 0 ? a.wr0 : a.wr1);
             float rho, jx, jy;
             site_moments(f, rho, jx, jy);
             bool finite = true;
@@ -109,11 +112,23 @@ __global__ __launch_bounds__(kMomBX) void k_moments(const typename Store<S>::T *
     }
 }
 
-// One block: fixed-order totals of the block partials, column means and
-// their variance over x.
+// Column means rho_y(x): one thread per column, row blocks in order.
+__global__ __launch_bounds__(256) void k_column_means(const double *__restrict__ colpart, int nrowblocks,
+                                                      double *__restrict__ colmean, int nx, int ny)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nx)
+        return;
+    double c = 0.0;
+    for (int r = 0; r < nrowblocks; ++r)
+        c += colpart[(int64_t)r * nx + x];
+    colmean[x] = c / (double)ny;
+}
+
+// One block: fixed-order totals of the block partials and of the column
+// means, then the variance of the column means over x.
 __global__ __launch_bounds__(256) void k_moments_final(const double *__restrict__ part, int nblocks,
-                                                       const double *__restrict__ colpart, int nrowblocks,
-                                                       double *__restrict__ colmean, int nx, int ny,
+                                                       const double *__restrict__ colmean, int nx,
                                                        double *__restrict__ result)
 {
     __shared__ double lds[4][kNPart + 1];
@@ -122,14 +137,8 @@ __global__ __launch_bounds__(256) void k_moments_final(const double *__restrict_
 #pragma unroll
         for (int k = 0; k < kNPart; ++k)
             v[k] += part[(int64_t)b * kNPart + k];
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-        double c = 0.0;
-        for (int r = 0; r < nrowblocks; ++r)
-            c += colpart[(int64_t)r * nx + x];
-        c /= (double)ny;
-        colmean[x] = c;
-        v[kNPart] += c;
-    }
+    for (int x = threadIdx.x; x < nx; x += blockDim.x)
+        v[kNPart] += colmean[x];
     block_sum<kNPart + 1>(v, lds);
     __shared__ double mean_s;
     if (threadIdx.x == 0)
@@ -174,8 +183,8 @@ hipError_t launch_moments(const lbm_params &p, const StepArgs &a, const void *sr
         break;
     default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(256), 0, s, part, gx * gy, colpart, gy, colmean, p.nx, p.ny,
-                       result);
+    hipLaunchKernelGGL(k_column_means, dim3((p.nx + 255) / 256), dim3(256), 0, s, colpart, gy, colmean, p.nx, p.ny);
+    hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(256), 0, s, part, gx * gy, colmean, p.nx, result);
     return hipGetLastError();
 }
 

@@ -1,63 +1,102 @@
 // Fused per-site step of the modified D2Q7 lattice Boltzmann method on
-// gfx950: load the seven post-streaming populations of a site, compute rho
-// and j, the target velocity u*, relax towards xi(rho, u*), add zero-sum
-// noise, correct negative populations and push each population to its
-// neighbour in the other buffer (algorithm of the appendix "Summary of
-// modified lattice Boltzmann model algorithm", with the stored state taken
-// after streaming).
+// gfx950, in the order of the algorithm of the appendix "Summary of modified
+// lattice Boltzmann model algorithm": (i) stream by gathering population i of
+// site r from r - e_i in the source buffer, (ii) rho and j, (iii) the target
+// velocity u* and xi(rho, u*), (iv) BGK relaxation, (v) zero-sum noise,
+// (vi) negative correction; the seven results are stored at r in the other
+// buffer.
 //
 // The step is bandwidth-bound (7 loads + 7 stores per site, ~100 flops and
-// one Philox call), so there is no matrix-core work: the kernels are laid out
-// for coalesced 64-lane row segments of the structure-of-arrays planes.
+// one Philox call), so there is no matrix-core work.  Streaming is a gather
+// (x-shifted loads, aligned stores): on MI355X a wavefront's shifted loads
+// merge in L2 at no HBM cost, whereas shifted stores leave partial cache
+// lines at tile edges, measured 7% slower at 4096^2.
 #include "internal.h"
 
 namespace lbm {
 
 // ---------------------------------------------------------------------------
-// Passive and CIL: u* depends on the site alone.  A block is BX x BY sites
-// (BX a multiple of 64 so a wavefront covers 64 consecutive x of one row).
+// Passive and CIL: u* depends on the site alone.  A block is a BX x BY tile
+// (BX a multiple of 64 so each wavefront covers 64 consecutive x of one row);
+// the 1-D grid of tiles is remapped so each XCD owns a contiguous run of
+// tiles.  Offsets are 32-bit element indices from per-plane base pointers.
 // ---------------------------------------------------------------------------
+struct TileGrid {
+    int ntx;    // tiles along x
+    int remap;  // 1: XCD-contiguous tile order (cache-resident lattices)
+};
+
 template <int M, int S>
 __global__ __launch_bounds__(256) void k_step_local(const typename Store<S>::T *__restrict__ src,
                                                     typename Store<S>::T *__restrict__ dst, StepArgs a,
-                                                    uint32_t t_lo, uint32_t t_hi)
+                                                    uint32_t t_lo, uint32_t t_hi, TileGrid g)
+{
+    using T = typename Store<S>::T;
+    const int L = g.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int tyi = L / g.ntx, txi = L - tyi * g.ntx;
+    const int x = txi * blockDim.x + threadIdx.x;
+    const int y = tyi * blockDim.y + threadIdx.y;
+    if (x >= a.nx || y >= a.ny)
+        return;
+    const uint32_t plane = (uint32_t)a.plane;
+    const PullSources32 g_src = pull_sources32(a, x, y);
+    float f[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        f[i] = Store<S>::widen(ld32(src + (size_t)i * plane, g_src.idx[i]), i == 0 ? a.wr0 : a.wr1);
+    float rho, jx, jy, ux, uy;
+    site_moments(f, rho, jx, jy);
+    local_ustar<M>(a, rho, jx, jy, ux, uy);
+    site_collide(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
+    const uint32_t own = g_src.idx[0];
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        st32(dst + (size_t)i * plane, own, Store<S>::narrow(f[i], i == 0 ? a.wr0 : a.wr1));
+}
+
+// Same body with 64-bit offsets, for buffers of 2^30 elements per plane set
+// or more.
+template <int M, int S>
+__global__ __launch_bounds__(256) void k_step_local64(const typename Store<S>::T *__restrict__ src,
+                                                      typename Store<S>::T *__restrict__ dst, StepArgs a,
+                                                      uint32_t t_lo, uint32_t t_hi)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     if (x >= a.nx || y >= a.ny)
         return;
-    const int64_t own = (int64_t)y * a.pitch + x;
+    const PullSources g_src = pull_sources(a, x, y);
     float f[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        f[i] = Store<S>::load(src, i * a.plane + own, i == 0 ? a.wr0 : a.wr1);
+        f[i] = Store<S>::load(src, i * a.plane + g_src.idx[i], i == 0 ? a.wr0 : a.wr1);
     float rho, jx, jy, ux, uy;
     site_moments(f, rho, jx, jy);
     local_ustar<M>(a, rho, jx, jy, ux, uy);
     site_collide(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
-    const PushTargets t = push_targets(a, x, y);
+    const int64_t own = g_src.idx[0];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        Store<S>::store(dst, i * a.plane + t.idx[i], f[i], i == 0 ? a.wr0 : a.wr1);
+        Store<S>::store(dst, i * a.plane + own, f[i], i == 0 ? a.wr0 : a.wr1);
 }
 
 // ---------------------------------------------------------------------------
-// MIPS: u* needs the density of the six neighbours at the same time level.
-// A 64 x 4 tile stages rho of the tile plus a one-site ring in LDS; ring
-// sites recompute rho from their seven populations (served from L2).  Every
-// LDS slot holds rho at its periodically wrapped lattice site, so ragged
-// tiles and lattices narrower than a tile need no special case.
+// MIPS: u* needs the streamed density of the six neighbours.  A 64 x 4 tile
+// stages rho of the tile plus a one-site ring in LDS; ring sites gather their
+// seven streamed populations themselves (served from L2).  Every LDS slot
+// holds rho at its periodically wrapped lattice site, so ragged tiles and
+// lattices narrower than a tile need no special case.
 // ---------------------------------------------------------------------------
 constexpr int kMipsTX = 64, kMipsTY = 4;
 
 template <int S>
 __device__ __forceinline__ float rho_at(const typename Store<S>::T *src, const StepArgs &a, int x, int y)
 {
-    const int64_t o = (int64_t)y * a.pitch + x;
+    const PullSources g_src = pull_sources(a, x, y);
     float f[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        f[i] = Store<S>::load(src, i * a.plane + o, i == 0 ? a.wr0 : a.wr1);
+        f[i] = Store<S>::load(src, i * a.plane + g_src.idx[i], i == 0 ? a.wr0 : a.wr1);
     return f[0] + ((f[1] + f[4]) + ((f[2] + f[5]) + (f[3] + f[6])));
 }
 
@@ -80,11 +119,11 @@ __global__ __launch_bounds__(256) void k_step_mips(const typename Store<S>::T *_
     const int x = x0 + tx, y = y0 + ty;
     const bool live = x < a.nx && y < a.ny;
     const int xw = wrapi(x, a.nx), yw = wrapi(y, a.ny);
-    const int64_t own = (int64_t)yw * a.pitch + xw;
+    const PullSources g_src = pull_sources(a, xw, yw);
     float f[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        f[i] = Store<S>::load(src, i * a.plane + own, i == 0 ? a.wr0 : a.wr1);
+        f[i] = Store<S>::load(src, i * a.plane + g_src.idx[i], i == 0 ? a.wr0 : a.wr1);
     float rho, jx, jy;
     site_moments(f, rho, jx, jy);
     srho[ty + 1][tx + 1] = rho;
@@ -124,10 +163,10 @@ __global__ __launch_bounds__(256) void k_step_mips(const typename Store<S>::T *_
     float ux, uy;
     mips_ustar(a, rho, nb, ux, uy);
     site_collide(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
-    const PushTargets t = push_targets(a, x, y);
+    const int64_t own = g_src.idx[0];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        Store<S>::store(dst, i * a.plane + t.idx[i], f[i], i == 0 ? a.wr0 : a.wr1);
+        Store<S>::store(dst, i * a.plane + own, f[i], i == 0 ? a.wr0 : a.wr1);
 }
 
 // ---------------------------------------------------------------------------
@@ -137,6 +176,17 @@ static dim3 local_block(int nx)
 {
     int bx = nx >= 256 ? 256 : ((nx + 63) / 64) * 64;
     return dim3(bx, 256 / bx, 1);
+}
+
+static bool fits32(const StepArgs &a) { return (uint64_t)a.plane * 7ull < (1ull << 30); }
+
+// Measured on MI355X: with both buffers inside the 256 MB Infinity Cache
+// the XCD-contiguous tile order is faster (L2-local tile edges); for lattices
+// streamed from HBM the hardware's round-robin order spreads the channels
+// better and wins.
+static int want_remap(const StepArgs &a, size_t elem)
+{
+    return 2ull * 7ull * (uint64_t)a.plane * elem <= (192ull << 20);
 }
 
 template <int S>
@@ -150,13 +200,23 @@ static hipError_t launch_step_s(const lbm_params &p, const StepArgs &a, const vo
     if (p.model == kMips) {
         dim3 blk(kMipsTX, kMipsTY), grd((p.nx + kMipsTX - 1) / kMipsTX, (p.ny + kMipsTY - 1) / kMipsTY);
         hipLaunchKernelGGL((k_step_mips<S>), grd, blk, 0, s, in, out, a, tlo, thi);
-    } else {
-        dim3 blk = local_block(p.nx);
-        dim3 grd((p.nx + blk.x - 1) / blk.x, (p.ny + blk.y - 1) / blk.y);
+        return hipGetLastError();
+    }
+    dim3 blk = local_block(p.nx);
+    const int ntx = (p.nx + blk.x - 1) / blk.x, nty = (p.ny + blk.y - 1) / blk.y;
+    if (fits32(a)) {
+        TileGrid g{ntx, want_remap(a, sizeof(T))};
+        dim3 grd((unsigned)ntx * (unsigned)nty);
         if (p.model == kCil)
-            hipLaunchKernelGGL((k_step_local<kCil, S>), grd, blk, 0, s, in, out, a, tlo, thi);
+            hipLaunchKernelGGL((k_step_local<kCil, S>), grd, blk, 0, s, in, out, a, tlo, thi, g);
         else
-            hipLaunchKernelGGL((k_step_local<kPassive, S>), grd, blk, 0, s, in, out, a, tlo, thi);
+            hipLaunchKernelGGL((k_step_local<kPassive, S>), grd, blk, 0, s, in, out, a, tlo, thi, g);
+    } else {
+        dim3 grd(ntx, nty);
+        if (p.model == kCil)
+            hipLaunchKernelGGL((k_step_local64<kCil, S>), grd, blk, 0, s, in, out, a, tlo, thi);
+        else
+            hipLaunchKernelGGL((k_step_local64<kPassive, S>), grd, blk, 0, s, in, out, a, tlo, thi);
     }
     return hipGetLastError();
 }

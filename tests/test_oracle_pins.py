@@ -564,14 +564,20 @@ def test_observables_closed_forms(orc):
     p = orc.make_params(nx, ny, orc.CIL, A=A, B=B)
     one = np.ones((ny, nx))
     f = xi_field(orc, r0 * one, u0 * 0.6 * one, u0 * 0.8 * one)
-    o = orc.observables(p, f)
+    o = orc.observables(p, f, streamed=False)
     assert abs(o["phi"] - u0) < 1e-13 and abs(o["zeta"] - A * r0 * r0) < 1e-13 and o["drho"] < 1e-14
     assert abs(o["M"] - r0 * nx * ny) < 1e-12
     # sinusoidal density on offset rows: std of rho_y(x) = eps cos(k/4)/sqrt 2
     eps, k = 0.01, 2 * math.pi * 3 / nx
     xp, _ = phys_coords(nx, ny)
     f = xi_field(orc, r0 + eps * np.sin(k * xp), 0 * one, 0 * one)
-    assert abs(orc.observables(p, f)["drho"] - eps * math.cos(k / 4) / math.sqrt(2)) < 1e-14
+    assert abs(orc.observables(p, f, streamed=False)["drho"] - eps * math.cos(k / 4) / math.sqrt(2)) < 1e-14
+    # a stored state's observables are those of its streamed populations:
+    # streaming xi(rho(x), 0) averages rho over the stencil, which multiplies
+    # a density wave along x by sum_i w_i cos(k e_ix) = 1/2 + (cos k + 2 cos(k/2))/6
+    damp = 0.5 + (math.cos(k) + 2 * math.cos(k / 2)) / 6
+    assert abs(orc.observables(p, f)["drho"] - damp * eps * math.cos(k / 4) / math.sqrt(2)) < 1e-14
+    assert abs(orc.observables(p, f)["M"] - orc.observables(p, f, streamed=False)["M"]) < 1e-12
 
 
 def test_phi_bounded_by_B(orc):
@@ -591,13 +597,13 @@ def test_initialisation_statistics(orc):
     A, B = 2.0, 0.3
     p = orc.make_params(nx, ny, orc.CIL, A=A, B=B, seed=11)
     f = orc.initialise(p, mode=1, rho_mean=0.2, rho_spread=0.1)
-    rho, ux, uy = orc.fields(p, f)
+    rho, ux, uy = orc.fields(p, f, streamed=False)
     assert rho.min() >= 0.18 and rho.max() <= 0.22
     assert abs(rho.mean() - 0.2) < 3 * 0.2 * 0.1 / math.sqrt(3 * rho.size)
     assert np.allclose(np.hypot(ux, uy), B - A * rho ** 2, atol=1e-15)
     ang = np.arctan2(uy, ux)
     assert abs(np.cos(ang).mean()) < 0.05 and abs(np.sin(ang).mean()) < 0.05
     f2 = orc.initialise(p, mode=2, rho_mean=0.2, rho_spread=0.1, angle_std=0.05)
-    _, ux, uy = orc.fields(p, f2)
+    _, ux, uy = orc.fields(p, f2, streamed=False)
     ang = np.arctan2(uy, ux)
     assert abs(ang.std() - 0.05) < 0.005 and abs(ang.mean()) < 0.005
