@@ -26,6 +26,8 @@ StepArgs make_step_args(const lbm_params &p, int64_t pitch);
 // Parameter validation shared by lbm_create and lbm_sweep_batch.
 int32_t validate_params(const lbm_params *p, int64_t pitch);
 
+// Compile-time variant of the site body for these arguments (kUnitTau, kNoisy).
+int step_flags(const StepArgs &a);
 // One fused step src -> dst at absolute step t.
 hipError_t launch_step(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
                        hipStream_t s);

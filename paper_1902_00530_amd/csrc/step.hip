@@ -18,22 +18,16 @@ namespace lbm {
 // ---------------------------------------------------------------------------
 // Passive and CIL: u* depends on the site alone.  A block is a BX x BY tile
 // (BX a multiple of 64 so each wavefront covers 64 consecutive x of one row);
-// the 1-D grid of tiles is remapped so each XCD owns a contiguous run of
-// tiles.  Offsets are 32-bit element indices from per-plane base pointers.
+// the grid is laid out in row groups so each row of tiles runs on one XCD.
+// Offsets are 32-bit element indices from per-plane base pointers.
 // ---------------------------------------------------------------------------
-struct TileGrid {
-    int ntx;    // tiles along x
-    int remap;  // 1: XCD-contiguous tile order (cache-resident lattices)
-};
-
-template <int M, int S>
+template <int M, int S, int F>
 __global__ __launch_bounds__(256) void k_step_local(const typename Store<S>::T *__restrict__ src,
                                                     typename Store<S>::T *__restrict__ dst, StepArgs a,
-                                                    uint32_t t_lo, uint32_t t_hi, TileGrid g)
+                                                    uint32_t t_lo, uint32_t t_hi)
 {
-    using T = typename Store<S>::T;
-    const int L = g.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    const int tyi = L / g.ntx, txi = L - tyi * g.ntx;
+    int txi, tyi;
+    row_group_tile(txi, tyi);
     const int x = txi * blockDim.x + threadIdx.x;
     const int y = tyi * blockDim.y + threadIdx.y;
     if (x >= a.nx || y >= a.ny)
@@ -47,7 +41,7 @@ __global__ __launch_bounds__(256) void k_step_local(const typename Store<S>::T *
     float rho, jx, jy, ux, uy;
     site_moments(f, rho, jx, jy);
     local_ustar<M>(a, rho, jx, jy, ux, uy);
-    site_collide(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
+    site_collide<F>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
     const uint32_t own = g_src.idx[0];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
@@ -56,7 +50,7 @@ __global__ __launch_bounds__(256) void k_step_local(const typename Store<S>::T *
 
 // Same body with 64-bit offsets, for buffers of 2^30 elements per plane set
 // or more.
-template <int M, int S>
+template <int M, int S, int F>
 __global__ __launch_bounds__(256) void k_step_local64(const typename Store<S>::T *__restrict__ src,
                                                       typename Store<S>::T *__restrict__ dst, StepArgs a,
                                                       uint32_t t_lo, uint32_t t_hi)
@@ -73,7 +67,7 @@ __global__ __launch_bounds__(256) void k_step_local64(const typename Store<S>::T
     float rho, jx, jy, ux, uy;
     site_moments(f, rho, jx, jy);
     local_ustar<M>(a, rho, jx, jy, ux, uy);
-    site_collide(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
+    site_collide<F>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
     const int64_t own = g_src.idx[0];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
@@ -106,7 +100,7 @@ __device__ __forceinline__ int wrapi(int v, int n)
     return v < 0 ? v + n : v;
 }
 
-template <int S>
+template <int S, int F>
 __global__ __launch_bounds__(256) void k_step_mips(const typename Store<S>::T *__restrict__ src,
                                                    typename Store<S>::T *__restrict__ dst, StepArgs a,
                                                    uint32_t t_lo, uint32_t t_hi)
@@ -162,7 +156,7 @@ __global__ __launch_bounds__(256) void k_step_mips(const typename Store<S>::T *_
     nb[6] = srho[cy - 1][cx + p];
     float ux, uy;
     mips_ustar(a, rho, nb, ux, uy);
-    site_collide(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
+    site_collide<F>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
     const int64_t own = g_src.idx[0];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
@@ -180,18 +174,9 @@ static dim3 local_block(int nx)
 
 static bool fits32(const StepArgs &a) { return (uint64_t)a.plane * 7ull < (1ull << 30); }
 
-// Measured on MI355X: with both buffers inside the 256 MB Infinity Cache
-// the XCD-contiguous tile order is faster (L2-local tile edges); for lattices
-// streamed from HBM the hardware's round-robin order spreads the channels
-// better and wins.
-static int want_remap(const StepArgs &a, size_t elem)
-{
-    return 2ull * 7ull * (uint64_t)a.plane * elem <= (192ull << 20);
-}
-
-template <int S>
-static hipError_t launch_step_s(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
-                                hipStream_t s)
+template <int S, int F>
+static hipError_t launch_step_sf(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
+                                 hipStream_t s)
 {
     using T = typename Store<S>::T;
     const uint32_t tlo = (uint32_t)((uint64_t)t & 0xffffffffu), thi = (uint32_t)((uint64_t)t >> 32);
@@ -199,26 +184,39 @@ static hipError_t launch_step_s(const lbm_params &p, const StepArgs &a, const vo
     T *out = (T *)dst;
     if (p.model == kMips) {
         dim3 blk(kMipsTX, kMipsTY), grd((p.nx + kMipsTX - 1) / kMipsTX, (p.ny + kMipsTY - 1) / kMipsTY);
-        hipLaunchKernelGGL((k_step_mips<S>), grd, blk, 0, s, in, out, a, tlo, thi);
+        hipLaunchKernelGGL((k_step_mips<S, F>), grd, blk, 0, s, in, out, a, tlo, thi);
         return hipGetLastError();
     }
     dim3 blk = local_block(p.nx);
     const int ntx = (p.nx + blk.x - 1) / blk.x, nty = (p.ny + blk.y - 1) / blk.y;
     if (fits32(a)) {
-        TileGrid g{ntx, want_remap(a, sizeof(T))};
-        dim3 grd((unsigned)ntx * (unsigned)nty);
+        dim3 grd(8u * (unsigned)ntx, (unsigned)((nty + 7) / 8));
         if (p.model == kCil)
-            hipLaunchKernelGGL((k_step_local<kCil, S>), grd, blk, 0, s, in, out, a, tlo, thi, g);
+            hipLaunchKernelGGL((k_step_local<kCil, S, F>), grd, blk, 0, s, in, out, a, tlo, thi);
         else
-            hipLaunchKernelGGL((k_step_local<kPassive, S>), grd, blk, 0, s, in, out, a, tlo, thi, g);
+            hipLaunchKernelGGL((k_step_local<kPassive, S, F>), grd, blk, 0, s, in, out, a, tlo, thi);
     } else {
         dim3 grd(ntx, nty);
         if (p.model == kCil)
-            hipLaunchKernelGGL((k_step_local64<kCil, S>), grd, blk, 0, s, in, out, a, tlo, thi);
+            hipLaunchKernelGGL((k_step_local64<kCil, S, F>), grd, blk, 0, s, in, out, a, tlo, thi);
         else
-            hipLaunchKernelGGL((k_step_local64<kPassive, S>), grd, blk, 0, s, in, out, a, tlo, thi);
+            hipLaunchKernelGGL((k_step_local64<kPassive, S, F>), grd, blk, 0, s, in, out, a, tlo, thi);
     }
     return hipGetLastError();
+}
+
+int step_flags(const StepArgs &a) { return (a.omega == 1.0f ? kUnitTau : 0) | (a.noisy ? kNoisy : 0); }
+
+template <int S>
+static hipError_t launch_step_s(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
+                                hipStream_t s)
+{
+    switch (step_flags(a)) {
+    case 0: return launch_step_sf<S, 0>(p, a, src, dst, t, s);
+    case kUnitTau: return launch_step_sf<S, kUnitTau>(p, a, src, dst, t, s);
+    case kNoisy: return launch_step_sf<S, kNoisy>(p, a, src, dst, t, s);
+    default: return launch_step_sf<S, kUnitTau | kNoisy>(p, a, src, dst, t, s);
+    }
 }
 
 hipError_t launch_step(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
