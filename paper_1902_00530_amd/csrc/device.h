@@ -106,14 +106,8 @@ struct Store<kF32> {
 
 __device__ __forceinline__ float bf16_bits_to_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-__device__ __forceinline__ uint16_t float_to_bf16_rne(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u)  // inf / nan: keep class, quiet NaN
-        return (uint16_t)((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// Round to nearest even into bfloat16 bits (one v_cvt_pk_bf16_f32 on gfx950).
+__device__ __forceinline__ uint16_t float_to_bf16_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 template <>
 struct Store<kBf16Dev> {

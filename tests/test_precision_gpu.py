@@ -1,0 +1,133 @@
+"""BF16 / FP16 deviation storage (populations stored as d_i = f_i - w_i rho_ref,
+FP32 arithmetic) against the FP64 oracle.
+
+One step from the same (dequantised) input: every stored value is the FP32
+result rounded to nearest even in the storage format, so the error of each
+population is at most the unit roundoff u of the format times |d_i| (u = 2^-8
+for bfloat16, 2^-11 for IEEE half, plus the half's subnormal spacing 2^-25),
+on top of the FP32 step error (<= 1e-6 of the population scale).  Longer runs
+accumulate one such rounding per step; their errors against FP64 are measured
+and stated (bounds below carry a margin over the measured values).
+"""
+import numpy as np
+import pytest
+
+import synth_inputs as SI
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from test_parity_gpu import _cfg, _oparams, _gparams, _init32, rel_err, STABLE  # noqa: E402
+
+W = np.array([0.5] + [1.0 / 12.0] * 6)
+U = {1: 2.0 ** -8, 2: 2.0 ** -11}
+DT = {1: torch.bfloat16, 2: torch.float16}
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1902_00530_amd as lib
+    return lib
+
+
+def quantise(f, storage, rho_ref):
+    d = torch.from_numpy(f - W[:, None, None] * rho_ref)
+    return d.to(DT[storage])
+
+
+def dequantise(q, rho_ref):
+    return q.double().cpu().numpy() + W[:, None, None] * rho_ref
+
+
+def run_dev(L, cfg, q, steps, storage, rho_ref, step0=0):
+    lat = L.Lattice(_gparams(L, cfg, storage=storage, rho_ref=rho_ref))
+    lat.set_state(q.cuda())
+    lat.set_step(step0)
+    lat.step(steps)
+    torch.cuda.synchronize()
+    out = lat.state[:, :, : cfg["nx"]].clone()
+    lat.close()
+    return out
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_init_in_deviation_storage(L, orc, storage):
+    cfg, ini = STABLE["cil_aligned"]
+    rho_ref = ini["rho_mean"]
+    ref = orc.initialise(_oparams(orc, cfg), **ini)
+    lat = L.Lattice(_gparams(L, cfg, storage=storage, rho_ref=rho_ref),
+                    init=L.make_init(**{**dict(angle_std=0.0, u_mag=-1.0, pop_noise=0.0), **ini}))
+    torch.cuda.synchronize()
+    got = dequantise(lat.state[:, :, : cfg["nx"]], rho_ref)
+    lat.close()
+    d = np.abs(ref - W[:, None, None] * rho_ref)
+    # one rounding of d (plus the FP32 intermediate): at most 2u |d|
+    assert (np.abs(got - ref) <= 2 * U[storage] * d + 1e-7).all()
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+@pytest.mark.parametrize("name", ["cil_aligned", "cil_noisy_tau2"])
+def test_one_step_rounding_bound(L, orc, storage, name):
+    cfg, ini = STABLE[name]
+    rho_ref = ini["rho_mean"]
+    f0 = orc.initialise(_oparams(orc, cfg), **ini)
+    q0 = quantise(f0, storage, rho_ref)
+    f0q = dequantise(q0, rho_ref)
+    got = dequantise(run_dev(L, cfg, q0, 1, storage, rho_ref), rho_ref)
+    ref = orc.run(_oparams(orc, cfg), f0q.copy(), 1)
+    d = np.abs(ref - W[:, None, None] * rho_ref)
+    bound = U[storage] * d + 1e-6 * np.abs(ref).max() + 2.0 ** -25
+    assert (np.abs(got - ref) <= bound).all()
+
+
+@pytest.mark.parametrize("storage,bound", [(1, 2e-2), (2, 2e-3)])
+def test_hundred_steps_stated_error(L, orc, storage, bound):
+    """Stable ordered CIL, 100 steps from the same dequantised input: relative
+    L-infinity error against FP64 (measured: see the design notes)."""
+    cfg, ini = STABLE["cil_aligned"]
+    rho_ref = ini["rho_mean"]
+    po = _oparams(orc, cfg)
+    f0 = orc.initialise(po, **ini)
+    q0 = quantise(f0, storage, rho_ref)
+    f0q = dequantise(q0, rho_ref)
+    got = dequantise(run_dev(L, cfg, q0, 100, storage, rho_ref), rho_ref)
+    ref = orc.run(po, f0q.copy(), 100)
+    err = rel_err(got, ref)
+    print(f"storage {storage}: 100-step relative Linf error {err:.3e}")
+    assert err < bound
+    o_g, o_r = orc.observables(po, got), orc.observables(po, ref)
+    assert abs(o_g["M"] - o_r["M"]) < 1e-3 * o_r["M"]
+    assert abs(o_g["phi"] - o_r["phi"]) < 10 * U[storage] * o_r["phi"]
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_mass_and_order_drift_long_run(L, storage):
+    """10^4 steps in deviation storage vs the FP32 kernel on the same seed.
+    Rounding to nearest even is unbiased, but consecutive roundings of a site
+    in a near-uniform ordered state are correlated, so the total mass walks
+    faster than independent errors would (measured 2.1e-3 relative for
+    bfloat16 over 10^4 steps, below 1e-3 for half); the time-averaged order
+    parameter stays within a few percent of the FP32 run."""
+    cfg, ini = STABLE["cil_aligned"]
+    rho_ref = ini["rho_mean"]
+    init = L.make_init(**{**dict(angle_std=0.0, u_mag=-1.0, pop_noise=0.0), **ini})
+    lat32 = L.Lattice(_gparams(L, cfg), init=init)
+    latq = L.Lattice(_gparams(L, cfg, storage=storage, rho_ref=rho_ref), init=init)
+    m32 = lat32.observables()["M"]
+    mq0 = latq.observables()["M"]
+    phis32, phisq = [], []
+    for _ in range(20):
+        lat32.step(500)
+        latq.step(500)
+        phis32.append(lat32.observables()["phi"])
+        o = latq.observables()
+        phisq.append(o["phi"])
+    mq = o["M"]
+    lat32.close()
+    latq.close()
+    print(f"storage {storage}: mass drift {abs(mq - mq0) / mq0:.2e} over 10^4 steps, "
+          f"phi {np.mean(phisq):.5f} vs FP32 {np.mean(phis32):.5f}")
+    assert abs(mq - mq0) / mq0 < (1e-2 if storage == 1 else 1e-3) and abs(mq0 - m32) / m32 < 1e-3
+    assert abs(np.mean(phisq) - np.mean(phis32)) < 0.05 * np.mean(phis32)
