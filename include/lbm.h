@@ -167,27 +167,38 @@ const char *lbm_last_error(void);
 
 /* ------------------------------------------------------------------------
  * Batched sweeps: n independent lattices of arbitrary sizes and parameters
- * advanced together, one kernel launch per step for the whole batch, the
- * step loop captured in a HIP graph.
+ * (the paper's repeated runs over a grid of mean density and model constants,
+ * appendix "Simulation procedure for results") advanced together: one kernel
+ * launch per step covers every lattice, and one sample period (its steps and
+ * the FP64 sampling kernels) is captured once in a HIP graph and replayed.
  * ---------------------------------------------------------------------- */
 typedef struct lbm_sweep_opts {
-    int64_t n_steps;      /* steps to run */
-    int64_t sample_every; /* observables every sample_every steps (0: only at the end) */
-    int64_t step0;        /* absolute step index of the first step */
-    int32_t tile_rows;    /* rows per work tile; 0 = autotuned / default */
-    int32_t use_graph;    /* 1: capture the step loop in a HIP graph */
+    int64_t n_steps;      /* steps to run (a multiple of sample_every) */
+    int64_t sample_every; /* observables every sample_every steps (0: once, at the end) */
+    int64_t step0;        /* absolute step index of the first step (noise counter) */
+    int32_t tile_rows;    /* work tile 256x1, 128x2 or 64x4 sites for 1, 2, 4; 0 = tuned
+                             (timed on the batch itself, cached per batch signature) */
+    int32_t use_graph;    /* 1: replay one captured sample period as a HIP graph */
 } lbm_sweep_opts;
 
-/* Workspace bytes lbm_sweep_batch needs for these n lattices. */
-size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n);
+/* Workspace bytes lbm_sweep_batch needs for these n lattices and n_samples
+ * samples per lattice (0 on invalid arguments). */
+size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samples);
 
-/* Run a batch.  ps[n]: per-lattice parameters (F32 storage only); bufs[2n]:
- * device buffers, lattice l uses bufs[2l] (holding its state, pitch = nx)
- * and bufs[2l+1]; ws: device workspace of ws_bytes >=
- * lbm_sweep_workspace_bytes(); out: host array of n * n_samples lbm_obs,
- * n_samples = n_steps / sample_every (or 1 if sample_every == 0), sample s of
- * lattice l at out[l * n_samples + s].  After the call lattice l's state is in
- * bufs[2l + (n_steps & 1)].  Synchronises the stream at the end. */
+/* Run a batch.  ps[n]: per-lattice parameters; every lattice uses F32
+ * storage, the same model (CIL or passive), and agrees on tau == 1 and on
+ * sigma == 0; nx*ny*7 < 2^30, ny <= 32760.  bufs[2n]: caller-owned device
+ * buffers [7][ny][nx], lattice l's state in bufs[2l] and bufs[2l+1] free.
+ * ws: caller-owned device workspace of ws_bytes >=
+ * lbm_sweep_workspace_bytes(ps, n, n_samples).  out: host array of
+ * n * n_samples lbm_obs, n_samples = n_steps / sample_every (1 if
+ * sample_every == 0), sample s of lattice l at out[l * n_samples + s].  The
+ * steps of lattice l use its own seed and the noise counters
+ * step0 .. step0 + n_steps - 1, so a lattice gives the same result as
+ * lbm_step on its own.  Afterwards lattice l's state is in
+ * bufs[2l + (n_steps & 1)].  Synchronises the stream at the end.  Errors:
+ * LBM_EINVAL for the conditions above, LBM_EUNSUPPORTED for other storages or
+ * MIPS, LBM_ENONFINITE if a sample saw a non-finite population. */
 int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o, void *const *bufs, void *ws,
                         size_t ws_bytes, void *stream, lbm_obs *out);
 

@@ -71,7 +71,7 @@ _SIGS = {
     "lbm_add_density": (ctypes.c_int32, [_vp, ctypes.c_double]),
     "lbm_destroy": (ctypes.c_int32, [_vp]),
     "lbm_last_error": (ctypes.c_char_p, []),
-    "lbm_sweep_workspace_bytes": (ctypes.c_size_t, [_P(lbm_params), ctypes.c_int32]),
+    "lbm_sweep_workspace_bytes": (ctypes.c_size_t, [_P(lbm_params), ctypes.c_int32, ctypes.c_int64]),
     "lbm_sweep_batch": (ctypes.c_int32, [_P(lbm_params), ctypes.c_int32, _P(lbm_sweep_opts), _P(_vp), _vp,
                                          ctypes.c_size_t, _vp, _P(lbm_obs)]),
 }
@@ -136,13 +136,57 @@ def lbm_destroy(ctx):
     return _check(_lib.lbm_destroy(ctx), "lbm_destroy")
 
 
-def lbm_sweep_workspace_bytes(params_array, n):
-    return _lib.lbm_sweep_workspace_bytes(params_array, int(n))
+def lbm_sweep_workspace_bytes(params_array, n, n_samples):
+    return _lib.lbm_sweep_workspace_bytes(params_array, int(n), int(n_samples))
 
 
 def lbm_sweep_batch(params_array, n, opts, bufs, ws, ws_bytes, stream, out):
     return _check(_lib.lbm_sweep_batch(params_array, int(n), ctypes.byref(opts), bufs, ws, int(ws_bytes), stream,
                                        out), "lbm_sweep_batch")
+
+
+class Batch:
+    """n lattices with torch-owned buffers, advanced by lbm_sweep_batch."""
+
+    def __init__(self, params_list, device="cuda"):
+        import torch
+        self.n = len(params_list)
+        self.params = (lbm_params * self.n)(*params_list)
+        self.buffers = [torch.zeros((7, p.ny, p.nx), dtype=torch.float32, device=device)
+                        for p in params_list for _ in range(2)]
+        self.bufs = (ctypes.c_void_p * (2 * self.n))(*[b.data_ptr() for b in self.buffers])
+        self.current = [0] * self.n
+        self.step_index = 0
+        self._ws = None
+
+    def state(self, l):
+        return self.buffers[2 * l + self.current[l]]
+
+    def set_state(self, l, f):
+        self.buffers[2 * l].copy_(f)
+        self.current[l] = 0
+
+    def run(self, n_steps, sample_every=0, tile_rows=0, use_graph=1, stream=None):
+        """Advance every lattice by n_steps; returns a list (per lattice) of
+        sample dicts."""
+        import torch
+        # the sweep expects each state in the first buffer of its pair
+        for l in range(self.n):
+            if self.current[l]:
+                self.buffers[2 * l].copy_(self.buffers[2 * l + 1])
+                self.current[l] = 0
+        n_samples = n_steps // sample_every if sample_every else 1
+        need = lbm_sweep_workspace_bytes(self.params, self.n, n_samples)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.buffers[0].device)
+        out = (lbm_obs * (self.n * n_samples))()
+        opts = lbm_sweep_opts(int(n_steps), int(sample_every), int(self.step_index), int(tile_rows), int(use_graph))
+        st = stream if stream is not None else torch.cuda.current_stream()
+        lbm_sweep_batch(self.params, self.n, opts, self.bufs, self._ws.data_ptr(), need, st.cuda_stream, out)
+        self.step_index += n_steps
+        for l in range(self.n):
+            self.current[l] = n_steps & 1
+        return [[out[l * n_samples + s].as_dict() for s in range(n_samples)] for l in range(self.n)]
 
 
 # ----------------------------------------------------------------- helpers

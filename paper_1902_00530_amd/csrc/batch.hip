@@ -1,22 +1,581 @@
-// Batched sweeps over many lattices (placeholder until the batched kernel lands).
+// Batched sweeps: many independent lattices of different sizes and
+// parameters advanced together (one kernel launch per step covers every
+// lattice), with FP64 observables sampled every sample_every steps.
+//
+// Work list.  Each lattice is cut into TX x TY tiles; the list of all tiles
+// of all lattices is built on the host.  Within a lattice, tiles are listed
+// in groups of eight tile rows, column by column, so that tile list position
+// b runs on XCD b mod 8 and a whole row of tiles stays on one XCD (the same
+// order as the single-lattice kernel).  A block reads its tile and its
+// lattice's descriptor with scalar loads and runs the same site body as the
+// single-lattice kernel, so a batch member gives bit-for-bit the result of
+// the single-lattice call with the same seed.
+//
+// Step loop.  One sample period (sample_every step kernels, the sampling
+// kernels, one counter update) is captured once in a HIP graph and replayed;
+// the step index and the buffer parity come from a small control block in
+// device memory that the last node advances, so no kernel arguments change
+// between replays and no kernel waits on another workgroup.
+#include <math.h>
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "internal.h"
+
+namespace lbm {
+
+struct BatchTile {
+    int32_t lat;
+    int16_t tx, ty;
+};
+
+struct LatDesc {
+    StepArgs a;
+    void *buf[2];
+    float B;            // CIL B for zeta
+    int32_t mt_begin;   // first moments tile
+    int32_t mt_count;   // moments tiles of this lattice
+    int32_t nrb;        // moments row blocks
+    int64_t col_off;    // offset of this lattice's column partials
+    int64_t cm_off;     // offset of this lattice's column means
+};
+
+struct MomTile {
+    int32_t lat;
+    int16_t cx, cy;
+};
+
+struct Ctrl {
+    int64_t t0;      // absolute step index of the next step
+    int64_t k0;      // steps done in this sweep (buffer parity)
+    int64_t sample;  // index of the next sample
+    int64_t pad;
+};
+
+constexpr int kMomRows = 16;
+
+// ---------------------------------------------------------------------------
+// Step kernel over the tile list.
+// ---------------------------------------------------------------------------
+template <int M, int F>
+__global__ __launch_bounds__(256) void k_batch_step(const BatchTile *__restrict__ tiles,
+                                                    const LatDesc *__restrict__ lats,
+                                                    const Ctrl *__restrict__ ctrl, int node)
+{
+    const BatchTile tl = tiles[blockIdx.x];
+    const LatDesc &L = lats[tl.lat];
+    const StepArgs a = L.a;
+    const int64_t t = ctrl->t0 + node;
+    const int par = (int)((ctrl->k0 + node) & 1);
+    const float *__restrict__ src = (const float *)L.buf[par];
+    float *__restrict__ dst = (float *)L.buf[par ^ 1];
+    const int x = tl.tx * blockDim.x + threadIdx.x;
+    const int y = tl.ty * blockDim.y + threadIdx.y;
+    if (x >= a.nx || y >= a.ny)
+        return;
+    const uint32_t plane = (uint32_t)a.plane;
+    const PullSources32 g_src = pull_sources32(a, x, y);
+    float f[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        f[i] = ld32(src + (size_t)i * plane, g_src.idx[i]);
+    float rho, jx, jy, ux, uy;
+    site_moments(f, rho, jx, jy);
+    local_ustar<M>(a, rho, jx, jy, ux, uy);
+    site_collide<F>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x,
+                    (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32));
+    const uint32_t own = g_src.idx[0];
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        st32(dst + (size_t)i * plane, own, f[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Sampling: per moments tile (256 columns x 16 rows of one lattice) FP64
+// partial sums of M, Jx, Jy, sum |j|, nonfinite and per-column density sums
+// of the streamed populations; then per lattice the fixed-order totals.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double bwave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_batch_moments(const MomTile *__restrict__ mt, const LatDesc *__restrict__ lats,
+                                                       const Ctrl *__restrict__ ctrl, int node,
+                                                       double *__restrict__ part, double *__restrict__ colpart)
+{
+    __shared__ double lds[4][5];
+    const MomTile m = mt[blockIdx.x];
+    const LatDesc &L = lats[m.lat];
+    const StepArgs a = L.a;
+    const int par = (int)((ctrl->k0 + node) & 1);
+    const float *__restrict__ src = (const float *)L.buf[par];
+    const int x = m.cx * 256 + threadIdx.x;
+    const int yb = m.cy * kMomRows;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (x < a.nx) {
+        double col = 0.0;
+        const int ye = min(yb + kMomRows, a.ny);
+        for (int y = yb; y < ye; ++y) {
+            const PullSources32 g = pull_sources32(a, x, y);
+            float f[7];
+            bool finite = true;
+#pragma unroll
+            for (int i = 0; i < 7; ++i) {
+                f[i] = ld32(src + (size_t)i * (uint32_t)a.plane, g.idx[i]);
+                finite = finite && isfinite(f[i]);
+            }
+            float rho, jx, jy;
+            site_moments(f, rho, jx, jy);
+            const double dx = jx, dy = jy;
+            acc[0] += (double)rho;
+            acc[1] += dx;
+            acc[2] += dy;
+            acc[3] += sqrt(dx * dx + dy * dy);
+            acc[4] += finite ? 0.0 : 1.0;
+            col += (double)rho;
+        }
+        colpart[L.col_off + (int64_t)m.cy * a.nx + x] = col;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+        acc[k] = bwave_sum(acc[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            lds[w][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            part[(int64_t)blockIdx.x * 5 + k] = ((lds[0][k] + lds[1][k]) + lds[2][k]) + lds[3][k];
+}
+
+// One block per lattice: totals of its tiles, column means, their variance;
+// writes 8 doubles {M, Jx, Jy, sum|j|, nonfinite, mean, var, step} of sample s.
+__global__ __launch_bounds__(256) void k_batch_final(const LatDesc *__restrict__ lats, const Ctrl *__restrict__ ctrl,
+                                                     int node, const double *__restrict__ part,
+                                                     const double *__restrict__ colpart, double *__restrict__ colmean,
+                                                     double *__restrict__ results, int n_samples)
+{
+    __shared__ double lds[4][6];
+    __shared__ double mean_s;
+    const LatDesc &L = lats[blockIdx.x];
+    const int nx = L.a.nx, ny = L.a.ny;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < L.mt_count; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            v[k] += part[(int64_t)(L.mt_begin + b) * 5 + k];
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+        double c = 0.0;
+        for (int r = 0; r < L.nrb; ++r)
+            c += colpart[L.col_off + (int64_t)r * nx + x];
+        c /= (double)ny;
+        colmean[L.cm_off + x] = c;
+        v[5] += c;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        v[k] = bwave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            lds[w][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        mean_s = (((lds[0][5] + lds[1][5]) + lds[2][5]) + lds[3][5]) / (double)nx;
+    __syncthreads();
+    const double mean = mean_s;
+    double q = 0.0;
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+        const double d = colmean[L.cm_off + x] - mean;
+        q += d * d;
+    }
+    q = bwave_sum(q);
+    __shared__ double lq[4];
+    if (lane == 0)
+        lq[w] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t s = ctrl->sample;
+        if (s < n_samples) {
+            double *r = results + ((int64_t)blockIdx.x * n_samples + s) * 8;
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+                r[k] = ((lds[0][k] + lds[1][k]) + lds[2][k]) + lds[3][k];
+            r[5] = mean;
+            r[6] = (((lq[0] + lq[1]) + lq[2]) + lq[3]) / (double)nx;
+            r[7] = (double)(ctrl->t0 + node);
+        }
+    }
+}
+
+__global__ void k_batch_advance(Ctrl *ctrl, int64_t period)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctrl->t0 += period;
+        ctrl->k0 += period;
+        ctrl->sample += 1;
+    }
+}
+
+__global__ void k_batch_set_ctrl(Ctrl *ctrl, int64_t t0)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctrl->t0 = t0;
+        ctrl->k0 = 0;
+        ctrl->sample = 0;
+        ctrl->pad = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side: layout of the workspace, tile lists, tile-shape tuning.
+// ---------------------------------------------------------------------------
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t lat, tiles, mtiles, ctrl, part, colpart, colmean, results, total;
+    int64_t n_tiles, n_mtiles, colpart_n, colmean_n;
+};
+
+static const int kShapes[3][2] = {{256, 1}, {128, 2}, {64, 4}};
+
+static int64_t count_tiles(const lbm_params *ps, int n, int tx, int ty)
+{
+    int64_t c = 0;
+    for (int l = 0; l < n; ++l) {
+        const int64_t ntx = (ps[l].nx + tx - 1) / tx, nty = (ps[l].ny + ty - 1) / ty;
+        c += ntx * ((nty + 7) / 8) * 8;  // rows padded to whole groups of eight
+    }
+    return c;
+}
+
+static Layout layout(const lbm_params *ps, int n, int64_t n_samples)
+{
+    Layout L{};
+    int64_t max_tiles = 0;
+    for (auto &sh : kShapes)
+        max_tiles = std::max(max_tiles, count_tiles(ps, n, sh[0], sh[1]));
+    L.n_tiles = max_tiles;
+    L.n_mtiles = 0;
+    L.colpart_n = 0;
+    L.colmean_n = 0;
+    for (int l = 0; l < n; ++l) {
+        const int64_t cx = (ps[l].nx + 255) / 256, cy = (ps[l].ny + kMomRows - 1) / kMomRows;
+        L.n_mtiles += cx * cy;
+        L.colpart_n += cy * ps[l].nx;
+        L.colmean_n += ps[l].nx;
+    }
+    size_t off = 0;
+    L.lat = off;
+    off = align256(off + sizeof(LatDesc) * n);
+    L.tiles = off;
+    off = align256(off + sizeof(BatchTile) * L.n_tiles);
+    L.mtiles = off;
+    off = align256(off + sizeof(MomTile) * L.n_mtiles);
+    L.ctrl = off;
+    off = align256(off + sizeof(Ctrl));
+    L.part = off;
+    off = align256(off + sizeof(double) * 5 * L.n_mtiles);
+    L.colpart = off;
+    off = align256(off + sizeof(double) * L.colpart_n);
+    L.colmean = off;
+    off = align256(off + sizeof(double) * L.colmean_n);
+    L.results = off;
+    off = align256(off + sizeof(double) * 8 * (size_t)n * (size_t)std::max<int64_t>(n_samples, 1));
+    L.total = off;
+    return L;
+}
+
+// Tile list of one shape, row-group order per lattice; tiles in the padding
+// rows of a lattice's last group point past the lattice and exit at once.
+static std::vector<BatchTile> build_tiles(const lbm_params *ps, int n, int tx, int ty)
+{
+    std::vector<BatchTile> v;
+    for (int l = 0; l < n; ++l) {
+        const int ntx = (ps[l].nx + tx - 1) / tx, nty = (ps[l].ny + ty - 1) / ty;
+        for (int g = 0; g < (nty + 7) / 8; ++g)
+            for (int c = 0; c < ntx; ++c)
+                for (int r = 0; r < 8; ++r)
+                    v.push_back(BatchTile{l, (int16_t)c, (int16_t)(8 * g + r)});
+    }
+    return v;
+}
+
+static int sweep_flags(const lbm_params *ps, int n)
+{
+    const int f = step_flags(make_step_args(ps[0], ps[0].nx));
+    for (int l = 1; l < n; ++l)
+        if (step_flags(make_step_args(ps[l], ps[l].nx)) != f)
+            return -1;
+    return f;
+}
+
+template <int M, int F>
+static hipError_t launch_batch_step_mf(int shape, int64_t ntiles, const BatchTile *tiles, const LatDesc *lats,
+                                       const Ctrl *ctrl, int node, hipStream_t s)
+{
+    dim3 blk(kShapes[shape][0], kShapes[shape][1]);
+    hipLaunchKernelGGL((k_batch_step<M, F>), dim3((unsigned)ntiles), blk, 0, s, tiles, lats, ctrl, node);
+    return hipGetLastError();
+}
+
+template <int M>
+static hipError_t launch_batch_step_m(int flags, int shape, int64_t ntiles, const BatchTile *tiles,
+                                      const LatDesc *lats, const Ctrl *ctrl, int node, hipStream_t s)
+{
+    switch (flags) {
+    case 0: return launch_batch_step_mf<M, 0>(shape, ntiles, tiles, lats, ctrl, node, s);
+    case kUnitTau: return launch_batch_step_mf<M, kUnitTau>(shape, ntiles, tiles, lats, ctrl, node, s);
+    case kNoisy: return launch_batch_step_mf<M, kNoisy>(shape, ntiles, tiles, lats, ctrl, node, s);
+    default: return launch_batch_step_mf<M, kUnitTau | kNoisy>(shape, ntiles, tiles, lats, ctrl, node, s);
+    }
+}
+
+static hipError_t launch_batch_step(int model, int flags, int shape, int64_t ntiles, const BatchTile *tiles,
+                                    const LatDesc *lats, const Ctrl *ctrl, int node, hipStream_t s)
+{
+    if (model == kCil)
+        return launch_batch_step_m<kCil>(flags, shape, ntiles, tiles, lats, ctrl, node, s);
+    return launch_batch_step_m<kPassive>(flags, shape, ntiles, tiles, lats, ctrl, node, s);
+}
+
+// Tuned tile shape per batch signature (arch + multiset of lattice sizes +
+// model + flags), kept for the life of the process.
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tuned;
+
+static std::string signature(const lbm_params *ps, int n, int flags)
+{
+    std::map<std::pair<int, int>, int> hist;
+    for (int l = 0; l < n; ++l)
+        hist[{ps[l].nx, ps[l].ny}]++;
+    std::string s = "gfx950/m" + std::to_string(ps[0].model) + "/f" + std::to_string(flags);
+    for (auto &h : hist)
+        s += "/" + std::to_string(h.first.first) + "x" + std::to_string(h.first.second) + ":" +
+             std::to_string(h.second);
+    return s;
+}
+
+}  // namespace lbm
 
 using namespace lbm;
 
 extern "C" {
 
-size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n)
+size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samples)
 {
-    (void)ps;
-    (void)n;
-    return 0;
+    if (!ps || n <= 0 || n_samples < 0)
+        return 0;
+    return layout(ps, n, n_samples).total;
 }
 
 int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o, void *const *bufs, void *ws,
                         size_t ws_bytes, void *stream, lbm_obs *out)
 {
-    (void)ps; (void)n; (void)o; (void)bufs; (void)ws; (void)ws_bytes; (void)stream; (void)out;
-    return fail(LBM_EUNSUPPORTED, "lbm_sweep_batch not built yet");
+    if (!ps || n <= 0 || !o || !bufs || !ws || !out)
+        return fail(LBM_EINVAL, "null argument or empty batch");
+    if (o->n_steps < 0 || o->sample_every < 0 || o->step0 < 0)
+        return fail(LBM_EINVAL, "negative step counts");
+    for (int l = 0; l < n; ++l) {
+        int32_t rc = validate_params(&ps[l], ps[l].nx);
+        if (rc)
+            return fail(rc, "lattice " + std::to_string(l) + ": " + lbm_last_error());
+        if (ps[l].storage != LBM_F32)
+            return fail(LBM_EUNSUPPORTED, "batched sweeps take F32 storage");
+        if (ps[l].model == LBM_MIPS)
+            return fail(LBM_EUNSUPPORTED, "batched sweeps take the local models (CIL, passive)");
+        if (ps[l].model != ps[0].model)
+            return fail(LBM_EINVAL, "all lattices of a batch must use the same model");
+        if ((uint64_t)ps[l].nx * ps[l].ny * 7ull >= (1ull << 30))
+            return fail(LBM_EINVAL, "batch lattices must hold fewer than 2^30 populations");
+        if (!bufs[2 * l] || !bufs[2 * l + 1] || bufs[2 * l] == bufs[2 * l + 1])
+            return fail(LBM_EINVAL, "lattice " + std::to_string(l) + ": null or equal buffers");
+        if (ps[l].ny > 32760 || ps[l].nx > 64 * 32760)
+            return fail(LBM_EINVAL, "batch lattices need ny <= 32760 and nx <= 2096640 (16-bit tile indices)");
+    }
+    const int flags = sweep_flags(ps, n);
+    if (flags < 0)
+        return fail(LBM_EINVAL, "all lattices of a batch must agree on tau == 1 and on sigma == 0");
+    const int64_t period = o->sample_every > 0 ? o->sample_every : std::max<int64_t>(o->n_steps, 1);
+    const int64_t n_samples = o->sample_every > 0 ? o->n_steps / o->sample_every : 1;
+    if (o->sample_every > 0 && o->n_steps % o->sample_every != 0)
+        return fail(LBM_EINVAL, "n_steps must be a multiple of sample_every");
+    const Layout Ly = layout(ps, n, n_samples);
+    if (ws_bytes < Ly.total)
+        return fail(LBM_EINVAL, "workspace smaller than lbm_sweep_workspace_bytes()");
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    LatDesc *d_lat = (LatDesc *)(w + Ly.lat);
+    BatchTile *d_tiles = (BatchTile *)(w + Ly.tiles);
+    MomTile *d_mt = (MomTile *)(w + Ly.mtiles);
+    Ctrl *d_ctrl = (Ctrl *)(w + Ly.ctrl);
+    double *d_part = (double *)(w + Ly.part);
+    double *d_colpart = (double *)(w + Ly.colpart);
+    double *d_colmean = (double *)(w + Ly.colmean);
+    double *d_results = (double *)(w + Ly.results);
+
+    // descriptors and the moments tile list
+    std::vector<LatDesc> lat(n);
+    std::vector<MomTile> mt;
+    int64_t col_off = 0, cm_off = 0;
+    for (int l = 0; l < n; ++l) {
+        LatDesc &D = lat[l];
+        D.a = make_step_args(ps[l], ps[l].nx);
+        D.buf[0] = bufs[2 * l];
+        D.buf[1] = bufs[2 * l + 1];
+        D.B = (float)ps[l].B;
+        const int cx = (ps[l].nx + 255) / 256, cy = (ps[l].ny + kMomRows - 1) / kMomRows;
+        D.mt_begin = (int32_t)mt.size();
+        D.mt_count = cx * cy;
+        D.nrb = cy;
+        D.col_off = col_off;
+        D.cm_off = cm_off;
+        for (int j = 0; j < cy; ++j)
+            for (int i = 0; i < cx; ++i)
+                mt.push_back(MomTile{l, (int16_t)i, (int16_t)j});
+        col_off += (int64_t)cy * ps[l].nx;
+        cm_off += ps[l].nx;
+    }
+    LBM_HIP_TRY(hipMemcpyAsync(d_lat, lat.data(), sizeof(LatDesc) * n, hipMemcpyHostToDevice, s));
+    LBM_HIP_TRY(hipMemcpyAsync(d_mt, mt.data(), sizeof(MomTile) * mt.size(), hipMemcpyHostToDevice, s));
+
+    // tile shape: caller's choice (tile_rows 1, 2, 4 -> 256x1, 128x2, 64x4),
+    // else the tuned one for this signature, else tune now: every tuning
+    // launch reads the state in the first buffer of each lattice and writes
+    // the second (free until the sweep starts), so the state is unchanged.
+    int shape = -1;
+    if (o->tile_rows == 1) shape = 0;
+    else if (o->tile_rows == 2) shape = 1;
+    else if (o->tile_rows == 4) shape = 2;
+    else if (o->tile_rows != 0)
+        return fail(LBM_EINVAL, "tile_rows must be 0, 1, 2 or 4");
+    const std::string sig = signature(ps, n, flags);
+    if (shape < 0) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(sig);
+        if (it != g_tuned.end())
+            shape = it->second;
+    }
+    std::vector<std::vector<BatchTile>> lists(3);
+    for (int k = 0; k < 3; ++k)
+        lists[k] = build_tiles(ps, n, kShapes[k][0], kShapes[k][1]);
+    if (shape < 0) {
+        shape = 0;
+        float best = 1e30f;
+        hipEvent_t e0, e1;
+        LBM_HIP_TRY(hipEventCreate(&e0));
+        LBM_HIP_TRY(hipEventCreate(&e1));
+        for (int k = 0; k < 3; ++k) {
+            LBM_HIP_TRY(hipMemcpyAsync(d_tiles, lists[k].data(), sizeof(BatchTile) * lists[k].size(),
+                                       hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_batch_set_ctrl, dim3(1), dim3(64), 0, s, d_ctrl, (int64_t)0);
+            float ms = 0.0f;
+            for (int rep = 0; rep < 2; ++rep) {
+                LBM_HIP_TRY(hipEventRecord(e0, s));
+                for (int rep4 = 0; rep4 < 4; ++rep4)  // node 0: first buffer -> second buffer
+                    LBM_HIP_TRY(launch_batch_step(ps[0].model, flags, k, (int64_t)lists[k].size(), d_tiles, d_lat,
+                                                  d_ctrl, 0, s));
+                LBM_HIP_TRY(hipEventRecord(e1, s));
+                LBM_HIP_TRY(hipEventSynchronize(e1));
+                float m = 0.0f;
+                LBM_HIP_TRY(hipEventElapsedTime(&m, e0, e1));
+                ms = rep == 0 ? m : std::min(ms, m);
+            }
+            if (ms < best) {
+                best = ms;
+                shape = k;
+            }
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[sig] = shape;
+    }
+    LBM_HIP_TRY(hipMemcpyAsync(d_tiles, lists[shape].data(), sizeof(BatchTile) * lists[shape].size(),
+                               hipMemcpyHostToDevice, s));
+    const int64_t ntiles = (int64_t)lists[shape].size();
+    const int64_t nmt = (int64_t)mt.size();
+    hipLaunchKernelGGL(k_batch_set_ctrl, dim3(1), dim3(64), 0, s, d_ctrl, (int64_t)o->step0);
+    LBM_HIP_TRY(hipGetLastError());
+
+    auto enqueue_period = [&](int64_t steps, bool sample) -> hipError_t {
+        for (int64_t node = 0; node < steps; ++node) {
+            hipError_t e = launch_batch_step(ps[0].model, flags, shape, ntiles, d_tiles, d_lat, d_ctrl, (int)node, s);
+            if (e != hipSuccess)
+                return e;
+        }
+        if (sample) {
+            hipLaunchKernelGGL(k_batch_moments, dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat, d_ctrl, (int)steps,
+                               d_part, d_colpart);
+            hipLaunchKernelGGL(k_batch_final, dim3((unsigned)n), dim3(256), 0, s, d_lat, d_ctrl, (int)steps, d_part,
+                               d_colpart, d_colmean, d_results, (int)n_samples);
+        }
+        hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, d_ctrl, steps);
+        return hipGetLastError();
+    };
+
+    const int64_t n_periods = o->n_steps / period;
+    const int64_t rest = o->n_steps - n_periods * period;
+    if (n_periods > 0) {
+        if (o->use_graph) {
+            // record one period on a private stream (the caller's may be the
+            // legacy null stream, which cannot be captured), replay it on the
+            // caller's stream
+            hipGraph_t g;
+            hipGraphExec_t ge;
+            hipStream_t cap;
+            LBM_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            hipStream_t saved = s;
+            s = cap;
+            hipError_t be = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            hipError_t ce = be == hipSuccess ? enqueue_period(period, true) : be;
+            hipError_t ee = be == hipSuccess ? hipStreamEndCapture(cap, &g) : be;
+            s = saved;
+            hipStreamDestroy(cap);
+            if (ce != hipSuccess)
+                return hip_fail(ce, "lbm_sweep_batch capture");
+            LBM_HIP_TRY(ee);
+            LBM_HIP_TRY(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+            for (int64_t p = 0; p < n_periods; ++p)
+                LBM_HIP_TRY(hipGraphLaunch(ge, s));
+            LBM_HIP_TRY(hipStreamSynchronize(s));
+            hipGraphExecDestroy(ge);
+            hipGraphDestroy(g);
+        } else {
+            for (int64_t p = 0; p < n_periods; ++p)
+                LBM_HIP_TRY(enqueue_period(period, true));
+        }
+    }
+    if (rest > 0 || o->n_steps == 0)
+        LBM_HIP_TRY(enqueue_period(rest, o->n_steps == 0));
+
+    std::vector<double> res((size_t)n * n_samples * 8);
+    LBM_HIP_TRY(hipMemcpyAsync(res.data(), d_results, sizeof(double) * res.size(), hipMemcpyDeviceToHost, s));
+    LBM_HIP_TRY(hipStreamSynchronize(s));
+    bool bad = false;
+    for (int l = 0; l < n; ++l)
+        for (int64_t k = 0; k < n_samples; ++k) {
+            const double *r = &res[((size_t)l * n_samples + k) * 8];
+            lbm_obs &ob = out[(size_t)l * n_samples + k];
+            finish_obs(ps[l], r, (int64_t)r[7], &ob);
+            bad = bad || ob.nonfinite;
+        }
+    if (bad)
+        return fail(LBM_ENONFINITE, "non-finite populations in a batch sample");
+    return LBM_OK;
 }
 
-}
+}  // extern "C"

@@ -83,3 +83,37 @@ def test_null_context_is_a_state_error():
     assert L._lib.lbm_moments(None, None, None, None, None) == L.LBM_ESTATE
     assert L._lib.lbm_destroy(None) == L.LBM_ESTATE
     assert L._lib.lbm_current_buffer(None) == L.LBM_ESTATE
+
+
+def _sweep(L, plist, n_steps=10, every=0, ws_bytes=None):
+    n = len(plist)
+    arr = (L.lbm_params * n)(*plist)
+    bufs = (ctypes.c_void_p * (2 * n))(*[ctypes.c_void_p(16 * (k + 1)) for k in range(2 * n)])
+    need = L._lib.lbm_sweep_workspace_bytes(arr, n, max(1, n_steps // every if every else 1))
+    opts = L.lbm_sweep_opts(n_steps, every, 0, 0, 1)
+    out = (L.lbm_obs * (n * 4))()
+    return L._lib.lbm_sweep_batch(arr, n, ctypes.byref(opts), bufs, ctypes.c_void_p(64),
+                                  need if ws_bytes is None else ws_bytes, None, out)
+
+
+def test_sweep_batch_rejects_invalid_batches():
+    import paper_1902_00530_amd as L
+    good = L.make_params(128, 128, L.LBM_CIL, tau=1.0, sigma=0.05, A=0.1, B=0.3)
+    assert _sweep(L, [good, L.make_params(128, 128, L.LBM_CIL, tau=2.0, sigma=0.05)]) == L.LBM_EINVAL
+    assert "tau" in L.lbm_last_error()
+    assert _sweep(L, [good, L.make_params(64, 64, L.LBM_CIL, tau=1.0, sigma=0.0)]) == L.LBM_EINVAL
+    assert _sweep(L, [L.make_params(128, 128, L.LBM_MIPS, rho_star=1.0)]) == L.LBM_EUNSUPPORTED
+    assert _sweep(L, [L.make_params(128, 128, L.LBM_CIL, storage=L.LBM_BF16_DEV)]) == L.LBM_EUNSUPPORTED
+    assert _sweep(L, [good, L.make_params(128, 128, L.LBM_PASSIVE, tau=1.0, sigma=0.05)]) == L.LBM_EINVAL
+    assert _sweep(L, [good], n_steps=10, every=3) == L.LBM_EINVAL
+    assert _sweep(L, [good], ws_bytes=100) == L.LBM_EINVAL
+    assert _sweep(L, [L.make_params(128, 127, L.LBM_CIL)]) == L.LBM_EINVAL
+    assert L._lib.lbm_sweep_workspace_bytes(None, 1, 1) == 0
+
+
+def test_sweep_workspace_grows_with_samples():
+    import paper_1902_00530_amd as L
+    arr = (L.lbm_params * 2)(L.make_params(128, 128, L.LBM_CIL), L.make_params(256, 192, L.LBM_CIL))
+    a = L._lib.lbm_sweep_workspace_bytes(arr, 2, 1)
+    b = L._lib.lbm_sweep_workspace_bytes(arr, 2, 100)
+    assert 0 < a < b and b - a >= 2 * 99 * 8 * 8 - 256

@@ -1,0 +1,126 @@
+"""Batched sweeps (lbm_sweep_batch) against single-lattice runs and the oracle.
+
+A batch member runs the same site body as the single-lattice kernel with its
+own seed and noise counters, so its state after the sweep must equal the
+single-lattice result bit for bit, for every work-tile shape and with or
+without graph replay; the FP64 samples use the same reduction tree as
+lbm_moments and must agree with it to rounding of the final divisions.
+"""
+import numpy as np
+import pytest
+
+import synth_inputs as SI
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from test_parity_gpu import _cfg, _oparams, _gparams, rel_err  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1902_00530_amd as lib
+    return lib
+
+
+def small_batch():
+    sizes = [(128, 192), (192, 128), (256, 256), (128, 128), (384, 130)]
+    cfgs = []
+    for l, (nx, ny) in enumerate(sizes):
+        cfgs.append(_cfg(SI.CIL, nx, ny, tau=1.0, sigma=4 / 70, A=0.125, B=0.3 * (0.2 + 0.2 * l),
+                         seed=SI.seed_for(2, l)))
+    return cfgs
+
+
+def init_states(L, cfgs):
+    states = []
+    for l, c in enumerate(cfgs):
+        lat = L.Lattice(_gparams(L, c), init=L.make_init(mode=1, rho_mean=0.3 + 0.3 * l, rho_spread=0.1))
+        torch.cuda.synchronize()
+        states.append(lat.state.clone())
+        lat.close()
+    return states
+
+
+def single_runs(L, cfgs, states, steps, sample_every=0):
+    finals, samples = [], []
+    for c, f0 in zip(cfgs, states):
+        lat = L.Lattice(_gparams(L, c))
+        lat.set_state(f0)
+        obs = []
+        if sample_every:
+            for _ in range(steps // sample_every):
+                lat.step(sample_every)
+                obs.append(lat.observables())
+        else:
+            lat.step(steps)
+            obs.append(lat.observables())
+        finals.append(lat.state.clone())
+        samples.append(obs)
+        lat.close()
+    return finals, samples
+
+
+@pytest.mark.parametrize("tile_rows,use_graph", [(1, 1), (2, 1), (4, 0), (0, 1)])
+def test_batch_member_equals_single_run(L, tile_rows, use_graph):
+    cfgs = small_batch()
+    states = init_states(L, cfgs)
+    steps, every = 37, 0
+    finals, samples = single_runs(L, cfgs, states, steps)
+    b = L.Batch([_gparams(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    out = b.run(steps, sample_every=every, tile_rows=tile_rows, use_graph=use_graph)
+    torch.cuda.synchronize()
+    for l in range(len(cfgs)):
+        assert torch.equal(b.state(l), finals[l]), l
+        o, s = out[l][0], samples[l][0]
+        assert o["step"] == steps
+        for k in ("M", "Jx", "Jy", "phi", "mean_speed", "zeta", "drho"):
+            assert abs(o[k] - s[k]) <= 1e-12 * max(1.0, abs(s[k])), (l, k, o[k], s[k])
+
+
+def test_batch_samples_and_resume(L):
+    cfgs = small_batch()
+    states = init_states(L, cfgs)
+    finals, samples = single_runs(L, cfgs, states, 40, sample_every=10)
+    b = L.Batch([_gparams(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    out1 = b.run(20, sample_every=10)
+    out2 = b.run(20, sample_every=10)   # continues the noise counters
+    for l in range(len(cfgs)):
+        got = out1[l] + out2[l]
+        assert [o["step"] for o in got] == [10, 20, 30, 40]
+        for o, s in zip(got, samples[l]):
+            assert abs(o["phi"] - s["phi"]) <= 1e-12 and abs(o["M"] - s["M"]) <= 1e-9 * s["M"]
+        assert torch.equal(b.state(l), finals[l])
+
+
+def test_batch_member_matches_oracle(L, orc):
+    cfgs = small_batch()[:2]
+    states = init_states(L, cfgs)
+    b = L.Batch([_gparams(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    b.run(3)
+    for l, c in enumerate(cfgs):
+        ref = orc.run(_oparams(orc, c), states[l].double().cpu().numpy(), 3)
+        assert rel_err(b.state(l).double().cpu().numpy(), ref) < 3e-6
+
+
+def test_batch_zero_steps_samples_initial_state(L):
+    cfgs = small_batch()[:2]
+    states = init_states(L, cfgs)
+    b = L.Batch([_gparams(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    out = b.run(0)
+    for l, c in enumerate(cfgs):
+        lat = L.Lattice(_gparams(L, c))
+        lat.set_state(states[l])
+        o = lat.observables()
+        lat.close()
+        assert out[l][0]["step"] == 0 and abs(out[l][0]["M"] - o["M"]) <= 1e-9 * o["M"]
