@@ -18,6 +18,8 @@ phase sweep against the same lattices run one by one) and the FP64 oracle
 timed on the host cores.
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -113,6 +115,30 @@ def time_batch(L, torch, cfgs, steps, warmup):
     return e0.elapsed_time(e1), [o[-1] for o in out]
 
 
+def source_fingerprint():
+    """sha256 over the library's kernel sources (names and contents)."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1902_00530_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the kernel sources as they are now (else None)."""
+    path = os.path.join(ROOT, "profiles", name)
+    try:
+        with open(path) as fh:
+            c = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_sha256") != source_fingerprint():
+        return None
+    return c
+
+
 def roofline(storage, sites_per_launch, per_launch_s, kernel):
     achieved = BYTES_PER_SITE[storage] * sites_per_launch / per_launch_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -170,6 +196,14 @@ def main():
         "phi": [round(o["phi"], 6) for o in obs],
         "wall_s": round(wall, 3),
     }
+
+    if mode == "batch" and args.workload == "cil1024x5" and args.storage == 0:
+        c = measured_traffic("counters_k_batch_step_cil_5x1024.json")
+        if c is not None:
+            line["roofline"]["traffic"] = round(c["traffic_bytes_per_launch"] / per_launch / 1e9, 1)
+            line["roofline"]["traffic_bytes_per_launch"] = c["traffic_bytes_per_launch"]
+            line["roofline"]["traffic_vs_algorithmic"] = round(
+                c["traffic_bytes_per_launch"] / c["algorithmic_bytes_per_launch"], 4)
 
     if not args.quick and args.workload == "cil1024x5" and args.storage == 0:
         var = {}
