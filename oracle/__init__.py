@@ -204,3 +204,25 @@ def stream(p, f):
     out = np.empty_like(f)
     lib().orc_stream(ctypes.byref(p), _dp(f), _dp(out))
     return out
+
+
+def coarsen(p, f, c):
+    """Coarse fields [3, ny/c, nx/c]: means over c x c blocks of rho, jx, jy
+    of the streamed populations of a stored state."""
+    rho, ux, uy = fields(p, f)
+    out = np.stack([rho, rho * ux, rho * uy])
+    return out.reshape(3, p.ny // c, c, p.nx // c, c).mean(axis=(2, 4))
+
+
+def lift(p, coarse, c):
+    """Stored state whose sites in each c x c block hold xi(rho, j/rho) of
+    the block (negative rho treated as 0)."""
+    ch, cw = coarse.shape[1], coarse.shape[2]
+    f = np.zeros((7, p.ny, p.nx))
+    for cy in range(ch):
+        for cx in range(cw):
+            r = max(coarse[0, cy, cx], 0.0)
+            ux = coarse[1, cy, cx] / r if r > 0 else 0.0
+            uy = coarse[2, cy, cx] / r if r > 0 else 0.0
+            f[:, cy * c:(cy + 1) * c, cx * c:(cx + 1) * c] = xi(r, ux, uy)[:, None, None]
+    return f
