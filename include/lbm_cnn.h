@@ -1,0 +1,90 @@
+/*
+ * lbm_cnn.h -- C ABI of the surrogate network and of the maps between
+ * populations and coarse fields (same library as lbm.h).
+ *
+ * The surrogate advances the coarse density and momentum fields (rho, jx, jy)
+ * of a lattice by a fixed number of lattice Boltzmann steps.  It is not part
+ * of the paper's method; the lattice Boltzmann step (lbm.h) is its data
+ * source and its judge.  Network: three 3x3 convolutions with circular
+ * padding (periodic lattice), cin -> 32 -> 32 -> 3 channels, ReLU after the
+ * first two, and a residual connection:
+ *     y = x[:, 0:3] + conv3(relu(conv2(relu(conv1(x))))).
+ * Tensors are NCHW float32 in device memory owned by the caller.  Weights
+ * are stored as bfloat16 bits (uint16) [out][in][3][3]; products are taken
+ * with the weights widened to float32 and summed in float32.  Biases are
+ * float32.  Every call enqueues work on the caller's stream (hipStream_t
+ * passed as void*) and never synchronises.  Errors as in lbm.h (LBM_EINVAL
+ * for bad shapes or null pointers, LBM_EHIP for runtime errors; message in
+ * lbm_last_error()).
+ */
+#ifndef LBM_CNN_H
+#define LBM_CNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lbm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_cnn_shape {
+    int32_t n;       /* samples (<= 65535) */
+    int32_t cin;     /* input channels, 3..32 (the first three are the fields) */
+    int32_t hidden;  /* hidden channels: must be 32 */
+    int32_t cout;    /* output channels: must be 3 */
+    int32_t h, w;    /* coarse field size (periodic) */
+} lbm_cnn_shape;
+
+typedef struct lbm_cnn_params {
+    const uint16_t *w[3]; /* bf16 weights [hidden][cin][3][3], [hidden][hidden][3][3], [cout][hidden][3][3] */
+    const float *b[3];    /* biases [hidden], [hidden], [cout] */
+} lbm_cnn_params;
+
+typedef struct lbm_cnn_grads {
+    float *w[3]; /* float32, shapes of lbm_cnn_params.w */
+    float *b[3];
+} lbm_cnn_grads;
+
+/* Device workspace bytes of lbm_cnn_forward / lbm_cnn_backward (0 if the shape
+ * is invalid). */
+size_t lbm_cnn_workspace_bytes(const lbm_cnn_shape *s);
+
+/* Forward pass.  x [n][cin][h][w]; a1, a2 [n][32][h][w] receive the hidden
+ * activations (after ReLU, kept for the backward pass); y [n][3][h][w]. */
+int32_t lbm_cnn_forward(const lbm_cnn_shape *s, const lbm_cnn_params *p, const float *x, float *a1, float *a2,
+                        float *y, void *ws, size_t ws_bytes, void *stream);
+
+/* Loss and gradients of the mean squared error mean((y - target)^2) for the
+ * forward pass that produced a1, a2, y from x.  g receives the gradients
+ * (overwritten); loss is one device float. */
+int32_t lbm_cnn_backward(const lbm_cnn_shape *s, const lbm_cnn_params *p, const float *x, const float *a1,
+                         const float *a2, const float *y, const float *target, const lbm_cnn_grads *g,
+                         float *loss, void *ws, size_t ws_bytes, void *stream);
+
+/* One Adam step (Kingma & Ba, algorithm 1) at step t >= 1 on a float32 master
+ * tensor theta[count] with moments m, v and gradient grad; with bf16_out the
+ * updated theta is also written as bfloat16 (round to nearest even). */
+int32_t lbm_cnn_adam(float *theta, float *m, float *v, const float *grad, int64_t count, float lr, float beta1,
+                     float beta2, float eps, int64_t t, uint16_t *bf16_out, void *stream);
+
+/* In place x[i][ch][..] = x[i][ch][..] * scale[ch] + shift[ch] for the first
+ * nc of c channels of n samples of hw pixels (normalisation of the fields). */
+int32_t lbm_channel_affine(float *x, int32_t n, int32_t c, int32_t nc, int64_t hw, const float *scale,
+                           const float *shift, void *stream);
+
+/* Coarse fields of a stored F32 state f [7][ny][nx] (pitch nx): out
+ * [3][ny/c][nx/c] = means over c x c blocks of sites of rho, jx, jy of the
+ * streamed populations.  c divides nx and ny and is 1 or even. */
+int32_t lbm_coarsen(const lbm_params *p, const float *f, int32_t c, float *out, void *stream);
+
+/* Stored F32 state f [7][ny][nx] from coarse fields [3][ny/c][nx/c]: every
+ * site of a block gets xi(rho, j/rho) of its block (steady state eq.
+ * fssD2Q7 with u* = u; negative rho is treated as 0). */
+int32_t lbm_lift(const lbm_params *p, const float *coarse, int32_t c, float *f, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_CNN_H */

@@ -48,6 +48,19 @@ class lbm_sweep_opts(ctypes.Structure):
                 ("tile_rows", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
+class lbm_cnn_shape(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("cin", ctypes.c_int32), ("hidden", ctypes.c_int32),
+                ("cout", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32)]
+
+
+class lbm_cnn_params(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p * 3), ("b", ctypes.c_void_p * 3)]
+
+
+class lbm_cnn_grads(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p * 3), ("b", ctypes.c_void_p * 3)]
+
+
 class LbmError(RuntimeError):
     def __init__(self, code, where):
         super().__init__(f"{where} failed ({code}): {lbm_last_error()}")
@@ -74,6 +87,17 @@ _SIGS = {
     "lbm_sweep_workspace_bytes": (ctypes.c_size_t, [_P(lbm_params), ctypes.c_int32, ctypes.c_int64]),
     "lbm_sweep_batch": (ctypes.c_int32, [_P(lbm_params), ctypes.c_int32, _P(lbm_sweep_opts), _P(_vp), _vp,
                                          ctypes.c_size_t, _vp, _P(lbm_obs)]),
+    "lbm_cnn_workspace_bytes": (ctypes.c_size_t, [_P(lbm_cnn_shape)]),
+    "lbm_cnn_forward": (ctypes.c_int32, [_P(lbm_cnn_shape), _P(lbm_cnn_params), _vp, _vp, _vp, _vp, _vp,
+                                         ctypes.c_size_t, _vp]),
+    "lbm_cnn_backward": (ctypes.c_int32, [_P(lbm_cnn_shape), _P(lbm_cnn_params), _vp, _vp, _vp, _vp, _vp,
+                                          _P(lbm_cnn_grads), _vp, _vp, ctypes.c_size_t, _vp]),
+    "lbm_cnn_adam": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_float, ctypes.c_int64, _vp, _vp]),
+    "lbm_channel_affine": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                            _vp, _vp, _vp]),
+    "lbm_coarsen": (ctypes.c_int32, [_P(lbm_params), _vp, ctypes.c_int32, _vp, _vp]),
+    "lbm_lift": (ctypes.c_int32, [_P(lbm_params), _vp, ctypes.c_int32, _vp, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -143,6 +167,38 @@ def lbm_sweep_workspace_bytes(params_array, n, n_samples):
 def lbm_sweep_batch(params_array, n, opts, bufs, ws, ws_bytes, stream, out):
     return _check(_lib.lbm_sweep_batch(params_array, int(n), ctypes.byref(opts), bufs, ws, int(ws_bytes), stream,
                                        out), "lbm_sweep_batch")
+
+
+def lbm_cnn_workspace_bytes(shape):
+    return _lib.lbm_cnn_workspace_bytes(ctypes.byref(shape))
+
+
+def lbm_cnn_forward(shape, params, x, a1, a2, y, ws, ws_bytes, stream):
+    return _check(_lib.lbm_cnn_forward(ctypes.byref(shape), ctypes.byref(params), x, a1, a2, y, ws, int(ws_bytes),
+                                       stream), "lbm_cnn_forward")
+
+
+def lbm_cnn_backward(shape, params, x, a1, a2, y, target, grads, loss, ws, ws_bytes, stream):
+    return _check(_lib.lbm_cnn_backward(ctypes.byref(shape), ctypes.byref(params), x, a1, a2, y, target,
+                                        ctypes.byref(grads), loss, ws, int(ws_bytes), stream), "lbm_cnn_backward")
+
+
+def lbm_cnn_adam(theta, m, v, grad, count, lr, beta1, beta2, eps, t, bf16_out, stream):
+    return _check(_lib.lbm_cnn_adam(theta, m, v, grad, int(count), float(lr), float(beta1), float(beta2),
+                                    float(eps), int(t), bf16_out, stream), "lbm_cnn_adam")
+
+
+def lbm_channel_affine(x, n, c, nc, hw, scale, shift, stream):
+    return _check(_lib.lbm_channel_affine(x, int(n), int(c), int(nc), int(hw), scale, shift, stream),
+                  "lbm_channel_affine")
+
+
+def lbm_coarsen(params, f, c, out, stream):
+    return _check(_lib.lbm_coarsen(ctypes.byref(params), f, int(c), out, stream), "lbm_coarsen")
+
+
+def lbm_lift(params, coarse, c, f, stream):
+    return _check(_lib.lbm_lift(ctypes.byref(params), coarse, int(c), f, stream), "lbm_lift")
 
 
 class Batch:

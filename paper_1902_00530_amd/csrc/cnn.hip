@@ -1,0 +1,524 @@
+// Surrogate network kernels: a three-layer convolutional net (3x3 kernels,
+// circular padding, ReLU, residual on the predicted fields) that advances the
+// coarse density and momentum fields of a lattice by k steps, its training
+// (mean-squared error, backward pass, Adam) and the maps between populations
+// and coarse fields.  Not part of the paper; it is judged by the lattice
+// Boltzmann step itself.
+//
+// Layout: activations NCHW float32; weights stored as bfloat16 (the Adam
+// step keeps float32 master copies) and widened once per pass to float32, so
+// every product is a bf16 x f32 -> f32 product with float32 accumulation.
+// Convolutions: one block = one sample x a 16 x 16 pixel tile x all output
+// channels; the input tile with its one-pixel halo sits in LDS, weights are
+// read with wave-uniform addresses (scalar loads), each thread keeps one
+// pixel's output channels in registers.  Reductions (weight gradients, loss)
+// use fixed partitions and orders, so results are deterministic.
+#include <math.h>
+
+#include "../../include/lbm_cnn.h"
+#include "internal.h"
+
+namespace lbm {
+
+constexpr int kTile = 16;
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution.  TR = 0: y[n,o,i,j] = b[o] + sum_c sum_k w[o,c,k]
+// x[n,c,i+ky-1,j+kx-1].  TR = 1 (input gradient of a convolution with
+// weights w[Cin_orig=co][Cout_orig=ci]): y[n,c,..] = sum_o sum_k
+// w[o,c,8-k] x[n,o,..], i.e. the same sum with transposed, flipped weights.
+// Epilogue in order: bias, ReLU, + resid[n, o] (first co channels of a
+// tensor with resid_c channels), * (mask[n, o] > 0).
+// ---------------------------------------------------------------------------
+template <int CO, int TR>
+__global__ __launch_bounds__(256) void k_conv3x3(const float *__restrict__ x, int ci_n, const float *__restrict__ w,
+                                                 const float *__restrict__ bias, const float *__restrict__ resid,
+                                                 int resid_c, const float *__restrict__ mask, int relu,
+                                                 float *__restrict__ y, int H, int W)
+{
+    extern __shared__ float s_in[];  // [ci_n][18][18]
+    constexpr int L = kTile + 2;
+    const int n = blockIdx.z;
+    const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
+    const int tid = threadIdx.x;
+    const size_t HW = (size_t)H * W;
+    const float *xn = x + (size_t)n * ci_n * HW;
+    for (int e = tid; e < ci_n * L * L; e += 256) {
+        const int c = e / (L * L), r = e - c * (L * L), li = r / L, lj = r - li * L;
+        int gi = i0 + li - 1, gj = j0 + lj - 1;
+        gi = gi < 0 ? gi + H : (gi >= H ? gi - H : gi);
+        gj = gj < 0 ? gj + W : (gj >= W ? gj - W : gj);
+        s_in[e] = xn[(size_t)c * HW + (size_t)gi * W + gj];
+    }
+    __syncthreads();
+    const int pi = tid >> 4, pj = tid & 15;
+    const int i = i0 + pi, j = j0 + pj;
+    if (i >= H || j >= W)
+        return;
+    float acc[CO];
+#pragma unroll
+    for (int o = 0; o < CO; ++o)
+        acc[o] = bias ? bias[o] : 0.0f;
+    for (int c = 0; c < ci_n; ++c) {
+        const float *t = s_in + c * L * L + pi * L + pj;
+        float v[9];
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx)
+                v[ky * 3 + kx] = t[ky * L + kx];
+#pragma unroll
+        for (int o = 0; o < CO; ++o) {
+            float s = acc[o];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const float wk = TR ? w[((size_t)c * CO + o) * 9 + (8 - k)] : w[((size_t)o * ci_n + c) * 9 + k];
+                s = fmaf(wk, v[k], s);
+            }
+            acc[o] = s;
+        }
+    }
+    const size_t pix = (size_t)i * W + j;
+#pragma unroll
+    for (int o = 0; o < CO; ++o) {
+        float r = acc[o];
+        if (relu)
+            r = fmaxf(r, 0.0f);
+        if (resid)
+            r += resid[((size_t)n * resid_c + o) * HW + pix];
+        if (mask)
+            r = mask[((size_t)n * CO + o) * HW + pix] > 0.0f ? r : 0.0f;
+        y[((size_t)n * CO + o) * HW + pix] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: dw[o,c,k] = sum_{n,i,j} dy[n,o,i,j] x[n,c,i+ky-1,j+kx-1].
+// One block per (o, c); the block walks every sample's 16 x 16 tiles with
+// the x tile (plus halo) and the dy tile in LDS; per-thread float sums, then
+// a fixed-order float64 block reduction.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double cwave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_conv3x3_wgrad(const float *__restrict__ dy, int co_n,
+                                                       const float *__restrict__ x, int ci_n, int N, int H, int W,
+                                                       float *__restrict__ dw)
+{
+    constexpr int L = kTile + 2;
+    __shared__ float s_x[L * L];
+    __shared__ float s_d[kTile * kTile];
+    __shared__ double s_red[4][9];
+    const int o = blockIdx.x / ci_n, c = blockIdx.x - o * ci_n;
+    const int tid = threadIdx.x, pi = tid >> 4, pj = tid & 15;
+    const size_t HW = (size_t)H * W;
+    const int tiles_i = (H + kTile - 1) / kTile, tiles_j = (W + kTile - 1) / kTile;
+    float acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int n = 0; n < N; ++n) {
+        const float *xn = x + ((size_t)n * ci_n + c) * HW;
+        const float *dn = dy + ((size_t)n * co_n + o) * HW;
+        for (int ti = 0; ti < tiles_i; ++ti)
+            for (int tj = 0; tj < tiles_j; ++tj) {
+                const int i0 = ti * kTile, j0 = tj * kTile;
+                __syncthreads();
+                for (int e = tid; e < L * L; e += 256) {
+                    const int li = e / L, lj = e - li * L;
+                    int gi = i0 + li - 1, gj = j0 + lj - 1;
+                    gi = gi < 0 ? gi + H : (gi >= H ? gi - H : gi);
+                    gj = gj < 0 ? gj + W : (gj >= W ? gj - W : gj);
+                    s_x[e] = xn[(size_t)gi * W + gj];
+                }
+                {
+                    const int gi = i0 + pi, gj = j0 + pj;
+                    s_d[tid] = (gi < H && gj < W) ? dn[(size_t)gi * W + gj] : 0.0f;
+                }
+                __syncthreads();
+                const float d = s_d[tid];
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < 3; ++kx)
+                        acc[ky * 3 + kx] = fmaf(d, s_x[(pi + ky) * L + pj + kx], acc[ky * 3 + kx]);
+            }
+    }
+    const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double s = cwave_sum((double)acc[k]);
+        if (lane == 0)
+            s_red[wv][k] = s;
+    }
+    __syncthreads();
+    if (tid < 9)
+        dw[((size_t)o * ci_n + c) * 9 + tid] =
+            (float)(((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid]);
+}
+
+// db[o] = sum_{n,i,j} dy[n,o,i,j]; one block per o, fixed order.
+__global__ __launch_bounds__(256) void k_bias_grad(const float *__restrict__ dy, int co_n, int N, int HW,
+                                                   float *__restrict__ db)
+{
+    __shared__ double s_red[4];
+    const int o = blockIdx.x;
+    double acc = 0.0;
+    for (int n = 0; n < N; ++n) {
+        const float *d = dy + ((size_t)n * co_n + o) * HW;
+        for (int p = threadIdx.x; p < HW; p += 256)
+            acc += (double)d[p];
+    }
+    acc = cwave_sum(acc);
+    if ((threadIdx.x & 63) == 0)
+        s_red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        db[o] = (float)(((s_red[0] + s_red[1]) + s_red[2]) + s_red[3]);
+}
+
+// Mean squared error: dy = 2 (y - t) / count, per-block float64 partials of
+// sum (y - t)^2; k_mse_final adds them in order.
+__global__ __launch_bounds__(256) void k_mse(const float *__restrict__ y, const float *__restrict__ t, int64_t count,
+                                             float *__restrict__ dy, double *__restrict__ part)
+{
+    __shared__ double s_red[4];
+    double acc = 0.0;
+    const float scale = (float)(2.0 / (double)count);
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
+        const float d = y[e] - t[e];
+        dy[e] = d * scale;
+        acc += (double)d * (double)d;
+    }
+    acc = cwave_sum(acc);
+    if ((threadIdx.x & 63) == 0)
+        s_red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
+}
+
+__global__ void k_mse_final(const double *__restrict__ part, int nparts, int64_t count, float *__restrict__ loss)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nparts; ++b)
+            s += part[b];
+        *loss = (float)(s / (double)count);
+    }
+}
+
+// bf16 weights -> float32 working copy.
+__global__ void k_widen_bf16(const uint16_t *__restrict__ w, int64_t count, float *__restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count)
+        out[e] = bf16_bits_to_float(w[e]);
+}
+
+// Adam (Kingma & Ba, algorithm 1) on a float32 master tensor; writes the
+// bf16 copy when bf16_out is given.
+__global__ void k_adam(float *__restrict__ theta, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, int64_t count, float lr, float beta1, float beta2, float eps,
+                       float bc1, float bc2, uint16_t *__restrict__ bf16_out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count)
+        return;
+    const float gi = g[e];
+    const float mi = beta1 * m[e] + (1.0f - beta1) * gi;
+    const float vi = beta2 * v[e] + (1.0f - beta2) * gi * gi;
+    m[e] = mi;
+    v[e] = vi;
+    const float th = theta[e] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    theta[e] = th;
+    if (bf16_out)
+        bf16_out[e] = float_to_bf16_rne(th);
+}
+
+// x[n, c, p] = x[n, c, p] * scale[c] + shift[c] for c < nc (in place).
+__global__ void k_channel_affine(float *__restrict__ x, int N, int C, int nc, int64_t HW,
+                                 const float *__restrict__ scale, const float *__restrict__ shift)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)nc * HW;
+    if (e >= (int64_t)N * per)
+        return;
+    const int64_t n = e / per, r = e - n * per;
+    const int c = (int)(r / HW);
+    float *p = x + (n * C + c) * HW + (r - (int64_t)c * HW);
+    *p = *p * scale[c] + shift[c];
+}
+
+// ---------------------------------------------------------------------------
+// Coarse fields of a lattice: the mean over c x c blocks of sites of rho, jx,
+// jy of the streamed populations (the fields step (ii) of the algorithm
+// sees), out[3][ny/c][nx/c].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_coarsen(const float *__restrict__ f, StepArgs a, int cs, int cw, int chh,
+                                                 float *__restrict__ out)
+{
+    const int cx = blockIdx.x * blockDim.x + threadIdx.x, cy = blockIdx.y;
+    if (cx >= cw)
+        return;
+    float r = 0.0f, jxs = 0.0f, jys = 0.0f;
+    for (int dy = 0; dy < cs; ++dy)
+        for (int dx = 0; dx < cs; ++dx) {
+            const int x = cx * cs + dx, y = cy * cs + dy;
+            const PullSources32 g = pull_sources32(a, x, y);
+            float v[7];
+#pragma unroll
+            for (int i = 0; i < 7; ++i)
+                v[i] = ld32(f + (size_t)i * (uint32_t)a.plane, g.idx[i]);
+            float rho, jx, jy;
+            site_moments(v, rho, jx, jy);
+            r += rho;
+            jxs += jx;
+            jys += jy;
+        }
+    const float inv = 1.0f / (float)(cs * cs);
+    const size_t cp = (size_t)chh * cw;
+    out[(size_t)cy * cw + cx] = r * inv;
+    out[cp + (size_t)cy * cw + cx] = jxs * inv;
+    out[2 * cp + (size_t)cy * cw + cx] = jys * inv;
+}
+
+// Populations from coarse fields: every site of a c x c block gets the
+// steady state xi(rho, j/rho) of its block (eq. fssD2Q7 with u* = u), as a
+// stored state.  rho <= 0 gives empty sites.
+__global__ __launch_bounds__(256) void k_lift(const float *__restrict__ coarse, StepArgs a, int cs, int cw, int chh,
+                                              float *__restrict__ f)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= a.nx)
+        return;
+    const int cx = x / cs, cy = y / cs;
+    const size_t cp = (size_t)chh * cw;
+    const float rho = fmaxf(coarse[(size_t)cy * cw + cx], 0.0f);
+    const float jx = coarse[cp + (size_t)cy * cw + cx], jy = coarse[2 * cp + (size_t)cy * cw + cx];
+    const float r = rho > 0.0f ? 1.0f / rho : 0.0f;
+    float eq[7];
+    site_equilibrium(rho, jx * r, jy * r, eq);
+    const uint32_t own = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        st32(f + (size_t)i * (uint32_t)a.plane, own, eq[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+static int64_t n_w(int a, int b) { return (int64_t)a * b * 9; }
+
+static bool shape_ok(const lbm_cnn_shape *s)
+{
+    return s && s->n > 0 && s->h > 0 && s->w > 0 && s->hidden == 32 && s->cout == 3 && s->cin >= 3 &&
+           s->cin <= 32 && (int64_t)s->h * s->w <= (1 << 26) && s->n <= 65535;
+}
+
+template <int CO, int TR>
+static hipError_t conv(const float *x, int ci, const float *w, const float *b, const float *resid, int resid_c,
+                       const float *mask, int relu, float *y, int N, int H, int W, hipStream_t s)
+{
+    dim3 grd((W + kTile - 1) / kTile, (H + kTile - 1) / kTile, N);
+    const size_t lds = (size_t)ci * (kTile + 2) * (kTile + 2) * sizeof(float);
+    hipLaunchKernelGGL((k_conv3x3<CO, TR>), grd, dim3(256), lds, s, x, ci, w, b, resid, resid_c, mask, relu, y, H, W);
+    return hipGetLastError();
+}
+
+struct CnnWs {
+    float *w[3];     // widened weights
+    double *part;    // loss partials
+    float *dy;       // dL/dy [n][cout][hw]
+    float *dz2;      // [n][hidden][hw]
+    float *dz1;      // [n][hidden][hw]
+    size_t total;
+};
+
+static const int kMseBlocks = 1024;
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Workspace: widened weights, loss partials and the backward pass's
+// intermediate gradients.  base == nullptr only measures the size.
+static CnnWs cnn_layout(const lbm_cnn_shape *s, char *base)
+{
+    CnnWs L{};
+    size_t off = 0, o[7];
+    const int64_t hw = (int64_t)s->h * s->w;
+    const int64_t sizes[3] = {n_w(s->hidden, s->cin), n_w(s->hidden, s->hidden), n_w(s->cout, s->hidden)};
+    for (int k = 0; k < 3; ++k) {
+        o[k] = off;
+        off = align256(off + sizes[k] * sizeof(float));
+    }
+    o[3] = off;
+    off = align256(off + kMseBlocks * sizeof(double));
+    o[4] = off;
+    off = align256(off + (size_t)s->n * s->cout * hw * sizeof(float));
+    o[5] = off;
+    off = align256(off + (size_t)s->n * s->hidden * hw * sizeof(float));
+    o[6] = off;
+    off = align256(off + (size_t)s->n * s->hidden * hw * sizeof(float));
+    L.total = off;
+    if (base) {
+        for (int k = 0; k < 3; ++k)
+            L.w[k] = (float *)(base + o[k]);
+        L.part = (double *)(base + o[3]);
+        L.dy = (float *)(base + o[4]);
+        L.dz2 = (float *)(base + o[5]);
+        L.dz1 = (float *)(base + o[6]);
+    }
+    return L;
+}
+
+static hipError_t widen(const lbm_cnn_shape *s, const lbm_cnn_params *p, const CnnWs &L, hipStream_t st)
+{
+    const int64_t sizes[3] = {n_w(s->hidden, s->cin), n_w(s->hidden, s->hidden), n_w(s->cout, s->hidden)};
+    for (int k = 0; k < 3; ++k)
+        hipLaunchKernelGGL(k_widen_bf16, dim3((unsigned)((sizes[k] + 255) / 256)), dim3(256), 0, st, p->w[k], sizes[k],
+                           L.w[k]);
+    return hipGetLastError();
+}
+
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" {
+
+size_t lbm_cnn_workspace_bytes(const lbm_cnn_shape *s)
+{
+    if (!shape_ok(s))
+        return 0;
+    return cnn_layout(s, nullptr).total;
+}
+
+int32_t lbm_cnn_forward(const lbm_cnn_shape *s, const lbm_cnn_params *p, const float *x, float *a1, float *a2,
+                        float *y, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!shape_ok(s))
+        return fail(LBM_EINVAL, "invalid network shape (hidden must be 32, cout 3, 3 <= cin <= 32)");
+    if (!p || !x || !a1 || !a2 || !y || !ws)
+        return fail(LBM_EINVAL, "null pointer");
+    for (int k = 0; k < 3; ++k)
+        if (!p->w[k] || !p->b[k])
+            return fail(LBM_EINVAL, "null weight or bias");
+    const CnnWs L = cnn_layout(s, (char *)ws);
+    if (ws_bytes < L.total)
+        return fail(LBM_EINVAL, "workspace smaller than lbm_cnn_workspace_bytes()");
+    hipStream_t st = (hipStream_t)stream;
+    LBM_HIP_TRY(widen(s, p, L, st));
+    LBM_HIP_TRY((conv<32, 0>(x, s->cin, L.w[0], p->b[0], nullptr, 0, nullptr, 1, a1, s->n, s->h, s->w, st)));
+    LBM_HIP_TRY((conv<32, 0>(a1, 32, L.w[1], p->b[1], nullptr, 0, nullptr, 1, a2, s->n, s->h, s->w, st)));
+    LBM_HIP_TRY((conv<3, 0>(a2, 32, L.w[2], p->b[2], x, s->cin, nullptr, 0, y, s->n, s->h, s->w, st)));
+    return LBM_OK;
+}
+
+int32_t lbm_cnn_backward(const lbm_cnn_shape *s, const lbm_cnn_params *p, const float *x, const float *a1,
+                         const float *a2, const float *y, const float *target, const lbm_cnn_grads *g,
+                         float *loss, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!shape_ok(s))
+        return fail(LBM_EINVAL, "invalid network shape (hidden must be 32, cout 3, 3 <= cin <= 32)");
+    if (!p || !x || !a1 || !a2 || !y || !target || !g || !loss || !ws)
+        return fail(LBM_EINVAL, "null pointer");
+    for (int k = 0; k < 3; ++k)
+        if (!g->w[k] || !g->b[k])
+            return fail(LBM_EINVAL, "null gradient buffer");
+    const CnnWs L = cnn_layout(s, (char *)ws);
+    if (ws_bytes < L.total)
+        return fail(LBM_EINVAL, "workspace smaller than lbm_cnn_workspace_bytes()");
+    hipStream_t st = (hipStream_t)stream;
+    const int N = s->n, H = s->h, W = s->w;
+    const int64_t hw = (int64_t)H * W, count = (int64_t)N * s->cout * hw;
+    LBM_HIP_TRY(widen(s, p, L, st));
+    hipLaunchKernelGGL(k_mse, dim3(kMseBlocks), dim3(256), 0, st, y, target, count, L.dy, L.part);
+    hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, st, L.part, kMseBlocks, count, loss);
+    // layer 3: y = x[:cout] + conv(a2, w2) + b2
+    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(s->cout * 32), dim3(256), 0, st, L.dy, s->cout, a2, 32, N, H, W, g->w[2]);
+    hipLaunchKernelGGL(k_bias_grad, dim3(s->cout), dim3(256), 0, st, L.dy, s->cout, N, (int)hw, g->b[2]);
+    LBM_HIP_TRY((conv<32, 1>(L.dy, s->cout, L.w[2], nullptr, nullptr, 0, a2, 0, L.dz2, N, H, W, st)));
+    // layer 2: a2 = relu(conv(a1, w1) + b1)
+    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(32 * 32), dim3(256), 0, st, L.dz2, 32, a1, 32, N, H, W, g->w[1]);
+    hipLaunchKernelGGL(k_bias_grad, dim3(32), dim3(256), 0, st, L.dz2, 32, N, (int)hw, g->b[1]);
+    LBM_HIP_TRY((conv<32, 1>(L.dz2, 32, L.w[1], nullptr, nullptr, 0, a1, 0, L.dz1, N, H, W, st)));
+    // layer 1: a1 = relu(conv(x, w0) + b0)
+    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(32 * s->cin), dim3(256), 0, st, L.dz1, 32, x, s->cin, N, H, W, g->w[0]);
+    hipLaunchKernelGGL(k_bias_grad, dim3(32), dim3(256), 0, st, L.dz1, 32, N, (int)hw, g->b[0]);
+    LBM_HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+int32_t lbm_cnn_adam(float *theta, float *m, float *v, const float *grad, int64_t count, float lr, float beta1,
+                     float beta2, float eps, int64_t t, uint16_t *bf16_out, void *stream)
+{
+    if (!theta || !m || !v || !grad || count < 0 || t < 1)
+        return fail(LBM_EINVAL, "invalid Adam arguments");
+    if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return fail(LBM_EINVAL, "invalid Adam hyper-parameters");
+    const float bc1 = (float)(1.0 - pow((double)beta1, (double)t));
+    const float bc2 = (float)(1.0 - pow((double)beta2, (double)t));
+    if (count > 0)
+        hipLaunchKernelGGL(k_adam, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, (hipStream_t)stream, theta, m,
+                           v, grad, count, lr, beta1, beta2, eps, bc1, bc2, bf16_out);
+    LBM_HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+int32_t lbm_channel_affine(float *x, int32_t n, int32_t c, int32_t nc, int64_t hw, const float *scale,
+                           const float *shift, void *stream)
+{
+    if (!x || !scale || !shift || n < 0 || c < 1 || nc < 0 || nc > c || hw < 0)
+        return fail(LBM_EINVAL, "invalid channel_affine arguments");
+    const int64_t total = (int64_t)n * nc * hw;
+    if (total > 0)
+        hipLaunchKernelGGL(k_channel_affine, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                           x, n, c, nc, hw, scale, shift);
+    LBM_HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+int32_t lbm_coarsen(const lbm_params *p, const float *f, int32_t c, float *out, void *stream)
+{
+    int32_t rc = validate_params(p, p ? p->nx : 0);
+    if (rc)
+        return rc;
+    if (!f || !out)
+        return fail(LBM_EINVAL, "null pointer");
+    if (p->storage != LBM_F32)
+        return fail(LBM_EUNSUPPORTED, "coarse fields take F32 storage");
+    if (c < 1 || p->nx % c || p->ny % c || ((c & 1) && c != 1))
+        return fail(LBM_EINVAL, "c must divide nx and ny and be 1 or even");
+    if ((uint64_t)p->nx * p->ny * 7ull >= (1ull << 30))
+        return fail(LBM_EINVAL, "lattice too large");
+    const StepArgs a = make_step_args(*p, p->nx);
+    const int cw = p->nx / c, chh = p->ny / c;
+    hipLaunchKernelGGL(k_coarsen, dim3((cw + 255) / 256, chh), dim3(256), 0, (hipStream_t)stream, f, a,
+                       c, cw, chh, out);
+    LBM_HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+int32_t lbm_lift(const lbm_params *p, const float *coarse, int32_t c, float *f, void *stream)
+{
+    int32_t rc = validate_params(p, p ? p->nx : 0);
+    if (rc)
+        return rc;
+    if (!f || !coarse)
+        return fail(LBM_EINVAL, "null pointer");
+    if (p->storage != LBM_F32)
+        return fail(LBM_EUNSUPPORTED, "lifting writes F32 storage");
+    if (c < 1 || p->nx % c || p->ny % c || ((c & 1) && c != 1))
+        return fail(LBM_EINVAL, "c must divide nx and ny and be 1 or even");
+    if ((uint64_t)p->nx * p->ny * 7ull >= (1ull << 30))
+        return fail(LBM_EINVAL, "lattice too large");
+    const StepArgs a = make_step_args(*p, p->nx);
+    hipLaunchKernelGGL(k_lift, dim3((p->nx + 255) / 256, p->ny), dim3(256), 0, (hipStream_t)stream, coarse, a, c,
+                       p->nx / c, p->ny / c, f);
+    LBM_HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+}  // extern "C"

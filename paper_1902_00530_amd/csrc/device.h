@@ -185,14 +185,10 @@ __device__ __forceinline__ void mips_ustar(const StepArgs &a, float rho, const f
     }
 }
 
-// BGK relaxation towards xi(rho, u*) (eq. fssD2Q7), zero-sum noise, and the
-// negative correction (pair form, rescale to rho where a rule fired).
-// Compile-time variants (no uniform branches inside the site body).
-enum StepFlags : int { kUnitTau = 1, kNoisy = 2 };
-
-template <int F>
-__device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], float rho, float ux, float uy,
-                                             uint32_t site, uint32_t t_lo, uint32_t t_hi)
+// Steady state xi(rho, u) of eq. fssD2Q7 in pair form: a_k = e_k.u,
+// base = 1 - 2|u|^2, xi_{k, k+3} = (rho/12)(base + 8 a_k^2 +- 4 a_k),
+// xi_0 = (rho/2) base.
+__device__ __forceinline__ void site_equilibrium(float rho, float ux, float uy, float eq[7])
 {
     const float usq = ux * ux + uy * uy;
     const float a1 = ux;
@@ -200,17 +196,27 @@ __device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], floa
     const float a3 = -0.5f * ux + kHalfSqrt3 * uy;
     const float r12 = fmaf(rho, kTwelfthHi, rho * kTwelfthLo);
     const float base = 1.0f - 2.0f * usq;
-    float eq[7];
     eq[0] = 0.5f * rho * base;
-    {
-        const float b1 = base + 8.0f * a1 * a1, b2 = base + 8.0f * a2 * a2, b3 = base + 8.0f * a3 * a3;
-        eq[1] = r12 * (b1 + 4.0f * a1);
-        eq[4] = r12 * (b1 - 4.0f * a1);
-        eq[2] = r12 * (b2 + 4.0f * a2);
-        eq[5] = r12 * (b2 - 4.0f * a2);
-        eq[3] = r12 * (b3 + 4.0f * a3);
-        eq[6] = r12 * (b3 - 4.0f * a3);
-    }
+    const float b1 = base + 8.0f * a1 * a1, b2 = base + 8.0f * a2 * a2, b3 = base + 8.0f * a3 * a3;
+    eq[1] = r12 * (b1 + 4.0f * a1);
+    eq[4] = r12 * (b1 - 4.0f * a1);
+    eq[2] = r12 * (b2 + 4.0f * a2);
+    eq[5] = r12 * (b2 - 4.0f * a2);
+    eq[3] = r12 * (b3 + 4.0f * a3);
+    eq[6] = r12 * (b3 - 4.0f * a3);
+}
+
+// Compile-time variants (no uniform branches inside the site body).
+enum StepFlags : int { kUnitTau = 1, kNoisy = 2 };
+
+// BGK relaxation towards xi(rho, u*) (eq. fssD2Q7), zero-sum noise, and the
+// negative correction (pair form, rescale to rho where a rule fired).
+template <int F>
+__device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], float rho, float ux, float uy,
+                                             uint32_t site, uint32_t t_lo, uint32_t t_hi)
+{
+    float eq[7];
+    site_equilibrium(rho, ux, uy, eq);
     if (F & kUnitTau) {
         // tau = 1 (the paper's CIL runs): the relaxation lands on xi exactly
 #pragma unroll
