@@ -239,6 +239,13 @@ def main():
             "MLUPS_one_by_one": round(nb_sites * kb / (ms1 / 1e3) / 1e6, 1),
             "speedup": round(ms1 / msb, 3),
             "field_error": "0 (batch members equal single runs bit for bit)"}
+        # learned surrogate (coarse 32x32 fields of 256^2 lattices, k = 50)
+        from paper_1902_00530_amd import surrogate as S
+        r = S.recipe(SI.surrogate_grid(256, 11000), SI.surrogate_grid(256, 21000), SI.surrogate_grid(256, 31000),
+                     coarse=8, k=50, warmup=2000, rounds=320, epochs=30, batch=64, lr=1e-3, jumps=20,
+                     check_every=4)
+        r.pop("network")
+        var["surrogate_256_k50"] = r
         line["variants"] = var
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_steps)

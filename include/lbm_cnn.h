@@ -74,6 +74,19 @@ int32_t lbm_cnn_adam(float *theta, float *m, float *v, const float *grad, int64_
 int32_t lbm_channel_affine(float *x, int32_t n, int32_t c, int32_t nc, int64_t hw, const float *scale,
                            const float *shift, void *stream);
 
+/* Per-sample relative L2 error of the first nc of c channels (n samples of
+ * hw pixels): out[s] = |a_s - b_s| / |b_s| in float64 (device array of n). */
+int32_t lbm_field_error(const float *a, const float *b, int32_t n, int32_t c, int32_t nc, int64_t hw, double *out,
+                        void *stream);
+
+/* Per-channel mean and standard deviation (population) of x [n][c][hw] in
+ * float64 (device arrays of c). */
+int32_t lbm_channel_stats(const float *x, int32_t n, int32_t c, int64_t hw, double *mean, double *stdev,
+                          void *stream);
+
+/* x[s][ch][:] = values[s] for s < n (device array of n floats). */
+int32_t lbm_fill_channel(float *x, int32_t n, int32_t c, int32_t ch, int64_t hw, const float *values, void *stream);
+
 /* Coarse fields of a stored F32 state f [7][ny][nx] (pitch nx): out
  * [3][ny/c][nx/c] = means over c x c blocks of sites of rho, jx, jy of the
  * streamed populations.  c divides nx and ny and is 1 or even. */
@@ -83,6 +96,15 @@ int32_t lbm_coarsen(const lbm_params *p, const float *f, int32_t c, float *out, 
  * site of a block gets xi(rho, j/rho) of its block (steady state eq.
  * fssD2Q7 with u* = u; negative rho is treated as 0). */
 int32_t lbm_lift(const lbm_params *p, const float *coarse, int32_t c, float *f, void *stream);
+
+/* lbm_coarsen / lbm_lift for n lattices of the shape p in one launch.  bufs:
+ * device array of n pointers to the lattices' stored F32 states; the coarse
+ * fields of lattice l start at out + l * out_stride (resp. coarse + l *
+ * in_stride), strides in floats, >= 3 (ny/c) (nx/c). */
+int32_t lbm_coarsen_many(const lbm_params *p, int32_t n, const float *const *bufs, int32_t c, float *out,
+                         int64_t out_stride, void *stream);
+int32_t lbm_lift_many(const lbm_params *p, int32_t n, const float *coarse, int64_t in_stride, int32_t c,
+                      float *const *bufs, void *stream);
 
 #ifdef __cplusplus
 }

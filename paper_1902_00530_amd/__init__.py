@@ -97,7 +97,16 @@ _SIGS = {
     "lbm_channel_affine": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                             _vp, _vp, _vp]),
     "lbm_coarsen": (ctypes.c_int32, [_P(lbm_params), _vp, ctypes.c_int32, _vp, _vp]),
+    "lbm_field_error": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                         _vp, _vp]),
+    "lbm_channel_stats": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp]),
+    "lbm_fill_channel": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _vp,
+                                          _vp]),
     "lbm_lift": (ctypes.c_int32, [_P(lbm_params), _vp, ctypes.c_int32, _vp, _vp]),
+    "lbm_coarsen_many": (ctypes.c_int32, [_P(lbm_params), ctypes.c_int32, _vp, ctypes.c_int32, _vp, ctypes.c_int64,
+                                          _vp]),
+    "lbm_lift_many": (ctypes.c_int32, [_P(lbm_params), ctypes.c_int32, _vp, ctypes.c_int64, ctypes.c_int32, _vp,
+                                       _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -197,8 +206,30 @@ def lbm_coarsen(params, f, c, out, stream):
     return _check(_lib.lbm_coarsen(ctypes.byref(params), f, int(c), out, stream), "lbm_coarsen")
 
 
+def lbm_field_error(a, b, n, c, nc, hw, out, stream):
+    return _check(_lib.lbm_field_error(a, b, int(n), int(c), int(nc), int(hw), out, stream), "lbm_field_error")
+
+
+def lbm_channel_stats(x, n, c, hw, mean, stdev, stream):
+    return _check(_lib.lbm_channel_stats(x, int(n), int(c), int(hw), mean, stdev, stream), "lbm_channel_stats")
+
+
+def lbm_fill_channel(x, n, c, ch, hw, values, stream):
+    return _check(_lib.lbm_fill_channel(x, int(n), int(c), int(ch), int(hw), values, stream), "lbm_fill_channel")
+
+
 def lbm_lift(params, coarse, c, f, stream):
     return _check(_lib.lbm_lift(ctypes.byref(params), coarse, int(c), f, stream), "lbm_lift")
+
+
+def lbm_coarsen_many(params, n, bufs, c, out, out_stride, stream):
+    return _check(_lib.lbm_coarsen_many(ctypes.byref(params), int(n), bufs, int(c), out, int(out_stride), stream),
+                  "lbm_coarsen_many")
+
+
+def lbm_lift_many(params, n, coarse, in_stride, c, bufs, stream):
+    return _check(_lib.lbm_lift_many(ctypes.byref(params), int(n), coarse, int(in_stride), int(c), bufs, stream),
+                  "lbm_lift_many")
 
 
 class Batch:
@@ -211,6 +242,10 @@ class Batch:
         self.buffers = [torch.zeros((7, p.ny, p.nx), dtype=torch.float32, device=device)
                         for p in params_list for _ in range(2)]
         self.bufs = (ctypes.c_void_p * (2 * self.n))(*[b.data_ptr() for b in self.buffers])
+        # device arrays of the n buffer pointers of each parity (for the
+        # many-lattice field maps)
+        self.dev_ptrs = [torch.tensor([self.buffers[2 * l + k].data_ptr() for l in range(self.n)],
+                                      dtype=torch.int64, device=device) for k in (0, 1)]
         self.current = [0] * self.n
         self.step_index = 0
         self._ws = None
@@ -222,27 +257,37 @@ class Batch:
         self.buffers[2 * l].copy_(f)
         self.current[l] = 0
 
-    def run(self, n_steps, sample_every=0, tile_rows=0, use_graph=1, stream=None):
-        """Advance every lattice by n_steps; returns a list (per lattice) of
-        sample dicts."""
+    def run(self, n_steps, sample_every=0, tile_rows=0, use_graph=1, stream=None, subset=None):
+        """Advance every lattice (or only the lattices listed in subset) by
+        n_steps; returns a list (per advanced lattice) of sample dicts."""
         import torch
+        idx = list(range(self.n)) if subset is None else [int(i) for i in subset]
+        m = len(idx)
+        if m == 0:
+            return []
         # the sweep expects each state in the first buffer of its pair
-        for l in range(self.n):
+        for l in idx:
             if self.current[l]:
                 self.buffers[2 * l].copy_(self.buffers[2 * l + 1])
                 self.current[l] = 0
+        if subset is None:
+            params, bufs = self.params, self.bufs
+        else:
+            params = (lbm_params * m)(*[self.params[l] for l in idx])
+            bufs = (ctypes.c_void_p * (2 * m))(*[self.bufs[2 * l + k] for l in idx for k in (0, 1)])
         n_samples = n_steps // sample_every if sample_every else 1
-        need = lbm_sweep_workspace_bytes(self.params, self.n, n_samples)
+        need = lbm_sweep_workspace_bytes(params, m, n_samples)
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.buffers[0].device)
-        out = (lbm_obs * (self.n * n_samples))()
+        out = (lbm_obs * (m * n_samples))()
         opts = lbm_sweep_opts(int(n_steps), int(sample_every), int(self.step_index), int(tile_rows), int(use_graph))
         st = stream if stream is not None else torch.cuda.current_stream()
-        lbm_sweep_batch(self.params, self.n, opts, self.bufs, self._ws.data_ptr(), need, st.cuda_stream, out)
-        self.step_index += n_steps
-        for l in range(self.n):
+        lbm_sweep_batch(params, m, opts, bufs, self._ws.data_ptr(), need, st.cuda_stream, out)
+        if subset is None:
+            self.step_index += n_steps
+        for l in idx:
             self.current[l] = n_steps & 1
-        return [[out[l * n_samples + s].as_dict() for s in range(n_samples)] for l in range(self.n)]
+        return [[out[q * n_samples + s].as_dict() for s in range(n_samples)] for q in range(m)]
 
 
 # ----------------------------------------------------------------- helpers

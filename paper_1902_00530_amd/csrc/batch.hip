@@ -471,7 +471,8 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     }
     std::vector<std::vector<BatchTile>> lists(3);
     for (int k = 0; k < 3; ++k)
-        lists[k] = build_tiles(ps, n, kShapes[k][0], kShapes[k][1]);
+        if (shape < 0 || k == shape)
+            lists[k] = build_tiles(ps, n, kShapes[k][0], kShapes[k][1]);
     if (shape < 0) {
         shape = 0;
         float best = 1e30f;

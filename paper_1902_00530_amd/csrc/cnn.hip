@@ -252,6 +252,83 @@ __global__ void k_channel_affine(float *__restrict__ x, int N, int C, int nc, in
     *p = *p * scale[c] + shift[c];
 }
 
+// Per-sample relative L2 error of the first nc channels: out[s] =
+// |a_s - b_s| / |b_s| (float64 sums, one block per sample, fixed order).
+__global__ __launch_bounds__(256) void k_field_error(const float *__restrict__ a, const float *__restrict__ b, int C,
+                                                     int nc, int64_t hw, double *__restrict__ out)
+{
+    __shared__ double s_red[2][4];
+    const int smp = blockIdx.x;
+    double num = 0.0, den = 0.0;
+    for (int64_t e = threadIdx.x; e < (int64_t)nc * hw; e += 256) {
+        const int64_t o = (int64_t)smp * C * hw + e;
+        const double d = (double)a[o] - (double)b[o];
+        num += d * d;
+        den += (double)b[o] * (double)b[o];
+    }
+    num = cwave_sum(num);
+    den = cwave_sum(den);
+    if ((threadIdx.x & 63) == 0) {
+        s_red[0][threadIdx.x >> 6] = num;
+        s_red[1][threadIdx.x >> 6] = den;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double nn = ((s_red[0][0] + s_red[0][1]) + s_red[0][2]) + s_red[0][3];
+        const double dd = ((s_red[1][0] + s_red[1][1]) + s_red[1][2]) + s_red[1][3];
+        out[smp] = dd > 0.0 ? sqrt(nn / dd) : (nn > 0.0 ? INFINITY : 0.0);
+    }
+}
+
+// Per-channel mean and standard deviation over n samples and hw pixels
+// (float64, one block per channel, two passes in a fixed order).
+__global__ __launch_bounds__(256) void k_channel_stats(const float *__restrict__ x, int n, int C, int64_t hw,
+                                                       double *__restrict__ mean, double *__restrict__ stdev)
+{
+    __shared__ double s_red[4];
+    __shared__ double s_mean;
+    const int c = blockIdx.x;
+    const int64_t cnt = (int64_t)n * hw;
+    double acc = 0.0;
+    for (int s = 0; s < n; ++s)
+        for (int64_t p = threadIdx.x; p < hw; p += 256)
+            acc += (double)x[((int64_t)s * C + c) * hw + p];
+    acc = cwave_sum(acc);
+    if ((threadIdx.x & 63) == 0)
+        s_red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        s_mean = (((s_red[0] + s_red[1]) + s_red[2]) + s_red[3]) / (double)cnt;
+    __syncthreads();
+    const double m = s_mean;
+    acc = 0.0;
+    for (int s = 0; s < n; ++s)
+        for (int64_t p = threadIdx.x; p < hw; p += 256) {
+            const double d = (double)x[((int64_t)s * C + c) * hw + p] - m;
+            acc += d * d;
+        }
+    acc = cwave_sum(acc);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        s_red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        mean[c] = m;
+        stdev[c] = sqrt((((s_red[0] + s_red[1]) + s_red[2]) + s_red[3]) / (double)cnt);
+    }
+}
+
+// x[s, ch, :] = values[s]
+__global__ void k_fill_channel(float *__restrict__ x, int n, int C, int ch, int64_t hw,
+                               const float *__restrict__ values)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * hw)
+        return;
+    const int64_t s = e / hw;
+    x[(s * C + ch) * hw + (e - s * hw)] = values[s];
+}
+
 // ---------------------------------------------------------------------------
 // Coarse fields of a lattice: the mean over c x c blocks of sites of rho, jx,
 // jy of the streamed populations (the fields step (ii) of the algorithm
@@ -283,6 +360,58 @@ __global__ __launch_bounds__(256) void k_coarsen(const float *__restrict__ f, St
     out[(size_t)cy * cw + cx] = r * inv;
     out[cp + (size_t)cy * cw + cx] = jxs * inv;
     out[2 * cp + (size_t)cy * cw + cx] = jys * inv;
+}
+
+// Many lattices of one shape: blockIdx.z selects the lattice, whose stored
+// state is bufs[z]; output rows of lattice z start at out + z * out_stride.
+__global__ __launch_bounds__(256) void k_coarsen_many(const float *const *__restrict__ bufs, StepArgs a, int cs,
+                                                      int cw, int chh, float *__restrict__ out, int64_t out_stride)
+{
+    const int cx = blockIdx.x * blockDim.x + threadIdx.x, cy = blockIdx.y;
+    if (cx >= cw)
+        return;
+    const float *f = bufs[blockIdx.z];
+    float r = 0.0f, jxs = 0.0f, jys = 0.0f;
+    for (int dy = 0; dy < cs; ++dy)
+        for (int dx = 0; dx < cs; ++dx) {
+            const PullSources32 g = pull_sources32(a, cx * cs + dx, cy * cs + dy);
+            float v[7];
+#pragma unroll
+            for (int i = 0; i < 7; ++i)
+                v[i] = ld32(f + (size_t)i * (uint32_t)a.plane, g.idx[i]);
+            float rho, jx, jy;
+            site_moments(v, rho, jx, jy);
+            r += rho;
+            jxs += jx;
+            jys += jy;
+        }
+    const float inv = 1.0f / (float)(cs * cs);
+    const size_t cp = (size_t)chh * cw;
+    float *o = out + (int64_t)blockIdx.z * out_stride;
+    o[(size_t)cy * cw + cx] = r * inv;
+    o[cp + (size_t)cy * cw + cx] = jxs * inv;
+    o[2 * cp + (size_t)cy * cw + cx] = jys * inv;
+}
+
+__global__ __launch_bounds__(256) void k_lift_many(const float *__restrict__ coarse, int64_t in_stride, StepArgs a,
+                                                   int cs, int cw, int chh, float *const *__restrict__ bufs)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= a.nx)
+        return;
+    const float *cf = coarse + (int64_t)blockIdx.z * in_stride;
+    float *f = bufs[blockIdx.z];
+    const int cx = x / cs, cy = y / cs;
+    const size_t cp = (size_t)chh * cw;
+    const float rho = fmaxf(cf[(size_t)cy * cw + cx], 0.0f);
+    const float jx = cf[cp + (size_t)cy * cw + cx], jy = cf[2 * cp + (size_t)cy * cw + cx];
+    const float r = rho > 0.0f ? 1.0f / rho : 0.0f;
+    float eq[7];
+    site_equilibrium(rho, jx * r, jy * r, eq);
+    const uint32_t own = (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x;
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        st32(f + (size_t)i * (uint32_t)a.plane, own, eq[i]);
 }
 
 // Populations from coarse fields: every site of a c x c block gets the
@@ -480,6 +609,39 @@ int32_t lbm_channel_affine(float *x, int32_t n, int32_t c, int32_t nc, int64_t h
     return LBM_OK;
 }
 
+int32_t lbm_field_error(const float *a, const float *b, int32_t n, int32_t c, int32_t nc, int64_t hw, double *out,
+                        void *stream)
+{
+    if (!a || !b || !out || n < 0 || c < 1 || nc < 1 || nc > c || hw < 1)
+        return fail(LBM_EINVAL, "invalid field_error arguments");
+    if (n > 0)
+        hipLaunchKernelGGL(k_field_error, dim3(n), dim3(256), 0, (hipStream_t)stream, a, b, c, nc, hw, out);
+    LBM_HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+int32_t lbm_channel_stats(const float *x, int32_t n, int32_t c, int64_t hw, double *mean, double *stdev,
+                          void *stream)
+{
+    if (!x || !mean || !stdev || n < 1 || c < 1 || hw < 1)
+        return fail(LBM_EINVAL, "invalid channel_stats arguments");
+    hipLaunchKernelGGL(k_channel_stats, dim3(c), dim3(256), 0, (hipStream_t)stream, x, n, c, hw, mean, stdev);
+    LBM_HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+int32_t lbm_fill_channel(float *x, int32_t n, int32_t c, int32_t ch, int64_t hw, const float *values, void *stream)
+{
+    if (!x || !values || n < 0 || c < 1 || ch < 0 || ch >= c || hw < 1)
+        return fail(LBM_EINVAL, "invalid fill_channel arguments");
+    const int64_t total = (int64_t)n * hw;
+    if (total > 0)
+        hipLaunchKernelGGL(k_fill_channel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                           x, n, c, ch, hw, values);
+    LBM_HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
 int32_t lbm_coarsen(const lbm_params *p, const float *f, int32_t c, float *out, void *stream)
 {
     int32_t rc = validate_params(p, p ? p->nx : 0);
@@ -497,6 +659,54 @@ int32_t lbm_coarsen(const lbm_params *p, const float *f, int32_t c, float *out, 
     const int cw = p->nx / c, chh = p->ny / c;
     hipLaunchKernelGGL(k_coarsen, dim3((cw + 255) / 256, chh), dim3(256), 0, (hipStream_t)stream, f, a,
                        c, cw, chh, out);
+    LBM_HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+static int32_t check_fields(const lbm_params *p, int32_t c)
+{
+    int32_t rc = validate_params(p, p ? p->nx : 0);
+    if (rc)
+        return rc;
+    if (p->storage != LBM_F32)
+        return fail(LBM_EUNSUPPORTED, "coarse fields take F32 storage");
+    if (c < 1 || p->nx % c || p->ny % c || ((c & 1) && c != 1))
+        return fail(LBM_EINVAL, "c must divide nx and ny and be 1 or even");
+    if ((uint64_t)p->nx * p->ny * 7ull >= (1ull << 30))
+        return fail(LBM_EINVAL, "lattice too large");
+    return LBM_OK;
+}
+
+int32_t lbm_coarsen_many(const lbm_params *p, int32_t n, const float *const *bufs, int32_t c, float *out,
+                         int64_t out_stride, void *stream)
+{
+    int32_t rc = check_fields(p, c);
+    if (rc)
+        return rc;
+    const int cw = p->nx / c, chh = p->ny / c;
+    if (!bufs || !out || n < 0 || n > 65535 || out_stride < 3ll * cw * chh)
+        return fail(LBM_EINVAL, "invalid coarsen_many arguments");
+    const StepArgs a = make_step_args(*p, p->nx);
+    if (n > 0)
+        hipLaunchKernelGGL(k_coarsen_many, dim3((cw + 255) / 256, chh, n), dim3(256), 0, (hipStream_t)stream, bufs,
+                           a, c, cw, chh, out, out_stride);
+    LBM_HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+int32_t lbm_lift_many(const lbm_params *p, int32_t n, const float *coarse, int64_t in_stride, int32_t c,
+                      float *const *bufs, void *stream)
+{
+    int32_t rc = check_fields(p, c);
+    if (rc)
+        return rc;
+    const int cw = p->nx / c, chh = p->ny / c;
+    if (!bufs || !coarse || n < 0 || n > 65535 || in_stride < 3ll * cw * chh)
+        return fail(LBM_EINVAL, "invalid lift_many arguments");
+    const StepArgs a = make_step_args(*p, p->nx);
+    if (n > 0)
+        hipLaunchKernelGGL(k_lift_many, dim3((p->nx + 255) / 256, p->ny, n), dim3(256), 0, (hipStream_t)stream,
+                           coarse, in_stride, a, c, cw, chh, bufs);
     LBM_HIP_TRY(hipGetLastError());
     return LBM_OK;
 }

@@ -95,3 +95,18 @@ def batch_sweep(n_lattices=256, seed=1003, sides=BATCH_SIDES, grid=16):
                         init=dict(mode=1, rho_mean=rho_mean, rho_spread=0.1, angle_std=0.0,
                                   u_mag=-1.0, pop_noise=0.0)))
     return out
+
+
+def surrogate_grid(side=256, seed_base=11000, n_rho=8, n_act=8):
+    """Lattices for the surrogate: an n_rho x n_act grid of mean density
+    0.3 .. 1.8 (lambda = 4 of 0.075 .. 0.45) and activity (B = 0.3 a,
+    a = 1/n_act .. 1), CIL with A = 0.125, tau = 1, sigma = 4/70, paper
+    initial state; one lattice per grid point, seed seed_base + index."""
+    out = []
+    for l in range(n_rho * n_act):
+        m, a = divmod(l, n_act)
+        out.append(dict(nx=side, ny=side, model=CIL, tau=1.0, sigma=4.0 / 70.0, A=0.125,
+                        B=0.3 * (a + 1) / n_act, C=0.0, rho_star=1.0, u_max=1.0, seed=seed_base + l,
+                        init=dict(mode=1, rho_mean=0.3 + 1.5 * m / max(1, n_rho - 1), rho_spread=0.1,
+                                  angle_std=0.0, u_mag=-1.0, pop_noise=0.0)))
+    return out
