@@ -112,6 +112,7 @@ def time_batch(L, torch, cfgs, steps, warmup):
     out = b.run(steps)
     e1.record(s)
     torch.cuda.synchronize()
+    time_batch.tile_rows = L.lbm_sweep_tile_rows(b.params, b.n)
     return e0.elapsed_time(e1), [o[-1] for o in out]
 
 
@@ -170,7 +171,9 @@ def main():
     t_wall = time.perf_counter()
     if mode == "batch":
         ms, obs = time_batch(L, torch, cfgs, args.steps, args.warmup)
-        launches, kernel = args.steps, "k_batch_step<CIL,unit-tau,noisy> (+1 FP64 sample at the end)"
+        launches = args.steps
+        tile = {1: "256x1", 2: "128x2", 4: "64x4"}.get(getattr(time_batch, "tile_rows", 0), "?")
+        kernel = f"k_batch_step<CIL,unit-tau,noisy>, tuned tile {tile} (+1 FP64 sample at the end)"
     else:
         ms, obs = time_single(L, torch, cfgs, args.steps, args.warmup, args.storage)
         launches, kernel = args.steps * len(cfgs), "k_step_local<CIL,F32,unit-tau,noisy>"

@@ -185,6 +185,11 @@ typedef struct lbm_sweep_opts {
  * samples per lattice (0 on invalid arguments). */
 size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samples);
 
+/* Work-tile rows (1, 2 or 4) the tuning chose for a batch with these
+ * lattices' sizes, model and step variant, 0 if not tuned yet in this
+ * process; negative on invalid arguments. */
+int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n);
+
 /* Run a batch.  ps[n]: per-lattice parameters; every lattice uses F32
  * storage, the same model (CIL or passive), and agrees on tau == 1 and on
  * sigma == 0; nx*ny*7 < 2^30, ny <= 32760.  bufs[2n]: caller-owned device

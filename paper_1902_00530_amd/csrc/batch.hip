@@ -375,6 +375,18 @@ using namespace lbm;
 
 extern "C" {
 
+int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n)
+{
+    if (!ps || n <= 0)
+        return fail(LBM_EINVAL, "null parameters or empty batch");
+    const int flags = sweep_flags(ps, n);
+    if (flags < 0)
+        return 0;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(signature(ps, n, flags));
+    return it == g_tuned.end() ? 0 : (it->second == 0 ? 1 : (it->second == 1 ? 2 : 4));
+}
+
 size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samples)
 {
     if (!ps || n <= 0 || n_samples < 0)
@@ -484,9 +496,9 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
                                        hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(k_batch_set_ctrl, dim3(1), dim3(64), 0, s, d_ctrl, (int64_t)0);
             float ms = 0.0f;
-            for (int rep = 0; rep < 2; ++rep) {
+            for (int rep = 0; rep < 3; ++rep) {
                 LBM_HIP_TRY(hipEventRecord(e0, s));
-                for (int rep4 = 0; rep4 < 4; ++rep4)  // node 0: first buffer -> second buffer
+                for (int rep10 = 0; rep10 < 10; ++rep10)  // node 0: first buffer -> second buffer
                     LBM_HIP_TRY(launch_batch_step(ps[0].model, flags, k, (int64_t)lists[k].size(), d_tiles, d_lat,
                                                   d_ctrl, 0, s));
                 LBM_HIP_TRY(hipEventRecord(e1, s));
