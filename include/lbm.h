@@ -169,15 +169,18 @@ const char *lbm_last_error(void);
  * Batched sweeps: n independent lattices of arbitrary sizes and parameters
  * (the paper's repeated runs over a grid of mean density and model constants,
  * appendix "Simulation procedure for results") advanced together: one kernel
- * launch per step covers every lattice, and one sample period (its steps and
- * the FP64 sampling kernels) is captured once in a HIP graph and replayed.
+ * launch per step (or per two steps) covers every lattice, and a sample
+ * period (its steps and the FP64 sampling kernels) is captured in HIP graphs
+ * of at most 1024 steps and replayed.
  * ---------------------------------------------------------------------- */
 typedef struct lbm_sweep_opts {
     int64_t n_steps;      /* steps to run (a multiple of sample_every) */
     int64_t sample_every; /* observables every sample_every steps (0: once, at the end) */
     int64_t step0;        /* absolute step index of the first step (noise counter) */
-    int32_t tile_rows;    /* work tile 256x1, 128x2 or 64x4 sites for 1, 2, 4; 0 = tuned
-                             (timed on the batch itself, cached per batch signature) */
+    int32_t tile_rows;    /* work tile: 1, 2, 4 = 256x1, 128x2, 64x4 sites, one step per
+                             launch; 8, 12, 16 = 64x8, 64x12, 64x16 sites, two steps per launch
+                             (the second from LDS); 0 = tuned (every shape timed on the
+                             batch itself, cached per batch signature) */
     int32_t use_graph;    /* 1: replay one captured sample period as a HIP graph */
 } lbm_sweep_opts;
 
@@ -185,9 +188,10 @@ typedef struct lbm_sweep_opts {
  * samples per lattice (0 on invalid arguments). */
 size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samples);
 
-/* Work-tile rows (1, 2 or 4) the tuning chose for a batch with these
- * lattices' sizes, model and step variant, 0 if not tuned yet in this
- * process; negative on invalid arguments. */
+/* Work-tile rows (1, 2, 4, 8 or 16, as in lbm_sweep_opts.tile_rows) the
+ * tuning chose for a batch with these lattices' sizes, model and step
+ * variant, 0 if not tuned yet in this process; negative on invalid
+ * arguments. */
 int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n);
 
 /* Run a batch.  ps[n]: per-lattice parameters; every lattice uses F32

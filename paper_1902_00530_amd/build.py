@@ -16,7 +16,11 @@ LIB = os.path.join(HERE, "liblbm.so")
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result",
+# -ffp-contract=on: a multiply and an add are fused only where they sit in one
+# source expression, so the site body rounds the same way in every kernel
+# that inlines it (the one- and two-step kernels give bit-identical states).
+COMMON = ["-O3", "-ffp-contract=on", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
+          "-Wno-unused-result",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(HERE, "..", "include")]
 

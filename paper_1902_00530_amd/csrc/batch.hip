@@ -1,6 +1,7 @@
 // Batched sweeps: many independent lattices of different sizes and
-// parameters advanced together (one kernel launch per step covers every
-// lattice), with FP64 observables sampled every sample_every steps.
+// parameters advanced together (one kernel launch per step, or per two steps,
+// covers every lattice), with FP64 observables sampled every sample_every
+// steps.
 //
 // Work list.  Each lattice is cut into TX x TY tiles; the list of all tiles
 // of all lattices is built on the host.  Within a lattice, tiles are listed
@@ -11,11 +12,20 @@
 // single-lattice kernel, so a batch member gives bit-for-bit the result of
 // the single-lattice call with the same seed.
 //
-// Step loop.  One sample period (sample_every step kernels, the sampling
-// kernels, one counter update) is captured once in a HIP graph and replayed;
-// the step index and the buffer parity come from a small control block in
-// device memory that the last node advances, so no kernel arguments change
-// between replays and no kernel waits on another workgroup.
+// Two steps per launch.  The state of step t+1 at a site depends on the state
+// of step t at the site and its six neighbours (one streaming move), so the
+// state of step t+2 on a 64 x TY tile needs step t+1 on the tile widened by
+// one site on every side, which needs step t widened by two.  The two-step
+// kernel computes step t+1 on the widened tile into LDS (gathering step t
+// from HBM), then step t+2 on the tile from LDS, and writes only that: one
+// read and one write of the state per two updates, for about
+// (66 (TY + 2)) / (64 TY) - 1 extra site bodies.
+//
+// Step loop.  One sample period (its step kernels, the sampling kernels, one
+// counter update) is captured once in a HIP graph and replayed; the step
+// index and the buffer parity come from a small control block in device
+// memory that the last node advances, so no kernel arguments change between
+// replays and no kernel waits on another workgroup.
 #include <math.h>
 
 #include <algorithm>
@@ -60,39 +70,190 @@ struct Ctrl {
 constexpr int kMomRows = 16;
 
 // ---------------------------------------------------------------------------
-// Step kernel over the tile list.
+// Step kernels over the tile list.  step_off: steps of this sample period
+// before this launch; launch_off: launches before it (the buffer parity).
 // ---------------------------------------------------------------------------
 template <int M, int F>
 __global__ __launch_bounds__(256) void k_batch_step(const BatchTile *__restrict__ tiles,
                                                     const LatDesc *__restrict__ lats,
-                                                    const Ctrl *__restrict__ ctrl, int node)
+                                                    const Ctrl *__restrict__ ctrl, int step_off, int launch_off)
 {
     const BatchTile tl = tiles[blockIdx.x];
     const LatDesc &L = lats[tl.lat];
     const StepArgs a = L.a;
-    const int64_t t = ctrl->t0 + node;
-    const int par = (int)((ctrl->k0 + node) & 1);
-    const float *__restrict__ src = (const float *)L.buf[par];
-    float *__restrict__ dst = (float *)L.buf[par ^ 1];
+    const int64_t t = ctrl->t0 + step_off;
+    const int par = (int)((ctrl->k0 + launch_off) & 1);
     const int x = tl.tx * blockDim.x + threadIdx.x;
     const int y = tl.ty * blockDim.y + threadIdx.y;
     if (x >= a.nx || y >= a.ny)
         return;
     const uint32_t plane = (uint32_t)a.plane;
+    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], 28u * plane);
+    const __amdgpu_buffer_rsrc_t dst = buffer_rsrc(L.buf[par ^ 1], 28u * plane);
     const PullSources32 g_src = pull_sources32(a, x, y);
     float f[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        f[i] = ld32(src + (size_t)i * plane, g_src.idx[i]);
+        f[i] = BufIO<float>::load(src, g_src.idx[i], i * plane);
     float rho, jx, jy, ux, uy;
     site_moments(f, rho, jx, jy);
     local_ustar<M>(a, rho, jx, jy, ux, uy);
-    site_collide<F>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x,
-                    (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32));
+    // batch buffers have pitch nx, so the own offset is the site index
     const uint32_t own = g_src.idx[0];
+    site_collide<F>(a, f, rho, ux, uy, own, (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32));
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        st32(dst + (size_t)i * plane, own, f[i]);
+        BufIO<float>::store(dst, own, i * plane, f[i]);
+}
+
+// Periodic image of a coordinate c in [-1, n + 64] on a ring of n sites.
+__device__ __forceinline__ int wrap_coord(int c, int n)
+{
+    if (c < 0)
+        c += n;
+    if (c >= n)
+        c -= n;
+    if (c >= n)  // rings shorter than the widened tile
+        c %= n;
+    return c;
+}
+
+// Steps t and t+1 on a 64 x TY tile (256 threads: wave w owns rows w, w+4,
+// ...).  mid holds step t+1 on the tile widened by one site, local
+// coordinates (lx, ly) = (x - x0 + 1, y - y0 + 1), planes of TY+2 rows of 66.
+template <int M, int F, int TY>
+__global__ __launch_bounds__(256) void k_batch_step2(const BatchTile *__restrict__ tiles,
+                                                     const LatDesc *__restrict__ lats,
+                                                     const Ctrl *__restrict__ ctrl, int step_off, int launch_off)
+{
+    constexpr int W = 66, H = TY + 2;
+    static_assert(TY % 4 == 0 && 2 * (TY + 2) <= 128, "rows per wave must split evenly; edges fit two waves");
+    __shared__ float mid[7 * H * W];
+    const BatchTile tl = tiles[blockIdx.x];
+    const LatDesc &L = lats[tl.lat];
+    const StepArgs a = L.a;
+    const int64_t t = ctrl->t0 + step_off;
+    const int64_t t1 = t + 1;
+    const int par = (int)((ctrl->k0 + launch_off) & 1);
+    const int x0 = tl.tx * 64, y0 = tl.ty * TY;
+    if (x0 >= a.nx || y0 >= a.ny)  // whole-block exit, before the barrier
+        return;
+    const uint32_t plane = (uint32_t)a.plane;
+    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], 28u * plane);
+    const __amdgpu_buffer_rsrc_t dst = buffer_rsrc(L.buf[par ^ 1], 28u * plane);
+    const uint32_t nx = (uint32_t)a.nx;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
+    const uint32_t ta_lo = (uint32_t)((uint64_t)t & 0xffffffffu), ta_hi = (uint32_t)((uint64_t)t >> 32);
+    const uint32_t tb_lo = (uint32_t)((uint64_t)t1 & 0xffffffffu), tb_hi = (uint32_t)((uint64_t)t1 >> 32);
+    // A tile whose sources (two sites around it) do not wrap: every offset is
+    // a wave-uniform row base plus the lane.
+    const bool interior = x0 >= 2 && x0 + 66 <= a.nx && y0 >= 2 && y0 + TY + 2 <= a.ny;
+
+    // First step on the widened tile, from HBM into LDS.  Wave w takes rows
+    // w, w+4, ... of the H rows; waves 2 and 3 own one row fewer (H = 2 mod 4)
+    // and take the two edge columns (2H sites) in that slot instead.  All of
+    // a wave's loads are issued before any of its sites is computed.
+    constexpr int NR = (H + 3) / 4;
+    float f[NR][7];
+    uint32_t site[NR];
+    auto load_row = [&](float *g, uint32_t &st, int ly, bool in) {
+        if (in) {
+            const int yg = y0 - 1 + ly;
+            const uint32_t p = (uint32_t)yg & 1u;
+            const uint32_t c = (uint32_t)yg * nx + (uint32_t)x0;  // offset of (x0, yg)
+            g[0] = BufIO<float>::load(src, lane, c);
+            g[1] = BufIO<float>::load(src, lane, plane + c - 1u);
+            g[2] = BufIO<float>::load(src, lane, 2u * plane + c - nx - 1u + p);
+            g[3] = BufIO<float>::load(src, lane, 3u * plane + c - nx + p);
+            g[4] = BufIO<float>::load(src, lane, 4u * plane + c + 1u);
+            g[5] = BufIO<float>::load(src, lane, 5u * plane + c + nx + p);
+            g[6] = BufIO<float>::load(src, lane, 6u * plane + c + nx - 1u + p);
+            st = c + (uint32_t)lane;
+        } else {
+            const int xg = wrap_coord(x0 + lane, a.nx), yg = wrap_coord(y0 - 1 + ly, a.ny);
+            const PullSources32 q = pull_sources32(a, xg, yg);
+#pragma unroll
+            for (int i = 0; i < 7; ++i)
+                g[i] = BufIO<float>::load(src, q.idx[i], i * plane);
+            st = q.idx[0];  // pitch nx: own offset = site index
+        }
+    };
+    auto compute = [&](float *g, uint32_t st, int lx, int ly) {
+        float rho, jx, jy, ux, uy;
+        site_moments(g, rho, jx, jy);
+        local_ustar<M>(a, rho, jx, jy, ux, uy);
+        site_collide<F>(a, g, rho, ux, uy, st, ta_lo, ta_hi);
+#pragma unroll
+        for (int i = 0; i < 7; ++i)
+            mid[(i * H + ly) * W + lx] = g[i];
+    };
+    // slots 0 .. NR-2: rows of every wave
+    if (interior) {
+#pragma unroll
+        for (int k = 0; k < NR - 1; ++k)
+            load_row(f[k], site[k], wv + 4 * k, true);
+    } else {
+#pragma unroll
+        for (int k = 0; k < NR - 1; ++k)
+            load_row(f[k], site[k], wv + 4 * k, false);
+    }
+    // slot NR-1: last row of waves 0 and 1, edge sites of waves 2 and 3
+    const int e = (wv - 2) * 64 + lane;
+    const bool edge = wv >= 2;
+    const int elx = edge ? (e < H ? 0 : W - 1) : lane + 1;
+    const int ely = edge ? (e < H ? e : e - H) : wv + 4 * (NR - 1);
+    bool elive = true;
+    if (!edge) {
+        load_row(f[NR - 1], site[NR - 1], ely, interior);
+    } else {
+        elive = e < 2 * H;
+        if (elive) {
+            const int xg = wrap_coord(x0 - 1 + elx, a.nx), yg = wrap_coord(y0 - 1 + ely, a.ny);
+            const PullSources32 q = pull_sources32(a, xg, yg);
+#pragma unroll
+            for (int i = 0; i < 7; ++i)
+                f[NR - 1][i] = BufIO<float>::load(src, q.idx[i], i * plane);
+            site[NR - 1] = q.idx[0];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NR - 1; ++k)
+        compute(f[k], site[k], lane + 1, wv + 4 * k);
+    if (elive)
+        compute(f[NR - 1], site[NR - 1], elx, ely);
+    __syncthreads();
+
+    // second step on the tile, from LDS into HBM; y0 is even, so row r has
+    // parity r & 1 = wv & 1
+    const int p = wv & 1;
+    auto second = [&](int r) {
+        const int lx = lane + 1, ly = r + 1;
+        float f[7];
+        f[0] = mid[(0 * H + ly) * W + lx];
+        f[1] = mid[(1 * H + ly) * W + lx - 1];
+        f[2] = mid[(2 * H + ly - 1) * W + lx - 1 + p];
+        f[3] = mid[(3 * H + ly - 1) * W + lx + p];
+        f[4] = mid[(4 * H + ly) * W + lx + 1];
+        f[5] = mid[(5 * H + ly + 1) * W + lx + p];
+        f[6] = mid[(6 * H + ly + 1) * W + lx - 1 + p];
+        float rho, jx, jy, ux, uy;
+        site_moments(f, rho, jx, jy);
+        local_ustar<M>(a, rho, jx, jy, ux, uy);
+        const uint32_t row = (uint32_t)(y0 + r) * nx + (uint32_t)x0;  // pitch nx
+        site_collide<F>(a, f, rho, ux, uy, row + (uint32_t)lane, tb_lo, tb_hi);
+#pragma unroll
+        for (int i = 0; i < 7; ++i)
+            BufIO<float>::store(dst, lane, i * plane + row, f[i]);
+    };
+    if (interior) {
+        for (int r = wv; r < TY; r += 4)
+            second(r);
+    } else {
+        for (int r = wv; r < TY; r += 4)
+            if (x0 + lane < a.nx && y0 + r < a.ny)
+                second(r);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -117,7 +278,7 @@ __global__ __launch_bounds__(256) void k_batch_moments(const MomTile *__restrict
     const LatDesc &L = lats[m.lat];
     const StepArgs a = L.a;
     const int par = (int)((ctrl->k0 + node) & 1);
-    const float *__restrict__ src = (const float *)L.buf[par];
+    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], 28u * (uint32_t)a.plane);
     const int x = m.cx * 256 + threadIdx.x;
     const int yb = m.cy * kMomRows;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -130,7 +291,7 @@ __global__ __launch_bounds__(256) void k_batch_moments(const MomTile *__restrict
             bool finite = true;
 #pragma unroll
             for (int i = 0; i < 7; ++i) {
-                f[i] = ld32(src + (size_t)i * (uint32_t)a.plane, g.idx[i]);
+                f[i] = BufIO<float>::load(src, g.idx[i], i * (uint32_t)a.plane);
                 finite = finite && isfinite(f[i]);
             }
             float rho, jx, jy;
@@ -221,12 +382,12 @@ __global__ __launch_bounds__(256) void k_batch_final(const LatDesc *__restrict__
     }
 }
 
-__global__ void k_batch_advance(Ctrl *ctrl, int64_t period)
+__global__ void k_batch_advance(Ctrl *ctrl, int64_t steps, int sampled)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        ctrl->t0 += period;
-        ctrl->k0 += period;
-        ctrl->sample += 1;
+        ctrl->t0 += steps;
+        ctrl->k0 += steps;
+        ctrl->sample += sampled;
     }
 }
 
@@ -247,10 +408,17 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t lat, tiles, mtiles, ctrl, part, colpart, colmean, results, total;
-    int64_t n_tiles, n_mtiles, colpart_n, colmean_n;
+    int64_t n_tiles1, n_tiles2, n_mtiles, colpart_n, colmean_n;
 };
 
-static const int kShapes[3][2] = {{256, 1}, {128, 2}, {64, 4}};
+// Work-tile shapes: sites across, rows, steps per launch.
+struct Shape {
+    int tx, ty, steps;
+};
+constexpr int kNumShapes = 6;
+constexpr int kNumSingle = 3;  // shapes 0..2 take one step per launch
+static const Shape kShapes[kNumShapes] = {{256, 1, 1}, {128, 2, 1}, {64, 4, 1}, {64, 8, 2}, {64, 12, 2}, {64, 16, 2}};
+constexpr int64_t kChunk = 1024;  // steps per captured graph, at most
 
 static int64_t count_tiles(const lbm_params *ps, int n, int tx, int ty)
 {
@@ -265,10 +433,13 @@ static int64_t count_tiles(const lbm_params *ps, int n, int tx, int ty)
 static Layout layout(const lbm_params *ps, int n, int64_t n_samples)
 {
     Layout L{};
-    int64_t max_tiles = 0;
-    for (auto &sh : kShapes)
-        max_tiles = std::max(max_tiles, count_tiles(ps, n, sh[0], sh[1]));
-    L.n_tiles = max_tiles;
+    // room for the list of one single-step shape and one two-step shape
+    L.n_tiles1 = 0;
+    L.n_tiles2 = 0;
+    for (int k = 0; k < kNumShapes; ++k) {
+        int64_t &m = k < kNumSingle ? L.n_tiles1 : L.n_tiles2;
+        m = std::max(m, count_tiles(ps, n, kShapes[k].tx, kShapes[k].ty));
+    }
     L.n_mtiles = 0;
     L.colpart_n = 0;
     L.colmean_n = 0;
@@ -282,7 +453,7 @@ static Layout layout(const lbm_params *ps, int n, int64_t n_samples)
     L.lat = off;
     off = align256(off + sizeof(LatDesc) * n);
     L.tiles = off;
-    off = align256(off + sizeof(BatchTile) * L.n_tiles);
+    off = align256(off + sizeof(BatchTile) * (L.n_tiles1 + L.n_tiles2));
     L.mtiles = off;
     off = align256(off + sizeof(MomTile) * L.n_mtiles);
     L.ctrl = off;
@@ -325,31 +496,43 @@ static int sweep_flags(const lbm_params *ps, int n)
 
 template <int M, int F>
 static hipError_t launch_batch_step_mf(int shape, int64_t ntiles, const BatchTile *tiles, const LatDesc *lats,
-                                       const Ctrl *ctrl, int node, hipStream_t s)
+                                       const Ctrl *ctrl, int step_off, int launch_off, hipStream_t s)
 {
-    dim3 blk(kShapes[shape][0], kShapes[shape][1]);
-    hipLaunchKernelGGL((k_batch_step<M, F>), dim3((unsigned)ntiles), blk, 0, s, tiles, lats, ctrl, node);
+    const Shape &sh = kShapes[shape];
+    if (sh.steps == 1)
+        hipLaunchKernelGGL((k_batch_step<M, F>), dim3((unsigned)ntiles), dim3(sh.tx, sh.ty), 0, s, tiles, lats, ctrl,
+                           step_off, launch_off);
+    else if (sh.ty == 8)
+        hipLaunchKernelGGL((k_batch_step2<M, F, 8>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
+                           step_off, launch_off);
+    else if (sh.ty == 12)
+        hipLaunchKernelGGL((k_batch_step2<M, F, 12>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
+                           step_off, launch_off);
+    else
+        hipLaunchKernelGGL((k_batch_step2<M, F, 16>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
+                           step_off, launch_off);
     return hipGetLastError();
 }
 
 template <int M>
 static hipError_t launch_batch_step_m(int flags, int shape, int64_t ntiles, const BatchTile *tiles,
-                                      const LatDesc *lats, const Ctrl *ctrl, int node, hipStream_t s)
+                                      const LatDesc *lats, const Ctrl *ctrl, int so, int lo, hipStream_t s)
 {
     switch (flags) {
-    case 0: return launch_batch_step_mf<M, 0>(shape, ntiles, tiles, lats, ctrl, node, s);
-    case kUnitTau: return launch_batch_step_mf<M, kUnitTau>(shape, ntiles, tiles, lats, ctrl, node, s);
-    case kNoisy: return launch_batch_step_mf<M, kNoisy>(shape, ntiles, tiles, lats, ctrl, node, s);
-    default: return launch_batch_step_mf<M, kUnitTau | kNoisy>(shape, ntiles, tiles, lats, ctrl, node, s);
+    case 0: return launch_batch_step_mf<M, 0>(shape, ntiles, tiles, lats, ctrl, so, lo, s);
+    case kUnitTau: return launch_batch_step_mf<M, kUnitTau>(shape, ntiles, tiles, lats, ctrl, so, lo, s);
+    case kNoisy: return launch_batch_step_mf<M, kNoisy>(shape, ntiles, tiles, lats, ctrl, so, lo, s);
+    default: return launch_batch_step_mf<M, kUnitTau | kNoisy>(shape, ntiles, tiles, lats, ctrl, so, lo, s);
     }
 }
 
 static hipError_t launch_batch_step(int model, int flags, int shape, int64_t ntiles, const BatchTile *tiles,
-                                    const LatDesc *lats, const Ctrl *ctrl, int node, hipStream_t s)
+                                    const LatDesc *lats, const Ctrl *ctrl, int step_off, int launch_off,
+                                    hipStream_t s)
 {
     if (model == kCil)
-        return launch_batch_step_m<kCil>(flags, shape, ntiles, tiles, lats, ctrl, node, s);
-    return launch_batch_step_m<kPassive>(flags, shape, ntiles, tiles, lats, ctrl, node, s);
+        return launch_batch_step_m<kCil>(flags, shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+    return launch_batch_step_m<kPassive>(flags, shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
 }
 
 // Tuned tile shape per batch signature (arch + multiset of lattice sizes +
@@ -384,7 +567,7 @@ int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n)
         return 0;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(signature(ps, n, flags));
-    return it == g_tuned.end() ? 0 : (it->second == 0 ? 1 : (it->second == 1 ? 2 : 4));
+    return it == g_tuned.end() ? 0 : kShapes[it->second].ty;
 }
 
 size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samples)
@@ -421,7 +604,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     const int flags = sweep_flags(ps, n);
     if (flags < 0)
         return fail(LBM_EINVAL, "all lattices of a batch must agree on tau == 1 and on sigma == 0");
-    const int64_t period = o->sample_every > 0 ? o->sample_every : std::max<int64_t>(o->n_steps, 1);
+    const int64_t period = o->sample_every > 0 ? o->sample_every : o->n_steps;
     const int64_t n_samples = o->sample_every > 0 ? o->n_steps / o->sample_every : 1;
     if (o->sample_every > 0 && o->n_steps % o->sample_every != 0)
         return fail(LBM_EINVAL, "n_steps must be a multiple of sample_every");
@@ -464,16 +647,18 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     LBM_HIP_TRY(hipMemcpyAsync(d_lat, lat.data(), sizeof(LatDesc) * n, hipMemcpyHostToDevice, s));
     LBM_HIP_TRY(hipMemcpyAsync(d_mt, mt.data(), sizeof(MomTile) * mt.size(), hipMemcpyHostToDevice, s));
 
-    // tile shape: caller's choice (tile_rows 1, 2, 4 -> 256x1, 128x2, 64x4),
-    // else the tuned one for this signature, else tune now: every tuning
-    // launch reads the state in the first buffer of each lattice and writes
-    // the second (free until the sweep starts), so the state is unchanged.
+    // tile shape: caller's choice (tile_rows 1, 2, 4: 256x1, 128x2, 64x4
+    // sites, one step per launch; 8, 16: 64x8, 64x16 sites, two steps per
+    // launch), else the tuned one for this signature, else tune now: every
+    // tuning launch reads the state in the first buffer of each lattice and
+    // writes the second (free until the sweep starts), so the state is
+    // unchanged.
     int shape = -1;
-    if (o->tile_rows == 1) shape = 0;
-    else if (o->tile_rows == 2) shape = 1;
-    else if (o->tile_rows == 4) shape = 2;
-    else if (o->tile_rows != 0)
-        return fail(LBM_EINVAL, "tile_rows must be 0, 1, 2 or 4");
+    for (int k = 0; k < kNumShapes; ++k)
+        if (o->tile_rows == kShapes[k].ty)
+            shape = k;
+    if (shape < 0 && o->tile_rows != 0)
+        return fail(LBM_EINVAL, "tile_rows must be 0, 1, 2, 4, 8, 12 or 16");
     const std::string sig = signature(ps, n, flags);
     if (shape < 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -481,30 +666,37 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         if (it != g_tuned.end())
             shape = it->second;
     }
-    std::vector<std::vector<BatchTile>> lists(3);
-    for (int k = 0; k < 3; ++k)
-        if (shape < 0 || k == shape)
-            lists[k] = build_tiles(ps, n, kShapes[k][0], kShapes[k][1]);
+    BatchTile *d_tiles1 = d_tiles, *d_tiles2 = d_tiles + Ly.n_tiles1;
+    hipError_t up_err = hipSuccess;
+    auto upload = [&](int k) -> std::pair<BatchTile *, int64_t> {
+        const std::vector<BatchTile> v = build_tiles(ps, n, kShapes[k].tx, kShapes[k].ty);
+        BatchTile *d = k < kNumSingle ? d_tiles1 : d_tiles2;
+        up_err = hipMemcpyAsync(d, v.data(), sizeof(BatchTile) * v.size(), hipMemcpyHostToDevice, s);
+        // the host vector dies here: wait for the copy
+        if (up_err == hipSuccess)
+            up_err = hipStreamSynchronize(s);
+        return {up_err == hipSuccess ? d : nullptr, (int64_t)v.size()};
+    };
     if (shape < 0) {
-        shape = 0;
         float best = 1e30f;
         hipEvent_t e0, e1;
         LBM_HIP_TRY(hipEventCreate(&e0));
         LBM_HIP_TRY(hipEventCreate(&e1));
-        for (int k = 0; k < 3; ++k) {
-            LBM_HIP_TRY(hipMemcpyAsync(d_tiles, lists[k].data(), sizeof(BatchTile) * lists[k].size(),
-                                       hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_batch_set_ctrl, dim3(1), dim3(64), 0, s, d_ctrl, (int64_t)0);
+        hipLaunchKernelGGL(k_batch_set_ctrl, dim3(1), dim3(64), 0, s, d_ctrl, (int64_t)0);
+        for (int k = 0; k < kNumShapes; ++k) {
+            auto tl = upload(k);
+            if (!tl.first)
+                return hip_fail(up_err, "tile list upload");
             float ms = 0.0f;
             for (int rep = 0; rep < 3; ++rep) {
                 LBM_HIP_TRY(hipEventRecord(e0, s));
-                for (int rep10 = 0; rep10 < 10; ++rep10)  // node 0: first buffer -> second buffer
-                    LBM_HIP_TRY(launch_batch_step(ps[0].model, flags, k, (int64_t)lists[k].size(), d_tiles, d_lat,
-                                                  d_ctrl, 0, s));
+                for (int r10 = 0; r10 < 10; ++r10)  // first buffer -> second buffer
+                    LBM_HIP_TRY(launch_batch_step(ps[0].model, flags, k, tl.second, tl.first, d_lat, d_ctrl, 0, 0, s));
                 LBM_HIP_TRY(hipEventRecord(e1, s));
                 LBM_HIP_TRY(hipEventSynchronize(e1));
                 float m = 0.0f;
                 LBM_HIP_TRY(hipEventElapsedTime(&m, e0, e1));
+                m /= (float)kShapes[k].steps;  // per step
                 ms = rep == 0 ? m : std::min(ms, m);
             }
             if (ms < best) {
@@ -517,16 +709,39 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tuned[sig] = shape;
     }
-    LBM_HIP_TRY(hipMemcpyAsync(d_tiles, lists[shape].data(), sizeof(BatchTile) * lists[shape].size(),
-                               hipMemcpyHostToDevice, s));
-    const int64_t ntiles = (int64_t)lists[shape].size();
+    // the chosen list, and for a two-step shape the 256x1 list for the
+    // single steps that keep the launch count's parity equal to the step
+    // count's (so the state ends in bufs[2l + (n_steps & 1)])
+    const bool two = kShapes[shape].steps == 2;
+    auto main_list = upload(shape);
+    if (!main_list.first)
+        return hip_fail(up_err, "tile list upload");
+    std::pair<BatchTile *, int64_t> one_list = main_list;
+    if (two) {
+        one_list = upload(0);
+        if (!one_list.first)
+            return hip_fail(up_err, "tile list upload");
+    }
     const int64_t nmt = (int64_t)mt.size();
     hipLaunchKernelGGL(k_batch_set_ctrl, dim3(1), dim3(64), 0, s, d_ctrl, (int64_t)o->step0);
     LBM_HIP_TRY(hipGetLastError());
 
-    auto enqueue_period = [&](int64_t steps, bool sample) -> hipError_t {
-        for (int64_t node = 0; node < steps; ++node) {
-            hipError_t e = launch_batch_step(ps[0].model, flags, shape, ntiles, d_tiles, d_lat, d_ctrl, (int)node, s);
+    // `steps` steps, then the sample if asked, then the counter update
+    auto enqueue = [&](int64_t steps, bool sample) -> hipError_t {
+        int64_t done = 0, launches = 0;
+        if (two) {
+            int64_t q = steps / 2;
+            q -= q & 1;  // an even number of two-step launches
+            for (; launches < q; ++launches, done += 2) {
+                hipError_t e = launch_batch_step(ps[0].model, flags, shape, main_list.second, main_list.first, d_lat,
+                                                 d_ctrl, (int)done, (int)launches, s);
+                if (e != hipSuccess)
+                    return e;
+            }
+        }
+        for (; done < steps; ++launches, ++done) {
+            hipError_t e = launch_batch_step(ps[0].model, flags, two ? 0 : shape, one_list.second, one_list.first,
+                                             d_lat, d_ctrl, (int)done, (int)launches, s);
             if (e != hipSuccess)
                 return e;
         }
@@ -536,44 +751,64 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
             hipLaunchKernelGGL(k_batch_final, dim3((unsigned)n), dim3(256), 0, s, d_lat, d_ctrl, (int)steps, d_part,
                                d_colpart, d_colmean, d_results, (int)n_samples);
         }
-        hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, d_ctrl, steps);
+        hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, d_ctrl, steps, sample ? 1 : 0);
         return hipGetLastError();
     };
-
-    const int64_t n_periods = o->n_steps / period;
-    const int64_t rest = o->n_steps - n_periods * period;
-    if (n_periods > 0) {
-        if (o->use_graph) {
-            // record one period on a private stream (the caller's may be the
-            // legacy null stream, which cannot be captured), replay it on the
-            // caller's stream
-            hipGraph_t g;
-            hipGraphExec_t ge;
-            hipStream_t cap;
-            LBM_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-            hipStream_t saved = s;
-            s = cap;
-            hipError_t be = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-            hipError_t ce = be == hipSuccess ? enqueue_period(period, true) : be;
-            hipError_t ee = be == hipSuccess ? hipStreamEndCapture(cap, &g) : be;
-            s = saved;
-            hipStreamDestroy(cap);
-            if (ce != hipSuccess)
-                return hip_fail(ce, "lbm_sweep_batch capture");
-            LBM_HIP_TRY(ee);
-            LBM_HIP_TRY(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-            for (int64_t p = 0; p < n_periods; ++p)
-                LBM_HIP_TRY(hipGraphLaunch(ge, s));
-            LBM_HIP_TRY(hipStreamSynchronize(s));
-            hipGraphExecDestroy(ge);
-            hipGraphDestroy(g);
-        } else {
-            for (int64_t p = 0; p < n_periods; ++p)
-                LBM_HIP_TRY(enqueue_period(period, true));
+    // a sample period runs as `reps` chunks of `chunk` steps and a tail of
+    // `tail` steps plus the sample; each of the two pieces is captured once
+    // (on a private stream: the caller's may be the legacy null stream, which
+    // cannot be captured) and replayed on the caller's stream
+    const int64_t chunk = std::min<int64_t>(period, kChunk);
+    const int64_t reps = o->n_steps == 0 ? 0 : (period - 1) / chunk;
+    const int64_t tail = o->n_steps == 0 ? 0 : period - reps * chunk;
+    const int64_t n_periods = o->n_steps == 0 ? 1 : o->n_steps / period;
+    auto capture = [&](int64_t steps, bool sample, hipGraphExec_t *ge) -> hipError_t {
+        hipGraph_t g;
+        hipStream_t cap;
+        hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            return e;
+        hipStream_t saved = s;
+        s = cap;
+        hipError_t be = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        hipError_t ce = be == hipSuccess ? enqueue(steps, sample) : be;
+        hipError_t ee = be == hipSuccess ? hipStreamEndCapture(cap, &g) : be;
+        s = saved;
+        hipStreamDestroy(cap);
+        if (ce != hipSuccess)
+            return ce;
+        if (ee != hipSuccess)
+            return ee;
+        e = hipGraphInstantiate(ge, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        return e;
+    };
+    if (o->use_graph) {
+        hipGraphExec_t g_chunk = nullptr, g_tail = nullptr;
+        hipError_t e = reps > 0 ? capture(chunk, false, &g_chunk) : hipSuccess;
+        if (e == hipSuccess)
+            e = capture(tail, true, &g_tail);
+        for (int64_t p = 0; p < n_periods && e == hipSuccess; ++p) {
+            for (int64_t r = 0; r < reps && e == hipSuccess; ++r)
+                e = hipGraphLaunch(g_chunk, s);
+            if (e == hipSuccess)
+                e = hipGraphLaunch(g_tail, s);
+        }
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (g_chunk)
+            hipGraphExecDestroy(g_chunk);
+        if (g_tail)
+            hipGraphExecDestroy(g_tail);
+        if (e != hipSuccess)
+            return hip_fail(e, "lbm_sweep_batch graph");
+    } else {
+        for (int64_t p = 0; p < n_periods; ++p) {
+            for (int64_t r = 0; r < reps; ++r)
+                LBM_HIP_TRY(enqueue(chunk, false));
+            LBM_HIP_TRY(enqueue(tail, true));
         }
     }
-    if (rest > 0 || o->n_steps == 0)
-        LBM_HIP_TRY(enqueue_period(rest, o->n_steps == 0));
 
     std::vector<double> res((size_t)n * n_samples * 8);
     LBM_HIP_TRY(hipMemcpyAsync(res.data(), d_results, sizeof(double) * res.size(), hipMemcpyDeviceToHost, s));

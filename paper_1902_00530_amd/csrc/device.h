@@ -64,27 +64,27 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 }
 
 // Zero-sum noise of one site and step (eq. noiseDensityConservation with
-// uniform raw draws).  With 16-bit draws h_i the raw value is
+// uniform raw draws), added to f.  With 16-bit draws h_i the raw value is
 // sigma (2 h_i - 65535) / 65536; subtracting the mean over the seven
-// directions leaves sigma (7 h_i - H) / 229376 with H = sum h_i, an exact
-// integer times one constant.
-__device__ __forceinline__ void site_noise(const StepArgs &a, uint32_t site, uint32_t t_lo, uint32_t t_hi,
-                                           float eta[7])
+// directions leaves sigma (7 h_i - H) / 229376 with H = sum h_i.  The h_i, H
+// and 7 h_i - H are integers below 2^20 in magnitude, exact in float; one fma
+// then scales and adds each.
+__device__ __forceinline__ void site_add_noise(const StepArgs &a, uint32_t site, uint32_t t_lo, uint32_t t_hi,
+                                               float f[7])
 {
     const Philox4 w = philox4x32_10(site, t_lo, t_hi, 0u, a.key0, a.key1);
-    int h[7];
-    h[0] = (int)(w.v[0] & 0xffffu);
-    h[1] = (int)(w.v[0] >> 16);
-    h[2] = (int)(w.v[1] & 0xffffu);
-    h[3] = (int)(w.v[1] >> 16);
-    h[4] = (int)(w.v[2] & 0xffffu);
-    h[5] = (int)(w.v[2] >> 16);
-    h[6] = (int)(w.v[3] & 0xffffu);
-    const int H = h[0] + h[1] + h[2] + h[3] + h[4] + h[5] + h[6];
-    // (7 h_i - H) is an exact integer below 2^20 in magnitude
+    float h[7];
+    h[0] = (float)(w.v[0] & 0xffffu);
+    h[1] = (float)(w.v[0] >> 16);
+    h[2] = (float)(w.v[1] & 0xffffu);
+    h[3] = (float)(w.v[1] >> 16);
+    h[4] = (float)(w.v[2] & 0xffffu);
+    h[5] = (float)(w.v[2] >> 16);
+    h[6] = (float)(w.v[3] & 0xffffu);
+    const float H = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + h[6]);
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        eta[i] = (float)(7 * h[i] - H) * a.noise_scale;
+        f[i] = fmaf(fmaf(h[i], 7.0f, -H), a.noise_scale, f[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -156,7 +156,10 @@ __device__ __forceinline__ void local_ustar(const StepArgs &a, float rho, float 
     if (M == kCil) {
         const float u0 = fmaxf(a.B - a.A * rho * rho, 0.0f);
         const float jn2 = jx * jx + jy * jy;
-        const float s = jn2 > 0.0f ? u0 * rsqrtf(jn2) : 0.0f;
+        // 1/|j| from the hardware reciprocal square root, which flushes
+        // denormal inputs: jn2 is taken times 2^32 (exact, and normal for
+        // every jn2 > 0 below 2^96) and the result times 2^16
+        const float s = jn2 > 0.0f ? u0 * (__builtin_amdgcn_rsqf(jn2 * 0x1p32f) * 0x1p16f) : 0.0f;
         ux = s * jx;
         uy = s * jy;
     } else {
@@ -227,13 +230,8 @@ __device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], floa
         for (int i = 0; i < 7; ++i)
             f[i] = f[i] - (f[i] - eq[i]) * a.omega;
     }
-    if (F & kNoisy) {
-        float eta[7];
-        site_noise(a, site, t_lo, t_hi, eta);
-#pragma unroll
-        for (int i = 0; i < 7; ++i)
-            f[i] += eta[i];
-    }
+    if (F & kNoisy)
+        site_add_noise(a, site, t_lo, t_hi, f);
     bool fired = false;
     if (f[0] < 0.0f) {
         f[0] = 0.0f;
@@ -299,8 +297,8 @@ __device__ __forceinline__ PullSources32 pull_sources32(const StepArgs &a, int x
     const uint32_t xp = x == a.nx - 1 ? 0 : x + 1;
     const uint32_t P = (uint32_t)a.pitch;
     const uint32_t ry = (uint32_t)y * P;
-    const uint32_t ru = (y == a.ny - 1 ? 0u : (uint32_t)(y + 1)) * P;
-    const uint32_t rd = (y == 0 ? (uint32_t)(a.ny - 1) : (uint32_t)(y - 1)) * P;
+    const uint32_t ru = y == a.ny - 1 ? 0u : ry + P;
+    const uint32_t rd = y == 0 ? (uint32_t)(a.ny - 1) * P : ry - P;
     const uint32_t xr = p ? xp : (uint32_t)x;  // x + p
     const uint32_t xl = p ? (uint32_t)x : xm;  // x - 1 + p
     PullSources32 t;
@@ -340,5 +338,54 @@ __device__ __forceinline__ void st32(T *base, uint32_t elem, T v)
 {
     *(T *)((char *)base + elem * (uint32_t)sizeof(T)) = v;
 }
+
+// Buffer-resource access (gfx9 raw buffers: stride 0, 32-bit data format in
+// the third descriptor word).  One resource spans a whole population buffer;
+// the plane offset goes in the scalar offset and the element offset in the
+// vector offset, so no per-lane 64-bit address is formed.  Accesses past
+// num_records bytes read 0 and write nothing.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T>
+struct BufIO;
+
+template <>
+struct BufIO<float> {
+    __device__ __forceinline__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t elem, uint32_t first)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, elem * 4u, first * 4u, 0));
+    }
+    __device__ __forceinline__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t elem, uint32_t first, float v)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, elem * 4u, first * 4u, 0);
+    }
+};
+
+template <>
+struct BufIO<uint16_t> {
+    __device__ __forceinline__ static uint16_t load(__amdgpu_buffer_rsrc_t r, uint32_t elem, uint32_t first)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, elem * 2u, first * 2u, 0);
+    }
+    __device__ __forceinline__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t elem, uint32_t first, uint16_t v)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(v, r, elem * 2u, first * 2u, 0);
+    }
+};
+
+template <>
+struct BufIO<_Float16> {
+    __device__ __forceinline__ static _Float16 load(__amdgpu_buffer_rsrc_t r, uint32_t elem, uint32_t first)
+    {
+        return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, elem * 2u, first * 2u, 0));
+    }
+    __device__ __forceinline__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t elem, uint32_t first, _Float16 v)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, elem * 2u, first * 2u, 0);
+    }
+};
 
 }  // namespace lbm

@@ -32,12 +32,15 @@ __global__ __launch_bounds__(256) void k_step_local(const typename Store<S>::T *
     const int y = tyi * blockDim.y + threadIdx.y;
     if (x >= a.nx || y >= a.ny)
         return;
+    using T = typename Store<S>::T;
     const uint32_t plane = (uint32_t)a.plane;
+    const uint32_t bytes = 7u * plane * (uint32_t)sizeof(T);  // < 2^32: 7 plane < 2^30
+    const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(src, bytes), rd = buffer_rsrc(dst, bytes);
     const PullSources32 g_src = pull_sources32(a, x, y);
     float f[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        f[i] = Store<S>::widen(ld32(src + (size_t)i * plane, g_src.idx[i]), i == 0 ? a.wr0 : a.wr1);
+        f[i] = Store<S>::widen(BufIO<T>::load(rs, g_src.idx[i], i * plane), i == 0 ? a.wr0 : a.wr1);
     float rho, jx, jy, ux, uy;
     site_moments(f, rho, jx, jy);
     local_ustar<M>(a, rho, jx, jy, ux, uy);
@@ -45,7 +48,7 @@ __global__ __launch_bounds__(256) void k_step_local(const typename Store<S>::T *
     const uint32_t own = g_src.idx[0];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        st32(dst + (size_t)i * plane, own, Store<S>::narrow(f[i], i == 0 ? a.wr0 : a.wr1));
+        BufIO<T>::store(rd, own, i * plane, Store<S>::narrow(f[i], i == 0 ? a.wr0 : a.wr1));
 }
 
 // Same body with 64-bit offsets, for buffers of 2^30 elements per plane set

@@ -18,6 +18,8 @@ inside a sweep, and the check it is judged by.
 """
 import ctypes
 
+import math
+
 import numpy as np
 
 from . import (Batch, lbm_channel_affine, lbm_channel_stats, lbm_cnn_adam, lbm_cnn_backward, lbm_cnn_forward,
@@ -246,7 +248,10 @@ def fit_normalisation(net, X, stream):
 
 def train(net, X, T, epochs, batch, lr, stream, seed=0, log=None):
     """Adam on normalised pairs (inputs and targets share the channel
-    normalisation so the residual connection predicts the change)."""
+    normalisation so the residual connection predicts the change), with the
+    step size taken down from lr to lr/20 over the epochs on a half cosine
+    (the targets carry the method's own noise, so a constant step leaves the
+    weights wandering at the end)."""
     import torch
     Xn = X.clone()
     Tn = T.clone()
@@ -256,12 +261,13 @@ def train(net, X, T, epochs, batch, lr, stream, seed=0, log=None):
     n = X.shape[0]
     losses = []
     for ep in range(epochs):
+        lr_ep = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * ep / max(1, epochs))))
         perm = torch.randperm(n, generator=g).to(X.device)
         tot = 0.0
         nb = 0
         for s in range(0, n - batch + 1, batch):
             idx = perm[s:s + batch]
-            loss = net.train_step(Xn[idx].contiguous(), Tn[idx, :COUT].contiguous(), lr, stream)
+            loss = net.train_step(Xn[idx].contiguous(), Tn[idx, :COUT].contiguous(), lr_ep, stream)
             tot += float(loss.item()) if (nb % 16 == 0) else 0.0
             nb += 1
         losses.append(tot / max(1, (nb + 15) // 16))

@@ -2,8 +2,8 @@
 
 A batch member runs the same site body as the single-lattice kernel with its
 own seed and noise counters, so its state after the sweep must equal the
-single-lattice result bit for bit, for every work-tile shape and with or
-without graph replay; the FP64 samples use the same reduction tree as
+single-lattice result bit for bit, for every work-tile shape (one or two steps
+per launch) and with or without graph replay; the FP64 samples use the same reduction tree as
 lbm_moments and must agree with it to rounding of the final divisions.
 """
 import numpy as np
@@ -63,11 +63,13 @@ def single_runs(L, cfgs, states, steps, sample_every=0):
     return finals, samples
 
 
-@pytest.mark.parametrize("tile_rows,use_graph", [(1, 1), (2, 1), (4, 0), (0, 1)])
-def test_batch_member_equals_single_run(L, tile_rows, use_graph):
+@pytest.mark.parametrize("tile_rows,use_graph,steps", [(1, 1, 37), (2, 1, 37), (4, 0, 37), (0, 1, 37),
+                                                      (8, 1, 37), (16, 1, 38), (16, 0, 37), (8, 0, 6),
+                                                      (12, 1, 39)])
+def test_batch_member_equals_single_run(L, tile_rows, use_graph, steps):
     cfgs = small_batch()
     states = init_states(L, cfgs)
-    steps, every = 37, 0
+    every = 0
     finals, samples = single_runs(L, cfgs, states, steps)
     b = L.Batch([_gparams(L, c) for c in cfgs])
     for l, f0 in enumerate(states):
@@ -82,15 +84,16 @@ def test_batch_member_equals_single_run(L, tile_rows, use_graph):
             assert abs(o[k] - s[k]) <= 1e-12 * max(1.0, abs(s[k])), (l, k, o[k], s[k])
 
 
-def test_batch_samples_and_resume(L):
+@pytest.mark.parametrize("tile_rows", [0, 16])
+def test_batch_samples_and_resume(L, tile_rows):
     cfgs = small_batch()
     states = init_states(L, cfgs)
     finals, samples = single_runs(L, cfgs, states, 40, sample_every=10)
     b = L.Batch([_gparams(L, c) for c in cfgs])
     for l, f0 in enumerate(states):
         b.set_state(l, f0)
-    out1 = b.run(20, sample_every=10)
-    out2 = b.run(20, sample_every=10)   # continues the noise counters
+    out1 = b.run(20, sample_every=10, tile_rows=tile_rows)
+    out2 = b.run(20, sample_every=10, tile_rows=tile_rows)   # continues the noise counters
     for l in range(len(cfgs)):
         got = out1[l] + out2[l]
         assert [o["step"] for o in got] == [10, 20, 30, 40]
@@ -124,3 +127,25 @@ def test_batch_zero_steps_samples_initial_state(L):
         o = lat.observables()
         lat.close()
         assert out[l][0]["step"] == 0 and abs(out[l][0]["M"] - o["M"]) <= 1e-9 * o["M"]
+
+
+@pytest.mark.parametrize("tile_rows", [1, 12, 16])
+def test_batch_small_lattices_and_long_period(L, tile_rows):
+    """Lattices narrower and shorter than a work tile (the widened two-step
+    tile wraps around them more than once) over a sample period longer than
+    one captured chunk (2100 steps: two chunks and a tail)."""
+    sizes = [(2, 2), (40, 6), (66, 18), (64, 16), (130, 34)]
+    cfgs = [_cfg(SI.CIL, nx, ny, tau=1.0, sigma=4 / 70, A=0.125, B=0.3, seed=SI.seed_for(4, l))
+            for l, (nx, ny) in enumerate(sizes)]
+    states = init_states(L, cfgs)
+    steps = 2100
+    finals, samples = single_runs(L, cfgs, states, steps)
+    b = L.Batch([_gparams(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    out = b.run(steps, tile_rows=tile_rows)
+    for l in range(len(cfgs)):
+        assert torch.equal(b.state(l), finals[l]), (l, sizes[l])
+        assert out[l][0]["step"] == steps
+        assert abs(out[l][0]["M"] - samples[l][0]["M"]) <= 1e-12 * samples[l][0]["M"]
+

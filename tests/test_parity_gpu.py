@@ -337,8 +337,8 @@ def test_zero_density_sites(L, orc):
 
 def test_full_size_cil_1024(L, orc):
     """The benchmark workload's lattice (1024 x 1024, CIL, FP32, launch
-    configuration of the benchmark): GPU init and 5 steps against the oracle on
-    the whole lattice."""
+    configuration of the benchmark): GPU init, one step and five steps
+    against the oracle on the whole lattice."""
     cfg = SI.cil_1024(1.0)
     ini = cfg.pop("init")
     po = _oparams(orc, cfg)
@@ -347,10 +347,19 @@ def test_full_size_cil_1024(L, orc):
     torch.cuda.synchronize()
     g0 = lat.state[:, :, : cfg["nx"]].double().cpu().numpy()
     assert rel_err(g0, f0) < 2e-7
-    lat.step(5)
+    lat.step(1)
+    got1 = lat.state[:, :, : cfg["nx"]].double().cpu().numpy()
+    lat.step(4)
     got = lat.state[:, :, : cfg["nx"]].double().cpu().numpy()
     lat.close()
+    assert rel_err(got1, orc.run(po, g0.copy(), 1)) < 1e-6
     ref = orc.run(po, g0.copy(), 5)
-    # paper-scaled noise: rounding is amplified ~2x over 5 steps (oracle
-    # self-sensitivity), on top of <= 1e-6 per step
-    assert rel_err(got, ref) < 1e-5
+    d = got - ref
+    assert np.sqrt((d * d).mean() / (ref * ref).mean()) < 1e-6
+    # This disordered start with the paper's noise is chaotic: u* = U0 j/|j|
+    # is ill-conditioned where |j| is small, and the oracle itself turns a
+    # 1e-7 relative perturbation into `amp` x 1e-7 after five steps.  The
+    # one-step error (< 1e-6) grows by at most that factor at the worst
+    # sites, summed over the steps.
+    amp = _self_sensitivity(orc, po, g0, 5) / 1e-7
+    assert rel_err(got, ref) < 2e-6 * amp
