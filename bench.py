@@ -5,20 +5,21 @@ in FP32, one per mean density 0.5, 0.75, 1.0, 1.25, 1.5 (the paper's CIL
 parameters A = 2, B = 0.3, tau = 1, sigma = 1/70 rescaled by lambda = 4 to
 A = 0.125, sigma = 4/70), Gaussian polarisation noise (std 0.05) about +x.
 One timed step advances all five lattices by one lattice Boltzmann step; the
-five lattices run as one batch (lbm_sweep_batch: one kernel per step over
-every lattice, one sample period replayed as a HIP graph), with the FP64
-observables sampled once at the end of the timed steps.  Inputs are
+five lattices run as one batch (lbm_sweep_batch with its tuned work tile:
+two steps per launch on 64 x 16 tiles, graphs of up to 1024 steps), with the
+FP64 observables sampled once at the end of the timed steps.  Inputs are
 synthetic, seeded and resident in HBM before timing starts.
 
 Prints one JSON line: MLUPS (million lattice-site updates per second), the
-roofline of the step kernel (algorithmic 56 B per site-update in FP32, 28 B
-in the 16-bit deviation storages, against the 8 TB/s HBM3E peak), variants
-(per-lattice launches, 4096^2 in FP32 / BF16 / FP16, a 256-lattice batched
-phase sweep against the same lattices run one by one) and the FP64 oracle
-timed on the host cores.
+roofline of the dominant kernel (the two-step kernel against the VALU issue
+peak, with its HBM bytes beside it; a one-step kernel against the 8 TB/s HBM3E
+peak at 56 B per site-update in FP32, 28 B in the 16-bit deviation
+storages), variants (one step per launch, per-lattice launches, 4096^2 in
+FP32 / BF16 / FP16, a 256-lattice batched phase sweep against the same
+lattices run one by one, the learned surrogate) and the FP64 oracle timed on
+the host cores.
 """
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -30,6 +31,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 BYTES_PER_SITE = {0: 56, 1: 28, 2: 28}
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU lane-instructions per site-update of the fused CIL step (FP32, tau 1,
+# noise on), measured as SQ_INSTS_VALU / SQ_WAVES of the one-step kernel with
+# one site per lane (profiles/k_batch_step2_cil_5x1024.md)
+VALU_PER_SITE_UPDATE = 190
 
 
 def parse():
@@ -43,6 +50,10 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline measurement only (no variants)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=25)
+    ap.add_argument("--tile-rows", type=int, default=0,
+                    help="batch work tile: 0 tuned, 1/2/4 one step per launch, 8/12/16 two steps per launch")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy a 7 x 1024 x 1024 float buffer --steps times (counter calibration)")
     return ap.parse_args()
 
 
@@ -97,31 +108,72 @@ def time_single(L, torch, cfgs, steps, warmup, storage=0):
     return ms, obs
 
 
-def time_batch(L, torch, cfgs, steps, warmup):
-    """All lattices advanced by lbm_sweep_batch (one launch per step)."""
+def time_batch(L, torch, cfgs, steps, warmup, tile_rows=0):
+    """All lattices advanced by lbm_sweep_batch (one launch per step, or per
+    two steps for the two-step tiles)."""
     lats = make_lattices(L, cfgs)
     b = L.Batch([lat.params for lat in lats])
     for l, lat in enumerate(lats):
         b.set_state(l, lat.state)
         lat.close()
-    b.run(warmup)
+    b.run(warmup, tile_rows=tile_rows)
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
-    out = b.run(steps)
+    out = b.run(steps, tile_rows=tile_rows)
     e1.record(s)
     torch.cuda.synchronize()
-    time_batch.tile_rows = L.lbm_sweep_tile_rows(b.params, b.n)
+    time_batch.tile_rows = tile_rows or L.lbm_sweep_tile_rows(b.params, b.n)
     return e0.elapsed_time(e1), [o[-1] for o in out]
 
 
+CHUNK = 1024  # steps per captured graph in lbm_sweep_batch
+
+
+def batch_launches(steps, rows):
+    """(two-step launches, one-step launches) of an unsampled sweep of `steps`
+    steps with work-tile rows `rows`: the same schedule lbm_sweep_batch
+    builds (graphs of at most CHUNK steps; in each, an even number of
+    two-step launches, then one-step launches for the rest)."""
+    if rows < 8:
+        return 0, steps
+    two = one = 0
+    left = steps
+    while left > 0:
+        c = min(left, CHUNK)
+        q = c // 2
+        q -= q & 1
+        two += q
+        one += c - 2 * q
+        left -= c
+    return two, one
+
+
+def copy_probe(torch, copies):
+    """A plain copy of 7 x 1024 x 1024 floats (28 MiB read, 28 MiB written)
+    `copies` times: the known-size kernel the HBM counters are scaled by."""
+    a = torch.rand((7, 1024, 1024), device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(copies):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"copy_probe": {"bytes_read_per_copy": a.numel() * 4, "bytes_written_per_copy": b.numel() * 4,
+                           "copies": copies}}
+
+
+# the sources the batched step kernels are built from (their bodies, the
+# parameters the host prepares for them, and the launch code)
+KERNEL_SOURCES = ("batch.hip", "capi.hip", "device.h", "internal.h")
+
+
 def source_fingerprint():
-    """sha256 over the library's kernel sources (names and contents)."""
+    """sha256 over the batched step kernels' sources (names and contents)."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1902_00530_amd", "csrc", "*"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for name in KERNEL_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_1902_00530_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
@@ -138,6 +190,26 @@ def measured_traffic(name):
     if c.get("source_sha256") != source_fingerprint():
         return None
     return c
+
+
+def roofline_two_step(sites, per_launch_s, kernel, rows):
+    """Two steps per launch: 2 x sites site-updates of VALU work against the
+    VALU issue peak; the HBM side is the state read and written once."""
+    tops = VALU_PER_SITE_UPDATE * 2 * sites / per_launch_s / 1e12
+    hbm = BYTES_PER_SITE[0] * sites / per_launch_s / 1e9
+    r = {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+         "unit": "T VALU lane-instructions/s", "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": None,
+         "kernel": kernel, "avg_launch_us": round(per_launch_s * 1e6, 3),
+         "valu_per_site_update": VALU_PER_SITE_UPDATE, "site_updates_per_launch": 2 * sites,
+         "hbm": {"achieved": round(hbm, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                 "frac": round(hbm / HBM_PEAK_GBPS, 4), "bytes_per_launch": BYTES_PER_SITE[0] * sites}}
+    c = measured_traffic(f"counters_k_batch_step2_{rows}_cil_5x1024.json")
+    if c is not None and c.get("sites") == sites:
+        r["traffic"] = round(c["traffic_bytes_per_launch"] / per_launch_s / 1e9, 1)
+        r["traffic_unit"] = "GB/s (measured HBM bytes per launch / avg launch)"
+        r["traffic_bytes_per_launch"] = c["traffic_bytes_per_launch"]
+        r["traffic_vs_algorithmic"] = round(c["traffic_bytes_per_launch"] / c["algorithmic_bytes_per_launch"], 4)
+    return r
 
 
 def roofline(storage, sites_per_launch, per_launch_s, kernel):
@@ -159,6 +231,9 @@ def main():
     import synth_inputs as SI
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        print(json.dumps(copy_probe(torch, args.steps)), flush=True)
+        return
     if args.workload == "cil1024x5":
         cfgs = [SI.cil_1024(r, l) for l, r in enumerate(SI.CIL_DENSITIES)]
         wname = "CIL 5 x 1024x1024 periodic D2Q7, mean density 0.5..1.5 (x4 scaled), sigma 4/70, tau 1"
@@ -169,11 +244,21 @@ def main():
     mode = args.mode if args.storage == 0 else "single"
 
     t_wall = time.perf_counter()
+    rows = 0
     if mode == "batch":
-        ms, obs = time_batch(L, torch, cfgs, args.steps, args.warmup)
-        launches = args.steps
-        tile = {1: "256x1", 2: "128x2", 4: "64x4"}.get(getattr(time_batch, "tile_rows", 0), "?")
-        kernel = f"k_batch_step<CIL,unit-tau,noisy>, tuned tile {tile} (+1 FP64 sample at the end)"
+        ms, obs = time_batch(L, torch, cfgs, args.steps, args.warmup, args.tile_rows)
+        rows = time_batch.tile_rows
+        two, one = batch_launches(args.steps, rows)
+        if two:
+            # a one-step launch moves the same bytes as a two-step launch
+            # and does half the site work: count it as half a launch
+            launches = two + 0.5 * one
+            kernel = (f"k_batch_step2<CIL,unit-tau,noisy,{rows}> (64x{rows} tiles, two steps per launch; "
+                      f"{two} launches + {one} one-step launches + 1 FP64 sample)")
+        else:
+            launches = args.steps
+            tile = {1: "256x1", 2: "128x2", 4: "64x4"}.get(rows, "?")
+            kernel = f"k_batch_step<CIL,unit-tau,noisy>, tile {tile} (+1 FP64 sample at the end)"
     else:
         ms, obs = time_single(L, torch, cfgs, args.steps, args.warmup, args.storage)
         launches, kernel = args.steps * len(cfgs), "k_step_local<CIL,F32,unit-tau,noisy>"
@@ -195,14 +280,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "lattices": len(cfgs), "sites": sites, "storage": args.storage,
                    "mode": mode},
-        "roofline": roofline(args.storage, sites / (launches / args.steps), per_launch, kernel),
+        "roofline": (roofline_two_step(sites, per_launch, kernel, rows) if rows >= 8 else
+                     roofline(args.storage, sites / (launches / args.steps), per_launch, kernel)),
         "phi": [round(o["phi"], 6) for o in obs],
         "wall_s": round(wall, 3),
     }
 
-    if mode == "batch" and args.workload == "cil1024x5" and args.storage == 0:
-        c = measured_traffic("counters_k_batch_step_cil_5x1024.json")
-        if c is not None:
+    if mode == "batch" and args.workload == "cil1024x5" and args.storage == 0 and rows < 8:
+        c = measured_traffic(f"counters_k_batch_step_{rows}_cil_5x1024.json")
+        if c is not None and c.get("sites") == sites:
             line["roofline"]["traffic"] = round(c["traffic_bytes_per_launch"] / per_launch / 1e9, 1)
             line["roofline"]["traffic_bytes_per_launch"] = c["traffic_bytes_per_launch"]
             line["roofline"]["traffic_vs_algorithmic"] = round(
@@ -211,6 +297,18 @@ def main():
     if not args.quick and args.workload == "cil1024x5" and args.storage == 0:
         var = {}
         k = max(200, args.steps // 4)
+        # the same batch with one step per launch (256 x 1 tiles): the plain
+        # fused step against the HBM roofline
+        ms_one, _ = time_batch(L, torch, cfgs, k, 20, tile_rows=1)
+        per_one = ms_one / 1e3 / k
+        r1 = roofline(0, sites, per_one, "k_batch_step<CIL,unit-tau,noisy>, 256x1 tiles")
+        c = measured_traffic("counters_k_batch_step_1_cil_5x1024.json")
+        if c is not None and c.get("sites") == sites:
+            r1["traffic"] = round(c["traffic_bytes_per_launch"] / per_one / 1e9, 1)
+            r1["traffic_vs_algorithmic"] = round(c["traffic_bytes_per_launch"] / c["algorithmic_bytes_per_launch"], 4)
+        var["cil1024x5_one_step_per_launch"] = {"MLUPS": round(sites * k / (ms_one / 1e3) / 1e6, 1),
+                                                "roofline": r1,
+                                                "two_step_speedup": round((ms_one / k) / (ms / args.steps), 3)}
         ms1, _ = time_single(L, torch, cfgs, k, 20)
         var["cil1024x5_per_lattice_launches"] = {"MLUPS": round(sites * k / (ms1 / 1e3) / 1e6, 1),
                                                   "batch_speedup": round((ms1 / k) / (ms / args.steps), 3)}
@@ -230,6 +328,11 @@ def main():
                 v["stated_error_vs_fp64"] = {"bf16_dev": "100-step rel Linf 1.9e-3, mass drift 2.1e-3 / 1e4 steps",
                                              "f16_dev": "100-step rel Linf 2.4e-4, mass drift 2.8e-5 / 1e4 steps"}[name]
             var["cil4096_" + name] = v
+        # FP32 at 4096^2 through the batched path (two steps per launch)
+        ms2, _ = time_batch(L, torch, big, 200, 10)
+        rows2 = time_batch.tile_rows
+        var["cil4096_f32_two_step"] = {"MLUPS": round(nbig * 200 / (ms2 / 1e3) / 1e6, 1), "tile_rows": rows2,
+                                       "speedup_vs_f32_one_step": round(f32 / (ms2 / 1e3 / 200), 3)}
         # 256-lattice batched phase sweep vs the same lattices one by one
         bcfgs = SI.batch_sweep()
         nb_sites = sum(c["nx"] * c["ny"] for c in bcfgs)

@@ -178,7 +178,7 @@ typedef struct lbm_sweep_opts {
     int64_t sample_every; /* observables every sample_every steps (0: once, at the end) */
     int64_t step0;        /* absolute step index of the first step (noise counter) */
     int32_t tile_rows;    /* work tile: 1, 2, 4 = 256x1, 128x2, 64x4 sites, one step per
-                             launch; 8, 12, 16 = 64x8, 64x12, 64x16 sites, two steps per launch
+                             launch; 8, 16 = 64x8, 64x16 sites, two steps per launch
                              (the second from LDS); 0 = tuned (every shape timed on the
                              batch itself, cached per batch signature) */
     int32_t use_graph;    /* 1: replay one captured sample period as a HIP graph */

@@ -415,9 +415,9 @@ struct Layout {
 struct Shape {
     int tx, ty, steps;
 };
-constexpr int kNumShapes = 6;
+constexpr int kNumShapes = 5;
 constexpr int kNumSingle = 3;  // shapes 0..2 take one step per launch
-static const Shape kShapes[kNumShapes] = {{256, 1, 1}, {128, 2, 1}, {64, 4, 1}, {64, 8, 2}, {64, 12, 2}, {64, 16, 2}};
+static const Shape kShapes[kNumShapes] = {{256, 1, 1}, {128, 2, 1}, {64, 4, 1}, {64, 8, 2}, {64, 16, 2}};
 constexpr int64_t kChunk = 1024;  // steps per captured graph, at most
 
 static int64_t count_tiles(const lbm_params *ps, int n, int tx, int ty)
@@ -504,9 +504,6 @@ static hipError_t launch_batch_step_mf(int shape, int64_t ntiles, const BatchTil
                            step_off, launch_off);
     else if (sh.ty == 8)
         hipLaunchKernelGGL((k_batch_step2<M, F, 8>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
-                           step_off, launch_off);
-    else if (sh.ty == 12)
-        hipLaunchKernelGGL((k_batch_step2<M, F, 12>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
                            step_off, launch_off);
     else
         hipLaunchKernelGGL((k_batch_step2<M, F, 16>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
@@ -658,7 +655,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         if (o->tile_rows == kShapes[k].ty)
             shape = k;
     if (shape < 0 && o->tile_rows != 0)
-        return fail(LBM_EINVAL, "tile_rows must be 0, 1, 2, 4, 8, 12 or 16");
+        return fail(LBM_EINVAL, "tile_rows must be 0, 1, 2, 4, 8 or 16");
     const std::string sig = signature(ps, n, flags);
     if (shape < 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -683,22 +680,47 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         LBM_HIP_TRY(hipEventCreate(&e0));
         LBM_HIP_TRY(hipEventCreate(&e1));
         hipLaunchKernelGGL(k_batch_set_ctrl, dim3(1), dim3(64), 0, s, d_ctrl, (int64_t)0);
+        // each shape: ten launches captured in a graph (as the sweep runs
+        // them), replayed once to warm up and three times timed; the least
+        // time per step wins
         for (int k = 0; k < kNumShapes; ++k) {
             auto tl = upload(k);
             if (!tl.first)
                 return hip_fail(up_err, "tile list upload");
-            float ms = 0.0f;
-            for (int rep = 0; rep < 3; ++rep) {
-                LBM_HIP_TRY(hipEventRecord(e0, s));
-                for (int r10 = 0; r10 < 10; ++r10)  // first buffer -> second buffer
-                    LBM_HIP_TRY(launch_batch_step(ps[0].model, flags, k, tl.second, tl.first, d_lat, d_ctrl, 0, 0, s));
-                LBM_HIP_TRY(hipEventRecord(e1, s));
-                LBM_HIP_TRY(hipEventSynchronize(e1));
+            hipStream_t cap;
+            LBM_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            for (int r10 = 0; r10 < 10 && e == hipSuccess; ++r10)  // first buffer -> second buffer
+                e = launch_batch_step(ps[0].model, flags, k, tl.second, tl.first, d_lat, d_ctrl, 0, 0, cap);
+            hipError_t ee = hipStreamEndCapture(cap, &g);
+            hipStreamDestroy(cap);
+            if (e == hipSuccess)
+                e = ee;
+            hipGraphExec_t ge = nullptr;
+            if (e == hipSuccess)
+                e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            if (g)
+                hipGraphDestroy(g);
+            float ms = 1e30f;
+            for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+                e = hipEventRecord(e0, s);
+                if (e == hipSuccess)
+                    e = hipGraphLaunch(ge, s);
+                if (e == hipSuccess)
+                    e = hipEventRecord(e1, s);
+                if (e == hipSuccess)
+                    e = hipEventSynchronize(e1);
                 float m = 0.0f;
-                LBM_HIP_TRY(hipEventElapsedTime(&m, e0, e1));
-                m /= (float)kShapes[k].steps;  // per step
-                ms = rep == 0 ? m : std::min(ms, m);
+                if (e == hipSuccess)
+                    e = hipEventElapsedTime(&m, e0, e1);
+                if (rep > 0)
+                    ms = std::min(ms, m / (float)kShapes[k].steps);
             }
+            if (ge)
+                hipGraphExecDestroy(ge);
+            if (e != hipSuccess)
+                return hip_fail(e, "tile-shape tuning");
             if (ms < best) {
                 best = ms;
                 shape = k;

@@ -68,8 +68,8 @@ StepArgs make_step_args(const lbm_params &p, int64_t pitch)
     a.plane = (int64_t)p.ny * pitch;
     a.omega = (float)(1.0 / p.tau);
     a.noise_scale = (float)(p.sigma / 229376.0);
-    a.A = (float)p.A;
-    a.B = (float)p.B;
+    a.A16 = (float)p.A * 65536.0f;
+    a.B16 = (float)p.B * 65536.0f;
     a.C = (float)p.C;
     a.rho_star = p.model == LBM_MIPS ? (float)p.rho_star : 1.0f;
     a.inv_rho_star = p.model == LBM_MIPS ? (float)(1.0 / p.rho_star) : 1.0f;

@@ -21,7 +21,7 @@ struct StepArgs {
     int64_t plane;      // elements per population plane (ny * pitch)
     float omega;        // 1 / tau (0 for tau = +inf)
     float noise_scale;  // sigma / 229376: eta_i = (7 h_i - sum h) * noise_scale
-    float A, B;         // CIL
+    float A16, B16;     // CIL A and B times 2^16 (exact), see local_ustar
     float C, rho_star, inv_rho_star, u_max;  // MIPS
     float wr0, wr1;     // w_0 rho_ref, w_i rho_ref (deviation storages)
     uint32_t key0, key1;
@@ -154,12 +154,13 @@ template <int M>
 __device__ __forceinline__ void local_ustar(const StepArgs &a, float rho, float jx, float jy, float &ux, float &uy)
 {
     if (M == kCil) {
-        const float u0 = fmaxf(a.B - a.A * rho * rho, 0.0f);
-        const float jn2 = jx * jx + jy * jy;
         // 1/|j| from the hardware reciprocal square root, which flushes
         // denormal inputs: jn2 is taken times 2^32 (exact, and normal for
-        // every jn2 > 0 below 2^96) and the result times 2^16
-        const float s = jn2 > 0.0f ? u0 * (__builtin_amdgcn_rsqf(jn2 * 0x1p32f) * 0x1p16f) : 0.0f;
+        // every jn2 > 0 below 2^96), and U0 comes times 2^16 from the
+        // pre-scaled A and B (exact), so s = U0 / |j| with no extra rounding
+        const float u0s = fmaxf(a.B16 - a.A16 * rho * rho, 0.0f);
+        const float jn2 = jx * jx + jy * jy;
+        const float s = jn2 > 0.0f ? u0s * __builtin_amdgcn_rsqf(jn2 * 0x1p32f) : 0.0f;
         ux = s * jx;
         uy = s * jy;
     } else {
@@ -232,14 +233,19 @@ __device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], floa
     }
     if (F & kNoisy)
         site_add_noise(a, site, t_lo, t_hi, f);
+    // f < 0 as a class test (negative infinity, normal, denormal or zero):
+    // one compare per population with no NaN canonicalisation, NaN excluded
+    // as by the ordered compare.  -0 counts as negative here; the rules then
+    // leave the values as they are and only the rescale to rho runs.
+    constexpr int kNegative = 0x3c;
     bool fired = false;
-    if (f[0] < 0.0f) {
+    if (__builtin_amdgcn_classf(f[0], kNegative)) {
         f[0] = 0.0f;
         fired = true;
     }
 #pragma unroll
     for (int k = 1; k <= 3; ++k) {
-        if (f[k] < 0.0f || f[k + 3] < 0.0f) {
+        if (__builtin_amdgcn_classf(f[k], kNegative) | __builtin_amdgcn_classf(f[k + 3], kNegative)) {
             const float d = f[k] - f[k + 3];
             f[k] = fmaxf(d, 0.0f);
             f[k + 3] = fmaxf(-d, 0.0f);
@@ -247,11 +253,13 @@ __device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], floa
         }
     }
     if (fired) {
+        // every f_i >= 0 here, so a zero sum means zero populations and the
+        // factor 0 gives them back unchanged
         const float s = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6];
         const float r = s > 0.0f ? rho * __builtin_amdgcn_rcpf(s) : 0.0f;
 #pragma unroll
         for (int i = 0; i < 7; ++i)
-            f[i] = s > 0.0f ? f[i] * r : 0.0f;
+            f[i] *= r;
     }
 }
 
