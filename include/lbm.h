@@ -181,7 +181,11 @@ typedef struct lbm_sweep_opts {
                              launch; 8, 16 = 64x8, 64x16 sites, two steps per launch
                              (the second from LDS); 0 = tuned (every shape timed on the
                              batch itself, cached per batch signature) */
-    int32_t use_graph;    /* 1: replay one captured sample period as a HIP graph */
+    int32_t use_graph;    /* 0: launch every kernel directly; 1: run each sample period
+                             as captured HIP graphs of at most 1024 steps, kept (16 most
+                             recent) and replayed by later calls with the same batch,
+                             workspace and step counts; 2: prepare only: tune and
+                             capture those graphs, run nothing and leave out unwritten */
 } lbm_sweep_opts;
 
 /* Workspace bytes lbm_sweep_batch needs for these n lattices and n_samples

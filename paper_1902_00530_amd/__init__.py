@@ -264,7 +264,9 @@ class Batch:
 
     def run(self, n_steps, sample_every=0, tile_rows=0, use_graph=1, stream=None, subset=None):
         """Advance every lattice (or only the lattices listed in subset) by
-        n_steps; returns a list (per advanced lattice) of sample dicts."""
+        n_steps; returns a list (per advanced lattice) of sample dicts.
+        use_graph=2 only prepares the launch plan for such a call (tuning,
+        captured graphs) and advances nothing."""
         import torch
         idx = list(range(self.n)) if subset is None else [int(i) for i in subset]
         m = len(idx)
@@ -288,6 +290,8 @@ class Batch:
         opts = lbm_sweep_opts(int(n_steps), int(sample_every), int(self.step_index), int(tile_rows), int(use_graph))
         st = stream if stream is not None else torch.cuda.current_stream()
         lbm_sweep_batch(params, m, opts, bufs, self._ws.data_ptr(), need, st.cuda_stream, out)
+        if use_graph == 2:  # prepared the launch plan only; no step ran
+            return []
         if subset is None:
             self.step_index += n_steps
         for l in idx:

@@ -31,8 +31,10 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.h"
@@ -549,6 +551,60 @@ static std::string signature(const lbm_params *ps, int n, int flags)
     return s;
 }
 
+// Instantiated sample-period graphs, least recently used first out.
+struct GraphKey {
+    int device;
+    const void *tiles_main, *tiles_one, *lat, *ctrl, *mt, *part, *colpart, *colmean, *results;
+    int model, flags, shape;
+    int64_t ntiles_main, ntiles_one, nmt, n, n_samples, steps;
+    int sample;
+    auto tie() const
+    {
+        return std::tie(device, tiles_main, tiles_one, lat, ctrl, mt, part, colpart, colmean, results, model, flags,
+                        shape, ntiles_main, ntiles_one, nmt, n, n_samples, steps, sample);
+    }
+    bool operator==(const GraphKey &o) const { return tie() == o.tie(); }
+};
+
+// An executable graph, destroyed when the last holder lets go (the cache or
+// a call still running it).
+struct GraphExec {
+    hipGraphExec_t exec = nullptr;
+    ~GraphExec()
+    {
+        if (exec)
+            hipGraphExecDestroy(exec);
+    }
+};
+using GraphPtr = std::shared_ptr<GraphExec>;
+
+constexpr size_t kGraphCacheSize = 16;
+static std::mutex g_graph_mu;
+// most recently used last; never destroyed, so no HIP call runs from a static
+// destructor after the runtime may have shut down at process exit
+static auto &g_graphs = *new std::vector<std::pair<GraphKey, GraphPtr>>();
+
+static GraphPtr graph_cache_get(const GraphKey &k)
+{
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (size_t i = 0; i < g_graphs.size(); ++i)
+        if (g_graphs[i].first == k) {
+            auto hit = g_graphs[i];
+            g_graphs.erase(g_graphs.begin() + (ptrdiff_t)i);
+            g_graphs.push_back(hit);
+            return hit.second;
+        }
+    return nullptr;
+}
+
+static void graph_cache_put(const GraphKey &k, const GraphPtr &g)
+{
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    if (g_graphs.size() >= kGraphCacheSize)
+        g_graphs.erase(g_graphs.begin());
+    g_graphs.emplace_back(k, g);
+}
+
 }  // namespace lbm
 
 using namespace lbm;
@@ -581,6 +637,8 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         return fail(LBM_EINVAL, "null argument or empty batch");
     if (o->n_steps < 0 || o->sample_every < 0 || o->step0 < 0)
         return fail(LBM_EINVAL, "negative step counts");
+    if (o->use_graph < 0 || o->use_graph > 2)
+        return fail(LBM_EINVAL, "use_graph must be 0, 1 or 2");
     for (int l = 0; l < n; ++l) {
         int32_t rc = validate_params(&ps[l], ps[l].nx);
         if (rc)
@@ -665,13 +723,14 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     }
     BatchTile *d_tiles1 = d_tiles, *d_tiles2 = d_tiles + Ly.n_tiles1;
     hipError_t up_err = hipSuccess;
+    // host copies of the uploaded lists stay alive until the stream is
+    // synchronised at the end of this call
+    std::vector<std::vector<BatchTile>> host_lists;
     auto upload = [&](int k) -> std::pair<BatchTile *, int64_t> {
-        const std::vector<BatchTile> v = build_tiles(ps, n, kShapes[k].tx, kShapes[k].ty);
+        host_lists.push_back(build_tiles(ps, n, kShapes[k].tx, kShapes[k].ty));
+        const std::vector<BatchTile> &v = host_lists.back();
         BatchTile *d = k < kNumSingle ? d_tiles1 : d_tiles2;
         up_err = hipMemcpyAsync(d, v.data(), sizeof(BatchTile) * v.size(), hipMemcpyHostToDevice, s);
-        // the host vector dies here: wait for the copy
-        if (up_err == hipSuccess)
-            up_err = hipStreamSynchronize(s);
         return {up_err == hipSuccess ? d : nullptr, (int64_t)v.size()};
     };
     if (shape < 0) {
@@ -784,7 +843,19 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     const int64_t reps = o->n_steps == 0 ? 0 : (period - 1) / chunk;
     const int64_t tail = o->n_steps == 0 ? 0 : period - reps * chunk;
     const int64_t n_periods = o->n_steps == 0 ? 1 : o->n_steps / period;
-    auto capture = [&](int64_t steps, bool sample, hipGraphExec_t *ge) -> hipError_t {
+    auto capture = [&](int64_t steps, bool sample, GraphPtr *ge) -> hipError_t {
+        // an instantiated graph bakes in the launch shapes and the workspace
+        // addresses it reads (descriptors and tile lists are uploaded again by
+        // every call before it runs), so it is kept and replayed by later
+        // calls with the same key
+        int dev = 0;
+        hipGetDevice(&dev);
+        const GraphKey key{dev, (const void *)main_list.first, (const void *)one_list.first, (const void *)d_lat,
+                           (const void *)d_ctrl, (const void *)d_mt, (const void *)d_part, (const void *)d_colpart,
+                           (const void *)d_colmean, (const void *)d_results, ps[0].model, flags, shape,
+                           main_list.second, one_list.second, nmt, (int64_t)n, n_samples, steps, sample ? 1 : 0};
+        if ((*ge = graph_cache_get(key)))
+            return hipSuccess;
         hipGraph_t g;
         hipStream_t cap;
         hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
@@ -801,27 +872,35 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
             return ce;
         if (ee != hipSuccess)
             return ee;
-        e = hipGraphInstantiate(ge, g, nullptr, nullptr, 0);
+        auto holder = std::make_shared<GraphExec>();
+        e = hipGraphInstantiate(&holder->exec, g, nullptr, nullptr, 0);
         hipGraphDestroy(g);
+        if (e == hipSuccess) {
+            *ge = holder;
+            graph_cache_put(key, holder);
+        }
         return e;
     };
     if (o->use_graph) {
-        hipGraphExec_t g_chunk = nullptr, g_tail = nullptr;
+        GraphPtr g_chunk, g_tail;
         hipError_t e = reps > 0 ? capture(chunk, false, &g_chunk) : hipSuccess;
         if (e == hipSuccess)
             e = capture(tail, true, &g_tail);
+        if (o->use_graph == 2) {  // prepare only: the graphs are cached, nothing runs
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(s);
+            if (e != hipSuccess)
+                return hip_fail(e, "lbm_sweep_batch graph");
+            return LBM_OK;
+        }
         for (int64_t p = 0; p < n_periods && e == hipSuccess; ++p) {
             for (int64_t r = 0; r < reps && e == hipSuccess; ++r)
-                e = hipGraphLaunch(g_chunk, s);
+                e = hipGraphLaunch(g_chunk->exec, s);
             if (e == hipSuccess)
-                e = hipGraphLaunch(g_tail, s);
+                e = hipGraphLaunch(g_tail->exec, s);
         }
         if (e == hipSuccess)
             e = hipStreamSynchronize(s);
-        if (g_chunk)
-            hipGraphExecDestroy(g_chunk);
-        if (g_tail)
-            hipGraphExecDestroy(g_tail);
         if (e != hipSuccess)
             return hip_fail(e, "lbm_sweep_batch graph");
     } else {

@@ -176,7 +176,7 @@ class FieldSampler:
             self.batch.set_state(l, f)
 
     def advance(self, steps):
-        self.batch.run(steps, use_graph=1 if steps >= 200 else 0)
+        self.batch.run(steps)
 
     def coarse_fields(self, batch, out, stream):
         coarse_fields(batch, self.params[0], self.c, self.act, out, stream)
@@ -193,7 +193,7 @@ class FieldSampler:
                       stream)
         self.judge.current = [0] * n
         self.judge.step_index = self.batch.step_index
-        self.judge.run(self.k, use_graph=0)
+        self.judge.run(self.k)
         out = torch.empty_like(X)
         self.coarse_fields(self.judge, out, stream)
         return out
@@ -297,7 +297,8 @@ def sweep(net, sampler, jumps, check_every, tol, stream):
         Y = predict(net, X, stream)
         if fallen.any():
             fb = np.nonzero(fallen)[0]
-            lbm.run(sampler.k, tile_rows=1, use_graph=0, subset=fb)
+            # a fixed two-step tile: every new subset would otherwise be tuned
+            lbm.run(sampler.k, tile_rows=16, subset=fb)
             F = torch.empty_like(X)
             sampler.coarse_fields(lbm, F, stream)
             idx = torch.from_numpy(fb).to(sampler.device)

@@ -85,12 +85,12 @@ def test_null_context_is_a_state_error():
     assert L._lib.lbm_current_buffer(None) == L.LBM_ESTATE
 
 
-def _sweep(L, plist, n_steps=10, every=0, ws_bytes=None):
+def _sweep(L, plist, n_steps=10, every=0, ws_bytes=None, tile_rows=0, use_graph=1):
     n = len(plist)
     arr = (L.lbm_params * n)(*plist)
     bufs = (ctypes.c_void_p * (2 * n))(*[ctypes.c_void_p(16 * (k + 1)) for k in range(2 * n)])
     need = L._lib.lbm_sweep_workspace_bytes(arr, n, max(1, n_steps // every if every else 1))
-    opts = L.lbm_sweep_opts(n_steps, every, 0, 0, 1)
+    opts = L.lbm_sweep_opts(n_steps, every, 0, tile_rows, use_graph)
     out = (L.lbm_obs * (n * 4))()
     return L._lib.lbm_sweep_batch(arr, n, ctypes.byref(opts), bufs, ctypes.c_void_p(64),
                                   need if ws_bytes is None else ws_bytes, None, out)
@@ -108,6 +108,8 @@ def test_sweep_batch_rejects_invalid_batches():
     assert _sweep(L, [good], n_steps=10, every=3) == L.LBM_EINVAL
     assert _sweep(L, [good], ws_bytes=100) == L.LBM_EINVAL
     assert _sweep(L, [L.make_params(128, 127, L.LBM_CIL)]) == L.LBM_EINVAL
+    assert _sweep(L, [good], use_graph=3) == L.LBM_EINVAL and "use_graph" in L.lbm_last_error()
+    assert _sweep(L, [good], use_graph=-1) == L.LBM_EINVAL
     assert L._lib.lbm_sweep_workspace_bytes(None, 1, 1) == 0
 
 

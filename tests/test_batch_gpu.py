@@ -149,3 +149,25 @@ def test_batch_small_lattices_and_long_period(L, tile_rows):
         assert out[l][0]["step"] == steps
         assert abs(out[l][0]["M"] - samples[l][0]["M"]) <= 1e-12 * samples[l][0]["M"]
 
+
+
+def test_batch_repeated_calls_replay_cached_graphs(L):
+    """Later calls with the same batch and step counts replay the graphs the
+    first call instantiated (the descriptors are uploaded again each time);
+    the states must still follow the single-lattice runs bit for bit, also
+    when a call with other counts comes in between."""
+    cfgs = small_batch()
+    states = init_states(L, cfgs)
+    finals, _ = single_runs(L, cfgs, states, 3 * 37 + 20)
+    b = L.Batch([_gparams(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    assert b.run(37, tile_rows=16, use_graph=2) == []   # prepares only: the state stays
+    for l in range(len(cfgs)):
+        assert torch.equal(b.state(l), states[l])
+    b.run(37, tile_rows=16)
+    b.run(20, sample_every=10, tile_rows=16)
+    b.run(37, tile_rows=16)
+    b.run(37, tile_rows=16)
+    for l in range(len(cfgs)):
+        assert torch.equal(b.state(l), finals[l]), l
