@@ -15,6 +15,8 @@
 // use fixed partitions and orders, so results are deterministic.
 #include <math.h>
 
+#include <algorithm>
+
 #include "../../include/lbm_cnn.h"
 #include "internal.h"
 
@@ -29,74 +31,94 @@ constexpr int kTile = 16;
 // w[o,c,8-k] x[n,o,..], i.e. the same sum with transposed, flipped weights.
 // Epilogue in order: bias, ReLU, + resid[n, o] (first co channels of a
 // tensor with resid_c channels), * (mask[n, o] > 0).
+//
+// One block = one sample x a 16 x 16 pixel tile x OG of the co_n output
+// channels (blockIdx.z = sample * groups + group), so small batches of small
+// fields still give several blocks per CU; the input tile with its halo is
+// staged in LDS kChunk channels at a time.  Every output sums over c and k in
+// increasing order, as the definition reads.
 // ---------------------------------------------------------------------------
-template <int CO, int TR>
+constexpr int kChunk = 8;
+
+template <int OG, int TR>
 __global__ __launch_bounds__(256) void k_conv3x3(const float *__restrict__ x, int ci_n, const float *__restrict__ w,
-                                                 const float *__restrict__ bias, const float *__restrict__ resid,
-                                                 int resid_c, const float *__restrict__ mask, int relu,
-                                                 float *__restrict__ y, int H, int W)
+                                                 int co_n, const float *__restrict__ bias,
+                                                 const float *__restrict__ resid, int resid_c,
+                                                 const float *__restrict__ mask, int relu, float *__restrict__ y,
+                                                 int H, int W)
 {
-    extern __shared__ float s_in[];  // [ci_n][18][18]
     constexpr int L = kTile + 2;
-    const int n = blockIdx.z;
+    __shared__ float s_in[kChunk * L * L];
+    const int groups = co_n / OG;
+    const int n = blockIdx.z / groups, o0 = (blockIdx.z - n * groups) * OG;
     const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
     const int tid = threadIdx.x;
     const size_t HW = (size_t)H * W;
     const float *xn = x + (size_t)n * ci_n * HW;
-    for (int e = tid; e < ci_n * L * L; e += 256) {
-        const int c = e / (L * L), r = e - c * (L * L), li = r / L, lj = r - li * L;
-        int gi = i0 + li - 1, gj = j0 + lj - 1;
-        gi = gi < 0 ? gi + H : (gi >= H ? gi - H : gi);
-        gj = gj < 0 ? gj + W : (gj >= W ? gj - W : gj);
-        s_in[e] = xn[(size_t)c * HW + (size_t)gi * W + gj];
-    }
-    __syncthreads();
     const int pi = tid >> 4, pj = tid & 15;
     const int i = i0 + pi, j = j0 + pj;
-    if (i >= H || j >= W)
-        return;
-    float acc[CO];
+    float acc[OG];
 #pragma unroll
-    for (int o = 0; o < CO; ++o)
-        acc[o] = bias ? bias[o] : 0.0f;
-    for (int c = 0; c < ci_n; ++c) {
-        const float *t = s_in + c * L * L + pi * L + pj;
-        float v[9];
+    for (int o = 0; o < OG; ++o)
+        acc[o] = bias ? bias[o0 + o] : 0.0f;
+    for (int c0 = 0; c0 < ci_n; c0 += kChunk) {
+        const int cc = min(kChunk, ci_n - c0);
+        __syncthreads();  // the previous chunk is no longer read
+        for (int e = tid; e < cc * L * L; e += 256) {
+            const int c = e / (L * L), r = e - c * (L * L), li = r / L, lj = r - li * L;
+            int gi = i0 + li - 1, gj = j0 + lj - 1;
+            gi = gi < 0 ? gi + H : (gi >= H ? gi - H : gi);
+            gj = gj < 0 ? gj + W : (gj >= W ? gj - W : gj);
+            s_in[e] = xn[(size_t)(c0 + c) * HW + (size_t)gi * W + gj];
+        }
+        __syncthreads();
+        for (int c = 0; c < cc; ++c) {
+            const float *t = s_in + c * L * L + pi * L + pj;
+            float v[9];
 #pragma unroll
-        for (int ky = 0; ky < 3; ++ky)
+            for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
-            for (int kx = 0; kx < 3; ++kx)
-                v[ky * 3 + kx] = t[ky * L + kx];
+                for (int kx = 0; kx < 3; ++kx)
+                    v[ky * 3 + kx] = t[ky * L + kx];
+            const int cg = c0 + c;
 #pragma unroll
-        for (int o = 0; o < CO; ++o) {
-            float s = acc[o];
+            for (int o = 0; o < OG; ++o) {
+                float sum = acc[o];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const float wk = TR ? w[((size_t)c * CO + o) * 9 + (8 - k)] : w[((size_t)o * ci_n + c) * 9 + k];
-                s = fmaf(wk, v[k], s);
+                for (int k = 0; k < 9; ++k) {
+                    const float wk = TR ? w[((size_t)cg * co_n + o0 + o) * 9 + (8 - k)]
+                                        : w[((size_t)(o0 + o) * ci_n + cg) * 9 + k];
+                    sum = fmaf(wk, v[k], sum);
+                }
+                acc[o] = sum;
             }
-            acc[o] = s;
         }
     }
+    if (i >= H || j >= W)
+        return;
     const size_t pix = (size_t)i * W + j;
 #pragma unroll
-    for (int o = 0; o < CO; ++o) {
+    for (int o = 0; o < OG; ++o) {
+        const int og = o0 + o;
         float r = acc[o];
         if (relu)
             r = fmaxf(r, 0.0f);
         if (resid)
-            r += resid[((size_t)n * resid_c + o) * HW + pix];
+            r += resid[((size_t)n * resid_c + og) * HW + pix];
         if (mask)
-            r = mask[((size_t)n * CO + o) * HW + pix] > 0.0f ? r : 0.0f;
-        y[((size_t)n * CO + o) * HW + pix] = r;
+            r = mask[((size_t)n * co_n + og) * HW + pix] > 0.0f ? r : 0.0f;
+        y[((size_t)n * co_n + og) * HW + pix] = r;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradient: dw[o,c,k] = sum_{n,i,j} dy[n,o,i,j] x[n,c,i+ky-1,j+kx-1].
-// One block per (o, c); the block walks every sample's 16 x 16 tiles with
-// the x tile (plus halo) and the dy tile in LDS; per-thread float sums, then
-// a fixed-order float64 block reduction.
+// Weight and bias gradients: dw[o,c,k] = sum_{n,i,j} dy[n,o,i,j]
+// x[n,c,i+ky-1,j+kx-1], db[o] = sum dy[n,o,i,j].  One block per (sample,
+// 16 x 16 tile) writes its partial sums (float, in pixel order) to
+// part[block][co_n ci_n 9 + co_n]; k_grad_reduce adds the blocks in order in
+// float64.  Per chunk of kChunk input channels, thread t takes the pair
+// (OG output channels, one input channel) t mod pairs and the pixel group
+// t / pairs; the pixel groups of a pair are then added in order through LDS.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double cwave_sum(double v)
 {
@@ -106,77 +128,109 @@ __device__ __forceinline__ double cwave_sum(double v)
     return v;
 }
 
+template <int OG>
 __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const float *__restrict__ dy, int co_n,
-                                                       const float *__restrict__ x, int ci_n, int N, int H, int W,
-                                                       float *__restrict__ dw)
+                                                       const float *__restrict__ x, int ci_n, int H, int W,
+                                                       float *__restrict__ part)
 {
     constexpr int L = kTile + 2;
-    __shared__ float s_x[L * L];
-    __shared__ float s_d[kTile * kTile];
-    __shared__ double s_red[4][9];
-    const int o = blockIdx.x / ci_n, c = blockIdx.x - o * ci_n;
-    const int tid = threadIdx.x, pi = tid >> 4, pj = tid & 15;
+    __shared__ float s_x[kChunk * L * L];      // x tile, kChunk input channels
+    __shared__ float s_d[32 * kTile * kTile];  // dy tile, all (<= 32) output channels
+    __shared__ float s_red[256 * 9];           // pixel-group partials
+    const int tiles_j = (W + kTile - 1) / kTile, tiles_i = (H + kTile - 1) / kTile;
+    const int n = blockIdx.x / (tiles_i * tiles_j), tt = blockIdx.x - n * (tiles_i * tiles_j);
+    const int ti = tt / tiles_j;
+    const int i0 = ti * kTile, j0 = (tt - ti * tiles_j) * kTile;
+    const int tid = threadIdx.x;
     const size_t HW = (size_t)H * W;
-    const int tiles_i = (H + kTile - 1) / kTile, tiles_j = (W + kTile - 1) / kTile;
-    float acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int n = 0; n < N; ++n) {
-        const float *xn = x + ((size_t)n * ci_n + c) * HW;
-        const float *dn = dy + ((size_t)n * co_n + o) * HW;
-        for (int ti = 0; ti < tiles_i; ++ti)
-            for (int tj = 0; tj < tiles_j; ++tj) {
-                const int i0 = ti * kTile, j0 = tj * kTile;
-                __syncthreads();
-                for (int e = tid; e < L * L; e += 256) {
-                    const int li = e / L, lj = e - li * L;
-                    int gi = i0 + li - 1, gj = j0 + lj - 1;
-                    gi = gi < 0 ? gi + H : (gi >= H ? gi - H : gi);
-                    gj = gj < 0 ? gj + W : (gj >= W ? gj - W : gj);
-                    s_x[e] = xn[(size_t)gi * W + gj];
-                }
-                {
-                    const int gi = i0 + pi, gj = j0 + pj;
-                    s_d[tid] = (gi < H && gj < W) ? dn[(size_t)gi * W + gj] : 0.0f;
-                }
-                __syncthreads();
-                const float d = s_d[tid];
+    const int pairs = (co_n / OG) * kChunk;  // divides 256 (checked on the host)
+    const int pg = 256 / pairs;              // pixel groups
+    const int pair = tid % pairs, grp = tid / pairs;
+    const int og = pair / kChunk, cl = pair - og * kChunk;
+    const int nw = co_n * ci_n * 9;
+    float *out = part + (size_t)blockIdx.x * (nw + co_n);
+    // dy tile (zero outside the field)
+    for (int e = tid; e < co_n * kTile * kTile; e += 256) {
+        const int o = e / (kTile * kTile), r = e - o * (kTile * kTile), li = r / kTile, lj = r - li * kTile;
+        const int gi = i0 + li, gj = j0 + lj;
+        s_d[e] = (gi < H && gj < W) ? dy[((size_t)n * co_n + o) * HW + (size_t)gi * W + gj] : 0.0f;
+    }
+    for (int c0 = 0; c0 < ci_n; c0 += kChunk) {
+        __syncthreads();
+        for (int e = tid; e < kChunk * L * L; e += 256) {
+            const int c = e / (L * L), r = e - c * (L * L), li = r / L, lj = r - li * L;
+            int gi = i0 + li - 1, gj = j0 + lj - 1;
+            gi = gi < 0 ? gi + H : (gi >= H ? gi - H : gi);
+            gj = gj < 0 ? gj + W : (gj >= W ? gj - W : gj);
+            s_x[e] = c0 + c < ci_n ? x[((size_t)n * ci_n + c0 + c) * HW + (size_t)gi * W + gj] : 0.0f;
+        }
+        __syncthreads();
+        float acc[OG][9];
 #pragma unroll
-                for (int ky = 0; ky < 3; ++ky)
+        for (int o = 0; o < OG; ++o)
 #pragma unroll
-                    for (int kx = 0; kx < 3; ++kx)
-                        acc[ky * 3 + kx] = fmaf(d, s_x[(pi + ky) * L + pj + kx], acc[ky * 3 + kx]);
+            for (int k = 0; k < 9; ++k)
+                acc[o][k] = 0.0f;
+        for (int p = grp; p < kTile * kTile; p += pg) {
+            const int pi = p >> 4, pj = p & 15;
+            const float *t = s_x + cl * L * L + pi * L + pj;
+            float v[9];
+#pragma unroll
+            for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx)
+                    v[ky * 3 + kx] = t[ky * L + kx];
+#pragma unroll
+            for (int o = 0; o < OG; ++o) {
+                const float d = s_d[(og * OG + o) * kTile * kTile + p];
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    acc[o][k] = fmaf(d, v[k], acc[o][k]);
             }
-    }
-    const int lane = tid & 63, wv = tid >> 6;
+        }
+        // the pixel groups of one pair, added in group order
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const double s = cwave_sum((double)acc[k]);
-        if (lane == 0)
-            s_red[wv][k] = s;
+        for (int o = 0; o < OG; ++o) {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                s_red[tid * 9 + k] = acc[o][k];
+            __syncthreads();
+            if (tid < pairs && c0 + cl < ci_n) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    float sum = 0.0f;
+                    for (int g = 0; g < pg; ++g)
+                        sum += s_red[(g * pairs + tid) * 9 + k];
+                    out[((size_t)(og * OG + o) * ci_n + c0 + cl) * 9 + k] = sum;
+                }
+            }
+        }
     }
-    __syncthreads();
-    if (tid < 9)
-        dw[((size_t)o * ci_n + c) * 9 + tid] =
-            (float)(((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid]);
+    // bias: thread o adds its dy tile in pixel order
+    if (tid < co_n) {
+        float sum = 0.0f;
+        for (int p = 0; p < kTile * kTile; ++p)
+            sum += s_d[tid * kTile * kTile + p];
+        out[nw + tid] = sum;
+    }
 }
 
-// db[o] = sum_{n,i,j} dy[n,o,i,j]; one block per o, fixed order.
-__global__ __launch_bounds__(256) void k_bias_grad(const float *__restrict__ dy, int co_n, int N, int HW,
-                                                   float *__restrict__ db)
+// g[e] = sum over blocks b, in order, of part[b][e] (float64); e < nw goes to
+// the weight gradient, e >= nw to the bias gradient.
+__global__ __launch_bounds__(256) void k_grad_reduce(const float *__restrict__ part, int nblocks, int nw, int nb,
+                                                     float *__restrict__ gw, float *__restrict__ gb)
 {
-    __shared__ double s_red[4];
-    const int o = blockIdx.x;
-    double acc = 0.0;
-    for (int n = 0; n < N; ++n) {
-        const float *d = dy + ((size_t)n * co_n + o) * HW;
-        for (int p = threadIdx.x; p < HW; p += 256)
-            acc += (double)d[p];
-    }
-    acc = cwave_sum(acc);
-    if ((threadIdx.x & 63) == 0)
-        s_red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0)
-        db[o] = (float)(((s_red[0] + s_red[1]) + s_red[2]) + s_red[3]);
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nw + nb)
+        return;
+    double sum = 0.0;
+    for (int b = 0; b < nblocks; ++b)
+        sum += (double)part[(size_t)b * (nw + nb) + e];
+    if (e < nw)
+        gw[e] = (float)sum;
+    else
+        gb[e - nw] = (float)sum;
 }
 
 // Mean squared error: dy = 2 (y - t) / count, per-block float64 partials of
@@ -200,14 +254,21 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ y, const 
         part[blockIdx.x] = ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
 }
 
-__global__ void k_mse_final(const double *__restrict__ part, int nparts, int64_t count, float *__restrict__ loss)
+// One block of 256: thread t adds partials t, t + 256, ... in order, then a
+// fixed tree over the threads.
+__global__ __launch_bounds__(256) void k_mse_final(const double *__restrict__ part, int nparts, int64_t count,
+                                                   float *__restrict__ loss)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int b = 0; b < nparts; ++b)
-            s += part[b];
-        *loss = (float)(s / (double)count);
-    }
+    __shared__ double s_red[4];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += 256)
+        s += part[b];
+    s = cwave_sum(s);
+    if ((threadIdx.x & 63) == 0)
+        s_red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        *loss = (float)((((s_red[0] + s_red[1]) + s_red[2]) + s_red[3]) / (double)count);
 }
 
 // bf16 weights -> float32 working copy.
@@ -447,19 +508,37 @@ static bool shape_ok(const lbm_cnn_shape *s)
            s->cin <= 32 && (int64_t)s->h * s->w <= (1 << 26) && s->n <= 65535;
 }
 
-template <int CO, int TR>
-static hipError_t conv(const float *x, int ci, const float *w, const float *b, const float *resid, int resid_c,
-                       const float *mask, int relu, float *y, int N, int H, int W, hipStream_t s)
+// co output channels in groups of OG (co % OG == 0)
+template <int OG, int TR>
+static hipError_t conv(const float *x, int ci, const float *w, int co, const float *b, const float *resid,
+                       int resid_c, const float *mask, int relu, float *y, int N, int H, int W, hipStream_t s)
 {
-    dim3 grd((W + kTile - 1) / kTile, (H + kTile - 1) / kTile, N);
-    const size_t lds = (size_t)ci * (kTile + 2) * (kTile + 2) * sizeof(float);
-    hipLaunchKernelGGL((k_conv3x3<CO, TR>), grd, dim3(256), lds, s, x, ci, w, b, resid, resid_c, mask, relu, y, H, W);
+    dim3 grd((W + kTile - 1) / kTile, (H + kTile - 1) / kTile, N * (co / OG));
+    hipLaunchKernelGGL((k_conv3x3<OG, TR>), grd, dim3(256), 0, s, x, ci, w, co, b, resid, resid_c, mask, relu, y, H,
+                       W);
+    return hipGetLastError();
+}
+
+static int conv_tiles(int H, int W) { return ((H + kTile - 1) / kTile) * ((W + kTile - 1) / kTile); }
+
+// Weight and bias gradients of one layer (co output, ci input channels):
+// per-tile partials, then their ordered sum.
+template <int OG>
+static hipError_t wgrad(const float *dy, int co, const float *x, int ci, int N, int H, int W, float *part, float *gw,
+                        float *gb, hipStream_t s)
+{
+    const int blocks = N * conv_tiles(H, W);
+    hipLaunchKernelGGL((k_conv3x3_wgrad<OG>), dim3(blocks), dim3(256), 0, s, dy, co, x, ci, H, W, part);
+    const int total = co * ci * 9 + co;
+    hipLaunchKernelGGL(k_grad_reduce, dim3((total + 255) / 256), dim3(256), 0, s, part, blocks, co * ci * 9, co, gw,
+                       gb);
     return hipGetLastError();
 }
 
 struct CnnWs {
     float *w[3];     // widened weights
     double *part;    // loss partials
+    float *gpart;    // per-tile gradient partials
     float *dy;       // dL/dy [n][cout][hw]
     float *dz2;      // [n][hidden][hw]
     float *dz1;      // [n][hidden][hw]
@@ -484,6 +563,9 @@ static CnnWs cnn_layout(const lbm_cnn_shape *s, char *base)
     }
     o[3] = off;
     off = align256(off + kMseBlocks * sizeof(double));
+    const size_t gpart = off;  // the largest layer: hidden x hidden weights
+    off = align256(off + (size_t)s->n * conv_tiles(s->h, s->w) *
+                             (size_t)(s->hidden * std::max(s->hidden, s->cin) * 9 + s->hidden) * sizeof(float));
     o[4] = off;
     off = align256(off + (size_t)s->n * s->cout * hw * sizeof(float));
     o[5] = off;
@@ -495,6 +577,7 @@ static CnnWs cnn_layout(const lbm_cnn_shape *s, char *base)
         for (int k = 0; k < 3; ++k)
             L.w[k] = (float *)(base + o[k]);
         L.part = (double *)(base + o[3]);
+        L.gpart = (float *)(base + gpart);
         L.dy = (float *)(base + o[4]);
         L.dz2 = (float *)(base + o[5]);
         L.dz1 = (float *)(base + o[6]);
@@ -539,9 +622,9 @@ int32_t lbm_cnn_forward(const lbm_cnn_shape *s, const lbm_cnn_params *p, const f
         return fail(LBM_EINVAL, "workspace smaller than lbm_cnn_workspace_bytes()");
     hipStream_t st = (hipStream_t)stream;
     LBM_HIP_TRY(widen(s, p, L, st));
-    LBM_HIP_TRY((conv<32, 0>(x, s->cin, L.w[0], p->b[0], nullptr, 0, nullptr, 1, a1, s->n, s->h, s->w, st)));
-    LBM_HIP_TRY((conv<32, 0>(a1, 32, L.w[1], p->b[1], nullptr, 0, nullptr, 1, a2, s->n, s->h, s->w, st)));
-    LBM_HIP_TRY((conv<3, 0>(a2, 32, L.w[2], p->b[2], x, s->cin, nullptr, 0, y, s->n, s->h, s->w, st)));
+    LBM_HIP_TRY((conv<8, 0>(x, s->cin, L.w[0], 32, p->b[0], nullptr, 0, nullptr, 1, a1, s->n, s->h, s->w, st)));
+    LBM_HIP_TRY((conv<8, 0>(a1, 32, L.w[1], 32, p->b[1], nullptr, 0, nullptr, 1, a2, s->n, s->h, s->w, st)));
+    LBM_HIP_TRY((conv<3, 0>(a2, 32, L.w[2], 3, p->b[2], x, s->cin, nullptr, 0, y, s->n, s->h, s->w, st)));
     return LBM_OK;
 }
 
@@ -564,18 +647,15 @@ int32_t lbm_cnn_backward(const lbm_cnn_shape *s, const lbm_cnn_params *p, const 
     const int64_t hw = (int64_t)H * W, count = (int64_t)N * s->cout * hw;
     LBM_HIP_TRY(widen(s, p, L, st));
     hipLaunchKernelGGL(k_mse, dim3(kMseBlocks), dim3(256), 0, st, y, target, count, L.dy, L.part);
-    hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, st, L.part, kMseBlocks, count, loss);
+    hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(256), 0, st, L.part, kMseBlocks, count, loss);
     // layer 3: y = x[:cout] + conv(a2, w2) + b2
-    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(s->cout * 32), dim3(256), 0, st, L.dy, s->cout, a2, 32, N, H, W, g->w[2]);
-    hipLaunchKernelGGL(k_bias_grad, dim3(s->cout), dim3(256), 0, st, L.dy, s->cout, N, (int)hw, g->b[2]);
-    LBM_HIP_TRY((conv<32, 1>(L.dy, s->cout, L.w[2], nullptr, nullptr, 0, a2, 0, L.dz2, N, H, W, st)));
+    LBM_HIP_TRY(wgrad<3>(L.dy, s->cout, a2, 32, N, H, W, L.gpart, g->w[2], g->b[2], st));
+    LBM_HIP_TRY((conv<8, 1>(L.dy, s->cout, L.w[2], 32, nullptr, nullptr, 0, a2, 0, L.dz2, N, H, W, st)));
     // layer 2: a2 = relu(conv(a1, w1) + b1)
-    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(32 * 32), dim3(256), 0, st, L.dz2, 32, a1, 32, N, H, W, g->w[1]);
-    hipLaunchKernelGGL(k_bias_grad, dim3(32), dim3(256), 0, st, L.dz2, 32, N, (int)hw, g->b[1]);
-    LBM_HIP_TRY((conv<32, 1>(L.dz2, 32, L.w[1], nullptr, nullptr, 0, a1, 0, L.dz1, N, H, W, st)));
+    LBM_HIP_TRY(wgrad<4>(L.dz2, 32, a1, 32, N, H, W, L.gpart, g->w[1], g->b[1], st));
+    LBM_HIP_TRY((conv<8, 1>(L.dz2, 32, L.w[1], 32, nullptr, nullptr, 0, a1, 0, L.dz1, N, H, W, st)));
     // layer 1: a1 = relu(conv(x, w0) + b0)
-    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(32 * s->cin), dim3(256), 0, st, L.dz1, 32, x, s->cin, N, H, W, g->w[0]);
-    hipLaunchKernelGGL(k_bias_grad, dim3(32), dim3(256), 0, st, L.dz1, 32, N, (int)hw, g->b[0]);
+    LBM_HIP_TRY(wgrad<4>(L.dz1, 32, x, s->cin, N, H, W, L.gpart, g->w[0], g->b[0], st));
     LBM_HIP_TRY(hipGetLastError());
     return LBM_OK;
 }
