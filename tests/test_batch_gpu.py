@@ -14,7 +14,7 @@ import synth_inputs as SI
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-from test_parity_gpu import _cfg, _oparams, _gparams, rel_err  # noqa: E402
+from test_parity_gpu import _cfg, _oparams, _gparams, _self_sensitivity, rel_err  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -171,3 +171,38 @@ def test_batch_repeated_calls_replay_cached_graphs(L):
     b.run(37, tile_rows=16)
     for l in range(len(cfgs)):
         assert torch.equal(b.state(l), finals[l]), l
+
+
+def test_full_size_two_step_batch_matches_oracle(L, orc):
+    """The benchmark's workload and launch configuration (five 1024 x 1024
+    CIL lattices, 64 x 16 two-step tiles, graphs): four steps (two two-step
+    launches) against the oracle on the whole of one lattice, and the other
+    lattices against single-lattice runs bit for bit."""
+    cfgs = [SI.cil_1024(r, l) for l, r in enumerate(SI.CIL_DENSITIES)]
+    inits = [c.pop("init") for c in cfgs]
+    lats = [L.Lattice(_gparams(L, c), init=L.make_init(**ini)) for c, ini in zip(cfgs, inits)]
+    torch.cuda.synchronize()
+    states = [lat.state.clone() for lat in lats]
+    for lat in lats:
+        lat.step(4)
+    torch.cuda.synchronize()
+    singles = [lat.state.clone() for lat in lats]
+    for lat in lats:
+        lat.close()
+    b = L.Batch([_gparams(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    b.run(4, tile_rows=16)
+    for l in range(len(cfgs)):
+        assert torch.equal(b.state(l), singles[l]), l
+    l = 2
+    po = _oparams(orc, cfgs[l])
+    f0 = states[l].double().cpu().numpy()
+    ref = orc.run(po, f0.copy(), 4)
+    got = b.state(l).double().cpu().numpy()
+    d = got - ref
+    assert np.sqrt((d * d).mean() / (ref * ref).mean()) < 1e-6
+    # chaotic start: the max-norm bound follows the oracle's own amplification
+    # of a 1e-7 perturbation over the same steps (as for the one-step path)
+    amp = _self_sensitivity(orc, po, f0, 4) / 1e-7
+    assert rel_err(got, ref) < 2e-6 * max(amp, 1.0)
