@@ -186,6 +186,10 @@ typedef struct lbm_sweep_opts {
                              recent) and replayed by later calls with the same batch,
                              workspace and step counts; 2: prepare only: tune and
                              capture those graphs, run nothing and leave out unwritten */
+    const double *drho;   /* NULL, or host array of n density changes: right after each
+                             sample, every population of lattice l gains drho[l] / 7
+                             (the density ramp of the paper's protocol, appendix
+                             "Simulation procedure for results"); finite values only */
 } lbm_sweep_opts;
 
 /* Workspace bytes lbm_sweep_batch needs for these n lattices and n_samples

@@ -226,3 +226,10 @@ def lift(p, coarse, c):
             uy = coarse[2, cy, cx] / r if r > 0 else 0.0
             f[:, cy * c:(cy + 1) * c, cx * c:(cx + 1) * c] = xi(r, ux, uy)[:, None, None]
     return f
+
+
+def add_density(f, drho):
+    """The density change of the paper's protocol (appendix "Simulation
+    procedure for results"): drho / 7 added to every population of every site,
+    which raises the mean density by drho."""
+    return np.asarray(f, dtype=np.float64) + drho / 7.0

@@ -11,6 +11,8 @@ import ctypes
 import math
 import os
 
+import numpy as np
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
@@ -45,7 +47,8 @@ class lbm_obs(ctypes.Structure):
 
 class lbm_sweep_opts(ctypes.Structure):
     _fields_ = [("n_steps", ctypes.c_int64), ("sample_every", ctypes.c_int64), ("step0", ctypes.c_int64),
-                ("tile_rows", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("tile_rows", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("drho", ctypes.POINTER(ctypes.c_double))]
 
 
 class lbm_cnn_shape(ctypes.Structure):
@@ -262,11 +265,13 @@ class Batch:
         self.buffers[2 * l].copy_(f)
         self.current[l] = 0
 
-    def run(self, n_steps, sample_every=0, tile_rows=0, use_graph=1, stream=None, subset=None):
+    def run(self, n_steps, sample_every=0, tile_rows=0, use_graph=1, stream=None, subset=None, drho=None):
         """Advance every lattice (or only the lattices listed in subset) by
         n_steps; returns a list (per advanced lattice) of sample dicts.
         use_graph=2 only prepares the launch plan for such a call (tuning,
-        captured graphs) and advances nothing."""
+        captured graphs) and advances nothing.  drho (a number, or one per
+        advanced lattice): right after each sample every population gains
+        drho / 7, the density ramp of the paper's protocol."""
         import torch
         idx = list(range(self.n)) if subset is None else [int(i) for i in subset]
         m = len(idx)
@@ -288,6 +293,12 @@ class Batch:
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.buffers[0].device)
         out = (lbm_obs * (m * n_samples))()
         opts = lbm_sweep_opts(int(n_steps), int(sample_every), int(self.step_index), int(tile_rows), int(use_graph))
+        if drho is not None:
+            vals = [float(drho)] * m if np.isscalar(drho) else [float(v) for v in drho]
+            if len(vals) != m:
+                raise ValueError("drho needs one value per advanced lattice")
+            dr = (ctypes.c_double * m)(*vals)
+            opts.drho = dr
         st = stream if stream is not None else torch.cuda.current_stream()
         lbm_sweep_batch(params, m, opts, bufs, self._ws.data_ptr(), need, st.cuda_stream, out)
         if use_graph == 2:  # prepared the launch plan only; no step ran

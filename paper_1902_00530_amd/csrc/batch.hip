@@ -55,6 +55,7 @@ struct LatDesc {
     int32_t nrb;        // moments row blocks
     int64_t col_off;    // offset of this lattice's column partials
     int64_t cm_off;     // offset of this lattice's column means
+    float add;          // added to every population after each sample (drho / 7)
 };
 
 struct MomTile {
@@ -384,6 +385,33 @@ __global__ __launch_bounds__(256) void k_batch_final(const LatDesc *__restrict__
     }
 }
 
+// The density change of the paper's protocol (appendix "Simulation procedure
+// for results"): every population of lattice l gains drho_l / 7, in the
+// buffer that holds the state after this period's steps; per moments tile.
+__global__ __launch_bounds__(256) void k_batch_add_density(const MomTile *__restrict__ mt,
+                                                           const LatDesc *__restrict__ lats,
+                                                           const Ctrl *__restrict__ ctrl, int node)
+{
+    const MomTile m = mt[blockIdx.x];
+    const LatDesc &L = lats[m.lat];
+    const float add = L.add;
+    if (add == 0.0f)
+        return;
+    const StepArgs &a = L.a;
+    const int par = (int)((ctrl->k0 + node) & 1);
+    float *f = (float *)L.buf[par];
+    const int x = m.cx * 256 + threadIdx.x;
+    if (x >= a.nx)
+        return;
+    const int ye = min(m.cy * kMomRows + kMomRows, a.ny);
+    for (int y = m.cy * kMomRows; y < ye; ++y)
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+            float *p = f + (size_t)i * (size_t)a.plane + (size_t)y * (size_t)a.pitch + x;
+            *p = *p + add;
+        }
+}
+
 __global__ void k_batch_advance(Ctrl *ctrl, int64_t steps, int sampled)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -557,11 +585,11 @@ struct GraphKey {
     const void *tiles_main, *tiles_one, *lat, *ctrl, *mt, *part, *colpart, *colmean, *results;
     int model, flags, shape;
     int64_t ntiles_main, ntiles_one, nmt, n, n_samples, steps;
-    int sample;
+    int sample, add;
     auto tie() const
     {
         return std::tie(device, tiles_main, tiles_one, lat, ctrl, mt, part, colpart, colmean, results, model, flags,
-                        shape, ntiles_main, ntiles_one, nmt, n, n_samples, steps, sample);
+                        shape, ntiles_main, ntiles_one, nmt, n, n_samples, steps, sample, add);
     }
     bool operator==(const GraphKey &o) const { return tie() == o.tie(); }
 };
@@ -639,6 +667,10 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         return fail(LBM_EINVAL, "negative step counts");
     if (o->use_graph < 0 || o->use_graph > 2)
         return fail(LBM_EINVAL, "use_graph must be 0, 1 or 2");
+    if (o->drho)
+        for (int l = 0; l < n; ++l)
+            if (!isfinite(o->drho[l]))
+                return fail(LBM_EINVAL, "drho must be finite");
     for (int l = 0; l < n; ++l) {
         int32_t rc = validate_params(&ps[l], ps[l].nx);
         if (rc)
@@ -687,6 +719,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         D.buf[0] = bufs[2 * l];
         D.buf[1] = bufs[2 * l + 1];
         D.B = (float)ps[l].B;
+        D.add = o->drho ? (float)(o->drho[l] / 7.0) : 0.0f;
         const int cx = (ps[l].nx + 255) / 256, cy = (ps[l].ny + kMomRows - 1) / kMomRows;
         D.mt_begin = (int32_t)mt.size();
         D.mt_count = cx * cy;
@@ -831,6 +864,9 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
                                d_part, d_colpart);
             hipLaunchKernelGGL(k_batch_final, dim3((unsigned)n), dim3(256), 0, s, d_lat, d_ctrl, (int)steps, d_part,
                                d_colpart, d_colmean, d_results, (int)n_samples);
+            if (o->drho)
+                hipLaunchKernelGGL(k_batch_add_density, dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat, d_ctrl,
+                                   (int)steps);
         }
         hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, d_ctrl, steps, sample ? 1 : 0);
         return hipGetLastError();
@@ -853,7 +889,8 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         const GraphKey key{dev, (const void *)main_list.first, (const void *)one_list.first, (const void *)d_lat,
                            (const void *)d_ctrl, (const void *)d_mt, (const void *)d_part, (const void *)d_colpart,
                            (const void *)d_colmean, (const void *)d_results, ps[0].model, flags, shape,
-                           main_list.second, one_list.second, nmt, (int64_t)n, n_samples, steps, sample ? 1 : 0};
+                           main_list.second, one_list.second, nmt, (int64_t)n, n_samples, steps, sample ? 1 : 0,
+                           o->drho ? 1 : 0};
         if ((*ge = graph_cache_get(key)))
             return hipSuccess;
         hipGraph_t g;
