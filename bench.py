@@ -355,6 +355,41 @@ def main():
                      check_every=4)
         r.pop("network")
         var["surrogate_256_k50"] = r
+        # the paper's measurement protocol (180 x 60 lattices, its CIL
+        # parameters): the hysteresis ramps at A = 2 (50 increasing and 50
+        # decreasing runs) and a (rho, A) phase diagram (9 A values x 10
+        # repeats, rho 0.05 .. 0.40 every 1e4 steps), every run a lattice of
+        # one batch
+        from paper_1902_00530_amd import protocol as P
+        code = {"HD": "D", "HO": "O", "B": "b", "RB": "R", "none": "-"}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = P.hysteresis(repeats=50)
+        torch.cuda.synchronize()
+        th = time.perf_counter() - t0
+        snap = {}
+        for r in (0.105, 0.1425, 0.185, 0.2875):
+            k = min(range(len(h["up"]["rho"])), key=lambda i: abs(h["up"]["rho"][i] - r))
+            snap[str(r)] = h["up"]["regime"][k]
+        upd = 2 * 50 * 180 * 60 * h["up"]["steps"]
+        var["protocol_hysteresis_A2"] = {
+            "runs": 100, "steps_per_run": h["up"]["steps"], "seconds": round(th, 3),
+            "MLUPS": round(upd / th / 1e6, 1),
+            "regimes_up": "".join(code[x] for x in h["up"]["regime"]),
+            "regimes_down": "".join(code[x] for x in h["down"]["regime"]),
+            "rho_from_to_step": [0.09, 0.35, 0.0025],
+            "regime_at_paper_snapshot_densities": snap}
+        A_vals = [0.0, 0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pd = P.phase_diagram(A_vals)
+        torch.cuda.synchronize()
+        tpd = time.perf_counter() - t0
+        var["protocol_phase_diagram"] = {
+            "runs": pd["lattices"], "steps_per_run": pd["steps"], "seconds": round(tpd, 3),
+            "MLUPS": round(pd["lattices"] * 180 * 60 * pd["steps"] / tpd / 1e6, 1),
+            "rho_from_to_step": [0.05, 0.40, 0.01],
+            "regimes_by_A": {str(a): "".join(code[x] for x in row) for a, row in zip(A_vals, pd["regime"])}}
         line["variants"] = var
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_steps)

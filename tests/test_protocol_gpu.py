@@ -102,3 +102,26 @@ def test_protocol_drivers_at_reduced_size(L):
     assert len(pd["regime"]) == 3 and all(len(r) == 3 for r in pd["regime"])
     # B - A rho^2 <= 0 at A = 10 from rho = sqrt(0.03) ~ 0.173: the last two points have no motion
     assert pd["regime"][2][1:] == ["none", "none"]
+
+
+def test_hysteresis_regimes_at_the_papers_snapshot_densities(L):
+    """The paper's increasing-density protocol at A = 2 (50 runs, t_sample 1500
+    up to rho = 0.2 and 500 above, 1e4 relaxation steps): the regime of the
+    mean observables at the four densities of its snapshot table.  A smoke
+    check of the paper's reported behaviour (stochastic runs, not a pin)."""
+    import os
+    from paper_1902_00530_amd import protocol as P
+    here = os.path.dirname(os.path.abspath(__file__))
+    want = [l.split() for l in open(os.path.join(here, "golden", "cil_snapshot_regimes.txt"))
+            if l.strip() and l[0] != "#"]
+    b = P.cil_batch(50, 0.09, 2.0, [50000 + r for r in range(50)])
+    b.run(10000)
+    phases = P.ramp_schedule(0.09, 0.35, 0.0025, lambda r: 500 if r > 0.2 + 1e-12 else 1500)
+    samples = P.run_ramp(b, phases, 0.0025)
+    rho = np.array([o["rho_nominal"] for o in samples[0]])
+    for r, regime in want:
+        k = int(np.argmin(np.abs(rho - float(r))))
+        phi = np.mean([s[k]["phi"] for s in samples])
+        band = np.mean([s[k]["drho"] for s in samples])
+        zeta = np.mean([s[k]["zeta"] for s in samples])
+        assert P.classify_cil(phi, band, zeta, rho[k], 2.0, 0.3) == regime, (r, phi, band, zeta)
