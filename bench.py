@@ -57,6 +57,22 @@ def parse():
     return ap.parse_args()
 
 
+def cpu_mips64(steps=1000):
+    """FP64 oracle on the MIPS 64 x 64 configuration (1000 steps)."""
+    import oracle as O
+    import synth_inputs as SI
+    cfg = SI.mips_small()
+    ini = cfg.pop("init")
+    p = O.make_params(cfg["nx"], cfg["ny"], cfg["model"], cfg["tau"], cfg["sigma"], cfg["A"], cfg["B"], cfg["C"],
+                      cfg["rho_star"], cfg["u_max"], cfg["seed"])
+    f = O.initialise(p, **ini)
+    t0 = time.perf_counter()
+    O.run(p, f, steps)
+    dt = time.perf_counter() - t0
+    return {"MLUPS": round(cfg["nx"] * cfg["ny"] * steps / dt / 1e6, 3), "seconds": round(dt, 3), "cores": 1,
+            "sample": f"MIPS 64x64, {steps} steps, FP64, single thread"}
+
+
 def cpu_baseline(steps):
     """FP64 oracle, single thread, on one lattice of the workload."""
     import oracle as O
@@ -331,6 +347,18 @@ def main():
                 v["stated_error_vs_fp64"] = {"bf16_dev": "100-step rel Linf 1.9e-3, mass drift 2.1e-3 / 1e4 steps",
                                              "f16_dev": "100-step rel Linf 2.4e-4, mass drift 2.8e-5 / 1e4 steps"}[name]
             var["cil4096_" + name] = v
+        # MIPS (density-dependent motility, LDS density halo): the 64 x 64
+        # configuration (1000 steps) and the same parameters at 4096^2
+        mcfg = SI.mips_small()
+        msm, _ = time_single(L, torch, [mcfg], 1000, 20)
+        var["mips64_1000_steps"] = {"MLUPS": round(64 * 64 * 1000 / (msm / 1e3) / 1e6, 2),
+                                    "ms": round(msm, 3), "us_per_step": round(msm, 3),
+                                    "note": "4,096 sites: one launch per step, launch-bound"}
+        mbig = dict(mcfg, nx=4096, ny=4096)
+        msb, _ = time_single(L, torch, [mbig], 100, 10)
+        rm = roofline(0, 4096 * 4096, msb / 1e3 / 100, "k_step_mips<F32,noisy>")
+        var["mips4096_f32"] = {"MLUPS": round(4096 * 4096 * 100 / (msb / 1e3) / 1e6, 1), "GBps": rm["achieved"],
+                               "frac_hbm": rm["frac"], "avg_launch_us": rm["avg_launch_us"]}
         # FP32 at 4096^2 through the batched path (two steps per launch)
         ms2, _ = time_batch(L, torch, big, 200, 10)
         rows2 = time_batch.tile_rows
@@ -393,6 +421,8 @@ def main():
         line["variants"] = var
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+        if not args.quick:
+            line["cpu_baseline"]["mips64_1000_steps"] = cpu_mips64()
     print(json.dumps(line), flush=True)
 
 

@@ -109,18 +109,6 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchTile *__restrict_
         BufIO<float>::store(dst, own, i * plane, f[i]);
 }
 
-// Periodic image of a coordinate c in [-1, n + 64] on a ring of n sites.
-__device__ __forceinline__ int wrap_coord(int c, int n)
-{
-    if (c < 0)
-        c += n;
-    if (c >= n)
-        c -= n;
-    if (c >= n)  // rings shorter than the widened tile
-        c %= n;
-    return c;
-}
-
 // Steps t and t+1 on a 64 x TY tile (256 threads: wave w owns rows w, w+4,
 // ...).  mid holds step t+1 on the tile widened by one site, local
 // coordinates (lx, ly) = (x - x0 + 1, y - y0 + 1), planes of TY+2 rows of 66.

@@ -320,6 +320,18 @@ __device__ __forceinline__ PullSources32 pull_sources32(const StepArgs &a, int x
     return t;
 }
 
+// Periodic image of a coordinate c in [-1, n + 65] on a ring of n sites.
+__device__ __forceinline__ int wrap_coord(int c, int n)
+{
+    if (c < 0)
+        c += n;
+    if (c >= n)
+        c -= n;
+    if (c >= n)  // rings shorter than the widened tile
+        c %= n;
+    return c;
+}
+
 // Blocks are handed to the eight XCDs round-robin (block b runs on XCD
 // b mod 8).  Tiles are therefore taken in groups of 8 rows: with a grid of
 // (8 ntx, ceil(nty / 8)) blocks, block (bx, by) covers tile row 8 by + (bx & 7)
