@@ -109,17 +109,45 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchTile *__restrict_
         BufIO<float>::store(dst, own, i * plane, f[i]);
 }
 
-// Steps t and t+1 on a 64 x TY tile (256 threads: wave w owns rows w, w+4,
-// ...).  mid holds step t+1 on the tile widened by one site, local
-// coordinates (lx, ly) = (x - x0 + 1, y - y0 + 1), planes of TY+2 rows of 66.
-template <int M, int F, int TY>
-__global__ __launch_bounds__(256) void k_batch_step2(const BatchTile *__restrict__ tiles,
+// Step t+1 on the widened tile as the second step reads it, in local
+// coordinates (lx, ly) = (x - x0 + 1, y - y0 + 1): population 0 only at the
+// tile's own sites (TY rows of 64), 1 and 4 on the tile's rows (ly 1..TY),
+// 2 and 3 one row lower (ly 0..TY-1), 5 and 6 one row higher (ly 2..TY+1),
+// each TY rows of 66.  At TY = 16 that is 29,440 bytes, so five blocks fit
+// in a CU's 160 KB of LDS (all seven planes of all TY+2 rows would not).
+template <int TY>
+struct MidLayout {
+    static constexpr int W = 66;
+    static constexpr int kSize = TY * 64 + 6 * TY * W;
+    // plane base and first row of plane i
+    static constexpr int base(int i)
+    {
+        return i == 0 ? 0 : TY * 64 + (i == 1 ? 0 : i == 4 ? 1 : i == 2 ? 2 : i == 3 ? 3 : i == 5 ? 4 : 5) * TY * W;
+    }
+    static constexpr int row0(int i) { return i == 0 || i == 1 || i == 4 ? 1 : (i == 2 || i == 3 ? 0 : 2); }
+    __device__ static int at(int i, int lx, int ly)
+    {
+        return i == 0 ? (ly - 1) * 64 + (lx - 1) : base(i) + (ly - row0(i)) * W + lx;
+    }
+    // whether the second step reads population i of local site (lx, ly)
+    __device__ static bool kept(int i, int lx, int ly)
+    {
+        const int r = ly - row0(i);
+        return r >= 0 && r < TY && (i != 0 || (lx >= 1 && lx <= 64));
+    }
+};
+
+// Steps t and t+1 on a 64 x TY tile (NW waves: wave w owns rows w, w+NW,
+// ...); the first step's results go to LDS in the MidLayout above.
+template <int M, int F, int TY, int NW>
+__global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__restrict__ tiles,
                                                      const LatDesc *__restrict__ lats,
                                                      const Ctrl *__restrict__ ctrl, int step_off, int launch_off)
 {
+    using ML = MidLayout<TY>;
     constexpr int W = 66, H = TY + 2;
-    static_assert(TY % 4 == 0 && 2 * (TY + 2) <= 128, "rows per wave must split evenly; edges fit two waves");
-    __shared__ float mid[7 * H * W];
+    static_assert(NW % 2 == 0 && TY % NW == 0 && 2 * (TY + 2) <= 64 * (NW - 2), "rows per wave split evenly; edges fit");
+    __shared__ float mid[ML::kSize];
     const BatchTile tl = tiles[blockIdx.x];
     const LatDesc &L = lats[tl.lat];
     const StepArgs a = L.a;
@@ -142,10 +170,10 @@ __global__ __launch_bounds__(256) void k_batch_step2(const BatchTile *__restrict
     const bool interior = x0 >= 2 && x0 + 66 <= a.nx && y0 >= 2 && y0 + TY + 2 <= a.ny;
 
     // First step on the widened tile, from HBM into LDS.  Wave w takes rows
-    // w, w+4, ... of the H rows; waves 2 and 3 own one row fewer (H = 2 mod 4)
-    // and take the two edge columns (2H sites) in that slot instead.  All of
-    // a wave's loads are issued before any of its sites is computed.
-    constexpr int NR = (H + 3) / 4;
+    // w, w+NW, ... of the H rows; waves 2 and up own one row fewer (H = 2 mod
+    // NW) and take the two edge columns (2H sites) in that slot instead.  All
+    // of a wave's loads are issued before any of its sites is computed.
+    constexpr int NR = (H + NW - 1) / NW;
     float f[NR][7];
     uint32_t site[NR];
     auto load_row = [&](float *g, uint32_t &st, int ly, bool in) {
@@ -177,23 +205,24 @@ __global__ __launch_bounds__(256) void k_batch_step2(const BatchTile *__restrict
         site_collide<F>(a, g, rho, ux, uy, st, ta_lo, ta_hi);
 #pragma unroll
         for (int i = 0; i < 7; ++i)
-            mid[(i * H + ly) * W + lx] = g[i];
+            if (ML::kept(i, lx, ly))
+                mid[ML::at(i, lx, ly)] = g[i];
     };
     // slots 0 .. NR-2: rows of every wave
     if (interior) {
 #pragma unroll
         for (int k = 0; k < NR - 1; ++k)
-            load_row(f[k], site[k], wv + 4 * k, true);
+            load_row(f[k], site[k], wv + NW * k, true);
     } else {
 #pragma unroll
         for (int k = 0; k < NR - 1; ++k)
-            load_row(f[k], site[k], wv + 4 * k, false);
+            load_row(f[k], site[k], wv + NW * k, false);
     }
-    // slot NR-1: last row of waves 0 and 1, edge sites of waves 2 and 3
+    // slot NR-1: last row of waves 0 and 1, edge sites of waves 2 and up
     const int e = (wv - 2) * 64 + lane;
     const bool edge = wv >= 2;
     const int elx = edge ? (e < H ? 0 : W - 1) : lane + 1;
-    const int ely = edge ? (e < H ? e : e - H) : wv + 4 * (NR - 1);
+    const int ely = edge ? (e < H ? e : e - H) : wv + NW * (NR - 1);
     bool elive = true;
     if (!edge) {
         load_row(f[NR - 1], site[NR - 1], ely, interior);
@@ -210,7 +239,7 @@ __global__ __launch_bounds__(256) void k_batch_step2(const BatchTile *__restrict
     }
 #pragma unroll
     for (int k = 0; k < NR - 1; ++k)
-        compute(f[k], site[k], lane + 1, wv + 4 * k);
+        compute(f[k], site[k], lane + 1, wv + NW * k);
     if (elive)
         compute(f[NR - 1], site[NR - 1], elx, ely);
     __syncthreads();
@@ -221,13 +250,13 @@ __global__ __launch_bounds__(256) void k_batch_step2(const BatchTile *__restrict
     auto second = [&](int r) {
         const int lx = lane + 1, ly = r + 1;
         float f[7];
-        f[0] = mid[(0 * H + ly) * W + lx];
-        f[1] = mid[(1 * H + ly) * W + lx - 1];
-        f[2] = mid[(2 * H + ly - 1) * W + lx - 1 + p];
-        f[3] = mid[(3 * H + ly - 1) * W + lx + p];
-        f[4] = mid[(4 * H + ly) * W + lx + 1];
-        f[5] = mid[(5 * H + ly + 1) * W + lx + p];
-        f[6] = mid[(6 * H + ly + 1) * W + lx - 1 + p];
+        f[0] = mid[ML::at(0, lx, ly)];
+        f[1] = mid[ML::at(1, lx - 1, ly)];
+        f[2] = mid[ML::at(2, lx - 1 + p, ly - 1)];
+        f[3] = mid[ML::at(3, lx + p, ly - 1)];
+        f[4] = mid[ML::at(4, lx + 1, ly)];
+        f[5] = mid[ML::at(5, lx + p, ly + 1)];
+        f[6] = mid[ML::at(6, lx - 1 + p, ly + 1)];
         float rho, jx, jy, ux, uy;
         site_moments(f, rho, jx, jy);
         local_ustar<M>(a, rho, jx, jy, ux, uy);
@@ -238,10 +267,10 @@ __global__ __launch_bounds__(256) void k_batch_step2(const BatchTile *__restrict
             BufIO<float>::store(dst, lane, i * plane + row, f[i]);
     };
     if (interior) {
-        for (int r = wv; r < TY; r += 4)
+        for (int r = wv; r < TY; r += NW)
             second(r);
     } else {
-        for (int r = wv; r < TY; r += 4)
+        for (int r = wv; r < TY; r += NW)
             if (x0 + lane < a.nx && y0 + r < a.ny)
                 second(r);
     }
@@ -521,10 +550,10 @@ static hipError_t launch_batch_step_mf(int shape, int64_t ntiles, const BatchTil
         hipLaunchKernelGGL((k_batch_step<M, F>), dim3((unsigned)ntiles), dim3(sh.tx, sh.ty), 0, s, tiles, lats, ctrl,
                            step_off, launch_off);
     else if (sh.ty == 8)
-        hipLaunchKernelGGL((k_batch_step2<M, F, 8>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
+        hipLaunchKernelGGL((k_batch_step2<M, F, 8, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
                            step_off, launch_off);
     else
-        hipLaunchKernelGGL((k_batch_step2<M, F, 16>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
+        hipLaunchKernelGGL((k_batch_step2<M, F, 16, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
                            step_off, launch_off);
     return hipGetLastError();
 }
