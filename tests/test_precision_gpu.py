@@ -82,6 +82,24 @@ def test_one_step_rounding_bound(L, orc, storage, name):
     assert (np.abs(got - ref) <= bound).all()
 
 
+@pytest.mark.parametrize("storage", [1, 2])
+def test_one_step_rounding_bound_mips(L, orc, storage):
+    """MIPS (neighbour densities staged in LDS) in deviation storage: the same
+    one-step bound, on a 200 x 70 lattice with ragged tiles in both
+    directions."""
+    cfg = _cfg(SI.MIPS, 200, 70, tau=2.0, sigma=8 / 70, C=1.0, rho_star=1.6, u_max=0.3)
+    ini = dict(mode=1, rho_mean=1.0, rho_spread=0.1, u_mag=0.1, pop_noise=1e-3)
+    rho_ref = ini["rho_mean"]
+    f0 = orc.initialise(_oparams(orc, cfg), **ini)
+    q0 = quantise(f0, storage, rho_ref)
+    f0q = dequantise(q0, rho_ref)
+    got = dequantise(run_dev(L, cfg, q0, 1, storage, rho_ref), rho_ref)
+    ref = orc.run(_oparams(orc, cfg), f0q.copy(), 1)
+    d = np.abs(ref - W[:, None, None] * rho_ref)
+    bound = U[storage] * d + 1e-6 * np.abs(ref).max() + 2.0 ** -25
+    assert (np.abs(got - ref) <= bound).all()
+
+
 @pytest.mark.parametrize("storage,bound", [(1, 2e-2), (2, 2e-3)])
 def test_hundred_steps_stated_error(L, orc, storage, bound):
     """Stable ordered CIL, 100 steps from the same dequantised input: relative
