@@ -188,7 +188,8 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const float *__restrict__
                     acc[o][k] = fmaf(d, v[k], acc[o][k]);
             }
         }
-        // the pixel groups of one pair, added in group order
+        // the pixel groups of one (pair, tap), added in group order, one
+        // (pair, tap) per thread
 #pragma unroll
         for (int o = 0; o < OG; ++o) {
             __syncthreads();
@@ -196,13 +197,14 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const float *__restrict__
             for (int k = 0; k < 9; ++k)
                 s_red[tid * 9 + k] = acc[o][k];
             __syncthreads();
-            if (tid < pairs && c0 + cl < ci_n) {
-#pragma unroll
-                for (int k = 0; k < 9; ++k) {
+            for (int q = tid; q < pairs * 9; q += 256) {
+                const int qp = q / 9, k = q - qp * 9;
+                const int qog = qp / kChunk, qcl = qp - qog * kChunk;
+                if (c0 + qcl < ci_n) {
                     float sum = 0.0f;
                     for (int g = 0; g < pg; ++g)
-                        sum += s_red[(g * pairs + tid) * 9 + k];
-                    out[((size_t)(og * OG + o) * ci_n + c0 + cl) * 9 + k] = sum;
+                        sum += s_red[(g * pairs + qp) * 9 + k];
+                    out[((size_t)(qog * OG + o) * ci_n + c0 + qcl) * 9 + k] = sum;
                 }
             }
         }
@@ -216,21 +218,29 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const float *__restrict__
     }
 }
 
-// g[e] = sum over blocks b, in order, of part[b][e] (float64); e < nw goes to
-// the weight gradient, e >= nw to the bias gradient.
+// g[e] = the sum over blocks b of part[b][e] (float64); e < nw goes to the
+// weight gradient, e >= nw to the bias gradient.  A block takes 64 entries
+// with 4 threads each: thread slice s adds blocks s, s + 4, ... in order, then
+// the four slices are added in order.
 __global__ __launch_bounds__(256) void k_grad_reduce(const float *__restrict__ part, int nblocks, int nw, int nb,
                                                      float *__restrict__ gw, float *__restrict__ gb)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nw + nb)
-        return;
+    __shared__ double s_sum[4][64];
+    const int col = threadIdx.x & 63, slice = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + col;
     double sum = 0.0;
-    for (int b = 0; b < nblocks; ++b)
-        sum += (double)part[(size_t)b * (nw + nb) + e];
-    if (e < nw)
-        gw[e] = (float)sum;
-    else
-        gb[e - nw] = (float)sum;
+    if (e < nw + nb)
+        for (int b = slice; b < nblocks; b += 4)
+            sum += (double)part[(size_t)b * (nw + nb) + e];
+    s_sum[slice][col] = sum;
+    __syncthreads();
+    if (slice == 0 && e < nw + nb) {
+        const double t = ((s_sum[0][col] + s_sum[1][col]) + s_sum[2][col]) + s_sum[3][col];
+        if (e < nw)
+            gw[e] = (float)t;
+        else
+            gb[e - nw] = (float)t;
+    }
 }
 
 // Mean squared error: dy = 2 (y - t) / count, per-block float64 partials of
@@ -530,7 +540,7 @@ static hipError_t wgrad(const float *dy, int co, const float *x, int ci, int N, 
     const int blocks = N * conv_tiles(H, W);
     hipLaunchKernelGGL((k_conv3x3_wgrad<OG>), dim3(blocks), dim3(256), 0, s, dy, co, x, ci, H, W, part);
     const int total = co * ci * 9 + co;
-    hipLaunchKernelGGL(k_grad_reduce, dim3((total + 255) / 256), dim3(256), 0, s, part, blocks, co * ci * 9, co, gw,
+    hipLaunchKernelGGL(k_grad_reduce, dim3((total + 63) / 64), dim3(256), 0, s, part, blocks, co * ci * 9, co, gw,
                        gb);
     return hipGetLastError();
 }
