@@ -11,9 +11,9 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    src = os.path.join(HERE, "lbm_oracle.c")
+    srcs = [os.path.join(HERE, "lbm_oracle.c"), os.path.join(HERE, "lbm_oracle_q9.c")]
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
-           "-o", LIB + ".tmp", src, "-lm"]
+           "-o", LIB + ".tmp", *srcs, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

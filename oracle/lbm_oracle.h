@@ -93,4 +93,27 @@ void orc_fields_of(const orc_params *p, const double *f, double *rho, double *ux
 void orc_observables(const orc_params *p, const double *f, orc_obs *out);
 void orc_fields(const orc_params *p, const double *f, double *rho, double *ux, double *uy);
 
+/* ------------------------------------------------------------------------
+ * Square-lattice (D2Q9) variant, lbm_oracle_q9.c: populations f[9][ny][nx];
+ * same parameter, init and observable structs; ny may be odd.
+ * ---------------------------------------------------------------------- */
+void orc9_lattice_vector(int i, double *ex, double *ey);
+double orc9_weight(int i);
+int orc9_opposite(int i);
+void orc9_neighbour(int nx, int ny, int x, int y, int i, int *xn, int *yn);
+void orc9_xi(double rho, double ux, double uy, double out[9]);
+void orc9_moments(const double f[9], double *rho, double *jx, double *jy);
+void orc9_gradient(const double rho_nb[9], double *gx, double *gy);
+void orc9_draws(const uint32_t w[4], uint32_t h[9]);
+void orc9_noise(const orc_params *p, uint32_t site, int64_t step, double eta[9]);
+int orc9_correct(double f[9], double rho);
+void orc9_stream(const orc_params *p, const double *in, double *out);
+int orc9_step(const orc_params *p, double *f, int64_t step);
+int orc9_run(const orc_params *p, double *f, int64_t step0, int64_t n);
+int orc9_initialise(const orc_params *p, const orc_init *in, double *f);
+void orc9_fields_of(const orc_params *p, const double *f, double *rho, double *ux, double *uy);
+void orc9_observables_of(const orc_params *p, const double *f, orc_obs *out);
+void orc9_fields(const orc_params *p, const double *f, double *rho, double *ux, double *uy);
+void orc9_observables(const orc_params *p, const double *f, orc_obs *out);
+
 #endif

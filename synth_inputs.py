@@ -18,9 +18,10 @@ def rng(seed):
     return np.random.default_rng(int(seed))
 
 
-def random_populations(nx, ny, seed, lo=0.01, hi=0.2, dtype=np.float64):
-    """Positive populations [7, ny, nx], independent uniform in [lo, hi)."""
-    return rng(seed).uniform(lo, hi, size=(7, ny, nx)).astype(dtype)
+def random_populations(nx, ny, seed, lo=0.01, hi=0.2, dtype=np.float64, q=7):
+    """Positive populations [q, ny, nx] (q = 7 triangular, 9 square lattice),
+    independent uniform in [lo, hi)."""
+    return rng(seed).uniform(lo, hi, size=(q, ny, nx)).astype(dtype)
 
 
 def symmetric_populations(nx, ny, seed, lo=0.01, hi=0.2):
@@ -31,9 +32,9 @@ def symmetric_populations(nx, ny, seed, lo=0.01, hi=0.2):
     return f
 
 
-def near_negative_populations(nx, ny, seed):
+def near_negative_populations(nx, ny, seed, q=7):
     """Small populations so that noise drives some of them negative."""
-    return rng(seed).uniform(0.0, 0.02, size=(7, ny, nx))
+    return rng(seed).uniform(0.0, 0.02, size=(q, ny, nx))
 
 
 def seed_for(config_index, lattice_index=0):
