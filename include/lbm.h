@@ -37,6 +37,26 @@
  *    d = f_i - f_opp (the paper's rule (ii), in closed form); if either rule
  *    fired, the site is rescaled to this step's density.
  *
+ * Square-lattice variant (lattice = LBM_D2Q9).  The same algorithm on the
+ * standard D2Q9 velocity set, whose sound speed is c_s^2 = 1/3 (the paper
+ * notes that c_s is a property of the lattice, appendix "Chapman-Enskog
+ * Expansion"):
+ *  - e_0 = 0; e_1..e_4 = (1,0), (0,1), (-1,0), (0,-1); e_5..e_8 = (1,1),
+ *    (-1,1), (-1,-1), (1,-1); weights 4/9, 1/9, 1/36; opposite pairs 1-3,
+ *    2-4, 5-7, 6-8; site (x, y) at (x, y), periodic; ny may be odd.
+ *  - xi_i(rho, u) = w_i rho [1 + 3 e_i.u + (9/2)(e_i.u)^2 - (3/2)|u|^2].
+ *  - MIPS gradient: grad rho = 3 sum_i w_i e_i rho(r + e_i), the paper's
+ *    construction of its isotropic stencil on this lattice.
+ *  - Noise: the raw draw of direction i is sigma (2 U_i - 1),
+ *    U_i = (h_i + 1/2)/16384, h_i = bits 14 i .. 14 i + 13 of the 128-bit
+ *    Philox4x32-10 output (word 0 lowest; same key and counter as above);
+ *    eta_i subtracts the mean of the nine.
+ *  - A population buffer is [9][ny][pitch]; every plane must be below 2^32
+ *    bytes (ny * pitch < 2^30 for F32, < 2^31 for the 16-bit storages).
+ *  - lbm_add_density adds drho/9 to every population.
+ *  - Batched sweeps and the coarse-field calls take D2Q7 only
+ *    (LBM_EUNSUPPORTED).
+ *
  * Memory ownership.  The caller owns every device buffer passed in
  * (population buffers, field outputs, batch buffers, workspaces, network
  * tensors) and the HIP stream, and keeps them alive until the context that
@@ -72,6 +92,10 @@ extern "C" {
 #define LBM_MIPS 1    /* u* = C (1 - rho/rho*) grad rho for rho < rho*, |u*| <= U_max */
 #define LBM_CIL 2     /* u* = U0(rho) u/|u|, U0 = B - A rho^2 if B >= A rho^2, else 0 */
 
+/* Velocity sets. */
+#define LBM_D2Q7 0 /* triangular lattice, offset rows (the paper's) */
+#define LBM_D2Q9 1 /* square lattice, c_s^2 = 1/3 */
+
 /* Population storage. */
 #define LBM_F32 0      /* float32 populations */
 #define LBM_BF16_DEV 1 /* bfloat16 deviations d_i = f_i - w_i rho_ref (round to nearest even) */
@@ -83,7 +107,7 @@ extern "C" {
 #define LBM_INIT_GAUSS_DIR 2   /* direction normal about +x with std angle_std */
 
 typedef struct lbm_params {
-    int32_t nx, ny;    /* lattice size; ny even, ny <= 65535; nx * ny < 2^32 */
+    int32_t nx, ny;    /* lattice size; ny <= 65535; nx * ny < 2^32; ny even on D2Q7 */
     int32_t model;     /* LBM_PASSIVE / LBM_MIPS / LBM_CIL */
     int32_t storage;   /* LBM_F32 / LBM_BF16_DEV / LBM_F16_DEV */
     double tau;        /* relaxation time, >= 1 (appendix "Negative Correction"); +inf = streaming only */
@@ -93,6 +117,8 @@ typedef struct lbm_params {
     double u_max;      /* MIPS clamp */
     double rho_ref;    /* reference density of the deviation storages */
     uint64_t seed;     /* Philox key */
+    int32_t lattice;   /* LBM_D2Q7 / LBM_D2Q9 */
+    int32_t reserved;  /* 0 */
 } lbm_params;
 
 typedef struct lbm_init {
@@ -122,16 +148,17 @@ typedef struct lbm_ctx lbm_ctx;
 
 /* Create a lattice context on the current HIP device.
  *   p       parameters (copied).
- *   f_a,f_b two caller-owned device buffers [7][ny][pitch] of the storage
- *           type; the state starts in f_a.
+ *   f_a,f_b two caller-owned device buffers [Q][ny][pitch] of the storage
+ *           type (Q = 7 on D2Q7, 9 on D2Q9); the state starts in f_a.
  *   pitch   row pitch in elements, >= nx.
  *   init    initial state written into f_a (NULL or LBM_INIT_NONE: the caller
  *           has filled f_a).
  *   stream  caller's hipStream_t (NULL: the null stream), cast to void*.
  *   out     receives the context.
- * Returns LBM_EINVAL for nx < 2, odd, < 2 or > 65535 ny, nx*ny >= 2^32, pitch < nx,
- * tau < 1, sigma < 0, non-finite or negative model constants, null or equal
- * buffers, unknown model/storage/init mode. */
+ * Returns LBM_EINVAL for nx < 2, ny < 2 or > 65535 (or odd on D2Q7),
+ * nx*ny >= 2^32, pitch < nx, tau < 1, sigma < 0, non-finite or negative model
+ * constants, null or equal buffers, unknown lattice/model/storage/init mode;
+ * LBM_EUNSUPPORTED for a D2Q9 plane of 2^32 bytes or more. */
 int32_t lbm_create(const lbm_params *p, void *f_a, void *f_b, int64_t pitch, const lbm_init *init,
                    void *stream, lbm_ctx **out);
 
@@ -155,8 +182,9 @@ int32_t lbm_current_buffer(const lbm_ctx *c);
 int64_t lbm_get_step(const lbm_ctx *c);
 int32_t lbm_set_step(lbm_ctx *c, int64_t step);
 
-/* Add drho/7 to every population of the stored state (the adiabatic density
- * change of the appendix "CIL Model: General notes").  Enqueued, no sync. */
+/* Add drho/7 (D2Q9: drho/9) to every population of the stored state (the
+ * adiabatic density change of the appendix "CIL Model: General notes"), which
+ * raises every site's density by drho.  Enqueued, no sync. */
 int32_t lbm_add_density(lbm_ctx *c, double drho);
 
 /* Release the context (waits for its stream first). */
@@ -202,8 +230,9 @@ size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samp
  * arguments. */
 int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n);
 
-/* Run a batch.  ps[n]: per-lattice parameters; every lattice uses F32
- * storage, the same model (CIL or passive), and agrees on tau == 1 and on
+/* Run a batch.  ps[n]: per-lattice parameters; every lattice uses the D2Q7
+ * lattice, F32 storage, the same model (CIL or passive), and agrees on
+ * tau == 1 and on
  * sigma == 0; nx*ny*7 < 2^30, ny <= 32760.  bufs[2n]: caller-owned device
  * buffers [7][ny][nx], lattice l's state in bufs[2l] and bufs[2l+1] free.
  * ws: caller-owned device workspace of ws_bytes >=

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ENONFINITE, LBM_EUNSUPPORTED, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_PASSIVE, LBM_MIPS, LBM_CIL = 0, 1, 2
 LBM_F32, LBM_BF16_DEV, LBM_F16_DEV = 0, 1, 2
+LBM_D2Q7, LBM_D2Q9 = 0, 1
 LBM_INIT_NONE, LBM_INIT_UNIFORM_DIR, LBM_INIT_GAUSS_DIR = 0, 1, 2
 
 
@@ -27,7 +28,7 @@ class lbm_params(ctypes.Structure):
                 ("storage", ctypes.c_int32), ("tau", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("A", ctypes.c_double), ("B", ctypes.c_double), ("C", ctypes.c_double),
                 ("rho_star", ctypes.c_double), ("u_max", ctypes.c_double), ("rho_ref", ctypes.c_double),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("lattice", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class lbm_init(ctypes.Structure):
@@ -313,9 +314,15 @@ class Batch:
 # ----------------------------------------------------------------- helpers
 
 def make_params(nx, ny, model, tau=1.0, sigma=0.0, A=0.0, B=0.0, C=0.0, rho_star=1.0, u_max=1.0, seed=0,
-                storage=LBM_F32, rho_ref=0.0):
+                storage=LBM_F32, rho_ref=0.0, lattice=LBM_D2Q7):
     return lbm_params(int(nx), int(ny), int(model), int(storage), float(tau), float(sigma), float(A), float(B),
-                      float(C), float(rho_star), float(u_max), float(rho_ref), int(seed) & 0xFFFFFFFFFFFFFFFF)
+                      float(C), float(rho_star), float(u_max), float(rho_ref), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                      int(lattice), 0)
+
+
+def n_populations(params):
+    """Populations per site: 7 on the triangular lattice, 9 on the square one."""
+    return 9 if params.lattice == LBM_D2Q9 else 7
 
 
 def make_init(mode=LBM_INIT_UNIFORM_DIR, rho_mean=1.0, rho_spread=0.1, angle_std=0.0, u_mag=-1.0, pop_noise=0.0):
@@ -329,15 +336,17 @@ def storage_dtype(storage):
 
 
 class Lattice:
-    """One lattice with torch-owned population buffers [7, ny, pitch] on the
-    current device; every operation is a call of the C ABI."""
+    """One lattice with torch-owned population buffers [Q, ny, pitch] on the
+    current device (Q = 7 on D2Q7, 9 on D2Q9); every operation is a call of
+    the C ABI."""
 
     def __init__(self, params, init=None, pitch=None, stream=None, device="cuda"):
         import torch
         self.params = params
         self.pitch = int(pitch or params.nx)
         dt = storage_dtype(params.storage)
-        self.buffers = [torch.zeros((7, params.ny, self.pitch), dtype=dt, device=device) for _ in range(2)]
+        q = n_populations(params)
+        self.buffers = [torch.zeros((q, params.ny, self.pitch), dtype=dt, device=device) for _ in range(2)]
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.ctx = lbm_create(params, self.buffers[0].data_ptr(), self.buffers[1].data_ptr(), self.pitch, init,
                               self.stream.cuda_stream)
@@ -350,7 +359,7 @@ class Lattice:
         return self.buffers[lbm_current_buffer(self.ctx)]
 
     def set_state(self, f):
-        """Copy populations [7, ny, nx] (storage dtype) into the current buffer."""
+        """Copy populations [Q, ny, nx] (storage dtype) into the current buffer."""
         self.state[:, :, : self.params.nx].copy_(f)
 
     def fields(self):

@@ -692,6 +692,8 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         int32_t rc = validate_params(&ps[l], ps[l].nx);
         if (rc)
             return fail(rc, "lattice " + std::to_string(l) + ": " + lbm_last_error());
+        if (ps[l].lattice != LBM_D2Q7)
+            return fail(LBM_EUNSUPPORTED, "batched sweeps take the D2Q7 lattice");
         if (ps[l].storage != LBM_F32)
             return fail(LBM_EUNSUPPORTED, "batched sweeps take F32 storage");
         if (ps[l].model == LBM_MIPS)

@@ -32,9 +32,11 @@ int32_t validate_params(const lbm_params *p, int64_t pitch)
 {
     if (!p)
         return fail(LBM_EINVAL, "null parameters");
+    if (p->lattice != LBM_D2Q7 && p->lattice != LBM_D2Q9)
+        return fail(LBM_EINVAL, "unknown lattice");
     if (p->nx < 2 || p->ny < 2)
         return fail(LBM_EINVAL, "nx and ny must be >= 2");
-    if (p->ny & 1)
+    if (p->lattice == LBM_D2Q7 && (p->ny & 1))
         return fail(LBM_EINVAL, "ny must be even (offset-row triangular lattice)");
     if (p->ny > 65535)
         return fail(LBM_EINVAL, "ny must be <= 65535 (one grid row of blocks per lattice row)");
@@ -56,6 +58,8 @@ int32_t validate_params(const lbm_params *p, int64_t pitch)
         return fail(LBM_EINVAL, "rho_star must be finite and > 0 for MIPS");
     if (p->storage != LBM_F32 && !finite_nonneg(p->rho_ref))
         return fail(LBM_EINVAL, "rho_ref must be finite and >= 0 for deviation storage");
+    if (p->lattice == LBM_D2Q9 && (uint64_t)p->ny * (uint64_t)pitch * (p->storage == LBM_F32 ? 4u : 2u) >= (1ull << 32))
+        return fail(LBM_EUNSUPPORTED, "D2Q9 population planes must be below 2^32 bytes");
     return LBM_OK;
 }
 
@@ -67,7 +71,8 @@ StepArgs make_step_args(const lbm_params &p, int64_t pitch)
     a.pitch = pitch;
     a.plane = (int64_t)p.ny * pitch;
     a.omega = (float)(1.0 / p.tau);
-    a.noise_scale = (float)(p.sigma / 229376.0);
+    const bool q9 = p.lattice == LBM_D2Q9;
+    a.noise_scale = (float)(q9 ? p.sigma / 73728.0 : p.sigma / 229376.0);
     a.A16 = (float)p.A * 65536.0f;
     a.B16 = (float)p.B * 65536.0f;
     a.C = (float)p.C;
@@ -75,8 +80,9 @@ StepArgs make_step_args(const lbm_params &p, int64_t pitch)
     a.inv_rho_star = p.model == LBM_MIPS ? (float)(1.0 / p.rho_star) : 1.0f;
     a.u_max = (float)p.u_max;
     const double rr = p.storage == LBM_F32 ? 0.0 : p.rho_ref;
-    a.wr0 = (float)(0.5 * rr);
-    a.wr1 = (float)(rr / 12.0);
+    a.wr0 = (float)(q9 ? 4.0 * rr / 9.0 : 0.5 * rr);
+    a.wr1 = (float)(q9 ? rr / 9.0 : rr / 12.0);
+    a.wr2 = (float)(q9 ? rr / 36.0 : rr / 12.0);
     a.key0 = (uint32_t)(p.seed & 0xffffffffu);
     a.key1 = (uint32_t)(p.seed >> 32);
     a.noisy = p.sigma != 0.0;
@@ -131,7 +137,8 @@ int32_t lbm_create(const lbm_params *p, void *f_a, void *f_b, int64_t pitch, con
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&c->h_result, 8 * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess && init && init->mode != LBM_INIT_NONE)
-        e = launch_init(*p, *init, c->args, f_a, c->stream);
+        e = p->lattice == LBM_D2Q9 ? launch_init_q9(*p, *init, c->args, f_a, c->stream)
+                                   : launch_init(*p, *init, c->args, f_a, c->stream);
     if (e != hipSuccess) {
         rc = hip_fail(e, "lbm_create");
         if (c->d_scratch) hipFree(c->d_scratch);
@@ -151,7 +158,9 @@ int32_t lbm_step(lbm_ctx *c, int64_t n)
     if (n < 0)
         return fail(LBM_EINVAL, "negative step count");
     for (int64_t k = 0; k < n; ++k) {
-        hipError_t e = launch_step(c->p, c->args, c->buf[c->cur], c->buf[c->cur ^ 1], c->step, c->stream);
+        hipError_t e = c->p.lattice == LBM_D2Q9
+                           ? launch_step_q9(c->p, c->args, c->buf[c->cur], c->buf[c->cur ^ 1], c->step, c->stream)
+                           : launch_step(c->p, c->args, c->buf[c->cur], c->buf[c->cur ^ 1], c->step, c->stream);
         if (e != hipSuccess)
             return hip_fail(e, "lbm_step");
         c->cur ^= 1;
@@ -205,7 +214,10 @@ int32_t lbm_add_density(lbm_ctx *c, double drho)
         return fail(LBM_ESTATE, "null context");
     if (!isfinite(drho))
         return fail(LBM_EINVAL, "drho must be finite");
-    LBM_HIP_TRY(launch_add_density(c->p, c->args, c->buf[c->cur], drho, c->stream));
+    if (c->p.lattice == LBM_D2Q9)
+        LBM_HIP_TRY(launch_add_density_q9(c->p, c->args, c->buf[c->cur], drho, c->stream));
+    else
+        LBM_HIP_TRY(launch_add_density(c->p, c->args, c->buf[c->cur], drho, c->stream));
     return LBM_OK;
 }
 

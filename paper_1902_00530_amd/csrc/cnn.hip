@@ -739,6 +739,8 @@ int32_t lbm_coarsen(const lbm_params *p, const float *f, int32_t c, float *out, 
         return rc;
     if (!f || !out)
         return fail(LBM_EINVAL, "null pointer");
+    if (p->lattice != LBM_D2Q7)
+        return fail(LBM_EUNSUPPORTED, "coarse fields take the D2Q7 lattice");
     if (p->storage != LBM_F32)
         return fail(LBM_EUNSUPPORTED, "coarse fields take F32 storage");
     if (c < 1 || p->nx % c || p->ny % c || ((c & 1) && c != 1))
@@ -758,6 +760,8 @@ static int32_t check_fields(const lbm_params *p, int32_t c)
     int32_t rc = validate_params(p, p ? p->nx : 0);
     if (rc)
         return rc;
+    if (p->lattice != LBM_D2Q7)
+        return fail(LBM_EUNSUPPORTED, "coarse fields take the D2Q7 lattice");
     if (p->storage != LBM_F32)
         return fail(LBM_EUNSUPPORTED, "coarse fields take F32 storage");
     if (c < 1 || p->nx % c || p->ny % c || ((c & 1) && c != 1))
@@ -808,6 +812,8 @@ int32_t lbm_lift(const lbm_params *p, const float *coarse, int32_t c, float *f, 
         return rc;
     if (!f || !coarse)
         return fail(LBM_EINVAL, "null pointer");
+    if (p->lattice != LBM_D2Q7)
+        return fail(LBM_EUNSUPPORTED, "lifting takes the D2Q7 lattice");
     if (p->storage != LBM_F32)
         return fail(LBM_EUNSUPPORTED, "lifting writes F32 storage");
     if (c < 1 || p->nx % c || p->ny % c || ((c & 1) && c != 1))

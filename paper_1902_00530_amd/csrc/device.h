@@ -20,10 +20,12 @@ struct StepArgs {
     int64_t pitch;      // elements per row
     int64_t plane;      // elements per population plane (ny * pitch)
     float omega;        // 1 / tau (0 for tau = +inf)
-    float noise_scale;  // sigma / 229376: eta_i = (7 h_i - sum h) * noise_scale
+    float noise_scale;  // D2Q7: sigma / 229376, eta_i = (7 h_i - sum h) * noise_scale;
+                        // D2Q9: sigma / 73728, eta_i = (9 h_i - sum h) * noise_scale
     float A16, B16;     // CIL A and B times 2^16 (exact), see local_ustar
     float C, rho_star, inv_rho_star, u_max;  // MIPS
-    float wr0, wr1;     // w_0 rho_ref, w_i rho_ref (deviation storages)
+    float wr0, wr1, wr2;  // w_i rho_ref (deviation storages): D2Q7 rest, moving;
+                          // D2Q9 rest, axes, diagonals
     uint32_t key0, key1;
     int32_t noisy;      // sigma != 0
 };
@@ -170,12 +172,11 @@ __device__ __forceinline__ void local_ustar(const StepArgs &a, float rho, float 
     }
 }
 
-// MIPS target velocity from the six neighbour densities (isotropic stencil,
-// component form) with the U_max clamp that keeps the direction.
-__device__ __forceinline__ void mips_ustar(const StepArgs &a, float rho, const float nb[7], float &ux, float &uy)
+// MIPS target velocity (eq. bu_mips) from the density gradient, with the
+// U_max clamp that keeps the direction.
+__device__ __forceinline__ void mips_from_gradient(const StepArgs &a, float rho, float gx, float gy, float &ux,
+                                                   float &uy)
 {
-    const float gx = (2.0f * (nb[1] - nb[4]) + (nb[2] + nb[6]) - (nb[3] + nb[5])) * (1.0f / 6.0f);
-    const float gy = ((nb[2] + nb[3]) - (nb[5] + nb[6])) * kInv2Sqrt3;
     float k = 0.0f;
     if (rho < a.rho_star)
         k = a.C * (1.0f - rho * a.inv_rho_star);
@@ -187,6 +188,15 @@ __device__ __forceinline__ void mips_ustar(const StepArgs &a, float rho, const f
         ux *= s;
         uy *= s;
     }
+}
+
+// MIPS target velocity from the six neighbour densities (isotropic stencil,
+// component form).
+__device__ __forceinline__ void mips_ustar(const StepArgs &a, float rho, const float nb[7], float &ux, float &uy)
+{
+    const float gx = (2.0f * (nb[1] - nb[4]) + (nb[2] + nb[6]) - (nb[3] + nb[5])) * (1.0f / 6.0f);
+    const float gy = ((nb[2] + nb[3]) - (nb[5] + nb[6])) * kInv2Sqrt3;
+    mips_from_gradient(a, rho, gx, gy, ux, uy);
 }
 
 // Steady state xi(rho, u) of eq. fssD2Q7 in pair form: a_k = e_k.u,

@@ -35,6 +35,11 @@ hipError_t launch_step(const lbm_params &p, const StepArgs &a, const void *src, 
 hipError_t launch_init(const lbm_params &p, const lbm_init &in, const StepArgs &a, void *dst, hipStream_t s);
 // f_i += drho / 7 in place.
 hipError_t launch_add_density(const lbm_params &p, const StepArgs &a, void *buf, double drho, hipStream_t s);
+// The same three on the square (D2Q9) lattice (f_i += drho / 9).
+hipError_t launch_step_q9(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
+                          hipStream_t s);
+hipError_t launch_init_q9(const lbm_params &p, const lbm_init &in, const StepArgs &a, void *dst, hipStream_t s);
+hipError_t launch_add_density_q9(const lbm_params &p, const StepArgs &a, void *buf, double drho, hipStream_t s);
 
 // Moments and FP64 reductions.  scratch: device doubles of
 // moments_scratch_doubles(p); result: 8 device doubles

@@ -11,6 +11,7 @@
 // thread per column) and pass 3 (one block) adds the block partials and the
 // column means in a fixed order, so the result does not depend on
 // scheduling.
+#include "device_q9.h"
 #include "internal.h"
 
 namespace lbm {
@@ -61,7 +62,33 @@ __device__ __forceinline__ void block_sum(double v[N], double (*lds)[N])
     __syncthreads();
 }
 
-template <int S>
+// The streamed populations of site (x, y) and their rho, j and finiteness,
+// on the triangular (Q = 7) or the square (Q = 9) lattice.
+template <int S, int Q>
+__device__ __forceinline__ void gathered_moments(const typename Store<S>::T *src, const StepArgs &a, int x, int y,
+                                                 float &rho, float &jx, float &jy, bool &finite)
+{
+    float f[Q];
+    if constexpr (Q == 7) {
+        const PullSources g_src = pull_sources(a, x, y);
+#pragma unroll
+        for (int i = 0; i < 7; ++i)
+            f[i] = Store<S>::load(src, i * a.plane + g_src.idx[i], i == 0 ? a.wr0 : a.wr1);
+        site_moments(f, rho, jx, jy);
+    } else {
+        const Q9Sources g_src = q9_sources(a, x, y);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            f[i] = Store<S>::load(src, i * a.plane + g_src.idx[i], q9_wr(a, i));
+        q9_moments(f, rho, jx, jy);
+    }
+    finite = true;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        finite = finite && isfinite(f[i]);
+}
+
+template <int S, int Q>
 __global__ __launch_bounds__(kMomBX) void k_moments(const typename Store<S>::T *__restrict__ src, StepArgs a,
                                                     float *__restrict__ rho_out, float *__restrict__ ux_out,
                                                     float *__restrict__ uy_out, double *__restrict__ part,
@@ -75,17 +102,9 @@ __global__ __launch_bounds__(kMomBX) void k_moments(const typename Store<S>::T *
     if (x < a.nx) {
         const int ye = min(yb + kRowsPerBlock, a.ny);
         for (int y = yb; y < ye; ++y) {
-            const PullSources g_src = pull_sources(a, x, y);
-            float f[7];
-#pragma unroll
-            for (int i = 0; i < 7; ++i)
-                f[i] = Store<S>::load(src, i * a.plane + g_src.idx[i], i == 0 ? a.wr0 : a.wr1);
             float rho, jx, jy;
-            site_moments(f, rho, jx, jy);
-            bool finite = true;
-#pragma unroll
-            for (int i = 0; i < 7; ++i)
-                finite = finite && isfinite(f[i]);
+            bool finite;
+            gathered_moments<S, Q>(src, a, x, y, rho, jx, jy, finite);
             const double dr = rho, dx = jx, dy = jy;
             acc[0] += dr;
             acc[1] += dx;
@@ -169,17 +188,29 @@ hipError_t launch_moments(const lbm_params &p, const StepArgs &a, const void *sr
     double *colpart = part + (size_t)gx * gy * kNPart;
     double *colmean = colpart + (size_t)gy * p.nx;
     dim3 grd(gx, gy), blk(kMomBX);
+    const bool q9 = p.lattice == LBM_D2Q9;
     switch (p.storage) {
     case kF32:
-        hipLaunchKernelGGL(k_moments<kF32>, grd, blk, 0, s, (const float *)src, a, rho, ux, uy, part, colpart);
+        if (q9)
+            hipLaunchKernelGGL((k_moments<kF32, 9>), grd, blk, 0, s, (const float *)src, a, rho, ux, uy, part, colpart);
+        else
+            hipLaunchKernelGGL((k_moments<kF32, 7>), grd, blk, 0, s, (const float *)src, a, rho, ux, uy, part, colpart);
         break;
     case kBf16Dev:
-        hipLaunchKernelGGL(k_moments<kBf16Dev>, grd, blk, 0, s, (const uint16_t *)src, a, rho, ux, uy, part,
-                           colpart);
+        if (q9)
+            hipLaunchKernelGGL((k_moments<kBf16Dev, 9>), grd, blk, 0, s, (const uint16_t *)src, a, rho, ux, uy, part,
+                               colpart);
+        else
+            hipLaunchKernelGGL((k_moments<kBf16Dev, 7>), grd, blk, 0, s, (const uint16_t *)src, a, rho, ux, uy, part,
+                               colpart);
         break;
     case kF16Dev:
-        hipLaunchKernelGGL(k_moments<kF16Dev>, grd, blk, 0, s, (const _Float16 *)src, a, rho, ux, uy, part,
-                           colpart);
+        if (q9)
+            hipLaunchKernelGGL((k_moments<kF16Dev, 9>), grd, blk, 0, s, (const _Float16 *)src, a, rho, ux, uy, part,
+                               colpart);
+        else
+            hipLaunchKernelGGL((k_moments<kF16Dev, 7>), grd, blk, 0, s, (const _Float16 *)src, a, rho, ux, uy, part,
+                               colpart);
         break;
     default: return hipErrorInvalidValue;
     }

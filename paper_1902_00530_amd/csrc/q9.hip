@@ -1,0 +1,306 @@
+// Fused step of the square-lattice (D2Q9) variant on gfx950: the algorithm
+// of the appendix "Summary of modified lattice Boltzmann model algorithm" on
+// the D2Q9 velocity set (site body in device_q9.h).  Population i of site r is
+// gathered from r - e_i in the source buffer, collided, and stored at r in
+// the other buffer: 9 loads and 9 stores, 72 B per site-update in F32.
+//
+// Each population plane gets its own buffer resource, so element offsets are
+// 32-bit within a plane and the lattice may hold up to 2^30 F32 sites per
+// plane.  Like the D2Q7 path, the step is bound by HBM bandwidth and has no
+// matrix-core work.
+#include "device_q9.h"
+#include "internal.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Passive and CIL (u* from the site alone).  A block is a BX x BY tile with
+// BX a multiple of 64, laid out in row groups so each row of tiles runs on
+// one XCD.
+// ---------------------------------------------------------------------------
+template <int M, int S, int F>
+__global__ __launch_bounds__(256) void k_q9_step_local(const typename Store<S>::T *__restrict__ src,
+                                                       typename Store<S>::T *__restrict__ dst, StepArgs a,
+                                                       uint32_t t_lo, uint32_t t_hi)
+{
+    int txi, tyi;
+    row_group_tile(txi, tyi);
+    const int x = txi * blockDim.x + threadIdx.x;
+    const int y = tyi * blockDim.y + threadIdx.y;
+    if (x >= a.nx || y >= a.ny)
+        return;
+    using T = typename Store<S>::T;
+    const uint32_t plane = (uint32_t)a.plane;
+    const Q9Sources g = q9_sources(a, x, y);
+    float f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        f[i] = Store<S>::widen(BufIO<T>::load(q9_plane_rsrc(src, i, plane), g.idx[i], 0u), q9_wr(a, i));
+    float rho, jx, jy, ux, uy;
+    q9_moments(f, rho, jx, jy);
+    local_ustar<M>(a, rho, jx, jy, ux, uy);
+    q9_collide<F>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        BufIO<T>::store(q9_plane_rsrc(dst, i, plane), g.idx[0], 0u, Store<S>::narrow(f[i], q9_wr(a, i)));
+}
+
+// ---------------------------------------------------------------------------
+// MIPS: u* needs the streamed density of the eight neighbours.  A 64 x 16
+// tile (256 threads; wave w owns rows w, w+4, w+8, w+12, one column per lane)
+// stages rho of the tile and of its one-site ring (rows above and below,
+// corners included, and the two edge columns: 164 sites, taken by waves
+// 0-2) in LDS.  The tile's own populations stay in registers from the
+// density pass to the collision.  On tiles whose sources do not wrap, a
+// row's nine loads share one vector offset (the lane) and wave-uniform
+// scalar offsets.  Every LDS slot holds rho at its periodically wrapped
+// site, so ragged tiles and lattices narrower than a tile need no special
+// case.
+// ---------------------------------------------------------------------------
+constexpr int kQ9MipsRows = 16;
+
+template <int S, int F>
+__global__ __launch_bounds__(256) void k_q9_step_mips(const typename Store<S>::T *__restrict__ src,
+                                                      typename Store<S>::T *__restrict__ dst, StepArgs a,
+                                                      uint32_t t_lo, uint32_t t_hi)
+{
+    using T = typename Store<S>::T;
+    constexpr int W = 66, H = kQ9MipsRows + 2, RW = kQ9MipsRows / 4;
+    constexpr int kRing = 2 * W + 2 * kQ9MipsRows;  // 164
+    __shared__ float srho[H * W];
+    int txi, tyi;
+    row_group_tile(txi, tyi);
+    const int x0 = txi * 64, y0 = tyi * kQ9MipsRows;
+    if (y0 >= a.ny)  // padding tile rows of the last group: the whole block
+        return;
+    const uint32_t plane = (uint32_t)a.plane, P = (uint32_t)a.pitch, nx = (uint32_t)a.nx;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const bool interior = x0 >= 1 && x0 + 65 <= a.nx && y0 >= 1 && y0 + kQ9MipsRows + 1 <= a.ny;
+    auto load_wrapped = [&](float *g, int x, int y) {
+        const Q9Sources q = q9_sources(a, wrap_coord(x, a.nx), wrap_coord(y, a.ny));
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            g[i] = Store<S>::widen(BufIO<T>::load(q9_plane_rsrc(src, i, plane), q.idx[i], 0u), q9_wr(a, i));
+    };
+    float f[RW][9];
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        const int y = y0 + wv + 4 * k;
+        if (interior) {
+            const uint32_t c = (uint32_t)y * P + (uint32_t)x0;  // offset of (x0, y)
+            const uint32_t e[9] = {c, c - 1u, c - P, c + 1u, c + P, c - P - 1u, c - P + 1u, c + P + 1u, c + P - 1u};
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                f[k][i] = Store<S>::widen(BufIO<T>::load(q9_plane_rsrc(src, i, plane), lane, e[i]), q9_wr(a, i));
+        } else {
+            load_wrapped(f[k], x0 + lane, y);
+        }
+    }
+    const int re = wv * 64 + lane;  // this lane's ring site (waves 0-2)
+    if (re < kRing) {
+        int rlx, rly;
+        if (re < W) {
+            rlx = re;
+            rly = 0;
+        } else if (re < 2 * W) {
+            rlx = re - W;
+            rly = H - 1;
+        } else {
+            rlx = re < 2 * W + kQ9MipsRows ? 0 : W - 1;
+            rly = 1 + (re - 2 * W) % kQ9MipsRows;
+        }
+        float g[9], jx, jy;
+        load_wrapped(g, x0 - 1 + rlx, y0 - 1 + rly);
+        q9_moments(g, srho[rly * W + rlx], jx, jy);
+    }
+    float rho[RW];
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        float jx, jy;
+        q9_moments(f[k], rho[k], jx, jy);
+        srho[(wv + 4 * k + 1) * W + lane + 1] = rho[k];
+    }
+    __syncthreads();
+    const int x = x0 + lane;
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        const int r = wv + 4 * k, y = y0 + r;
+        if (x >= a.nx || y >= a.ny)
+            continue;
+        const int c = (r + 1) * W + lane + 1;
+        float nb[9];
+        nb[0] = rho[k];
+        nb[1] = srho[c + 1];
+        nb[2] = srho[c + W];
+        nb[3] = srho[c - 1];
+        nb[4] = srho[c - W];
+        nb[5] = srho[c + W + 1];
+        nb[6] = srho[c + W - 1];
+        nb[7] = srho[c - W - 1];
+        nb[8] = srho[c - W + 1];
+        float ux, uy;
+        q9_mips_ustar(a, rho[k], nb, ux, uy);
+        q9_collide<F>(a, f[k], rho[k], ux, uy, (uint32_t)y * nx + (uint32_t)x, t_lo, t_hi);
+        const uint32_t own = (uint32_t)y * P + (uint32_t)x;
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            BufIO<T>::store(q9_plane_rsrc(dst, i, plane), own, 0u, Store<S>::narrow(f[k][i], q9_wr(a, i)));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int S, int F>
+static hipError_t launch_q9_sf(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
+                               hipStream_t s)
+{
+    using T = typename Store<S>::T;
+    const uint32_t tlo = (uint32_t)((uint64_t)t & 0xffffffffu), thi = (uint32_t)((uint64_t)t >> 32);
+    const T *in = (const T *)src;
+    T *out = (T *)dst;
+    if (p.model == kMips) {
+        const int ntx = (p.nx + 63) / 64, nty = (p.ny + kQ9MipsRows - 1) / kQ9MipsRows;
+        dim3 grd(8u * (unsigned)ntx, (unsigned)((nty + 7) / 8));
+        hipLaunchKernelGGL((k_q9_step_mips<S, F>), grd, dim3(256), 0, s, in, out, a, tlo, thi);
+        return hipGetLastError();
+    }
+    const int bx = p.nx >= 256 ? 256 : ((p.nx + 63) / 64) * 64;
+    dim3 blk(bx, 256 / bx);
+    const int ntx = (p.nx + blk.x - 1) / blk.x, nty = (p.ny + blk.y - 1) / blk.y;
+    dim3 grd(8u * (unsigned)ntx, (unsigned)((nty + 7) / 8));
+    if (p.model == kCil)
+        hipLaunchKernelGGL((k_q9_step_local<kCil, S, F>), grd, blk, 0, s, in, out, a, tlo, thi);
+    else
+        hipLaunchKernelGGL((k_q9_step_local<kPassive, S, F>), grd, blk, 0, s, in, out, a, tlo, thi);
+    return hipGetLastError();
+}
+
+template <int S>
+static hipError_t launch_q9_s(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
+                              hipStream_t s)
+{
+    switch (step_flags(a)) {
+    case 0: return launch_q9_sf<S, 0>(p, a, src, dst, t, s);
+    case kUnitTau: return launch_q9_sf<S, kUnitTau>(p, a, src, dst, t, s);
+    case kNoisy: return launch_q9_sf<S, kNoisy>(p, a, src, dst, t, s);
+    default: return launch_q9_sf<S, kUnitTau | kNoisy>(p, a, src, dst, t, s);
+    }
+}
+
+hipError_t launch_step_q9(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
+                          hipStream_t s)
+{
+    switch (p.storage) {
+    case kF32: return launch_q9_s<kF32>(p, a, src, dst, t, s);
+    case kBf16Dev: return launch_q9_s<kBf16Dev>(p, a, src, dst, t, s);
+    case kF16Dev: return launch_q9_s<kF16Dev>(p, a, src, dst, t, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Initial state (appendix "CIL Model: General notes") in FP64, rounded once
+// into the storage: the variates of the D2Q7 initial state (counter
+// (site, 0, 0, 1): direction, density, Box-Muller angle) with this lattice's
+// steady state; the optional population perturbation takes the nine 14-bit
+// draws of counter (site, 0, 0, 2).
+// ---------------------------------------------------------------------------
+struct Q9InitArgs {
+    int32_t mode, model;
+    double rho_mean, rho_spread, angle_std, u_mag, pop_noise, A, B;
+};
+
+template <int S>
+__global__ __launch_bounds__(256) void k_q9_init(typename Store<S>::T *__restrict__ dst, StepArgs a, Q9InitArgs in)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= a.nx)
+        return;
+    const uint32_t site = (uint32_t)y * (uint32_t)a.nx + (uint32_t)x;
+    const Philox4 w = philox4x32_10(site, 0u, 0u, 1u, a.key0, a.key1);
+    double u[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        u[k] = ((double)w.v[k] + 0.5) * (1.0 / 4294967296.0);
+    const double two_pi = 6.283185307179586476925;
+    const double theta = in.mode == LBM_INIT_GAUSS_DIR ? in.angle_std * sqrt(-2.0 * log(u[2])) * cos(two_pi * u[3])
+                                                       : two_pi * u[0];
+    const double r = in.rho_mean * (1.0 + in.rho_spread * (2.0 * u[1] - 1.0));
+    double mag = 0.0;
+    if (in.u_mag >= 0.0)
+        mag = in.u_mag;
+    else if (in.model == kCil)
+        mag = fmax(in.B - in.A * r * r, 0.0);
+    const double vx = mag * cos(theta), vy = mag * sin(theta);
+    const double base = 1.0 - 1.5 * (vx * vx + vy * vy);
+    const double al[4] = {vx, vy, vx + vy, vy - vx};  // e_1, e_2, e_5, e_6 dotted with v
+    const int first[4] = {1, 2, 5, 6};
+    double g[9];
+    g[0] = (4.0 / 9.0) * r * base;
+    for (int k = 0; k < 4; ++k) {
+        const double wr = (k < 2 ? 1.0 / 9.0 : 1.0 / 36.0) * r;
+        const double b = base + 4.5 * al[k] * al[k];
+        g[first[k]] = wr * (b + 3.0 * al[k]);
+        g[first[k] + 2] = wr * (b - 3.0 * al[k]);
+    }
+    if (in.pop_noise != 0.0) {
+        float h[9];
+        q9_draws(philox4x32_10(site, 0u, 0u, 2u, a.key0, a.key1), h);
+        for (int i = 0; i < 9; ++i)
+            g[i] += in.pop_noise * (2.0 * (((double)h[i] + 0.5) * (1.0 / 16384.0)) - 1.0);
+    }
+    const int64_t own = (int64_t)y * a.pitch + x;
+    for (int i = 0; i < 9; ++i)
+        Store<S>::store(dst, i * a.plane + own, (float)g[i], q9_wr(a, i));
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_q9_add_density(typename Store<S>::T *__restrict__ buf, StepArgs a,
+                                                        float add)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= a.nx)
+        return;
+    const int64_t own = (int64_t)y * a.pitch + x;
+    for (int i = 0; i < 9; ++i) {
+        const float wr = q9_wr(a, i);
+        const float v = Store<S>::load(buf, i * a.plane + own, wr);
+        Store<S>::store(buf, i * a.plane + own, v + add, wr);
+    }
+}
+
+hipError_t launch_init_q9(const lbm_params &p, const lbm_init &in, const StepArgs &a, void *dst, hipStream_t s)
+{
+    Q9InitArgs ia{in.mode, p.model, in.rho_mean, in.rho_spread, in.angle_std, in.u_mag, in.pop_noise, p.A, p.B};
+    dim3 blk(256), grd((p.nx + 255) / 256, p.ny);
+    switch (p.storage) {
+    case kF32: hipLaunchKernelGGL(k_q9_init<kF32>, grd, blk, 0, s, (float *)dst, a, ia); break;
+    case kBf16Dev: hipLaunchKernelGGL(k_q9_init<kBf16Dev>, grd, blk, 0, s, (uint16_t *)dst, a, ia); break;
+    case kF16Dev: hipLaunchKernelGGL(k_q9_init<kF16Dev>, grd, blk, 0, s, (_Float16 *)dst, a, ia); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_add_density_q9(const lbm_params &p, const StepArgs &a, void *buf, double drho, hipStream_t s)
+{
+    const float add = (float)(drho / 9.0);
+    dim3 blk(256), grd((p.nx + 255) / 256, p.ny);
+    switch (p.storage) {
+    case kF32: hipLaunchKernelGGL(k_q9_add_density<kF32>, grd, blk, 0, s, (float *)buf, a, add); break;
+    case kBf16Dev:
+        hipLaunchKernelGGL(k_q9_add_density<kBf16Dev>, grd, blk, 0, s, (uint16_t *)buf, a, add);
+        break;
+    case kF16Dev:
+        hipLaunchKernelGGL(k_q9_add_density<kF16Dev>, grd, blk, 0, s, (_Float16 *)buf, a, add);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lbm

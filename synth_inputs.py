@@ -76,6 +76,26 @@ def cil_4096(n=4096, rho_mean=0.74):
                           u_mag=-1.0, pop_noise=0.0))
 
 
+def q9_cil_4096(n=4096, rho_mean=0.74, mode=2):
+    """Square-lattice (D2Q9) CIL run, 4096 x 4096: the CIL parameters and
+    the start of cil_1024 (lambda = 4 of A = 2, B = 0.3, tau = 1, sigma =
+    1/70; Gaussian polarisation noise, std 0.05, about +x); mode=1 gives the
+    disordered start (uniform directions) instead."""
+    return dict(nx=n, ny=n, model=CIL, tau=1.0, sigma=4.0 / 70.0, A=0.125, B=0.3, C=0.0,
+                rho_star=1.0, u_max=1.0, seed=seed_for(5),
+                init=dict(mode=int(mode), rho_mean=float(rho_mean), rho_spread=0.1, angle_std=0.05,
+                          u_mag=-1.0, pop_noise=0.0))
+
+
+def q9_mips_4096(n=4096):
+    """Square-lattice (D2Q9) MIPS run, 4096 x 4096: the parameters of
+    mips_small (lambda = 8 of tau = 2, C = 50, rho* = 0.2, U_max = 0.3,
+    sigma = 1/70, mean density 0.125)."""
+    return dict(nx=n, ny=n, model=MIPS, tau=2.0, sigma=8.0 / 70.0, A=0.0, B=0.0, C=6.25,
+                rho_star=1.6, u_max=0.3, seed=seed_for(6),
+                init=dict(mode=1, rho_mean=1.0, rho_spread=0.0, angle_std=0.0, u_mag=0.1, pop_noise=1e-3))
+
+
 BATCH_SIDES = (128, 192, 256, 384, 512)
 
 

@@ -52,6 +52,7 @@ def _create(L, p, pitch=None, a=1, b=2, init=None):
     ("ny", 63, "even"), ("nx", 1, ">= 2"), ("ny", 0, ">= 2"), ("tau", 0.5, "tau"),
     ("tau", float("nan"), "tau"), ("sigma", -0.1, "sigma"), ("sigma", float("inf"), "sigma"),
     ("A", -1.0, "A, B"), ("B", float("nan"), "A, B"), ("model", 7, "model"), ("storage", 9, "storage"),
+    ("lattice", 2, "lattice"), ("lattice", -1, "lattice"),
 ])
 def test_create_rejects_invalid_parameters(field, value, msg):
     import paper_1902_00530_amd as L
@@ -75,6 +76,33 @@ def test_create_rejects_bad_buffers_and_pitch():
     bad_init = L.make_init(mode=9)
     assert L._lib.lbm_create(ctypes.byref(p), ctypes.c_void_p(1), ctypes.c_void_p(2), 64, ctypes.byref(bad_init),
                              None, ctypes.byref(ctypes.c_void_p())) == L.LBM_EINVAL
+
+
+def test_square_lattice_validation():
+    """D2Q9 takes odd ny (its checks pass and the call reaches the device: a
+    HIP error without a GPU, a context with one), rejects planes of 2^32
+    bytes or more, and is refused by batched sweeps and coarse fields."""
+    import paper_1902_00530_amd as L
+
+    def passes_validation(p):
+        rc, ctx = _create(L, p)  # no init: nothing is launched on the buffers
+        if rc == L.LBM_OK:
+            L._lib.lbm_destroy(ctx)
+        return rc in (L.LBM_OK, L.LBM_EHIP)
+
+    assert passes_validation(L.make_params(64, 63, L.LBM_CIL, A=0.1, B=0.3, lattice=L.LBM_D2Q9))
+    p7 = L.make_params(64, 63, L.LBM_CIL, A=0.1, B=0.3)
+    assert _create(L, p7)[0] == L.LBM_EINVAL
+    big = L.make_params(32768, 32768, L.LBM_CIL, lattice=L.LBM_D2Q9)
+    assert _create(L, big)[0] == L.LBM_EUNSUPPORTED and "2^32" in L.lbm_last_error()
+    assert passes_validation(L.make_params(32768, 32768, L.LBM_CIL, lattice=L.LBM_D2Q9, storage=L.LBM_BF16_DEV,
+                                           rho_ref=1.0))
+    q9 = L.make_params(128, 128, L.LBM_CIL, tau=1.0, sigma=0.05, A=0.1, B=0.3, lattice=L.LBM_D2Q9)
+    assert _sweep(L, [q9]) == L.LBM_EUNSUPPORTED and "D2Q7" in L.lbm_last_error()
+    assert L._lib.lbm_coarsen(ctypes.byref(q9), ctypes.c_void_p(16), 4, ctypes.c_void_p(32), None) == \
+        L.LBM_EUNSUPPORTED
+    assert L._lib.lbm_lift(ctypes.byref(q9), ctypes.c_void_p(16), 4, ctypes.c_void_p(32), None) == \
+        L.LBM_EUNSUPPORTED
 
 
 def test_null_context_is_a_state_error():
