@@ -15,9 +15,10 @@ roofline of the dominant kernel (the two-step kernel against the VALU issue
 peak, with its HBM bytes beside it; a one-step kernel against the 8 TB/s HBM3E
 peak at 56 B per site-update in FP32, 28 B in the 16-bit deviation
 storages), variants (one step per launch, per-lattice launches, 4096^2 in
-FP32 / BF16 / FP16, a 256-lattice batched phase sweep against the same
-lattices run one by one, the learned surrogate) and the FP64 oracle timed on
-the host cores.
+FP32 / BF16 / FP16, MIPS, the square-lattice (D2Q9) variant at 72 B per
+site-update, a 256-lattice batched phase sweep against the same lattices run
+one by one, the learned surrogate, the paper's measurement protocol) and the
+FP64 oracle timed on the host cores.
 """
 import argparse
 import hashlib
@@ -90,23 +91,23 @@ def cpu_baseline(steps):
             "sample": f"one 1024x1024 CIL lattice (mean density 1.0) for {steps} steps, FP64, single thread"}
 
 
-def gparams(L, c, storage=0, rho_ref=0.0):
+def gparams(L, c, storage=0, rho_ref=0.0, lattice=0):
     return L.make_params(c["nx"], c["ny"], c["model"], c["tau"], c["sigma"], c["A"], c["B"], c["C"], c["rho_star"],
-                         c["u_max"], c["seed"], storage=storage, rho_ref=rho_ref)
+                         c["u_max"], c["seed"], storage=storage, rho_ref=rho_ref, lattice=lattice)
 
 
-def make_lattices(L, cfgs, storage=0):
+def make_lattices(L, cfgs, storage=0, lattice=0):
     lats = []
     for c in cfgs:
         c = dict(c)
         ini = c.pop("init")
-        lats.append(L.Lattice(gparams(L, c, storage, ini["rho_mean"]), init=L.make_init(**ini)))
+        lats.append(L.Lattice(gparams(L, c, storage, ini["rho_mean"], lattice), init=L.make_init(**ini)))
     return lats
 
 
-def time_single(L, torch, cfgs, steps, warmup, storage=0):
+def time_single(L, torch, cfgs, steps, warmup, storage=0, lattice=0):
     """Each lattice stepped by lbm_step (one launch per lattice per step)."""
-    lats = make_lattices(L, cfgs, storage)
+    lats = make_lattices(L, cfgs, storage, lattice)
     for lat in lats:
         lat.step(warmup)
     torch.cuda.synchronize()
@@ -231,11 +232,14 @@ def roofline_two_step(sites, per_launch_s, kernel, rows):
     return r
 
 
-def roofline(storage, sites_per_launch, per_launch_s, kernel):
-    achieved = BYTES_PER_SITE[storage] * sites_per_launch / per_launch_s / 1e9
+def roofline(storage, sites_per_launch, per_launch_s, kernel, q=7):
+    """HBM roofline of a one-step kernel: each site's q populations read once
+    and written once (q = 7 triangular, 9 square lattice)."""
+    per_site = BYTES_PER_SITE[storage] * q // 7
+    achieved = per_site * sites_per_launch / per_launch_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": kernel,
-            "bytes_per_site": BYTES_PER_SITE[storage], "avg_launch_us": round(per_launch_s * 1e6, 3)}
+            "bytes_per_site": per_site, "avg_launch_us": round(per_launch_s * 1e6, 3)}
 
 
 def main():
@@ -359,6 +363,25 @@ def main():
         rm = roofline(0, 4096 * 4096, msb / 1e3 / 100, "k_step_mips<F32,noisy>")
         var["mips4096_f32"] = {"MLUPS": round(4096 * 4096 * 100 / (msb / 1e3) / 1e6, 1), "GBps": rm["achieved"],
                                "frac_hbm": rm["frac"], "avg_launch_us": rm["avg_launch_us"]}
+        # the square lattice (D2Q9, 72 B per site-update in FP32): CIL in the
+        # three storages and MIPS at 4096^2, one launch per step
+        q9c = [SI.q9_cil_4096()]
+        q9f32 = None
+        for st, name in ((0, "f32"), (1, "bf16_dev"), (2, "f16_dev")):
+            msq, _ = time_single(L, torch, q9c, 200, 10, st, lattice=L.LBM_D2Q9)
+            per = msq / 1e3 / 200
+            r = roofline(st, nbig, per, f"k_q9_step_local<CIL,{name}>", q=9)
+            v = {"MLUPS": round(nbig / per / 1e6, 1), "GBps": r["achieved"], "frac_hbm": r["frac"],
+                 "avg_launch_us": r["avg_launch_us"], "bytes_per_site": r["bytes_per_site"]}
+            if st == 0:
+                q9f32 = per
+            else:
+                v["speedup_vs_f32"] = round(q9f32 / per, 3)
+            var["q9_cil4096_" + name] = v
+        msq, _ = time_single(L, torch, [SI.q9_mips_4096()], 100, 10, lattice=L.LBM_D2Q9)
+        rq = roofline(0, nbig, msq / 1e3 / 100, "k_q9_step_mips<F32,noisy>", q=9)
+        var["q9_mips4096_f32"] = {"MLUPS": round(nbig * 100 / (msq / 1e3) / 1e6, 1), "GBps": rq["achieved"],
+                                  "frac_hbm": rq["frac"], "avg_launch_us": rq["avg_launch_us"]}
         # FP32 at 4096^2 through the batched path (two steps per launch)
         ms2, _ = time_batch(L, torch, big, 200, 10)
         rows2 = time_batch.tile_rows
