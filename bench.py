@@ -45,7 +45,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="cil1024x5", choices=["cil1024x5", "cil4096"])
+    ap.add_argument("--workload", default="cil1024x5",
+                    choices=["cil1024x5", "cil4096", "q9_cil4096", "q9_mips4096"],
+                    help="q9_*: the square-lattice (D2Q9) variant, one launch per step")
     ap.add_argument("--storage", type=int, default=0, help="0 f32, 1 bf16 deviations, 2 fp16 deviations")
     ap.add_argument("--mode", default="batch", choices=["batch", "single"])
     ap.add_argument("--quick", action="store_true", help="headline measurement only (no variants)")
@@ -89,6 +91,25 @@ def cpu_baseline(steps):
     return {"value": round(cfg["nx"] * cfg["ny"] * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
             "kind": "oracle",
             "sample": f"one 1024x1024 CIL lattice (mean density 1.0) for {steps} steps, FP64, single thread"}
+
+
+def cpu_q9(steps):
+    """FP64 square-lattice (D2Q9) oracle, single thread, on a 1024 x 1024
+    lattice with the CIL parameters of the D2Q9 workload."""
+    import oracle as O
+    from oracle import q9
+    import synth_inputs as SI
+    cfg = SI.q9_cil_4096(n=1024)
+    ini = cfg.pop("init")
+    p = O.make_params(cfg["nx"], cfg["ny"], cfg["model"], cfg["tau"], cfg["sigma"], cfg["A"], cfg["B"], cfg["C"],
+                      cfg["rho_star"], cfg["u_max"], cfg["seed"])
+    f = q9.initialise(p, **ini)
+    t0 = time.perf_counter()
+    q9.run(p, f, steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(cfg["nx"] * cfg["ny"] * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"one 1024x1024 D2Q9 CIL lattice (mean density 0.74) for {steps} steps, FP64, single thread"}
 
 
 def gparams(L, c, storage=0, rho_ref=0.0, lattice=0):
@@ -186,19 +207,21 @@ def copy_probe(torch, copies):
 # the sources the batched step kernels are built from (their bodies, the
 # parameters the host prepares for them, and the launch code)
 KERNEL_SOURCES = ("batch.hip", "capi.hip", "device.h", "internal.h")
+# sources of the square-lattice (D2Q9) step kernels
+Q9_SOURCES = ("q9.hip", "device_q9.h", "device.h", "capi.hip", "internal.h")
 
 
-def source_fingerprint():
-    """sha256 over the batched step kernels' sources (names and contents)."""
+def source_fingerprint(files=KERNEL_SOURCES):
+    """sha256 over a kernel's sources (names and contents)."""
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in files:
         h.update(name.encode())
         with open(os.path.join(ROOT, "paper_1902_00530_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(name):
+def measured_traffic(name, files=KERNEL_SOURCES):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the kernel sources as they are now (else None)."""
     path = os.path.join(ROOT, "profiles", name)
@@ -207,9 +230,20 @@ def measured_traffic(name):
             c = json.load(fh)
     except (OSError, ValueError):
         return None
-    if c.get("source_sha256") != source_fingerprint():
+    if c.get("source_sha256") != source_fingerprint(files):
         return None
     return c
+
+
+def attach_traffic(r, name, files, sites, per_launch_s):
+    """Fill roofline r's traffic from a committed counter summary of the same
+    kernel sources and lattice size."""
+    c = measured_traffic(name, files)
+    if c is not None and c.get("sites") == sites:
+        r["traffic"] = round(c["traffic_bytes_per_launch"] / per_launch_s / 1e9, 1)
+        r["traffic_bytes_per_launch"] = c["traffic_bytes_per_launch"]
+        r["traffic_vs_algorithmic"] = round(c["traffic_bytes_per_launch"] / c["algorithmic_bytes_per_launch"], 4)
+    return r
 
 
 def roofline_two_step(sites, per_launch_s, kernel, rows):
@@ -257,14 +291,21 @@ def main():
     if args.copy_probe:
         print(json.dumps(copy_probe(torch, args.steps)), flush=True)
         return
+    lattice, q = 0, 7
     if args.workload == "cil1024x5":
         cfgs = [SI.cil_1024(r, l) for l, r in enumerate(SI.CIL_DENSITIES)]
         wname = "CIL 5 x 1024x1024 periodic D2Q7, mean density 0.5..1.5 (x4 scaled), sigma 4/70, tau 1"
-    else:
+    elif args.workload == "cil4096":
         cfgs = [SI.cil_4096()]
         wname = "CIL 4096x4096 periodic D2Q7, mean density 0.74 (x4 scaled), sigma 4/70, tau 1"
+    elif args.workload == "q9_cil4096":
+        cfgs, lattice, q = [SI.q9_cil_4096()], L.LBM_D2Q9, 9
+        wname = "CIL 4096x4096 periodic D2Q9, mean density 0.74 (x4 scaled), sigma 4/70, tau 1"
+    else:
+        cfgs, lattice, q = [SI.q9_mips_4096()], L.LBM_D2Q9, 9
+        wname = "MIPS 4096x4096 periodic D2Q9, mean density 1.0 (x8 scaled), sigma 8/70, tau 2"
     sites = sum(c["nx"] * c["ny"] for c in cfgs)
-    mode = args.mode if args.storage == 0 else "single"
+    mode = args.mode if args.storage == 0 and lattice == 0 else "single"
 
     t_wall = time.perf_counter()
     rows = 0
@@ -283,13 +324,18 @@ def main():
             tile = {1: "256x1", 2: "128x2", 4: "64x4"}.get(rows, "?")
             kernel = f"k_batch_step<CIL,unit-tau,noisy>, tile {tile} (+1 FP64 sample at the end)"
     else:
-        ms, obs = time_single(L, torch, cfgs, args.steps, args.warmup, args.storage)
-        launches, kernel = args.steps * len(cfgs), "k_step_local<CIL,F32,unit-tau,noisy>"
+        ms, obs = time_single(L, torch, cfgs, args.steps, args.warmup, args.storage, lattice)
+        st = {0: "F32", 1: "BF16dev", 2: "F16dev"}[args.storage]
+        launches = args.steps * len(cfgs)
+        kernel = {"q9_cil4096": f"k_q9_step_local<CIL,{st},unit-tau,noisy>",
+                  "q9_mips4096": f"k_q9_step_mips<{st},noisy>"}.get(args.workload,
+                                                                     f"k_step_local<CIL,{st},unit-tau,noisy>")
     wall = time.perf_counter() - t_wall
     per_launch = ms / 1e3 / launches
     mlups = sites * args.steps / (ms / 1e3) / 1e6
     line = {
-        "metric": "MLUPS of the fused CIL step (FP32) and % of HBM peak",
+        "metric": ("MLUPS of the fused CIL step (FP32) and % of HBM peak" if lattice == 0 else
+                   f"MLUPS of the fused D2Q9 {'MIPS' if args.workload == 'q9_mips4096' else 'CIL'} step"),
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -304,10 +350,13 @@ def main():
         "config": {"workload": wname, "lattices": len(cfgs), "sites": sites, "storage": args.storage,
                    "mode": mode},
         "roofline": (roofline_two_step(sites, per_launch, kernel, rows) if rows >= 8 else
-                     roofline(args.storage, sites / (launches / args.steps), per_launch, kernel)),
+                     roofline(args.storage, sites / (launches / args.steps), per_launch, kernel, q)),
         "phi": [round(o["phi"], 6) for o in obs],
         "wall_s": round(wall, 3),
     }
+
+    if args.workload == "q9_cil4096" and args.storage == 0:
+        attach_traffic(line["roofline"], "counters_k_q9_step_local_cil_4096.json", Q9_SOURCES, sites, per_launch)
 
     if mode == "batch" and args.workload == "cil1024x5" and args.storage == 0 and rows < 8:
         c = measured_traffic(f"counters_k_batch_step_{rows}_cil_5x1024.json")
@@ -373,6 +422,11 @@ def main():
             r = roofline(st, nbig, per, f"k_q9_step_local<CIL,{name}>", q=9)
             v = {"MLUPS": round(nbig / per / 1e6, 1), "GBps": r["achieved"], "frac_hbm": r["frac"],
                  "avg_launch_us": r["avg_launch_us"], "bytes_per_site": r["bytes_per_site"]}
+            if st == 0:
+                attach_traffic(r, "counters_k_q9_step_local_cil_4096.json", Q9_SOURCES, nbig, per)
+                if r["traffic"] is not None:
+                    v["traffic_GBps"] = r["traffic"]
+                    v["traffic_vs_algorithmic"] = r["traffic_vs_algorithmic"]
             if st == 0:
                 q9f32 = per
             else:
@@ -443,9 +497,10 @@ def main():
             "regimes_by_A": {str(a): "".join(code[x] for x in row) for a, row in zip(A_vals, pd["regime"])}}
         line["variants"] = var
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_steps)
-        if not args.quick:
+        line["cpu_baseline"] = cpu_q9(args.cpu_steps) if lattice else cpu_baseline(args.cpu_steps)
+        if not args.quick and not lattice:
             line["cpu_baseline"]["mips64_1000_steps"] = cpu_mips64()
+            line["cpu_baseline"]["q9_cil1024"] = cpu_q9(10)
     print(json.dumps(line), flush=True)
 
 
