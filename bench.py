@@ -279,7 +279,7 @@ def roofline(storage, sites_per_launch, per_launch_s, kernel, q=7):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "this library runs on one GPU only; multi-GPU runs are not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch

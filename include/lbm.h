@@ -84,7 +84,7 @@ extern "C" {
 #define LBM_EINVAL (-1)       /* invalid argument (sizes, parameters, null pointers) */
 #define LBM_EHIP (-2)         /* HIP runtime error; message kept */
 #define LBM_ENONFINITE (-3)   /* a reduction saw a NaN or infinite population */
-#define LBM_EUNSUPPORTED (-4) /* valid request this build does not implement */
+#define LBM_EUNSUPPORTED (-4) /* valid request the library does not implement */
 #define LBM_ESTATE (-5)       /* call out of order (e.g. destroyed context) */
 
 /* Models: how u* is computed. */

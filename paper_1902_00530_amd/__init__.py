@@ -72,7 +72,7 @@ class LbmError(RuntimeError):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() (hipcc, gfx950)")
+    raise ImportError(f"{LIB_PATH} is not built: run python paper_1902_00530_amd/build.py (hipcc, gfx950)")
 
 _lib = ctypes.CDLL(LIB_PATH)
 _vp = ctypes.c_void_p
