@@ -208,7 +208,9 @@ typedef struct lbm_sweep_opts {
     int32_t tile_rows;    /* work tile: 1, 2, 4 = 256x1, 128x2, 64x4 sites, one step per
                              launch; 8, 16 = 64x8, 64x16 sites, two steps per launch
                              (the second from LDS); 0 = tuned (every shape timed on the
-                             batch itself, cached per batch signature) */
+                             batch itself, cached per batch signature).  MIPS batches
+                             take 0 or 16: 64x16 tiles, one step per launch, neighbour
+                             densities in LDS */
     int32_t use_graph;    /* 0: launch every kernel directly; 1: run each sample period
                              as captured HIP graphs of at most 1024 steps, kept (16 most
                              recent) and replayed by later calls with the same batch,
@@ -226,12 +228,12 @@ size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samp
 
 /* Work-tile rows (1, 2, 4, 8 or 16, as in lbm_sweep_opts.tile_rows) the
  * tuning chose for a batch with these lattices' sizes, model and step
- * variant, 0 if not tuned yet in this process; negative on invalid
- * arguments. */
+ * variant (MIPS: 16 once such a batch has run), 0 if not tuned yet in this
+ * process; negative on invalid arguments. */
 int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n);
 
 /* Run a batch.  ps[n]: per-lattice parameters; every lattice uses the D2Q7
- * lattice, F32 storage, the same model (CIL or passive), and agrees on
+ * lattice, F32 storage, the same model (CIL, MIPS or passive), and agrees on
  * tau == 1 and on
  * sigma == 0; nx*ny*7 < 2^30, ny <= 32760.  bufs[2n]: caller-owned device
  * buffers [7][ny][nx], lattice l's state in bufs[2l] and bufs[2l+1] free.
@@ -244,7 +246,7 @@ int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n);
  * lbm_step on its own.  Afterwards lattice l's state is in
  * bufs[2l + (n_steps & 1)].  Synchronises the stream at the end.  Errors:
  * LBM_EINVAL for the conditions above, LBM_EUNSUPPORTED for other storages or
- * MIPS, LBM_ENONFINITE if a sample saw a non-finite population. */
+ * lattices, LBM_ENONFINITE if a sample saw a non-finite population. */
 int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o, void *const *bufs, void *ws,
                         size_t ws_bytes, void *stream, lbm_obs *out);
 

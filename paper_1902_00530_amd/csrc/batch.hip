@@ -109,6 +109,27 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchTile *__restrict_
         BufIO<float>::store(dst, own, i * plane, f[i]);
 }
 
+// MIPS over a list of 64 x 16 tiles (the tile body of the single-lattice
+// MIPS kernel, mips_tile_step), one step per launch.
+template <int F>
+__global__ __launch_bounds__(256) void k_batch_step_mips(const BatchTile *__restrict__ tiles,
+                                                         const LatDesc *__restrict__ lats,
+                                                         const Ctrl *__restrict__ ctrl, int step_off, int launch_off)
+{
+    __shared__ float srho[kMipsTileLds];
+    const BatchTile tl = tiles[blockIdx.x];
+    const LatDesc &L = lats[tl.lat];
+    const StepArgs a = L.a;
+    const int64_t t = ctrl->t0 + step_off;
+    const int par = (int)((ctrl->k0 + launch_off) & 1);
+    const int x0 = tl.tx * 64, y0 = tl.ty * kMipsRows;
+    if (x0 >= a.nx || y0 >= a.ny)  // whole-block exit, before the barrier
+        return;
+    const uint32_t bytes = 28u * (uint32_t)a.plane;
+    mips_tile_step<kF32, F>(buffer_rsrc(L.buf[par], bytes), buffer_rsrc(L.buf[par ^ 1], bytes), a, x0, y0,
+                            (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32), srho);
+}
+
 // Step t+1 on the widened tile as the second step reads it, in local
 // coordinates (lx, ly) = (x - x0 + 1, y - y0 + 1): population 0 only at the
 // tile's own sites (TY rows of 64), 1 and 4 on the tile's rows (ly 1..TY),
@@ -458,13 +479,16 @@ struct Layout {
     int64_t n_tiles1, n_tiles2, n_mtiles, colpart_n, colmean_n;
 };
 
-// Work-tile shapes: sites across, rows, steps per launch.
+// Work-tile shapes: sites across, rows, steps per launch.  Shapes 0..4 serve
+// the local models (CIL, passive) and are tuned; shape 5 is the MIPS tile.
 struct Shape {
     int tx, ty, steps;
 };
-constexpr int kNumShapes = 5;
-constexpr int kNumSingle = 3;  // shapes 0..2 take one step per launch
-static const Shape kShapes[kNumShapes] = {{256, 1, 1}, {128, 2, 1}, {64, 4, 1}, {64, 8, 2}, {64, 16, 2}};
+constexpr int kNumShapes = 6;
+constexpr int kNumTuned = 5;
+constexpr int kMipsShape = 5;
+static const Shape kShapes[kNumShapes] = {{256, 1, 1}, {128, 2, 1}, {64, 4, 1},
+                                          {64, 8, 2},  {64, 16, 2}, {64, kMipsRows, 1}};
 constexpr int64_t kChunk = 1024;  // steps per captured graph, at most
 
 static int64_t count_tiles(const lbm_params *ps, int n, int tx, int ty)
@@ -484,7 +508,7 @@ static Layout layout(const lbm_params *ps, int n, int64_t n_samples)
     L.n_tiles1 = 0;
     L.n_tiles2 = 0;
     for (int k = 0; k < kNumShapes; ++k) {
-        int64_t &m = k < kNumSingle ? L.n_tiles1 : L.n_tiles2;
+        int64_t &m = kShapes[k].steps == 1 ? L.n_tiles1 : L.n_tiles2;
         m = std::max(m, count_tiles(ps, n, kShapes[k].tx, kShapes[k].ty));
     }
     L.n_mtiles = 0;
@@ -570,10 +594,28 @@ static hipError_t launch_batch_step_m(int flags, int shape, int64_t ntiles, cons
     }
 }
 
+template <int F>
+static hipError_t launch_batch_mips_f(int64_t ntiles, const BatchTile *tiles, const LatDesc *lats, const Ctrl *ctrl,
+                                      int step_off, int launch_off, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_batch_step_mips<F>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl, step_off,
+                       launch_off);
+    return hipGetLastError();
+}
+
 static hipError_t launch_batch_step(int model, int flags, int shape, int64_t ntiles, const BatchTile *tiles,
                                     const LatDesc *lats, const Ctrl *ctrl, int step_off, int launch_off,
                                     hipStream_t s)
 {
+    if (model == kMips) {
+        switch (flags) {
+        case 0: return launch_batch_mips_f<0>(ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+        case kUnitTau: return launch_batch_mips_f<kUnitTau>(ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+        case kNoisy: return launch_batch_mips_f<kNoisy>(ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+        default:
+            return launch_batch_mips_f<kUnitTau | kNoisy>(ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+        }
+    }
     if (model == kCil)
         return launch_batch_step_m<kCil>(flags, shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
     return launch_batch_step_m<kPassive>(flags, shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
@@ -618,7 +660,7 @@ struct GraphExec {
     ~GraphExec()
     {
         if (exec)
-            hipGraphExecDestroy(exec);
+            (void)hipGraphExecDestroy(exec);
     }
 };
 using GraphPtr = std::shared_ptr<GraphExec>;
@@ -696,8 +738,6 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
             return fail(LBM_EUNSUPPORTED, "batched sweeps take the D2Q7 lattice");
         if (ps[l].storage != LBM_F32)
             return fail(LBM_EUNSUPPORTED, "batched sweeps take F32 storage");
-        if (ps[l].model == LBM_MIPS)
-            return fail(LBM_EUNSUPPORTED, "batched sweeps take the local models (CIL, passive)");
         if (ps[l].model != ps[0].model)
             return fail(LBM_EINVAL, "all lattices of a batch must use the same model");
         if ((uint64_t)ps[l].nx * ps[l].ny * 7ull >= (1ull << 30))
@@ -717,6 +757,35 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     const Layout Ly = layout(ps, n, n_samples);
     if (ws_bytes < Ly.total)
         return fail(LBM_EINVAL, "workspace smaller than lbm_sweep_workspace_bytes()");
+    // tile shape: caller's choice (tile_rows 1, 2, 4: 256x1, 128x2, 64x4
+    // sites, one step per launch; 8, 16: 64x8, 64x16 sites, two steps per
+    // launch; MIPS always 64x16, one step per launch), else the tuned one for
+    // this signature, else tuned below: every tuning launch reads the state
+    // in the first buffer of each lattice and writes the second (free until
+    // the sweep starts), so the state is unchanged.
+    int shape = -1;
+    const bool mips = ps[0].model == LBM_MIPS;
+    for (int k = 0; k < kNumTuned; ++k)
+        if (o->tile_rows == kShapes[k].ty)
+            shape = k;
+    if (mips) {
+        if (o->tile_rows != 0 && o->tile_rows != kMipsRows)
+            return fail(LBM_EINVAL, "MIPS batches take tile_rows 0 or 16 (64x16 tiles, one step per launch)");
+        shape = kMipsShape;
+    } else if (shape < 0 && o->tile_rows != 0) {
+        return fail(LBM_EINVAL, "tile_rows must be 0, 1, 2, 4, 8 or 16");
+    }
+    const std::string sig = signature(ps, n, flags);
+    if (mips) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[sig] = kMipsShape;
+    }
+    if (shape < 0) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(sig);
+        if (it != g_tuned.end())
+            shape = it->second;
+    }
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
     LatDesc *d_lat = (LatDesc *)(w + Ly.lat);
@@ -754,25 +823,6 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     LBM_HIP_TRY(hipMemcpyAsync(d_lat, lat.data(), sizeof(LatDesc) * n, hipMemcpyHostToDevice, s));
     LBM_HIP_TRY(hipMemcpyAsync(d_mt, mt.data(), sizeof(MomTile) * mt.size(), hipMemcpyHostToDevice, s));
 
-    // tile shape: caller's choice (tile_rows 1, 2, 4: 256x1, 128x2, 64x4
-    // sites, one step per launch; 8, 16: 64x8, 64x16 sites, two steps per
-    // launch), else the tuned one for this signature, else tune now: every
-    // tuning launch reads the state in the first buffer of each lattice and
-    // writes the second (free until the sweep starts), so the state is
-    // unchanged.
-    int shape = -1;
-    for (int k = 0; k < kNumShapes; ++k)
-        if (o->tile_rows == kShapes[k].ty)
-            shape = k;
-    if (shape < 0 && o->tile_rows != 0)
-        return fail(LBM_EINVAL, "tile_rows must be 0, 1, 2, 4, 8 or 16");
-    const std::string sig = signature(ps, n, flags);
-    if (shape < 0) {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tuned.find(sig);
-        if (it != g_tuned.end())
-            shape = it->second;
-    }
     BatchTile *d_tiles1 = d_tiles, *d_tiles2 = d_tiles + Ly.n_tiles1;
     hipError_t up_err = hipSuccess;
     // host copies of the uploaded lists stay alive until the stream is
@@ -781,7 +831,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     auto upload = [&](int k) -> std::pair<BatchTile *, int64_t> {
         host_lists.push_back(build_tiles(ps, n, kShapes[k].tx, kShapes[k].ty));
         const std::vector<BatchTile> &v = host_lists.back();
-        BatchTile *d = k < kNumSingle ? d_tiles1 : d_tiles2;
+        BatchTile *d = kShapes[k].steps == 1 ? d_tiles1 : d_tiles2;
         up_err = hipMemcpyAsync(d, v.data(), sizeof(BatchTile) * v.size(), hipMemcpyHostToDevice, s);
         return {up_err == hipSuccess ? d : nullptr, (int64_t)v.size()};
     };
@@ -794,7 +844,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         // each shape: ten launches captured in a graph (as the sweep runs
         // them), replayed once to warm up and three times timed; the least
         // time per step wins
-        for (int k = 0; k < kNumShapes; ++k) {
+        for (int k = 0; k < kNumTuned; ++k) {
             auto tl = upload(k);
             if (!tl.first)
                 return hip_fail(up_err, "tile list upload");

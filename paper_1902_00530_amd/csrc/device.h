@@ -418,4 +418,109 @@ struct BufIO<_Float16> {
     }
 };
 
+// ---------------------------------------------------------------------------
+// MIPS step of one 64 x 16 tile at (x0, y0) (u* needs the streamed density of
+// the six neighbours).  256 threads: wave w owns rows w, w+4, w+8, w+12, one
+// column per lane.  rho of the tile and of a one-site ring (the rows above
+// and below and the two edge columns: 164 sites, taken by waves 0-2) is
+// staged in LDS (srho, kMipsTileLds floats).  The tile's own populations stay
+// in registers from the density pass to the collision; every load of a wave
+// is issued before any of its sites is computed.  On tiles whose sources do
+// not wrap, a row's seven loads share one vector offset (the lane) and
+// wave-uniform scalar offsets.  Every LDS slot holds rho at its periodically
+// wrapped lattice site, so ragged tiles and lattices narrower than a tile need
+// no special case.  rs / rd cover the source and destination population
+// buffers ([7][ny][pitch], 32-bit element offsets).  The single-lattice and
+// the batched MIPS kernels both run this body.
+// ---------------------------------------------------------------------------
+constexpr int kMipsRows = 16;
+constexpr int kMipsTileLds = (kMipsRows + 2) * 66;
+
+template <int S, int F>
+__device__ __forceinline__ void mips_tile_step(__amdgpu_buffer_rsrc_t rs, __amdgpu_buffer_rsrc_t rd,
+                                               const StepArgs &a, int x0, int y0, uint32_t t_lo, uint32_t t_hi,
+                                               float *srho)
+{
+    using T = typename Store<S>::T;
+    constexpr int W = 66, H = kMipsRows + 2, RW = kMipsRows / 4;  // RW rows per wave
+    constexpr int kRing = 2 * W + 2 * kMipsRows;                  // 164
+    const uint32_t plane = (uint32_t)a.plane, P = (uint32_t)a.pitch, nx = (uint32_t)a.nx;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const bool interior = x0 >= 1 && x0 + 65 <= a.nx && y0 >= 1 && y0 + kMipsRows + 1 <= a.ny;
+    // the seven streamed populations of site (x, y), periodically wrapped
+    auto load_wrapped = [&](float *g, int x, int y) {
+        const PullSources32 q = pull_sources32(a, wrap_coord(x, a.nx), wrap_coord(y, a.ny));
+#pragma unroll
+        for (int i = 0; i < 7; ++i)
+            g[i] = Store<S>::widen(BufIO<T>::load(rs, q.idx[i], i * plane), i == 0 ? a.wr0 : a.wr1);
+    };
+    float f[RW][7];
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        const int y = y0 + wv + 4 * k;
+        if (interior) {
+            const uint32_t p = (uint32_t)y & 1u;
+            const uint32_t c = (uint32_t)y * P + (uint32_t)x0;  // offset of (x0, y)
+            const uint32_t e[7] = {c, plane + c - 1u, 2u * plane + c - P - 1u + p, 3u * plane + c - P + p,
+                                   4u * plane + c + 1u, 5u * plane + c + P + p, 6u * plane + c + P - 1u + p};
+#pragma unroll
+            for (int i = 0; i < 7; ++i)
+                f[k][i] = Store<S>::widen(BufIO<T>::load(rs, lane, e[i]), i == 0 ? a.wr0 : a.wr1);
+        } else {
+            load_wrapped(f[k], x0 + lane, y);
+        }
+    }
+    const int re = wv * 64 + lane;  // this lane's ring site (waves 0-2)
+    if (re < kRing) {
+        int rlx, rly;
+        if (re < W) {
+            rlx = re;
+            rly = 0;
+        } else if (re < 2 * W) {
+            rlx = re - W;
+            rly = H - 1;
+        } else {
+            rlx = re < 2 * W + kMipsRows ? 0 : W - 1;
+            rly = 1 + (re - 2 * W) % kMipsRows;
+        }
+        float g[7];
+        load_wrapped(g, x0 - 1 + rlx, y0 - 1 + rly);
+        srho[rly * W + rlx] = g[0] + ((g[1] + g[4]) + ((g[2] + g[5]) + (g[3] + g[6])));
+    }
+    float rho[RW];
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        float jx, jy;
+        site_moments(f[k], rho[k], jx, jy);
+        srho[(wv + 4 * k + 1) * W + lane + 1] = rho[k];
+    }
+    __syncthreads();
+    // collisions; row r of the tile has parity r & 1 = wv & 1 (y0 is even)
+    const int p = wv & 1;
+    const int x = x0 + lane;
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        const int r = wv + 4 * k, y = y0 + r;
+        if (x >= a.nx || y >= a.ny)
+            continue;
+        const int cx = lane + 1, cy = r + 1;
+        float nb[7];
+        nb[0] = rho[k];
+        nb[1] = srho[cy * W + cx + 1];
+        nb[2] = srho[(cy + 1) * W + cx + p];
+        nb[3] = srho[(cy + 1) * W + cx - 1 + p];
+        nb[4] = srho[cy * W + cx - 1];
+        nb[5] = srho[(cy - 1) * W + cx - 1 + p];
+        nb[6] = srho[(cy - 1) * W + cx + p];
+        float ux, uy;
+        mips_ustar(a, rho[k], nb, ux, uy);
+        site_collide<F>(a, f[k], rho[k], ux, uy, (uint32_t)y * nx + (uint32_t)x, t_lo, t_hi);
+        const uint32_t own = (uint32_t)y * P + (uint32_t)x;
+#pragma unroll
+        for (int i = 0; i < 7; ++i)
+            BufIO<T>::store(rd, own, i * plane, Store<S>::narrow(f[k][i], i == 0 ? a.wr0 : a.wr1));
+    }
+}
+
 }  // namespace lbm

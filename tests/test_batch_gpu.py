@@ -206,3 +206,77 @@ def test_full_size_two_step_batch_matches_oracle(L, orc):
     # of a 1e-7 perturbation over the same steps (as for the one-step path)
     amp = _self_sensitivity(orc, po, f0, 4) / 1e-7
     assert rel_err(got, ref) < 2e-6 * max(amp, 1.0)
+
+
+# ---------------------------------------------------------------- MIPS batches
+
+def mips_batch():
+    """MIPS lattices (the 64^2 workload's parameters) of uneven sizes, some
+    narrower or shorter than the 64 x 16 tile, with their own seeds."""
+    sizes = [(2, 2), (40, 6), (66, 18), (128, 192), (200, 70), (130, 34)]
+    return [_cfg(SI.MIPS, nx, ny, tau=2.0, sigma=8 / 70, C=6.25, rho_star=1.6, u_max=0.3, seed=SI.seed_for(7, l))
+            for l, (nx, ny) in enumerate(sizes)]
+
+
+def mips_states(L, cfgs):
+    states = []
+    for l, c in enumerate(cfgs):
+        lat = L.Lattice(_gparams(L, c), init=L.make_init(mode=1, rho_mean=0.8 + 0.1 * l, rho_spread=0.1,
+                                                         u_mag=0.1, pop_noise=1e-3))
+        torch.cuda.synchronize()
+        states.append(lat.state.clone())
+        lat.close()
+    return states
+
+
+@pytest.mark.parametrize("use_graph,steps", [(1, 37), (0, 37), (1, 1100)])
+def test_mips_batch_member_equals_single_run(L, use_graph, steps):
+    """The batched MIPS kernel runs the single-lattice MIPS tile body: every
+    member equals its lbm_step run bit for bit (1100 steps cross a captured
+    chunk), and the tile shape reported for the batch is its 64 x 16 tile."""
+    cfgs = mips_batch()
+    states = mips_states(L, cfgs)
+    finals, samples = single_runs(L, cfgs, states, steps)
+    b = L.Batch([_gparams(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    out = b.run(steps, use_graph=use_graph)
+    torch.cuda.synchronize()
+    for l in range(len(cfgs)):
+        assert torch.equal(b.state(l), finals[l]), l
+        o, s = out[l][0], samples[l][0]
+        for k in ("M", "phi", "drho"):
+            assert abs(o[k] - s[k]) <= 1e-12 * max(1.0, abs(s[k])), (l, k)
+    assert L.lbm_sweep_tile_rows(b.params, b.n) == 16
+
+
+def test_mips_batch_samples_density_ramp_and_oracle(L, orc):
+    """Samples every 10 steps with the protocol's density change after each,
+    against single runs with lbm_add_density (bit for bit), and three steps
+    against the oracle."""
+    cfgs = mips_batch()[2:5]
+    states = mips_states(L, cfgs)
+    drho = [0.01, -0.02, 0.03]
+    b = L.Batch([_gparams(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    out = b.run(30, sample_every=10, drho=drho)
+    for l, c in enumerate(cfgs):
+        lat = L.Lattice(_gparams(L, c))
+        lat.set_state(states[l])
+        obs = []
+        for _ in range(3):
+            lat.step(10)
+            obs.append(lat.observables())
+            lat.add_density(drho[l])
+        assert torch.equal(b.state(l), lat.state), l
+        lat.close()
+        for o, s in zip(out[l], obs):
+            assert abs(o["M"] - s["M"]) <= 1e-12 * s["M"] and abs(o["drho"] - s["drho"]) <= 1e-12
+    b2 = L.Batch([_gparams(L, c) for c in cfgs[:2]])
+    for l in range(2):
+        b2.set_state(l, states[l])
+    b2.run(3)
+    for l, c in enumerate(cfgs[:2]):
+        ref = orc.run(_oparams(orc, c), states[l].double().cpu().numpy(), 3)
+        assert rel_err(b2.state(l).double().cpu().numpy(), ref) < 3e-6
