@@ -495,6 +495,24 @@ def main():
             "MLUPS": round(pd["lattices"] * 180 * 60 * pd["steps"] / tpd / 1e6, 1),
             "rho_from_to_step": [0.05, 0.40, 0.01],
             "regimes_by_A": {str(a): "".join(code[x] for x in row) for a, row in zip(A_vals, pd["regime"])}}
+        # the paper's MIPS noise ramp (90 x 30, its MIPS parameter table, sigma
+        # 1/70 -> 3/70 by 1/700), six mean densities x two runs in one batch;
+        # relaxation and sampling shortened (paper: 1e6 steps, 100 samples
+        # every 1e4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mr = P.mips_noise_ramp()
+        torch.cuda.synchronize()
+        tmr = time.perf_counter() - t0
+        var["protocol_mips_noise_ramp"] = {
+            "runs": mr["lattices"], "steps_per_run": mr["steps"], "seconds": round(tmr, 3),
+            "MLUPS": round(mr["lattices"] * 90 * 30 * mr["steps"] / tmr / 1e6, 1),
+            "sigma_from_to_step": [round(1 / 70, 6), round(3 / 70, 6), round(1 / 700, 6)],
+            "steps_per_sigma": {"relax": 50000, "samples": 50, "sample_every": 1000},
+            "regimes_by_rho": {str(r): "".join("P" if x == "PS" else "h" for x in row)
+                               for r, row in zip(mr["rho"], mr["regime"])},
+            "sigma_homogeneous_by_rho": {str(r): (round(x, 5) if x is not None else None)
+                                         for r, x in zip(mr["rho"], mr["sigma_homogeneous"])}}
         line["variants"] = var
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_q9(args.cpu_steps) if lattice else cpu_baseline(args.cpu_steps)

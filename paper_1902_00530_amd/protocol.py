@@ -23,7 +23,7 @@ import math
 
 import numpy as np
 
-from . import Batch, LBM_CIL, Lattice, make_init, make_params
+from . import Batch, LBM_CIL, LBM_MIPS, Lattice, make_init, make_params
 
 CIL_PHI_THRESHOLD = 0.024
 CIL_BANDING_THRESHOLD = 0.012
@@ -32,6 +32,9 @@ MIPS_BANDING_THRESHOLD = 0.0430
 
 # The paper's CIL runs: 180 x 60 sites, B = 0.3, tau = 1, sigma = 1/70.
 PAPER_CIL = dict(nx=180, ny=60, B=0.3, tau=1.0, sigma=1.0 / 70.0)
+# The paper's MIPS parameter table (tau, C, rho*, U_max); its phase-diagram
+# runs use 90 x 30 sites and raise sigma from 1/70 to 3/70 by 1/700.
+PAPER_MIPS = dict(tau=2.0, C=50.0, rho_star=0.2, u_max=0.3)
 
 
 def classify_cil(phi, banding, zeta, rho_mean, A, B, density_scale=1.0):
@@ -158,3 +161,58 @@ def phase_diagram(A_values, rho_lo=0.05, rho_hi=0.40, step=0.01, t_sample=10000,
         out["zeta"].append(zeta.tolist())
         out["regime"].append([classify_cil(phi[k], band[k], zeta[k], rho[k], A_values[a], B) for k in range(len(rho))])
     return out
+
+
+def mips_batch(rho_means, seeds, sigma=1.0 / 70.0, nx=90, ny=30):
+    """MIPS lattices with the paper's parameter table, one per (mean density,
+    seed): density uniform within +-10% of the mean, a random direction of
+    small speed (0.01), f = f^SS."""
+    params = [make_params(nx, ny, LBM_MIPS, sigma=sigma, seed=int(seeds[l]), **PAPER_MIPS)
+              for l in range(len(rho_means))]
+    b = Batch(params)
+    for l, p in enumerate(params):
+        lat = Lattice(p, init=make_init(mode=1, rho_mean=rho_means[l], rho_spread=0.1, u_mag=0.01))
+        b.set_state(l, lat.state)
+        lat.close()
+    return b
+
+
+def sigma_schedule(sigma_lo=1.0 / 70.0, sigma_hi=3.0 / 70.0, step=1.0 / 700.0):
+    """Noise strengths of the MIPS ramp, sigma_lo to sigma_hi inclusive."""
+    n = int(round((sigma_hi - sigma_lo) / step)) + 1
+    return [sigma_lo + k * step for k in range(n)]
+
+
+def mips_noise_ramp(rho_means=(0.06, 0.08, 0.10, 0.125, 0.15, 0.18), repeats=2, sigmas=None, init_steps=200000,
+                    relax_steps=50000, sample_every=1000, n_samples=50, seed_base=90000, nx=90, ny=30):
+    """The MIPS experiment of the paper (section "Simulation procedure for
+    results"): each run starts at sigma = sigma_0, relaxes, then for every
+    noise strength of the schedule relaxes relax_steps and takes n_samples
+    samples every sample_every steps before the noise rises.  All densities
+    and repeats run as one batch.  The paper relaxes 10^6 steps after each
+    rise and samples 100 times every 10^4 steps; the defaults here are
+    shorter.  Returns the noise strengths, the densities, the banding measure
+    per (density, sigma) averaged over samples and repeats, the regime
+    ('PS' / 'H') and, per density, the first sigma of the schedule at which it
+    is homogeneous."""
+    sigmas = sigma_schedule() if sigmas is None else list(sigmas)
+    rhos = [float(r) for r in rho_means for _ in range(repeats)]
+    b = mips_batch(rhos, [seed_base + l for l in range(len(rhos))], sigma=sigmas[0], nx=nx, ny=ny)
+    b.run(init_steps)
+    band = np.zeros((len(rho_means), len(sigmas)))
+    for k, sg in enumerate(sigmas):
+        for l in range(b.n):
+            b.params[l].sigma = sg
+        b.run(relax_steps)
+        out = b.run(sample_every * n_samples, sample_every=sample_every)
+        per_run = np.array([np.mean([o["drho"] for o in out[l]]) for l in range(b.n)])
+        band[:, k] = per_run.reshape(len(rho_means), repeats).mean(axis=1)
+    regime = [[classify_mips(v) for v in row] for row in band]
+    sigma_c = []
+    for row in regime:
+        hom = [sigmas[k] for k, r in enumerate(row) if r == "H"]
+        sigma_c.append(hom[0] if hom else None)
+    return {"sigma": sigmas, "rho": list(rho_means), "banding": band.tolist(), "regime": regime,
+            "sigma_homogeneous": sigma_c,
+            "steps": int(init_steps + len(sigmas) * (relax_steps + sample_every * n_samples)),
+            "lattices": b.n}

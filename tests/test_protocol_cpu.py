@@ -40,3 +40,14 @@ def test_hysteresis_schedule():
     # phase diagram: 0.05 .. 0.40 in steps of 0.01, one t_sample
     pd = P.ramp_schedule(0.05, 0.40, 0.01, lambda r: 10000)
     assert len(pd) == 1 and len(pd[0][1]) == 36
+
+
+def test_mips_noise_schedule():
+    """The MIPS ramp of the appendix "Simulation procedure for results":
+    sigma from 1/70 to 3/70 in steps of 1/700 (21 noise strengths)."""
+    from paper_1902_00530_amd import protocol as P
+    s = P.sigma_schedule()
+    assert len(s) == 21 and abs(s[0] - 1 / 70) < 1e-15 and abs(s[-1] - 3 / 70) < 1e-15
+    assert np.allclose(np.diff(s), 1 / 700, rtol=0, atol=1e-15)
+    assert P.classify_mips(0.0431) == "PS" and P.classify_mips(0.0430) == "H"
+    assert P.classify_mips(0.1, density_scale=8.0) == "H" and P.classify_mips(0.4, density_scale=8.0) == "PS"

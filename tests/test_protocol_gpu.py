@@ -125,3 +125,34 @@ def test_hysteresis_regimes_at_the_papers_snapshot_densities(L):
         band = np.mean([s[k]["drho"] for s in samples])
         zeta = np.mean([s[k]["zeta"] for s in samples])
         assert P.classify_cil(phi, band, zeta, rho[k], 2.0, 0.3) == regime, (r, phi, band, zeta)
+
+
+def test_mips_regimes_at_the_papers_snapshot_points(L):
+    """MIPS at the (density, noise) pairs of the paper's snapshot table, two
+    runs each on 90 x 30 sites, 10^5 steps from the random start and 20
+    samples every 10^3 steps: the regime of the mean banding measure.  A smoke
+    check of the paper's reported behaviour (stochastic runs, not a pin)."""
+    import os
+    from paper_1902_00530_amd import protocol as P
+    here = os.path.dirname(os.path.abspath(__file__))
+    want = [l.split() for l in open(os.path.join(here, "golden", "mips_snapshot_regimes.txt"))
+            if l.strip() and l[0] != "#"]
+    rhos = [float(r) for r, _, _ in want for _ in range(2)]
+    b = P.mips_batch(rhos, [7000 + l for l in range(len(rhos))])
+    for l, (_, s, _) in enumerate(w for w in want for _ in range(2)):
+        b.params[l].sigma = float(s)
+    b.run(100000)
+    out = b.run(20000, sample_every=1000)
+    for k, (r, s, regime) in enumerate(want):
+        band = np.mean([o["drho"] for l in (2 * k, 2 * k + 1) for o in out[l]])
+        assert P.classify_mips(band) == regime, (r, s, band)
+
+
+def test_mips_noise_ramp_driver(L):
+    """The MIPS ramp driver end to end at reduced length: phase separated at
+    sigma = 1/70, homogeneous at 3/70 for a density inside the binodal."""
+    from paper_1902_00530_amd import protocol as P
+    res = P.mips_noise_ramp(rho_means=(0.125,), repeats=2, sigmas=[1 / 70, 3 / 70], init_steps=100000,
+                            relax_steps=20000, sample_every=1000, n_samples=20)
+    assert res["regime"] == [["PS", "H"]] and res["sigma_homogeneous"] == [3 / 70]
+    assert res["steps"] == 100000 + 2 * (20000 + 20000) and res["lattices"] == 2
