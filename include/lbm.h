@@ -209,8 +209,8 @@ typedef struct lbm_sweep_opts {
                              launch; 8, 16 = 64x8, 64x16 sites, two steps per launch
                              (the second from LDS); 0 = tuned (every shape timed on the
                              batch itself, cached per batch signature).  MIPS batches
-                             take 0 or 16: 64x16 tiles, one step per launch, neighbour
-                             densities in LDS */
+                             take 0 (tuned), 4 or 16: 64x4 or 64x16 tiles, one step per
+                             launch, neighbour densities in LDS */
     int32_t use_graph;    /* 0: launch every kernel directly; 1: run each sample period
                              as captured HIP graphs of at most 1024 steps, kept (16 most
                              recent) and replayed by later calls with the same batch,
@@ -228,8 +228,8 @@ size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samp
 
 /* Work-tile rows (1, 2, 4, 8 or 16, as in lbm_sweep_opts.tile_rows) the
  * tuning chose for a batch with these lattices' sizes, model and step
- * variant (MIPS: 16 once such a batch has run), 0 if not tuned yet in this
- * process; negative on invalid arguments. */
+ * variant (MIPS: 4 or 16), 0 if not tuned yet in this process; negative on
+ * invalid arguments. */
 int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n);
 
 /* Run a batch.  ps[n]: per-lattice parameters; every lattice uses the D2Q7

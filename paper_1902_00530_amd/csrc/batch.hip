@@ -109,24 +109,24 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchTile *__restrict_
         BufIO<float>::store(dst, own, i * plane, f[i]);
 }
 
-// MIPS over a list of 64 x 16 tiles (the tile body of the single-lattice
+// MIPS over a list of 64 x ROWS tiles (the tile body of the single-lattice
 // MIPS kernel, mips_tile_step), one step per launch.
-template <int F>
+template <int F, int ROWS>
 __global__ __launch_bounds__(256) void k_batch_step_mips(const BatchTile *__restrict__ tiles,
                                                          const LatDesc *__restrict__ lats,
                                                          const Ctrl *__restrict__ ctrl, int step_off, int launch_off)
 {
-    __shared__ float srho[kMipsTileLds];
+    __shared__ float srho[mips_tile_lds(ROWS)];
     const BatchTile tl = tiles[blockIdx.x];
     const LatDesc &L = lats[tl.lat];
     const StepArgs a = L.a;
     const int64_t t = ctrl->t0 + step_off;
     const int par = (int)((ctrl->k0 + launch_off) & 1);
-    const int x0 = tl.tx * 64, y0 = tl.ty * kMipsRows;
+    const int x0 = tl.tx * 64, y0 = tl.ty * ROWS;
     if (x0 >= a.nx || y0 >= a.ny)  // whole-block exit, before the barrier
         return;
     const uint32_t bytes = 28u * (uint32_t)a.plane;
-    mips_tile_step<kF32, F>(buffer_rsrc(L.buf[par], bytes), buffer_rsrc(L.buf[par ^ 1], bytes), a, x0, y0,
+    mips_tile_step<kF32, F, ROWS>(buffer_rsrc(L.buf[par], bytes), buffer_rsrc(L.buf[par ^ 1], bytes), a, x0, y0,
                             (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32), srho);
 }
 
@@ -480,15 +480,16 @@ struct Layout {
 };
 
 // Work-tile shapes: sites across, rows, steps per launch.  Shapes 0..4 serve
-// the local models (CIL, passive) and are tuned; shape 5 is the MIPS tile.
+// the local models (CIL, passive), shapes 5 and 6 MIPS (64 x 16 and 64 x 4,
+// one step per launch); each model's shapes are tuned among themselves.
 struct Shape {
     int tx, ty, steps;
 };
-constexpr int kNumShapes = 6;
+constexpr int kNumShapes = 7;
 constexpr int kNumTuned = 5;
-constexpr int kMipsShape = 5;
-static const Shape kShapes[kNumShapes] = {{256, 1, 1}, {128, 2, 1}, {64, 4, 1},
-                                          {64, 8, 2},  {64, 16, 2}, {64, kMipsRows, 1}};
+constexpr int kMipsShape = 5, kMipsShape4 = 6;
+static const Shape kShapes[kNumShapes] = {{256, 1, 1}, {128, 2, 1}, {64, 4, 1}, {64, 8, 2},
+                                          {64, 16, 2}, {64, 16, 1}, {64, 4, 1}};
 constexpr int64_t kChunk = 1024;  // steps per captured graph, at most
 
 static int64_t count_tiles(const lbm_params *ps, int n, int tx, int ty)
@@ -595,11 +596,15 @@ static hipError_t launch_batch_step_m(int flags, int shape, int64_t ntiles, cons
 }
 
 template <int F>
-static hipError_t launch_batch_mips_f(int64_t ntiles, const BatchTile *tiles, const LatDesc *lats, const Ctrl *ctrl,
-                                      int step_off, int launch_off, hipStream_t s)
+static hipError_t launch_batch_mips_f(int shape, int64_t ntiles, const BatchTile *tiles, const LatDesc *lats,
+                                      const Ctrl *ctrl, int step_off, int launch_off, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_batch_step_mips<F>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl, step_off,
-                       launch_off);
+    if (shape == kMipsShape4)
+        hipLaunchKernelGGL((k_batch_step_mips<F, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
+                           step_off, launch_off);
+    else
+        hipLaunchKernelGGL((k_batch_step_mips<F, kMipsRows>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats,
+                           ctrl, step_off, launch_off);
     return hipGetLastError();
 }
 
@@ -609,11 +614,12 @@ static hipError_t launch_batch_step(int model, int flags, int shape, int64_t nti
 {
     if (model == kMips) {
         switch (flags) {
-        case 0: return launch_batch_mips_f<0>(ntiles, tiles, lats, ctrl, step_off, launch_off, s);
-        case kUnitTau: return launch_batch_mips_f<kUnitTau>(ntiles, tiles, lats, ctrl, step_off, launch_off, s);
-        case kNoisy: return launch_batch_mips_f<kNoisy>(ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+        case 0: return launch_batch_mips_f<0>(shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+        case kUnitTau:
+            return launch_batch_mips_f<kUnitTau>(shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+        case kNoisy: return launch_batch_mips_f<kNoisy>(shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
         default:
-            return launch_batch_mips_f<kUnitTau | kNoisy>(ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+            return launch_batch_mips_f<kUnitTau | kNoisy>(shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
         }
     }
     if (model == kCil)
@@ -765,21 +771,20 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     // the sweep starts), so the state is unchanged.
     int shape = -1;
     const bool mips = ps[0].model == LBM_MIPS;
-    for (int k = 0; k < kNumTuned; ++k)
+    // the shapes this model may take (tuned among themselves)
+    std::vector<int> cands;
+    if (mips)
+        cands = {kMipsShape, kMipsShape4};
+    else
+        for (int k = 0; k < kNumTuned; ++k)
+            cands.push_back(k);
+    for (int k : cands)
         if (o->tile_rows == kShapes[k].ty)
             shape = k;
-    if (mips) {
-        if (o->tile_rows != 0 && o->tile_rows != kMipsRows)
-            return fail(LBM_EINVAL, "MIPS batches take tile_rows 0 or 16 (64x16 tiles, one step per launch)");
-        shape = kMipsShape;
-    } else if (shape < 0 && o->tile_rows != 0) {
-        return fail(LBM_EINVAL, "tile_rows must be 0, 1, 2, 4, 8 or 16");
-    }
+    if (shape < 0 && o->tile_rows != 0)
+        return fail(LBM_EINVAL, mips ? "MIPS batches take tile_rows 0, 4 or 16 (64-wide tiles, one step per launch)"
+                                     : "tile_rows must be 0, 1, 2, 4, 8 or 16");
     const std::string sig = signature(ps, n, flags);
-    if (mips) {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[sig] = kMipsShape;
-    }
     if (shape < 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(sig);
@@ -844,7 +849,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         // each shape: ten launches captured in a graph (as the sweep runs
         // them), replayed once to warm up and three times timed; the least
         // time per step wins
-        for (int k = 0; k < kNumTuned; ++k) {
+        for (int k : cands) {
             auto tl = upload(k);
             if (!tl.first)
                 return hip_fail(up_err, "tile list upload");

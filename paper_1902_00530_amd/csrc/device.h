@@ -419,11 +419,11 @@ struct BufIO<_Float16> {
 };
 
 // ---------------------------------------------------------------------------
-// MIPS step of one 64 x 16 tile at (x0, y0) (u* needs the streamed density of
-// the six neighbours).  256 threads: wave w owns rows w, w+4, w+8, w+12, one
-// column per lane.  rho of the tile and of a one-site ring (the rows above
-// and below and the two edge columns: 164 sites, taken by waves 0-2) is
-// staged in LDS (srho, kMipsTileLds floats).  The tile's own populations stay
+// MIPS step of one 64 x ROWS tile at (x0, y0), ROWS = 4 or 16 (u* needs the
+// streamed density of the six neighbours).  256 threads: wave w owns rows w,
+// w+4, ..., one column per lane.  rho of the tile and of a one-site ring (the
+// rows above and below and the two edge columns: 2 x 66 + 2 ROWS sites, taken
+// by waves 0-2) is staged in LDS (srho, mips_tile_lds(ROWS) floats).  The tile's own populations stay
 // in registers from the density pass to the collision; every load of a wave
 // is issued before any of its sites is computed.  On tiles whose sources do
 // not wrap, a row's seven loads share one vector offset (the lane) and
@@ -434,20 +434,21 @@ struct BufIO<_Float16> {
 // the batched MIPS kernels both run this body.
 // ---------------------------------------------------------------------------
 constexpr int kMipsRows = 16;
-constexpr int kMipsTileLds = (kMipsRows + 2) * 66;
+constexpr int mips_tile_lds(int rows) { return (rows + 2) * 66; }
 
-template <int S, int F>
+template <int S, int F, int ROWS = kMipsRows>
 __device__ __forceinline__ void mips_tile_step(__amdgpu_buffer_rsrc_t rs, __amdgpu_buffer_rsrc_t rd,
                                                const StepArgs &a, int x0, int y0, uint32_t t_lo, uint32_t t_hi,
                                                float *srho)
 {
     using T = typename Store<S>::T;
-    constexpr int W = 66, H = kMipsRows + 2, RW = kMipsRows / 4;  // RW rows per wave
-    constexpr int kRing = 2 * W + 2 * kMipsRows;                  // 164
+    static_assert(ROWS == 4 || ROWS == 16, "four waves own the rows; waves 0-2 cover the ring");
+    constexpr int W = 66, H = ROWS + 2, RW = ROWS / 4;  // RW rows per wave
+    constexpr int kRing = 2 * W + 2 * ROWS;             // 164 or 140
     const uint32_t plane = (uint32_t)a.plane, P = (uint32_t)a.pitch, nx = (uint32_t)a.nx;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const bool interior = x0 >= 1 && x0 + 65 <= a.nx && y0 >= 1 && y0 + kMipsRows + 1 <= a.ny;
+    const bool interior = x0 >= 1 && x0 + 65 <= a.nx && y0 >= 1 && y0 + ROWS + 1 <= a.ny;
     // the seven streamed populations of site (x, y), periodically wrapped
     auto load_wrapped = [&](float *g, int x, int y) {
         const PullSources32 q = pull_sources32(a, wrap_coord(x, a.nx), wrap_coord(y, a.ny));
@@ -481,8 +482,8 @@ __device__ __forceinline__ void mips_tile_step(__amdgpu_buffer_rsrc_t rs, __amdg
             rlx = re - W;
             rly = H - 1;
         } else {
-            rlx = re < 2 * W + kMipsRows ? 0 : W - 1;
-            rly = 1 + (re - 2 * W) % kMipsRows;
+            rlx = re < 2 * W + ROWS ? 0 : W - 1;
+            rly = 1 + (re - 2 * W) % ROWS;
         }
         float g[7];
         load_wrapped(g, x0 - 1 + rlx, y0 - 1 + rly);

@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_step_mips(const typename Store<S>::T *_
                                                    uint32_t t_lo, uint32_t t_hi)
 {
     using T = typename Store<S>::T;
-    __shared__ float srho[kMipsTileLds];
+    __shared__ float srho[mips_tile_lds(kMipsRows)];
     int txi, tyi;
     row_group_tile(txi, tyi);
     const int x0 = txi * 64, y0 = tyi * kMipsRows;

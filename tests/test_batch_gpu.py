@@ -229,25 +229,27 @@ def mips_states(L, cfgs):
     return states
 
 
-@pytest.mark.parametrize("use_graph,steps", [(1, 37), (0, 37), (1, 1100)])
-def test_mips_batch_member_equals_single_run(L, use_graph, steps):
-    """The batched MIPS kernel runs the single-lattice MIPS tile body: every
-    member equals its lbm_step run bit for bit (1100 steps cross a captured
-    chunk), and the tile shape reported for the batch is its 64 x 16 tile."""
+@pytest.mark.parametrize("tile_rows,use_graph,steps", [(16, 1, 37), (4, 0, 37), (0, 1, 1100), (4, 1, 1100)])
+def test_mips_batch_member_equals_single_run(L, tile_rows, use_graph, steps):
+    """The batched MIPS kernel runs the single-lattice MIPS tile body (on
+    64 x 16 or 64 x 4 tiles): every member equals its lbm_step run (64 x 16
+    tiles) bit for bit (1100 steps cross a captured chunk), and the tuned
+    shape is one of the two MIPS tiles."""
     cfgs = mips_batch()
     states = mips_states(L, cfgs)
     finals, samples = single_runs(L, cfgs, states, steps)
     b = L.Batch([_gparams(L, c) for c in cfgs])
     for l, f0 in enumerate(states):
         b.set_state(l, f0)
-    out = b.run(steps, use_graph=use_graph)
+    out = b.run(steps, tile_rows=tile_rows, use_graph=use_graph)
     torch.cuda.synchronize()
     for l in range(len(cfgs)):
         assert torch.equal(b.state(l), finals[l]), l
         o, s = out[l][0], samples[l][0]
         for k in ("M", "phi", "drho"):
             assert abs(o[k] - s[k]) <= 1e-12 * max(1.0, abs(s[k])), (l, k)
-    assert L.lbm_sweep_tile_rows(b.params, b.n) == 16
+    if tile_rows == 0:
+        assert L.lbm_sweep_tile_rows(b.params, b.n) in (4, 16)
 
 
 def test_mips_batch_samples_density_ramp_and_oracle(L, orc):
