@@ -184,17 +184,19 @@ def sigma_schedule(sigma_lo=1.0 / 70.0, sigma_hi=3.0 / 70.0, step=1.0 / 700.0):
 
 
 def mips_noise_ramp(rho_means=(0.06, 0.08, 0.10, 0.125, 0.15, 0.18), repeats=2, sigmas=None, init_steps=200000,
-                    relax_steps=50000, sample_every=1000, n_samples=50, seed_base=90000, nx=90, ny=30):
+                    relax_steps=50000, sample_every=1000, n_samples=50, seed_base=90000, nx=90, ny=30,
+                    progress=None):
     """The MIPS experiment of the paper (section "Simulation procedure for
     results"): each run starts at sigma = sigma_0, relaxes, then for every
     noise strength of the schedule relaxes relax_steps and takes n_samples
     samples every sample_every steps before the noise rises.  All densities
     and repeats run as one batch.  The paper relaxes 10^6 steps after each
     rise and samples 100 times every 10^4 steps; the defaults here are
-    shorter.  Returns the noise strengths, the densities, the banding measure
-    per (density, sigma) averaged over samples and repeats, the regime
-    ('PS' / 'H') and, per density, the first sigma of the schedule at which it
-    is homogeneous."""
+    shorter.  progress, if given, is called with (sigma, banding per density)
+    after each noise strength.  Returns the noise strengths, the densities,
+    the banding measure per (density, sigma) averaged over samples and
+    repeats, the regime ('PS' / 'H') and, per density, the first sigma of the
+    schedule at which it is homogeneous."""
     sigmas = sigma_schedule() if sigmas is None else list(sigmas)
     rhos = [float(r) for r in rho_means for _ in range(repeats)]
     b = mips_batch(rhos, [seed_base + l for l in range(len(rhos))], sigma=sigmas[0], nx=nx, ny=ny)
@@ -207,6 +209,8 @@ def mips_noise_ramp(rho_means=(0.06, 0.08, 0.10, 0.125, 0.15, 0.18), repeats=2, 
         out = b.run(sample_every * n_samples, sample_every=sample_every)
         per_run = np.array([np.mean([o["drho"] for o in out[l]]) for l in range(b.n)])
         band[:, k] = per_run.reshape(len(rho_means), repeats).mean(axis=1)
+        if progress is not None:
+            progress(sg, band[:, k].tolist())
     regime = [[classify_mips(v) for v in row] for row in band]
     sigma_c = []
     for row in regime:
