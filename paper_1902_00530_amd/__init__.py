@@ -74,6 +74,13 @@ class LbmError(RuntimeError):
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built: run python paper_1902_00530_amd/build.py (hipcc, gfx950)")
 
+# torch first: it loads its own HIP and HSA runtimes (sonames libamdhip64.so.7
+# and libhsa-runtime64.so.1), which the library's dependencies then resolve
+# to, so the process holds one runtime.  Loaded the other way round, torch
+# would bring a second copy beside the system one and the library's first
+# HIP call would find no device.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 _vp = ctypes.c_void_p
 _P = ctypes.POINTER
