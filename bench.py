@@ -35,9 +35,11 @@ BYTES_PER_SITE = {0: 56, 1: 28, 2: 28}
 # VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # VALU lane-instructions per site-update of the fused CIL step (FP32, tau 1,
-# noise on), measured as SQ_INSTS_VALU / SQ_WAVES of the one-step kernel with
-# one site per lane (profiles/k_batch_step2_cil_5x1024.md)
-VALU_PER_SITE_UPDATE = 190
+# noise on): SQ_INSTS_VALU / SQ_WAVES of the one-step kernel with one site
+# per lane.  valu_per_site_update() reads the current figure from the counter
+# summary in profiles/; this is the last measured value, used when that
+# summary was taken on other kernel sources.
+VALU_PER_SITE_UPDATE = 183
 
 
 def parse():
@@ -246,15 +248,27 @@ def attach_traffic(r, name, files, sites, per_launch_s):
     return r
 
 
+def valu_per_site_update():
+    """The per-unit VALU figure of the ALU roofline: SQ_INSTS_VALU x 64 /
+    site-updates of the one-step kernel (one site per lane) from its committed
+    counter summary when that was taken on the current kernel sources, else
+    the last measured value (VALU_PER_SITE_UPDATE).  Returns (value, source)."""
+    c = measured_traffic("counters_k_batch_step_1_cil_5x1024.json")
+    if c is not None and c.get("valu_lane_instructions_per_site_update"):
+        return float(c["valu_lane_instructions_per_site_update"]), "counters_k_batch_step_1_cil_5x1024.json"
+    return float(VALU_PER_SITE_UPDATE), "stated (counter summary taken on other kernel sources)"
+
+
 def roofline_two_step(sites, per_launch_s, kernel, rows):
     """Two steps per launch: 2 x sites site-updates of VALU work against the
     VALU issue peak; the HBM side is the state read and written once."""
-    tops = VALU_PER_SITE_UPDATE * 2 * sites / per_launch_s / 1e12
+    vpu, vsrc = valu_per_site_update()
+    tops = vpu * 2 * sites / per_launch_s / 1e12
     hbm = BYTES_PER_SITE[0] * sites / per_launch_s / 1e9
     r = {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
          "unit": "T VALU lane-instructions/s", "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": None,
          "kernel": kernel, "avg_launch_us": round(per_launch_s * 1e6, 3),
-         "valu_per_site_update": VALU_PER_SITE_UPDATE, "site_updates_per_launch": 2 * sites,
+         "valu_per_site_update": vpu, "valu_per_site_update_source": vsrc, "site_updates_per_launch": 2 * sites,
          "hbm": {"achieved": round(hbm, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                  "frac": round(hbm / HBM_PEAK_GBPS, 4), "bytes_per_launch": BYTES_PER_SITE[0] * sites}}
     c = measured_traffic(f"counters_k_batch_step2_{rows}_cil_5x1024.json")

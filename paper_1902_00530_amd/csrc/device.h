@@ -70,19 +70,20 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 // sigma (2 h_i - 65535) / 65536; subtracting the mean over the seven
 // directions leaves sigma (7 h_i - H) / 229376 with H = sum h_i.  The h_i, H
 // and 7 h_i - H are integers below 2^20 in magnitude, exact in float; one fma
-// then scales and adds each.
+// then scales and adds each.  The halves are taken as 16-bit values so that
+// each becomes one convert with a word select (SDWA), no mask or shift.
 __device__ __forceinline__ void site_add_noise(const StepArgs &a, uint32_t site, uint32_t t_lo, uint32_t t_hi,
                                                float f[7])
 {
     const Philox4 w = philox4x32_10(site, t_lo, t_hi, 0u, a.key0, a.key1);
     float h[7];
-    h[0] = (float)(w.v[0] & 0xffffu);
-    h[1] = (float)(w.v[0] >> 16);
-    h[2] = (float)(w.v[1] & 0xffffu);
-    h[3] = (float)(w.v[1] >> 16);
-    h[4] = (float)(w.v[2] & 0xffffu);
-    h[5] = (float)(w.v[2] >> 16);
-    h[6] = (float)(w.v[3] & 0xffffu);
+    h[0] = (float)(uint16_t)w.v[0];
+    h[1] = (float)(uint16_t)(w.v[0] >> 16);
+    h[2] = (float)(uint16_t)w.v[1];
+    h[3] = (float)(uint16_t)(w.v[1] >> 16);
+    h[4] = (float)(uint16_t)w.v[2];
+    h[5] = (float)(uint16_t)(w.v[2] >> 16);
+    h[6] = (float)(uint16_t)w.v[3];
     const float H = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + h[6]);
 #pragma unroll
     for (int i = 0; i < 7; ++i)
