@@ -39,7 +39,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # per lane.  valu_per_site_update() reads the current figure from the counter
 # summary in profiles/; this is the last measured value, used when that
 # summary was taken on other kernel sources.
-VALU_PER_SITE_UPDATE = 183
+VALU_PER_SITE_UPDATE = 185
 
 
 def parse():
