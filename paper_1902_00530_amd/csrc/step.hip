@@ -166,25 +166,30 @@ __global__ __launch_bounds__(256) void k_step_mips64(const typename Store<S>::T 
 }
 
 // ---------------------------------------------------------------------------
-// MIPS: the 64 x 16 tile body (mips_tile_step in device.h) on a grid in row
-// groups.  Offsets are 32-bit (7 planes below 2^30 elements); larger
-// lattices take k_step_mips64.
+// MIPS: the 64 x ROWS tile body (mips_tile_step in device.h) on a grid in row
+// groups: ROWS = 16, or 4 on lattices too small to fill the GPU with 64 x 16
+// tiles (a wave then owns one row, so a launch ends sooner; the per-site
+// arithmetic is the same).  Offsets are 32-bit (7 planes below 2^30
+// elements); larger lattices take k_step_mips64.
 // ---------------------------------------------------------------------------
-template <int S, int F>
+template <int S, int F, int ROWS>
 __global__ __launch_bounds__(256) void k_step_mips(const typename Store<S>::T *__restrict__ src,
                                                    typename Store<S>::T *__restrict__ dst, StepArgs a,
                                                    uint32_t t_lo, uint32_t t_hi)
 {
     using T = typename Store<S>::T;
-    __shared__ float srho[mips_tile_lds(kMipsRows)];
+    __shared__ float srho[mips_tile_lds(ROWS)];
     int txi, tyi;
     row_group_tile(txi, tyi);
-    const int x0 = txi * 64, y0 = tyi * kMipsRows;
+    const int x0 = txi * 64, y0 = tyi * ROWS;
     if (y0 >= a.ny)  // padding tile rows of the last group: the whole block
         return;
     const uint32_t bytes = 7u * (uint32_t)a.plane * (uint32_t)sizeof(T);  // < 2^32: 7 planes < 2^30 elements
-    mips_tile_step<S, F>(buffer_rsrc(src, bytes), buffer_rsrc(dst, bytes), a, x0, y0, t_lo, t_hi, srho);
+    mips_tile_step<S, F, ROWS>(buffer_rsrc(src, bytes), buffer_rsrc(dst, bytes), a, x0, y0, t_lo, t_hi, srho);
 }
+
+// 64 x 16 MIPS tiles below this count leave the GPU under-filled (two per CU)
+constexpr int64_t kMipsSmallTiles = 512;
 
 // ---------------------------------------------------------------------------
 // Launchers
@@ -208,8 +213,14 @@ static hipError_t launch_step_sf(const lbm_params &p, const StepArgs &a, const v
     if (p.model == kMips) {
         if (fits32(a)) {
             const int ntx = (p.nx + 63) / 64, nty = (p.ny + kMipsRows - 1) / kMipsRows;
-            dim3 grd(8u * (unsigned)ntx, (unsigned)((nty + 7) / 8));
-            hipLaunchKernelGGL((k_step_mips<S, F>), grd, dim3(256), 0, s, in, out, a, tlo, thi);
+            if ((int64_t)ntx * nty < kMipsSmallTiles) {
+                const int nty4 = (p.ny + 3) / 4;
+                dim3 grd(8u * (unsigned)ntx, (unsigned)((nty4 + 7) / 8));
+                hipLaunchKernelGGL((k_step_mips<S, F, 4>), grd, dim3(256), 0, s, in, out, a, tlo, thi);
+            } else {
+                dim3 grd(8u * (unsigned)ntx, (unsigned)((nty + 7) / 8));
+                hipLaunchKernelGGL((k_step_mips<S, F, kMipsRows>), grd, dim3(256), 0, s, in, out, a, tlo, thi);
+            }
         } else {
             dim3 blk(kMipsTX, kMipsTY), grd((p.nx + kMipsTX - 1) / kMipsTX, (p.ny + kMipsTY - 1) / kMipsTY);
             hipLaunchKernelGGL((k_step_mips64<S, F>), grd, blk, 0, s, in, out, a, tlo, thi);

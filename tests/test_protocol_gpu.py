@@ -156,3 +156,16 @@ def test_mips_noise_ramp_driver(L):
                             relax_steps=20000, sample_every=1000, n_samples=20)
     assert res["regime"] == [["PS", "H"]] and res["sigma_homogeneous"] == [3 / 70]
     assert res["steps"] == 100000 + 2 * (20000 + 20000) and res["lattices"] == 2
+
+
+def test_phase_diagram_brackets_the_critical_point(L):
+    """The (rho, A) diagram at the paper's parameters with four repeats at
+    A = 2 and A = 3.5: banded regimes (B or RB) appear at A = 2 and none at
+    A = 3.5, on either side of the paper's critical point (A_c ~ 2.75).  A
+    smoke check of the paper's reported behaviour (stochastic runs, not a
+    pin)."""
+    from paper_1902_00530_amd import protocol as P
+    pd = P.phase_diagram([2.0, 3.5], repeats=4)
+    a2, a35 = pd["regime"]
+    assert {"B", "RB"} & set(a2), a2
+    assert not ({"B", "RB"} & set(a35)), a35
