@@ -842,9 +842,19 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     };
     if (shape < 0) {
         float best = 1e30f;
-        hipEvent_t e0, e1;
-        LBM_HIP_TRY(hipEventCreate(&e0));
-        LBM_HIP_TRY(hipEventCreate(&e1));
+        struct EventPair {  // destroyed on every exit path
+            hipEvent_t a = nullptr, b = nullptr;
+            ~EventPair()
+            {
+                if (a)
+                    (void)hipEventDestroy(a);
+                if (b)
+                    (void)hipEventDestroy(b);
+            }
+        } ev;
+        LBM_HIP_TRY(hipEventCreate(&ev.a));
+        LBM_HIP_TRY(hipEventCreate(&ev.b));
+        hipEvent_t e0 = ev.a, e1 = ev.b;
         hipLaunchKernelGGL(k_batch_set_ctrl, dim3(1), dim3(64), 0, s, d_ctrl, (int64_t)0);
         // each shape: ten launches captured in a graph (as the sweep runs
         // them), replayed once to warm up and three times timed; the least
@@ -892,8 +902,6 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
                 shape = k;
             }
         }
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tuned[sig] = shape;
     }
