@@ -54,8 +54,8 @@
  *  - A population buffer is [9][ny][pitch]; every plane must be below 2^32
  *    bytes (ny * pitch < 2^30 for F32, < 2^31 for the 16-bit storages).
  *  - lbm_add_density adds drho/9 to every population.
- *  - Batched sweeps and the coarse-field calls take D2Q7 only
- *    (LBM_EUNSUPPORTED).
+ *  - Batched sweeps run D2Q9 one step per launch; the coarse-field calls take
+ *    D2Q7 only (LBM_EUNSUPPORTED).
  *
  * Memory ownership.  The caller owns every device buffer passed in
  * (population buffers, field outputs, batch buffers, workspaces, network
@@ -210,14 +210,15 @@ typedef struct lbm_sweep_opts {
                              (the second from LDS); 0 = tuned (every shape timed on the
                              batch itself, cached per batch signature).  MIPS batches
                              take 0 (tuned), 4 or 16: 64x4 or 64x16 tiles, one step per
-                             launch, neighbour densities in LDS */
+                             launch, neighbour densities in LDS.  D2Q9 batches take one
+                             step per launch: 0, 1, 2 or 4 (MIPS: 0 or 16) */
     int32_t use_graph;    /* 0: launch every kernel directly; 1: run each sample period
                              as captured HIP graphs of at most 1024 steps, kept (16 most
                              recent) and replayed by later calls with the same batch,
                              workspace and step counts; 2: prepare only: tune and
                              capture those graphs, run nothing and leave out unwritten */
     const double *drho;   /* NULL, or host array of n density changes: right after each
-                             sample, every population of lattice l gains drho[l] / 7
+                             sample, every population of lattice l gains drho[l] / Q
                              (the density ramp of the paper's protocol, appendix
                              "Simulation procedure for results"); finite values only */
 } lbm_sweep_opts;
@@ -232,11 +233,12 @@ size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samp
  * invalid arguments. */
 int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n);
 
-/* Run a batch.  ps[n]: per-lattice parameters; every lattice uses the D2Q7
- * lattice, F32 storage, the same model (CIL, MIPS or passive), and agrees on
- * tau == 1 and on
- * sigma == 0; nx*ny*7 < 2^30, ny <= 32760.  bufs[2n]: caller-owned device
- * buffers [7][ny][nx], lattice l's state in bufs[2l] and bufs[2l+1] free.
+/* Run a batch.  ps[n]: per-lattice parameters; every lattice uses the same
+ * velocity set (D2Q7 or D2Q9), F32 storage, the same model (CIL, MIPS or
+ * passive), and agrees on tau == 1 and on
+ * sigma == 0; nx*ny*Q < 2^30 (Q = 7 or 9 populations), ny <= 32760.
+ * bufs[2n]: caller-owned device buffers [Q][ny][nx], lattice l's state in
+ * bufs[2l] and bufs[2l+1] free.
  * ws: caller-owned device workspace of ws_bytes >=
  * lbm_sweep_workspace_bytes(ps, n, n_samples).  out: host array of
  * n * n_samples lbm_obs, n_samples = n_steps / sample_every (1 if

@@ -255,7 +255,7 @@ class Batch:
         import torch
         self.n = len(params_list)
         self.params = (lbm_params * self.n)(*params_list)
-        self.buffers = [torch.zeros((7, p.ny, p.nx), dtype=torch.float32, device=device)
+        self.buffers = [torch.zeros((n_populations(p), p.ny, p.nx), dtype=torch.float32, device=device)
                         for p in params_list for _ in range(2)]
         self.bufs = (ctypes.c_void_p * (2 * self.n))(*[b.data_ptr() for b in self.buffers])
         # device arrays of the n buffer pointers of each parity (for the
@@ -279,7 +279,8 @@ class Batch:
         use_graph=2 only prepares the launch plan for such a call (tuning,
         captured graphs) and advances nothing.  drho (a number, or one per
         advanced lattice): right after each sample every population gains
-        drho / 7, the density ramp of the paper's protocol."""
+        drho / Q (Q = 7 or 9 populations), the density ramp of the paper's
+        protocol."""
         import torch
         idx = list(range(self.n)) if subset is None else [int(i) for i in subset]
         m = len(idx)

@@ -37,6 +37,7 @@
 #include <tuple>
 #include <vector>
 
+#include "device_q9.h"
 #include "internal.h"
 
 namespace lbm {
@@ -55,7 +56,7 @@ struct LatDesc {
     int32_t nrb;        // moments row blocks
     int64_t col_off;    // offset of this lattice's column partials
     int64_t cm_off;     // offset of this lattice's column means
-    float add;          // added to every population after each sample (drho / 7)
+    float add;          // added to every population after each sample (drho / Q)
 };
 
 struct MomTile {
@@ -128,6 +129,44 @@ __global__ __launch_bounds__(256) void k_batch_step_mips(const BatchTile *__rest
     const uint32_t bytes = 28u * (uint32_t)a.plane;
     mips_tile_step<kF32, F, ROWS>(buffer_rsrc(L.buf[par], bytes), buffer_rsrc(L.buf[par ^ 1], bytes), a, x0, y0,
                             (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32), srho);
+}
+
+// The square lattice (D2Q9) over the tile list: the single-lattice site body
+// (passive, CIL) and MIPS tile body, one step per launch.
+template <int M, int F>
+__global__ __launch_bounds__(256) void k_batch_q9_step(const BatchTile *__restrict__ tiles,
+                                                       const LatDesc *__restrict__ lats,
+                                                       const Ctrl *__restrict__ ctrl, int step_off, int launch_off)
+{
+    const BatchTile tl = tiles[blockIdx.x];
+    const LatDesc &L = lats[tl.lat];
+    const StepArgs a = L.a;
+    const int64_t t = ctrl->t0 + step_off;
+    const int par = (int)((ctrl->k0 + launch_off) & 1);
+    const int x = tl.tx * blockDim.x + threadIdx.x;
+    const int y = tl.ty * blockDim.y + threadIdx.y;
+    if (x >= a.nx || y >= a.ny)
+        return;
+    q9_site_step<M, kF32, F>((const float *)L.buf[par], (float *)L.buf[par ^ 1], a, x, y,
+                             (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32));
+}
+
+template <int F>
+__global__ __launch_bounds__(256) void k_batch_q9_step_mips(const BatchTile *__restrict__ tiles,
+                                                            const LatDesc *__restrict__ lats,
+                                                            const Ctrl *__restrict__ ctrl, int step_off, int launch_off)
+{
+    __shared__ float srho[(kQ9MipsRows + 2) * 66];
+    const BatchTile tl = tiles[blockIdx.x];
+    const LatDesc &L = lats[tl.lat];
+    const StepArgs a = L.a;
+    const int64_t t = ctrl->t0 + step_off;
+    const int par = (int)((ctrl->k0 + launch_off) & 1);
+    const int x0 = tl.tx * 64, y0 = tl.ty * kQ9MipsRows;
+    if (x0 >= a.nx || y0 >= a.ny)  // whole-block exit, before the barrier
+        return;
+    q9_mips_tile_step<kF32, F>((const float *)L.buf[par], (float *)L.buf[par ^ 1], a, x0, y0,
+                               (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32), srho);
 }
 
 // Step t+1 on the widened tile as the second step reads it, in local
@@ -310,6 +349,8 @@ __device__ __forceinline__ double bwave_sum(double v)
     return v;
 }
 
+// Q = 7 (triangular) or 9 (square lattice).
+template <int Q>
 __global__ __launch_bounds__(256) void k_batch_moments(const MomTile *__restrict__ mt, const LatDesc *__restrict__ lats,
                                                        const Ctrl *__restrict__ ctrl, int node,
                                                        double *__restrict__ part, double *__restrict__ colpart)
@@ -319,7 +360,7 @@ __global__ __launch_bounds__(256) void k_batch_moments(const MomTile *__restrict
     const LatDesc &L = lats[m.lat];
     const StepArgs a = L.a;
     const int par = (int)((ctrl->k0 + node) & 1);
-    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], 28u * (uint32_t)a.plane);
+    const uint32_t plane = (uint32_t)a.plane;
     const int x = m.cx * 256 + threadIdx.x;
     const int yb = m.cy * kMomRows;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -327,16 +368,27 @@ __global__ __launch_bounds__(256) void k_batch_moments(const MomTile *__restrict
         double col = 0.0;
         const int ye = min(yb + kMomRows, a.ny);
         for (int y = yb; y < ye; ++y) {
-            const PullSources32 g = pull_sources32(a, x, y);
-            float f[7];
+            float f[Q];
             bool finite = true;
-#pragma unroll
-            for (int i = 0; i < 7; ++i) {
-                f[i] = BufIO<float>::load(src, g.idx[i], i * (uint32_t)a.plane);
-                finite = finite && isfinite(f[i]);
-            }
             float rho, jx, jy;
-            site_moments(f, rho, jx, jy);
+            if constexpr (Q == 7) {
+                const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], 28u * plane);
+                const PullSources32 g = pull_sources32(a, x, y);
+#pragma unroll
+                for (int i = 0; i < 7; ++i)
+                    f[i] = BufIO<float>::load(src, g.idx[i], i * plane);
+                site_moments(f, rho, jx, jy);
+            } else {
+                const float *src = (const float *)L.buf[par];
+                const Q9Sources g = q9_sources(a, x, y);
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    f[i] = BufIO<float>::load(q9_plane_rsrc(src, i, plane), g.idx[i], 0u);
+                q9_moments(f, rho, jx, jy);
+            }
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                finite = finite && isfinite(f[i]);
             const double dx = jx, dy = jy;
             acc[0] += (double)rho;
             acc[1] += dx;
@@ -424,8 +476,9 @@ __global__ __launch_bounds__(256) void k_batch_final(const LatDesc *__restrict__
 }
 
 // The density change of the paper's protocol (appendix "Simulation procedure
-// for results"): every population of lattice l gains drho_l / 7, in the
+// for results"): every population of lattice l gains drho_l / Q, in the
 // buffer that holds the state after this period's steps; per moments tile.
+template <int Q>
 __global__ __launch_bounds__(256) void k_batch_add_density(const MomTile *__restrict__ mt,
                                                            const LatDesc *__restrict__ lats,
                                                            const Ctrl *__restrict__ ctrl, int node)
@@ -444,7 +497,7 @@ __global__ __launch_bounds__(256) void k_batch_add_density(const MomTile *__rest
     const int ye = min(m.cy * kMomRows + kMomRows, a.ny);
     for (int y = m.cy * kMomRows; y < ye; ++y)
 #pragma unroll
-        for (int i = 0; i < 7; ++i) {
+        for (int i = 0; i < Q; ++i) {
             float *p = f + (size_t)i * (size_t)a.plane + (size_t)y * (size_t)a.pitch + x;
             *p = *p + add;
         }
@@ -608,10 +661,39 @@ static hipError_t launch_batch_mips_f(int shape, int64_t ntiles, const BatchTile
     return hipGetLastError();
 }
 
-static hipError_t launch_batch_step(int model, int flags, int shape, int64_t ntiles, const BatchTile *tiles,
-                                    const LatDesc *lats, const Ctrl *ctrl, int step_off, int launch_off,
-                                    hipStream_t s)
+template <int F>
+static hipError_t launch_batch_q9_f(int model, int shape, int64_t ntiles, const BatchTile *tiles, const LatDesc *lats,
+                                    const Ctrl *ctrl, int step_off, int launch_off, hipStream_t s)
 {
+    const Shape &sh = kShapes[shape];
+    if (model == kMips)
+        hipLaunchKernelGGL((k_batch_q9_step_mips<F>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
+                           step_off, launch_off);
+    else if (model == kCil)
+        hipLaunchKernelGGL((k_batch_q9_step<kCil, F>), dim3((unsigned)ntiles), dim3(sh.tx, sh.ty), 0, s, tiles, lats,
+                           ctrl, step_off, launch_off);
+    else
+        hipLaunchKernelGGL((k_batch_q9_step<kPassive, F>), dim3((unsigned)ntiles), dim3(sh.tx, sh.ty), 0, s, tiles,
+                           lats, ctrl, step_off, launch_off);
+    return hipGetLastError();
+}
+
+static hipError_t launch_batch_step(int lattice, int model, int flags, int shape, int64_t ntiles,
+                                    const BatchTile *tiles, const LatDesc *lats, const Ctrl *ctrl, int step_off,
+                                    int launch_off, hipStream_t s)
+{
+    if (lattice == LBM_D2Q9) {
+        switch (flags) {
+        case 0: return launch_batch_q9_f<0>(model, shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+        case kUnitTau:
+            return launch_batch_q9_f<kUnitTau>(model, shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+        case kNoisy:
+            return launch_batch_q9_f<kNoisy>(model, shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+        default:
+            return launch_batch_q9_f<kUnitTau | kNoisy>(model, shape, ntiles, tiles, lats, ctrl, step_off,
+                                                        launch_off, s);
+        }
+    }
     if (model == kMips) {
         switch (flags) {
         case 0: return launch_batch_mips_f<0>(shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
@@ -627,8 +709,8 @@ static hipError_t launch_batch_step(int model, int flags, int shape, int64_t nti
     return launch_batch_step_m<kPassive>(flags, shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
 }
 
-// Tuned tile shape per batch signature (arch + multiset of lattice sizes +
-// model + flags), kept for the life of the process.
+// Tuned tile shape per batch signature (arch + lattice type + multiset of
+// lattice sizes + model + flags), kept for the life of the process.
 static std::mutex g_tune_mu;
 static std::map<std::string, int> g_tuned;
 
@@ -637,7 +719,8 @@ static std::string signature(const lbm_params *ps, int n, int flags)
     std::map<std::pair<int, int>, int> hist;
     for (int l = 0; l < n; ++l)
         hist[{ps[l].nx, ps[l].ny}]++;
-    std::string s = "gfx950/m" + std::to_string(ps[0].model) + "/f" + std::to_string(flags);
+    std::string s = "gfx950/q" + std::to_string(ps[0].lattice == LBM_D2Q9 ? 9 : 7) + "/m" +
+                    std::to_string(ps[0].model) + "/f" + std::to_string(flags);
     for (auto &h : hist)
         s += "/" + std::to_string(h.first.first) + "x" + std::to_string(h.first.second) + ":" +
              std::to_string(h.second);
@@ -648,13 +731,13 @@ static std::string signature(const lbm_params *ps, int n, int flags)
 struct GraphKey {
     int device;
     const void *tiles_main, *tiles_one, *lat, *ctrl, *mt, *part, *colpart, *colmean, *results;
-    int model, flags, shape;
+    int lattice, model, flags, shape;
     int64_t ntiles_main, ntiles_one, nmt, n, n_samples, steps;
     int sample, add;
     auto tie() const
     {
-        return std::tie(device, tiles_main, tiles_one, lat, ctrl, mt, part, colpart, colmean, results, model, flags,
-                        shape, ntiles_main, ntiles_one, nmt, n, n_samples, steps, sample, add);
+        return std::tie(device, tiles_main, tiles_one, lat, ctrl, mt, part, colpart, colmean, results, lattice, model,
+                        flags, shape, ntiles_main, ntiles_one, nmt, n, n_samples, steps, sample, add);
     }
     bool operator==(const GraphKey &o) const { return tie() == o.tie(); }
 };
@@ -740,13 +823,13 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         int32_t rc = validate_params(&ps[l], ps[l].nx);
         if (rc)
             return fail(rc, "lattice " + std::to_string(l) + ": " + lbm_last_error());
-        if (ps[l].lattice != LBM_D2Q7)
-            return fail(LBM_EUNSUPPORTED, "batched sweeps take the D2Q7 lattice");
+        if (ps[l].lattice != ps[0].lattice)
+            return fail(LBM_EINVAL, "all lattices of a batch must use the same velocity set");
         if (ps[l].storage != LBM_F32)
             return fail(LBM_EUNSUPPORTED, "batched sweeps take F32 storage");
         if (ps[l].model != ps[0].model)
             return fail(LBM_EINVAL, "all lattices of a batch must use the same model");
-        if ((uint64_t)ps[l].nx * ps[l].ny * 7ull >= (1ull << 30))
+        if ((uint64_t)ps[l].nx * ps[l].ny * (ps[l].lattice == LBM_D2Q9 ? 9ull : 7ull) >= (1ull << 30))
             return fail(LBM_EINVAL, "batch lattices must hold fewer than 2^30 populations");
         if (!bufs[2 * l] || !bufs[2 * l + 1] || bufs[2 * l] == bufs[2 * l + 1])
             return fail(LBM_EINVAL, "lattice " + std::to_string(l) + ": null or equal buffers");
@@ -770,20 +853,24 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     // in the first buffer of each lattice and writes the second (free until
     // the sweep starts), so the state is unchanged.
     int shape = -1;
-    const bool mips = ps[0].model == LBM_MIPS;
-    // the shapes this model may take (tuned among themselves)
+    const bool mips = ps[0].model == LBM_MIPS, q9 = ps[0].lattice == LBM_D2Q9;
+    // the shapes this model and lattice may take (tuned among themselves):
+    // D2Q9 takes one step per launch (local models 256x1, 128x2, 64x4; MIPS
+    // 64x16)
     std::vector<int> cands;
     if (mips)
-        cands = {kMipsShape, kMipsShape4};
+        cands = q9 ? std::vector<int>{kMipsShape} : std::vector<int>{kMipsShape, kMipsShape4};
     else
-        for (int k = 0; k < kNumTuned; ++k)
+        for (int k = 0; k < (q9 ? kNumTuned - 2 : kNumTuned); ++k)
             cands.push_back(k);
     for (int k : cands)
         if (o->tile_rows == kShapes[k].ty)
             shape = k;
     if (shape < 0 && o->tile_rows != 0)
-        return fail(LBM_EINVAL, mips ? "MIPS batches take tile_rows 0, 4 or 16 (64-wide tiles, one step per launch)"
-                                     : "tile_rows must be 0, 1, 2, 4, 8 or 16");
+        return fail(LBM_EINVAL, q9 ? (mips ? "D2Q9 MIPS batches take tile_rows 0 or 16"
+                                           : "D2Q9 batches take tile_rows 0, 1, 2 or 4 (one step per launch)")
+                                   : mips ? "MIPS batches take tile_rows 0, 4 or 16 (64-wide tiles, one step per launch)"
+                                          : "tile_rows must be 0, 1, 2, 4, 8 or 16");
     const std::string sig = signature(ps, n, flags);
     if (shape < 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -812,7 +899,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         D.buf[0] = bufs[2 * l];
         D.buf[1] = bufs[2 * l + 1];
         D.B = (float)ps[l].B;
-        D.add = o->drho ? (float)(o->drho[l] / 7.0) : 0.0f;
+        D.add = o->drho ? (float)(o->drho[l] / (ps[l].lattice == LBM_D2Q9 ? 9.0 : 7.0)) : 0.0f;
         const int cx = (ps[l].nx + 255) / 256, cy = (ps[l].ny + kMomRows - 1) / kMomRows;
         D.mt_begin = (int32_t)mt.size();
         D.mt_count = cx * cy;
@@ -868,7 +955,8 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
             for (int r10 = 0; r10 < 10 && e == hipSuccess; ++r10)  // first buffer -> second buffer
-                e = launch_batch_step(ps[0].model, flags, k, tl.second, tl.first, d_lat, d_ctrl, 0, 0, cap);
+                e = launch_batch_step(ps[0].lattice, ps[0].model, flags, k, tl.second, tl.first, d_lat, d_ctrl, 0,
+                                      0, cap);
             hipError_t ee = hipStreamEndCapture(cap, &g);
             hipStreamDestroy(cap);
             if (e == hipSuccess)
@@ -929,25 +1017,32 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
             int64_t q = steps / 2;
             q -= q & 1;  // an even number of two-step launches
             for (; launches < q; ++launches, done += 2) {
-                hipError_t e = launch_batch_step(ps[0].model, flags, shape, main_list.second, main_list.first, d_lat,
-                                                 d_ctrl, (int)done, (int)launches, s);
+                hipError_t e = launch_batch_step(ps[0].lattice, ps[0].model, flags, shape, main_list.second,
+                                                 main_list.first, d_lat, d_ctrl, (int)done, (int)launches, s);
                 if (e != hipSuccess)
                     return e;
             }
         }
         for (; done < steps; ++launches, ++done) {
-            hipError_t e = launch_batch_step(ps[0].model, flags, two ? 0 : shape, one_list.second, one_list.first,
-                                             d_lat, d_ctrl, (int)done, (int)launches, s);
+            hipError_t e = launch_batch_step(ps[0].lattice, ps[0].model, flags, two ? 0 : shape, one_list.second,
+                                             one_list.first, d_lat, d_ctrl, (int)done, (int)launches, s);
             if (e != hipSuccess)
                 return e;
         }
         if (sample) {
-            hipLaunchKernelGGL(k_batch_moments, dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat, d_ctrl, (int)steps,
-                               d_part, d_colpart);
+            if (q9)
+                hipLaunchKernelGGL(k_batch_moments<9>, dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat, d_ctrl,
+                                   (int)steps, d_part, d_colpart);
+            else
+                hipLaunchKernelGGL(k_batch_moments<7>, dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat, d_ctrl,
+                                   (int)steps, d_part, d_colpart);
             hipLaunchKernelGGL(k_batch_final, dim3((unsigned)n), dim3(256), 0, s, d_lat, d_ctrl, (int)steps, d_part,
                                d_colpart, d_colmean, d_results, (int)n_samples);
-            if (o->drho)
-                hipLaunchKernelGGL(k_batch_add_density, dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat, d_ctrl,
+            if (o->drho && q9)
+                hipLaunchKernelGGL(k_batch_add_density<9>, dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat, d_ctrl,
+                                   (int)steps);
+            else if (o->drho)
+                hipLaunchKernelGGL(k_batch_add_density<7>, dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat, d_ctrl,
                                    (int)steps);
         }
         hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, d_ctrl, steps, sample ? 1 : 0);
@@ -970,7 +1065,8 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         hipGetDevice(&dev);
         const GraphKey key{dev, (const void *)main_list.first, (const void *)one_list.first, (const void *)d_lat,
                            (const void *)d_ctrl, (const void *)d_mt, (const void *)d_part, (const void *)d_colpart,
-                           (const void *)d_colmean, (const void *)d_results, ps[0].model, flags, shape,
+                           (const void *)d_colmean, (const void *)d_results, ps[0].lattice, ps[0].model, flags,
+                           shape,
                            main_list.second, one_list.second, nmt, (int64_t)n, n_samples, steps, sample ? 1 : 0,
                            o->drho ? 1 : 0};
         if ((*ge = graph_cache_get(key)))

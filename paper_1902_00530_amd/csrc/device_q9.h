@@ -177,4 +177,126 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t q9_plane_rsrc(const T *base, i
     return buffer_rsrc(base + (size_t)i * plane, plane * (uint32_t)sizeof(T));
 }
 
+// One site-update of the local models (passive, CIL) at (x, y): the nine
+// streamed populations gathered from their periodic sources, collided, and
+// stored at (x, y) in dst.  src and dst are [9][ny][pitch] population buffers.
+template <int M, int S, int F>
+__device__ __forceinline__ void q9_site_step(const typename Store<S>::T *src, typename Store<S>::T *dst,
+                                             const StepArgs &a, int x, int y, uint32_t t_lo, uint32_t t_hi)
+{
+    using T = typename Store<S>::T;
+    const uint32_t plane = (uint32_t)a.plane;
+    const Q9Sources g = q9_sources(a, x, y);
+    float f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        f[i] = Store<S>::widen(BufIO<T>::load(q9_plane_rsrc(src, i, plane), g.idx[i], 0u), q9_wr(a, i));
+    float rho, jx, jy, ux, uy;
+    q9_moments(f, rho, jx, jy);
+    local_ustar<M>(a, rho, jx, jy, ux, uy);
+    q9_collide<F>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        BufIO<T>::store(q9_plane_rsrc(dst, i, plane), g.idx[0], 0u, Store<S>::narrow(f[i], q9_wr(a, i)));
+}
+
+// ---------------------------------------------------------------------------
+// MIPS step of one 64 x 16 tile at (x0, y0) (u* needs the streamed density of
+// the eight neighbours).  256 threads: wave w owns rows w, w+4, w+8, w+12,
+// one column per lane.  rho of the tile and of its one-site ring (rows above
+// and below, corners included, and the two edge columns: 164 sites, taken by
+// waves 0-2) is staged in LDS (srho, 18 x 66 floats).  The tile's own
+// populations stay in registers from the density pass to the collision.  On
+// tiles whose sources do not wrap, a row's nine loads share one vector offset
+// (the lane) and wave-uniform scalar offsets.  Every LDS slot holds rho at
+// its periodically wrapped site, so ragged tiles and lattices narrower than
+// a tile need no special case.  The single-lattice and the batched D2Q9 MIPS
+// kernels both run this body.
+// ---------------------------------------------------------------------------
+constexpr int kQ9MipsRows = 16;
+
+template <int S, int F>
+__device__ __forceinline__ void q9_mips_tile_step(const typename Store<S>::T *src, typename Store<S>::T *dst,
+                                                  const StepArgs &a, int x0, int y0, uint32_t t_lo, uint32_t t_hi,
+                                                  float *srho)
+{
+    using T = typename Store<S>::T;
+    constexpr int W = 66, H = kQ9MipsRows + 2, RW = kQ9MipsRows / 4;
+    constexpr int kRing = 2 * W + 2 * kQ9MipsRows;  // 164
+    const uint32_t plane = (uint32_t)a.plane, P = (uint32_t)a.pitch, nx = (uint32_t)a.nx;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const bool interior = x0 >= 1 && x0 + 65 <= a.nx && y0 >= 1 && y0 + kQ9MipsRows + 1 <= a.ny;
+    auto load_wrapped = [&](float *g, int x, int y) {
+        const Q9Sources q = q9_sources(a, wrap_coord(x, a.nx), wrap_coord(y, a.ny));
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            g[i] = Store<S>::widen(BufIO<T>::load(q9_plane_rsrc(src, i, plane), q.idx[i], 0u), q9_wr(a, i));
+    };
+    float f[RW][9];
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        const int y = y0 + wv + 4 * k;
+        if (interior) {
+            const uint32_t c = (uint32_t)y * P + (uint32_t)x0;  // offset of (x0, y)
+            const uint32_t e[9] = {c, c - 1u, c - P, c + 1u, c + P, c - P - 1u, c - P + 1u, c + P + 1u, c + P - 1u};
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                f[k][i] = Store<S>::widen(BufIO<T>::load(q9_plane_rsrc(src, i, plane), lane, e[i]), q9_wr(a, i));
+        } else {
+            load_wrapped(f[k], x0 + lane, y);
+        }
+    }
+    const int re = wv * 64 + lane;  // this lane's ring site (waves 0-2)
+    if (re < kRing) {
+        int rlx, rly;
+        if (re < W) {
+            rlx = re;
+            rly = 0;
+        } else if (re < 2 * W) {
+            rlx = re - W;
+            rly = H - 1;
+        } else {
+            rlx = re < 2 * W + kQ9MipsRows ? 0 : W - 1;
+            rly = 1 + (re - 2 * W) % kQ9MipsRows;
+        }
+        float g[9], jx, jy;
+        load_wrapped(g, x0 - 1 + rlx, y0 - 1 + rly);
+        q9_moments(g, srho[rly * W + rlx], jx, jy);
+    }
+    float rho[RW];
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        float jx, jy;
+        q9_moments(f[k], rho[k], jx, jy);
+        srho[(wv + 4 * k + 1) * W + lane + 1] = rho[k];
+    }
+    __syncthreads();
+    const int x = x0 + lane;
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        const int r = wv + 4 * k, y = y0 + r;
+        if (x >= a.nx || y >= a.ny)
+            continue;
+        const int c = (r + 1) * W + lane + 1;
+        float nb[9];
+        nb[0] = rho[k];
+        nb[1] = srho[c + 1];
+        nb[2] = srho[c + W];
+        nb[3] = srho[c - 1];
+        nb[4] = srho[c - W];
+        nb[5] = srho[c + W + 1];
+        nb[6] = srho[c + W - 1];
+        nb[7] = srho[c - W - 1];
+        nb[8] = srho[c - W + 1];
+        float ux, uy;
+        q9_mips_ustar(a, rho[k], nb, ux, uy);
+        q9_collide<F>(a, f[k], rho[k], ux, uy, (uint32_t)y * nx + (uint32_t)x, t_lo, t_hi);
+        const uint32_t own = (uint32_t)y * P + (uint32_t)x;
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            BufIO<T>::store(q9_plane_rsrc(dst, i, plane), own, 0u, Store<S>::narrow(f[k][i], q9_wr(a, i)));
+    }
+}
+
 }  // namespace lbm

@@ -29,124 +29,25 @@ __global__ __launch_bounds__(256) void k_q9_step_local(const typename Store<S>::
     const int y = tyi * blockDim.y + threadIdx.y;
     if (x >= a.nx || y >= a.ny)
         return;
-    using T = typename Store<S>::T;
-    const uint32_t plane = (uint32_t)a.plane;
-    const Q9Sources g = q9_sources(a, x, y);
-    float f[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-        f[i] = Store<S>::widen(BufIO<T>::load(q9_plane_rsrc(src, i, plane), g.idx[i], 0u), q9_wr(a, i));
-    float rho, jx, jy, ux, uy;
-    q9_moments(f, rho, jx, jy);
-    local_ustar<M>(a, rho, jx, jy, ux, uy);
-    q9_collide<F>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-        BufIO<T>::store(q9_plane_rsrc(dst, i, plane), g.idx[0], 0u, Store<S>::narrow(f[i], q9_wr(a, i)));
+    q9_site_step<M, S, F>(src, dst, a, x, y, t_lo, t_hi);
 }
 
 // ---------------------------------------------------------------------------
-// MIPS: u* needs the streamed density of the eight neighbours.  A 64 x 16
-// tile (256 threads; wave w owns rows w, w+4, w+8, w+12, one column per lane)
-// stages rho of the tile and of its one-site ring (rows above and below,
-// corners included, and the two edge columns: 164 sites, taken by waves
-// 0-2) in LDS.  The tile's own populations stay in registers from the
-// density pass to the collision.  On tiles whose sources do not wrap, a
-// row's nine loads share one vector offset (the lane) and wave-uniform
-// scalar offsets.  Every LDS slot holds rho at its periodically wrapped
-// site, so ragged tiles and lattices narrower than a tile need no special
-// case.
+// MIPS: the 64 x 16 tile body (q9_mips_tile_step in device_q9.h) on a grid
+// in row groups.
 // ---------------------------------------------------------------------------
-constexpr int kQ9MipsRows = 16;
-
 template <int S, int F>
 __global__ __launch_bounds__(256) void k_q9_step_mips(const typename Store<S>::T *__restrict__ src,
                                                       typename Store<S>::T *__restrict__ dst, StepArgs a,
                                                       uint32_t t_lo, uint32_t t_hi)
 {
-    using T = typename Store<S>::T;
-    constexpr int W = 66, H = kQ9MipsRows + 2, RW = kQ9MipsRows / 4;
-    constexpr int kRing = 2 * W + 2 * kQ9MipsRows;  // 164
-    __shared__ float srho[H * W];
+    __shared__ float srho[(kQ9MipsRows + 2) * 66];
     int txi, tyi;
     row_group_tile(txi, tyi);
     const int x0 = txi * 64, y0 = tyi * kQ9MipsRows;
     if (y0 >= a.ny)  // padding tile rows of the last group: the whole block
         return;
-    const uint32_t plane = (uint32_t)a.plane, P = (uint32_t)a.pitch, nx = (uint32_t)a.nx;
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const bool interior = x0 >= 1 && x0 + 65 <= a.nx && y0 >= 1 && y0 + kQ9MipsRows + 1 <= a.ny;
-    auto load_wrapped = [&](float *g, int x, int y) {
-        const Q9Sources q = q9_sources(a, wrap_coord(x, a.nx), wrap_coord(y, a.ny));
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            g[i] = Store<S>::widen(BufIO<T>::load(q9_plane_rsrc(src, i, plane), q.idx[i], 0u), q9_wr(a, i));
-    };
-    float f[RW][9];
-#pragma unroll
-    for (int k = 0; k < RW; ++k) {
-        const int y = y0 + wv + 4 * k;
-        if (interior) {
-            const uint32_t c = (uint32_t)y * P + (uint32_t)x0;  // offset of (x0, y)
-            const uint32_t e[9] = {c, c - 1u, c - P, c + 1u, c + P, c - P - 1u, c - P + 1u, c + P + 1u, c + P - 1u};
-#pragma unroll
-            for (int i = 0; i < 9; ++i)
-                f[k][i] = Store<S>::widen(BufIO<T>::load(q9_plane_rsrc(src, i, plane), lane, e[i]), q9_wr(a, i));
-        } else {
-            load_wrapped(f[k], x0 + lane, y);
-        }
-    }
-    const int re = wv * 64 + lane;  // this lane's ring site (waves 0-2)
-    if (re < kRing) {
-        int rlx, rly;
-        if (re < W) {
-            rlx = re;
-            rly = 0;
-        } else if (re < 2 * W) {
-            rlx = re - W;
-            rly = H - 1;
-        } else {
-            rlx = re < 2 * W + kQ9MipsRows ? 0 : W - 1;
-            rly = 1 + (re - 2 * W) % kQ9MipsRows;
-        }
-        float g[9], jx, jy;
-        load_wrapped(g, x0 - 1 + rlx, y0 - 1 + rly);
-        q9_moments(g, srho[rly * W + rlx], jx, jy);
-    }
-    float rho[RW];
-#pragma unroll
-    for (int k = 0; k < RW; ++k) {
-        float jx, jy;
-        q9_moments(f[k], rho[k], jx, jy);
-        srho[(wv + 4 * k + 1) * W + lane + 1] = rho[k];
-    }
-    __syncthreads();
-    const int x = x0 + lane;
-#pragma unroll
-    for (int k = 0; k < RW; ++k) {
-        const int r = wv + 4 * k, y = y0 + r;
-        if (x >= a.nx || y >= a.ny)
-            continue;
-        const int c = (r + 1) * W + lane + 1;
-        float nb[9];
-        nb[0] = rho[k];
-        nb[1] = srho[c + 1];
-        nb[2] = srho[c + W];
-        nb[3] = srho[c - 1];
-        nb[4] = srho[c - W];
-        nb[5] = srho[c + W + 1];
-        nb[6] = srho[c + W - 1];
-        nb[7] = srho[c - W - 1];
-        nb[8] = srho[c - W + 1];
-        float ux, uy;
-        q9_mips_ustar(a, rho[k], nb, ux, uy);
-        q9_collide<F>(a, f[k], rho[k], ux, uy, (uint32_t)y * nx + (uint32_t)x, t_lo, t_hi);
-        const uint32_t own = (uint32_t)y * P + (uint32_t)x;
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            BufIO<T>::store(q9_plane_rsrc(dst, i, plane), own, 0u, Store<S>::narrow(f[k][i], q9_wr(a, i)));
-    }
+    q9_mips_tile_step<S, F>(src, dst, a, x0, y0, t_lo, t_hi, srho);
 }
 
 // ---------------------------------------------------------------------------

@@ -81,7 +81,8 @@ def test_create_rejects_bad_buffers_and_pitch():
 def test_square_lattice_validation():
     """D2Q9 takes odd ny (its checks pass and the call reaches the device: a
     HIP error without a GPU, a context with one), rejects planes of 2^32
-    bytes or more, and is refused by batched sweeps and coarse fields."""
+    bytes or more, is refused by the coarse-field calls, and in batched
+    sweeps takes one step per launch and no mixing with D2Q7."""
     import paper_1902_00530_amd as L
 
     def passes_validation(p):
@@ -98,7 +99,13 @@ def test_square_lattice_validation():
     assert passes_validation(L.make_params(32768, 32768, L.LBM_CIL, lattice=L.LBM_D2Q9, storage=L.LBM_BF16_DEV,
                                            rho_ref=1.0))
     q9 = L.make_params(128, 128, L.LBM_CIL, tau=1.0, sigma=0.05, A=0.1, B=0.3, lattice=L.LBM_D2Q9)
-    assert _sweep(L, [q9]) == L.LBM_EUNSUPPORTED and "D2Q7" in L.lbm_last_error()
+    q7 = L.make_params(128, 128, L.LBM_CIL, tau=1.0, sigma=0.05, A=0.1, B=0.3)
+    assert _sweep(L, [q9, q7]) == L.LBM_EINVAL and "velocity set" in L.lbm_last_error()
+    assert _sweep(L, [q9], tile_rows=8) == L.LBM_EINVAL and "D2Q9" in L.lbm_last_error()
+    q9m = L.make_params(128, 128, L.LBM_MIPS, tau=2.0, rho_star=1.0, lattice=L.LBM_D2Q9)
+    assert _sweep(L, [q9m], tile_rows=4) == L.LBM_EINVAL
+    q9h = L.make_params(128, 128, L.LBM_CIL, storage=L.LBM_BF16_DEV, rho_ref=1.0, lattice=L.LBM_D2Q9)
+    assert _sweep(L, [q9h]) == L.LBM_EUNSUPPORTED
     assert L._lib.lbm_coarsen(ctypes.byref(q9), ctypes.c_void_p(16), 4, ctypes.c_void_p(32), None) == \
         L.LBM_EUNSUPPORTED
     assert L._lib.lbm_lift(ctypes.byref(q9), ctypes.c_void_p(16), 4, ctypes.c_void_p(32), None) == \

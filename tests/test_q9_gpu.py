@@ -378,3 +378,84 @@ def test_full_size_4096(L, q9, orc, which):
     del f0
     ref = q9.run(po, g0, 1)
     assert rel_err(got, ref) < 1e-6
+
+
+# ---------------------------------------------------------------- batched sweeps
+
+def _q9_batch(model):
+    sizes = [(2, 2), (40, 7), (66, 19), (128, 64), (200, 71), (130, 33)]
+    kw = {SI.CIL: dict(tau=1.0, sigma=4 / 70, A=0.125, B=0.3),
+          SI.PASSIVE: dict(tau=1.3, sigma=0.01),
+          SI.MIPS: dict(tau=2.0, sigma=8 / 70, C=6.25, rho_star=1.6, u_max=0.3)}[model]
+    return [_cfg(model, nx, ny, seed=SI.seed_for(8, l), **kw) for l, (nx, ny) in enumerate(sizes)]
+
+
+def _q9_states(L, cfgs):
+    states = []
+    for l, c in enumerate(cfgs):
+        mips = c["model"] == SI.MIPS
+        ini = dict(mode=1, rho_mean=0.8 + 0.1 * l, rho_spread=0.1, u_mag=0.1 if mips else -1.0,
+                   pop_noise=1e-3 if mips else 0.0)
+        lat = L.Lattice(_gp(L, c), init=L.make_init(**{**FULL_INIT, **ini}))
+        torch.cuda.synchronize()
+        states.append(lat.state.clone())
+        lat.close()
+    return states
+
+
+@pytest.mark.parametrize("model,tile_rows,use_graph,steps", [
+    (SI.CIL, 1, 1, 37), (SI.CIL, 2, 0, 37), (SI.CIL, 4, 1, 37), (SI.CIL, 0, 1, 1100), (SI.PASSIVE, 0, 1, 37),
+    (SI.MIPS, 16, 1, 37), (SI.MIPS, 0, 0, 1100)])
+def test_batch_member_equals_single_run(L, model, tile_rows, use_graph, steps):
+    """D2Q9 batches run the single-lattice site and tile bodies: every member
+    of lattices of uneven sizes (odd ny, narrower than a tile) equals its
+    lbm_step run bit for bit, for every tile shape, with and without graphs,
+    across a captured chunk (1100 steps)."""
+    cfgs = _q9_batch(model)
+    states = _q9_states(L, cfgs)
+    b = L.Batch([_gp(L, c) for c in cfgs])
+    assert b.buffers[0].shape[0] == Q
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    out = b.run(steps, tile_rows=tile_rows, use_graph=use_graph)
+    for l, c in enumerate(cfgs):
+        lat = L.Lattice(_gp(L, c))
+        lat.set_state(states[l])
+        lat.step(steps)
+        o = lat.observables()
+        assert torch.equal(b.state(l), lat.state), l
+        lat.close()
+        for k in ("M", "phi", "zeta", "drho"):
+            assert abs(out[l][0][k] - o[k]) <= 1e-12 * max(1.0, abs(o[k])), (l, k)
+
+
+def test_batch_samples_density_ramp_and_oracle(L, q9, orc):
+    """Samples every 10 steps with the protocol's density change (drho / 9
+    per population) after each, against single runs with lbm_add_density bit
+    for bit; three steps against the D2Q9 oracle."""
+    cfgs = _q9_batch(SI.CIL)[2:5]
+    states = _q9_states(L, cfgs)
+    drho = [0.01, -0.02, 0.03]
+    b = L.Batch([_gp(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    out = b.run(30, sample_every=10, drho=drho)
+    for l, c in enumerate(cfgs):
+        lat = L.Lattice(_gp(L, c))
+        lat.set_state(states[l])
+        obs = []
+        for _ in range(3):
+            lat.step(10)
+            obs.append(lat.observables())
+            lat.add_density(drho[l])
+        assert torch.equal(b.state(l), lat.state), l
+        lat.close()
+        for o, s in zip(out[l], obs):
+            assert abs(o["M"] - s["M"]) <= 1e-12 * s["M"] and abs(o["drho"] - s["drho"]) <= 1e-12
+    b2 = L.Batch([_gp(L, c) for c in cfgs[:2]])
+    for l in range(2):
+        b2.set_state(l, states[l])
+    b2.run(3)
+    for l, c in enumerate(cfgs[:2]):
+        ref = q9.run(_op(orc, c), states[l].double().cpu().numpy(), 3)
+        assert rel_err(b2.state(l).double().cpu().numpy(), ref) < 3e-6
