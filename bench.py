@@ -148,10 +148,10 @@ def time_single(L, torch, cfgs, steps, warmup, storage=0, lattice=0):
     return ms, obs
 
 
-def time_batch(L, torch, cfgs, steps, warmup, tile_rows=0):
+def time_batch(L, torch, cfgs, steps, warmup, tile_rows=0, lattice=0):
     """All lattices advanced by lbm_sweep_batch (one launch per step, or per
     two steps for the two-step tiles)."""
-    lats = make_lattices(L, cfgs)
+    lats = make_lattices(L, cfgs, lattice=lattice)
     b = L.Batch([lat.params for lat in lats])
     for l, lat in enumerate(lats):
         b.set_state(l, lat.state)
@@ -463,6 +463,15 @@ def main():
         ms1, _ = time_single(L, torch, bcfgs, kb, 10)
         var["batch256_phase_sweep"] = {
             "lattices": len(bcfgs), "sites": nb_sites,
+            "MLUPS_batched": round(nb_sites * kb / (msb / 1e3) / 1e6, 1),
+            "MLUPS_one_by_one": round(nb_sites * kb / (ms1 / 1e3) / 1e6, 1),
+            "speedup": round(ms1 / msb, 3),
+            "field_error": "0 (batch members equal single runs bit for bit)"}
+        # the same sweep on the square lattice (D2Q9, one step per launch)
+        msb, _ = time_batch(L, torch, bcfgs, kb, 10, lattice=L.LBM_D2Q9)
+        ms1, _ = time_single(L, torch, bcfgs, kb, 10, lattice=L.LBM_D2Q9)
+        var["q9_batch256_phase_sweep"] = {
+            "lattices": len(bcfgs), "sites": nb_sites, "tile_rows": time_batch.tile_rows,
             "MLUPS_batched": round(nb_sites * kb / (msb / 1e3) / 1e6, 1),
             "MLUPS_one_by_one": round(nb_sites * kb / (ms1 / 1e3) / 1e6, 1),
             "speedup": round(ms1 / msb, 3),
