@@ -169,6 +169,155 @@ __global__ __launch_bounds__(256) void k_batch_q9_step_mips(const BatchTile *__r
                                (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32), srho);
 }
 
+// D2Q9, two steps per launch on a 64 x TY tile (the scheme of k_batch_step2
+// below on the square lattice).  The second step reads population i of site
+// (lx, ly) from the first step's site (lx - e_ix, ly - e_iy), local
+// coordinates (lx, ly) = (x - x0 + 1, y - y0 + 1): every plane keeps TY rows
+// of the widened tile's 66 columns, starting one row lower (e_iy = 1: planes
+// 2, 5, 6), on the tile's rows (e_iy = 0: 0, 1, 3) or one row higher
+// (e_iy = -1: 4, 7, 8).  At TY = 16 that is 38,016 bytes, four blocks per CU.
+template <int TY>
+struct Q9MidLayout {
+    static constexpr int W = 66;
+    static constexpr int kSize = 9 * TY * W;
+    __host__ __device__ static constexpr int row0(int i)
+    {
+        return (i == 2 || i == 5 || i == 6) ? 0 : (i == 4 || i == 7 || i == 8) ? 2 : 1;
+    }
+    __device__ static int at(int i, int lx, int ly) { return (i * TY + ly - row0(i)) * W + lx; }
+    __device__ static bool kept(int i, int ly)
+    {
+        const int r = ly - row0(i);
+        return r >= 0 && r < TY;
+    }
+};
+
+template <int M, int F, int TY, int NW>
+__global__ __launch_bounds__(64 * NW) void k_batch_q9_step2(const BatchTile *__restrict__ tiles,
+                                                            const LatDesc *__restrict__ lats,
+                                                            const Ctrl *__restrict__ ctrl, int step_off,
+                                                            int launch_off)
+{
+    using ML = Q9MidLayout<TY>;
+    constexpr int W = 66, H = TY + 2;
+    static_assert(NW % 2 == 0 && TY % NW == 0 && 2 * (TY + 2) <= 64 * (NW - 2), "rows per wave split evenly; edges fit");
+    __shared__ float mid[ML::kSize];
+    const BatchTile tl = tiles[blockIdx.x];
+    const LatDesc &L = lats[tl.lat];
+    const StepArgs a = L.a;
+    const int64_t t = ctrl->t0 + step_off;
+    const int64_t t1 = t + 1;
+    const int par = (int)((ctrl->k0 + launch_off) & 1);
+    const int x0 = tl.tx * 64, y0 = tl.ty * TY;
+    if (x0 >= a.nx || y0 >= a.ny)  // whole-block exit, before the barrier
+        return;
+    const uint32_t plane = (uint32_t)a.plane, nx = (uint32_t)a.nx;
+    const float *src = (const float *)L.buf[par];
+    float *dst = (float *)L.buf[par ^ 1];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
+    const uint32_t ta_lo = (uint32_t)((uint64_t)t & 0xffffffffu), ta_hi = (uint32_t)((uint64_t)t >> 32);
+    const uint32_t tb_lo = (uint32_t)((uint64_t)t1 & 0xffffffffu), tb_hi = (uint32_t)((uint64_t)t1 >> 32);
+    // sources two sites around the tile do not wrap: wave-uniform row bases
+    const bool interior = x0 >= 2 && x0 + 66 <= a.nx && y0 >= 2 && y0 + TY + 2 <= a.ny;
+
+    // first step on the widened tile, from HBM into LDS (wave w: rows w,
+    // w+NW, ...; waves 2 and up take the two edge columns in their last slot)
+    constexpr int NR = (H + NW - 1) / NW;
+    float f[NR][9];
+    uint32_t site[NR];
+    auto load_row = [&](float *g, uint32_t &st, int ly, bool in) {
+        if (in) {
+            const uint32_t c = (uint32_t)(y0 - 1 + ly) * nx + (uint32_t)x0;  // offset of (x0, y)
+            const uint32_t e[9] = {c, c - 1u, c - nx, c + 1u, c + nx, c - nx - 1u, c - nx + 1u, c + nx + 1u,
+                                   c + nx - 1u};
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                g[i] = BufIO<float>::load(q9_plane_rsrc(src, i, plane), lane, e[i]);
+            st = c + (uint32_t)lane;
+        } else {
+            const Q9Sources q = q9_sources(a, wrap_coord(x0 + lane, a.nx), wrap_coord(y0 - 1 + ly, a.ny));
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                g[i] = BufIO<float>::load(q9_plane_rsrc(src, i, plane), q.idx[i], 0u);
+            st = q.idx[0];  // pitch nx: own offset = site index
+        }
+    };
+    auto compute = [&](float *g, uint32_t st, int lx, int ly) {
+        float rho, jx, jy, ux, uy;
+        q9_moments(g, rho, jx, jy);
+        local_ustar<M>(a, rho, jx, jy, ux, uy);
+        q9_collide<F>(a, g, rho, ux, uy, st, ta_lo, ta_hi);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            if (ML::kept(i, ly))
+                mid[ML::at(i, lx, ly)] = g[i];
+    };
+    if (interior) {
+#pragma unroll
+        for (int k = 0; k < NR - 1; ++k)
+            load_row(f[k], site[k], wv + NW * k, true);
+    } else {
+#pragma unroll
+        for (int k = 0; k < NR - 1; ++k)
+            load_row(f[k], site[k], wv + NW * k, false);
+    }
+    const int e = (wv - 2) * 64 + lane;
+    const bool edge = wv >= 2;
+    const int elx = edge ? (e < H ? 0 : W - 1) : lane + 1;
+    const int ely = edge ? (e < H ? e : e - H) : wv + NW * (NR - 1);
+    bool elive = true;
+    if (!edge) {
+        load_row(f[NR - 1], site[NR - 1], ely, interior);
+    } else {
+        elive = e < 2 * H;
+        if (elive) {
+            const Q9Sources q = q9_sources(a, wrap_coord(x0 - 1 + elx, a.nx), wrap_coord(y0 - 1 + ely, a.ny));
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                f[NR - 1][i] = BufIO<float>::load(q9_plane_rsrc(src, i, plane), q.idx[i], 0u);
+            site[NR - 1] = q.idx[0];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NR - 1; ++k)
+        compute(f[k], site[k], lane + 1, wv + NW * k);
+    if (elive)
+        compute(f[NR - 1], site[NR - 1], elx, ely);
+    __syncthreads();
+
+    // second step on the tile, from LDS into HBM
+    auto second = [&](int r) {
+        const int lx = lane + 1, ly = r + 1;
+        float g[9];
+        g[0] = mid[ML::at(0, lx, ly)];
+        g[1] = mid[ML::at(1, lx - 1, ly)];
+        g[2] = mid[ML::at(2, lx, ly - 1)];
+        g[3] = mid[ML::at(3, lx + 1, ly)];
+        g[4] = mid[ML::at(4, lx, ly + 1)];
+        g[5] = mid[ML::at(5, lx - 1, ly - 1)];
+        g[6] = mid[ML::at(6, lx + 1, ly - 1)];
+        g[7] = mid[ML::at(7, lx + 1, ly + 1)];
+        g[8] = mid[ML::at(8, lx - 1, ly + 1)];
+        float rho, jx, jy, ux, uy;
+        q9_moments(g, rho, jx, jy);
+        local_ustar<M>(a, rho, jx, jy, ux, uy);
+        const uint32_t row = (uint32_t)(y0 + r) * nx + (uint32_t)x0;  // pitch nx
+        q9_collide<F>(a, g, rho, ux, uy, row + (uint32_t)lane, tb_lo, tb_hi);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            BufIO<float>::store(q9_plane_rsrc(dst, i, plane), lane, row, g[i]);
+    };
+    if (interior) {
+        for (int r = wv; r < TY; r += NW)
+            second(r);
+    } else {
+        for (int r = wv; r < TY; r += NW)
+            if (x0 + lane < a.nx && y0 + r < a.ny)
+                second(r);
+    }
+}
+
 // Step t+1 on the widened tile as the second step reads it, in local
 // coordinates (lx, ly) = (x - x0 + 1, y - y0 + 1): population 0 only at the
 // tile's own sites (TY rows of 64), 1 and 4 on the tile's rows (ly 1..TY),
@@ -661,6 +810,18 @@ static hipError_t launch_batch_mips_f(int shape, int64_t ntiles, const BatchTile
     return hipGetLastError();
 }
 
+template <int M, int F>
+static void launch_q9_two(int ty, int64_t ntiles, const BatchTile *tiles, const LatDesc *lats, const Ctrl *ctrl,
+                          int step_off, int launch_off, hipStream_t s)
+{
+    if (ty == 8)
+        hipLaunchKernelGGL((k_batch_q9_step2<M, F, 8, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
+                           step_off, launch_off);
+    else
+        hipLaunchKernelGGL((k_batch_q9_step2<M, F, 16, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats,
+                           ctrl, step_off, launch_off);
+}
+
 template <int F>
 static hipError_t launch_batch_q9_f(int model, int shape, int64_t ntiles, const BatchTile *tiles, const LatDesc *lats,
                                     const Ctrl *ctrl, int step_off, int launch_off, hipStream_t s)
@@ -669,6 +830,10 @@ static hipError_t launch_batch_q9_f(int model, int shape, int64_t ntiles, const 
     if (model == kMips)
         hipLaunchKernelGGL((k_batch_q9_step_mips<F>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
                            step_off, launch_off);
+    else if (sh.steps == 2 && model == kCil)
+        launch_q9_two<kCil, F>(sh.ty, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+    else if (sh.steps == 2)
+        launch_q9_two<kPassive, F>(sh.ty, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
     else if (model == kCil)
         hipLaunchKernelGGL((k_batch_q9_step<kCil, F>), dim3((unsigned)ntiles), dim3(sh.tx, sh.ty), 0, s, tiles, lats,
                            ctrl, step_off, launch_off);
@@ -855,22 +1020,21 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     int shape = -1;
     const bool mips = ps[0].model == LBM_MIPS, q9 = ps[0].lattice == LBM_D2Q9;
     // the shapes this model and lattice may take (tuned among themselves):
-    // D2Q9 takes one step per launch (local models 256x1, 128x2, 64x4; MIPS
-    // 64x16)
+    // MIPS one step per launch (D2Q7 64x16 or 64x4, D2Q9 64x16), the local
+    // models every shape
     std::vector<int> cands;
     if (mips)
         cands = q9 ? std::vector<int>{kMipsShape} : std::vector<int>{kMipsShape, kMipsShape4};
     else
-        for (int k = 0; k < (q9 ? kNumTuned - 2 : kNumTuned); ++k)
+        for (int k = 0; k < kNumTuned; ++k)
             cands.push_back(k);
     for (int k : cands)
         if (o->tile_rows == kShapes[k].ty)
             shape = k;
     if (shape < 0 && o->tile_rows != 0)
-        return fail(LBM_EINVAL, q9 ? (mips ? "D2Q9 MIPS batches take tile_rows 0 or 16"
-                                           : "D2Q9 batches take tile_rows 0, 1, 2 or 4 (one step per launch)")
-                                   : mips ? "MIPS batches take tile_rows 0, 4 or 16 (64-wide tiles, one step per launch)"
-                                          : "tile_rows must be 0, 1, 2, 4, 8 or 16");
+        return fail(LBM_EINVAL, mips ? (q9 ? "D2Q9 MIPS batches take tile_rows 0 or 16"
+                                          : "MIPS batches take tile_rows 0, 4 or 16 (64-wide tiles, one step per launch)")
+                                     : "tile_rows must be 0, 1, 2, 4, 8 or 16");
     const std::string sig = signature(ps, n, flags);
     if (shape < 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);

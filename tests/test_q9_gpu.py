@@ -405,12 +405,14 @@ def _q9_states(L, cfgs):
 
 @pytest.mark.parametrize("model,tile_rows,use_graph,steps", [
     (SI.CIL, 1, 1, 37), (SI.CIL, 2, 0, 37), (SI.CIL, 4, 1, 37), (SI.CIL, 0, 1, 1100), (SI.PASSIVE, 0, 1, 37),
+    (SI.CIL, 16, 1, 37), (SI.CIL, 8, 0, 38), (SI.PASSIVE, 16, 1, 39), (SI.CIL, 16, 1, 1100),
     (SI.MIPS, 16, 1, 37), (SI.MIPS, 0, 0, 1100)])
 def test_batch_member_equals_single_run(L, model, tile_rows, use_graph, steps):
     """D2Q9 batches run the single-lattice site and tile bodies: every member
     of lattices of uneven sizes (odd ny, narrower than a tile) equals its
-    lbm_step run bit for bit, for every tile shape, with and without graphs,
-    across a captured chunk (1100 steps)."""
+    lbm_step run bit for bit, for every tile shape (one step per launch, or
+    two on 64 x 8 and 64 x 16 tiles with the first step widened into LDS),
+    with and without graphs, across a captured chunk (1100 steps)."""
     cfgs = _q9_batch(model)
     states = _q9_states(L, cfgs)
     b = L.Batch([_gp(L, c) for c in cfgs])
