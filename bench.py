@@ -446,6 +446,11 @@ def main():
             else:
                 v["speedup_vs_f32"] = round(q9f32 / per, 3)
             var["q9_cil4096_" + name] = v
+        # D2Q9 at 4096^2 through the batched path (tuned: two steps per launch)
+        msq2, _ = time_batch(L, torch, q9c, 200, 10, lattice=L.LBM_D2Q9)
+        var["q9_cil4096_f32_two_step"] = {"MLUPS": round(nbig * 200 / (msq2 / 1e3) / 1e6, 1),
+                                          "tile_rows": time_batch.tile_rows,
+                                          "speedup_vs_f32_one_step": round(q9f32 / (msq2 / 1e3 / 200), 3)}
         msq, _ = time_single(L, torch, [SI.q9_mips_4096()], 100, 10, lattice=L.LBM_D2Q9)
         rq = roofline(0, nbig, msq / 1e3 / 100, "k_q9_step_mips<F32,noisy>", q=9)
         var["q9_mips4096_f32"] = {"MLUPS": round(nbig * 100 / (msq / 1e3) / 1e6, 1), "GBps": rq["achieved"],
@@ -467,7 +472,7 @@ def main():
             "MLUPS_one_by_one": round(nb_sites * kb / (ms1 / 1e3) / 1e6, 1),
             "speedup": round(ms1 / msb, 3),
             "field_error": "0 (batch members equal single runs bit for bit)"}
-        # the same sweep on the square lattice (D2Q9, one step per launch)
+        # the same sweep on the square lattice (D2Q9, tuned tiles)
         msb, _ = time_batch(L, torch, bcfgs, kb, 10, lattice=L.LBM_D2Q9)
         ms1, _ = time_single(L, torch, bcfgs, kb, 10, lattice=L.LBM_D2Q9)
         var["q9_batch256_phase_sweep"] = {
