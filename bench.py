@@ -51,7 +51,8 @@ def parse():
                     choices=["cil1024x5", "cil4096", "q9_cil4096", "q9_mips4096"],
                     help="q9_*: the square-lattice (D2Q9) variant, one launch per step")
     ap.add_argument("--storage", type=int, default=0, help="0 f32, 1 bf16 deviations, 2 fp16 deviations")
-    ap.add_argument("--mode", default="batch", choices=["batch", "single"])
+    ap.add_argument("--mode", default=None, choices=["batch", "single"],
+                    help="default: batch for the D2Q7 FP32 workloads, single (lbm_step) otherwise")
     ap.add_argument("--quick", action="store_true", help="headline measurement only (no variants)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=25)
@@ -211,6 +212,8 @@ def copy_probe(torch, copies):
 KERNEL_SOURCES = ("batch.hip", "capi.hip", "device.h", "internal.h")
 # sources of the square-lattice (D2Q9) step kernels
 Q9_SOURCES = ("q9.hip", "device_q9.h", "device.h", "capi.hip", "internal.h")
+# sources of the batched D2Q9 kernels
+KERNEL_SOURCES_Q9B = ("batch.hip", "device_q9.h", "device.h", "capi.hip", "internal.h")
 
 
 def source_fingerprint(files=KERNEL_SOURCES):
@@ -280,6 +283,16 @@ def roofline_two_step(sites, per_launch_s, kernel, rows):
     return r
 
 
+def roofline_q9_two_step(sites, per_launch_s, kernel):
+    """D2Q9, two steps per launch: the state (72 B per site in FP32) crosses
+    HBM once per launch for two site-updates; reported against the HBM peak
+    (the D2Q9 VALU count is not measured)."""
+    r = roofline(0, sites, per_launch_s, kernel, q=9)
+    r["site_updates_per_launch"] = 2 * sites
+    r["note"] = "algorithmic bytes of one read and one write of the state per launch (two site-updates)"
+    return r
+
+
 def roofline(storage, sites_per_launch, per_launch_s, kernel, q=7):
     """HBM roofline of a one-step kernel: each site's q populations read once
     and written once (q = 7 triangular, 9 square lattice)."""
@@ -319,15 +332,21 @@ def main():
         cfgs, lattice, q = [SI.q9_mips_4096()], L.LBM_D2Q9, 9
         wname = "MIPS 4096x4096 periodic D2Q9, mean density 1.0 (x8 scaled), sigma 8/70, tau 2"
     sites = sum(c["nx"] * c["ny"] for c in cfgs)
-    mode = args.mode if args.storage == 0 and lattice == 0 else "single"
+    mode = args.mode or ("batch" if lattice == 0 else "single")
+    if args.storage != 0:
+        mode = "single"
 
     t_wall = time.perf_counter()
     rows = 0
     if mode == "batch":
-        ms, obs = time_batch(L, torch, cfgs, args.steps, args.warmup, args.tile_rows)
+        ms, obs = time_batch(L, torch, cfgs, args.steps, args.warmup, args.tile_rows, lattice)
         rows = time_batch.tile_rows
         two, one = batch_launches(args.steps, rows)
-        if two:
+        if lattice:
+            launches = two + 0.5 * one if two else args.steps
+            kernel = (f"k_batch_q9_step2<CIL,unit-tau,noisy,{rows}> (64x{rows} tiles, two steps per launch)" if two
+                      else f"k_batch_q9_step (one step per launch, tile rows {rows})")
+        elif two:
             # a one-step launch moves the same bytes as a two-step launch
             # and does half the site work: count it as half a launch
             launches = two + 0.5 * one
@@ -362,15 +381,20 @@ def main():
         "dtype": {0: "f32", 1: "bf16 storage, f32 math", 2: "f16 storage, f32 math"}[args.storage],
         "data": "synthetic",
         "config": {"workload": wname, "lattices": len(cfgs), "sites": sites, "storage": args.storage,
-                   "mode": mode},
-        "roofline": (roofline_two_step(sites, per_launch, kernel, rows) if rows >= 8 else
-                     roofline(args.storage, sites / (launches / args.steps), per_launch, kernel, q)),
+                   "mode": mode, **({"tile_rows": rows} if mode == "batch" else {})},
+        "roofline": (roofline_two_step(sites, per_launch, kernel, rows) if rows >= 8 and not lattice else
+                     roofline(args.storage, sites / (launches / args.steps), per_launch, kernel, q)
+                     if rows < 8 else roofline_q9_two_step(sites, per_launch, kernel)),
         "phi": [round(o["phi"], 6) for o in obs],
         "wall_s": round(wall, 3),
     }
 
     if args.workload == "q9_cil4096" and args.storage == 0:
-        attach_traffic(line["roofline"], "counters_k_q9_step_local_cil_4096.json", Q9_SOURCES, sites, per_launch)
+        if mode == "single":
+            attach_traffic(line["roofline"], "counters_k_q9_step_local_cil_4096.json", Q9_SOURCES, sites, per_launch)
+        elif rows >= 8:
+            attach_traffic(line["roofline"], f"counters_k_batch_q9_step2_{rows}_cil_4096.json", KERNEL_SOURCES_Q9B,
+                           sites, per_launch)
 
     if mode == "batch" and args.workload == "cil1024x5" and args.storage == 0 and rows < 8:
         c = measured_traffic(f"counters_k_batch_step_{rows}_cil_5x1024.json")

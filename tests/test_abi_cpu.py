@@ -82,7 +82,8 @@ def test_square_lattice_validation():
     """D2Q9 takes odd ny (its checks pass and the call reaches the device: a
     HIP error without a GPU, a context with one), rejects planes of 2^32
     bytes or more, is refused by the coarse-field calls, and in batched
-    sweeps takes one step per launch and no mixing with D2Q7."""
+    sweeps takes every tile shape on the local models (64 x 16 only on
+    MIPS) and no mixing with D2Q7."""
     import paper_1902_00530_amd as L
 
     def passes_validation(p):
@@ -101,9 +102,12 @@ def test_square_lattice_validation():
     q9 = L.make_params(128, 128, L.LBM_CIL, tau=1.0, sigma=0.05, A=0.1, B=0.3, lattice=L.LBM_D2Q9)
     q7 = L.make_params(128, 128, L.LBM_CIL, tau=1.0, sigma=0.05, A=0.1, B=0.3)
     assert _sweep(L, [q9, q7]) == L.LBM_EINVAL and "velocity set" in L.lbm_last_error()
-    assert _sweep(L, [q9], tile_rows=8) == L.LBM_EINVAL and "D2Q9" in L.lbm_last_error()
+    for rows in (1, 2, 4, 8, 16):  # the local models take every tile shape, two-step ones included
+        assert _sweep(L, [q9], tile_rows=rows) in (L.LBM_OK, L.LBM_EHIP)
+    assert _sweep(L, [q9], tile_rows=32) == L.LBM_EINVAL
     q9m = L.make_params(128, 128, L.LBM_MIPS, tau=2.0, rho_star=1.0, lattice=L.LBM_D2Q9)
-    assert _sweep(L, [q9m], tile_rows=4) == L.LBM_EINVAL
+    for rows in (4, 8):
+        assert _sweep(L, [q9m], tile_rows=rows) == L.LBM_EINVAL and "D2Q9" in L.lbm_last_error()
     q9h = L.make_params(128, 128, L.LBM_CIL, storage=L.LBM_BF16_DEV, rho_ref=1.0, lattice=L.LBM_D2Q9)
     assert _sweep(L, [q9h]) == L.LBM_EUNSUPPORTED
     assert L._lib.lbm_coarsen(ctypes.byref(q9), ctypes.c_void_p(16), 4, ctypes.c_void_p(32), None) == \
