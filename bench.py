@@ -40,6 +40,9 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # summary in profiles/; this is the last measured value, used when that
 # summary was taken on other kernel sources.
 VALU_PER_SITE_UPDATE = 185
+# the same for the square lattice (D2Q9): the one-step batch kernel with one
+# site per lane (256 x 1 tiles), CIL, FP32, tau 1, noise on
+Q9_VALU_PER_SITE_UPDATE = 223
 
 
 def parse():
@@ -283,14 +286,28 @@ def roofline_two_step(sites, per_launch_s, kernel, rows):
     return r
 
 
+def q9_valu_per_site_update():
+    """valu_per_site_update() of the D2Q9 one-step batch kernel (256 x 1
+    tiles), from its counter summary when taken on the current sources."""
+    c = measured_traffic("counters_k_batch_q9_step_1_cil_4096.json", KERNEL_SOURCES_Q9B)
+    if c is not None and c.get("valu_lane_instructions_per_site_update"):
+        return float(c["valu_lane_instructions_per_site_update"]), "counters_k_batch_q9_step_1_cil_4096.json"
+    return float(Q9_VALU_PER_SITE_UPDATE), "stated (counter summary taken on other kernel sources)"
+
+
 def roofline_q9_two_step(sites, per_launch_s, kernel):
-    """D2Q9, two steps per launch: the state (72 B per site in FP32) crosses
-    HBM once per launch for two site-updates; reported against the HBM peak
-    (the D2Q9 VALU count is not measured)."""
-    r = roofline(0, sites, per_launch_s, kernel, q=9)
-    r["site_updates_per_launch"] = 2 * sites
-    r["note"] = "algorithmic bytes of one read and one write of the state per launch (two site-updates)"
-    return r
+    """D2Q9, two steps per launch: 2 x sites site-updates of VALU work (the
+    one-step kernel's count per update) against the VALU issue peak; the HBM
+    side is the state (72 B per site in FP32) read and written once."""
+    vpu, vsrc = q9_valu_per_site_update()
+    tops = vpu * 2 * sites / per_launch_s / 1e12
+    hbm = 72 * sites / per_launch_s / 1e9
+    return {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+            "unit": "T VALU lane-instructions/s", "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": None,
+            "kernel": kernel, "avg_launch_us": round(per_launch_s * 1e6, 3),
+            "valu_per_site_update": vpu, "valu_per_site_update_source": vsrc, "site_updates_per_launch": 2 * sites,
+            "hbm": {"achieved": round(hbm, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": round(hbm / HBM_PEAK_GBPS, 4), "bytes_per_launch": 72 * sites}}
 
 
 def roofline(storage, sites_per_launch, per_launch_s, kernel, q=7):
