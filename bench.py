@@ -51,11 +51,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="cil1024x5",
-                    choices=["cil1024x5", "cil4096", "q9_cil4096", "q9_mips4096"],
-                    help="q9_*: the square-lattice (D2Q9) variant, one launch per step")
+                    choices=["cil1024x5", "cil4096", "mips4096", "q9_cil4096", "q9_mips4096"],
+                    help="mips4096: the 64 x 64 MIPS workload's parameters on 4096 x 4096; q9_*: the "
+                         "square-lattice (D2Q9) variant, one launch per step")
     ap.add_argument("--storage", type=int, default=0, help="0 f32, 1 bf16 deviations, 2 fp16 deviations")
     ap.add_argument("--mode", default=None, choices=["batch", "single"],
-                    help="default: batch for the D2Q7 FP32 workloads, single (lbm_step) otherwise")
+                    help="default: batch for the D2Q7 CIL workloads in FP32, single (lbm_step) otherwise")
     ap.add_argument("--quick", action="store_true", help="headline measurement only (no variants)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=25)
@@ -217,6 +218,8 @@ KERNEL_SOURCES = ("batch.hip", "capi.hip", "device.h", "internal.h")
 Q9_SOURCES = ("q9.hip", "device_q9.h", "device.h", "capi.hip", "internal.h")
 # sources of the batched D2Q9 kernels
 KERNEL_SOURCES_Q9B = ("batch.hip", "device_q9.h", "device.h", "capi.hip", "internal.h")
+# sources of the single-lattice D2Q7 step kernels (lbm_step)
+STEP_SOURCES = ("step.hip", "device.h", "capi.hip", "internal.h")
 
 
 def source_fingerprint(files=KERNEL_SOURCES):
@@ -342,6 +345,9 @@ def main():
     elif args.workload == "cil4096":
         cfgs = [SI.cil_4096()]
         wname = "CIL 4096x4096 periodic D2Q7, mean density 0.74 (x4 scaled), sigma 4/70, tau 1"
+    elif args.workload == "mips4096":
+        cfgs = [dict(SI.mips_small(), nx=4096, ny=4096)]
+        wname = "MIPS 4096x4096 periodic D2Q7, mean density 1.0 (x8 scaled), sigma 8/70, tau 2"
     elif args.workload == "q9_cil4096":
         cfgs, lattice, q = [SI.q9_cil_4096()], L.LBM_D2Q9, 9
         wname = "CIL 4096x4096 periodic D2Q9, mean density 0.74 (x4 scaled), sigma 4/70, tau 1"
@@ -349,8 +355,8 @@ def main():
         cfgs, lattice, q = [SI.q9_mips_4096()], L.LBM_D2Q9, 9
         wname = "MIPS 4096x4096 periodic D2Q9, mean density 1.0 (x8 scaled), sigma 8/70, tau 2"
     sites = sum(c["nx"] * c["ny"] for c in cfgs)
-    mode = args.mode or ("batch" if lattice == 0 else "single")
-    if args.storage != 0:
+    mode = args.mode or ("batch" if args.workload in ("cil1024x5", "cil4096") else "single")
+    if args.storage != 0 or args.workload == "mips4096":  # lbm_step only
         mode = "single"
 
     t_wall = time.perf_counter()
@@ -378,13 +384,15 @@ def main():
         st = {0: "F32", 1: "BF16dev", 2: "F16dev"}[args.storage]
         launches = args.steps * len(cfgs)
         kernel = {"q9_cil4096": f"k_q9_step_local<CIL,{st},unit-tau,noisy>",
-                  "q9_mips4096": f"k_q9_step_mips<{st},noisy>"}.get(args.workload,
+                  "q9_mips4096": f"k_q9_step_mips<{st},noisy>",
+                  "mips4096": f"k_step_mips<{st},noisy>"}.get(args.workload,
                                                                      f"k_step_local<CIL,{st},unit-tau,noisy>")
     wall = time.perf_counter() - t_wall
     per_launch = ms / 1e3 / launches
     mlups = sites * args.steps / (ms / 1e3) / 1e6
     line = {
-        "metric": ("MLUPS of the fused CIL step (FP32) and % of HBM peak" if lattice == 0 else
+        "metric": ("MLUPS of the fused MIPS step" if args.workload == "mips4096" else
+                   "MLUPS of the fused CIL step (FP32) and % of HBM peak" if lattice == 0 else
                    f"MLUPS of the fused D2Q9 {'MIPS' if args.workload == 'q9_mips4096' else 'CIL'} step"),
         "value": round(mlups, 1),
         "unit": "MLUPS",
@@ -412,6 +420,9 @@ def main():
         elif rows >= 8:
             attach_traffic(line["roofline"], f"counters_k_batch_q9_step2_{rows}_cil_4096.json", KERNEL_SOURCES_Q9B,
                            sites, per_launch)
+
+    if args.workload == "mips4096" and args.storage == 0:
+        attach_traffic(line["roofline"], "counters_k_step_mips_4096.json", STEP_SOURCES, sites, per_launch)
 
     if mode == "batch" and args.workload == "cil1024x5" and args.storage == 0 and rows < 8:
         c = measured_traffic(f"counters_k_batch_step_{rows}_cil_5x1024.json")
