@@ -533,6 +533,19 @@ def main():
             "MLUPS_one_by_one": round(nb_sites * kb / (ms1 / 1e3) / 1e6, 1),
             "speedup": round(ms1 / msb, 3),
             "field_error": "0 (batch members equal single runs bit for bit)"}
+        # the paper's MIPS batch: 12 lattices of 90 x 30 (six densities, two
+        # repeats), 20000 steps, in each batch form
+        mcf = [dict(nx=90, ny=30, model=SI.MIPS, tau=2.0, sigma=1.0 / 70.0, A=0.0, B=0.0, C=50.0, rho_star=0.2,
+                    u_max=0.3, seed=SI.seed_for(11, l),
+                    init=dict(mode=1, rho_mean=r, rho_spread=0.0, angle_std=0.0, u_mag=0.1, pop_noise=1e-3))
+               for l, r in enumerate((0.06, 0.08, 0.10, 0.125, 0.15, 0.18) * 2)]
+        forms = {}
+        for name, rows in (("64x16", 16), ("64x4", 4), ("resident", L.LBM_TILE_RESIDENT), ("tuned", 0)):
+            msr, _ = time_batch(L, torch, mcf, 20000, 1000, rows)
+            forms[name] = {"us_per_step": round(msr * 1e3 / 20000, 3),
+                           "MLUPS": round(12 * 2700 * 20000 / (msr / 1e3) / 1e6, 1)}
+        forms["tuned"]["tile_rows"] = time_batch.tile_rows
+        var["mips_paper_batch_12x90x30"] = forms
         # learned surrogate (coarse 32x32 fields of 256^2 lattices, k = 50)
         from paper_1902_00530_amd import surrogate as S
         r = S.recipe(SI.surrogate_grid(256, 11000), SI.surrogate_grid(256, 21000), SI.surrogate_grid(256, 31000),

@@ -201,6 +201,15 @@ const char *lbm_last_error(void);
  * period (its steps and the FP64 sampling kernels) is captured in HIP graphs
  * of at most 1024 steps and replayed.
  * ---------------------------------------------------------------------- */
+/* lbm_sweep_opts.tile_rows value (no tile has that many rows) for the
+ * LDS-resident form: each D2Q7 lattice of at most 4096 sites lives in the LDS
+ * of one CU (one 1024-lane workgroup per
+ * lattice) for all the steps of a captured chunk, one launch per chunk; the
+ * state crosses HBM only at the chunk's ends.  For lattices of the paper's
+ * size (90 x 30), where one launch per step leaves the GPU bound by launch
+ * latency. */
+#define LBM_TILE_RESIDENT 1024
+
 typedef struct lbm_sweep_opts {
     int64_t n_steps;      /* steps to run (a multiple of sample_every) */
     int64_t sample_every; /* observables every sample_every steps (0: once, at the end) */
@@ -210,8 +219,11 @@ typedef struct lbm_sweep_opts {
                              (the second from LDS); 0 = tuned (every shape timed on the
                              batch itself, cached per batch signature).  MIPS batches
                              take 0 (tuned), 4 or 16: 64x4 or 64x16 tiles, one step per
-                             launch, neighbour densities in LDS.  D2Q9 batches take one
-                             step per launch: 0, 1, 2 or 4 (MIPS: 0 or 16) */
+                             launch, neighbour densities in LDS.  LBM_TILE_RESIDENT (1024):
+                             whole lattices in LDS (D2Q7, every lattice at most 4096
+                             sites, any model; tuned among the others when the batch
+                             qualifies).  D2Q9 batches take 0, 1, 2, 4, 8 or 16 (MIPS:
+                             0 or 16) */
     int32_t use_graph;    /* 0: launch every kernel directly; 1: run each sample period
                              as captured HIP graphs of at most 1024 steps, kept (16 most
                              recent) and replayed by later calls with the same batch,
@@ -227,10 +239,10 @@ typedef struct lbm_sweep_opts {
  * samples per lattice (0 on invalid arguments). */
 size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samples);
 
-/* Work-tile rows (1, 2, 4, 8 or 16, as in lbm_sweep_opts.tile_rows) the
- * tuning chose for a batch with these lattices' sizes, model and step
- * variant (MIPS: 4 or 16), 0 if not tuned yet in this process; negative on
- * invalid arguments. */
+/* Work-tile rows (1, 2, 4, 8 or 16, as in lbm_sweep_opts.tile_rows, or
+ * LBM_TILE_RESIDENT) the tuning chose for a batch with these lattices' sizes,
+ * model and step variant (MIPS: 4, 16 or LBM_TILE_RESIDENT), 0 if not tuned
+ * yet in this process; negative on invalid arguments. */
 int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n);
 
 /* Run a batch.  ps[n]: per-lattice parameters; every lattice uses the same

@@ -131,6 +131,99 @@ __global__ __launch_bounds__(256) void k_batch_step_mips(const BatchTile *__rest
                             (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32), srho);
 }
 
+// Whole lattices resident in LDS (D2Q7, at most kResidentSites sites each):
+// one workgroup of 1024 lanes per lattice runs every step of the launch
+// without leaving its CU.  The state is read from HBM once; each step pulls
+// every site's populations out of LDS into registers (for MIPS also putting
+// each site's density into LDS), waits, collides with the site body of the
+// tile kernels and writes the populations back to LDS in place; after the
+// last step the state goes to HBM, into the buffer the step count's parity
+// names (as after the same number of one-step launches).  A lattice of the
+// paper's size (90 x 30) then costs one CU for a whole sample period instead
+// of a launch per step.  Results equal the tile kernels' bit for bit.
+constexpr int kResidentSites = 4096;
+constexpr int kResidentLanes = 1024;
+constexpr int kResidentPer = (kResidentSites + kResidentLanes - 1) / kResidentLanes;  // sites per lane
+
+template <int M, int F>
+__global__ __launch_bounds__(kResidentLanes) void k_batch_resident(const LatDesc *__restrict__ lats,
+                                                                  const Ctrl *__restrict__ ctrl, int steps)
+{
+    __shared__ float st[8 * kResidentSites];  // plane i of the state at i * S, densities at 7 * S
+    const LatDesc &L = lats[blockIdx.x];
+    const StepArgs a = L.a;  // pitch nx: plane i holds S = nx * ny contiguous floats
+    const int S = a.nx * a.ny;
+    const int par = (int)(ctrl->k0 & 1);
+    const float *__restrict__ src = (const float *)L.buf[par];
+    float *__restrict__ dst = (float *)L.buf[par ^ (steps & 1)];
+    const int tid = threadIdx.x;
+    float *rho_l = st + 7 * S;
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        for (int e = tid; e < S; e += kResidentLanes)
+            st[i * S + e] = src[(int64_t)i * a.plane + e];
+    // this lane's sites s = tid + j * 1024 and their coordinates
+    int sx[kResidentPer], sy[kResidentPer];
+#pragma unroll
+    for (int j = 0; j < kResidentPer; ++j) {
+        const int s = tid + j * kResidentLanes;
+        sy[j] = s / a.nx;
+        sx[j] = s - sy[j] * a.nx;
+    }
+    __syncthreads();
+    const int64_t t0 = ctrl->t0;
+    for (int k = 0; k < steps; ++k) {
+        const uint64_t t = (uint64_t)(t0 + k);
+        const uint32_t tlo = (uint32_t)(t & 0xffffffffu), thi = (uint32_t)(t >> 32);
+        float f[kResidentPer][7], rho[kResidentPer], jx[kResidentPer], jy[kResidentPer];
+#pragma unroll
+        for (int j = 0; j < kResidentPer; ++j) {
+            const int s = tid + j * kResidentLanes;
+            if (s < S) {
+                const PullSources32 q = pull_sources32(a, sx[j], sy[j]);
+#pragma unroll
+                for (int i = 0; i < 7; ++i)
+                    f[j][i] = st[i * S + (int)q.idx[i]];
+                site_moments(f[j], rho[j], jx[j], jy[j]);
+                if (M == kMips)
+                    rho_l[s] = rho[j];
+            }
+        }
+        __syncthreads();  // every pull done (the state may be overwritten), densities in place
+#pragma unroll
+        for (int j = 0; j < kResidentPer; ++j) {
+            const int s = tid + j * kResidentLanes;
+            if (s < S) {
+                float ux, uy;
+                if (M == kMips) {
+                    // density at r + e_i: the pull source of the opposite population
+                    const PullSources32 q = pull_sources32(a, sx[j], sy[j]);
+                    float nb[7];
+                    nb[0] = rho[j];
+                    nb[1] = rho_l[q.idx[4]];
+                    nb[2] = rho_l[q.idx[5]];
+                    nb[3] = rho_l[q.idx[6]];
+                    nb[4] = rho_l[q.idx[1]];
+                    nb[5] = rho_l[q.idx[2]];
+                    nb[6] = rho_l[q.idx[3]];
+                    mips_ustar(a, rho[j], nb, ux, uy);
+                } else {
+                    local_ustar<M>(a, rho[j], jx[j], jy[j], ux, uy);
+                }
+                site_collide<F>(a, f[j], rho[j], ux, uy, (uint32_t)s, tlo, thi);
+#pragma unroll
+                for (int i = 0; i < 7; ++i)
+                    st[i * S + s] = f[j][i];
+            }
+        }
+        __syncthreads();  // the step's writes precede the next step's pulls
+    }
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        for (int e = tid; e < S; e += kResidentLanes)
+            dst[(int64_t)i * a.plane + e] = st[i * S + e];
+}
+
 // The square lattice (D2Q9) over the tile list: the single-lattice site body
 // (passive, CIL) and MIPS tile body, one step per launch.
 template <int M, int F>
@@ -693,6 +786,19 @@ constexpr int kMipsShape = 5, kMipsShape4 = 6;
 static const Shape kShapes[kNumShapes] = {{256, 1, 1}, {128, 2, 1}, {64, 4, 1}, {64, 8, 2},
                                           {64, 16, 2}, {64, 16, 1}, {64, 4, 1}};
 constexpr int64_t kChunk = 1024;  // steps per captured graph, at most
+// the LDS-resident form (k_batch_resident): no tile list, every step of a
+// graph chunk in one launch; a tuning launch runs an odd number of steps, so
+// it writes the second buffer like the tile shapes' tuning launches
+constexpr int kResident = kNumShapes;
+constexpr int kResidentTuneSteps = 63;
+
+static bool resident_fits(const lbm_params *ps, int n)
+{
+    for (int l = 0; l < n; ++l)
+        if (ps[l].lattice != LBM_D2Q7 || (int64_t)ps[l].nx * ps[l].ny > kResidentSites)
+            return false;
+    return true;
+}
 
 static int64_t count_tiles(const lbm_params *ps, int n, int tx, int ty)
 {
@@ -807,6 +913,32 @@ static hipError_t launch_batch_mips_f(int shape, int64_t ntiles, const BatchTile
     else
         hipLaunchKernelGGL((k_batch_step_mips<F, kMipsRows>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats,
                            ctrl, step_off, launch_off);
+    return hipGetLastError();
+}
+
+template <int M>
+static void launch_resident_m(int flags, int n, const LatDesc *lats, const Ctrl *ctrl, int steps, hipStream_t s)
+{
+    const dim3 grd((unsigned)n), blk(kResidentLanes);
+    switch (flags) {
+    case 0: hipLaunchKernelGGL((k_batch_resident<M, 0>), grd, blk, 0, s, lats, ctrl, steps); break;
+    case kUnitTau: hipLaunchKernelGGL((k_batch_resident<M, kUnitTau>), grd, blk, 0, s, lats, ctrl, steps); break;
+    case kNoisy: hipLaunchKernelGGL((k_batch_resident<M, kNoisy>), grd, blk, 0, s, lats, ctrl, steps); break;
+    default:
+        hipLaunchKernelGGL((k_batch_resident<M, kUnitTau | kNoisy>), grd, blk, 0, s, lats, ctrl, steps);
+        break;
+    }
+}
+
+static hipError_t launch_resident(int model, int flags, int n, const LatDesc *lats, const Ctrl *ctrl, int steps,
+                                  hipStream_t s)
+{
+    if (model == LBM_MIPS)
+        launch_resident_m<kMips>(flags, n, lats, ctrl, steps, s);
+    else if (model == LBM_CIL)
+        launch_resident_m<kCil>(flags, n, lats, ctrl, steps, s);
+    else
+        launch_resident_m<kPassive>(flags, n, lats, ctrl, steps, s);
     return hipGetLastError();
 }
 
@@ -961,7 +1093,9 @@ int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n)
         return 0;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(signature(ps, n, flags));
-    return it == g_tuned.end() ? 0 : kShapes[it->second].ty;
+    if (it == g_tuned.end())
+        return 0;
+    return it->second == kResident ? LBM_TILE_RESIDENT : kShapes[it->second].ty;
 }
 
 size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samples)
@@ -1031,10 +1165,20 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     for (int k : cands)
         if (o->tile_rows == kShapes[k].ty)
             shape = k;
+    const bool resident_ok = resident_fits(ps, n);
+    if (resident_ok)
+        cands.push_back(kResident);
+    if (o->tile_rows == LBM_TILE_RESIDENT) {
+        if (!resident_ok)
+            return fail(LBM_EINVAL, "tile_rows LBM_TILE_RESIDENT needs D2Q7 lattices of at most " +
+                                        std::to_string(kResidentSites) + " sites");
+        shape = kResident;
+    }
     if (shape < 0 && o->tile_rows != 0)
         return fail(LBM_EINVAL, mips ? (q9 ? "D2Q9 MIPS batches take tile_rows 0 or 16"
-                                          : "MIPS batches take tile_rows 0, 4 or 16 (64-wide tiles, one step per launch)")
-                                     : "tile_rows must be 0, 1, 2, 4, 8 or 16");
+                                          : "MIPS batches take tile_rows 0, 4, 16 or LBM_TILE_RESIDENT")
+                                     : q9 ? "D2Q9 tile_rows must be 0, 1, 2, 4, 8 or 16"
+                                          : "tile_rows must be 0, 1, 2, 4, 8, 16 or LBM_TILE_RESIDENT");
     const std::string sig = signature(ps, n, flags);
     if (shape < 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1111,14 +1255,20 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         // them), replayed once to warm up and three times timed; the least
         // time per step wins
         for (int k : cands) {
-            auto tl = upload(k);
-            if (!tl.first)
-                return hip_fail(up_err, "tile list upload");
+            const bool res = k == kResident;
+            std::pair<BatchTile *, int64_t> tl{nullptr, 0};
+            if (!res) {
+                tl = upload(k);
+                if (!tl.first)
+                    return hip_fail(up_err, "tile list upload");
+            }
             hipStream_t cap;
             LBM_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-            for (int r10 = 0; r10 < 10 && e == hipSuccess; ++r10)  // first buffer -> second buffer
+            if (res && e == hipSuccess)  // first buffer -> second buffer
+                e = launch_resident(ps[0].model, flags, n, d_lat, d_ctrl, kResidentTuneSteps, cap);
+            for (int r10 = 0; r10 < 10 && !res && e == hipSuccess; ++r10)
                 e = launch_batch_step(ps[0].lattice, ps[0].model, flags, k, tl.second, tl.first, d_lat, d_ctrl, 0,
                                       0, cap);
             hipError_t ee = hipStreamEndCapture(cap, &g);
@@ -1142,8 +1292,8 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
                 float m = 0.0f;
                 if (e == hipSuccess)
                     e = hipEventElapsedTime(&m, e0, e1);
-                if (rep > 0)
-                    ms = std::min(ms, m / (float)kShapes[k].steps);
+                if (rep > 0)  // time per ten steps
+                    ms = std::min(ms, res ? m * 10.0f / kResidentTuneSteps : m / (float)kShapes[k].steps);
             }
             if (ge)
                 hipGraphExecDestroy(ge);
@@ -1160,10 +1310,14 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     // the chosen list, and for a two-step shape the 256x1 list for the
     // single steps that keep the launch count's parity equal to the step
     // count's (so the state ends in bufs[2l + (n_steps & 1)])
-    const bool two = kShapes[shape].steps == 2;
-    auto main_list = upload(shape);
-    if (!main_list.first)
-        return hip_fail(up_err, "tile list upload");
+    const bool resident = shape == kResident;
+    const bool two = !resident && kShapes[shape].steps == 2;
+    std::pair<BatchTile *, int64_t> main_list{d_tiles1, 0};
+    if (!resident) {
+        main_list = upload(shape);
+        if (!main_list.first)
+            return hip_fail(up_err, "tile list upload");
+    }
     std::pair<BatchTile *, int64_t> one_list = main_list;
     if (two) {
         one_list = upload(0);
@@ -1177,6 +1331,12 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     // `steps` steps, then the sample if asked, then the counter update
     auto enqueue = [&](int64_t steps, bool sample) -> hipError_t {
         int64_t done = 0, launches = 0;
+        if (resident && steps > 0) {
+            hipError_t e = launch_resident(ps[0].model, flags, n, d_lat, d_ctrl, (int)steps, s);
+            if (e != hipSuccess)
+                return e;
+            done = steps;
+        }
         if (two) {
             int64_t q = steps / 2;
             q -= q & 1;  // an even number of two-step launches

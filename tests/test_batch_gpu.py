@@ -282,3 +282,110 @@ def test_mips_batch_samples_density_ramp_and_oracle(L, orc):
     for l, c in enumerate(cfgs[:2]):
         ref = orc.run(_oparams(orc, c), states[l].double().cpu().numpy(), 3)
         assert rel_err(b2.state(l).double().cpu().numpy(), ref) < 3e-6
+
+
+# ---------------------------------------------------------------- lattices resident in LDS
+
+RESIDENT_SIZES = [(2, 2), (40, 6), (90, 30), (66, 18), (64, 64), (130, 30), (7, 100)]
+RESIDENT_KW = {
+    "cil": (SI.CIL, dict(tau=1.0, sigma=4 / 70, A=0.125, B=0.3)),
+    "mips": (SI.MIPS, dict(tau=2.0, sigma=8 / 70, C=6.25, rho_star=1.6, u_max=0.3)),
+    "passive": (SI.PASSIVE, dict(tau=1.3, sigma=0.01)),
+    "passive_quiet": (SI.PASSIVE, dict(tau=1.3, sigma=0.0)),
+}
+
+
+def resident_batch(name):
+    """Lattices of at most 4096 sites (the paper's 90 x 30 MIPS lattice and
+    the 64 x 64 limit among them, some narrower than a wave), each with its
+    own seed."""
+    model, kw = RESIDENT_KW[name]
+    return [_cfg(model, nx, ny, seed=SI.seed_for(9, l), **kw) for l, (nx, ny) in enumerate(RESIDENT_SIZES)]
+
+
+def resident_states(L, cfgs):
+    states = []
+    for l, c in enumerate(cfgs):
+        mips = c["model"] == SI.MIPS
+        ini = dict(mode=1, rho_mean=0.6 + 0.1 * l, rho_spread=0.1, u_mag=0.1 if mips else 0.05,
+                   pop_noise=1e-3 if mips else 0.0)
+        if c["model"] == SI.CIL:
+            ini["u_mag"] = -1.0
+        lat = L.Lattice(_gparams(L, c), init=L.make_init(**ini))
+        torch.cuda.synchronize()
+        states.append(lat.state.clone())
+        lat.close()
+    return states
+
+
+@pytest.mark.parametrize("name,use_graph,steps", [("mips", 1, 1100), ("mips", 0, 37), ("cil", 1, 38),
+                                                  ("cil", 0, 1), ("passive", 1, 37), ("passive_quiet", 1, 2)])
+def test_resident_member_equals_single_run(L, name, use_graph, steps):
+    """Whole lattices in LDS (LBM_TILE_RESIDENT, every step of a captured chunk
+    in one launch): every member equals its lbm_step run bit for bit, for each
+    model and step variant (tau = 1 or not, noise on or off), with odd and even
+    step counts (the state ends in the buffer the parity names) and across a
+    captured chunk (1100 steps)."""
+    cfgs = resident_batch(name)
+    states = resident_states(L, cfgs)
+    finals, samples = single_runs(L, cfgs, states, steps)
+    b = L.Batch([_gparams(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    out = b.run(steps, tile_rows=L.LBM_TILE_RESIDENT, use_graph=use_graph)
+    torch.cuda.synchronize()
+    for l in range(len(cfgs)):
+        assert torch.equal(b.state(l), finals[l]), l
+        o, s = out[l][0], samples[l][0]
+        for k in ("M", "phi", "drho"):
+            assert abs(o[k] - s[k]) <= 1e-12 * max(1.0, abs(s[k])), (l, k)
+
+
+def test_resident_samples_density_ramp_and_oracle(L, orc):
+    """The protocol's pattern on LDS-resident MIPS lattices: samples every 10
+    steps with a density change after each, against single runs with
+    lbm_add_density (bit for bit); then three steps against the oracle."""
+    cfgs = resident_batch("mips")
+    states = resident_states(L, cfgs)
+    drho = [0.01 * (l - 3) for l in range(len(cfgs))]
+    b = L.Batch([_gparams(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    out = b.run(30, sample_every=10, drho=drho, tile_rows=L.LBM_TILE_RESIDENT)
+    for l, c in enumerate(cfgs):
+        lat = L.Lattice(_gparams(L, c))
+        lat.set_state(states[l])
+        obs = []
+        for _ in range(3):
+            lat.step(10)
+            obs.append(lat.observables())
+            lat.add_density(drho[l])
+        assert torch.equal(b.state(l), lat.state), l
+        lat.close()
+        for o, s in zip(out[l], obs):
+            assert abs(o["M"] - s["M"]) <= 1e-12 * s["M"] and abs(o["drho"] - s["drho"]) <= 1e-12
+    b2 = L.Batch([_gparams(L, c) for c in cfgs])
+    for l in range(len(cfgs)):
+        b2.set_state(l, states[l])
+    b2.run(3, tile_rows=L.LBM_TILE_RESIDENT)
+    for l in (2, 4):
+        ref = orc.run(_oparams(orc, cfgs[l]), states[l].double().cpu().numpy(), 3)
+        assert rel_err(b2.state(l).double().cpu().numpy(), ref) < 3e-6, l
+
+
+def test_resident_is_tuned_for_paper_sized_lattices(L):
+    """Twelve 90 x 30 MIPS lattices (the paper's noise-ramp batch): the tuning
+    picks among the 64 x 16, 64 x 4 and LDS-resident forms, and the tuned run
+    equals single runs bit for bit."""
+    model, kw = RESIDENT_KW["mips"]
+    cfgs = [_cfg(model, 90, 30, seed=SI.seed_for(10, l), **kw) for l in range(12)]
+    states = resident_states(L, cfgs)
+    finals, _ = single_runs(L, cfgs, states, 200)
+    b = L.Batch([_gparams(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    b.run(200)
+    torch.cuda.synchronize()
+    assert L.lbm_sweep_tile_rows(b.params, b.n) in (4, 16, L.LBM_TILE_RESIDENT)
+    for l in range(len(cfgs)):
+        assert torch.equal(b.state(l), finals[l]), l
