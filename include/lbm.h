@@ -197,7 +197,8 @@ const char *lbm_last_error(void);
  * Batched sweeps: n independent lattices of arbitrary sizes and parameters
  * (the paper's repeated runs over a grid of mean density and model constants,
  * appendix "Simulation procedure for results") advanced together: one kernel
- * launch per step (or per two steps) covers every lattice, and a sample
+ * launch per step (or per two steps, or per captured chunk of steps with the
+ * lattices resident in LDS) covers every lattice, and a sample
  * period (its steps and the FP64 sampling kernels) is captured in HIP graphs
  * of at most 1024 steps and replayed.
  * ---------------------------------------------------------------------- */
