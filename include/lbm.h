@@ -54,8 +54,8 @@
  *  - A population buffer is [9][ny][pitch]; every plane must be below 2^32
  *    bytes (ny * pitch < 2^30 for F32, < 2^31 for the 16-bit storages).
  *  - lbm_add_density adds drho/9 to every population.
- *  - Batched sweeps run D2Q9 one step per launch; the coarse-field calls take
- *    D2Q7 only (LBM_EUNSUPPORTED).
+ *  - Batched sweeps run D2Q9 with one or two steps per launch (not resident
+ *    in LDS); the coarse-field calls take D2Q7 only (LBM_EUNSUPPORTED).
  *
  * Memory ownership.  The caller owns every device buffer passed in
  * (population buffers, field outputs, batch buffers, workspaces, network
