@@ -128,6 +128,9 @@ def test_resident_form_validation():
     assert _sweep(L, [small], tile_rows=R) in (L.LBM_OK, L.LBM_EHIP)
     assert _sweep(L, [L.make_params(90, 30, L.LBM_CIL, A=0.1, B=0.3)], tile_rows=R) in (L.LBM_OK, L.LBM_EHIP)
     assert _sweep(L, [small, big], tile_rows=R) == L.LBM_EINVAL and "4096" in L.lbm_last_error()
+    over = L.make_params(2050, 2, L.LBM_CIL, A=0.1, B=0.3)  # 4100 sites, one row pair
+    assert _sweep(L, [over], tile_rows=R) == L.LBM_EINVAL
+    assert _sweep(L, [L.make_params(2048, 2, L.LBM_CIL, A=0.1, B=0.3)], tile_rows=R) in (L.LBM_OK, L.LBM_EHIP)
     assert _sweep(L, [big], tile_rows=3) == L.LBM_EINVAL and "LBM_TILE_RESIDENT" in L.lbm_last_error()
 
 
