@@ -810,6 +810,55 @@ static int64_t count_tiles(const lbm_params *ps, int n, int tx, int ty)
     return c;
 }
 
+// Lattices are independent, so a chunk of steps may run lattice group by
+// lattice group: every launch of the chunk for the first group, then for the
+// next.  A group's two buffers then stay in the 256 MiB Infinity Cache across
+// the chunk's launches instead of streaming from HBM every step.  The batch
+// takes the fewest groups of at most kCacheGroupBytes (as measured, larger
+// groups of fewer launches beat smaller ones down to that size), cut into
+// consecutive lattices of about equal bytes.
+constexpr uint64_t kCacheGroupBytes = 240ull << 20;
+
+static std::vector<int> cache_groups(const lbm_params *ps, int n)
+{
+    std::vector<uint64_t> b(n);
+    uint64_t total = 0;
+    for (int l = 0; l < n; ++l) {
+        b[l] = 2ull * (ps[l].lattice == LBM_D2Q9 ? 9ull : 7ull) * 4ull * (uint64_t)ps[l].nx * ps[l].ny;
+        total += b[l];
+    }
+    const uint64_t ng = (total + kCacheGroupBytes - 1) / kCacheGroupBytes;
+    const uint64_t target = (total + ng - 1) / ng;
+    std::vector<int> first{0};  // first lattice of each group, then n
+    uint64_t cum = 0, in_group = 0;
+    for (int l = 0; l < n; ++l) {
+        const uint64_t cut = (uint64_t)(first.size()) * target;  // where the next group begins
+        if (l > first.back() && (cum >= cut || in_group + b[l] > kCacheGroupBytes)) {
+            first.push_back(l);
+            in_group = 0;
+        }
+        cum += b[l];
+        in_group += b[l];
+    }
+    first.push_back(n);
+    return first;
+}
+
+// [begin, count) of each group's tiles in the list of shape k (build_tiles
+// lists each lattice's tiles contiguously, in lattice order)
+static std::vector<int64_t> group_ranges(const lbm_params *ps, const std::vector<int> &first, int k)
+{
+    std::vector<int64_t> r;
+    int64_t off = 0;
+    for (size_t g = 0; g + 1 < first.size(); ++g) {
+        const int64_t c = count_tiles(ps + first[g], first[g + 1] - first[g], kShapes[k].tx, kShapes[k].ty);
+        r.push_back(off);
+        r.push_back(c);
+        off += c;
+    }
+    return r;
+}
+
 static Layout layout(const lbm_params *ps, int n, int64_t n_samples)
 {
     Layout L{};
@@ -1031,10 +1080,11 @@ struct GraphKey {
     int lattice, model, flags, shape;
     int64_t ntiles_main, ntiles_one, nmt, n, n_samples, steps;
     int sample, add;
+    std::vector<int64_t> groups;  // tile ranges of the lattice groups
     auto tie() const
     {
         return std::tie(device, tiles_main, tiles_one, lat, ctrl, mt, part, colpart, colmean, results, lattice, model,
-                        flags, shape, ntiles_main, ntiles_one, nmt, n, n_samples, steps, sample, add);
+                        flags, shape, ntiles_main, ntiles_one, nmt, n, n_samples, steps, sample, add, groups);
     }
     bool operator==(const GraphKey &o) const { return tie() == o.tie(); }
 };
@@ -1327,6 +1377,12 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     const int64_t nmt = (int64_t)mt.size();
     hipLaunchKernelGGL(k_batch_set_ctrl, dim3(1), dim3(64), 0, s, d_ctrl, (int64_t)o->step0);
     LBM_HIP_TRY(hipGetLastError());
+    // lattice groups that fit the Infinity Cache (one group when resident)
+    const std::vector<int> gfirst = resident ? std::vector<int>{0, n} : cache_groups(ps, n);
+    const std::vector<int64_t> g_main = resident ? std::vector<int64_t>{0, 0} : group_ranges(ps, gfirst, shape);
+    const std::vector<int64_t> g_one = two ? group_ranges(ps, gfirst, 0) : g_main;
+    std::vector<int64_t> gkey(g_main);
+    gkey.insert(gkey.end(), g_one.begin(), g_one.end());
 
     // `steps` steps, then the sample if asked, then the counter update
     auto enqueue = [&](int64_t steps, bool sample) -> hipError_t {
@@ -1337,21 +1393,29 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
                 return e;
             done = steps;
         }
-        if (two) {
-            int64_t q = steps / 2;
-            q -= q & 1;  // an even number of two-step launches
-            for (; launches < q; ++launches, done += 2) {
-                hipError_t e = launch_batch_step(ps[0].lattice, ps[0].model, flags, shape, main_list.second,
-                                                 main_list.first, d_lat, d_ctrl, (int)done, (int)launches, s);
+        // every launch of the chunk for one lattice group, then the next
+        const int64_t d0 = done, l0 = launches;
+        for (size_t g = 0; g + 1 < gfirst.size() && !resident; ++g) {
+            done = d0;
+            launches = l0;
+            if (two) {
+                int64_t q = steps / 2;
+                q -= q & 1;  // an even number of two-step launches
+                for (; launches < q; ++launches, done += 2) {
+                    hipError_t e = launch_batch_step(ps[0].lattice, ps[0].model, flags, shape, g_main[2 * g + 1],
+                                                     main_list.first + g_main[2 * g], d_lat, d_ctrl, (int)done,
+                                                     (int)launches, s);
+                    if (e != hipSuccess)
+                        return e;
+                }
+            }
+            for (; done < steps; ++launches, ++done) {
+                hipError_t e = launch_batch_step(ps[0].lattice, ps[0].model, flags, two ? 0 : shape, g_one[2 * g + 1],
+                                                 one_list.first + g_one[2 * g], d_lat, d_ctrl, (int)done,
+                                                 (int)launches, s);
                 if (e != hipSuccess)
                     return e;
             }
-        }
-        for (; done < steps; ++launches, ++done) {
-            hipError_t e = launch_batch_step(ps[0].lattice, ps[0].model, flags, two ? 0 : shape, one_list.second,
-                                             one_list.first, d_lat, d_ctrl, (int)done, (int)launches, s);
-            if (e != hipSuccess)
-                return e;
         }
         if (sample) {
             if (q9)
@@ -1392,7 +1456,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
                            (const void *)d_colmean, (const void *)d_results, ps[0].lattice, ps[0].model, flags,
                            shape,
                            main_list.second, one_list.second, nmt, (int64_t)n, n_samples, steps, sample ? 1 : 0,
-                           o->drho ? 1 : 0};
+                           o->drho ? 1 : 0, gkey};
         if ((*ge = graph_cache_get(key)))
             return hipSuccess;
         hipGraph_t g;
