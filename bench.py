@@ -173,6 +173,9 @@ def time_batch(L, torch, cfgs, steps, warmup, tile_rows=0, lattice=0):
     e1.record(s)
     torch.cuda.synchronize()
     time_batch.tile_rows = tile_rows or L.lbm_sweep_tile_rows(b.params, b.n)
+    # each chunk runs lattice group by lattice group (groups sized for the
+    # Infinity Cache): a pass over the batch is that many kernel launches
+    time_batch.groups = 1 if time_batch.tile_rows == L.LBM_TILE_RESIDENT else L.lbm_sweep_groups(b.params, b.n)
     return e0.elapsed_time(e1), [o[-1] for o in out]
 
 
@@ -268,22 +271,24 @@ def valu_per_site_update():
     return float(VALU_PER_SITE_UPDATE), "stated (counter summary taken on other kernel sources)"
 
 
-def roofline_two_step(sites, per_launch_s, kernel, rows):
+def roofline_two_step(sites, per_launch_s, kernel, rows, total_sites=None):
     """Two steps per launch: 2 x sites site-updates of VALU work against the
-    VALU issue peak; the HBM side is the state read and written once."""
+    VALU issue peak; the HBM side is the state read and written once.  sites:
+    the sites one launch covers on average (a lattice group's share of the
+    batch, total_sites)."""
     vpu, vsrc = valu_per_site_update()
     tops = vpu * 2 * sites / per_launch_s / 1e12
     hbm = BYTES_PER_SITE[0] * sites / per_launch_s / 1e9
     r = {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
          "unit": "T VALU lane-instructions/s", "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": None,
          "kernel": kernel, "avg_launch_us": round(per_launch_s * 1e6, 3),
-         "valu_per_site_update": vpu, "valu_per_site_update_source": vsrc, "site_updates_per_launch": 2 * sites,
+         "valu_per_site_update": vpu, "valu_per_site_update_source": vsrc, "site_updates_per_launch": round(2 * sites),
          "hbm": {"achieved": round(hbm, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                  "frac": round(hbm / HBM_PEAK_GBPS, 4), "bytes_per_launch": BYTES_PER_SITE[0] * sites}}
     c = measured_traffic(f"counters_k_batch_step2_{rows}_cil_5x1024.json")
-    if c is not None and c.get("sites") == sites:
+    if c is not None and c.get("sites") == (total_sites or sites):
         r["traffic"] = round(c["traffic_bytes_per_launch"] / per_launch_s / 1e9, 1)
-        r["traffic_unit"] = "GB/s (measured HBM bytes per launch / avg launch)"
+        r["traffic_unit"] = "GB/s (measured bytes past the L2 per launch / avg launch)"
         r["traffic_bytes_per_launch"] = c["traffic_bytes_per_launch"]
         r["traffic_vs_algorithmic"] = round(c["traffic_bytes_per_launch"] / c["algorithmic_bytes_per_launch"], 4)
     return r
@@ -308,7 +313,7 @@ def roofline_q9_two_step(sites, per_launch_s, kernel):
     return {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
             "unit": "T VALU lane-instructions/s", "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": None,
             "kernel": kernel, "avg_launch_us": round(per_launch_s * 1e6, 3),
-            "valu_per_site_update": vpu, "valu_per_site_update_source": vsrc, "site_updates_per_launch": 2 * sites,
+            "valu_per_site_update": vpu, "valu_per_site_update_source": vsrc, "site_updates_per_launch": round(2 * sites),
             "hbm": {"achieved": round(hbm, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                     "frac": round(hbm / HBM_PEAK_GBPS, 4), "bytes_per_launch": 72 * sites}}
 
@@ -360,25 +365,27 @@ def main():
         mode = "single"
 
     t_wall = time.perf_counter()
-    rows = 0
+    rows, ngr = 0, 1
     if mode == "batch":
         ms, obs = time_batch(L, torch, cfgs, args.steps, args.warmup, args.tile_rows, lattice)
         rows = time_batch.tile_rows
+        ngr = time_batch.groups
         two, one = batch_launches(args.steps, rows)
+        gtxt = f"; {ngr} lattice groups per pass" if ngr > 1 else ""
         if lattice:
-            launches = two + 0.5 * one if two else args.steps
-            kernel = (f"k_batch_q9_step2<CIL,unit-tau,noisy,{rows}> (64x{rows} tiles, two steps per launch)" if two
-                      else f"k_batch_q9_step (one step per launch, tile rows {rows})")
+            launches = (two + 0.5 * one if two else args.steps) * ngr
+            kernel = (f"k_batch_q9_step2<CIL,unit-tau,noisy,{rows}> (64x{rows} tiles, two steps per launch{gtxt})"
+                      if two else f"k_batch_q9_step (one step per launch, tile rows {rows}{gtxt})")
         elif two:
             # a one-step launch moves the same bytes as a two-step launch
             # and does half the site work: count it as half a launch
-            launches = two + 0.5 * one
+            launches = (two + 0.5 * one) * ngr
             kernel = (f"k_batch_step2<CIL,unit-tau,noisy,{rows}> (64x{rows} tiles, two steps per launch; "
-                      f"{two} launches + {one} one-step launches + 1 FP64 sample)")
+                      f"{two * ngr} launches + {one * ngr} one-step launches + 1 FP64 sample{gtxt})")
         else:
-            launches = args.steps
+            launches = args.steps * ngr
             tile = {1: "256x1", 2: "128x2", 4: "64x4"}.get(rows, "?")
-            kernel = f"k_batch_step<CIL,unit-tau,noisy>, tile {tile} (+1 FP64 sample at the end)"
+            kernel = f"k_batch_step<CIL,unit-tau,noisy>, tile {tile} (+1 FP64 sample at the end{gtxt})"
     else:
         ms, obs = time_single(L, torch, cfgs, args.steps, args.warmup, args.storage, lattice)
         st = {0: "F32", 1: "BF16dev", 2: "F16dev"}[args.storage]
@@ -406,10 +413,10 @@ def main():
         "dtype": {0: "f32", 1: "bf16 storage, f32 math", 2: "f16 storage, f32 math"}[args.storage],
         "data": "synthetic",
         "config": {"workload": wname, "lattices": len(cfgs), "sites": sites, "storage": args.storage,
-                   "mode": mode, **({"tile_rows": rows} if mode == "batch" else {})},
-        "roofline": (roofline_two_step(sites, per_launch, kernel, rows) if rows >= 8 and not lattice else
-                     roofline(args.storage, sites / (launches / args.steps), per_launch, kernel, q)
-                     if rows < 8 else roofline_q9_two_step(sites, per_launch, kernel)),
+                   "mode": mode, **({"tile_rows": rows, "lattice_groups": ngr} if mode == "batch" else {})},
+        "roofline": (roofline_two_step(sites / ngr, per_launch, kernel, rows, sites) if rows >= 8 and not lattice
+                     else roofline(args.storage, sites / (launches / args.steps), per_launch, kernel, q)
+                     if rows < 8 else roofline_q9_two_step(sites / ngr, per_launch, kernel)),
         "phi": [round(o["phi"], 6) for o in obs],
         "wall_s": round(wall, 3),
     }
@@ -438,8 +445,9 @@ def main():
         # the same batch with one step per launch (256 x 1 tiles): the plain
         # fused step against the HBM roofline
         ms_one, _ = time_batch(L, torch, cfgs, k, 20, tile_rows=1)
-        per_one = ms_one / 1e3 / k
-        r1 = roofline(0, sites, per_one, "k_batch_step<CIL,unit-tau,noisy>, 256x1 tiles")
+        ng1 = time_batch.groups
+        per_one = ms_one / 1e3 / (k * ng1)
+        r1 = roofline(0, sites / ng1, per_one, f"k_batch_step<CIL,unit-tau,noisy>, 256x1 tiles, {ng1} lattice groups")
         c = measured_traffic("counters_k_batch_step_1_cil_5x1024.json")
         if c is not None and c.get("sites") == sites:
             r1["traffic"] = round(c["traffic_bytes_per_launch"] / per_one / 1e9, 1)

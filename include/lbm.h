@@ -246,6 +246,16 @@ size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samp
  * yet in this process; negative on invalid arguments. */
 int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n);
 
+/* Lattice groups a sweep of these n lattices runs each captured chunk in
+ * (tile forms; the LDS-resident form launches every lattice at once): the
+ * lattices are independent, so every launch of a chunk runs for the first
+ * group of consecutive lattices, then for the next, each group's two buffers
+ * (about equal shares, at most 240 MiB where one lattice is not larger) kept
+ * in the 256 MiB Infinity Cache across those launches.  A chunk of s steps
+ * therefore makes groups times the launches of one group.  LBM_EINVAL on
+ * invalid arguments. */
+int32_t lbm_sweep_groups(const lbm_params *ps, int32_t n);
+
 /* Run a batch.  ps[n]: per-lattice parameters; every lattice uses the same
  * velocity set (D2Q7 or D2Q9), F32 storage, the same model (CIL, MIPS or
  * passive), and agrees on tau == 1 and on

@@ -98,6 +98,7 @@ _SIGS = {
     "lbm_last_error": (ctypes.c_char_p, []),
     "lbm_sweep_workspace_bytes": (ctypes.c_size_t, [_P(lbm_params), ctypes.c_int32, ctypes.c_int64]),
     "lbm_sweep_tile_rows": (ctypes.c_int32, [_P(lbm_params), ctypes.c_int32]),
+    "lbm_sweep_groups": (ctypes.c_int32, [_P(lbm_params), ctypes.c_int32]),
     "lbm_sweep_batch": (ctypes.c_int32, [_P(lbm_params), ctypes.c_int32, _P(lbm_sweep_opts), _P(_vp), _vp,
                                          ctypes.c_size_t, _vp, _P(lbm_obs)]),
     "lbm_cnn_workspace_bytes": (ctypes.c_size_t, [_P(lbm_cnn_shape)]),
@@ -188,6 +189,11 @@ def lbm_sweep_workspace_bytes(params_array, n, n_samples):
 
 def lbm_sweep_tile_rows(params_array, n):
     return _lib.lbm_sweep_tile_rows(params_array, int(n))
+
+
+def lbm_sweep_groups(params_array, n):
+    """Lattice groups each captured chunk of a tiled sweep runs in."""
+    return _lib.lbm_sweep_groups(params_array, int(n))
 
 
 def lbm_sweep_batch(params_array, n, opts, bufs, ws, ws_bytes, stream, out):

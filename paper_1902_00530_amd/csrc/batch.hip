@@ -1134,6 +1134,13 @@ using namespace lbm;
 
 extern "C" {
 
+int32_t lbm_sweep_groups(const lbm_params *ps, int32_t n)
+{
+    if (!ps || n <= 0)
+        return fail(LBM_EINVAL, "null parameters or empty batch");
+    return (int32_t)cache_groups(ps, n).size() - 1;
+}
+
 int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n)
 {
     if (!ps || n <= 0)

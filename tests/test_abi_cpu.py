@@ -134,6 +134,26 @@ def test_resident_form_validation():
     assert _sweep(L, [big], tile_rows=3) == L.LBM_EINVAL and "LBM_TILE_RESIDENT" in L.lbm_last_error()
 
 
+def test_sweep_groups():
+    """The lattice groups a tiled sweep runs each chunk in: the fewest groups
+    whose two buffers stay within 240 MiB, in about equal shares of
+    consecutive lattices (host logic only, no GPU)."""
+    import synth_inputs as SI
+    import paper_1902_00530_amd as L
+
+    def groups(plist):
+        arr = (L.lbm_params * len(plist))(*plist)
+        return L.lbm_sweep_groups(arr, len(plist))
+    five = [L.make_params(1024, 1024, L.LBM_CIL, A=0.125, B=0.3, seed=l) for l in range(5)]
+    assert groups(five) == 2  # 294 MB of state: 176 + 117 MB
+    assert groups(five[:4]) == 1  # 235 MB fits
+    assert groups([L.make_params(1024, 1024, L.LBM_CIL, lattice=L.LBM_D2Q9) for _ in range(5)]) == 2
+    assert groups([L.make_params(4096, 4096, L.LBM_CIL)]) == 1  # one lattice larger than the budget
+    sweep = [L.make_params(c["nx"], c["ny"], c["model"], A=c["A"], B=c["B"]) for c in SI.batch_sweep()]
+    assert groups(sweep) == 5
+    assert L._lib.lbm_sweep_groups(None, 1) == L.LBM_EINVAL
+
+
 def test_null_context_is_a_state_error():
     import paper_1902_00530_amd as L
     assert L._lib.lbm_step(None, 1) == L.LBM_ESTATE
