@@ -197,10 +197,11 @@ const char *lbm_last_error(void);
  * Batched sweeps: n independent lattices of arbitrary sizes and parameters
  * (the paper's repeated runs over a grid of mean density and model constants,
  * appendix "Simulation procedure for results") advanced together: one kernel
- * launch per step (or per two steps, or per captured chunk of steps with the
- * lattices resident in LDS) covers every lattice, and a sample
- * period (its steps and the FP64 sampling kernels) is captured in HIP graphs
- * of at most 1024 steps and replayed.
+ * launch per step (or per two steps) covers every lattice of a lattice group
+ * (lbm_sweep_groups), or one launch runs a whole captured chunk of steps with
+ * the lattices resident in LDS; a sample period (its steps and the FP64
+ * sampling kernels) is captured in HIP graphs of at most 1024 steps and
+ * replayed.
  * ---------------------------------------------------------------------- */
 /* lbm_sweep_opts.tile_rows value (no tile has that many rows) for the
  * LDS-resident form: each D2Q7 lattice of at most 4096 sites lives in the LDS
