@@ -389,3 +389,39 @@ def test_resident_is_tuned_for_paper_sized_lattices(L):
     assert L.lbm_sweep_tile_rows(b.params, b.n) in (4, 16, L.LBM_TILE_RESIDENT)
     for l in range(len(cfgs)):
         assert torch.equal(b.state(l), finals[l]), l
+
+
+def test_lattice_groups_with_samples_and_density_ramp(L):
+    """The benchmark's five 1024 x 1024 lattices run as two lattice groups
+    (each group's state sized for the Infinity Cache): samples every 10 steps
+    with a density change after each, two steps per launch, equal to
+    single-lattice runs with lbm_add_density bit for bit."""
+    cfgs = [SI.cil_1024(r, l) for l, r in enumerate(SI.CIL_DENSITIES)]
+    inits = [c.pop("init") for c in cfgs]
+    params = [_gparams(L, c) for c in cfgs]
+    arr = (L.lbm_params * len(params))(*params)
+    assert L.lbm_sweep_groups(arr, len(params)) == 2
+    states = []
+    for p, ini in zip(params, inits):
+        lat = L.Lattice(p, init=L.make_init(**ini))
+        torch.cuda.synchronize()
+        states.append(lat.state.clone())
+        lat.close()
+    drho = [0.01, -0.01, 0.02, -0.02, 0.005]
+    b = L.Batch(params)
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    out = b.run(40, sample_every=10, drho=drho, tile_rows=16)
+    for l, p in enumerate(params):
+        lat = L.Lattice(p)
+        lat.set_state(states[l])
+        obs = []
+        for _ in range(4):
+            lat.step(10)
+            obs.append(lat.observables())
+            lat.add_density(drho[l])
+        assert torch.equal(b.state(l), lat.state), l
+        lat.close()
+        for o, s in zip(out[l], obs):
+            for k in ("M", "phi", "drho"):
+                assert abs(o[k] - s[k]) <= 1e-12 * max(1.0, abs(s[k])), (l, k)
