@@ -461,3 +461,33 @@ def test_batch_samples_density_ramp_and_oracle(L, q9, orc):
     for l, c in enumerate(cfgs[:2]):
         ref = q9.run(_op(orc, c), states[l].double().cpu().numpy(), 3)
         assert rel_err(b2.state(l).double().cpu().numpy(), ref) < 3e-6
+
+
+@pytest.mark.parametrize("tile_rows", [16, 1])
+def test_batch_lattice_groups(L, tile_rows):
+    """Five 1024 x 1024 square lattices (377 MB of state) run as two lattice
+    groups sized for the Infinity Cache: four steps (two two-step launches per
+    group, or four one-step launches) equal single-lattice runs bit for bit."""
+    cfgs = [SI.q9_cil_4096(n=1024, rho_mean=0.5 + 0.25 * l) for l in range(5)]
+    for l, c in enumerate(cfgs):
+        c["seed"] = SI.seed_for(12, l)
+    inits = [c.pop("init") for c in cfgs]
+    params = [_gp(L, c) for c in cfgs]
+    arr = (L.lbm_params * len(params))(*params)
+    assert L.lbm_sweep_groups(arr, len(params)) == 2
+    states, singles = [], []
+    for p, ini in zip(params, inits):
+        lat = L.Lattice(p, init=L.make_init(**ini))
+        torch.cuda.synchronize()
+        states.append(lat.state.clone())
+        lat.step(4)
+        torch.cuda.synchronize()
+        singles.append(lat.state.clone())
+        lat.close()
+    b = L.Batch(params)
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    b.run(4, tile_rows=tile_rows)
+    torch.cuda.synchronize()
+    for l in range(len(params)):
+        assert torch.equal(b.state(l), singles[l]), l
