@@ -1325,9 +1325,12 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
             hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
             if (res && e == hipSuccess)  // first buffer -> second buffer
                 e = launch_resident(ps[0].model, flags, n, d_lat, d_ctrl, kResidentTuneSteps, cap);
-            for (int r10 = 0; r10 < 10 && !res && e == hipSuccess; ++r10)
-                e = launch_batch_step(ps[0].lattice, ps[0].model, flags, k, tl.second, tl.first, d_lat, d_ctrl, 0,
-                                      0, cap);
+            // ten launches per lattice group, group after group, as the sweep runs them
+            const std::vector<int64_t> gr = res ? std::vector<int64_t>{} : group_ranges(ps, cache_groups(ps, n), k);
+            for (size_t g = 0; 2 * g < gr.size(); ++g)
+                for (int r10 = 0; r10 < 10 && e == hipSuccess; ++r10)
+                    e = launch_batch_step(ps[0].lattice, ps[0].model, flags, k, gr[2 * g + 1], tl.first + gr[2 * g],
+                                          d_lat, d_ctrl, 0, 0, cap);
             hipError_t ee = hipStreamEndCapture(cap, &g);
             hipStreamDestroy(cap);
             if (e == hipSuccess)
