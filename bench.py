@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--workload", default="cil1024x5",
                     choices=["cil1024x5", "cil4096", "mips4096", "q9_cil4096", "q9_mips4096"],
                     help="mips4096: the 64 x 64 MIPS workload's parameters on 4096 x 4096; q9_*: the "
-                         "square-lattice (D2Q9) variant, one launch per step")
+                         "square-lattice (D2Q9) variant (lbm_step; --mode batch: the batched path)")
     ap.add_argument("--storage", type=int, default=0, help="0 f32, 1 bf16 deviations, 2 fp16 deviations")
     ap.add_argument("--mode", default=None, choices=["batch", "single"],
                     help="default: batch for the D2Q7 CIL workloads in FP32, single (lbm_step) otherwise")
@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=25)
     ap.add_argument("--tile-rows", type=int, default=0,
-                    help="batch work tile: 0 tuned, 1/2/4 one step per launch, 8/12/16 two steps per launch")
+                    help="batch work tile: 0 tuned, 1/2/4 one step per launch, 8/16 two steps per launch, 1024 lattices resident in LDS")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 7 x 1024 x 1024 float buffer --steps times (counter calibration)")
     return ap.parse_args()
