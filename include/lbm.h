@@ -54,8 +54,9 @@
  *  - A population buffer is [9][ny][pitch]; every plane must be below 2^32
  *    bytes (ny * pitch < 2^30 for F32, < 2^31 for the 16-bit storages).
  *  - lbm_add_density adds drho/9 to every population.
- *  - Batched sweeps run D2Q9 with one or two steps per launch (not resident
- *    in LDS); the coarse-field calls take D2Q7 only (LBM_EUNSUPPORTED).
+ *  - Batched sweeps run D2Q9 with one or two steps per launch, or resident
+ *    in LDS up to 3072 sites; the coarse-field calls take D2Q7 only
+ *    (LBM_EUNSUPPORTED).
  *
  * Memory ownership.  The caller owns every device buffer passed in
  * (population buffers, field outputs, batch buffers, workspaces, network
@@ -204,8 +205,8 @@ const char *lbm_last_error(void);
  * replayed.
  * ---------------------------------------------------------------------- */
 /* lbm_sweep_opts.tile_rows value (no tile has that many rows) for the
- * LDS-resident form: each D2Q7 lattice of at most 4096 sites lives in the LDS
- * of one CU (one 1024-lane workgroup per
+ * LDS-resident form: each lattice of at most 4096 sites (D2Q7; 3072 on D2Q9)
+ * lives in the LDS of one CU (one 1024-lane workgroup per
  * lattice) for all the steps of a captured chunk, one launch per chunk; the
  * state crosses HBM only at the chunk's ends.  For lattices of the paper's
  * size (90 x 30), where one launch per step leaves the GPU bound by launch
@@ -222,10 +223,10 @@ typedef struct lbm_sweep_opts {
                              batch itself, cached per batch signature).  MIPS batches
                              take 0 (tuned), 4 or 16: 64x4 or 64x16 tiles, one step per
                              launch, neighbour densities in LDS.  LBM_TILE_RESIDENT (1024):
-                             whole lattices in LDS (D2Q7, every lattice at most 4096
-                             sites, any model; tuned among the others when the batch
-                             qualifies).  D2Q9 batches take 0, 1, 2, 4, 8 or 16 (MIPS:
-                             0 or 16) */
+                             whole lattices in LDS (every lattice at most 4096 sites
+                             on D2Q7, 3072 on D2Q9, any model; tuned among the others
+                             when the batch qualifies).  D2Q9 batches take 0, 1, 2, 4, 8
+                             or 16 (MIPS: 0 or 16), and LBM_TILE_RESIDENT */
     int32_t use_graph;    /* 0: launch every kernel directly; 1: run each sample period
                              as captured HIP graphs of at most 1024 steps, kept (16 most
                              recent) and replayed by later calls with the same batch,

@@ -20,7 +20,7 @@ LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ENONFINITE, LBM_EUNSUPPORTED, LBM_ESTATE = 0, 
 LBM_PASSIVE, LBM_MIPS, LBM_CIL = 0, 1, 2
 LBM_F32, LBM_BF16_DEV, LBM_F16_DEV = 0, 1, 2
 LBM_D2Q7, LBM_D2Q9 = 0, 1
-LBM_TILE_RESIDENT = 1024  # tile_rows of the LDS-resident batch form (D2Q7 lattices of <= 4096 sites)
+LBM_TILE_RESIDENT = 1024  # tile_rows of the LDS-resident batch form (<= 4096 sites on D2Q7, 3072 on D2Q9)
 LBM_INIT_NONE, LBM_INIT_UNIFORM_DIR, LBM_INIT_GAUSS_DIR = 0, 1, 2
 
 

@@ -224,6 +224,92 @@ __global__ __launch_bounds__(kResidentLanes) void k_batch_resident(const LatDesc
             dst[(int64_t)i * a.plane + e] = st[i * S + e];
 }
 
+// The same for the square lattice (D2Q9): nine planes and the densities, at
+// most kResidentSitesQ9 sites (120 KiB of LDS), the site body of the D2Q9
+// tile kernels (q9_moments, local_ustar or q9_mips_ustar, q9_collide).
+constexpr int kResidentSitesQ9 = 3072;
+constexpr int kResidentPerQ9 = (kResidentSitesQ9 + kResidentLanes - 1) / kResidentLanes;
+
+template <int M, int F>
+__global__ __launch_bounds__(kResidentLanes) void k_batch_resident_q9(const LatDesc *__restrict__ lats,
+                                                                     const Ctrl *__restrict__ ctrl, int steps)
+{
+    __shared__ float st[10 * kResidentSitesQ9];  // plane i of the state at i * S, densities at 9 * S
+    const LatDesc &L = lats[blockIdx.x];
+    const StepArgs a = L.a;  // pitch nx: plane i holds S = nx * ny contiguous floats
+    const int S = a.nx * a.ny;
+    const int par = (int)(ctrl->k0 & 1);
+    const float *__restrict__ src = (const float *)L.buf[par];
+    float *__restrict__ dst = (float *)L.buf[par ^ (steps & 1)];
+    const int tid = threadIdx.x;
+    float *rho_l = st + 9 * S;
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        for (int e = tid; e < S; e += kResidentLanes)
+            st[i * S + e] = src[(int64_t)i * a.plane + e];
+    int sx[kResidentPerQ9], sy[kResidentPerQ9];
+#pragma unroll
+    for (int j = 0; j < kResidentPerQ9; ++j) {
+        const int s = tid + j * kResidentLanes;
+        sy[j] = s / a.nx;
+        sx[j] = s - sy[j] * a.nx;
+    }
+    __syncthreads();
+    const int64_t t0 = ctrl->t0;
+    for (int k = 0; k < steps; ++k) {
+        const uint64_t t = (uint64_t)(t0 + k);
+        const uint32_t tlo = (uint32_t)(t & 0xffffffffu), thi = (uint32_t)(t >> 32);
+        float f[kResidentPerQ9][9], rho[kResidentPerQ9], jx[kResidentPerQ9], jy[kResidentPerQ9];
+#pragma unroll
+        for (int j = 0; j < kResidentPerQ9; ++j) {
+            const int s = tid + j * kResidentLanes;
+            if (s < S) {
+                const Q9Sources q = q9_sources(a, sx[j], sy[j]);
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    f[j][i] = st[i * S + (int)q.idx[i]];
+                q9_moments(f[j], rho[j], jx[j], jy[j]);
+                if (M == kMips)
+                    rho_l[s] = rho[j];
+            }
+        }
+        __syncthreads();  // every pull done (the state may be overwritten), densities in place
+#pragma unroll
+        for (int j = 0; j < kResidentPerQ9; ++j) {
+            const int s = tid + j * kResidentLanes;
+            if (s < S) {
+                float ux, uy;
+                if (M == kMips) {
+                    // density at r + e_i: the pull source of the opposite population
+                    const Q9Sources q = q9_sources(a, sx[j], sy[j]);
+                    float nb[9];
+                    nb[0] = rho[j];
+                    nb[1] = rho_l[q.idx[3]];
+                    nb[2] = rho_l[q.idx[4]];
+                    nb[3] = rho_l[q.idx[1]];
+                    nb[4] = rho_l[q.idx[2]];
+                    nb[5] = rho_l[q.idx[7]];
+                    nb[6] = rho_l[q.idx[8]];
+                    nb[7] = rho_l[q.idx[5]];
+                    nb[8] = rho_l[q.idx[6]];
+                    q9_mips_ustar(a, rho[j], nb, ux, uy);
+                } else {
+                    local_ustar<M>(a, rho[j], jx[j], jy[j], ux, uy);
+                }
+                q9_collide<F>(a, f[j], rho[j], ux, uy, (uint32_t)s, tlo, thi);
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    st[i * S + s] = f[j][i];
+            }
+        }
+        __syncthreads();  // the step's writes precede the next step's pulls
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        for (int e = tid; e < S; e += kResidentLanes)
+            dst[(int64_t)i * a.plane + e] = st[i * S + e];
+}
+
 // The square lattice (D2Q9) over the tile list: the single-lattice site body
 // (passive, CIL) and MIPS tile body, one step per launch.
 template <int M, int F>
@@ -795,7 +881,7 @@ constexpr int kResidentTuneSteps = 63;
 static bool resident_fits(const lbm_params *ps, int n)
 {
     for (int l = 0; l < n; ++l)
-        if (ps[l].lattice != LBM_D2Q7 || (int64_t)ps[l].nx * ps[l].ny > kResidentSites)
+        if ((int64_t)ps[l].nx * ps[l].ny > (ps[l].lattice == LBM_D2Q9 ? kResidentSitesQ9 : kResidentSites))
             return false;
     return true;
 }
@@ -965,29 +1051,38 @@ static hipError_t launch_batch_mips_f(int shape, int64_t ntiles, const BatchTile
     return hipGetLastError();
 }
 
-template <int M>
-static void launch_resident_m(int flags, int n, const LatDesc *lats, const Ctrl *ctrl, int steps, hipStream_t s)
+template <int M, int F>
+static void launch_resident_mf(bool q9, int n, const LatDesc *lats, const Ctrl *ctrl, int steps, hipStream_t s)
 {
     const dim3 grd((unsigned)n), blk(kResidentLanes);
+    if (q9)
+        hipLaunchKernelGGL((k_batch_resident_q9<M, F>), grd, blk, 0, s, lats, ctrl, steps);
+    else
+        hipLaunchKernelGGL((k_batch_resident<M, F>), grd, blk, 0, s, lats, ctrl, steps);
+}
+
+template <int M>
+static void launch_resident_m(bool q9, int flags, int n, const LatDesc *lats, const Ctrl *ctrl, int steps,
+                              hipStream_t s)
+{
     switch (flags) {
-    case 0: hipLaunchKernelGGL((k_batch_resident<M, 0>), grd, blk, 0, s, lats, ctrl, steps); break;
-    case kUnitTau: hipLaunchKernelGGL((k_batch_resident<M, kUnitTau>), grd, blk, 0, s, lats, ctrl, steps); break;
-    case kNoisy: hipLaunchKernelGGL((k_batch_resident<M, kNoisy>), grd, blk, 0, s, lats, ctrl, steps); break;
-    default:
-        hipLaunchKernelGGL((k_batch_resident<M, kUnitTau | kNoisy>), grd, blk, 0, s, lats, ctrl, steps);
-        break;
+    case 0: launch_resident_mf<M, 0>(q9, n, lats, ctrl, steps, s); break;
+    case kUnitTau: launch_resident_mf<M, kUnitTau>(q9, n, lats, ctrl, steps, s); break;
+    case kNoisy: launch_resident_mf<M, kNoisy>(q9, n, lats, ctrl, steps, s); break;
+    default: launch_resident_mf<M, kUnitTau | kNoisy>(q9, n, lats, ctrl, steps, s); break;
     }
 }
 
-static hipError_t launch_resident(int model, int flags, int n, const LatDesc *lats, const Ctrl *ctrl, int steps,
-                                  hipStream_t s)
+static hipError_t launch_resident(int lattice, int model, int flags, int n, const LatDesc *lats, const Ctrl *ctrl,
+                                  int steps, hipStream_t s)
 {
+    const bool q9 = lattice == LBM_D2Q9;
     if (model == LBM_MIPS)
-        launch_resident_m<kMips>(flags, n, lats, ctrl, steps, s);
+        launch_resident_m<kMips>(q9, flags, n, lats, ctrl, steps, s);
     else if (model == LBM_CIL)
-        launch_resident_m<kCil>(flags, n, lats, ctrl, steps, s);
+        launch_resident_m<kCil>(q9, flags, n, lats, ctrl, steps, s);
     else
-        launch_resident_m<kPassive>(flags, n, lats, ctrl, steps, s);
+        launch_resident_m<kPassive>(q9, flags, n, lats, ctrl, steps, s);
     return hipGetLastError();
 }
 
@@ -1227,15 +1322,15 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         cands.push_back(kResident);
     if (o->tile_rows == LBM_TILE_RESIDENT) {
         if (!resident_ok)
-            return fail(LBM_EINVAL, "tile_rows LBM_TILE_RESIDENT needs D2Q7 lattices of at most " +
-                                        std::to_string(kResidentSites) + " sites");
+            return fail(LBM_EINVAL, "tile_rows LBM_TILE_RESIDENT needs lattices of at most " +
+                                        std::to_string(kResidentSites) + " (D2Q7) or " +
+                                        std::to_string(kResidentSitesQ9) + " (D2Q9) sites");
         shape = kResident;
     }
     if (shape < 0 && o->tile_rows != 0)
-        return fail(LBM_EINVAL, mips ? (q9 ? "D2Q9 MIPS batches take tile_rows 0 or 16"
+        return fail(LBM_EINVAL, mips ? (q9 ? "D2Q9 MIPS batches take tile_rows 0, 16 or LBM_TILE_RESIDENT"
                                           : "MIPS batches take tile_rows 0, 4, 16 or LBM_TILE_RESIDENT")
-                                     : q9 ? "D2Q9 tile_rows must be 0, 1, 2, 4, 8 or 16"
-                                          : "tile_rows must be 0, 1, 2, 4, 8, 16 or LBM_TILE_RESIDENT");
+                                     : "tile_rows must be 0, 1, 2, 4, 8, 16 or LBM_TILE_RESIDENT");
     const std::string sig = signature(ps, n, flags);
     if (shape < 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1324,7 +1419,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
             if (res && e == hipSuccess)  // first buffer -> second buffer
-                e = launch_resident(ps[0].model, flags, n, d_lat, d_ctrl, kResidentTuneSteps, cap);
+                e = launch_resident(ps[0].lattice, ps[0].model, flags, n, d_lat, d_ctrl, kResidentTuneSteps, cap);
             // ten launches per lattice group, group after group, as the sweep runs them
             const std::vector<int64_t> gr = res ? std::vector<int64_t>{} : group_ranges(ps, cache_groups(ps, n), k);
             for (size_t g = 0; 2 * g < gr.size(); ++g)
@@ -1398,7 +1493,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     auto enqueue = [&](int64_t steps, bool sample) -> hipError_t {
         int64_t done = 0, launches = 0;
         if (resident && steps > 0) {
-            hipError_t e = launch_resident(ps[0].model, flags, n, d_lat, d_ctrl, (int)steps, s);
+            hipError_t e = launch_resident(ps[0].lattice, ps[0].model, flags, n, d_lat, d_ctrl, (int)steps, s);
             if (e != hipSuccess)
                 return e;
             done = steps;

@@ -108,7 +108,7 @@ def test_square_lattice_validation():
     q9m = L.make_params(128, 128, L.LBM_MIPS, tau=2.0, rho_star=1.0, lattice=L.LBM_D2Q9)
     for rows in (4, 8):
         assert _sweep(L, [q9m], tile_rows=rows) == L.LBM_EINVAL and "D2Q9" in L.lbm_last_error()
-    assert _sweep(L, [q9], tile_rows=L.LBM_TILE_RESIDENT) == L.LBM_EINVAL  # the resident form is D2Q7 only
+    assert _sweep(L, [q9], tile_rows=L.LBM_TILE_RESIDENT) == L.LBM_EINVAL  # 16384 sites: too large for LDS
     q9h = L.make_params(128, 128, L.LBM_CIL, storage=L.LBM_BF16_DEV, rho_ref=1.0, lattice=L.LBM_D2Q9)
     assert _sweep(L, [q9h]) == L.LBM_EUNSUPPORTED
     assert L._lib.lbm_coarsen(ctypes.byref(q9), ctypes.c_void_p(16), 4, ctypes.c_void_p(32), None) == \
@@ -118,9 +118,10 @@ def test_square_lattice_validation():
 
 
 def test_resident_form_validation():
-    """LBM_TILE_RESIDENT takes D2Q7 lattices of at most 4096 sites, any model
-    (the call then reaches the device: a HIP error without a GPU); a larger
-    lattice anywhere in the batch is refused before any HIP call."""
+    """LBM_TILE_RESIDENT takes lattices of at most 4096 sites (D2Q7) or 3072
+    (D2Q9), any model (the call then reaches the device: a HIP error without
+    a GPU); a larger lattice anywhere in the batch is refused before any HIP
+    call."""
     import paper_1902_00530_amd as L
     R = L.LBM_TILE_RESIDENT
     small = L.make_params(64, 64, L.LBM_MIPS, tau=2.0, rho_star=1.0)
@@ -131,6 +132,10 @@ def test_resident_form_validation():
     over = L.make_params(2050, 2, L.LBM_CIL, A=0.1, B=0.3)  # 4100 sites, one row pair
     assert _sweep(L, [over], tile_rows=R) == L.LBM_EINVAL
     assert _sweep(L, [L.make_params(2048, 2, L.LBM_CIL, A=0.1, B=0.3)], tile_rows=R) in (L.LBM_OK, L.LBM_EHIP)
+    # D2Q9: nine planes and the densities, at most 3072 sites
+    q9 = dict(lattice=L.LBM_D2Q9, A=0.1, B=0.3)
+    assert _sweep(L, [L.make_params(64, 48, L.LBM_CIL, **q9)], tile_rows=R) in (L.LBM_OK, L.LBM_EHIP)
+    assert _sweep(L, [L.make_params(62, 50, L.LBM_CIL, **q9)], tile_rows=R) == L.LBM_EINVAL
     assert _sweep(L, [big], tile_rows=3) == L.LBM_EINVAL and "LBM_TILE_RESIDENT" in L.lbm_last_error()
 
 

@@ -491,3 +491,78 @@ def test_batch_lattice_groups(L, tile_rows):
     torch.cuda.synchronize()
     for l in range(len(params)):
         assert torch.equal(b.state(l), singles[l]), l
+
+
+# ---------------------------------------------------------------- lattices resident in LDS
+
+Q9_RESIDENT_SIZES = [(2, 2), (3, 3), (40, 7), (90, 30), (66, 19), (64, 48), (7, 100)]
+
+
+def _q9_resident_batch(model):
+    kw = {SI.CIL: dict(tau=1.0, sigma=4 / 70, A=0.125, B=0.3),
+          SI.PASSIVE: dict(tau=1.3, sigma=0.01),
+          SI.MIPS: dict(tau=2.0, sigma=8 / 70, C=6.25, rho_star=1.6, u_max=0.3)}[model]
+    return [_cfg(model, nx, ny, seed=SI.seed_for(13, l), **kw) for l, (nx, ny) in enumerate(Q9_RESIDENT_SIZES)]
+
+
+@pytest.mark.parametrize("model,use_graph,steps", [(SI.MIPS, 1, 1100), (SI.MIPS, 0, 37), (SI.CIL, 1, 38),
+                                                   (SI.PASSIVE, 1, 37)])
+def test_resident_member_equals_single_run(L, model, use_graph, steps):
+    """Square lattices of at most 3072 sites (odd ny and lattices narrower
+    than a wave among them) resident in LDS: every member equals its lbm_step
+    run bit for bit, across a captured chunk (1100 steps)."""
+    cfgs = _q9_resident_batch(model)
+    states = _q9_states(L, cfgs)
+    b = L.Batch([_gp(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    out = b.run(steps, tile_rows=L.LBM_TILE_RESIDENT, use_graph=use_graph)
+    for l, c in enumerate(cfgs):
+        lat = L.Lattice(_gp(L, c))
+        lat.set_state(states[l])
+        lat.step(steps)
+        o = lat.observables()
+        assert torch.equal(b.state(l), lat.state), l
+        lat.close()
+        for k in ("M", "phi", "drho"):
+            assert abs(out[l][0][k] - o[k]) <= 1e-12 * max(1.0, abs(o[k])), (l, k)
+
+
+def test_resident_samples_density_ramp_and_tuning(L):
+    """Resident MIPS square lattices with samples every 10 steps and the
+    density change after each (drho / 9 per population), against single runs
+    with lbm_add_density bit for bit; and twelve 90 x 30 lattices tuned among
+    the tile and resident forms, equal to single runs."""
+    cfgs = _q9_resident_batch(SI.MIPS)
+    states = _q9_states(L, cfgs)
+    drho = [0.01 * (l - 3) for l in range(len(cfgs))]
+    b = L.Batch([_gp(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    out = b.run(30, sample_every=10, drho=drho, tile_rows=L.LBM_TILE_RESIDENT)
+    for l, c in enumerate(cfgs):
+        lat = L.Lattice(_gp(L, c))
+        lat.set_state(states[l])
+        obs = []
+        for _ in range(3):
+            lat.step(10)
+            obs.append(lat.observables())
+            lat.add_density(drho[l])
+        assert torch.equal(b.state(l), lat.state), l
+        lat.close()
+        for o, s in zip(out[l], obs):
+            assert abs(o["M"] - s["M"]) <= 1e-12 * s["M"] and abs(o["drho"] - s["drho"]) <= 1e-12
+    kw = dict(tau=2.0, sigma=8 / 70, C=6.25, rho_star=1.6, u_max=0.3)
+    cfgs = [_cfg(SI.MIPS, 90, 30, seed=SI.seed_for(14, l), **kw) for l in range(12)]
+    states = _q9_states(L, cfgs)
+    b = L.Batch([_gp(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    b.run(200)
+    assert L.lbm_sweep_tile_rows(b.params, b.n) in (16, L.LBM_TILE_RESIDENT)
+    for l, c in enumerate(cfgs):
+        lat = L.Lattice(_gp(L, c))
+        lat.set_state(states[l])
+        lat.step(200)
+        assert torch.equal(b.state(l), lat.state), l
+        lat.close()
