@@ -1427,14 +1427,14 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
                     e = launch_batch_step(ps[0].lattice, ps[0].model, flags, k, gr[2 * g + 1], tl.first + gr[2 * g],
                                           d_lat, d_ctrl, 0, 0, cap);
             hipError_t ee = hipStreamEndCapture(cap, &g);
-            hipStreamDestroy(cap);
+            (void)hipStreamDestroy(cap);
             if (e == hipSuccess)
                 e = ee;
             hipGraphExec_t ge = nullptr;
             if (e == hipSuccess)
                 e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
             if (g)
-                hipGraphDestroy(g);
+                (void)hipGraphDestroy(g);
             float ms = 1e30f;
             for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
                 e = hipEventRecord(e0, s);
@@ -1451,7 +1451,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
                     ms = std::min(ms, res ? m * 10.0f / kResidentTuneSteps : m / (float)kShapes[k].steps);
             }
             if (ge)
-                hipGraphExecDestroy(ge);
+                (void)hipGraphExecDestroy(ge);
             if (e != hipSuccess)
                 return hip_fail(e, "tile-shape tuning");
             if (ms < best) {
@@ -1555,7 +1555,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         // every call before it runs), so it is kept and replayed by later
         // calls with the same key
         int dev = 0;
-        hipGetDevice(&dev);
+        (void)hipGetDevice(&dev);
         const GraphKey key{dev, (const void *)main_list.first, (const void *)one_list.first, (const void *)d_lat,
                            (const void *)d_ctrl, (const void *)d_mt, (const void *)d_part, (const void *)d_colpart,
                            (const void *)d_colmean, (const void *)d_results, ps[0].lattice, ps[0].model, flags,
@@ -1575,14 +1575,14 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         hipError_t ce = be == hipSuccess ? enqueue(steps, sample) : be;
         hipError_t ee = be == hipSuccess ? hipStreamEndCapture(cap, &g) : be;
         s = saved;
-        hipStreamDestroy(cap);
+        (void)hipStreamDestroy(cap);
         if (ce != hipSuccess)
             return ce;
         if (ee != hipSuccess)
             return ee;
         auto holder = std::make_shared<GraphExec>();
         e = hipGraphInstantiate(&holder->exec, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (e == hipSuccess) {
             *ge = holder;
             graph_cache_put(key, holder);
