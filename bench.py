@@ -59,7 +59,8 @@ def parse():
                     help="default: batch for the D2Q7 CIL workloads in FP32, single (lbm_step) otherwise")
     ap.add_argument("--quick", action="store_true", help="headline measurement only (no variants)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=25)
+    ap.add_argument("--cpu-steps", type=int, default=24,
+                    help="oracle steps of the 1024^2 single-thread baseline run x 6 (default: 4 steps)")
     ap.add_argument("--tile-rows", type=int, default=0,
                     help="batch work tile: 0 tuned, 1/2/4 one step per launch, 8/16 two steps per launch, 1024 lattices resident in LDS")
     ap.add_argument("--copy-probe", action="store_true",
@@ -83,21 +84,62 @@ def cpu_mips64(steps=1000):
             "sample": f"MIPS 64x64, {steps} steps, FP64, single thread"}
 
 
+def host_cpu():
+    """(model name, logical CPUs of the machine, threads this process may use:
+    its CPU affinity, capped by OMP_NUM_THREADS when that is set)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    threads = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        threads = min(threads, int(env))
+    return model, os.cpu_count(), max(1, threads)
+
+
 def cpu_baseline(steps):
-    """FP64 oracle, single thread, on one lattice of the workload."""
+    """FP64 oracle on the CIL workload's parameters at 64^2, 256^2 and 1024^2
+    sites, on one host thread (the plain build) and on every thread this
+    process may use (the OpenMP build: rows of a step in parallel, the same
+    per-site arithmetic).  Each run takes about 4 M site-updates single
+    threaded (4x that on all threads), a few seconds in all.  value: all
+    threads at 1024^2, the benchmark's lattice size."""
     import oracle as O
     import synth_inputs as SI
-    cfg = SI.cil_1024(1.0)
-    ini = cfg.pop("init")
-    p = O.make_params(cfg["nx"], cfg["ny"], cfg["model"], cfg["tau"], cfg["sigma"], cfg["A"], cfg["B"], cfg["C"],
-                      cfg["rho_star"], cfg["u_max"], cfg["seed"])
-    f = O.initialise(p, **ini)
-    t0 = time.perf_counter()
-    O.run(p, f, steps)
-    dt = time.perf_counter() - t0
-    return {"value": round(cfg["nx"] * cfg["ny"] * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
-            "kind": "oracle",
-            "sample": f"one 1024x1024 CIL lattice (mean density 1.0) for {steps} steps, FP64, single thread"}
+    model, ncpu, threads = host_cpu()
+    table = {}
+    for n, s1 in ((64, 1000), (256, 64), (1024, max(1, steps // 6))):
+        cfg = dict(SI.cil_1024(1.0), nx=n, ny=n)
+        ini = cfg.pop("init")
+        p = O.make_params(cfg["nx"], cfg["ny"], cfg["model"], cfg["tau"], cfg["sigma"], cfg["A"], cfg["B"],
+                          cfg["C"], cfg["rho_star"], cfg["u_max"], cfg["seed"])
+        f0 = O.initialise(p, **ini)
+        row = {}
+        for th, st in ((1, s1), (threads, s1 * 4)):
+            f = f0.copy()
+            t0 = time.perf_counter()
+            if th == 1:
+                O.run(p, f, st)
+                used = 1
+            else:
+                used = O.run_parallel(p, f, st, th)
+            dt = time.perf_counter() - t0
+            row[str(used)] = {"MLUPS": round(n * n * st / dt / 1e6, 3), "steps": st, "seconds": round(dt, 3)}
+        table[f"{n}x{n}"] = row
+    top = table["1024x1024"][str(threads)] if str(threads) in table["1024x1024"] else \
+        list(table["1024x1024"].values())[-1]
+    return {"value": top["MLUPS"], "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": (f"one 1024x1024 CIL lattice (mean density 1.0) for {top['steps']} steps, FP64, "
+                       f"{threads} host threads (OpenMP over rows); the table gives 1 and {threads} threads "
+                       "at 64^2, 256^2 and 1024^2"),
+            "host_cpu_model": model, "host_logical_cpus": ncpu, "threads_available": threads,
+            "by_size_and_threads": table}
 
 
 def cpu_q9(steps):

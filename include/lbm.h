@@ -58,12 +58,12 @@
  *    in LDS up to 3072 sites; the coarse-field calls take D2Q7 only
  *    (LBM_EUNSUPPORTED).
  *
- * Memory ownership.  The caller owns every device buffer passed in
- * (population buffers, field outputs, batch buffers, workspaces, network
- * tensors) and the HIP stream, and keeps them alive until the context that
- * uses them is destroyed.  A context owns a host object, a small device
- * scratch for reductions (allocated by lbm_create, freed by lbm_destroy) and
- * any HIP graphs it captures.
+ * Memory ownership.  The library never allocates or frees device memory.
+ * The caller owns every device buffer passed in (population buffers, field
+ * outputs, batch buffers, workspaces, network tensors) and the HIP stream,
+ * and keeps them alive until the context that uses them is destroyed.  A
+ * context owns a host object and the HIP graphs it captures; its device
+ * scratch (step clock, reduction partials) lives in the caller's workspace.
  *
  * Errors.  Every entry point returns an int32_t status: LBM_OK (0) or a
  * negative code.  The message of the last error on the calling thread is
@@ -147,25 +147,40 @@ typedef struct lbm_obs {
 
 typedef struct lbm_ctx lbm_ctx;
 
+/* Device workspace bytes a context of these parameters needs (its step
+ * clock and the reduction scratch of lbm_moments); 0 on invalid
+ * parameters. */
+size_t lbm_workspace_bytes(const lbm_params *p, int64_t pitch);
+
 /* Create a lattice context on the current HIP device.
- *   p       parameters (copied).
- *   f_a,f_b two caller-owned device buffers [Q][ny][pitch] of the storage
- *           type (Q = 7 on D2Q7, 9 on D2Q9); the state starts in f_a.
- *   pitch   row pitch in elements, >= nx.
- *   init    initial state written into f_a (NULL or LBM_INIT_NONE: the caller
- *           has filled f_a).
- *   stream  caller's hipStream_t (NULL: the null stream), cast to void*.
- *   out     receives the context.
+ *   p        parameters (copied).
+ *   f_a,f_b  two caller-owned device buffers [Q][ny][pitch] of the storage
+ *            type (Q = 7 on D2Q7, 9 on D2Q9); the state starts in f_a.
+ *   pitch    row pitch in elements, >= nx.
+ *   init     initial state written into f_a (NULL or LBM_INIT_NONE: the
+ *            caller has filled f_a).
+ *   ws       caller-owned device workspace, 256-byte aligned, of ws_bytes >=
+ *            lbm_workspace_bytes(p, pitch); used by this context alone until
+ *            lbm_destroy.
+ *   stream   caller's hipStream_t (NULL: the null stream), cast to void*.
+ *   out      receives the context.
+ * Enqueues the initial state (if any) and the step clock's start; no sync.
  * Returns LBM_EINVAL for nx < 2, ny < 2 or > 65535 (or odd on D2Q7),
  * nx*ny >= 2^32, pitch < nx, tau < 1, sigma < 0, non-finite or negative model
- * constants, null or equal buffers, unknown lattice/model/storage/init mode;
- * LBM_EUNSUPPORTED for a D2Q9 plane of 2^32 bytes or more. */
-int32_t lbm_create(const lbm_params *p, void *f_a, void *f_b, int64_t pitch, const lbm_init *init,
-                   void *stream, lbm_ctx **out);
+ * constants, null or equal buffers, a null, misaligned or short workspace,
+ * unknown lattice/model/storage/init mode; LBM_EUNSUPPORTED for a D2Q9 plane
+ * of 2^32 bytes or more. */
+int32_t lbm_create(const lbm_params *p, void *f_a, void *f_b, int64_t pitch, const lbm_init *init, void *ws,
+                   size_t ws_bytes, void *stream, lbm_ctx **out);
 
-/* Enqueue n >= 0 steps on the context's stream (no synchronisation).  The
- * state alternates between the two buffers; lbm_current_buffer() tells which
- * holds it afterwards. */
+/* Enqueue n >= 0 steps on the context's stream (no synchronisation), one
+ * kernel launch per step.  Runs of 64 steps replay a HIP graph captured on
+ * first use (one per starting buffer); the remainder, and every step while
+ * the caller is capturing the stream itself, are launched directly.  Every
+ * launch reads its step index (the noise counter) from the workspace's step
+ * clock, so graphs replay with unchanged arguments.  The state alternates
+ * between the two buffers; lbm_current_buffer() tells which holds it
+ * afterwards. */
 int32_t lbm_step(lbm_ctx *c, int64_t n);
 
 /* Fields and observables of the stored state.  rho, ux, uy: caller-owned
@@ -179,7 +194,7 @@ int32_t lbm_moments(lbm_ctx *c, float *rho, float *ux, float *uy, lbm_obs *obs);
 int32_t lbm_current_buffer(const lbm_ctx *c);
 
 /* Absolute step index of the stored state (the Philox counter of the next
- * step); lbm_set_step sets it (checkpoint/resume). */
+ * step); lbm_set_step sets it (checkpoint/resume; enqueued on the stream). */
 int64_t lbm_get_step(const lbm_ctx *c);
 int32_t lbm_set_step(lbm_ctx *c, int64_t step);
 
@@ -236,6 +251,15 @@ typedef struct lbm_sweep_opts {
                              sample, every population of lattice l gains drho[l] / Q
                              (the density ramp of the paper's protocol, appendix
                              "Simulation procedure for results"); finite values only */
+    int32_t keep_tables;  /* 0: build and upload the batch's tables (lattice descriptors,
+                             tile lists) into ws.  1: the caller promises that ws still
+                             holds what the library wrote into it on the last call with
+                             this ws (it has not written into ws since, nor freed and
+                             reallocated it); tables that this call would write
+                             identically are then not rebuilt or uploaded, so a repeated
+                             sweep of one batch enqueues its first kernel without host
+                             work.  Pass 0 on the first call after allocating ws */
+    int32_t reserved;     /* 0 */
 } lbm_sweep_opts;
 
 /* Workspace bytes lbm_sweep_batch needs for these n lattices and n_samples

@@ -39,45 +39,59 @@ class Obs(ctypes.Structure):
 
 
 _lib = None
+_lib_omp = None
 
 
 def lib():
     global _lib
     if _lib is None:
-        path = _build.LIB
-        if not os.path.exists(path):
-            _build.build()
-        L = ctypes.CDLL(path)
-        dp = ctypes.POINTER(ctypes.c_double)
-        u32p = ctypes.POINTER(ctypes.c_uint32)
-        L.orc_philox4x32.argtypes = [ctypes.c_int, u32p, u32p, u32p]
-        L.orc_neighbour.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_int)] * 2
-        L.orc_lattice_vector.argtypes = [ctypes.c_int, dp, dp]
-        L.orc_weight.argtypes = [ctypes.c_int]
-        L.orc_weight.restype = ctypes.c_double
-        L.orc_xi.argtypes = [ctypes.c_double] * 3 + [dp]
-        L.orc_moments.argtypes = [dp, dp, dp, dp]
-        L.orc_ustar_local.argtypes = [ctypes.POINTER(Params), ctypes.c_double, ctypes.c_double,
-                                      ctypes.c_double, dp, dp]
-        L.orc_ustar_mips.argtypes = [ctypes.POINTER(Params), ctypes.c_double, ctypes.c_double,
-                                     ctypes.c_double, dp, dp]
-        L.orc_gradient.argtypes = [dp, dp, dp]
-        L.orc_noise.argtypes = [ctypes.POINTER(Params), ctypes.c_uint32, ctypes.c_int64, dp]
-        L.orc_correct.argtypes = [dp, ctypes.c_double]
-        L.orc_correct.restype = ctypes.c_int
-        L.orc_step.argtypes = [ctypes.POINTER(Params), dp, ctypes.c_int64]
-        L.orc_step.restype = ctypes.c_int
-        L.orc_run.argtypes = [ctypes.POINTER(Params), dp, ctypes.c_int64, ctypes.c_int64]
-        L.orc_run.restype = ctypes.c_int
-        L.orc_initialise.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Init), dp]
-        L.orc_initialise.restype = ctypes.c_int
-        L.orc_observables.argtypes = [ctypes.POINTER(Params), dp, ctypes.POINTER(Obs)]
-        L.orc_fields.argtypes = [ctypes.POINTER(Params), dp, dp, dp, dp]
-        L.orc_observables_of.argtypes = [ctypes.POINTER(Params), dp, ctypes.POINTER(Obs)]
-        L.orc_fields_of.argtypes = [ctypes.POINTER(Params), dp, dp, dp, dp]
-        L.orc_stream.argtypes = [ctypes.POINTER(Params), dp, dp]
-        _lib = L
+        _lib = _load(_build.LIB)
     return _lib
+
+
+def lib_parallel():
+    """The OpenMP build of the same sources (host-core timing only)."""
+    global _lib_omp
+    if _lib_omp is None:
+        _lib_omp = _load(_build.LIB_OMP)
+    return _lib_omp
+
+
+def _load(path):
+    if not os.path.exists(path):
+        _build.build()
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    L.orc_philox4x32.argtypes = [ctypes.c_int, u32p, u32p, u32p]
+    L.orc_neighbour.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_int)] * 2
+    L.orc_lattice_vector.argtypes = [ctypes.c_int, dp, dp]
+    L.orc_weight.argtypes = [ctypes.c_int]
+    L.orc_weight.restype = ctypes.c_double
+    L.orc_xi.argtypes = [ctypes.c_double] * 3 + [dp]
+    L.orc_moments.argtypes = [dp, dp, dp, dp]
+    L.orc_ustar_local.argtypes = [ctypes.POINTER(Params), ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, dp, dp]
+    L.orc_ustar_mips.argtypes = [ctypes.POINTER(Params), ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, dp, dp]
+    L.orc_gradient.argtypes = [dp, dp, dp]
+    L.orc_noise.argtypes = [ctypes.POINTER(Params), ctypes.c_uint32, ctypes.c_int64, dp]
+    L.orc_correct.argtypes = [dp, ctypes.c_double]
+    L.orc_correct.restype = ctypes.c_int
+    L.orc_step.argtypes = [ctypes.POINTER(Params), dp, ctypes.c_int64]
+    L.orc_step.restype = ctypes.c_int
+    L.orc_run.argtypes = [ctypes.POINTER(Params), dp, ctypes.c_int64, ctypes.c_int64]
+    L.orc_run.restype = ctypes.c_int
+    L.orc_initialise.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Init), dp]
+    L.orc_initialise.restype = ctypes.c_int
+    L.orc_observables.argtypes = [ctypes.POINTER(Params), dp, ctypes.POINTER(Obs)]
+    L.orc_fields.argtypes = [ctypes.POINTER(Params), dp, dp, dp, dp]
+    L.orc_observables_of.argtypes = [ctypes.POINTER(Params), dp, ctypes.POINTER(Obs)]
+    L.orc_fields_of.argtypes = [ctypes.POINTER(Params), dp, dp, dp, dp]
+    L.orc_stream.argtypes = [ctypes.POINTER(Params), dp, dp]
+    L.orc_set_threads.argtypes = [ctypes.c_int]
+    L.orc_set_threads.restype = ctypes.c_int
+    return L
 
 
 def _dp(a):
@@ -164,6 +178,18 @@ def run(p, f, nsteps, step0=0):
     if rc:
         raise ValueError(f"oracle run failed rc={rc}")
     return f
+
+
+def run_parallel(p, f, nsteps, threads, step0=0):
+    """run() with a step's rows on `threads` host threads (the OpenMP build);
+    returns the thread count in effect."""
+    assert f.dtype == np.float64 and f.flags.c_contiguous and f.shape == (7, p.ny, p.nx)
+    L = lib_parallel()
+    used = L.orc_set_threads(int(threads))
+    rc = L.orc_run(ctypes.byref(p), _dp(f), int(step0), int(nsteps))
+    if rc:
+        raise ValueError(f"oracle run failed rc={rc}")
+    return used
 
 
 def initialise(p, mode=INIT_UNIFORM_DIR, rho_mean=1.0, rho_spread=0.1, angle_std=0.0, u_mag=-1.0,

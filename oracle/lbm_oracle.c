@@ -24,12 +24,32 @@
  *   - the rescale of the negative correction uses this step's density and is
  *     applied only at sites where rule (i) or (ii) fired;
  *   - the MIPS clamp keeps the direction of u* and scales its length to U_max.
+ *
+ * The row loops of a step carry OpenMP pragmas: each row writes only its own
+ * sites, so the timing build (-fopenmp, liboracle_omp.so) runs rows on
+ * several host threads with the same per-site arithmetic; the plain build
+ * ignores the pragmas.
  */
 #include "lbm_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------
  * Philox4x32-R (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as
@@ -280,6 +300,7 @@ void orc_stream(const orc_params *p, const double *in, double *out)
 {
     const int nx = p->nx, ny = p->ny;
     const size_t n = plane(p);
+#pragma omp parallel for
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x)
             for (int i = 0; i < 7; ++i) {
@@ -309,6 +330,7 @@ int orc_step(const orc_params *p, double *f, int64_t step)
     /* (i) streaming */
     orc_stream(p, f, fs);
     /* (ii) densities of the whole streamed lattice (the MIPS gradient needs them) */
+#pragma omp parallel for
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             double g[7], r, jx, jy;
@@ -317,6 +339,7 @@ int orc_step(const orc_params *p, double *f, int64_t step)
             orc_moments(g, &r, &jx, &jy);
             rho[(size_t)y * nx + x] = r;
         }
+#pragma omp parallel for
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t s = (size_t)y * nx + x;

@@ -93,6 +93,10 @@ void orc_fields_of(const orc_params *p, const double *f, double *rho, double *ux
 void orc_observables(const orc_params *p, const double *f, orc_obs *out);
 void orc_fields(const orc_params *p, const double *f, double *rho, double *ux, double *uy);
 
+/* Host threads of a step's row loops in the OpenMP build (n <= 0 keeps the
+ * current count); returns the count in effect, 1 in the plain build. */
+int orc_set_threads(int n);
+
 /* ------------------------------------------------------------------------
  * Square-lattice (D2Q9) variant, lbm_oracle_q9.c: populations f[9][ny][nx];
  * same parameter, init and observable structs; ny may be odd.

@@ -50,7 +50,8 @@ class lbm_obs(ctypes.Structure):
 class lbm_sweep_opts(ctypes.Structure):
     _fields_ = [("n_steps", ctypes.c_int64), ("sample_every", ctypes.c_int64), ("step0", ctypes.c_int64),
                 ("tile_rows", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("drho", ctypes.POINTER(ctypes.c_double))]
+                ("drho", ctypes.POINTER(ctypes.c_double)), ("keep_tables", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class lbm_cnn_shape(ctypes.Structure):
@@ -87,7 +88,9 @@ _vp = ctypes.c_void_p
 _P = ctypes.POINTER
 
 _SIGS = {
-    "lbm_create": (ctypes.c_int32, [_P(lbm_params), _vp, _vp, ctypes.c_int64, _P(lbm_init), _vp, _P(_vp)]),
+    "lbm_workspace_bytes": (ctypes.c_size_t, [_P(lbm_params), ctypes.c_int64]),
+    "lbm_create": (ctypes.c_int32, [_P(lbm_params), _vp, _vp, ctypes.c_int64, _P(lbm_init), _vp, ctypes.c_size_t,
+                                    _vp, _P(_vp)]),
     "lbm_step": (ctypes.c_int32, [_vp, ctypes.c_int64]),
     "lbm_moments": (ctypes.c_int32, [_vp, _vp, _vp, _vp, _P(lbm_obs)]),
     "lbm_current_buffer": (ctypes.c_int32, [_vp]),
@@ -140,10 +143,15 @@ def _check(rc, where):
 
 # ----------------------------------------------------------------- raw ABI
 
-def lbm_create(params, f_a, f_b, pitch, init, stream):
+def lbm_workspace_bytes(params, pitch):
+    return _lib.lbm_workspace_bytes(ctypes.byref(params), int(pitch))
+
+
+def lbm_create(params, f_a, f_b, pitch, init, ws, ws_bytes, stream):
     ctx = _vp()
     _check(_lib.lbm_create(ctypes.byref(params), f_a, f_b, int(pitch),
-                           ctypes.byref(init) if init is not None else None, stream, ctypes.byref(ctx)),
+                           ctypes.byref(init) if init is not None else None, ws, int(ws_bytes), stream,
+                           ctypes.byref(ctx)),
            "lbm_create")
     return ctx
 
@@ -272,6 +280,7 @@ class Batch:
         self.current = [0] * self.n
         self.step_index = 0
         self._ws = None
+        self._ws_written = False
 
     def state(self, l):
         return self.buffers[2 * l + self.current[l]]
@@ -307,8 +316,12 @@ class Batch:
         need = lbm_sweep_workspace_bytes(params, m, n_samples)
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.buffers[0].device)
+            self._ws_written = False
         out = (lbm_obs * (m * n_samples))()
         opts = lbm_sweep_opts(int(n_steps), int(sample_every), int(self.step_index), int(tile_rows), int(use_graph))
+        # the workspace is this object's alone: after the first call with it,
+        # the library may keep the tables it wrote there
+        opts.keep_tables = 1 if self._ws_written else 0
         if drho is not None:
             vals = [float(drho)] * m if np.isscalar(drho) else [float(v) for v in drho]
             if len(vals) != m:
@@ -316,7 +329,10 @@ class Batch:
             dr = (ctypes.c_double * m)(*vals)
             opts.drho = dr
         st = stream if stream is not None else torch.cuda.current_stream()
-        lbm_sweep_batch(params, m, opts, bufs, self._ws.data_ptr(), need, st.cuda_stream, out)
+        try:
+            lbm_sweep_batch(params, m, opts, bufs, self._ws.data_ptr(), need, st.cuda_stream, out)
+        finally:
+            self._ws_written = True
         if use_graph == 2:  # prepared the launch plan only; no step ran
             return []
         if subset is None:
@@ -363,8 +379,12 @@ class Lattice:
         q = n_populations(params)
         self.buffers = [torch.zeros((q, params.ny, self.pitch), dtype=dt, device=device) for _ in range(2)]
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        nws = lbm_workspace_bytes(params, self.pitch)
+        if nws == 0:
+            raise LbmError(LBM_EINVAL, "lbm_workspace_bytes")
+        self.workspace = torch.empty(nws, dtype=torch.uint8, device=device)
         self.ctx = lbm_create(params, self.buffers[0].data_ptr(), self.buffers[1].data_ptr(), self.pitch, init,
-                              self.stream.cuda_stream)
+                              self.workspace.data_ptr(), nws, self.stream.cuda_stream)
 
     def step(self, n=1):
         lbm_step(self.ctx, n)

@@ -27,6 +27,7 @@
 // memory that the last node advances, so no kernel arguments change between
 // replays and no kernel waits on another workgroup.
 #include <math.h>
+#include <string.h>
 
 #include <algorithm>
 #include <chrono>
@@ -742,30 +743,47 @@ __global__ __launch_bounds__(256) void k_batch_moments(const MomTile *__restrict
             part[(int64_t)blockIdx.x * 5 + k] = ((lds[0][k] + lds[1][k]) + lds[2][k]) + lds[3][k];
 }
 
-// One block per lattice: totals of its tiles, column means, their variance;
-// writes 8 doubles {M, Jx, Jy, sum|j|, nonfinite, mean, var, step} of sample s.
+// Column means rho_y(x) of every lattice: one thread per column (grid y =
+// lattice), the column's row-block partials added in row order.  Many
+// blocks, so a sample of a few large lattices does not wait on a handful of
+// CUs walking every column.
+__global__ __launch_bounds__(256) void k_batch_colmeans(const LatDesc *__restrict__ lats,
+                                                        const double *__restrict__ colpart,
+                                                        double *__restrict__ colmean)
+{
+    const LatDesc &L = lats[blockIdx.y];
+    const int nx = L.a.nx;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx)
+        return;
+    const double *cp = colpart + L.col_off + x;
+    double c = 0.0;
+#pragma unroll 16
+    for (int r = 0; r < L.nrb; ++r)
+        c += cp[(int64_t)r * nx];
+    colmean[L.cm_off + x] = c / (double)L.a.ny;
+}
+
+// One block per lattice: totals of its tiles, the mean of its column means
+// and their variance; writes 8 doubles {M, Jx, Jy, sum|j|, nonfinite, mean,
+// var, step} of sample s.
 __global__ __launch_bounds__(256) void k_batch_final(const LatDesc *__restrict__ lats, const Ctrl *__restrict__ ctrl,
                                                      int node, const double *__restrict__ part,
-                                                     const double *__restrict__ colpart, double *__restrict__ colmean,
+                                                     const double *__restrict__ colmean,
                                                      double *__restrict__ results, int n_samples)
 {
     __shared__ double lds[4][6];
     __shared__ double mean_s;
     const LatDesc &L = lats[blockIdx.x];
-    const int nx = L.a.nx, ny = L.a.ny;
+    const int nx = L.a.nx;
+    const double *cm = colmean + L.cm_off;
     double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < L.mt_count; b += blockDim.x)
 #pragma unroll
         for (int k = 0; k < 5; ++k)
             v[k] += part[(int64_t)(L.mt_begin + b) * 5 + k];
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-        double c = 0.0;
-        for (int r = 0; r < L.nrb; ++r)
-            c += colpart[L.col_off + (int64_t)r * nx + x];
-        c /= (double)ny;
-        colmean[L.cm_off + x] = c;
-        v[5] += c;
-    }
+    for (int x = threadIdx.x; x < nx; x += blockDim.x)
+        v[5] += cm[x];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < 6; ++k)
@@ -781,7 +799,7 @@ __global__ __launch_bounds__(256) void k_batch_final(const LatDesc *__restrict__
     const double mean = mean_s;
     double q = 0.0;
     for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-        const double d = colmean[L.cm_off + x] - mean;
+        const double d = cm[x] - mean;
         q += d * d;
     }
     q = bwave_sum(q);
@@ -1223,6 +1241,39 @@ static void graph_cache_put(const GraphKey &k, const GraphPtr &g)
     g_graphs.emplace_back(k, g);
 }
 
+// What this library last wrote into the tables of a workspace (lattice
+// descriptors, moments tiles and the tile list held in each of the two list
+// regions), per device and workspace address.  A call with keep_tables set
+// takes the record at its word (its caller has not written into the
+// workspace since) and uploads only the tables that differ, so a repeated
+// sweep of the same batch starts its first kernel without host work.
+struct WsTables {
+    int lattice = -1;
+    std::vector<std::pair<int32_t, int32_t>> sizes;  // (nx, ny) of each lattice, in batch order
+    std::vector<LatDesc> lat;
+    int region[2] = {-1, -1};  // shape whose list is in the one-step / two-step region
+};
+constexpr size_t kWsRecords = 64;
+static std::mutex g_ws_mu;
+static auto &g_ws = *new std::map<std::pair<int, const void *>, WsTables>();
+
+// Field-by-field equality (bit patterns: +0 and -0 differ), so padding bytes
+// play no part.
+#define LBM_SAME(f) (memcmp(&x.f, &y.f, sizeof(x.f)) == 0)
+static bool same_args(const StepArgs &x, const StepArgs &y)
+{
+    return LBM_SAME(nx) && LBM_SAME(ny) && LBM_SAME(pitch) && LBM_SAME(plane) && LBM_SAME(omega) &&
+           LBM_SAME(noise_scale) && LBM_SAME(A16) && LBM_SAME(B16) && LBM_SAME(C) && LBM_SAME(rho_star) &&
+           LBM_SAME(inv_rho_star) && LBM_SAME(u_max) && LBM_SAME(wr0) && LBM_SAME(wr1) && LBM_SAME(wr2) &&
+           LBM_SAME(key0) && LBM_SAME(key1) && LBM_SAME(noisy);
+}
+static bool same_desc(const LatDesc &x, const LatDesc &y)
+{
+    return same_args(x.a, y.a) && LBM_SAME(buf) && LBM_SAME(B) && LBM_SAME(mt_begin) && LBM_SAME(mt_count) &&
+           LBM_SAME(nrb) && LBM_SAME(col_off) && LBM_SAME(cm_off) && LBM_SAME(add);
+}
+#undef LBM_SAME
+
 }  // namespace lbm
 
 using namespace lbm;
@@ -1349,10 +1400,11 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     double *d_colmean = (double *)(w + Ly.colmean);
     double *d_results = (double *)(w + Ly.results);
 
-    // descriptors and the moments tile list
+    // descriptors (and the moments tiles: per lattice, cx x cy tiles of 256
+    // columns x kMomRows rows)
     std::vector<LatDesc> lat(n);
-    std::vector<MomTile> mt;
-    int64_t col_off = 0, cm_off = 0;
+    std::vector<std::pair<int32_t, int32_t>> sizes(n);
+    int64_t col_off = 0, cm_off = 0, nmt = 0;
     for (int l = 0; l < n; ++l) {
         LatDesc &D = lat[l];
         D.a = make_step_args(ps[l], ps[l].nx);
@@ -1361,30 +1413,79 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         D.B = (float)ps[l].B;
         D.add = o->drho ? (float)(o->drho[l] / (ps[l].lattice == LBM_D2Q9 ? 9.0 : 7.0)) : 0.0f;
         const int cx = (ps[l].nx + 255) / 256, cy = (ps[l].ny + kMomRows - 1) / kMomRows;
-        D.mt_begin = (int32_t)mt.size();
+        D.mt_begin = (int32_t)nmt;
         D.mt_count = cx * cy;
         D.nrb = cy;
         D.col_off = col_off;
         D.cm_off = cm_off;
-        for (int j = 0; j < cy; ++j)
-            for (int i = 0; i < cx; ++i)
-                mt.push_back(MomTile{l, (int16_t)i, (int16_t)j});
+        nmt += (int64_t)cx * cy;
         col_off += (int64_t)cy * ps[l].nx;
         cm_off += ps[l].nx;
+        sizes[l] = {ps[l].nx, ps[l].ny};
     }
-    LBM_HIP_TRY(hipMemcpyAsync(d_lat, lat.data(), sizeof(LatDesc) * n, hipMemcpyHostToDevice, s));
-    LBM_HIP_TRY(hipMemcpyAsync(d_mt, mt.data(), sizeof(MomTile) * mt.size(), hipMemcpyHostToDevice, s));
+    // the workspace's record: a copy, written back once the uploads are enqueued
+    int dev = 0;
+    LBM_HIP_TRY(hipGetDevice(&dev));
+    const std::pair<int, const void *> ws_key{dev, ws};
+    WsTables rec;
+    if (o->keep_tables) {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        auto it = g_ws.find(ws_key);
+        if (it != g_ws.end())
+            rec = it->second;
+    }
+    const bool same_sizes = rec.lattice == ps[0].lattice && rec.sizes == sizes;
+    if (!same_sizes)
+        rec.region[0] = rec.region[1] = -1;
+    bool same_lat = same_sizes && rec.lat.size() == lat.size();
+    for (int l = 0; l < n && same_lat; ++l)
+        same_lat = same_desc(rec.lat[l], lat[l]);
+    // host copies of the uploaded tables stay alive until the stream is
+    // synchronised at the end of this call
+    std::vector<MomTile> mt;
+    std::vector<std::vector<BatchTile>> host_lists;
+    auto save_record = [&]() {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        if (g_ws.size() >= kWsRecords && !g_ws.count(ws_key))
+            g_ws.erase(g_ws.begin());
+        g_ws[ws_key] = rec;
+    };
+    // a failed call leaves the workspace's tables unknown
+    auto forget_record = [&]() {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        g_ws.erase(ws_key);
+    };
 
+    forget_record();  // until this call has written every table it uses
+    if (!same_lat)
+        LBM_HIP_TRY(hipMemcpyAsync(d_lat, lat.data(), sizeof(LatDesc) * n, hipMemcpyHostToDevice, s));
+    if (!same_sizes) {
+        mt.reserve((size_t)nmt);
+        for (int l = 0; l < n; ++l) {
+            const int cx = (ps[l].nx + 255) / 256, cy = (ps[l].ny + kMomRows - 1) / kMomRows;
+            for (int j = 0; j < cy; ++j)
+                for (int i = 0; i < cx; ++i)
+                    mt.push_back(MomTile{l, (int16_t)i, (int16_t)j});
+        }
+        LBM_HIP_TRY(hipMemcpyAsync(d_mt, mt.data(), sizeof(MomTile) * mt.size(), hipMemcpyHostToDevice, s));
+    }
+    rec.lattice = ps[0].lattice;
+    rec.sizes = sizes;
+    rec.lat = lat;
     BatchTile *d_tiles1 = d_tiles, *d_tiles2 = d_tiles + Ly.n_tiles1;
     hipError_t up_err = hipSuccess;
-    // host copies of the uploaded lists stay alive until the stream is
-    // synchronised at the end of this call
-    std::vector<std::vector<BatchTile>> host_lists;
+    // the tile list of shape k in its region (one-step shapes in the first,
+    // two-step shapes in the second), uploaded unless the region holds it
     auto upload = [&](int k) -> std::pair<BatchTile *, int64_t> {
+        const int r = kShapes[k].steps == 1 ? 0 : 1;
+        BatchTile *d = r == 0 ? d_tiles1 : d_tiles2;
+        const int64_t count = count_tiles(ps, n, kShapes[k].tx, kShapes[k].ty);
+        if (rec.region[r] == k)
+            return {d, count};
         host_lists.push_back(build_tiles(ps, n, kShapes[k].tx, kShapes[k].ty));
         const std::vector<BatchTile> &v = host_lists.back();
-        BatchTile *d = kShapes[k].steps == 1 ? d_tiles1 : d_tiles2;
         up_err = hipMemcpyAsync(d, v.data(), sizeof(BatchTile) * v.size(), hipMemcpyHostToDevice, s);
+        rec.region[r] = up_err == hipSuccess ? k : -1;
         return {up_err == hipSuccess ? d : nullptr, (int64_t)v.size()};
     };
     if (shape < 0) {
@@ -1479,7 +1580,9 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         if (!one_list.first)
             return hip_fail(up_err, "tile list upload");
     }
-    const int64_t nmt = (int64_t)mt.size();
+    int max_nx = 0;
+    for (int l = 0; l < n; ++l)
+        max_nx = std::max(max_nx, ps[l].nx);
     hipLaunchKernelGGL(k_batch_set_ctrl, dim3(1), dim3(64), 0, s, d_ctrl, (int64_t)o->step0);
     LBM_HIP_TRY(hipGetLastError());
     // lattice groups that fit the Infinity Cache (one group when resident)
@@ -1529,8 +1632,10 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
             else
                 hipLaunchKernelGGL(k_batch_moments<7>, dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat, d_ctrl,
                                    (int)steps, d_part, d_colpart);
+            hipLaunchKernelGGL(k_batch_colmeans, dim3((unsigned)((max_nx + 255) / 256), (unsigned)n), dim3(256), 0, s,
+                               d_lat, d_colpart, d_colmean);
             hipLaunchKernelGGL(k_batch_final, dim3((unsigned)n), dim3(256), 0, s, d_lat, d_ctrl, (int)steps, d_part,
-                               d_colpart, d_colmean, d_results, (int)n_samples);
+                               d_colmean, d_results, (int)n_samples);
             if (o->drho && q9)
                 hipLaunchKernelGGL(k_batch_add_density<9>, dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat, d_ctrl,
                                    (int)steps);
@@ -1554,8 +1659,6 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         // addresses it reads (descriptors and tile lists are uploaded again by
         // every call before it runs), so it is kept and replayed by later
         // calls with the same key
-        int dev = 0;
-        (void)hipGetDevice(&dev);
         const GraphKey key{dev, (const void *)main_list.first, (const void *)one_list.first, (const void *)d_lat,
                            (const void *)d_ctrl, (const void *)d_mt, (const void *)d_part, (const void *)d_colpart,
                            (const void *)d_colmean, (const void *)d_results, ps[0].lattice, ps[0].model, flags,
@@ -1599,6 +1702,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
                 e = hipStreamSynchronize(s);
             if (e != hipSuccess)
                 return hip_fail(e, "lbm_sweep_batch graph");
+            save_record();
             return LBM_OK;
         }
         for (int64_t p = 0; p < n_periods && e == hipSuccess; ++p) {
@@ -1622,6 +1726,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     std::vector<double> res((size_t)n * n_samples * 8);
     LBM_HIP_TRY(hipMemcpyAsync(res.data(), d_results, sizeof(double) * res.size(), hipMemcpyDeviceToHost, s));
     LBM_HIP_TRY(hipStreamSynchronize(s));
+    save_record();
     bool bad = false;
     for (int l = 0; l < n; ++l)
         for (int64_t k = 0; k < n_samples; ++k) {

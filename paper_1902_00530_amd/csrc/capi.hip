@@ -89,6 +89,65 @@ StepArgs make_step_args(const lbm_params &p, int64_t pitch)
     return a;
 }
 
+__global__ void k_set_clock(StepClock *clk, int slot, int64_t t)
+{
+    if ((blockIdx.x | threadIdx.x) == 0)
+        clk->t[slot] = t;
+}
+
+hipError_t launch_set_clock(StepClock *clk, int slot, int64_t t, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(64), 0, s, clk, slot, t);
+    return hipGetLastError();
+}
+
+// A context's workspace: the step clock, the 8 reduced doubles of a sample,
+// then the reduction scratch.
+constexpr size_t kWsClock = 0, kWsResult = 256, kWsScratch = 512;
+
+static size_t ctx_workspace_bytes(const lbm_params &p)
+{
+    return kWsScratch + ((moments_scratch_doubles(p) * sizeof(double) + 255) & ~(size_t)255);
+}
+
+// Steps per captured graph of lbm_step (even, so a replay leaves the state in
+// the buffer it started from).
+constexpr int64_t kGraphSteps = 64;
+
+static hipError_t enqueue_steps(lbm_ctx *c, int from, int64_t n, hipStream_t s)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        const int slot = (from + (int)(k & 1)) & 1;
+        hipError_t e = c->p.lattice == LBM_D2Q9
+                           ? launch_step_q9(c->p, c->args, c->buf[slot], c->buf[slot ^ 1], c->clk, slot, s)
+                           : launch_step(c->p, c->args, c->buf[slot], c->buf[slot ^ 1], c->clk, slot, s);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+// kGraphSteps steps from buffer `from`, captured on a private stream (the
+// caller's may be the legacy null stream, which cannot be captured).
+static hipError_t capture_steps(lbm_ctx *c, int from)
+{
+    hipStream_t cap;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess)
+        return e;
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    hipError_t ce = e == hipSuccess ? enqueue_steps(c, from, kGraphSteps, cap) : e;
+    hipError_t ee = e == hipSuccess ? hipStreamEndCapture(cap, &g) : e;
+    (void)hipStreamDestroy(cap);
+    e = ce != hipSuccess ? ce : ee;
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&c->graph[from], g, nullptr, nullptr, 0);
+    if (g)
+        (void)hipGraphDestroy(g);
+    return e;
+}
+
 }  // namespace lbm
 
 using namespace lbm;
@@ -97,8 +156,15 @@ extern "C" {
 
 const char *lbm_last_error(void) { return g_error.c_str(); }
 
-int32_t lbm_create(const lbm_params *p, void *f_a, void *f_b, int64_t pitch, const lbm_init *init, void *stream,
-                   lbm_ctx **out)
+size_t lbm_workspace_bytes(const lbm_params *p, int64_t pitch)
+{
+    if (validate_params(p, pitch) != LBM_OK)
+        return 0;
+    return ctx_workspace_bytes(*p);
+}
+
+int32_t lbm_create(const lbm_params *p, void *f_a, void *f_b, int64_t pitch, const lbm_init *init, void *ws,
+                   size_t ws_bytes, void *stream, lbm_ctx **out)
 {
     if (!out)
         return fail(LBM_EINVAL, "null output pointer");
@@ -110,6 +176,12 @@ int32_t lbm_create(const lbm_params *p, void *f_a, void *f_b, int64_t pitch, con
         return fail(LBM_EINVAL, "null population buffer");
     if (f_a == f_b)
         return fail(LBM_EINVAL, "f_a and f_b must be distinct buffers");
+    if (!ws)
+        return fail(LBM_EINVAL, "null workspace");
+    if ((uintptr_t)ws % 256 != 0)
+        return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < ctx_workspace_bytes(*p))
+        return fail(LBM_EINVAL, "workspace smaller than lbm_workspace_bytes()");
     if (init && (init->mode < LBM_INIT_NONE || init->mode > LBM_INIT_GAUSS_DIR))
         return fail(LBM_EINVAL, "unknown init mode");
     if (init && init->mode != LBM_INIT_NONE &&
@@ -128,22 +200,19 @@ int32_t lbm_create(const lbm_params *p, void *f_a, void *f_b, int64_t pitch, con
     c->buf[1] = f_b;
     c->cur = 0;
     c->step = 0;
+    char *w = (char *)ws;
+    c->clk = (StepClock *)(w + kWsClock);
+    c->d_result = (double *)(w + kWsResult);
+    c->d_scratch = (double *)(w + kWsScratch);
+    c->graph[0] = c->graph[1] = nullptr;
     hipError_t e = hipGetDevice(&c->device);
-    const size_t nd = moments_scratch_doubles(*p);
     if (e == hipSuccess)
-        e = hipMalloc((void **)&c->d_scratch, nd * sizeof(double));
-    if (e == hipSuccess)
-        e = hipMalloc((void **)&c->d_result, 8 * sizeof(double));
-    if (e == hipSuccess)
-        e = hipHostMalloc((void **)&c->h_result, 8 * sizeof(double), hipHostMallocDefault);
+        e = launch_set_clock(c->clk, 0, 0, c->stream);
     if (e == hipSuccess && init && init->mode != LBM_INIT_NONE)
         e = p->lattice == LBM_D2Q9 ? launch_init_q9(*p, *init, c->args, f_a, c->stream)
                                    : launch_init(*p, *init, c->args, f_a, c->stream);
     if (e != hipSuccess) {
         rc = hip_fail(e, "lbm_create");
-        if (c->d_scratch) hipFree(c->d_scratch);
-        if (c->d_result) hipFree(c->d_result);
-        if (c->h_result) hipHostFree(c->h_result);
         delete c;
         return rc;
     }
@@ -157,15 +226,23 @@ int32_t lbm_step(lbm_ctx *c, int64_t n)
         return fail(LBM_ESTATE, "null context");
     if (n < 0)
         return fail(LBM_EINVAL, "negative step count");
-    for (int64_t k = 0; k < n; ++k) {
-        hipError_t e = c->p.lattice == LBM_D2Q9
-                           ? launch_step_q9(c->p, c->args, c->buf[c->cur], c->buf[c->cur ^ 1], c->step, c->stream)
-                           : launch_step(c->p, c->args, c->buf[c->cur], c->buf[c->cur ^ 1], c->step, c->stream);
-        if (e != hipSuccess)
-            return hip_fail(e, "lbm_step");
-        c->cur ^= 1;
-        c->step += 1;
+    // whole graphs of kGraphSteps steps, then single launches; a stream that
+    // the caller is capturing gets single launches only
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(c->stream, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        cs = hipStreamCaptureStatusNone;
     }
+    int64_t left = n;
+    if (cs == hipStreamCaptureStatusNone && n >= kGraphSteps) {
+        if (!c->graph[c->cur])
+            LBM_HIP_TRY(capture_steps(c, c->cur));
+        for (; left >= kGraphSteps; left -= kGraphSteps)
+            LBM_HIP_TRY(hipGraphLaunch(c->graph[c->cur], c->stream));
+    }
+    LBM_HIP_TRY(enqueue_steps(c, c->cur, left, c->stream));
+    c->cur ^= (int)(n & 1);
+    c->step += n;
     return LBM_OK;
 }
 
@@ -176,9 +253,10 @@ int32_t lbm_moments(lbm_ctx *c, float *rho, float *ux, float *uy, lbm_obs *obs)
     LBM_HIP_TRY(launch_moments(c->p, c->args, c->buf[c->cur], rho, ux, uy, c->d_scratch, c->d_result, c->stream));
     if (!obs)
         return LBM_OK;
-    LBM_HIP_TRY(hipMemcpyAsync(c->h_result, c->d_result, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    double r[8];
+    LBM_HIP_TRY(hipMemcpyAsync(r, c->d_result, sizeof r, hipMemcpyDeviceToHost, c->stream));
     LBM_HIP_TRY(hipStreamSynchronize(c->stream));
-    finish_obs(c->p, c->h_result, c->step, obs);
+    finish_obs(c->p, r, c->step, obs);
     if (obs->nonfinite)
         return fail(LBM_ENONFINITE, "non-finite populations in the state");
     return LBM_OK;
@@ -204,6 +282,7 @@ int32_t lbm_set_step(lbm_ctx *c, int64_t step)
         return fail(LBM_ESTATE, "null context");
     if (step < 0)
         return fail(LBM_EINVAL, "negative step index");
+    LBM_HIP_TRY(launch_set_clock(c->clk, c->cur, step, c->stream));
     c->step = step;
     return LBM_OK;
 }
@@ -226,9 +305,9 @@ int32_t lbm_destroy(lbm_ctx *c)
     if (!c)
         return fail(LBM_ESTATE, "null context");
     hipError_t e = hipStreamSynchronize(c->stream);
-    hipFree(c->d_scratch);
-    hipFree(c->d_result);
-    hipHostFree(c->h_result);
+    for (int k = 0; k < 2; ++k)
+        if (c->graph[k])
+            (void)hipGraphExecDestroy(c->graph[k]);
     delete c;
     if (e != hipSuccess)
         return hip_fail(e, "lbm_destroy");

@@ -30,6 +30,24 @@ struct StepArgs {
     int32_t noisy;      // sigma != 0
 };
 
+// Step index of the single-lattice step kernels, kept in device memory so a
+// captured graph of steps replays with unchanged arguments: a launch reads
+// the absolute step index (the noise counter) from slot `slot` and the first
+// lane of block (0, 0) stores the next index in the other slot, which only
+// the next launch reads.  The slot is the buffer parity of the launch's
+// source.
+struct StepClock {
+    int64_t t[2];
+};
+
+__device__ __forceinline__ uint64_t clock_tick(StepClock *clk, int slot)
+{
+    const int64_t t = clk->t[slot];
+    if ((blockIdx.x | blockIdx.y | threadIdx.x | threadIdx.y) == 0)
+        clk->t[slot ^ 1] = t + 1;
+    return (uint64_t)t;
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplies with the Philox multipliers, a word permutation and a

@@ -28,16 +28,20 @@ int32_t validate_params(const lbm_params *p, int64_t pitch);
 
 // Compile-time variant of the site body for these arguments (kUnitTau, kNoisy).
 int step_flags(const StepArgs &a);
-// One fused step src -> dst at absolute step t.
-hipError_t launch_step(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
+// One fused step src -> dst; the step index comes from clock slot `slot`
+// and the next index goes to the other slot.
+hipError_t launch_step(const lbm_params &p, const StepArgs &a, const void *src, void *dst, StepClock *clk, int slot,
                        hipStream_t s);
 // Initial state into dst.
 hipError_t launch_init(const lbm_params &p, const lbm_init &in, const StepArgs &a, void *dst, hipStream_t s);
 // f_i += drho / 7 in place.
 hipError_t launch_add_density(const lbm_params &p, const StepArgs &a, void *buf, double drho, hipStream_t s);
 // The same three on the square (D2Q9) lattice (f_i += drho / 9).
-hipError_t launch_step_q9(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
-                          hipStream_t s);
+hipError_t launch_step_q9(const lbm_params &p, const StepArgs &a, const void *src, void *dst, StepClock *clk,
+                          int slot, hipStream_t s);
+// Set clock slot `slot` to step index t (enqueued; a kernel, so it may be
+// captured into a graph).
+hipError_t launch_set_clock(StepClock *clk, int slot, int64_t t, hipStream_t s);
 hipError_t launch_init_q9(const lbm_params &p, const lbm_init &in, const StepArgs &a, void *dst, hipStream_t s);
 hipError_t launch_add_density_q9(const lbm_params &p, const StepArgs &a, void *buf, double drho, hipStream_t s);
 
@@ -61,7 +65,11 @@ struct lbm_ctx {
     int cur;
     int64_t pitch;
     int64_t step;
-    double *d_scratch;   // reductions
-    double *d_result;    // 8 doubles
-    double *h_result;    // pinned, 8 doubles
+    // in the caller's workspace
+    lbm::StepClock *clk;  // device step index (two slots)
+    double *d_result;     // 8 doubles
+    double *d_scratch;    // reductions
+    // graphs of kGraphSteps steps starting from buffer 0 and from buffer 1,
+    // captured on first use
+    hipGraphExec_t graph[2];
 };

@@ -139,6 +139,7 @@ __global__ __launch_bounds__(256) void k_column_means(const double *__restrict__
     if (x >= nx)
         return;
     double c = 0.0;
+#pragma unroll 16
     for (int r = 0; r < nrowblocks; ++r)
         c += colpart[(int64_t)r * nx + x];
     colmean[x] = c / (double)ny;

@@ -21,8 +21,10 @@ namespace lbm {
 template <int M, int S, int F>
 __global__ __launch_bounds__(256) void k_q9_step_local(const typename Store<S>::T *__restrict__ src,
                                                        typename Store<S>::T *__restrict__ dst, StepArgs a,
-                                                       uint32_t t_lo, uint32_t t_hi)
+                                                       StepClock *__restrict__ clk, int slot)
 {
+    const uint64_t tt = clock_tick(clk, slot);
+    const uint32_t t_lo = (uint32_t)(tt & 0xffffffffu), t_hi = (uint32_t)(tt >> 32);
     int txi, tyi;
     row_group_tile(txi, tyi);
     const int x = txi * blockDim.x + threadIdx.x;
@@ -39,8 +41,10 @@ __global__ __launch_bounds__(256) void k_q9_step_local(const typename Store<S>::
 template <int S, int F>
 __global__ __launch_bounds__(256) void k_q9_step_mips(const typename Store<S>::T *__restrict__ src,
                                                       typename Store<S>::T *__restrict__ dst, StepArgs a,
-                                                      uint32_t t_lo, uint32_t t_hi)
+                                                      StepClock *__restrict__ clk, int slot)
 {
+    const uint64_t tt = clock_tick(clk, slot);
+    const uint32_t t_lo = (uint32_t)(tt & 0xffffffffu), t_hi = (uint32_t)(tt >> 32);
     __shared__ float srho[(kQ9MipsRows + 2) * 66];
     int txi, tyi;
     row_group_tile(txi, tyi);
@@ -54,17 +58,16 @@ __global__ __launch_bounds__(256) void k_q9_step_mips(const typename Store<S>::T
 // Launchers
 // ---------------------------------------------------------------------------
 template <int S, int F>
-static hipError_t launch_q9_sf(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
+static hipError_t launch_q9_sf(const lbm_params &p, const StepArgs &a, const void *src, void *dst, StepClock *clk, int slot,
                                hipStream_t s)
 {
     using T = typename Store<S>::T;
-    const uint32_t tlo = (uint32_t)((uint64_t)t & 0xffffffffu), thi = (uint32_t)((uint64_t)t >> 32);
     const T *in = (const T *)src;
     T *out = (T *)dst;
     if (p.model == kMips) {
         const int ntx = (p.nx + 63) / 64, nty = (p.ny + kQ9MipsRows - 1) / kQ9MipsRows;
         dim3 grd(8u * (unsigned)ntx, (unsigned)((nty + 7) / 8));
-        hipLaunchKernelGGL((k_q9_step_mips<S, F>), grd, dim3(256), 0, s, in, out, a, tlo, thi);
+        hipLaunchKernelGGL((k_q9_step_mips<S, F>), grd, dim3(256), 0, s, in, out, a, clk, slot);
         return hipGetLastError();
     }
     const int bx = p.nx >= 256 ? 256 : ((p.nx + 63) / 64) * 64;
@@ -72,31 +75,31 @@ static hipError_t launch_q9_sf(const lbm_params &p, const StepArgs &a, const voi
     const int ntx = (p.nx + blk.x - 1) / blk.x, nty = (p.ny + blk.y - 1) / blk.y;
     dim3 grd(8u * (unsigned)ntx, (unsigned)((nty + 7) / 8));
     if (p.model == kCil)
-        hipLaunchKernelGGL((k_q9_step_local<kCil, S, F>), grd, blk, 0, s, in, out, a, tlo, thi);
+        hipLaunchKernelGGL((k_q9_step_local<kCil, S, F>), grd, blk, 0, s, in, out, a, clk, slot);
     else
-        hipLaunchKernelGGL((k_q9_step_local<kPassive, S, F>), grd, blk, 0, s, in, out, a, tlo, thi);
+        hipLaunchKernelGGL((k_q9_step_local<kPassive, S, F>), grd, blk, 0, s, in, out, a, clk, slot);
     return hipGetLastError();
 }
 
 template <int S>
-static hipError_t launch_q9_s(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
+static hipError_t launch_q9_s(const lbm_params &p, const StepArgs &a, const void *src, void *dst, StepClock *clk, int slot,
                               hipStream_t s)
 {
     switch (step_flags(a)) {
-    case 0: return launch_q9_sf<S, 0>(p, a, src, dst, t, s);
-    case kUnitTau: return launch_q9_sf<S, kUnitTau>(p, a, src, dst, t, s);
-    case kNoisy: return launch_q9_sf<S, kNoisy>(p, a, src, dst, t, s);
-    default: return launch_q9_sf<S, kUnitTau | kNoisy>(p, a, src, dst, t, s);
+    case 0: return launch_q9_sf<S, 0>(p, a, src, dst, clk, slot, s);
+    case kUnitTau: return launch_q9_sf<S, kUnitTau>(p, a, src, dst, clk, slot, s);
+    case kNoisy: return launch_q9_sf<S, kNoisy>(p, a, src, dst, clk, slot, s);
+    default: return launch_q9_sf<S, kUnitTau | kNoisy>(p, a, src, dst, clk, slot, s);
     }
 }
 
-hipError_t launch_step_q9(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
+hipError_t launch_step_q9(const lbm_params &p, const StepArgs &a, const void *src, void *dst, StepClock *clk, int slot,
                           hipStream_t s)
 {
     switch (p.storage) {
-    case kF32: return launch_q9_s<kF32>(p, a, src, dst, t, s);
-    case kBf16Dev: return launch_q9_s<kBf16Dev>(p, a, src, dst, t, s);
-    case kF16Dev: return launch_q9_s<kF16Dev>(p, a, src, dst, t, s);
+    case kF32: return launch_q9_s<kF32>(p, a, src, dst, clk, slot, s);
+    case kBf16Dev: return launch_q9_s<kBf16Dev>(p, a, src, dst, clk, slot, s);
+    case kF16Dev: return launch_q9_s<kF16Dev>(p, a, src, dst, clk, slot, s);
     }
     return hipErrorInvalidValue;
 }

@@ -24,8 +24,10 @@ namespace lbm {
 template <int M, int S, int F>
 __global__ __launch_bounds__(256) void k_step_local(const typename Store<S>::T *__restrict__ src,
                                                     typename Store<S>::T *__restrict__ dst, StepArgs a,
-                                                    uint32_t t_lo, uint32_t t_hi)
+                                                    StepClock *__restrict__ clk, int slot)
 {
+    const uint64_t tt = clock_tick(clk, slot);
+    const uint32_t t_lo = (uint32_t)(tt & 0xffffffffu), t_hi = (uint32_t)(tt >> 32);
     int txi, tyi;
     row_group_tile(txi, tyi);
     const int x = txi * blockDim.x + threadIdx.x;
@@ -56,8 +58,10 @@ __global__ __launch_bounds__(256) void k_step_local(const typename Store<S>::T *
 template <int M, int S, int F>
 __global__ __launch_bounds__(256) void k_step_local64(const typename Store<S>::T *__restrict__ src,
                                                       typename Store<S>::T *__restrict__ dst, StepArgs a,
-                                                      uint32_t t_lo, uint32_t t_hi)
+                                                      StepClock *__restrict__ clk, int slot)
 {
+    const uint64_t tt = clock_tick(clk, slot);
+    const uint32_t t_lo = (uint32_t)(tt & 0xffffffffu), t_hi = (uint32_t)(tt >> 32);
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     if (x >= a.nx || y >= a.ny)
@@ -105,8 +109,10 @@ __device__ __forceinline__ int wrapi(int v, int n)
 template <int S, int F>
 __global__ __launch_bounds__(256) void k_step_mips64(const typename Store<S>::T *__restrict__ src,
                                                    typename Store<S>::T *__restrict__ dst, StepArgs a,
-                                                   uint32_t t_lo, uint32_t t_hi)
+                                                   StepClock *__restrict__ clk, int slot)
 {
+    const uint64_t tt = clock_tick(clk, slot);
+    const uint32_t t_lo = (uint32_t)(tt & 0xffffffffu), t_hi = (uint32_t)(tt >> 32);
     constexpr int LX = kMipsTX + 2, LY = kMipsTY + 2;
     __shared__ float srho[LY][LX];
     const int tx = threadIdx.x, ty = threadIdx.y;
@@ -175,8 +181,10 @@ __global__ __launch_bounds__(256) void k_step_mips64(const typename Store<S>::T 
 template <int S, int F, int ROWS>
 __global__ __launch_bounds__(256) void k_step_mips(const typename Store<S>::T *__restrict__ src,
                                                    typename Store<S>::T *__restrict__ dst, StepArgs a,
-                                                   uint32_t t_lo, uint32_t t_hi)
+                                                   StepClock *__restrict__ clk, int slot)
 {
+    const uint64_t tt = clock_tick(clk, slot);
+    const uint32_t t_lo = (uint32_t)(tt & 0xffffffffu), t_hi = (uint32_t)(tt >> 32);
     using T = typename Store<S>::T;
     __shared__ float srho[mips_tile_lds(ROWS)];
     int txi, tyi;
@@ -203,11 +211,10 @@ static dim3 local_block(int nx)
 static bool fits32(const StepArgs &a) { return (uint64_t)a.plane * 7ull < (1ull << 30); }
 
 template <int S, int F>
-static hipError_t launch_step_sf(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
+static hipError_t launch_step_sf(const lbm_params &p, const StepArgs &a, const void *src, void *dst, StepClock *clk, int slot,
                                  hipStream_t s)
 {
     using T = typename Store<S>::T;
-    const uint32_t tlo = (uint32_t)((uint64_t)t & 0xffffffffu), thi = (uint32_t)((uint64_t)t >> 32);
     const T *in = (const T *)src;
     T *out = (T *)dst;
     if (p.model == kMips) {
@@ -216,14 +223,14 @@ static hipError_t launch_step_sf(const lbm_params &p, const StepArgs &a, const v
             if ((int64_t)ntx * nty < kMipsSmallTiles) {
                 const int nty4 = (p.ny + 3) / 4;
                 dim3 grd(8u * (unsigned)ntx, (unsigned)((nty4 + 7) / 8));
-                hipLaunchKernelGGL((k_step_mips<S, F, 4>), grd, dim3(256), 0, s, in, out, a, tlo, thi);
+                hipLaunchKernelGGL((k_step_mips<S, F, 4>), grd, dim3(256), 0, s, in, out, a, clk, slot);
             } else {
                 dim3 grd(8u * (unsigned)ntx, (unsigned)((nty + 7) / 8));
-                hipLaunchKernelGGL((k_step_mips<S, F, kMipsRows>), grd, dim3(256), 0, s, in, out, a, tlo, thi);
+                hipLaunchKernelGGL((k_step_mips<S, F, kMipsRows>), grd, dim3(256), 0, s, in, out, a, clk, slot);
             }
         } else {
             dim3 blk(kMipsTX, kMipsTY), grd((p.nx + kMipsTX - 1) / kMipsTX, (p.ny + kMipsTY - 1) / kMipsTY);
-            hipLaunchKernelGGL((k_step_mips64<S, F>), grd, blk, 0, s, in, out, a, tlo, thi);
+            hipLaunchKernelGGL((k_step_mips64<S, F>), grd, blk, 0, s, in, out, a, clk, slot);
         }
         return hipGetLastError();
     }
@@ -232,15 +239,15 @@ static hipError_t launch_step_sf(const lbm_params &p, const StepArgs &a, const v
     if (fits32(a)) {
         dim3 grd(8u * (unsigned)ntx, (unsigned)((nty + 7) / 8));
         if (p.model == kCil)
-            hipLaunchKernelGGL((k_step_local<kCil, S, F>), grd, blk, 0, s, in, out, a, tlo, thi);
+            hipLaunchKernelGGL((k_step_local<kCil, S, F>), grd, blk, 0, s, in, out, a, clk, slot);
         else
-            hipLaunchKernelGGL((k_step_local<kPassive, S, F>), grd, blk, 0, s, in, out, a, tlo, thi);
+            hipLaunchKernelGGL((k_step_local<kPassive, S, F>), grd, blk, 0, s, in, out, a, clk, slot);
     } else {
         dim3 grd(ntx, nty);
         if (p.model == kCil)
-            hipLaunchKernelGGL((k_step_local64<kCil, S, F>), grd, blk, 0, s, in, out, a, tlo, thi);
+            hipLaunchKernelGGL((k_step_local64<kCil, S, F>), grd, blk, 0, s, in, out, a, clk, slot);
         else
-            hipLaunchKernelGGL((k_step_local64<kPassive, S, F>), grd, blk, 0, s, in, out, a, tlo, thi);
+            hipLaunchKernelGGL((k_step_local64<kPassive, S, F>), grd, blk, 0, s, in, out, a, clk, slot);
     }
     return hipGetLastError();
 }
@@ -248,24 +255,24 @@ static hipError_t launch_step_sf(const lbm_params &p, const StepArgs &a, const v
 int step_flags(const StepArgs &a) { return (a.omega == 1.0f ? kUnitTau : 0) | (a.noisy ? kNoisy : 0); }
 
 template <int S>
-static hipError_t launch_step_s(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
+static hipError_t launch_step_s(const lbm_params &p, const StepArgs &a, const void *src, void *dst, StepClock *clk, int slot,
                                 hipStream_t s)
 {
     switch (step_flags(a)) {
-    case 0: return launch_step_sf<S, 0>(p, a, src, dst, t, s);
-    case kUnitTau: return launch_step_sf<S, kUnitTau>(p, a, src, dst, t, s);
-    case kNoisy: return launch_step_sf<S, kNoisy>(p, a, src, dst, t, s);
-    default: return launch_step_sf<S, kUnitTau | kNoisy>(p, a, src, dst, t, s);
+    case 0: return launch_step_sf<S, 0>(p, a, src, dst, clk, slot, s);
+    case kUnitTau: return launch_step_sf<S, kUnitTau>(p, a, src, dst, clk, slot, s);
+    case kNoisy: return launch_step_sf<S, kNoisy>(p, a, src, dst, clk, slot, s);
+    default: return launch_step_sf<S, kUnitTau | kNoisy>(p, a, src, dst, clk, slot, s);
     }
 }
 
-hipError_t launch_step(const lbm_params &p, const StepArgs &a, const void *src, void *dst, int64_t t,
+hipError_t launch_step(const lbm_params &p, const StepArgs &a, const void *src, void *dst, StepClock *clk, int slot,
                        hipStream_t s)
 {
     switch (p.storage) {
-    case kF32: return launch_step_s<kF32>(p, a, src, dst, t, s);
-    case kBf16Dev: return launch_step_s<kBf16Dev>(p, a, src, dst, t, s);
-    case kF16Dev: return launch_step_s<kF16Dev>(p, a, src, dst, t, s);
+    case kF32: return launch_step_s<kF32>(p, a, src, dst, clk, slot, s);
+    case kBf16Dev: return launch_step_s<kBf16Dev>(p, a, src, dst, clk, slot, s);
+    case kF16Dev: return launch_step_s<kF16Dev>(p, a, src, dst, clk, slot, s);
     }
     return hipErrorInvalidValue;
 }

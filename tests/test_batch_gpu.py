@@ -425,3 +425,55 @@ def test_lattice_groups_with_samples_and_density_ramp(L):
         for o, s in zip(out[l], obs):
             for k in ("M", "phi", "drho"):
                 assert abs(o[k] - s[k]) <= 1e-12 * max(1.0, abs(s[k])), (l, k)
+
+
+def _raw_sweep(L, params, bufs, ws, steps, keep, tile_rows=16, sample_every=0):
+    import ctypes
+    n = len(params)
+    pa = (L.lbm_params * n)(*params)
+    bp = (ctypes.c_void_p * (2 * n))(*[t.data_ptr() for t in bufs])
+    ns = steps // sample_every if sample_every else 1
+    out = (L.lbm_obs * (n * ns))()
+    o = L.lbm_sweep_opts(steps, sample_every, 0, tile_rows, 1)
+    o.keep_tables = keep
+    L.lbm_sweep_batch(pa, n, o, bp, ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream, out)
+    return [out[k].as_dict() for k in range(n * ns)]
+
+
+def test_keep_tables_reuses_only_what_still_holds(L):
+    """keep_tables = 1 skips rebuilding and uploading the tables a workspace
+    already holds.  One workspace serves, in turn: a batch (tables written),
+    the same batch again (tables kept), the same sizes with other seeds and
+    buffers (descriptors differ: uploaded again), other sizes (everything
+    uploaded again) and a batch of a two-step shape after a one-step one (the
+    other tile list region).  Every call's states equal single-lattice runs
+    bit for bit."""
+    cfgs = small_batch()
+    states = init_states(L, cfgs)
+    ws = torch.empty(1 << 26, dtype=torch.uint8, device="cuda")
+    steps = 21
+
+    def make_bufs(states_):
+        return [t for f in states_ for t in (torch.empty_like(f), torch.empty_like(f))]
+
+    def run(cfgs_, states_, bufs, keep, tile_rows):
+        for l, f in enumerate(states_):  # same buffers (descriptors unchanged), fresh start
+            bufs[2 * l].copy_(f)
+            bufs[2 * l + 1].zero_()
+        _raw_sweep(L, [_gparams(L, c) for c in cfgs_], bufs, ws, steps, keep, tile_rows)
+        torch.cuda.synchronize()
+        finals, _ = single_runs(L, cfgs_, states_, steps)
+        for l in range(len(cfgs_)):
+            assert torch.equal(bufs[2 * l + (steps & 1)], finals[l]), (l, keep, tile_rows)
+
+    bufs = make_bufs(states)
+    run(cfgs, states, bufs, 0, 16)
+    run(cfgs, states, bufs, 1, 16)  # every table kept
+    reseeded = [dict(c, seed=c["seed"] + 99) for c in cfgs]
+    run(reseeded, states, bufs, 1, 16)  # descriptors uploaded, tile lists kept
+    run(cfgs, states, make_bufs(states), 1, 16)  # other buffers: descriptors uploaded
+    other_bufs = make_bufs(states[1:4])
+    run(cfgs[1:4], states[1:4], other_bufs, 1, 1)  # other sizes: every table uploaded
+    run(cfgs[1:4], states[1:4], other_bufs, 1, 16)
+    run(cfgs, states, bufs, 1, 1)
+    run(cfgs, states, bufs, 1, 16)

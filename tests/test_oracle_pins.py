@@ -607,3 +607,93 @@ def test_initialisation_statistics(orc):
     _, ux, uy = orc.fields(p, f2, streamed=False)
     ang = np.arctan2(uy, ux)
     assert abs(ang.std() - 0.05) < 0.005 and abs(ang.mean()) < 0.005
+
+
+# ---------------------------------------------------------------- coarse fields (surrogate's maps)
+
+def _neighbour(x, y, i, nx, ny):
+    """Site r + e_i of (x, y) on the offset-row lattice (the table of the
+    conventions: odd rows sit half a site to the right)."""
+    p = y % 2
+    dx, dy = [(0, 0), (1, 0), (p, 1), (p - 1, 1), (-1, 0), (p - 1, -1), (p, -1)][i]
+    return (x + dx) % nx, (y + dy) % ny
+
+
+def test_coarsen_is_the_block_mean_of_the_streamed_moments(orc):
+    """A stored state built so that its streamed populations are a planted
+    random pattern g (f_i(s) = g_i(s + e_i), by the geometric neighbour table,
+    not the oracle's streaming): coarsen must return, block by block, the means
+    of rho = sum_i g_i and j = sum_i g_i e_i over the c x c sites of that block
+    (row-major blocks [3][ny/c][nx/c], nx != ny so a transposed layout fails)."""
+    nx, ny, c = 24, 12, 4
+    p = orc.make_params(nx, ny, orc.CIL, A=0.1, B=0.3)
+    rng = np.random.default_rng(11)
+    g = rng.uniform(0.0, 1.0, size=(7, ny, nx))
+    # plant distinct block levels so a misplaced block cannot match by chance
+    for by in range(ny // c):
+        for bx in range(nx // c):
+            g[:, by * c:(by + 1) * c, bx * c:(bx + 1) * c] += 3.0 * by + 0.5 * bx
+    f = np.zeros_like(g)
+    for y in range(ny):
+        for x in range(nx):
+            for i in range(7):
+                sx, sy = _neighbour(x, y, i, nx, ny)
+                f[i, y, x] = g[i, sy, sx]
+    E = np.array([[0.0, 0.0]] + [[math.cos(k * math.pi / 3), math.sin(k * math.pi / 3)] for k in range(6)])
+    got = orc.coarsen(p, f, c)
+    assert got.shape == (3, ny // c, nx // c)
+    for by in range(ny // c):
+        for bx in range(nx // c):
+            blk = g[:, by * c:(by + 1) * c, bx * c:(bx + 1) * c]
+            rho = blk.sum(axis=0).mean()
+            jx = np.einsum("i,iyx->yx", E[:, 0], blk).mean()
+            jy = np.einsum("i,iyx->yx", E[:, 1], blk).mean()
+            assert abs(got[0, by, bx] - rho) < 1e-13 * rho
+            assert abs(got[1, by, bx] - jx) < 1e-13 * rho
+            assert abs(got[2, by, bx] - jy) < 1e-13 * rho
+
+
+def test_lift_gives_each_block_its_own_fields(orc):
+    """lift puts the steady state xi of block (by, bx) on exactly the c x c
+    sites of that block: the unstreamed fields of the lifted state return each
+    block's rho and u = j / rho (Sigma xi = rho, Sigma xi e = rho u), and a
+    block with rho <= 0 lifts to empty sites."""
+    nx, ny, c = 20, 8, 4
+    p = orc.make_params(nx, ny, orc.CIL, A=0.1, B=0.3)
+    rng = np.random.default_rng(12)
+    hb, wb = ny // c, nx // c
+    coarse = np.zeros((3, hb, wb))
+    coarse[0] = rng.uniform(0.5, 2.0, size=(hb, wb))
+    u = rng.uniform(-0.2, 0.2, size=(2, hb, wb))
+    coarse[1] = coarse[0] * u[0]
+    coarse[2] = coarse[0] * u[1]
+    coarse[0, 1, 3] = 0.0
+    coarse[:, 0, 2] = (-0.4, 0.1, -0.2)  # negative density: treated as 0
+    f = orc.lift(p, coarse, c)
+    rho, ux, uy = orc.fields(p, f, streamed=False)
+    for y in range(ny):
+        for x in range(nx):
+            by, bx = y // c, x // c
+            r = coarse[0, by, bx]
+            if r <= 0.0:
+                assert np.all(f[:, y, x] == 0.0) and rho[y, x] == 0.0
+                assert ux[y, x] == 0.0 and uy[y, x] == 0.0
+                continue
+            assert abs(rho[y, x] - r) < 1e-14 * r
+            assert abs(ux[y, x] - coarse[1, by, bx] / r) < 1e-14
+            assert abs(uy[y, x] - coarse[2, by, bx] / r) < 1e-14
+
+
+def test_parallel_build_equals_the_plain_build(orc):
+    """The OpenMP build (the CPU baseline's host-core timing) runs the rows of
+    a step on several threads; every row writes only its own sites, so the
+    state after a run equals the plain build's bit for bit (CIL and MIPS)."""
+    for model, kw, ini in ((orc.CIL, dict(tau=1.0, sigma=4 / 70, A=0.125, B=0.3), dict(rho_mean=0.74)),
+                           (orc.MIPS, dict(tau=2.0, sigma=8 / 70, C=6.25, rho_star=1.6, u_max=0.3),
+                            dict(rho_mean=1.0, u_mag=0.1, pop_noise=1e-3))):
+        p = orc.make_params(96, 34, model, seed=9, **kw)
+        f = orc.initialise(p, mode=1, **ini)
+        a = orc.run(p, f.copy(), 7)
+        b = f.copy()
+        assert orc.run_parallel(p, b, 7, 4) >= 1
+        assert np.array_equal(a, b)

@@ -336,9 +336,11 @@ def test_zero_density_sites(L, orc):
 
 
 def test_full_size_cil_1024(L, orc):
-    """The benchmark workload's lattice (1024 x 1024, CIL, FP32, launch
-    configuration of the benchmark): GPU init, one step and five steps
-    against the oracle on the whole lattice."""
+    """The benchmark workload's lattice (1024 x 1024, CIL, FP32) through
+    lbm_step's one-step kernel: GPU init, one step and five steps against the
+    oracle on the whole lattice.  (The benchmark's own launch configuration,
+    the batched two-step kernel on the five 1024 x 1024 lattices, is checked
+    against the oracle in test_batch_gpu.py.)"""
     cfg = SI.cil_1024(1.0)
     ini = cfg.pop("init")
     po = _oparams(orc, cfg)
@@ -363,3 +365,70 @@ def test_full_size_cil_1024(L, orc):
     # sites, summed over the steps.
     amp = _self_sensitivity(orc, po, g0, 5) / 1e-7
     assert rel_err(got, ref) < 2e-6 * amp
+
+
+@pytest.mark.parametrize("name", ["cil_ho", "mips"])
+def test_64bit_offset_kernels(L, orc, name):
+    """Lattices whose seven planes hold 2^30 elements or more take the
+    64-bit-offset kernels (k_step_local64, k_step_mips64 on 64 x 4 tiles with
+    their own ring loader).  A 96 x 6 lattice with a row pitch that pushes
+    7 ny pitch past 2^30 (4.3 GB per buffer) reaches that path: init, one
+    step and three steps against the oracle on the live columns, and the
+    observables of lbm_moments."""
+    cfg = dict(CFGS[name], nx=96, ny=6)
+    pitch = -(-(1 << 30) // (7 * 6) // 64) * 64
+    assert 7 * 6 * pitch >= 1 << 30
+    ini = INITS[name]
+    po = _oparams(orc, cfg)
+    lat = L.Lattice(_gparams(L, cfg), init=L.make_init(**{**dict(angle_std=0.0, u_mag=-1.0, pop_noise=0.0), **ini}),
+                    pitch=pitch)
+    torch.cuda.synchronize()
+    g0 = lat.state[:, :, : cfg["nx"]].double().cpu().numpy()
+    assert rel_err(g0, orc.initialise(po, **ini)) < 2e-7
+    lat.step(1)
+    got1 = lat.state[:, :, : cfg["nx"]].double().cpu().numpy()
+    lat.step(2)
+    got3 = lat.state[:, :, : cfg["nx"]].double().cpu().numpy()
+    obs = lat.observables()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    assert rel_err(got1, orc.run(po, g0.copy(), 1)) < 1e-6
+    ref3 = orc.run(po, g0.copy(), 3)
+    assert rel_err(got3, ref3) < 1e-5
+    oo = orc.observables(po, ref3)
+    assert abs(obs["M"] - oo["M"]) < 1e-6 * oo["M"]
+    assert abs(obs["phi"] - oo["phi"]) < 1e-5
+
+
+def test_step_graph_replay_is_bitwise_and_keeps_the_clock(L, orc):
+    """lbm_step replays captured graphs of 64 steps (one per starting
+    buffer) and launches the rest directly; every launch reads its noise
+    counter from the device step clock.  One step at a time, and 1 + 200
+    steps (three replays of the graph from the second buffer, eight direct
+    launches), give the same state bit for bit; lbm_set_step on the device
+    clock restarts the counter (a run from step 1000 against the oracle's)."""
+    cfg, ini = STABLE["cil_aligned"]
+    f0 = _init32(orc, cfg, ini)
+    a = L.Lattice(_gparams(L, cfg))
+    b = L.Lattice(_gparams(L, cfg))
+    for lat in (a, b):
+        lat.set_state(torch.from_numpy(f0.astype(np.float32)).cuda())
+    a.step(1)
+    a.step(200)
+    for _ in range(201):
+        b.step(1)
+    torch.cuda.synchronize()
+    assert a.step_index == b.step_index == 201
+    assert torch.equal(a.state, b.state)
+    a.close()
+    b.close()
+    c = L.Lattice(_gparams(L, cfg))
+    c.set_state(torch.from_numpy(f0.astype(np.float32)).cuda())
+    c.set_step(1000)
+    c.step(130)
+    torch.cuda.synchronize()
+    got = c.state[:, :, : cfg["nx"]].double().cpu().numpy()
+    c.close()
+    ref = orc.run(_oparams(orc, cfg), f0.copy(), 130, step0=1000)
+    assert rel_err(got, ref) < 1e-5
