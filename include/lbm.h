@@ -190,6 +190,22 @@ int32_t lbm_step(lbm_ctx *c, int64_t n);
  * NaN or infinite. */
 int32_t lbm_moments(lbm_ctx *c, float *rho, float *ux, float *uy, lbm_obs *obs);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the fields
+ * and observables of lbm_moments for a population buffer f ([Q][ny][pitch]
+ * of p's storage type, read only) without a context or workspace.  The
+ * reduction partials live in a static device array of the library, 12 MiB
+ * per GPU, held until the process ends; lattices whose partials need more
+ * (moments partials grow as nx * ny / 16 doubles: up to about 5000 x 5000
+ * sites) return LBM_EINVAL, and lbm_moments serves them.  step is copied into
+ * obs->step.  rho, ux, uy: caller-owned device arrays [ny][nx] or NULL; obs:
+ * host struct or NULL (with obs the call synchronises the stream and returns
+ * LBM_ENONFINITE after filling obs if a population is not finite).  Calls on
+ * one GPU share its array: calls that overlap on one GPU (two streams, two
+ * threads) race.  No device memory is allocated or freed. */
+int32_t lbm_observe(const lbm_params *p, const void *f, int64_t pitch, int64_t step, float *rho, float *ux,
+                    float *uy, void *stream, lbm_obs *obs);
+
 /* 0 if the state is in f_a, 1 if in f_b; negative on error. */
 int32_t lbm_current_buffer(const lbm_ctx *c);
 

@@ -93,6 +93,8 @@ _SIGS = {
                                     _vp, _P(_vp)]),
     "lbm_step": (ctypes.c_int32, [_vp, ctypes.c_int64]),
     "lbm_moments": (ctypes.c_int32, [_vp, _vp, _vp, _vp, _P(lbm_obs)]),
+    "lbm_observe": (ctypes.c_int32, [_P(lbm_params), _vp, ctypes.c_int64, ctypes.c_int64, _vp, _vp, _vp, _vp,
+                                     _P(lbm_obs)]),
     "lbm_current_buffer": (ctypes.c_int32, [_vp]),
     "lbm_get_step": (ctypes.c_int64, [_vp]),
     "lbm_set_step": (ctypes.c_int32, [_vp, ctypes.c_int64]),
@@ -165,6 +167,18 @@ def lbm_moments(ctx, rho=None, ux=None, uy=None, want_obs=True, check=True):
     rc = _lib.lbm_moments(ctx, rho, ux, uy, ctypes.byref(obs) if obs is not None else None)
     if check and rc not in (LBM_OK,):
         raise LbmError(rc, "lbm_moments")
+    return obs, rc
+
+
+def lbm_observe(params, f, pitch, step, rho=None, ux=None, uy=None, stream=None, want_obs=True, check=True):
+    """Fields and observables of a population buffer with no context or
+    workspace (the library's static scratch; for callers that cannot
+    allocate)."""
+    obs = lbm_obs() if want_obs else None
+    rc = _lib.lbm_observe(ctypes.byref(params), f, int(pitch), int(step), rho, ux, uy, stream,
+                          ctypes.byref(obs) if obs is not None else None)
+    if check and rc != LBM_OK:
+        raise LbmError(rc, "lbm_observe")
     return obs, rc
 
 
