@@ -244,6 +244,8 @@ const char *lbm_last_error(void);
  * latency. */
 #define LBM_TILE_RESIDENT 1024
 
+struct lbm_surrogate; /* lbm_cnn.h */
+
 typedef struct lbm_sweep_opts {
     int64_t n_steps;      /* steps to run (a multiple of sample_every) */
     int64_t sample_every; /* observables every sample_every steps (0: once, at the end) */
@@ -275,7 +277,31 @@ typedef struct lbm_sweep_opts {
                              identically are then not rebuilt or uploaded, so a repeated
                              sweep of one batch enqueues its first kernel without host
                              work.  Pass 0 on the first call after allocating ws */
+    /* Surrogate sweep (lbm_cnn.h; not part of the paper's method).  With
+     * surrogate != NULL the network advances the coarse fields (rho, jx, jy
+     * and the lattice's B as a constant channel) of every lattice by k steps
+     * per evaluation; every check_every evaluations the method judges each
+     * lattice still on the network from the same coarse state (lift to the
+     * steady state of each cell, k steps with the sweep's noise counters,
+     * coarsen) and a lattice whose relative L2 field error exceeds tol
+     * continues from the judge's populations with the method (fallback).  At
+     * the end each lattice still on the network is lifted from its coarse
+     * fields into bufs[2l + (n_steps & 1)] and sampled like the others.
+     * Needs n_steps a multiple of k, sample_every 0 or n_steps, no drho,
+     * D2Q7 CIL or passive lattices of (w c) x (h c) sites (the surrogate's
+     * coarse grid), n <= max_batch, the surrogate's stream, and ws of
+     * lbm_sweep_workspace_bytes(ps, n, 1). */
+    int32_t check_every;  /* surrogate: evaluations between checks (>= 1) */
+    struct lbm_surrogate *surrogate; /* NULL: the method alone */
+    int32_t k;            /* surrogate: steps per network evaluation; must equal its k */
     int32_t reserved;     /* 0 */
+    double tol;           /* surrogate: fallback bound on the relative L2 error of (rho, j) */
+    float *coarse_out;    /* surrogate, optional: device [n][cin][h][w], final coarse fields */
+    int32_t *fallen_out;  /* surrogate, optional: host [n], 1 where the lattice fell back */
+    double *check_errors_out; /* surrogate, optional: host [max_checks][n], each check's
+                                 errors (NaN for lattices fallen before it) */
+    int64_t max_checks;   /* rows of check_errors_out */
+    int64_t *n_checks_out; /* surrogate, optional: host, checks made */
 } lbm_sweep_opts;
 
 /* Workspace bytes lbm_sweep_batch needs for these n lattices and n_samples
@@ -307,15 +333,26 @@ int32_t lbm_sweep_groups(const lbm_params *ps, int32_t n);
  * ws: caller-owned device workspace of ws_bytes >=
  * lbm_sweep_workspace_bytes(ps, n, n_samples).  out: host array of
  * n * n_samples lbm_obs, n_samples = n_steps / sample_every (1 if
- * sample_every == 0), sample s of lattice l at out[l * n_samples + s].  The
+ * sample_every == 0), sample s of lattice l at out[l * n_samples + s]; or
+ * NULL: the call only enqueues the sweep (no synchronisation, unless it had
+ * to upload tables from host memory) and the samples stay in ws until
+ * lbm_sweep_samples reads them.  The
  * steps of lattice l use its own seed and the noise counters
  * step0 .. step0 + n_steps - 1, so a lattice gives the same result as
  * lbm_step on its own.  Afterwards lattice l's state is in
- * bufs[2l + (n_steps & 1)].  Synchronises the stream at the end.  Errors:
- * LBM_EINVAL for the conditions above, LBM_EUNSUPPORTED for other storages or
- * lattices, LBM_ENONFINITE if a sample saw a non-finite population. */
+ * bufs[2l + (n_steps & 1)].  With out != NULL, synchronises the stream at
+ * the end.  Errors: LBM_EINVAL for the conditions above, LBM_EUNSUPPORTED for
+ * other storages or lattices, LBM_ENONFINITE if a sample saw a non-finite
+ * population. */
 int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o, void *const *bufs, void *ws,
                         size_t ws_bytes, void *stream, lbm_obs *out);
+
+/* The n * n_samples samples a sweep with out == NULL left in ws (same ps, n
+ * and n_samples as that call), into out as lbm_sweep_batch would have
+ * written them.  Synchronises the stream first.  LBM_ENONFINITE if a sample
+ * saw a non-finite population. */
+int32_t lbm_sweep_samples(const lbm_params *ps, int32_t n, int64_t n_samples, const void *ws, void *stream,
+                          lbm_obs *out);
 
 #ifdef __cplusplus
 }

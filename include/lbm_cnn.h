@@ -106,6 +106,78 @@ int32_t lbm_coarsen_many(const lbm_params *p, int32_t n, const float *const *buf
 int32_t lbm_lift_many(const lbm_params *p, int32_t n, const float *coarse, int64_t in_stride, int32_t c,
                       float *const *bufs, void *stream);
 
+/* ------------------------------------------------------------------------
+ * The surrogate as one object: a host handle over a caller-owned parameter
+ * block (float32 master weights and biases, Adam moments, bfloat16 weight
+ * copies, the field normalisation) and a caller-owned workspace
+ * (activations, gradients, a sweep's coarse fields).  Fields are
+ * [n][cin][h][w] float32: rho, jx, jy, then (cin = 4) a constant channel
+ * (the lattice's activity B in a sweep).  The network sees (x - mean) / std
+ * per channel and its three outputs are mapped back by std and mean.  Work
+ * is enqueued on the handle's stream; lbm_surrogate_create (with init) and
+ * lbm_surrogate_destroy synchronise it.
+ * ---------------------------------------------------------------------- */
+typedef struct lbm_surrogate lbm_surrogate;
+
+typedef struct lbm_surrogate_desc {
+    int32_t cin;       /* input channels, 3 or 4 */
+    int32_t h, w;      /* coarse grid (h * w <= 2^20) */
+    int32_t coarse;    /* lattice sites per coarse cell side (1 or even) */
+    int32_t k;         /* lattice Boltzmann steps one evaluation advances */
+    int32_t max_batch; /* most samples per call (and lattices per sweep), <= 65535 */
+} lbm_surrogate_desc;
+
+/* Bytes of the parameter block / workspace (0 for an invalid description). */
+size_t lbm_surrogate_param_bytes(const lbm_surrogate_desc *d);
+size_t lbm_surrogate_workspace_bytes(const lbm_surrogate_desc *d);
+
+/* A handle over params (256-byte aligned, lbm_surrogate_param_bytes) and ws
+ * (256-byte aligned, ws_bytes >= lbm_surrogate_workspace_bytes), both
+ * caller-owned and kept alive until lbm_surrogate_destroy.  init != 0 fills
+ * params: He-uniform weights from seed (a tenth on the output layer), zero
+ * biases and moments, identity normalisation; init == 0 takes params as they
+ * are (e.g. a trained block).  The Adam step count starts at 0. */
+int32_t lbm_surrogate_create(const lbm_surrogate_desc *d, void *params, int32_t init, uint64_t seed, void *ws,
+                             size_t ws_bytes, void *stream, lbm_surrogate **out);
+
+/* Normalisation from the per-channel mean and standard deviation of n
+ * samples x (float64 statistics). */
+int32_t lbm_surrogate_fit_normalisation(lbm_surrogate *s, const float *x, int32_t n);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, step size lr) on the mean
+ * squared error of the normalised output against the normalised target
+ * fields, over the samples idx[0..n) of x and target (device int32 array;
+ * NULL: the first n).  x and target are [N][cin][h][w] (only the first three
+ * target channels are used), n <= max_batch.  loss: NULL or one device float
+ * receiving this step's loss. */
+int32_t lbm_surrogate_train_step(lbm_surrogate *s, const float *x, const float *target, const int32_t *idx,
+                                 int32_t n, float lr, float *loss);
+
+/* y [n][cin][h][w] = the network's fields k steps after x (channels 0..2)
+ * and x's constant channels; n <= max_batch, y != x. */
+int32_t lbm_surrogate_predict(lbm_surrogate *s, const float *x, int32_t n, float *y);
+
+/* Where the tensors of a surrogate's parameter block are (device pointers
+ * into it), for checkpoints and inspection: the float32 masters theta (w1,
+ * b1, w2, b2, w3, b3, shapes as in lbm_cnn_params), their Adam moments, the
+ * bfloat16 weight copies the network computes with (a caller that writes
+ * theta must write these too), and norm = [4][cin]: input scale, input
+ * shift, output scale, output shift. */
+typedef struct lbm_surrogate_view {
+    float *theta[6];
+    float *m[6];
+    float *v[6];
+    int64_t count[6];
+    uint16_t *w_bf16[3];
+    float *norm;
+    int64_t adam_steps; /* Adam steps taken by this handle */
+} lbm_surrogate_view;
+
+int32_t lbm_surrogate_view_of(const lbm_surrogate *s, lbm_surrogate_view *v);
+
+/* Release the handle (after its stream's work). */
+int32_t lbm_surrogate_destroy(lbm_surrogate *s);
+
 #ifdef __cplusplus
 }
 #endif

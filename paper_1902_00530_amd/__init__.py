@@ -51,7 +51,21 @@ class lbm_sweep_opts(ctypes.Structure):
     _fields_ = [("n_steps", ctypes.c_int64), ("sample_every", ctypes.c_int64), ("step0", ctypes.c_int64),
                 ("tile_rows", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("drho", ctypes.POINTER(ctypes.c_double)), ("keep_tables", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("surrogate", ctypes.c_void_p), ("k", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tol", ctypes.c_double), ("coarse_out", ctypes.c_void_p),
+                ("fallen_out", ctypes.POINTER(ctypes.c_int32)), ("check_errors_out", ctypes.POINTER(ctypes.c_double)),
+                ("max_checks", ctypes.c_int64), ("n_checks_out", ctypes.POINTER(ctypes.c_int64))]
+
+
+class lbm_surrogate_view(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_void_p * 6), ("m", ctypes.c_void_p * 6), ("v", ctypes.c_void_p * 6),
+                ("count", ctypes.c_int64 * 6), ("w_bf16", ctypes.c_void_p * 3), ("norm", ctypes.c_void_p),
+                ("adam_steps", ctypes.c_int64)]
+
+
+class lbm_surrogate_desc(ctypes.Structure):
+    _fields_ = [("cin", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32), ("coarse", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
 
 
 class lbm_cnn_shape(ctypes.Structure):
@@ -106,6 +120,8 @@ _SIGS = {
     "lbm_sweep_groups": (ctypes.c_int32, [_P(lbm_params), ctypes.c_int32]),
     "lbm_sweep_batch": (ctypes.c_int32, [_P(lbm_params), ctypes.c_int32, _P(lbm_sweep_opts), _P(_vp), _vp,
                                          ctypes.c_size_t, _vp, _P(lbm_obs)]),
+    "lbm_sweep_samples": (ctypes.c_int32, [_P(lbm_params), ctypes.c_int32, ctypes.c_int64, _vp, _vp,
+                                           _P(lbm_obs)]),
     "lbm_cnn_workspace_bytes": (ctypes.c_size_t, [_P(lbm_cnn_shape)]),
     "lbm_cnn_forward": (ctypes.c_int32, [_P(lbm_cnn_shape), _P(lbm_cnn_params), _vp, _vp, _vp, _vp, _vp,
                                          ctypes.c_size_t, _vp]),
@@ -126,6 +142,15 @@ _SIGS = {
                                           _vp]),
     "lbm_lift_many": (ctypes.c_int32, [_P(lbm_params), ctypes.c_int32, _vp, ctypes.c_int64, ctypes.c_int32, _vp,
                                        _vp]),
+    "lbm_surrogate_param_bytes": (ctypes.c_size_t, [_P(lbm_surrogate_desc)]),
+    "lbm_surrogate_workspace_bytes": (ctypes.c_size_t, [_P(lbm_surrogate_desc)]),
+    "lbm_surrogate_create": (ctypes.c_int32, [_P(lbm_surrogate_desc), _vp, ctypes.c_int32, ctypes.c_uint64, _vp,
+                                              ctypes.c_size_t, _vp, _P(_vp)]),
+    "lbm_surrogate_fit_normalisation": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32]),
+    "lbm_surrogate_train_step": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, _vp]),
+    "lbm_surrogate_predict": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp]),
+    "lbm_surrogate_destroy": (ctypes.c_int32, [_vp]),
+    "lbm_surrogate_view_of": (ctypes.c_int32, [_vp, _P(lbm_surrogate_view)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -223,6 +248,11 @@ def lbm_sweep_batch(params_array, n, opts, bufs, ws, ws_bytes, stream, out):
                                        out), "lbm_sweep_batch")
 
 
+def lbm_sweep_samples(params_array, n, n_samples, ws, stream, out):
+    return _check(_lib.lbm_sweep_samples(params_array, int(n), int(n_samples), ws, stream, out),
+                  "lbm_sweep_samples")
+
+
 def lbm_cnn_workspace_bytes(shape):
     return _lib.lbm_cnn_workspace_bytes(ctypes.byref(shape))
 
@@ -277,6 +307,44 @@ def lbm_lift_many(params, n, coarse, in_stride, c, bufs, stream):
                   "lbm_lift_many")
 
 
+def lbm_surrogate_param_bytes(desc):
+    return _lib.lbm_surrogate_param_bytes(ctypes.byref(desc))
+
+
+def lbm_surrogate_workspace_bytes(desc):
+    return _lib.lbm_surrogate_workspace_bytes(ctypes.byref(desc))
+
+
+def lbm_surrogate_create(desc, params, init, seed, ws, ws_bytes, stream):
+    h = _vp()
+    _check(_lib.lbm_surrogate_create(ctypes.byref(desc), params, int(init), int(seed) & 0xFFFFFFFFFFFFFFFF, ws,
+                                     int(ws_bytes), stream, ctypes.byref(h)), "lbm_surrogate_create")
+    return h
+
+
+def lbm_surrogate_fit_normalisation(h, x, n):
+    return _check(_lib.lbm_surrogate_fit_normalisation(h, x, int(n)), "lbm_surrogate_fit_normalisation")
+
+
+def lbm_surrogate_train_step(h, x, target, idx, n, lr, loss):
+    return _check(_lib.lbm_surrogate_train_step(h, x, target, idx, int(n), float(lr), loss),
+                  "lbm_surrogate_train_step")
+
+
+def lbm_surrogate_predict(h, x, n, y):
+    return _check(_lib.lbm_surrogate_predict(h, x, int(n), y), "lbm_surrogate_predict")
+
+
+def lbm_surrogate_view_of(h):
+    v = lbm_surrogate_view()
+    _check(_lib.lbm_surrogate_view_of(h, ctypes.byref(v)), "lbm_surrogate_view_of")
+    return v
+
+
+def lbm_surrogate_destroy(h):
+    return _check(_lib.lbm_surrogate_destroy(h), "lbm_surrogate_destroy")
+
+
 class Batch:
     """n lattices with torch-owned buffers, advanced by lbm_sweep_batch."""
 
@@ -303,14 +371,16 @@ class Batch:
         self.buffers[2 * l].copy_(f)
         self.current[l] = 0
 
-    def run(self, n_steps, sample_every=0, tile_rows=0, use_graph=1, stream=None, subset=None, drho=None):
+    def run(self, n_steps, sample_every=0, tile_rows=0, use_graph=1, stream=None, subset=None, drho=None,
+            fetch=True):
         """Advance every lattice (or only the lattices listed in subset) by
         n_steps; returns a list (per advanced lattice) of sample dicts.
         use_graph=2 only prepares the launch plan for such a call (tuning,
         captured graphs) and advances nothing.  drho (a number, or one per
         advanced lattice): right after each sample every population gains
         drho / Q (Q = 7 or 9 populations), the density ramp of the paper's
-        protocol."""
+        protocol.  fetch=False only enqueues the sweep (no synchronisation)
+        and returns None; samples() reads its samples afterwards."""
         import torch
         idx = list(range(self.n)) if subset is None else [int(i) for i in subset]
         m = len(idx)
@@ -331,7 +401,7 @@ class Batch:
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.buffers[0].device)
             self._ws_written = False
-        out = (lbm_obs * (m * n_samples))()
+        out = (lbm_obs * (m * n_samples))() if fetch else None
         opts = lbm_sweep_opts(int(n_steps), int(sample_every), int(self.step_index), int(tile_rows), int(use_graph))
         # the workspace is this object's alone: after the first call with it,
         # the library may keep the tables it wrote there
@@ -353,6 +423,60 @@ class Batch:
             self.step_index += n_steps
         for l in idx:
             self.current[l] = n_steps & 1
+        self._last = (params, m, n_samples)
+        if not fetch:
+            return None
+        return [[out[q * n_samples + s].as_dict() for s in range(n_samples)] for q in range(m)]
+
+    def surrogate_sweep(self, sur, n_steps, check_every, tol, tile_rows=0, coarse_out=None):
+        """Advance every lattice by n_steps with the surrogate sur (network
+        evaluations of k steps, checks by the method every check_every
+        evaluations, fallback where the check error exceeds tol), in one
+        lbm_sweep_batch call on the surrogate's stream.  Returns (samples of
+        the final states, fallen flags, per-check error arrays with NaN for
+        lattices fallen before the check)."""
+        import torch
+        for l in range(self.n):
+            if self.current[l]:
+                self.buffers[2 * l].copy_(self.buffers[2 * l + 1])
+                self.current[l] = 0
+        n = self.n
+        need = lbm_sweep_workspace_bytes(self.params, n, 1)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.buffers[0].device)
+            self._ws_written = False
+        out = (lbm_obs * n)()
+        opts = lbm_sweep_opts(int(n_steps), 0, int(self.step_index), int(tile_rows), 1)
+        opts.surrogate = sur.handle
+        opts.k = sur.k
+        opts.check_every = int(check_every)
+        opts.tol = float(tol)
+        max_checks = n_steps // sur.k // max(1, int(check_every)) + 1
+        fallen = (ctypes.c_int32 * n)()
+        errs = (ctypes.c_double * (n * max_checks))()
+        nchk = ctypes.c_int64(0)
+        opts.fallen_out = fallen
+        opts.check_errors_out = errs
+        opts.max_checks = max_checks
+        opts.n_checks_out = ctypes.pointer(nchk)
+        opts.coarse_out = coarse_out.data_ptr() if coarse_out is not None else None
+        try:
+            lbm_sweep_batch(self.params, n, opts, self.bufs, self._ws.data_ptr(), need, sur.stream.cuda_stream, out)
+        finally:
+            self._ws_written = True
+        self.step_index += n_steps
+        for l in range(n):
+            self.current[l] = n_steps & 1
+        e = np.ctypeslib.as_array(errs)[: nchk.value * n].reshape(nchk.value, n).copy()
+        return [out[l].as_dict() for l in range(n)], np.ctypeslib.as_array(fallen).astype(bool), list(e)
+
+    def samples(self, stream=None):
+        """Samples of the last run(..., fetch=False) (synchronises the stream)."""
+        import torch
+        params, m, n_samples = self._last
+        out = (lbm_obs * (m * n_samples))()
+        st = stream if stream is not None else torch.cuda.current_stream()
+        lbm_sweep_samples(params, m, n_samples, self._ws.data_ptr(), st.cuda_stream, out)
         return [[out[q * n_samples + s].as_dict() for s in range(n_samples)] for q in range(m)]
 
 

@@ -1274,6 +1274,27 @@ static bool same_desc(const LatDesc &x, const LatDesc &y)
 }
 #undef LBM_SAME
 
+// Copy a sweep's samples (8 doubles each, lattice-major) to the host after
+// the stream's work and turn them into lbm_obs.
+static int32_t read_samples(const lbm_params *ps, int n, int64_t n_samples, const double *d_results, hipStream_t s,
+                            lbm_obs *out)
+{
+    std::vector<double> res((size_t)n * n_samples * 8);
+    LBM_HIP_TRY(hipMemcpyAsync(res.data(), d_results, sizeof(double) * res.size(), hipMemcpyDeviceToHost, s));
+    LBM_HIP_TRY(hipStreamSynchronize(s));
+    bool bad = false;
+    for (int l = 0; l < n; ++l)
+        for (int64_t k = 0; k < n_samples; ++k) {
+            const double *r = &res[((size_t)l * n_samples + k) * 8];
+            lbm_obs &ob = out[(size_t)l * n_samples + k];
+            finish_obs(ps[l], r, (int64_t)r[7], &ob);
+            bad = bad || ob.nonfinite;
+        }
+    if (bad)
+        return fail(LBM_ENONFINITE, "non-finite populations in a batch sample");
+    return LBM_OK;
+}
+
 }  // namespace lbm
 
 using namespace lbm;
@@ -1311,7 +1332,7 @@ size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samp
 int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o, void *const *bufs, void *ws,
                         size_t ws_bytes, void *stream, lbm_obs *out)
 {
-    if (!ps || n <= 0 || !o || !bufs || !ws || !out)
+    if (!ps || n <= 0 || !o || !bufs || !ws)
         return fail(LBM_EINVAL, "null argument or empty batch");
     if (o->n_steps < 0 || o->sample_every < 0 || o->step0 < 0)
         return fail(LBM_EINVAL, "negative step counts");
@@ -1348,6 +1369,8 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     const Layout Ly = layout(ps, n, n_samples);
     if (ws_bytes < Ly.total)
         return fail(LBM_EINVAL, "workspace smaller than lbm_sweep_workspace_bytes()");
+    if (o->surrogate)
+        return surrogate_sweep(ps, n, o, bufs, ws, ws_bytes, (hipStream_t)stream, out);
     // tile shape: caller's choice (tile_rows 1, 2, 4: 256x1, 128x2, 64x4
     // sites, one step per launch; 8, 16: 64x8, 64x16 sites, two steps per
     // launch; MIPS always 64x16, one step per launch), else the tuned one for
@@ -1457,6 +1480,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     };
 
     forget_record();  // until this call has written every table it uses
+    const bool uploaded_desc = !same_lat || !same_sizes;
     if (!same_lat)
         LBM_HIP_TRY(hipMemcpyAsync(d_lat, lat.data(), sizeof(LatDesc) * n, hipMemcpyHostToDevice, s));
     if (!same_sizes) {
@@ -1723,21 +1747,34 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         }
     }
 
-    std::vector<double> res((size_t)n * n_samples * 8);
-    LBM_HIP_TRY(hipMemcpyAsync(res.data(), d_results, sizeof(double) * res.size(), hipMemcpyDeviceToHost, s));
-    LBM_HIP_TRY(hipStreamSynchronize(s));
-    save_record();
-    bool bad = false;
-    for (int l = 0; l < n; ++l)
-        for (int64_t k = 0; k < n_samples; ++k) {
-            const double *r = &res[((size_t)l * n_samples + k) * 8];
-            lbm_obs &ob = out[(size_t)l * n_samples + k];
-            finish_obs(ps[l], r, (int64_t)r[7], &ob);
-            bad = bad || ob.nonfinite;
-        }
-    if (bad)
-        return fail(LBM_ENONFINITE, "non-finite populations in a batch sample");
-    return LBM_OK;
+    const bool uploaded = uploaded_desc || !host_lists.empty();
+    if (!out) {
+        // enqueue only: the samples stay in the workspace (lbm_sweep_samples);
+        // a call that uploaded tables from host vectors waits for those copies
+        if (uploaded)
+            LBM_HIP_TRY(hipStreamSynchronize(s));
+        save_record();
+        return LBM_OK;
+    }
+    int32_t rc = read_samples(ps, n, n_samples, d_results, s, out);
+    if (rc != LBM_EHIP)
+        save_record();
+    return rc;
+}
+
+int32_t lbm_sweep_samples(const lbm_params *ps, int32_t n, int64_t n_samples, const void *ws, void *stream,
+                          lbm_obs *out)
+{
+    if (!ps || n <= 0 || n_samples <= 0 || !ws || !out)
+        return fail(LBM_EINVAL, "null argument, empty batch or no samples");
+    for (int l = 0; l < n; ++l) {
+        int32_t rc = validate_params(&ps[l], ps[l].nx);
+        if (rc)
+            return fail(rc, "lattice " + std::to_string(l) + ": " + lbm_last_error());
+    }
+    const Layout Ly = layout(ps, n, n_samples);
+    return read_samples(ps, n, n_samples, (const double *)((const char *)ws + Ly.results), (hipStream_t)stream,
+                        out);
 }
 
 }  // extern "C"

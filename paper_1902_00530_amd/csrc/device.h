@@ -35,17 +35,19 @@ struct StepArgs {
 // the absolute step index (the noise counter) from slot `slot` and the first
 // lane of block (0, 0) stores the next index in the other slot, which only
 // the next launch reads.  The slot is the buffer parity of the launch's
-// source.
+// source.  The store comes at the end of the kernel (site (0, 0), which
+// every lattice has, so that lane never leaves early), so the read is waited
+// on only where the noise needs it, after the population loads are issued.
 struct StepClock {
     int64_t t[2];
 };
 
-__device__ __forceinline__ uint64_t clock_tick(StepClock *clk, int slot)
+__device__ __forceinline__ uint64_t clock_read(const StepClock *clk, int slot) { return (uint64_t)clk->t[slot]; }
+
+__device__ __forceinline__ void clock_advance(StepClock *clk, int slot, uint64_t t)
 {
-    const int64_t t = clk->t[slot];
     if ((blockIdx.x | blockIdx.y | threadIdx.x | threadIdx.y) == 0)
-        clk->t[slot ^ 1] = t + 1;
-    return (uint64_t)t;
+        clk->t[slot ^ 1] = (int64_t)t + 1;
 }
 
 // ---------------------------------------------------------------------------

@@ -51,6 +51,10 @@ hipError_t launch_add_density_q9(const lbm_params &p, const StepArgs &a, void *b
 size_t moments_scratch_doubles(const lbm_params &p);
 hipError_t launch_moments(const lbm_params &p, const StepArgs &a, const void *src, float *rho, float *ux,
                           float *uy, double *scratch, double *result, hipStream_t s);
+// The surrogate form of lbm_sweep_batch (opts->surrogate set; arguments
+// validated as for a plain sweep).
+int32_t surrogate_sweep(const lbm_params *ps, int n, const lbm_sweep_opts *o, void *const *bufs, void *ws,
+                        size_t ws_bytes, hipStream_t st, lbm_obs *out);
 // Turn the 8 reduced doubles into an lbm_obs (host).
 void finish_obs(const lbm_params &p, const double *r, int64_t step, lbm_obs *o);
 

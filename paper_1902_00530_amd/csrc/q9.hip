@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void k_q9_step_local(const typename Store<S>::
                                                        typename Store<S>::T *__restrict__ dst, StepArgs a,
                                                        StepClock *__restrict__ clk, int slot)
 {
-    const uint64_t tt = clock_tick(clk, slot);
+    const uint64_t tt = clock_read(clk, slot);
     const uint32_t t_lo = (uint32_t)(tt & 0xffffffffu), t_hi = (uint32_t)(tt >> 32);
     int txi, tyi;
     row_group_tile(txi, tyi);
@@ -32,6 +32,7 @@ __global__ __launch_bounds__(256) void k_q9_step_local(const typename Store<S>::
     if (x >= a.nx || y >= a.ny)
         return;
     q9_site_step<M, S, F>(src, dst, a, x, y, t_lo, t_hi);
+    clock_advance(clk, slot, tt);
 }
 
 // ---------------------------------------------------------------------------
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(256) void k_q9_step_mips(const typename Store<S>::T
                                                       typename Store<S>::T *__restrict__ dst, StepArgs a,
                                                       StepClock *__restrict__ clk, int slot)
 {
-    const uint64_t tt = clock_tick(clk, slot);
+    const uint64_t tt = clock_read(clk, slot);
     const uint32_t t_lo = (uint32_t)(tt & 0xffffffffu), t_hi = (uint32_t)(tt >> 32);
     __shared__ float srho[(kQ9MipsRows + 2) * 66];
     int txi, tyi;
@@ -52,6 +53,7 @@ __global__ __launch_bounds__(256) void k_q9_step_mips(const typename Store<S>::T
     if (y0 >= a.ny)  // padding tile rows of the last group: the whole block
         return;
     q9_mips_tile_step<S, F>(src, dst, a, x0, y0, t_lo, t_hi, srho);
+    clock_advance(clk, slot, tt);
 }
 
 // ---------------------------------------------------------------------------

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void k_step_local(const typename Store<S>::T *
                                                     typename Store<S>::T *__restrict__ dst, StepArgs a,
                                                     StepClock *__restrict__ clk, int slot)
 {
-    const uint64_t tt = clock_tick(clk, slot);
+    const uint64_t tt = clock_read(clk, slot);
     const uint32_t t_lo = (uint32_t)(tt & 0xffffffffu), t_hi = (uint32_t)(tt >> 32);
     int txi, tyi;
     row_group_tile(txi, tyi);
@@ -51,6 +51,7 @@ __global__ __launch_bounds__(256) void k_step_local(const typename Store<S>::T *
 #pragma unroll
     for (int i = 0; i < 7; ++i)
         BufIO<T>::store(rd, own, i * plane, Store<S>::narrow(f[i], i == 0 ? a.wr0 : a.wr1));
+    clock_advance(clk, slot, tt);
 }
 
 // Same body with 64-bit offsets, for buffers of 2^30 elements per plane set
@@ -60,7 +61,7 @@ __global__ __launch_bounds__(256) void k_step_local64(const typename Store<S>::T
                                                       typename Store<S>::T *__restrict__ dst, StepArgs a,
                                                       StepClock *__restrict__ clk, int slot)
 {
-    const uint64_t tt = clock_tick(clk, slot);
+    const uint64_t tt = clock_read(clk, slot);
     const uint32_t t_lo = (uint32_t)(tt & 0xffffffffu), t_hi = (uint32_t)(tt >> 32);
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -79,6 +80,7 @@ __global__ __launch_bounds__(256) void k_step_local64(const typename Store<S>::T
 #pragma unroll
     for (int i = 0; i < 7; ++i)
         Store<S>::store(dst, i * a.plane + own, f[i], i == 0 ? a.wr0 : a.wr1);
+    clock_advance(clk, slot, tt);
 }
 
 // ---------------------------------------------------------------------------
@@ -111,7 +113,7 @@ __global__ __launch_bounds__(256) void k_step_mips64(const typename Store<S>::T 
                                                    typename Store<S>::T *__restrict__ dst, StepArgs a,
                                                    StepClock *__restrict__ clk, int slot)
 {
-    const uint64_t tt = clock_tick(clk, slot);
+    const uint64_t tt = clock_read(clk, slot);
     const uint32_t t_lo = (uint32_t)(tt & 0xffffffffu), t_hi = (uint32_t)(tt >> 32);
     constexpr int LX = kMipsTX + 2, LY = kMipsTY + 2;
     __shared__ float srho[LY][LX];
@@ -169,6 +171,7 @@ __global__ __launch_bounds__(256) void k_step_mips64(const typename Store<S>::T 
 #pragma unroll
     for (int i = 0; i < 7; ++i)
         Store<S>::store(dst, i * a.plane + own, f[i], i == 0 ? a.wr0 : a.wr1);
+    clock_advance(clk, slot, tt);
 }
 
 // ---------------------------------------------------------------------------
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(256) void k_step_mips(const typename Store<S>::T *_
                                                    typename Store<S>::T *__restrict__ dst, StepArgs a,
                                                    StepClock *__restrict__ clk, int slot)
 {
-    const uint64_t tt = clock_tick(clk, slot);
+    const uint64_t tt = clock_read(clk, slot);
     const uint32_t t_lo = (uint32_t)(tt & 0xffffffffu), t_hi = (uint32_t)(tt >> 32);
     using T = typename Store<S>::T;
     __shared__ float srho[mips_tile_lds(ROWS)];
@@ -194,6 +197,7 @@ __global__ __launch_bounds__(256) void k_step_mips(const typename Store<S>::T *_
         return;
     const uint32_t bytes = 7u * (uint32_t)a.plane * (uint32_t)sizeof(T);  // < 2^32: 7 planes < 2^30 elements
     mips_tile_step<S, F, ROWS>(buffer_rsrc(src, bytes), buffer_rsrc(dst, bytes), a, x0, y0, t_lo, t_hi, srho);
+    clock_advance(clk, slot, tt);
 }
 
 // 64 x 16 MIPS tiles below this count leave the GPU under-filled (two per CU)

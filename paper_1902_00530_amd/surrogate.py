@@ -3,11 +3,14 @@ that advances the coarse density and momentum fields of a lattice by k
 lattice Boltzmann steps, trained on pairs the method itself generates and
 judged by it.
 
-Every arithmetic step runs in the library's HIP kernels (lbm_cnn.h, lbm.h):
-the lattice Boltzmann steps (lbm_sweep_batch), coarse-graining and lifting
-(lbm_coarsen, lbm_lift), normalisation (lbm_channel_affine), the network's
-forward and backward passes (lbm_cnn_forward / lbm_cnn_backward) and Adam
-(lbm_cnn_adam).  This module orders those calls and owns the tensors.
+Every arithmetic step runs in the library's HIP kernels behind its C ABI
+(lbm_cnn.h, lbm.h): the lattice Boltzmann steps (lbm_sweep_batch),
+coarse-graining and lifting (lbm_coarsen_many, lbm_lift_many), and the
+surrogate object (lbm_surrogate_create / _fit_normalisation / _train_step /
+_predict / _destroy: normalisation, forward and backward passes, Adam).  A
+surrogate sweep with its checks and fallbacks is one lbm_sweep_batch call
+(lbm_sweep_opts.surrogate).  This module orders those calls and owns the
+tensors.
 
 Fields: X = (rho, jx, jy, B) on the coarse grid, with B the lattice's
 activity constant as a fourth, constant channel (the dynamics depend on it).
@@ -22,10 +25,10 @@ import math
 
 import numpy as np
 
-from . import (Batch, lbm_channel_affine, lbm_channel_stats, lbm_cnn_adam, lbm_cnn_backward, lbm_cnn_forward,
-               lbm_cnn_grads, lbm_cnn_params, lbm_cnn_shape, lbm_cnn_workspace_bytes, lbm_coarsen_many,
-               lbm_field_error, lbm_fill_channel, lbm_lift_many, lbm_obs, lbm_params, lbm_sweep_batch,
-               lbm_sweep_opts, lbm_sweep_workspace_bytes)
+from . import (Batch, lbm_coarsen_many, lbm_field_error, lbm_fill_channel, lbm_lift_many, lbm_surrogate_create,
+               lbm_surrogate_desc, lbm_surrogate_destroy, lbm_surrogate_fit_normalisation,
+               lbm_surrogate_param_bytes, lbm_surrogate_predict, lbm_surrogate_train_step,
+               lbm_surrogate_workspace_bytes)
 
 CIN, HIDDEN, COUT = 4, 32, 3
 
@@ -34,98 +37,56 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-class Network:
-    """Weights (bf16 copies + float32 masters), Adam state and per-channel
-    normalisation of the surrogate network."""
+class Surrogate:
+    """The library's surrogate object (lbm_surrogate_*): its parameter block
+    (weights, Adam moments, normalisation) and workspace are torch tensors
+    owned here, its work runs on one stream."""
 
-    def __init__(self, seed=0, device="cuda"):
+    def __init__(self, h, w, coarse, k, max_batch, cin=CIN, seed=0, device="cuda", stream=None):
         import torch
-        rng = np.random.default_rng(seed)
-        shapes = [(HIDDEN, CIN, 3, 3), (HIDDEN, HIDDEN, 3, 3), (COUT, HIDDEN, 3, 3)]
-        fan = [9 * CIN, 9 * HIDDEN, 9 * HIDDEN]
-        self.master_w, self.w, self.b = [], [], []
-        for k, (sh, fi) in enumerate(zip(shapes, fan)):
-            lim = np.sqrt(6.0 / fi) * (0.1 if k == 2 else 1.0)
-            m = torch.from_numpy(rng.uniform(-lim, lim, size=sh)).float().to(device)
-            self.master_w.append(m)
-            self.w.append(m.to(torch.bfloat16))
-            self.b.append(torch.zeros(sh[0], device=device))
-        self.tensors = [self.master_w[0], self.b[0], self.master_w[1], self.b[1], self.master_w[2], self.b[2]]
-        self.m = [torch.zeros_like(t) for t in self.tensors]
-        self.v = [torch.zeros_like(t) for t in self.tensors]
-        self.grads = [torch.zeros_like(t) for t in self.tensors]
-        self.t = 0
-        self.scale = torch.ones(CIN, device=device)
-        self.shift = torch.zeros(CIN, device=device)
-        self.inv_scale = torch.ones(CIN, device=device)
-        self.inv_shift = torch.zeros(CIN, device=device)
-        self.device = device
-        self._buf = {}
+        self.desc = lbm_surrogate_desc(int(cin), int(h), int(w), int(coarse), int(k), int(max_batch))
+        self.k, self.coarse, self.max_batch, self.cin = int(k), int(coarse), int(max_batch), int(cin)
+        pb, wb = lbm_surrogate_param_bytes(self.desc), lbm_surrogate_workspace_bytes(self.desc)
+        if not pb or not wb:
+            raise ValueError("invalid surrogate description")
+        self.params = torch.zeros(pb, dtype=torch.uint8, device=device)
+        self.ws = torch.empty(wb, dtype=torch.uint8, device=device)
+        self.loss = torch.zeros(1, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.handle = lbm_surrogate_create(self.desc, self.params.data_ptr(), 1, seed, self.ws.data_ptr(), wb,
+                                           self.stream.cuda_stream)
 
-    def params(self):
-        return lbm_cnn_params((ctypes.c_void_p * 3)(*[w.data_ptr() for w in self.w]),
-                              (ctypes.c_void_p * 3)(*[b.data_ptr() for b in self.b]))
+    def fit_normalisation(self, X):
+        """Per-channel normalisation from the mean and spread of samples X."""
+        lbm_surrogate_fit_normalisation(self.handle, X.data_ptr(), X.shape[0])
 
-    def grad_struct(self):
-        g = self.grads
-        return lbm_cnn_grads((ctypes.c_void_p * 3)(g[0].data_ptr(), g[2].data_ptr(), g[4].data_ptr()),
-                             (ctypes.c_void_p * 3)(g[1].data_ptr(), g[3].data_ptr(), g[5].data_ptr()))
+    def train_step(self, X, T, idx, lr):
+        """One Adam step on the samples idx (device int32) of X and T; returns
+        the loss tensor (device)."""
+        lbm_surrogate_train_step(self.handle, X.data_ptr(), T.data_ptr(), idx.data_ptr(), idx.numel(), lr,
+                                 self.loss.data_ptr())
+        return self.loss
 
-    def set_normalisation(self, mean, std):
-        """Inputs are mapped to (x - mean)/std per channel (float arrays of CIN)."""
+    def predict(self, X):
+        """The network's coarse fields k steps after X (constant channels
+        carried over), in chunks of max_batch samples."""
         import torch
-        std = np.where(np.asarray(std) > 0, std, 1.0)
-        self.scale = torch.tensor(1.0 / std, dtype=torch.float32, device=self.device)
-        self.shift = torch.tensor(-np.asarray(mean) / std, dtype=torch.float32, device=self.device)
-        self.inv_scale = torch.tensor(std, dtype=torch.float32, device=self.device)
-        self.inv_shift = torch.tensor(mean, dtype=torch.float32, device=self.device)
+        Y = torch.empty_like(X)
+        for s in range(0, X.shape[0], self.max_batch):
+            m = min(self.max_batch, X.shape[0] - s)
+            lbm_surrogate_predict(self.handle, X[s:s + m].data_ptr(), m, Y[s:s + m].data_ptr())
+        return Y
 
-    def _buffers(self, n, h, w):
-        import torch
-        key = (n, h, w)
-        if key not in self._buf:
-            shape = lbm_cnn_shape(n, CIN, HIDDEN, COUT, h, w)
-            self._buf[key] = dict(
-                shape=shape,
-                a1=torch.empty((n, HIDDEN, h, w), device=self.device),
-                a2=torch.empty((n, HIDDEN, h, w), device=self.device),
-                y=torch.empty((n, COUT, h, w), device=self.device),
-                ws=torch.empty(lbm_cnn_workspace_bytes(shape), dtype=torch.uint8, device=self.device),
-                loss=torch.empty(1, device=self.device))
-        return self._buf[key]
+    def close(self):
+        if self.handle:
+            lbm_surrogate_destroy(self.handle)
+            self.handle = None
 
-    def normalise(self, x, stream, channels=CIN):
-        lbm_channel_affine(_ptr(x), x.shape[0], x.shape[1], channels, x.shape[2] * x.shape[3], _ptr(self.scale),
-                           _ptr(self.shift), stream)
-
-    def denormalise(self, y, stream):
-        lbm_channel_affine(_ptr(y), y.shape[0], y.shape[1], COUT, y.shape[2] * y.shape[3], _ptr(self.inv_scale),
-                           _ptr(self.inv_shift), stream)
-
-    def forward_normalised(self, xn, stream):
-        """Network output for normalised inputs (n, CIN, h, w); returns the
-        (reused) output tensor in normalised units."""
-        n, _, h, w = xn.shape
-        B = self._buffers(n, h, w)
-        lbm_cnn_forward(B["shape"], self.params(), _ptr(xn), _ptr(B["a1"]), _ptr(B["a2"]), _ptr(B["y"]),
-                        _ptr(B["ws"]), B["ws"].numel(), stream)
-        return B["y"]
-
-    def train_step(self, xn, tn, lr, stream, beta1=0.9, beta2=0.999, eps=1e-8):
-        """One Adam step on a normalised batch; returns the loss tensor (device)."""
-        n, _, h, w = xn.shape
-        B = self._buffers(n, h, w)
-        p = self.params()
-        lbm_cnn_forward(B["shape"], p, _ptr(xn), _ptr(B["a1"]), _ptr(B["a2"]), _ptr(B["y"]), _ptr(B["ws"]),
-                        B["ws"].numel(), stream)
-        lbm_cnn_backward(B["shape"], p, _ptr(xn), _ptr(B["a1"]), _ptr(B["a2"]), _ptr(B["y"]), _ptr(tn),
-                         self.grad_struct(), _ptr(B["loss"]), _ptr(B["ws"]), B["ws"].numel(), stream)
-        self.t += 1
-        for k, (th, m, v, g) in enumerate(zip(self.tensors, self.m, self.v, self.grads)):
-            out = _ptr(self.w[k // 2]) if k % 2 == 0 else None
-            lbm_cnn_adam(_ptr(th), _ptr(m), _ptr(v), _ptr(g), th.numel(), lr, beta1, beta2, eps, self.t, out,
-                         stream)
-        return B["loss"]
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------
@@ -212,15 +173,9 @@ def relative_l2(a, b, stream, channels=COUT):
     return out.cpu().numpy()
 
 
-def predict(net, X, stream):
+def predict(net, X, stream=None):
     """Surrogate prediction of X' for coarse fields X (unnormalised)."""
-    xn = X.clone()
-    net.normalise(xn, stream)
-    y = net.forward_normalised(xn, stream).clone()
-    net.denormalise(y, stream)
-    out = X.clone()
-    out[:, :COUT] = y
-    return out
+    return net.predict(X)
 
 
 def generate_pairs(sampler, rounds, warmup, stream):
@@ -239,37 +194,28 @@ def generate_pairs(sampler, rounds, warmup, stream):
     return X, T
 
 
-def fit_normalisation(net, X, stream):
+def fit_normalisation(net, X, stream=None):
     """Per-channel mean and standard deviation of the training inputs."""
-    import torch
-    mean = torch.empty(CIN, dtype=torch.float64, device=X.device)
-    std = torch.empty(CIN, dtype=torch.float64, device=X.device)
-    lbm_channel_stats(_ptr(X), X.shape[0], CIN, X.shape[2] * X.shape[3], _ptr(mean), _ptr(std), stream)
-    net.set_normalisation(mean.cpu().numpy(), std.cpu().numpy())
+    net.fit_normalisation(X)
 
 
-def train(net, X, T, epochs, batch, lr, stream, seed=0, log=None):
-    """Adam on normalised pairs (inputs and targets share the channel
-    normalisation so the residual connection predicts the change), with the
-    step size taken down from lr to lr/20 over the epochs on a half cosine
-    (the targets carry the method's own noise, so a constant step leaves the
-    weights wandering at the end)."""
+def train(net, X, T, epochs, batch, lr, stream=None, seed=0, log=None):
+    """Adam on the pairs (inputs and targets share the channel normalisation,
+    so the residual connection predicts the change), one library call per
+    mini-batch of sample indices, with the step size taken down from lr to
+    lr/20 over the epochs on a half cosine (the targets carry the method's own
+    noise, so a constant step leaves the weights wandering at the end)."""
     import torch
-    Xn = X.clone()
-    Tn = T.clone()
-    net.normalise(Xn, stream)
-    net.normalise(Tn, stream, channels=COUT)
     g = torch.Generator(device="cpu").manual_seed(seed)
     n = X.shape[0]
     losses = []
     for ep in range(epochs):
         lr_ep = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * ep / max(1, epochs))))
-        perm = torch.randperm(n, generator=g).to(X.device)
+        perm = torch.randperm(n, generator=g).to(dtype=torch.int32).to(X.device)
         tot = 0.0
         nb = 0
         for s in range(0, n - batch + 1, batch):
-            idx = perm[s:s + batch]
-            loss = net.train_step(Xn[idx].contiguous(), Tn[idx, :COUT].contiguous(), lr_ep, stream)
+            loss = net.train_step(X, T, perm[s:s + batch], lr_ep)
             tot += float(loss.item()) if (nb % 16 == 0) else 0.0
             nb += 1
         losses.append(tot / max(1, (nb + 15) // 16))
@@ -278,88 +224,23 @@ def train(net, X, T, epochs, batch, lr, stream, seed=0, log=None):
     return losses
 
 
-def _advance_lattices(sampler, idx, from_judge, stream):
-    """One lattice Boltzmann call advancing lattices idx by k steps, each from
-    its fine state (sampler.batch) or, where from_judge[l], from the judge's
-    lifted state; the noise counters continue the sampler's.  Returns the
-    coarse fields (n, CIN, h, w) of every lattice's advanced state (rows of
-    lattices not in idx are left as they are)."""
-    import torch
-    lbm, judge = sampler.batch, sampler.judge
-    k = sampler.k
-    srcs = []
-    for l in idx:
-        b = judge if from_judge[l] else lbm
-        if b.current[l]:  # every state in the first buffer of its pair
-            b.buffers[2 * l].copy_(b.buffers[2 * l + 1])
-            b.current[l] = 0
-        srcs.append(b)
-    m = len(idx)
-    params = (lbm_params * m)(*[sampler.params[l] for l in idx])
-    bufs = (ctypes.c_void_p * (2 * m))(*[srcs[q].bufs[2 * l + h] for q, l in enumerate(idx) for h in (0, 1)])
-    need = lbm_sweep_workspace_bytes(params, m, 1)
-    if sampler.ws is None or sampler.ws.numel() < need:
-        sampler.ws = torch.empty(need, dtype=torch.uint8, device=sampler.device)
-    out = (lbm_obs * m)()
-    # a fixed two-step tile: every new subset would otherwise be tuned
-    opts = lbm_sweep_opts(int(k), 0, int(lbm.step_index), 16, 1)
-    lbm_sweep_batch(params, m, opts, bufs, _ptr(sampler.ws), need, stream, out)
-    for q, l in enumerate(idx):
-        srcs[q].current[l] = k & 1
-    ptrs = torch.tensor([(judge if from_judge[l] else lbm).state(l).data_ptr() for l in range(len(sampler.params))],
-                        dtype=torch.int64, device=sampler.device)
-    F = torch.empty((len(sampler.params), CIN, sampler.h, sampler.w), device=sampler.device)
-    hw = sampler.h * sampler.w
-    lbm_coarsen_many(sampler.params[0], len(sampler.params), _ptr(ptrs), sampler.c, _ptr(F), CIN * hw, stream)
-    lbm_fill_channel(_ptr(F), len(sampler.params), CIN, 3, hw, _ptr(sampler.act), stream)
-    return F
-
-
-def sweep(net, sampler, jumps, check_every, tol, stream):
-    """Surrogate sweep with checks and fallback.  Every jump advances every
-    lattice by k steps: lattices on the surrogate by one network evaluation
-    of their coarse fields, lattices that have fallen back by k lattice
-    Boltzmann steps of their own populations.  Every check_every jumps the
-    lattice Boltzmann method judges the surrogate lattices from the same
-    coarse state (lift, k steps, coarsen); a lattice whose relative L2 error
-    exceeds tol takes the judge's result and continues from the judge's
-    populations with the lattice Boltzmann method.  The fallen lattices and,
-    at a check, the judged ones run in one batched call.  Returns the final
-    coarse fields, the fallback flags and the check errors of each check."""
+def sweep(net, sampler, jumps, check_every, tol, stream=None):
+    """Surrogate sweep with checks and fallback: one lbm_sweep_batch call
+    (lbm_sweep_opts.surrogate) over the sampler's lattices.  Every jump
+    advances every lattice by k steps: lattices on the surrogate by one
+    network evaluation of their coarse fields, lattices that have fallen back
+    by k lattice Boltzmann steps of their own populations.  Every check_every
+    jumps the method judges the surrogate lattices from the same coarse state
+    (lift, k steps, coarsen); a lattice whose relative L2 error exceeds tol
+    takes the judge's result and continues from the judge's populations with
+    the method.  Returns the final coarse fields, the fallback flags and the
+    errors of each check (for the lattices still on the surrogate then)."""
     import torch
     n = len(sampler.params)
     X = torch.empty((n, CIN, sampler.h, sampler.w), device=sampler.device)
-    sampler.coarse_fields(sampler.batch, X, stream)
-    fallen = np.zeros(n, dtype=bool)
-    errors = []
-    lbm, judge = sampler.batch, sampler.judge
-    for j in range(jumps):
-        Y = predict(net, X, stream)
-        check = (j + 1) % check_every == 0 and not fallen.all()
-        if check:
-            lbm_lift_many(sampler.params[0], n, _ptr(X), CIN * sampler.h * sampler.w, sampler.c,
-                          _ptr(judge.dev_ptrs[0]), stream)
-            judge.current = [0] * n
-        idx = [l for l in range(n) if fallen[l] or check]
-        if idx:
-            F = _advance_lattices(sampler, idx, [check and not fallen[l] for l in range(n)], stream)
-            if fallen.any():
-                fb = torch.from_numpy(np.nonzero(fallen)[0]).to(sampler.device)
-                Y[fb] = F[fb]
-            if check:
-                e = relative_l2(Y, F, stream)
-                errors.append(e[~fallen])
-                newly = (e > tol) & ~fallen
-                for i in np.nonzero(newly)[0]:
-                    lbm.buffers[2 * i].copy_(judge.state(i))
-                    lbm.current[i] = 0
-                if newly.any():
-                    nw = torch.from_numpy(np.nonzero(newly)[0]).to(sampler.device)
-                    Y[nw] = F[nw]
-                    fallen |= newly
-        lbm.step_index += sampler.k
-        X = Y
-    return X, fallen, errors
+    _, fallen, errs = sampler.batch.surrogate_sweep(net, jumps * sampler.k, check_every, tol, coarse_out=X)
+    net.stream.synchronize()
+    return X, fallen, [e[~np.isnan(e)] for e in errs]
 
 
 # ---------------------------------------------------------------------------
@@ -412,7 +293,7 @@ def recipe(train_cfgs, test_cfgs, sweep_cfgs, coarse=8, k=50, warmup=2000, round
     hs.batch.step_index += 7919   # other noise counters, same coarse state
     Th2 = hs.judge_from(Xh, st)
     hs.batch.step_index -= 7919
-    net = Network(seed=0)
+    net = Surrogate(smp.h, smp.w, coarse, k, max(batch, len(test_cfgs), len(sweep_cfgs)), seed=0)
     fit_normalisation(net, X, st)
     floor = float(relative_l2(Th2, Th, st).mean())
     res["persistence_error"] = float(relative_l2(Xh, Th, st).mean())

@@ -224,3 +224,30 @@ def test_sweep_workspace_grows_with_samples():
     a = L._lib.lbm_sweep_workspace_bytes(arr, 2, 1)
     b = L._lib.lbm_sweep_workspace_bytes(arr, 2, 100)
     assert 0 < a < b and b - a >= 2 * 99 * 8 * 8 - 256
+
+
+def test_surrogate_descriptions_and_create_validation():
+    """The surrogate object: sizes of its parameter block and workspace, and
+    create's checks before any device work (cin 3 or 4, coarse 1 or even,
+    k >= 1, 1 <= max_batch <= 65535, 256-byte aligned caller buffers, a large
+    enough workspace)."""
+    import paper_1902_00530_amd as L
+    good = L.lbm_surrogate_desc(4, 32, 32, 8, 50, 64)
+    pb, wb = L.lbm_surrogate_param_bytes(good), L.lbm_surrogate_workspace_bytes(good)
+    nparam = 32 * 4 * 9 + 32 + 32 * 32 * 9 + 32 + 3 * 32 * 9 + 3
+    assert pb >= 3 * nparam * 4 + (32 * 4 * 9 + 32 * 32 * 9 + 3 * 32 * 9) * 2 and pb % 256 == 0
+    assert wb >= 64 * (4 + 3 + 32 + 32 + 3 + 3 * 4) * 32 * 32 * 4
+    for bad in (L.lbm_surrogate_desc(5, 32, 32, 8, 50, 64), L.lbm_surrogate_desc(4, 32, 32, 3, 50, 64),
+                L.lbm_surrogate_desc(4, 32, 32, 8, 0, 64), L.lbm_surrogate_desc(4, 32, 32, 8, 50, 0),
+                L.lbm_surrogate_desc(4, 0, 32, 8, 50, 64), L.lbm_surrogate_desc(4, 32, 32, 8, 50, 70000)):
+        assert L.lbm_surrogate_param_bytes(bad) == 0 and L.lbm_surrogate_workspace_bytes(bad) == 0
+    h = ctypes.c_void_p()
+    create = L._lib.lbm_surrogate_create
+    assert create(ctypes.byref(L.lbm_surrogate_desc(5, 32, 32, 8, 50, 64)), ctypes.c_void_p(4096), 0, 0,
+                  ctypes.c_void_p(8192), wb, None, ctypes.byref(h)) == L.LBM_EINVAL
+    assert create(ctypes.byref(good), ctypes.c_void_p(4096 + 4), 0, 0, ctypes.c_void_p(8192), wb, None,
+                  ctypes.byref(h)) == L.LBM_EINVAL and "aligned" in L.lbm_last_error()
+    assert create(ctypes.byref(good), ctypes.c_void_p(4096), 0, 0, ctypes.c_void_p(8192), wb - 1, None,
+                  ctypes.byref(h)) == L.LBM_EINVAL and "workspace" in L.lbm_last_error()
+    assert L._lib.lbm_surrogate_train_step(None, None, None, None, 1, ctypes.c_float(1e-3), None) == L.LBM_ESTATE
+    assert L._lib.lbm_surrogate_predict(None, None, 1, None) == L.LBM_ESTATE

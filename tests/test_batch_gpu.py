@@ -477,3 +477,27 @@ def test_keep_tables_reuses_only_what_still_holds(L):
     run(cfgs[1:4], states[1:4], other_bufs, 1, 16)
     run(cfgs, states, bufs, 1, 1)
     run(cfgs, states, bufs, 1, 16)
+
+
+def test_enqueue_only_sweep_and_later_samples(L):
+    """A sweep called with out == NULL only enqueues its work; its samples
+    stay in the workspace until lbm_sweep_samples reads them, and equal the
+    synchronous call's samples, with the same final states."""
+    cfgs = small_batch()
+    states = init_states(L, cfgs)
+    res = []
+    for fetch in (True, False):
+        b = L.Batch([_gparams(L, c) for c in cfgs])
+        for l, f0 in enumerate(states):
+            b.set_state(l, f0)
+        b.run(8)  # tables written (and a second call that keeps them)
+        out = b.run(24, sample_every=8, tile_rows=16, fetch=fetch)
+        if not fetch:
+            assert out is None
+            out = b.samples()
+        torch.cuda.synchronize()
+        res.append((out, [b.state(l).clone() for l in range(len(cfgs))]))
+    (o1, s1), (o2, s2) = res
+    assert o1 == o2 and len(o1[0]) == 3
+    for a, b_ in zip(s1, s2):
+        assert torch.equal(a, b_)
