@@ -198,10 +198,10 @@ def time_single(L, torch, cfgs, steps, warmup, storage=0, lattice=0):
     return ms, obs
 
 
-def time_batch(L, torch, cfgs, steps, warmup, tile_rows=0, lattice=0):
+def time_batch(L, torch, cfgs, steps, warmup, tile_rows=0, lattice=0, storage=0):
     """All lattices advanced by lbm_sweep_batch (one launch per step, or per
     two steps for the two-step tiles)."""
-    lats = make_lattices(L, cfgs, lattice=lattice)
+    lats = make_lattices(L, cfgs, storage, lattice)
     b = L.Batch([lat.params for lat in lats])
     for l, lat in enumerate(lats):
         b.set_state(l, lat.state)
@@ -409,13 +409,13 @@ def main():
         wname = "MIPS 4096x4096 periodic D2Q9, mean density 1.0 (x8 scaled), sigma 8/70, tau 2"
     sites = sum(c["nx"] * c["ny"] for c in cfgs)
     mode = args.mode or ("batch" if args.workload in ("cil1024x5", "cil4096") else "single")
-    if args.storage != 0 or args.workload == "mips4096":  # lbm_step only
+    if args.workload == "mips4096":  # lbm_step only
         mode = "single"
 
     t_wall = time.perf_counter()
     rows, ngr = 0, 1
     if mode == "batch":
-        ms, obs = time_batch(L, torch, cfgs, args.steps, args.warmup, args.tile_rows, lattice)
+        ms, obs = time_batch(L, torch, cfgs, args.steps, args.warmup, args.tile_rows, lattice, args.storage)
         rows = time_batch.tile_rows
         ngr = time_batch.groups
         two, one = batch_launches(args.steps, rows)
@@ -580,6 +580,16 @@ def main():
             "MLUPS_one_by_one": round(nb_sites * kb / (ms1 / 1e3) / 1e6, 1),
             "speedup": round(ms1 / msb, 3),
             "field_error": "0 (batch members equal single runs bit for bit)"}
+        # the same sweep with 16-bit deviation storage, batched, against the
+        # plain FP32 form (one lattice per launch) and the FP32 batch
+        for st, name in ((1, "bf16_dev"), (2, "f16_dev")):
+            ms16, _ = time_batch(L, torch, bcfgs, kb, 10, storage=st)
+            var["batch256_phase_sweep_" + name] = {
+                "MLUPS_batched": round(nb_sites * kb / (ms16 / 1e3) / 1e6, 1), "tile_rows": time_batch.tile_rows,
+                "speedup_vs_fp32_one_by_one": round(ms1 / ms16, 3),
+                "speedup_vs_fp32_batched": round(msb / ms16, 3),
+                "field_error": ("members equal lbm_step runs in the same storage bit for bit; storage error vs the "
+                                "FP64 oracle as stated for cil4096_" + name)}
         # the same sweep on the square lattice (D2Q9, tuned tiles)
         msb, _ = time_batch(L, torch, bcfgs, kb, 10, lattice=L.LBM_D2Q9)
         ms1, _ = time_single(L, torch, bcfgs, kb, 10, lattice=L.LBM_D2Q9)

@@ -325,11 +325,12 @@ int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n);
 int32_t lbm_sweep_groups(const lbm_params *ps, int32_t n);
 
 /* Run a batch.  ps[n]: per-lattice parameters; every lattice uses the same
- * velocity set (D2Q7 or D2Q9), F32 storage, the same model (CIL, MIPS or
- * passive), and agrees on tau == 1 and on
- * sigma == 0; nx*ny*Q < 2^30 (Q = 7 or 9 populations), ny <= 32760.
- * bufs[2n]: caller-owned device buffers [Q][ny][nx], lattice l's state in
- * bufs[2l] and bufs[2l+1] free.
+ * velocity set (D2Q7 or D2Q9), the same storage (F32; on D2Q7 also
+ * BF16_DEV or F16_DEV, each step rounding its results into the storage as
+ * lbm_step does), the same model (CIL, MIPS or passive), and agrees on
+ * tau == 1 and on sigma == 0; nx*ny*Q < 2^30 (Q = 7 or 9 populations),
+ * ny <= 32760.  bufs[2n]: caller-owned device buffers [Q][ny][nx] of the
+ * storage type, lattice l's state in bufs[2l] and bufs[2l+1] free.
  * ws: caller-owned device workspace of ws_bytes >=
  * lbm_sweep_workspace_bytes(ps, n, n_samples).  out: host array of
  * n * n_samples lbm_obs, n_samples = n_steps / sample_every (1 if
@@ -339,7 +340,7 @@ int32_t lbm_sweep_groups(const lbm_params *ps, int32_t n);
  * lbm_sweep_samples reads them.  The
  * steps of lattice l use its own seed and the noise counters
  * step0 .. step0 + n_steps - 1, so a lattice gives the same result as
- * lbm_step on its own.  Afterwards lattice l's state is in
+ * lbm_step on its own (bit for bit).  Afterwards lattice l's state is in
  * bufs[2l + (n_steps & 1)].  With out != NULL, synchronises the stream at
  * the end.  Errors: LBM_EINVAL for the conditions above, LBM_EUNSUPPORTED for
  * other storages or lattices, LBM_ENONFINITE if a sample saw a non-finite

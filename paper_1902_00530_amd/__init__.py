@@ -352,7 +352,7 @@ class Batch:
         import torch
         self.n = len(params_list)
         self.params = (lbm_params * self.n)(*params_list)
-        self.buffers = [torch.zeros((n_populations(p), p.ny, p.nx), dtype=torch.float32, device=device)
+        self.buffers = [torch.zeros((n_populations(p), p.ny, p.nx), dtype=storage_dtype(p.storage), device=device)
                         for p in params_list for _ in range(2)]
         self.bufs = (ctypes.c_void_p * (2 * self.n))(*[b.data_ptr() for b in self.buffers])
         # device arrays of the n buffer pointers of each parity (for the

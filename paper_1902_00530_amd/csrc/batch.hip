@@ -36,6 +36,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "device_q9.h"
@@ -78,7 +79,7 @@ constexpr int kMomRows = 16;
 // Step kernels over the tile list.  step_off: steps of this sample period
 // before this launch; launch_off: launches before it (the buffer parity).
 // ---------------------------------------------------------------------------
-template <int M, int F>
+template <int M, int ST, int F>
 __global__ __launch_bounds__(256) void k_batch_step(const BatchTile *__restrict__ tiles,
                                                     const LatDesc *__restrict__ lats,
                                                     const Ctrl *__restrict__ ctrl, int step_off, int launch_off)
@@ -92,14 +93,15 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchTile *__restrict_
     const int y = tl.ty * blockDim.y + threadIdx.y;
     if (x >= a.nx || y >= a.ny)
         return;
+    using T = typename Store<ST>::T;
     const uint32_t plane = (uint32_t)a.plane;
-    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], 28u * plane);
-    const __amdgpu_buffer_rsrc_t dst = buffer_rsrc(L.buf[par ^ 1], 28u * plane);
+    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], 7u * plane * (uint32_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t dst = buffer_rsrc(L.buf[par ^ 1], 7u * plane * (uint32_t)sizeof(T));
     const PullSources32 g_src = pull_sources32(a, x, y);
     float f[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        f[i] = BufIO<float>::load(src, g_src.idx[i], i * plane);
+        f[i] = Store<ST>::widen(BufIO<T>::load(src, g_src.idx[i], i * plane), i == 0 ? a.wr0 : a.wr1);
     float rho, jx, jy, ux, uy;
     site_moments(f, rho, jx, jy);
     local_ustar<M>(a, rho, jx, jy, ux, uy);
@@ -108,12 +110,12 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchTile *__restrict_
     site_collide<F>(a, f, rho, ux, uy, own, (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32));
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        BufIO<float>::store(dst, own, i * plane, f[i]);
+        BufIO<T>::store(dst, own, i * plane, Store<ST>::narrow(f[i], i == 0 ? a.wr0 : a.wr1));
 }
 
 // MIPS over a list of 64 x ROWS tiles (the tile body of the single-lattice
 // MIPS kernel, mips_tile_step), one step per launch.
-template <int F, int ROWS>
+template <int ST, int F, int ROWS>
 __global__ __launch_bounds__(256) void k_batch_step_mips(const BatchTile *__restrict__ tiles,
                                                          const LatDesc *__restrict__ lats,
                                                          const Ctrl *__restrict__ ctrl, int step_off, int launch_off)
@@ -127,8 +129,8 @@ __global__ __launch_bounds__(256) void k_batch_step_mips(const BatchTile *__rest
     const int x0 = tl.tx * 64, y0 = tl.ty * ROWS;
     if (x0 >= a.nx || y0 >= a.ny)  // whole-block exit, before the barrier
         return;
-    const uint32_t bytes = 28u * (uint32_t)a.plane;
-    mips_tile_step<kF32, F, ROWS>(buffer_rsrc(L.buf[par], bytes), buffer_rsrc(L.buf[par ^ 1], bytes), a, x0, y0,
+    const uint32_t bytes = 7u * (uint32_t)a.plane * (uint32_t)sizeof(typename Store<ST>::T);
+    mips_tile_step<ST, F, ROWS>(buffer_rsrc(L.buf[par], bytes), buffer_rsrc(L.buf[par ^ 1], bytes), a, x0, y0,
                             (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32), srho);
 }
 
@@ -146,23 +148,27 @@ constexpr int kResidentSites = 4096;
 constexpr int kResidentLanes = 1024;
 constexpr int kResidentPer = (kResidentSites + kResidentLanes - 1) / kResidentLanes;  // sites per lane
 
-template <int M, int F>
+template <int M, int ST, int F>
 __global__ __launch_bounds__(kResidentLanes) void k_batch_resident(const LatDesc *__restrict__ lats,
                                                                   const Ctrl *__restrict__ ctrl, int steps)
 {
+    using T = typename Store<ST>::T;
     __shared__ float st[8 * kResidentSites];  // plane i of the state at i * S, densities at 7 * S
     const LatDesc &L = lats[blockIdx.x];
-    const StepArgs a = L.a;  // pitch nx: plane i holds S = nx * ny contiguous floats
+    const StepArgs a = L.a;  // pitch nx: plane i holds S = nx * ny contiguous elements
     const int S = a.nx * a.ny;
     const int par = (int)(ctrl->k0 & 1);
-    const float *__restrict__ src = (const float *)L.buf[par];
-    float *__restrict__ dst = (float *)L.buf[par ^ (steps & 1)];
+    const T *__restrict__ src = (const T *)L.buf[par];
+    T *__restrict__ dst = (T *)L.buf[par ^ (steps & 1)];
     const int tid = threadIdx.x;
     float *rho_l = st + 7 * S;
+    // the state is kept in LDS as stored (16-bit storages: the stored bits),
+    // so every step rounds and widens exactly as lbm_step's loads and stores
+    T *sv = (T *)st;
 #pragma unroll
     for (int i = 0; i < 7; ++i)
         for (int e = tid; e < S; e += kResidentLanes)
-            st[i * S + e] = src[(int64_t)i * a.plane + e];
+            sv[i * S + e] = src[(int64_t)i * a.plane + e];
     // this lane's sites s = tid + j * 1024 and their coordinates
     int sx[kResidentPer], sy[kResidentPer];
 #pragma unroll
@@ -184,7 +190,7 @@ __global__ __launch_bounds__(kResidentLanes) void k_batch_resident(const LatDesc
                 const PullSources32 q = pull_sources32(a, sx[j], sy[j]);
 #pragma unroll
                 for (int i = 0; i < 7; ++i)
-                    f[j][i] = st[i * S + (int)q.idx[i]];
+                    f[j][i] = Store<ST>::widen(sv[i * S + (int)q.idx[i]], i == 0 ? a.wr0 : a.wr1);
                 site_moments(f[j], rho[j], jx[j], jy[j]);
                 if (M == kMips)
                     rho_l[s] = rho[j];
@@ -214,7 +220,7 @@ __global__ __launch_bounds__(kResidentLanes) void k_batch_resident(const LatDesc
                 site_collide<F>(a, f[j], rho[j], ux, uy, (uint32_t)s, tlo, thi);
 #pragma unroll
                 for (int i = 0; i < 7; ++i)
-                    st[i * S + s] = f[j][i];
+                    sv[i * S + s] = Store<ST>::narrow(f[j][i], i == 0 ? a.wr0 : a.wr1);
             }
         }
         __syncthreads();  // the step's writes precede the next step's pulls
@@ -222,7 +228,7 @@ __global__ __launch_bounds__(kResidentLanes) void k_batch_resident(const LatDesc
 #pragma unroll
     for (int i = 0; i < 7; ++i)
         for (int e = tid; e < S; e += kResidentLanes)
-            dst[(int64_t)i * a.plane + e] = st[i * S + e];
+            dst[(int64_t)i * a.plane + e] = sv[i * S + e];
 }
 
 // The same for the square lattice (D2Q9): nine planes and the densities, at
@@ -528,7 +534,7 @@ struct MidLayout {
 
 // Steps t and t+1 on a 64 x TY tile (NW waves: wave w owns rows w, w+NW,
 // ...); the first step's results go to LDS in the MidLayout above.
-template <int M, int F, int TY, int NW>
+template <int M, int ST, int F, int TY, int NW>
 __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__restrict__ tiles,
                                                      const LatDesc *__restrict__ lats,
                                                      const Ctrl *__restrict__ ctrl, int step_off, int launch_off)
@@ -546,9 +552,13 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
     const int x0 = tl.tx * 64, y0 = tl.ty * TY;
     if (x0 >= a.nx || y0 >= a.ny)  // whole-block exit, before the barrier
         return;
+    using T = typename Store<ST>::T;
     const uint32_t plane = (uint32_t)a.plane;
-    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], 28u * plane);
-    const __amdgpu_buffer_rsrc_t dst = buffer_rsrc(L.buf[par ^ 1], 28u * plane);
+    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], 7u * plane * (uint32_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t dst = buffer_rsrc(L.buf[par ^ 1], 7u * plane * (uint32_t)sizeof(T));
+    auto ld = [&](uint32_t elem, uint32_t first, int i) {
+        return Store<ST>::widen(BufIO<T>::load(src, elem, first), i == 0 ? a.wr0 : a.wr1);
+    };
     const uint32_t nx = (uint32_t)a.nx;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
@@ -570,20 +580,20 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
             const int yg = y0 - 1 + ly;
             const uint32_t p = (uint32_t)yg & 1u;
             const uint32_t c = (uint32_t)yg * nx + (uint32_t)x0;  // offset of (x0, yg)
-            g[0] = BufIO<float>::load(src, lane, c);
-            g[1] = BufIO<float>::load(src, lane, plane + c - 1u);
-            g[2] = BufIO<float>::load(src, lane, 2u * plane + c - nx - 1u + p);
-            g[3] = BufIO<float>::load(src, lane, 3u * plane + c - nx + p);
-            g[4] = BufIO<float>::load(src, lane, 4u * plane + c + 1u);
-            g[5] = BufIO<float>::load(src, lane, 5u * plane + c + nx + p);
-            g[6] = BufIO<float>::load(src, lane, 6u * plane + c + nx - 1u + p);
+            g[0] = ld(lane, c, 0);
+            g[1] = ld(lane, plane + c - 1u, 1);
+            g[2] = ld(lane, 2u * plane + c - nx - 1u + p, 2);
+            g[3] = ld(lane, 3u * plane + c - nx + p, 3);
+            g[4] = ld(lane, 4u * plane + c + 1u, 4);
+            g[5] = ld(lane, 5u * plane + c + nx + p, 5);
+            g[6] = ld(lane, 6u * plane + c + nx - 1u + p, 6);
             st = c + (uint32_t)lane;
         } else {
             const int xg = wrap_coord(x0 + lane, a.nx), yg = wrap_coord(y0 - 1 + ly, a.ny);
             const PullSources32 q = pull_sources32(a, xg, yg);
 #pragma unroll
             for (int i = 0; i < 7; ++i)
-                g[i] = BufIO<float>::load(src, q.idx[i], i * plane);
+                g[i] = ld(q.idx[i], i * plane, i);
             st = q.idx[0];  // pitch nx: own offset = site index
         }
     };
@@ -594,8 +604,8 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
         site_collide<F>(a, g, rho, ux, uy, st, ta_lo, ta_hi);
 #pragma unroll
         for (int i = 0; i < 7; ++i)
-            if (ML::kept(i, lx, ly))
-                mid[ML::at(i, lx, ly)] = g[i];
+            if (ML::kept(i, lx, ly))  // the value a store and the next step's load would give
+                mid[ML::at(i, lx, ly)] = Store<ST>::round(g[i], i == 0 ? a.wr0 : a.wr1);
     };
     // slots 0 .. NR-2: rows of every wave
     if (interior) {
@@ -622,7 +632,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
             const PullSources32 q = pull_sources32(a, xg, yg);
 #pragma unroll
             for (int i = 0; i < 7; ++i)
-                f[NR - 1][i] = BufIO<float>::load(src, q.idx[i], i * plane);
+                f[NR - 1][i] = ld(q.idx[i], i * plane, i);
             site[NR - 1] = q.idx[0];
         }
     }
@@ -653,7 +663,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
         site_collide<F>(a, f, rho, ux, uy, row + (uint32_t)lane, tb_lo, tb_hi);
 #pragma unroll
         for (int i = 0; i < 7; ++i)
-            BufIO<float>::store(dst, lane, i * plane + row, f[i]);
+            BufIO<T>::store(dst, lane, i * plane + row, Store<ST>::narrow(f[i], i == 0 ? a.wr0 : a.wr1));
     };
     if (interior) {
         for (int r = wv; r < TY; r += NW)
@@ -678,8 +688,8 @@ __device__ __forceinline__ double bwave_sum(double v)
     return v;
 }
 
-// Q = 7 (triangular) or 9 (square lattice).
-template <int Q>
+// Q = 7 (triangular) or 9 (square lattice, F32 storage only).
+template <int Q, int ST>
 __global__ __launch_bounds__(256) void k_batch_moments(const MomTile *__restrict__ mt, const LatDesc *__restrict__ lats,
                                                        const Ctrl *__restrict__ ctrl, int node,
                                                        double *__restrict__ part, double *__restrict__ colpart)
@@ -701,11 +711,12 @@ __global__ __launch_bounds__(256) void k_batch_moments(const MomTile *__restrict
             bool finite = true;
             float rho, jx, jy;
             if constexpr (Q == 7) {
-                const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], 28u * plane);
+                using T = typename Store<ST>::T;
+                const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], 7u * plane * (uint32_t)sizeof(T));
                 const PullSources32 g = pull_sources32(a, x, y);
 #pragma unroll
                 for (int i = 0; i < 7; ++i)
-                    f[i] = BufIO<float>::load(src, g.idx[i], i * plane);
+                    f[i] = Store<ST>::widen(BufIO<T>::load(src, g.idx[i], i * plane), i == 0 ? a.wr0 : a.wr1);
                 site_moments(f, rho, jx, jy);
             } else {
                 const float *src = (const float *)L.buf[par];
@@ -824,7 +835,7 @@ __global__ __launch_bounds__(256) void k_batch_final(const LatDesc *__restrict__
 // The density change of the paper's protocol (appendix "Simulation procedure
 // for results"): every population of lattice l gains drho_l / Q, in the
 // buffer that holds the state after this period's steps; per moments tile.
-template <int Q>
+template <int Q, int ST>
 __global__ __launch_bounds__(256) void k_batch_add_density(const MomTile *__restrict__ mt,
                                                            const LatDesc *__restrict__ lats,
                                                            const Ctrl *__restrict__ ctrl, int node)
@@ -836,7 +847,8 @@ __global__ __launch_bounds__(256) void k_batch_add_density(const MomTile *__rest
         return;
     const StepArgs &a = L.a;
     const int par = (int)((ctrl->k0 + node) & 1);
-    float *f = (float *)L.buf[par];
+    using T = typename Store<ST>::T;
+    T *f = (T *)L.buf[par];
     const int x = m.cx * 256 + threadIdx.x;
     if (x >= a.nx)
         return;
@@ -844,8 +856,9 @@ __global__ __launch_bounds__(256) void k_batch_add_density(const MomTile *__rest
     for (int y = m.cy * kMomRows; y < ye; ++y)
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            float *p = f + (size_t)i * (size_t)a.plane + (size_t)y * (size_t)a.pitch + x;
-            *p = *p + add;
+            const float wr = Q == 7 ? (i == 0 ? a.wr0 : a.wr1) : 0.0f;
+            T *p = f + (size_t)i * (size_t)a.plane + (size_t)y * (size_t)a.pitch + x;
+            *p = Store<ST>::narrow(Store<ST>::widen(*p, wr) + add, wr);
         }
 }
 
@@ -928,7 +941,8 @@ static std::vector<int> cache_groups(const lbm_params *ps, int n)
     std::vector<uint64_t> b(n);
     uint64_t total = 0;
     for (int l = 0; l < n; ++l) {
-        b[l] = 2ull * (ps[l].lattice == LBM_D2Q9 ? 9ull : 7ull) * 4ull * (uint64_t)ps[l].nx * ps[l].ny;
+        b[l] = 2ull * (ps[l].lattice == LBM_D2Q9 ? 9ull : 7ull) * (ps[l].storage == LBM_F32 ? 4ull : 2ull) *
+               (uint64_t)ps[l].nx * ps[l].ny;
         total += b[l];
     }
     const uint64_t ng = (total + kCacheGroupBytes - 1) / kCacheGroupBytes;
@@ -1027,81 +1041,90 @@ static int sweep_flags(const lbm_params *ps, int n)
     return f;
 }
 
-template <int M, int F>
+// Runtime storage and flags to compile-time template arguments.
+template <int V>
+using IntTag = std::integral_constant<int, V>;
+
+template <class Fn>
+static hipError_t with_storage(int storage, Fn &&fn)
+{
+    switch (storage) {
+    case kF32: return fn(IntTag<kF32>{});
+    case kBf16Dev: return fn(IntTag<kBf16Dev>{});
+    case kF16Dev: return fn(IntTag<kF16Dev>{});
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class Fn>
+static hipError_t with_flags(int flags, Fn &&fn)
+{
+    switch (flags) {
+    case 0: return fn(IntTag<0>{});
+    case kUnitTau: return fn(IntTag<kUnitTau>{});
+    case kNoisy: return fn(IntTag<kNoisy>{});
+    default: return fn(IntTag<kUnitTau | kNoisy>{});
+    }
+}
+
+template <int M, int ST, int F>
 static hipError_t launch_batch_step_mf(int shape, int64_t ntiles, const BatchTile *tiles, const LatDesc *lats,
                                        const Ctrl *ctrl, int step_off, int launch_off, hipStream_t s)
 {
     const Shape &sh = kShapes[shape];
     if (sh.steps == 1)
-        hipLaunchKernelGGL((k_batch_step<M, F>), dim3((unsigned)ntiles), dim3(sh.tx, sh.ty), 0, s, tiles, lats, ctrl,
-                           step_off, launch_off);
+        hipLaunchKernelGGL((k_batch_step<M, ST, F>), dim3((unsigned)ntiles), dim3(sh.tx, sh.ty), 0, s, tiles, lats,
+                           ctrl, step_off, launch_off);
     else if (sh.ty == 8)
-        hipLaunchKernelGGL((k_batch_step2<M, F, 8, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
+        hipLaunchKernelGGL((k_batch_step2<M, ST, F, 8, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
                            step_off, launch_off);
     else
-        hipLaunchKernelGGL((k_batch_step2<M, F, 16, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
-                           step_off, launch_off);
-    return hipGetLastError();
-}
-
-template <int M>
-static hipError_t launch_batch_step_m(int flags, int shape, int64_t ntiles, const BatchTile *tiles,
-                                      const LatDesc *lats, const Ctrl *ctrl, int so, int lo, hipStream_t s)
-{
-    switch (flags) {
-    case 0: return launch_batch_step_mf<M, 0>(shape, ntiles, tiles, lats, ctrl, so, lo, s);
-    case kUnitTau: return launch_batch_step_mf<M, kUnitTau>(shape, ntiles, tiles, lats, ctrl, so, lo, s);
-    case kNoisy: return launch_batch_step_mf<M, kNoisy>(shape, ntiles, tiles, lats, ctrl, so, lo, s);
-    default: return launch_batch_step_mf<M, kUnitTau | kNoisy>(shape, ntiles, tiles, lats, ctrl, so, lo, s);
-    }
-}
-
-template <int F>
-static hipError_t launch_batch_mips_f(int shape, int64_t ntiles, const BatchTile *tiles, const LatDesc *lats,
-                                      const Ctrl *ctrl, int step_off, int launch_off, hipStream_t s)
-{
-    if (shape == kMipsShape4)
-        hipLaunchKernelGGL((k_batch_step_mips<F, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
-                           step_off, launch_off);
-    else
-        hipLaunchKernelGGL((k_batch_step_mips<F, kMipsRows>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats,
+        hipLaunchKernelGGL((k_batch_step2<M, ST, F, 16, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats,
                            ctrl, step_off, launch_off);
     return hipGetLastError();
 }
 
-template <int M, int F>
-static void launch_resident_mf(bool q9, int n, const LatDesc *lats, const Ctrl *ctrl, int steps, hipStream_t s)
+template <int ST, int F>
+static hipError_t launch_batch_mips_f(int shape, int64_t ntiles, const BatchTile *tiles, const LatDesc *lats,
+                                      const Ctrl *ctrl, int step_off, int launch_off, hipStream_t s)
+{
+    if (shape == kMipsShape4)
+        hipLaunchKernelGGL((k_batch_step_mips<ST, F, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
+                           step_off, launch_off);
+    else
+        hipLaunchKernelGGL((k_batch_step_mips<ST, F, kMipsRows>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles,
+                           lats, ctrl, step_off, launch_off);
+    return hipGetLastError();
+}
+
+// Every lattice of the batch in one CU's LDS (D2Q9: F32 storage only).
+static hipError_t launch_resident(int lattice, int model, int storage, int flags, int n, const LatDesc *lats,
+                                  const Ctrl *ctrl, int steps, hipStream_t s)
 {
     const dim3 grd((unsigned)n), blk(kResidentLanes);
-    if (q9)
-        hipLaunchKernelGGL((k_batch_resident_q9<M, F>), grd, blk, 0, s, lats, ctrl, steps);
-    else
-        hipLaunchKernelGGL((k_batch_resident<M, F>), grd, blk, 0, s, lats, ctrl, steps);
-}
-
-template <int M>
-static void launch_resident_m(bool q9, int flags, int n, const LatDesc *lats, const Ctrl *ctrl, int steps,
-                              hipStream_t s)
-{
-    switch (flags) {
-    case 0: launch_resident_mf<M, 0>(q9, n, lats, ctrl, steps, s); break;
-    case kUnitTau: launch_resident_mf<M, kUnitTau>(q9, n, lats, ctrl, steps, s); break;
-    case kNoisy: launch_resident_mf<M, kNoisy>(q9, n, lats, ctrl, steps, s); break;
-    default: launch_resident_mf<M, kUnitTau | kNoisy>(q9, n, lats, ctrl, steps, s); break;
-    }
-}
-
-static hipError_t launch_resident(int lattice, int model, int flags, int n, const LatDesc *lats, const Ctrl *ctrl,
-                                  int steps, hipStream_t s)
-{
-    const bool q9 = lattice == LBM_D2Q9;
-    if (model == LBM_MIPS)
-        launch_resident_m<kMips>(q9, flags, n, lats, ctrl, steps, s);
-    else if (model == LBM_CIL)
-        launch_resident_m<kCil>(q9, flags, n, lats, ctrl, steps, s);
-    else
-        launch_resident_m<kPassive>(q9, flags, n, lats, ctrl, steps, s);
-    return hipGetLastError();
+    return with_storage(storage, [&](auto st) {
+        constexpr int ST = decltype(st)::value;
+        return with_flags(flags, [&](auto fl) {
+            constexpr int F = decltype(fl)::value;
+            if (lattice == LBM_D2Q9) {
+                if (ST != kF32)
+                    return hipErrorInvalidValue;
+                if (model == LBM_MIPS)
+                    hipLaunchKernelGGL((k_batch_resident_q9<kMips, F>), grd, blk, 0, s, lats, ctrl, steps);
+                else if (model == LBM_CIL)
+                    hipLaunchKernelGGL((k_batch_resident_q9<kCil, F>), grd, blk, 0, s, lats, ctrl, steps);
+                else
+                    hipLaunchKernelGGL((k_batch_resident_q9<kPassive, F>), grd, blk, 0, s, lats, ctrl, steps);
+            } else if (model == LBM_MIPS) {
+                hipLaunchKernelGGL((k_batch_resident<kMips, ST, F>), grd, blk, 0, s, lats, ctrl, steps);
+            } else if (model == LBM_CIL) {
+                hipLaunchKernelGGL((k_batch_resident<kCil, ST, F>), grd, blk, 0, s, lats, ctrl, steps);
+            } else {
+                hipLaunchKernelGGL((k_batch_resident<kPassive, ST, F>), grd, blk, 0, s, lats, ctrl, steps);
+            }
+            return hipGetLastError();
+        });
+    });
 }
 
 template <int M, int F>
@@ -1137,35 +1160,26 @@ static hipError_t launch_batch_q9_f(int model, int shape, int64_t ntiles, const 
     return hipGetLastError();
 }
 
-static hipError_t launch_batch_step(int lattice, int model, int flags, int shape, int64_t ntiles,
+// One launch of shape `shape` over a tile list (D2Q9: F32 storage only).
+static hipError_t launch_batch_step(int lattice, int model, int storage, int flags, int shape, int64_t ntiles,
                                     const BatchTile *tiles, const LatDesc *lats, const Ctrl *ctrl, int step_off,
                                     int launch_off, hipStream_t s)
 {
-    if (lattice == LBM_D2Q9) {
-        switch (flags) {
-        case 0: return launch_batch_q9_f<0>(model, shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
-        case kUnitTau:
-            return launch_batch_q9_f<kUnitTau>(model, shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
-        case kNoisy:
-            return launch_batch_q9_f<kNoisy>(model, shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
-        default:
-            return launch_batch_q9_f<kUnitTau | kNoisy>(model, shape, ntiles, tiles, lats, ctrl, step_off,
-                                                        launch_off, s);
-        }
-    }
-    if (model == kMips) {
-        switch (flags) {
-        case 0: return launch_batch_mips_f<0>(shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
-        case kUnitTau:
-            return launch_batch_mips_f<kUnitTau>(shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
-        case kNoisy: return launch_batch_mips_f<kNoisy>(shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
-        default:
-            return launch_batch_mips_f<kUnitTau | kNoisy>(shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
-        }
-    }
-    if (model == kCil)
-        return launch_batch_step_m<kCil>(flags, shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
-    return launch_batch_step_m<kPassive>(flags, shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+    return with_flags(flags, [&](auto fl) {
+        constexpr int F = decltype(fl)::value;
+        if (lattice == LBM_D2Q9)
+            return storage == kF32
+                       ? launch_batch_q9_f<F>(model, shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s)
+                       : hipErrorInvalidValue;
+        return with_storage(storage, [&](auto st) {
+            constexpr int ST = decltype(st)::value;
+            if (model == kMips)
+                return launch_batch_mips_f<ST, F>(shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+            if (model == kCil)
+                return launch_batch_step_mf<kCil, ST, F>(shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+            return launch_batch_step_mf<kPassive, ST, F>(shape, ntiles, tiles, lats, ctrl, step_off, launch_off, s);
+        });
+    });
 }
 
 // Tuned tile shape per batch signature (arch + lattice type + multiset of
@@ -1179,7 +1193,7 @@ static std::string signature(const lbm_params *ps, int n, int flags)
     for (int l = 0; l < n; ++l)
         hist[{ps[l].nx, ps[l].ny}]++;
     std::string s = "gfx950/q" + std::to_string(ps[0].lattice == LBM_D2Q9 ? 9 : 7) + "/m" +
-                    std::to_string(ps[0].model) + "/f" + std::to_string(flags);
+                    std::to_string(ps[0].model) + "/s" + std::to_string(ps[0].storage) + "/f" + std::to_string(flags);
     for (auto &h : hist)
         s += "/" + std::to_string(h.first.first) + "x" + std::to_string(h.first.second) + ":" +
              std::to_string(h.second);
@@ -1190,14 +1204,14 @@ static std::string signature(const lbm_params *ps, int n, int flags)
 struct GraphKey {
     int device;
     const void *tiles_main, *tiles_one, *lat, *ctrl, *mt, *part, *colpart, *colmean, *results;
-    int lattice, model, flags, shape;
+    int lattice, model, storage, flags, shape;
     int64_t ntiles_main, ntiles_one, nmt, n, n_samples, steps;
     int sample, add;
     std::vector<int64_t> groups;  // tile ranges of the lattice groups
     auto tie() const
     {
         return std::tie(device, tiles_main, tiles_one, lat, ctrl, mt, part, colpart, colmean, results, lattice, model,
-                        flags, shape, ntiles_main, ntiles_one, nmt, n, n_samples, steps, sample, add, groups);
+                        storage, flags, shape, ntiles_main, ntiles_one, nmt, n, n_samples, steps, sample, add, groups);
     }
     bool operator==(const GraphKey &o) const { return tie() == o.tie(); }
 };
@@ -1348,8 +1362,10 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
             return fail(rc, "lattice " + std::to_string(l) + ": " + lbm_last_error());
         if (ps[l].lattice != ps[0].lattice)
             return fail(LBM_EINVAL, "all lattices of a batch must use the same velocity set");
-        if (ps[l].storage != LBM_F32)
-            return fail(LBM_EUNSUPPORTED, "batched sweeps take F32 storage");
+        if (ps[l].storage != ps[0].storage)
+            return fail(LBM_EINVAL, "all lattices of a batch must use the same storage");
+        if (ps[l].storage != LBM_F32 && ps[l].lattice == LBM_D2Q9)
+            return fail(LBM_EUNSUPPORTED, "batched D2Q9 sweeps take F32 storage");
         if (ps[l].model != ps[0].model)
             return fail(LBM_EINVAL, "all lattices of a batch must use the same model");
         if ((uint64_t)ps[l].nx * ps[l].ny * (ps[l].lattice == LBM_D2Q9 ? 9ull : 7ull) >= (1ull << 30))
@@ -1544,12 +1560,12 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
             if (res && e == hipSuccess)  // first buffer -> second buffer
-                e = launch_resident(ps[0].lattice, ps[0].model, flags, n, d_lat, d_ctrl, kResidentTuneSteps, cap);
+                e = launch_resident(ps[0].lattice, ps[0].model, ps[0].storage, flags, n, d_lat, d_ctrl, kResidentTuneSteps, cap);
             // ten launches per lattice group, group after group, as the sweep runs them
             const std::vector<int64_t> gr = res ? std::vector<int64_t>{} : group_ranges(ps, cache_groups(ps, n), k);
             for (size_t g = 0; 2 * g < gr.size(); ++g)
                 for (int r10 = 0; r10 < 10 && e == hipSuccess; ++r10)
-                    e = launch_batch_step(ps[0].lattice, ps[0].model, flags, k, gr[2 * g + 1], tl.first + gr[2 * g],
+                    e = launch_batch_step(ps[0].lattice, ps[0].model, ps[0].storage, flags, k, gr[2 * g + 1], tl.first + gr[2 * g],
                                           d_lat, d_ctrl, 0, 0, cap);
             hipError_t ee = hipStreamEndCapture(cap, &g);
             (void)hipStreamDestroy(cap);
@@ -1620,7 +1636,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     auto enqueue = [&](int64_t steps, bool sample) -> hipError_t {
         int64_t done = 0, launches = 0;
         if (resident && steps > 0) {
-            hipError_t e = launch_resident(ps[0].lattice, ps[0].model, flags, n, d_lat, d_ctrl, (int)steps, s);
+            hipError_t e = launch_resident(ps[0].lattice, ps[0].model, ps[0].storage, flags, n, d_lat, d_ctrl, (int)steps, s);
             if (e != hipSuccess)
                 return e;
             done = steps;
@@ -1634,7 +1650,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
                 int64_t q = steps / 2;
                 q -= q & 1;  // an even number of two-step launches
                 for (; launches < q; ++launches, done += 2) {
-                    hipError_t e = launch_batch_step(ps[0].lattice, ps[0].model, flags, shape, g_main[2 * g + 1],
+                    hipError_t e = launch_batch_step(ps[0].lattice, ps[0].model, ps[0].storage, flags, shape, g_main[2 * g + 1],
                                                      main_list.first + g_main[2 * g], d_lat, d_ctrl, (int)done,
                                                      (int)launches, s);
                     if (e != hipSuccess)
@@ -1642,7 +1658,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
                 }
             }
             for (; done < steps; ++launches, ++done) {
-                hipError_t e = launch_batch_step(ps[0].lattice, ps[0].model, flags, two ? 0 : shape, g_one[2 * g + 1],
+                hipError_t e = launch_batch_step(ps[0].lattice, ps[0].model, ps[0].storage, flags, two ? 0 : shape, g_one[2 * g + 1],
                                                  one_list.first + g_one[2 * g], d_lat, d_ctrl, (int)done,
                                                  (int)launches, s);
                 if (e != hipSuccess)
@@ -1650,22 +1666,29 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
             }
         }
         if (sample) {
+            const int sto = ps[0].storage;
             if (q9)
-                hipLaunchKernelGGL(k_batch_moments<9>, dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat, d_ctrl,
-                                   (int)steps, d_part, d_colpart);
+                hipLaunchKernelGGL((k_batch_moments<9, kF32>), dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat,
+                                   d_ctrl, (int)steps, d_part, d_colpart);
             else
-                hipLaunchKernelGGL(k_batch_moments<7>, dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat, d_ctrl,
-                                   (int)steps, d_part, d_colpart);
+                (void)with_storage(sto, [&](auto st) {
+                    hipLaunchKernelGGL((k_batch_moments<7, decltype(st)::value>), dim3((unsigned)nmt), dim3(256), 0,
+                                       s, d_mt, d_lat, d_ctrl, (int)steps, d_part, d_colpart);
+                    return hipSuccess;
+                });
             hipLaunchKernelGGL(k_batch_colmeans, dim3((unsigned)((max_nx + 255) / 256), (unsigned)n), dim3(256), 0, s,
                                d_lat, d_colpart, d_colmean);
             hipLaunchKernelGGL(k_batch_final, dim3((unsigned)n), dim3(256), 0, s, d_lat, d_ctrl, (int)steps, d_part,
                                d_colmean, d_results, (int)n_samples);
             if (o->drho && q9)
-                hipLaunchKernelGGL(k_batch_add_density<9>, dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat, d_ctrl,
-                                   (int)steps);
+                hipLaunchKernelGGL((k_batch_add_density<9, kF32>), dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat,
+                                   d_ctrl, (int)steps);
             else if (o->drho)
-                hipLaunchKernelGGL(k_batch_add_density<7>, dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat, d_ctrl,
-                                   (int)steps);
+                (void)with_storage(sto, [&](auto st) {
+                    hipLaunchKernelGGL((k_batch_add_density<7, decltype(st)::value>), dim3((unsigned)nmt), dim3(256),
+                                       0, s, d_mt, d_lat, d_ctrl, (int)steps);
+                    return hipSuccess;
+                });
         }
         hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, d_ctrl, steps, sample ? 1 : 0);
         return hipGetLastError();
@@ -1685,7 +1708,8 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         // calls with the same key
         const GraphKey key{dev, (const void *)main_list.first, (const void *)one_list.first, (const void *)d_lat,
                            (const void *)d_ctrl, (const void *)d_mt, (const void *)d_part, (const void *)d_colpart,
-                           (const void *)d_colmean, (const void *)d_results, ps[0].lattice, ps[0].model, flags,
+                           (const void *)d_colmean, (const void *)d_results, ps[0].lattice, ps[0].model,
+                           ps[0].storage, flags,
                            shape,
                            main_list.second, one_list.second, nmt, (int64_t)n, n_samples, steps, sample ? 1 : 0,
                            o->drho ? 1 : 0, gkey};

@@ -125,6 +125,8 @@ struct Store<kF32> {
     __device__ __forceinline__ static void store(T *p, int64_t i, float v, float) { p[i] = v; }
     __device__ __forceinline__ static float widen(T v, float) { return v; }
     __device__ __forceinline__ static T narrow(float v, float) { return v; }
+    // the value a store and a later load give back
+    __device__ __forceinline__ static float round(float v, float) { return v; }
 };
 
 __device__ __forceinline__ float bf16_bits_to_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
@@ -139,6 +141,7 @@ struct Store<kBf16Dev> {
     __device__ __forceinline__ static void store(T *p, int64_t i, float v, float wr) { p[i] = float_to_bf16_rne(v - wr); }
     __device__ __forceinline__ static float widen(T v, float wr) { return bf16_bits_to_float(v) + wr; }
     __device__ __forceinline__ static T narrow(float v, float wr) { return float_to_bf16_rne(v - wr); }
+    __device__ __forceinline__ static float round(float v, float wr) { return widen(narrow(v, wr), wr); }
 };
 
 template <>
@@ -148,6 +151,7 @@ struct Store<kF16Dev> {
     __device__ __forceinline__ static void store(T *p, int64_t i, float v, float wr) { p[i] = (_Float16)(v - wr); }
     __device__ __forceinline__ static float widen(T v, float wr) { return (float)v + wr; }
     __device__ __forceinline__ static T narrow(float v, float wr) { return (_Float16)(v - wr); }
+    __device__ __forceinline__ static float round(float v, float wr) { return widen(narrow(v, wr), wr); }
 };
 
 // ---------------------------------------------------------------------------

@@ -249,8 +249,8 @@ int32_t surrogate_sweep(const lbm_params *ps, int n, const lbm_sweep_opts *o, vo
         return fail(LBM_EINVAL, "a surrogate sweep takes no density ramp");
     for (int l = 0; l < n; ++l) {
         const lbm_params &p = ps[l];
-        if (p.lattice != LBM_D2Q7 || p.model == LBM_MIPS)
-            return fail(LBM_EUNSUPPORTED, "surrogate sweeps take D2Q7 CIL or passive lattices");
+        if (p.lattice != LBM_D2Q7 || p.model == LBM_MIPS || p.storage != LBM_F32)
+            return fail(LBM_EUNSUPPORTED, "surrogate sweeps take D2Q7 CIL or passive lattices in F32 storage");
         if (p.nx != d.w * d.coarse || p.ny != d.h * d.coarse)
             return fail(LBM_EINVAL, "every lattice must be (w * coarse) x (h * coarse) sites");
     }

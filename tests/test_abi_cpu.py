@@ -208,7 +208,11 @@ def test_sweep_batch_rejects_invalid_batches():
     mips = L.make_params(128, 128, L.LBM_MIPS, tau=2.0, rho_star=1.0)
     assert _sweep(L, [mips], tile_rows=8) == L.LBM_EINVAL and "MIPS" in L.lbm_last_error()
     assert _sweep(L, [mips, good]) == L.LBM_EINVAL   # one model per batch
-    assert _sweep(L, [L.make_params(128, 128, L.LBM_CIL, storage=L.LBM_BF16_DEV)]) == L.LBM_EUNSUPPORTED
+    # 16-bit storages: D2Q7 only, one storage per batch
+    assert _sweep(L, [L.make_params(128, 128, L.LBM_CIL, storage=L.LBM_BF16_DEV, lattice=L.LBM_D2Q9)]) == \
+        L.LBM_EUNSUPPORTED
+    assert _sweep(L, [good, L.make_params(128, 128, L.LBM_CIL, tau=1.0, sigma=0.05, storage=L.LBM_F16_DEV)]) == \
+        L.LBM_EINVAL and "storage" in L.lbm_last_error()
     assert _sweep(L, [good, L.make_params(128, 128, L.LBM_PASSIVE, tau=1.0, sigma=0.05)]) == L.LBM_EINVAL
     assert _sweep(L, [good], n_steps=10, every=3) == L.LBM_EINVAL
     assert _sweep(L, [good], ws_bytes=100) == L.LBM_EINVAL

@@ -501,3 +501,80 @@ def test_enqueue_only_sweep_and_later_samples(L):
     assert o1 == o2 and len(o1[0]) == 3
     for a, b_ in zip(s1, s2):
         assert torch.equal(a, b_)
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+@pytest.mark.parametrize("tile_rows,use_graph", [(1, 1), (16, 1), (0, 1), (8, 0)])
+def test_16bit_batch_member_equals_single_run(L, storage, tile_rows, use_graph):
+    """BF16 / FP16 deviation storage in batched sweeps: every step rounds its
+    results into the storage as lbm_step's store does (the two-step kernel
+    rounds its first step's results in LDS the same way), so members equal
+    lbm_step runs bit for bit, samples and density ramp included."""
+    cfgs = small_batch()[:4]
+    rr = [0.3 + 0.3 * l for l in range(len(cfgs))]
+    gp = [L.make_params(c["nx"], c["ny"], c["model"], c["tau"], c["sigma"], c["A"], c["B"], c["C"], c["rho_star"],
+                        c["u_max"], c["seed"], storage=storage, rho_ref=rr[l]) for l, c in enumerate(cfgs)]
+    states = []
+    for l, p in enumerate(gp):
+        lat = L.Lattice(p, init=L.make_init(mode=1, rho_mean=rr[l], rho_spread=0.1))
+        torch.cuda.synchronize()
+        states.append(lat.state.clone())
+        lat.close()
+    steps, every = 14, 7
+    finals, samples = [], []
+    for p, f0 in zip(gp, states):
+        lat = L.Lattice(p)
+        lat.set_state(f0)
+        obs = []
+        for _ in range(steps // every):
+            lat.step(every)
+            obs.append(lat.observables())
+            lat.add_density(0.01)
+        finals.append(lat.state.clone())
+        samples.append(obs)
+        lat.close()
+    b = L.Batch(gp)
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    out = b.run(steps, sample_every=every, tile_rows=tile_rows, use_graph=use_graph, drho=0.01)
+    torch.cuda.synchronize()
+    for l in range(len(gp)):
+        assert b.state(l).dtype == f0.dtype
+        assert torch.equal(b.state(l), finals[l]), l
+        for s_b, s_l in zip(out[l], samples[l]):
+            assert abs(s_b["M"] - s_l["M"]) <= 1e-9 * abs(s_l["M"])
+            assert abs(s_b["phi"] - s_l["phi"]) <= 1e-12
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_16bit_mips_and_resident_batches(L, storage):
+    """MIPS (64 x 16 and 64 x 4 tiles) and the LDS-resident form in 16-bit
+    storage equal lbm_step runs bit for bit."""
+    import synth_inputs as SI_
+    cfgs = [dict(nx=90, ny=30, model=SI_.MIPS, tau=2.0, sigma=1.0 / 70.0, A=0.0, B=0.0, C=50.0, rho_star=0.2,
+                 u_max=0.3, seed=SI_.seed_for(9, l)) for l in range(3)]
+    rr = [0.10, 0.125, 0.15]
+    gp = [L.make_params(c["nx"], c["ny"], c["model"], c["tau"], c["sigma"], c["A"], c["B"], c["C"], c["rho_star"],
+                        c["u_max"], c["seed"], storage=storage, rho_ref=rr[l]) for l, c in enumerate(cfgs)]
+    states = []
+    for l, p in enumerate(gp):
+        lat = L.Lattice(p, init=L.make_init(mode=1, rho_mean=rr[l], rho_spread=0.1, u_mag=0.01))
+        torch.cuda.synchronize()
+        states.append(lat.state.clone())
+        lat.close()
+    steps = 41
+    finals = []
+    for p, f0 in zip(gp, states):
+        lat = L.Lattice(p)
+        lat.set_state(f0)
+        lat.step(steps)
+        finals.append(lat.state.clone())
+        lat.close()
+    for rows in (16, 4, L.LBM_TILE_RESIDENT):
+        b = L.Batch(gp)
+        for l, f0 in enumerate(states):
+            b.set_state(l, f0)
+        b.run(steps, tile_rows=rows)
+        torch.cuda.synchronize()
+        for l in range(len(gp)):
+            assert torch.equal(b.state(l), finals[l]), (rows, l)
