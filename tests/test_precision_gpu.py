@@ -149,3 +149,68 @@ def test_mass_and_order_drift_long_run(L, storage):
           f"phi {np.mean(phisq):.5f} vs FP32 {np.mean(phis32):.5f}")
     assert abs(mq - mq0) / mq0 < (1e-2 if storage == 1 else 1e-3) and abs(mq0 - m32) / m32 < 1e-3
     assert abs(np.mean(phisq) - np.mean(phis32)) < 0.05 * np.mean(phis32)
+
+
+def _golden_obs():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "precision_obs_256.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    return [(int(r[0]), float(r[1]), float(r[2]), float(r[3]), float(r[4])) for r in rows]
+
+
+def precision_observables(L, storage, seeds):
+    """phi, zeta and the banding measure averaged over the samples every 100
+    steps from step 10^4 to 2 x 10^4, and the relative mass change over the
+    2 x 10^4 steps, of the precision workload's 256 x 256 runs in storage
+    `storage` (one batch, one lattice per seed; members equal lbm_step runs
+    bit for bit)."""
+    ps, states = [], []
+    for s in seeds:
+        cfg = dict(SI.cil_4096(n=256), seed=s)
+        ini = cfg.pop("init")
+        p = _gparams(L, cfg, storage=storage, rho_ref=ini["rho_mean"] if storage else 0.0)
+        lat = L.Lattice(p, init=L.make_init(**ini))
+        torch.cuda.synchronize()
+        states.append(lat.state.clone())
+        lat.close()
+        ps.append(p)
+    b = L.Batch(ps)
+    for l, f in enumerate(states):
+        b.set_state(l, f)
+    m0 = [o[0]["M"] for o in b.run(0)]
+    first = b.run(10_000, sample_every=10_000)
+    rest = b.run(10_000, sample_every=100)
+    out = []
+    for l in range(len(seeds)):
+        obs = first[l] + rest[l]
+        assert [o["step"] for o in obs] == list(range(10_000, 20_001, 100))
+        out.append((np.mean([o["phi"] for o in obs]), np.mean([o["zeta"] for o in obs]),
+                    np.mean([o["drho"] for o in obs]), obs[-1]["M"] / m0[l] - 1.0))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2])
+def test_time_averaged_observables_against_the_oracle(L, storage):
+    """Matched 256 x 256 runs of the precision workload (four seeds) against
+    the FP64 oracle's runs of the same seeds (tests/golden/precision_obs_256.txt,
+    written by make_precision_obs.py from the oracle alone): the seed-averaged
+    phi, zeta and banding measure over steps 10^4 .. 2 x 10^4 agree within
+    four standard errors of the difference of two four-seed means (from the
+    oracle's seed-to-seed spread), and the mass drift over 2 x 10^4 steps is
+    stated: FP32 and FP16 within 1e-5, bfloat16 within 1e-2."""
+    gold = _golden_obs()
+    seeds = [g[0] for g in gold]
+    ref = np.array([g[1:] for g in gold])
+    got = precision_observables(L, storage, seeds)
+    n = len(seeds)
+    names = ("phi", "zeta", "drho")
+    for k, name in enumerate(names):
+        sd = ref[:, k].std(ddof=1)
+        tol = 4.0 * np.sqrt(2.0 / n) * sd + 1e-6
+        diff = got[:, k].mean() - ref[:, k].mean()
+        print(f"storage {storage} {name}: gpu {got[:, k].mean():.6f} oracle {ref[:, k].mean():.6f} "
+              f"diff {diff:+.2e} (bound {tol:.2e}; per seed {np.round(got[:, k] - ref[:, k], 6)})")
+        assert abs(diff) <= tol, (name, diff, tol)
+    drift = np.abs(got[:, 3]).max()
+    print(f"storage {storage}: mass drift over 2e4 steps {drift:.2e} (oracle {np.abs(ref[:, 3]).max():.2e})")
+    assert drift < (1e-2 if storage == 1 else 1e-5)
