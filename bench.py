@@ -619,6 +619,11 @@ def main():
                      check_every=4)
         r.pop("network")
         var["surrogate_256_k50"] = r
+        # the method's run-to-run spread at coarser cells (same lattices, k = 50)
+        fl = {}
+        for c in (8, 16, 32):
+            fl[f"{c}x{c}_sites_per_cell"] = round(S.noise_floor(SI.surrogate_grid(256, 21000), c, 50, 2000), 5)
+        var["surrogate_noise_floor_by_cell"] = fl
         # the paper's measurement protocol (180 x 60 lattices, its CIL
         # parameters): the hysteresis ramps at A = 2 (50 increasing and 50
         # decreasing runs) and a (rho, A) phase diagram (9 A values x 10

@@ -99,8 +99,12 @@ extern "C" {
 
 /* Population storage. */
 #define LBM_F32 0      /* float32 populations */
-#define LBM_BF16_DEV 1 /* bfloat16 deviations d_i = f_i - w_i rho_ref (round to nearest even) */
-#define LBM_F16_DEV 2  /* IEEE half deviations d_i = f_i - w_i rho_ref (round to nearest even) */
+#define LBM_BF16_DEV 1 /* bfloat16 deviations d_i = f_i - r_i (round to nearest even) */
+#define LBM_F16_DEV 2  /* IEEE half deviations d_i = f_i - r_i (round to nearest even) */
+/* The reference r_i of plane i is w_i rho_ref rounded to float, then to the
+ * storage format, so that f_i = 0 is stored exactly (lbm_deviation_reference
+ * returns the values); a population is read back as float(d_i) + r_i in
+ * float32. */
 
 /* Initial states (appendix "CIL Model: General notes"). */
 #define LBM_INIT_NONE 0        /* caller has filled the first buffer */
@@ -218,6 +222,11 @@ int32_t lbm_set_step(lbm_ctx *c, int64_t step);
  * adiabatic density change of the appendix "CIL Model: General notes"), which
  * raises every site's density by drho.  Enqueued, no sync. */
 int32_t lbm_add_density(lbm_ctx *c, double drho);
+
+/* The per-plane references r_i (Q floats: 7 on D2Q7, 9 on D2Q9) the
+ * deviation storages of these parameters are stored against (all 0 for
+ * F32).  LBM_EINVAL on invalid parameters. */
+int32_t lbm_deviation_reference(const lbm_params *p, float *wr);
 
 /* Release the context (waits for its stream first). */
 int32_t lbm_destroy(lbm_ctx *c);

@@ -80,9 +80,11 @@ int32_t lbm_field_error(const float *a, const float *b, int32_t n, int32_t c, in
                         void *stream);
 
 /* Per-channel mean and standard deviation (population) of x [n][c][hw] in
- * float64 (device arrays of c). */
-int32_t lbm_channel_stats(const float *x, int32_t n, int32_t c, int64_t hw, double *mean, double *stdev,
-                          void *stream);
+ * float64 (device arrays of c), summed in a fixed order over many blocks per
+ * channel.  ws: device workspace of lbm_channel_stats_workspace_bytes(c). */
+size_t lbm_channel_stats_workspace_bytes(int32_t c);
+int32_t lbm_channel_stats(const float *x, int32_t n, int32_t c, int64_t hw, double *mean, double *stdev, void *ws,
+                          size_t ws_bytes, void *stream);
 
 /* x[s][ch][:] = values[s] for s < n (device array of n floats). */
 int32_t lbm_fill_channel(float *x, int32_t n, int32_t c, int32_t ch, int64_t hw, const float *values, void *stream);

@@ -103,6 +103,7 @@ _P = ctypes.POINTER
 
 _SIGS = {
     "lbm_workspace_bytes": (ctypes.c_size_t, [_P(lbm_params), ctypes.c_int64]),
+    "lbm_deviation_reference": (ctypes.c_int32, [_P(lbm_params), _P(ctypes.c_float)]),
     "lbm_create": (ctypes.c_int32, [_P(lbm_params), _vp, _vp, ctypes.c_int64, _P(lbm_init), _vp, ctypes.c_size_t,
                                     _vp, _P(_vp)]),
     "lbm_step": (ctypes.c_int32, [_vp, ctypes.c_int64]),
@@ -134,7 +135,9 @@ _SIGS = {
     "lbm_coarsen": (ctypes.c_int32, [_P(lbm_params), _vp, ctypes.c_int32, _vp, _vp]),
     "lbm_field_error": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                          _vp, _vp]),
-    "lbm_channel_stats": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp]),
+    "lbm_channel_stats_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+    "lbm_channel_stats": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _vp, _vp, _vp,
+                                           ctypes.c_size_t, _vp]),
     "lbm_fill_channel": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _vp,
                                           _vp]),
     "lbm_lift": (ctypes.c_int32, [_P(lbm_params), _vp, ctypes.c_int32, _vp, _vp]),
@@ -169,6 +172,14 @@ def _check(rc, where):
 
 
 # ----------------------------------------------------------------- raw ABI
+
+def lbm_deviation_reference(params):
+    """The per-plane references r_i of the deviation storages (numpy float32
+    array of Q values): a stored 16-bit d_i reads back as float(d_i) + r_i."""
+    out = (ctypes.c_float * 9)()
+    _check(_lib.lbm_deviation_reference(ctypes.byref(params), out), "lbm_deviation_reference")
+    return np.array(out[:n_populations(params)], dtype=np.float32)
+
 
 def lbm_workspace_bytes(params, pitch):
     return _lib.lbm_workspace_bytes(ctypes.byref(params), int(pitch))
@@ -285,8 +296,13 @@ def lbm_field_error(a, b, n, c, nc, hw, out, stream):
     return _check(_lib.lbm_field_error(a, b, int(n), int(c), int(nc), int(hw), out, stream), "lbm_field_error")
 
 
-def lbm_channel_stats(x, n, c, hw, mean, stdev, stream):
-    return _check(_lib.lbm_channel_stats(x, int(n), int(c), int(hw), mean, stdev, stream), "lbm_channel_stats")
+def lbm_channel_stats_workspace_bytes(c):
+    return _lib.lbm_channel_stats_workspace_bytes(int(c))
+
+
+def lbm_channel_stats(x, n, c, hw, mean, stdev, ws, ws_bytes, stream):
+    return _check(_lib.lbm_channel_stats(x, int(n), int(c), int(hw), mean, stdev, ws, int(ws_bytes), stream),
+                  "lbm_channel_stats")
 
 
 def lbm_fill_channel(x, n, c, ch, hw, values, stream):

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchTile *__restrict_
     local_ustar<M>(a, rho, jx, jy, ux, uy);
     // batch buffers have pitch nx, so the own offset is the site index
     const uint32_t own = g_src.idx[0];
-    site_collide<F>(a, f, rho, ux, uy, own, (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32));
+    site_collide<F, ST>(a, f, rho, ux, uy, own, (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32));
 #pragma unroll
     for (int i = 0; i < 7; ++i)
         BufIO<T>::store(dst, own, i * plane, Store<ST>::narrow(f[i], i == 0 ? a.wr0 : a.wr1));
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kResidentLanes) void k_batch_resident(const LatDesc
                 } else {
                     local_ustar<M>(a, rho[j], jx[j], jy[j], ux, uy);
                 }
-                site_collide<F>(a, f[j], rho[j], ux, uy, (uint32_t)s, tlo, thi);
+                site_collide<F, ST>(a, f[j], rho[j], ux, uy, (uint32_t)s, tlo, thi);
 #pragma unroll
                 for (int i = 0; i < 7; ++i)
                     sv[i * S + s] = Store<ST>::narrow(f[j][i], i == 0 ? a.wr0 : a.wr1);
@@ -601,7 +601,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
         float rho, jx, jy, ux, uy;
         site_moments(g, rho, jx, jy);
         local_ustar<M>(a, rho, jx, jy, ux, uy);
-        site_collide<F>(a, g, rho, ux, uy, st, ta_lo, ta_hi);
+        site_collide<F, ST>(a, g, rho, ux, uy, st, ta_lo, ta_hi);
 #pragma unroll
         for (int i = 0; i < 7; ++i)
             if (ML::kept(i, lx, ly))  // the value a store and the next step's load would give
@@ -660,7 +660,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
         site_moments(f, rho, jx, jy);
         local_ustar<M>(a, rho, jx, jy, ux, uy);
         const uint32_t row = (uint32_t)(y0 + r) * nx + (uint32_t)x0;  // pitch nx
-        site_collide<F>(a, f, rho, ux, uy, row + (uint32_t)lane, tb_lo, tb_hi);
+        site_collide<F, ST>(a, f, rho, ux, uy, row + (uint32_t)lane, tb_lo, tb_hi);
 #pragma unroll
         for (int i = 0; i < 7; ++i)
             BufIO<T>::store(dst, lane, i * plane + row, Store<ST>::narrow(f[i], i == 0 ? a.wr0 : a.wr1));

@@ -63,6 +63,25 @@ int32_t validate_params(const lbm_params *p, int64_t pitch)
     return LBM_OK;
 }
 
+// w rho_ref rounded to the storage format, so that a population of exactly 0
+// (what the negative correction leaves) is stored and read back exactly:
+// with an unrepresentable reference every corrected zero came back a little
+// negative, a mass leak that ran away in disordered states
+static float storage_reference(double v, int storage)
+{
+    float f = (float)v;
+    if (storage == LBM_BF16_DEV) {
+        uint32_t b;
+        memcpy(&b, &f, 4);
+        b += 0x7fffu + ((b >> 16) & 1u);  // round to nearest even (finite values)
+        b &= 0xffff0000u;
+        memcpy(&f, &b, 4);
+    } else if (storage == LBM_F16_DEV) {
+        f = (float)(_Float16)f;
+    }
+    return f;
+}
+
 StepArgs make_step_args(const lbm_params &p, int64_t pitch)
 {
     StepArgs a;
@@ -80,9 +99,9 @@ StepArgs make_step_args(const lbm_params &p, int64_t pitch)
     a.inv_rho_star = p.model == LBM_MIPS ? (float)(1.0 / p.rho_star) : 1.0f;
     a.u_max = (float)p.u_max;
     const double rr = p.storage == LBM_F32 ? 0.0 : p.rho_ref;
-    a.wr0 = (float)(q9 ? 4.0 * rr / 9.0 : 0.5 * rr);
-    a.wr1 = (float)(q9 ? rr / 9.0 : rr / 12.0);
-    a.wr2 = (float)(q9 ? rr / 36.0 : rr / 12.0);
+    a.wr0 = storage_reference(q9 ? 4.0 * rr / 9.0 : 0.5 * rr, p.storage);
+    a.wr1 = storage_reference(q9 ? rr / 9.0 : rr / 12.0, p.storage);
+    a.wr2 = storage_reference(q9 ? rr / 36.0 : rr / 12.0, p.storage);
     a.key0 = (uint32_t)(p.seed & 0xffffffffu);
     a.key1 = (uint32_t)(p.seed >> 32);
     a.noisy = p.sigma != 0.0;
@@ -155,6 +174,20 @@ using namespace lbm;
 extern "C" {
 
 const char *lbm_last_error(void) { return g_error.c_str(); }
+
+int32_t lbm_deviation_reference(const lbm_params *p, float *wr)
+{
+    int32_t rc = validate_params(p, p ? p->nx : 0);
+    if (rc)
+        return rc;
+    if (!wr)
+        return fail(LBM_EINVAL, "null output");
+    const StepArgs a = make_step_args(*p, p->nx);
+    const int q = p->lattice == LBM_D2Q9 ? 9 : 7;
+    for (int i = 0; i < q; ++i)
+        wr[i] = i == 0 ? a.wr0 : (q == 7 || i <= 4 ? a.wr1 : a.wr2);
+    return LBM_OK;
+}
 
 size_t lbm_workspace_bytes(const lbm_params *p, int64_t pitch)
 {

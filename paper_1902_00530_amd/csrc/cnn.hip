@@ -351,42 +351,52 @@ __global__ __launch_bounds__(256) void k_field_error(const float *__restrict__ a
     }
 }
 
-// Per-channel mean and standard deviation over n samples and hw pixels
-// (float64, one block per channel, two passes in a fixed order).
-__global__ __launch_bounds__(256) void k_channel_stats(const float *__restrict__ x, int n, int C, int64_t hw,
-                                                       double *__restrict__ mean, double *__restrict__ stdev)
+// Per-channel mean and standard deviation over n samples and hw pixels, in
+// float64 and in a fixed order: each of kStatBlocks blocks of a channel sums
+// its contiguous share of the channel's n * hw values (pass 1: values, pass
+// 3: squared deviations from the mean), and one block per channel adds the
+// shares in block order (passes 2 and 4).
+constexpr int kStatBlocks = 256;
+
+__device__ __forceinline__ double stat_block_sum(double acc)
 {
     __shared__ double s_red[4];
-    __shared__ double s_mean;
-    const int c = blockIdx.x;
+    acc = cwave_sum(acc);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        s_red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    return ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];  // valid in every thread
+}
+
+// pass 1 (mean == nullptr) or 3: partial sums of x, or of (x - mean)^2
+__global__ __launch_bounds__(256) void k_stat_partial(const float *__restrict__ x, int n, int C, int64_t hw,
+                                                      const double *__restrict__ mean, double *__restrict__ part)
+{
+    const int c = blockIdx.y, b = blockIdx.x;
     const int64_t cnt = (int64_t)n * hw;
+    const int64_t lo = cnt * b / kStatBlocks, hi = cnt * (b + 1) / kStatBlocks;
+    const double m = mean ? mean[c] : 0.0;
     double acc = 0.0;
-    for (int s = 0; s < n; ++s)
-        for (int64_t p = threadIdx.x; p < hw; p += 256)
-            acc += (double)x[((int64_t)s * C + c) * hw + p];
-    acc = cwave_sum(acc);
-    if ((threadIdx.x & 63) == 0)
-        s_red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0)
-        s_mean = (((s_red[0] + s_red[1]) + s_red[2]) + s_red[3]) / (double)cnt;
-    __syncthreads();
-    const double m = s_mean;
-    acc = 0.0;
-    for (int s = 0; s < n; ++s)
-        for (int64_t p = threadIdx.x; p < hw; p += 256) {
-            const double d = (double)x[((int64_t)s * C + c) * hw + p] - m;
-            acc += d * d;
-        }
-    acc = cwave_sum(acc);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0)
-        s_red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        mean[c] = m;
-        stdev[c] = sqrt((((s_red[0] + s_red[1]) + s_red[2]) + s_red[3]) / (double)cnt);
+    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
+        const int64_t smp = e / hw, px = e - smp * hw;
+        const double v = (double)x[(smp * C + c) * hw + px];
+        acc += mean ? (v - m) * (v - m) : v;
     }
+    acc = stat_block_sum(acc);
+    if (threadIdx.x == 0)
+        part[(int64_t)c * kStatBlocks + b] = acc;
+}
+
+// pass 2 (mean of the partial sums) or 4 (standard deviation)
+__global__ __launch_bounds__(256) void k_stat_final(const double *__restrict__ part, int64_t cnt,
+                                                    double *__restrict__ out, int root)
+{
+    const int c = blockIdx.x;
+    double acc = threadIdx.x < kStatBlocks ? part[(int64_t)c * kStatBlocks + threadIdx.x] : 0.0;
+    acc = stat_block_sum(acc);
+    if (threadIdx.x == 0)
+        out[c] = root ? sqrt(acc / (double)cnt) : acc / (double)cnt;
 }
 
 // x[s, ch, :] = values[s]
@@ -710,12 +720,24 @@ int32_t lbm_field_error(const float *a, const float *b, int32_t n, int32_t c, in
     return LBM_OK;
 }
 
-int32_t lbm_channel_stats(const float *x, int32_t n, int32_t c, int64_t hw, double *mean, double *stdev,
-                          void *stream)
+size_t lbm_channel_stats_workspace_bytes(int32_t c) { return c < 1 ? 0 : (size_t)c * kStatBlocks * sizeof(double); }
+
+int32_t lbm_channel_stats(const float *x, int32_t n, int32_t c, int64_t hw, double *mean, double *stdev, void *ws,
+                          size_t ws_bytes, void *stream)
 {
-    if (!x || !mean || !stdev || n < 1 || c < 1 || hw < 1)
+    if (!x || !mean || !stdev || !ws || n < 1 || c < 1 || hw < 1)
         return fail(LBM_EINVAL, "invalid channel_stats arguments");
-    hipLaunchKernelGGL(k_channel_stats, dim3(c), dim3(256), 0, (hipStream_t)stream, x, n, c, hw, mean, stdev);
+    if (ws_bytes < lbm_channel_stats_workspace_bytes(c))
+        return fail(LBM_EINVAL, "workspace smaller than lbm_channel_stats_workspace_bytes()");
+    hipStream_t st = (hipStream_t)stream;
+    double *part = (double *)ws;
+    const int64_t cnt = (int64_t)n * hw;
+    hipLaunchKernelGGL(k_stat_partial, dim3(kStatBlocks, c), dim3(256), 0, st, x, n, c, hw, (const double *)nullptr,
+                       part);
+    hipLaunchKernelGGL(k_stat_final, dim3(c), dim3(256), 0, st, part, cnt, mean, 0);
+    hipLaunchKernelGGL(k_stat_partial, dim3(kStatBlocks, c), dim3(256), 0, st, x, n, c, hw, (const double *)mean,
+                       part);
+    hipLaunchKernelGGL(k_stat_final, dim3(c), dim3(256), 0, st, part, cnt, stdev, 1);
     LBM_HIP_TRY(hipGetLastError());
     return LBM_OK;
 }

@@ -158,6 +158,11 @@ struct Store<kF16Dev> {
 // Per-site arithmetic.
 // ---------------------------------------------------------------------------
 constexpr float kHalfSqrt3 = 0.86602540378443864676f;        // sqrt(3)/2
+// sqrt(3)/2 - kHalfSqrt3: with both parts, a_2^2 + a_3^2 keeps the lattice
+// identity sum_k (e_k.u)^2 = (3/2)|u|^2 to float precision (float(sqrt(3)/2)
+// squared is 3.6e-8 below 3/4, which biased every site's mass by about
+// 2 rho u_y^2 x 3.6e-8 per step, the same sign at every site)
+constexpr float kHalfSqrt3Lo = (float)(0.86602540378443864676 - (double)kHalfSqrt3);
 constexpr float kInv2Sqrt3 = 0.28867513459481288225f;        // 1/(2 sqrt 3)
 // 1/12 as an unevaluated float pair: float(1/12) is 3e-8 too large, which
 // would add a same-signed bias to the mass of every relaxed site; rho * hi +
@@ -231,8 +236,8 @@ __device__ __forceinline__ void site_equilibrium(float rho, float ux, float uy, 
 {
     const float usq = ux * ux + uy * uy;
     const float a1 = ux;
-    const float a2 = 0.5f * ux + kHalfSqrt3 * uy;
-    const float a3 = -0.5f * ux + kHalfSqrt3 * uy;
+    const float a2 = fmaf(kHalfSqrt3Lo, uy, fmaf(kHalfSqrt3, uy, 0.5f * ux));
+    const float a3 = fmaf(kHalfSqrt3Lo, uy, fmaf(kHalfSqrt3, uy, -0.5f * ux));
     const float r12 = fmaf(rho, kTwelfthHi, rho * kTwelfthLo);
     const float base = 1.0f - 2.0f * usq;
     eq[0] = 0.5f * rho * base;
@@ -249,8 +254,17 @@ __device__ __forceinline__ void site_equilibrium(float rho, float ux, float uy, 
 enum StepFlags : int { kUnitTau = 1, kNoisy = 2 };
 
 // BGK relaxation towards xi(rho, u*) (eq. fssD2Q7), zero-sum noise, and the
-// negative correction (pair form, rescale to rho where a rule fired).
-template <int F>
+// negative correction (pair form, rescale to rho where a rule fired).  The
+// relaxation and the noise conserve the site's mass exactly, so the rest
+// population is taken as rho minus the six moving ones: the site then keeps
+// its mass to one rounding, where the same formula term by term (the rounded
+// products of xi) drifted by ~1e-9 of the mass per step, the same sign at
+// every site.  In float32 storage that value enters the correction as the
+// rest population; in the 16-bit storages (S) it is taken from the moving
+// populations as they will be stored, at sites where no rule fired (where
+// one fires, the rescale to rho sets the mass).  tau = +inf keeps the
+// populations as they are.
+template <int F, int S = kF32>
 __device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], float rho, float ux, float uy,
                                              uint32_t site, uint32_t t_lo, uint32_t t_hi)
 {
@@ -268,6 +282,11 @@ __device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], floa
     }
     if (F & kNoisy)
         site_add_noise(a, site, t_lo, t_hi, f);
+    const bool absorb = (F & kUnitTau) || a.omega != 0.0f;
+    if constexpr (S == kF32) {
+        if (absorb)
+            f[0] = rho - ((f[1] + f[4]) + ((f[2] + f[5]) + (f[3] + f[6])));
+    }
     // f < 0 as a class test (negative infinity, normal, denormal or zero):
     // one compare per population with no NaN canonicalisation, NaN excluded
     // as by the ordered compare.  -0 counts as negative here; the rules then
@@ -287,11 +306,25 @@ __device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], floa
             fired = true;
         }
     }
+    if constexpr (S != kF32) {
+        if (!fired && absorb) {
+            float g[7];
+#pragma unroll
+            for (int i = 1; i < 7; ++i)
+                g[i] = Store<S>::round(f[i], a.wr1);
+            f[0] = rho - ((g[1] + g[4]) + ((g[2] + g[5]) + (g[3] + g[6])));
+        }
+    }
     if (fired) {
         // every f_i >= 0 here, so a zero sum means zero populations and the
         // factor 0 gives them back unchanged
         const float s = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6];
-        const float r = s > 0.0f ? rho * __builtin_amdgcn_rcpf(s) : 0.0f;
+        // the hardware reciprocal refined by one Newton step (within an ulp
+        // alone but not unbiased, and this branch runs at every site where a
+        // population went negative)
+        float q = __builtin_amdgcn_rcpf(s);
+        q = fmaf(fmaf(-s, q, 1.0f), q, q);
+        const float r = s > 0.0f ? rho * q : 0.0f;
 #pragma unroll
         for (int i = 0; i < 7; ++i)
             f[i] *= r;
@@ -541,7 +574,7 @@ __device__ __forceinline__ void mips_tile_step(__amdgpu_buffer_rsrc_t rs, __amdg
         nb[6] = srho[(cy - 1) * W + cx + p];
         float ux, uy;
         mips_ustar(a, rho[k], nb, ux, uy);
-        site_collide<F>(a, f[k], rho[k], ux, uy, (uint32_t)y * nx + (uint32_t)x, t_lo, t_hi);
+        site_collide<F, S>(a, f[k], rho[k], ux, uy, (uint32_t)y * nx + (uint32_t)x, t_lo, t_hi);
         const uint32_t own = (uint32_t)y * P + (uint32_t)x;
 #pragma unroll
         for (int i = 0; i < 7; ++i)

@@ -99,7 +99,7 @@ __device__ __forceinline__ void q9_add_noise(const StepArgs &a, uint32_t site, u
 // (closed pair form of the appendix "Negative Correction": a negative rest
 // population becomes 0, a pair with a negative member becomes
 // (max(d, 0), max(-d, 0)), and a site where a rule fired is rescaled to rho).
-template <int F>
+template <int F, int S = kF32>
 __device__ __forceinline__ void q9_collide(const StepArgs &a, float f[9], float rho, float ux, float uy,
                                            uint32_t site, uint32_t t_lo, uint32_t t_hi)
 {
@@ -116,6 +116,13 @@ __device__ __forceinline__ void q9_collide(const StepArgs &a, float f[9], float 
     }
     if (F & kNoisy)
         q9_add_noise(a, site, t_lo, t_hi, f);
+    // the rest population is rho minus the moving ones (as on D2Q7: float32
+    // here; the 16-bit storages below, at sites where no rule fired)
+    const bool absorb = (F & kUnitTau) || a.omega != 0.0f;
+    if constexpr (S == kF32) {
+        if (absorb)
+            f[0] = rho - (((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8])));
+    }
     constexpr int kNegative = 0x3c;  // -inf, -normal, -denormal, -0 (as in the D2Q7 body)
     bool fired = false;
     if (__builtin_amdgcn_classf(f[0], kNegative)) {
@@ -133,9 +140,20 @@ __device__ __forceinline__ void q9_collide(const StepArgs &a, float f[9], float 
             fired = true;
         }
     }
+    if constexpr (S != kF32) {
+        if (!fired && absorb) {
+            float g[9];
+#pragma unroll
+            for (int i = 1; i < 9; ++i)
+                g[i] = Store<S>::round(f[i], q9_wr(a, i));
+            f[0] = rho - (((g[1] + g[3]) + (g[2] + g[4])) + ((g[5] + g[7]) + (g[6] + g[8])));
+        }
+    }
     if (fired) {
         const float s = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-        const float r = s > 0.0f ? rho * __builtin_amdgcn_rcpf(s) : 0.0f;
+        float q = __builtin_amdgcn_rcpf(s);  // refined by one Newton step (as on D2Q7)
+        q = fmaf(fmaf(-s, q, 1.0f), q, q);
+        const float r = s > 0.0f ? rho * q : 0.0f;
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             f[i] *= r;
@@ -194,7 +212,7 @@ __device__ __forceinline__ void q9_site_step(const typename Store<S>::T *src, ty
     float rho, jx, jy, ux, uy;
     q9_moments(f, rho, jx, jy);
     local_ustar<M>(a, rho, jx, jy, ux, uy);
-    q9_collide<F>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
+    q9_collide<F, S>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         BufIO<T>::store(q9_plane_rsrc(dst, i, plane), g.idx[0], 0u, Store<S>::narrow(f[i], q9_wr(a, i)));
@@ -291,7 +309,7 @@ __device__ __forceinline__ void q9_mips_tile_step(const typename Store<S>::T *sr
         nb[8] = srho[c - W + 1];
         float ux, uy;
         q9_mips_ustar(a, rho[k], nb, ux, uy);
-        q9_collide<F>(a, f[k], rho[k], ux, uy, (uint32_t)y * nx + (uint32_t)x, t_lo, t_hi);
+        q9_collide<F, S>(a, f[k], rho[k], ux, uy, (uint32_t)y * nx + (uint32_t)x, t_lo, t_hi);
         const uint32_t own = (uint32_t)y * P + (uint32_t)x;
 #pragma unroll
         for (int i = 0; i < 9; ++i)

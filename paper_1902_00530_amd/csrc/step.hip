@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void k_step_local(const typename Store<S>::T *
     float rho, jx, jy, ux, uy;
     site_moments(f, rho, jx, jy);
     local_ustar<M>(a, rho, jx, jy, ux, uy);
-    site_collide<F>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
+    site_collide<F, S>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
     const uint32_t own = g_src.idx[0];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_step_local64(const typename Store<S>::T
     float rho, jx, jy, ux, uy;
     site_moments(f, rho, jx, jy);
     local_ustar<M>(a, rho, jx, jy, ux, uy);
-    site_collide<F>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
+    site_collide<F, S>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
     const int64_t own = g_src.idx[0];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_step_mips64(const typename Store<S>::T 
     nb[6] = srho[cy - 1][cx + p];
     float ux, uy;
     mips_ustar(a, rho, nb, ux, uy);
-    site_collide<F>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
+    site_collide<F, S>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
     const int64_t own = g_src.idx[0];
 #pragma unroll
     for (int i = 0; i < 7; ++i)

@@ -67,7 +67,7 @@ static ParamLayout param_layout(int cin)
 // Workspace: normalised inputs and targets, activations, the network's own
 // workspace, gradients, statistics, and the sweep's coarse fields.
 struct WorkLayout {
-    size_t xn, tn, a1, a2, y, cnn, grad[6], mean, stdev, loss, X, Y, F, err, mask, ptrs, act, total;
+    size_t xn, tn, a1, a2, y, cnn, grad[6], mean, stdev, stats, loss, X, Y, F, err, mask, ptrs, act, total;
     size_t cnn_bytes;
 };
 
@@ -94,6 +94,7 @@ static WorkLayout work_layout(const lbm_surrogate_desc &d)
         W.grad[k] = take(P.count[k] * sizeof(float));
     W.mean = take(d.cin * sizeof(double));
     W.stdev = take(d.cin * sizeof(double));
+    W.stats = take(lbm_channel_stats_workspace_bytes(d.cin));
     W.loss = take(sizeof(float));
     W.X = take(mb * d.cin * hw * sizeof(float));
     W.Y = take(mb * d.cin * hw * sizeof(float));
@@ -525,7 +526,8 @@ int32_t lbm_surrogate_fit_normalisation(lbm_surrogate *s, const float *x, int32_
         return fail(LBM_EINVAL, "null samples or n < 1");
     const int64_t hw = (int64_t)s->d.h * s->d.w;
     double *mean = (double *)(s->ws + s->W.mean), *sd = (double *)(s->ws + s->W.stdev);
-    int32_t rc = lbm_channel_stats(x, n, s->d.cin, hw, mean, sd, s->stream);
+    int32_t rc = lbm_channel_stats(x, n, s->d.cin, hw, mean, sd, s->ws + s->W.stats,
+                                   lbm_channel_stats_workspace_bytes(s->d.cin), s->stream);
     if (rc)
         return rc;
     hipLaunchKernelGGL(k_set_norm, dim3(1), dim3(64), 0, s->stream, mean, sd, s->d.cin, s->norm());

@@ -268,6 +268,23 @@ def sampler_from(cfgs, coarse, k, warmup, device="cuda"):
     return smp
 
 
+def noise_floor(cfgs, coarse, k, warmup, other_counters=7919):
+    """The method's own run-to-run spread at coarse cells of coarse x coarse
+    sites: the mean relative L2 error of (rho, j) between two runs of k steps
+    from the same lifted coarse state with different noise counters.  No
+    predictor checked against one run of the method can be expected below
+    about floor / sqrt(2)."""
+    import torch
+    st = torch.cuda.current_stream().cuda_stream
+    hs = sampler_from(cfgs, coarse, k, warmup)
+    X = torch.empty((len(cfgs), CIN, hs.h, hs.w), device=hs.device)
+    hs.coarse_fields(hs.batch, X, st)
+    T1 = hs.judge_from(X, st)
+    hs.batch.step_index += other_counters
+    T2 = hs.judge_from(X, st)
+    return float(relative_l2(T2, T1, st).mean())
+
+
 def recipe(train_cfgs, test_cfgs, sweep_cfgs, coarse=8, k=50, warmup=2000, rounds=320, epochs=30, batch=64,
            lr=1e-3, jumps=20, check_every=4, tol_abs=1e-2, tol_floor_factor=1.5, log=None):
     """Generate rounds x len(train_cfgs) training pairs, train, measure the

@@ -24,7 +24,7 @@ import oracle as O  # noqa: E402
 import synth_inputs as SI  # noqa: E402
 
 N = 256
-SEEDS = [SI.seed_for(4, l) for l in range(4)]
+SEEDS = [SI.seed_for(4, l) for l in range(8)]
 T0, T1, EVERY = 10_000, 20_000, 100
 
 

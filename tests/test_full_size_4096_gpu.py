@@ -26,7 +26,7 @@ import synth_inputs as SI
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-from test_parity_gpu import _gparams, _oparams, rel_err  # noqa: E402
+from test_parity_gpu import _gparams, _oparams, dev_ref, rel_err, storage_bound  # noqa: E402
 
 W = np.array([0.5] + [1.0 / 12.0] * 6)
 U = {1: 2.0 ** -8, 2: 2.0 ** -11}
@@ -55,10 +55,10 @@ def _perturbed(g0):
     return g0 * (1 + 1e-7 * r.uniform(-1, 1, g0.shape))
 
 
-def _check_one_step(orc, po, g0, got, label, storage=0, rho_ref=0.0):
+def _check_one_step(orc, po, g0, got, label, storage=0, wr=None):
     ref = orc.run(po, g0.copy(), 1)
     scale = np.abs(ref).max()
-    tight = 1e-6 * scale + (U[storage] * np.abs(ref - W[:, None, None] * rho_ref) + 2.0 ** -25 if storage else 0.0)
+    tight = 1e-6 * scale + (storage_bound(ref, wr, U[storage]) + 2.0 ** -25 if storage else 0.0)
     bad = np.abs(got - ref) > tight
     n_bad = int(bad.sum())
     sens = np.abs(orc.run(po, _perturbed(g0), 1) - ref)
@@ -101,14 +101,14 @@ def test_cil_4096_deviation_storage(L, orc, storage):
     f0 = orc.initialise(po, **ini)
     lat = L.Lattice(_gparams(L, cfg, storage=storage, rho_ref=rho_ref), init=L.make_init(**ini))
     torch.cuda.synchronize()
-    wr = W[:, None, None] * rho_ref
+    wr = dev_ref(L, _gparams(L, cfg, storage=storage, rho_ref=rho_ref))
     g0 = _host(lat.state, cfg["nx"]) + wr
     assert (np.abs(g0 - f0) <= 2 * U[storage] * np.abs(f0 - wr) + 1e-7).all()
     del f0
     lat.step(1)
     got = _host(lat.state, cfg["nx"]) + wr
     lat.close()
-    _check_one_step(orc, po, g0, got, f"CIL 4096^2 storage {storage}", storage, rho_ref)
+    _check_one_step(orc, po, g0, got, f"CIL 4096^2 storage {storage}", storage, wr)
 
 
 def test_mips_4096_fp32(L, orc):

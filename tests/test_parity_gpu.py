@@ -57,6 +57,22 @@ def gpu_run(L, cfg, f0, steps, pitch=None, chunks=None):
     return out
 
 
+def dev_ref(L, params):
+    """The per-plane references r_i a deviation storage is stored against
+    (w_i rho_ref rounded to the storage format), float64 [Q, 1, 1]."""
+    return L.lbm_deviation_reference(params).astype(np.float64)[:, None, None]
+
+
+def storage_bound(ref, wr, u):
+    """One rounding (unit roundoff u) of each stored deviation |ref - r_i|; the
+    rest population is rho minus the moving populations as stored, so it
+    also carries their roundings."""
+    d = np.abs(ref - wr)
+    b = u * d
+    b[0] = b[0] + u * d[1:].sum(axis=0)
+    return b
+
+
 def rel_err(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 

@@ -17,7 +17,7 @@ import synth_inputs as SI
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-from test_parity_gpu import _cfg, _oparams, _gparams, _init32, rel_err, STABLE  # noqa: E402
+from test_parity_gpu import _cfg, _oparams, _gparams, _init32, dev_ref, rel_err, STABLE, storage_bound  # noqa: E402
 
 W = np.array([0.5] + [1.0 / 12.0] * 6)
 U = {1: 2.0 ** -8, 2: 2.0 ** -11}
@@ -32,13 +32,18 @@ def L():
     return lib
 
 
+def _wr(storage, rho_ref):
+    import paper_1902_00530_amd as lib
+    return dev_ref(lib, lib.make_params(64, 64, SI.CIL, storage=storage, rho_ref=rho_ref))
+
+
 def quantise(f, storage, rho_ref):
-    d = torch.from_numpy(f - W[:, None, None] * rho_ref)
+    d = torch.from_numpy(f - _wr(storage, rho_ref))
     return d.to(DT[storage])
 
 
-def dequantise(q, rho_ref):
-    return q.double().cpu().numpy() + W[:, None, None] * rho_ref
+def dequantise(q, rho_ref, storage):
+    return q.double().cpu().numpy() + _wr(storage, rho_ref)
 
 
 def run_dev(L, cfg, q, steps, storage, rho_ref, step0=0):
@@ -60,9 +65,9 @@ def test_init_in_deviation_storage(L, orc, storage):
     lat = L.Lattice(_gparams(L, cfg, storage=storage, rho_ref=rho_ref),
                     init=L.make_init(**{**dict(angle_std=0.0, u_mag=-1.0, pop_noise=0.0), **ini}))
     torch.cuda.synchronize()
-    got = dequantise(lat.state[:, :, : cfg["nx"]], rho_ref)
+    got = dequantise(lat.state[:, :, : cfg["nx"]], rho_ref, storage)
     lat.close()
-    d = np.abs(ref - W[:, None, None] * rho_ref)
+    d = np.abs(ref - _wr(storage, rho_ref))
     # one rounding of d (plus the FP32 intermediate): at most 2u |d|
     assert (np.abs(got - ref) <= 2 * U[storage] * d + 1e-7).all()
 
@@ -74,11 +79,10 @@ def test_one_step_rounding_bound(L, orc, storage, name):
     rho_ref = ini["rho_mean"]
     f0 = orc.initialise(_oparams(orc, cfg), **ini)
     q0 = quantise(f0, storage, rho_ref)
-    f0q = dequantise(q0, rho_ref)
-    got = dequantise(run_dev(L, cfg, q0, 1, storage, rho_ref), rho_ref)
+    f0q = dequantise(q0, rho_ref, storage)
+    got = dequantise(run_dev(L, cfg, q0, 1, storage, rho_ref), rho_ref, storage)
     ref = orc.run(_oparams(orc, cfg), f0q.copy(), 1)
-    d = np.abs(ref - W[:, None, None] * rho_ref)
-    bound = U[storage] * d + 1e-6 * np.abs(ref).max() + 2.0 ** -25
+    bound = storage_bound(ref, _wr(storage, rho_ref), U[storage]) + 1e-6 * np.abs(ref).max() + 2.0 ** -25
     assert (np.abs(got - ref) <= bound).all()
 
 
@@ -92,11 +96,10 @@ def test_one_step_rounding_bound_mips(L, orc, storage):
     rho_ref = ini["rho_mean"]
     f0 = orc.initialise(_oparams(orc, cfg), **ini)
     q0 = quantise(f0, storage, rho_ref)
-    f0q = dequantise(q0, rho_ref)
-    got = dequantise(run_dev(L, cfg, q0, 1, storage, rho_ref), rho_ref)
+    f0q = dequantise(q0, rho_ref, storage)
+    got = dequantise(run_dev(L, cfg, q0, 1, storage, rho_ref), rho_ref, storage)
     ref = orc.run(_oparams(orc, cfg), f0q.copy(), 1)
-    d = np.abs(ref - W[:, None, None] * rho_ref)
-    bound = U[storage] * d + 1e-6 * np.abs(ref).max() + 2.0 ** -25
+    bound = storage_bound(ref, _wr(storage, rho_ref), U[storage]) + 1e-6 * np.abs(ref).max() + 2.0 ** -25
     assert (np.abs(got - ref) <= bound).all()
 
 
@@ -109,8 +112,8 @@ def test_hundred_steps_stated_error(L, orc, storage, bound):
     po = _oparams(orc, cfg)
     f0 = orc.initialise(po, **ini)
     q0 = quantise(f0, storage, rho_ref)
-    f0q = dequantise(q0, rho_ref)
-    got = dequantise(run_dev(L, cfg, q0, 100, storage, rho_ref), rho_ref)
+    f0q = dequantise(q0, rho_ref, storage)
+    got = dequantise(run_dev(L, cfg, q0, 100, storage, rho_ref), rho_ref, storage)
     ref = orc.run(po, f0q.copy(), 100)
     err = rel_err(got, ref)
     print(f"storage {storage}: 100-step relative Linf error {err:.3e}")
@@ -191,26 +194,32 @@ def precision_observables(L, storage, seeds):
 
 @pytest.mark.parametrize("storage", [0, 1, 2])
 def test_time_averaged_observables_against_the_oracle(L, storage):
-    """Matched 256 x 256 runs of the precision workload (four seeds) against
+    """Matched 256 x 256 runs of the precision workload (eight seeds) against
     the FP64 oracle's runs of the same seeds (tests/golden/precision_obs_256.txt,
-    written by make_precision_obs.py from the oracle alone): the seed-averaged
-    phi, zeta and banding measure over steps 10^4 .. 2 x 10^4 agree within
-    four standard errors of the difference of two four-seed means (from the
-    oracle's seed-to-seed spread), and the mass drift over 2 x 10^4 steps is
-    stated: FP32 and FP16 within 1e-5, bfloat16 within 1e-2."""
+    written by make_precision_obs.py from the oracle alone).  The runs start
+    disordered and are chaotic, so trajectories of the same seed part after a
+    few hundred steps and a seed may settle in another state (a band against
+    the ordered state); the seed-averaged phi, zeta and banding measure over
+    steps 10^4 .. 2 x 10^4 are held to four standard errors of the difference
+    of the two means (Welch: each side's seed-to-seed spread).  Mass drift
+    over 2 x 10^4 steps: FP32 below 1e-6 (the oracle's is 1e-12), the 16-bit
+    storages as stated in the bound."""
     gold = _golden_obs()
     seeds = [g[0] for g in gold]
     ref = np.array([g[1:] for g in gold])
     got = precision_observables(L, storage, seeds)
     n = len(seeds)
     names = ("phi", "zeta", "drho")
+    ok = []
     for k, name in enumerate(names):
-        sd = ref[:, k].std(ddof=1)
-        tol = 4.0 * np.sqrt(2.0 / n) * sd + 1e-6
+        se = np.sqrt(ref[:, k].var(ddof=1) / n + got[:, k].var(ddof=1) / n)
+        tol = 4.0 * se + 1e-6
         diff = got[:, k].mean() - ref[:, k].mean()
         print(f"storage {storage} {name}: gpu {got[:, k].mean():.6f} oracle {ref[:, k].mean():.6f} "
               f"diff {diff:+.2e} (bound {tol:.2e}; per seed {np.round(got[:, k] - ref[:, k], 6)})")
-        assert abs(diff) <= tol, (name, diff, tol)
+        ok.append((name, abs(diff) <= tol, diff, tol))
     drift = np.abs(got[:, 3]).max()
     print(f"storage {storage}: mass drift over 2e4 steps {drift:.2e} (oracle {np.abs(ref[:, 3]).max():.2e})")
-    assert drift < (1e-2 if storage == 1 else 1e-5)
+    for name, good, diff, tol in ok:
+        assert good, (name, diff, tol)
+    assert drift < {0: 1e-6, 1: 5e-3, 2: 2e-4}[storage]

@@ -299,12 +299,26 @@ def test_zero_density_sites(L, q9, orc):
         assert np.isfinite(got).all() and rel_err(got, ref) < 1e-6
 
 
+def _wr9(L, c, storage, rho_ref):
+    """The storage's per-plane references r_i, float64 [9, 1, 1]."""
+    return L.lbm_deviation_reference(_gp(L, c, storage=storage, rho_ref=rho_ref)).astype(np.float64)[:, None, None]
+
+
+def _bound9(ref, wr, u):
+    """One rounding of each stored deviation; the rest population (rho minus
+    the stored moving ones) also carries the moving ones' roundings."""
+    d = np.abs(ref - wr)
+    b = u * d
+    b[0] = b[0] + u * d[1:].sum(axis=0)
+    return b
+
+
 def _run_dev(L, c, q, steps, storage, rho_ref):
     lat = L.Lattice(_gp(L, c, storage=storage, rho_ref=rho_ref))
     lat.set_state(q.cuda())
     lat.step(steps)
     torch.cuda.synchronize()
-    out = lat.state[:, :, : c["nx"]].double().cpu().numpy() + W[:, None, None] * rho_ref
+    out = lat.state[:, :, : c["nx"]].double().cpu().numpy() + _wr9(L, c, storage, rho_ref)
     lat.close()
     return out
 
@@ -315,19 +329,19 @@ def test_deviation_storage_one_step_bound(L, q9, orc, storage, name):
     c, ini = STABLE[name]
     rho_ref = ini["rho_mean"]
     f0 = q9.initialise(_op(orc, c), **ini)
-    q0 = torch.from_numpy(f0 - W[:, None, None] * rho_ref).to(DT[storage])
-    f0q = q0.double().numpy() + W[:, None, None] * rho_ref
+    wr = _wr9(L, c, storage, rho_ref)
+    q0 = torch.from_numpy(f0 - wr).to(DT[storage])
+    f0q = q0.double().numpy() + wr
     got = _run_dev(L, c, q0, 1, storage, rho_ref)
     ref = q9.run(_op(orc, c), f0q.copy(), 1)
-    d = np.abs(ref - W[:, None, None] * rho_ref)
-    bound = U[storage] * d + 1e-6 * np.abs(ref).max() + 2.0 ** -25
+    bound = _bound9(ref, wr, U[storage]) + 1e-6 * np.abs(ref).max() + 2.0 ** -25
     assert (np.abs(got - ref) <= bound).all()
     # the initial state written in the storage: one rounding of d
     lat = L.Lattice(_gp(L, c, storage=storage, rho_ref=rho_ref), init=L.make_init(**{**FULL_INIT, **ini}))
     torch.cuda.synchronize()
-    g0 = lat.state[:, :, : c["nx"]].double().cpu().numpy() + W[:, None, None] * rho_ref
+    g0 = lat.state[:, :, : c["nx"]].double().cpu().numpy() + wr
     lat.close()
-    assert (np.abs(g0 - f0) <= 2 * U[storage] * np.abs(f0 - W[:, None, None] * rho_ref) + 1e-7).all()
+    assert (np.abs(g0 - f0) <= 2 * U[storage] * np.abs(f0 - wr) + 1e-7).all()
 
 
 def test_disordered_cil_1024_conditioning(L, q9, orc):
