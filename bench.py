@@ -332,7 +332,10 @@ def roofline_two_step(sites, per_launch_s, kernel, rows, total_sites=None):
          "kernel": kernel, "avg_launch_us": round(per_launch_s * 1e6, 3),
          "valu_per_site_update": vpu, "valu_per_site_update_source": vsrc, "site_updates_per_launch": round(2 * sites),
          "hbm": {"achieved": round(hbm, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                 "frac": round(hbm / HBM_PEAK_GBPS, 4), "bytes_per_launch": BYTES_PER_SITE[0] * sites}}
+                 "frac": round(hbm / HBM_PEAK_GBPS, 4), "bytes_per_launch": BYTES_PER_SITE[0] * sites},
+        "state_residency": ("Infinity Cache: lattice groups of at most 240 MiB keep their two buffers in the "
+                            "256 MiB cache across a chunk's launches, so these bytes are not HBM traffic; the "
+                            "step's HBM roofline is the line's hbm_roofline (4096^2, one step per launch)")}
     c = measured_traffic(f"counters_k_batch_step2_{rows}_cil_5x1024.json")
     if c is not None and c.get("sites") == (total_sites or sites):
         r["traffic"] = round(c["traffic_bytes_per_launch"] / per_launch_s / 1e9, 1)
@@ -440,7 +443,7 @@ def main():
         launches = args.steps * len(cfgs)
         kernel = {"q9_cil4096": f"k_q9_step_local<CIL,{st},unit-tau,noisy>",
                   "q9_mips4096": f"k_q9_step_mips<{st},noisy>",
-                  "mips4096": f"k_step_mips<{st},noisy>"}.get(args.workload,
+                  "mips4096": f"k_step_mips<{st},noisy,16,8>"}.get(args.workload,
                                                                      f"k_step_local<CIL,{st},unit-tau,noisy>")
     wall = time.perf_counter() - t_wall
     per_launch = ms / 1e3 / launches
@@ -478,6 +481,8 @@ def main():
 
     if args.workload == "mips4096" and args.storage == 0:
         attach_traffic(line["roofline"], "counters_k_step_mips_4096.json", STEP_SOURCES, sites, per_launch)
+    if args.workload == "cil4096" and args.storage == 0 and mode == "single":
+        attach_traffic(line["roofline"], "counters_k_step_local_cil_4096.json", STEP_SOURCES, sites, per_launch)
 
     if mode == "batch" and args.workload == "cil1024x5" and args.storage == 0 and rows < 8:
         c = measured_traffic(f"counters_k_batch_step_{rows}_cil_5x1024.json")
@@ -517,10 +522,21 @@ def main():
                  "avg_launch_us": r["avg_launch_us"]}
             if st == 0:
                 f32 = per
+                # the HBM roofline of the step: this lattice's state (940 MB)
+                # streams from HBM every launch, unlike the headline batch's
+                # lattice groups, which stay in the Infinity Cache
+                attach_traffic(r, "counters_k_step_local_cil_4096.json", STEP_SOURCES, nbig, per)
+                line["hbm_roofline"] = {
+                    "workload": "CIL 4096x4096 FP32, lbm_step, one step per launch", "bound": "hbm",
+                    "kernel": r["kernel"], "achieved": r["achieved"], "peak": r["peak"], "unit": r["unit"],
+                    "frac": r["frac"], "traffic": r["traffic"],
+                    "traffic_vs_algorithmic": r.get("traffic_vs_algorithmic"),
+                    "bytes_per_site": r["bytes_per_site"], "avg_launch_us": r["avg_launch_us"],
+                    "profile": "profiles/k_step_local_cil_4096.md"}
             else:
                 v["speedup_vs_f32"] = round(f32 / per, 3)
-                v["stated_error_vs_fp64"] = {"bf16_dev": "100-step rel Linf 1.9e-3, mass drift 2.1e-3 / 1e4 steps",
-                                             "f16_dev": "100-step rel Linf 2.4e-4, mass drift 2.8e-5 / 1e4 steps"}[name]
+                v["stated_error_vs_fp64"] = {"bf16_dev": "100-step rel Linf 2.9e-3, mass drift 1.7e-3 / 2e4 steps",
+                                             "f16_dev": "100-step rel Linf 3.4e-4, mass drift 4.9e-5 / 2e4 steps"}[name]
             var["cil4096_" + name] = v
         # MIPS (density-dependent motility, LDS density halo): the 64 x 64
         # configuration (1000 steps) and the same parameters at 4096^2
@@ -531,9 +547,11 @@ def main():
                                     "note": "4,096 sites: one launch per step, launch-bound"}
         mbig = dict(mcfg, nx=4096, ny=4096)
         msb, _ = time_single(L, torch, [mbig], 100, 10)
-        rm = roofline(0, 4096 * 4096, msb / 1e3 / 100, "k_step_mips<F32,noisy>")
+        rm = roofline(0, 4096 * 4096, msb / 1e3 / 100, "k_step_mips<F32,noisy,16,8>")
+        attach_traffic(rm, "counters_k_step_mips_4096.json", STEP_SOURCES, 4096 * 4096, msb / 1e3 / 100)
         var["mips4096_f32"] = {"MLUPS": round(4096 * 4096 * 100 / (msb / 1e3) / 1e6, 1), "GBps": rm["achieved"],
-                               "frac_hbm": rm["frac"], "avg_launch_us": rm["avg_launch_us"]}
+                               "frac_hbm": rm["frac"], "avg_launch_us": rm["avg_launch_us"],
+                               "traffic_GBps": rm["traffic"], "traffic_vs_algorithmic": rm.get("traffic_vs_algorithmic")}
         # the square lattice (D2Q9, 72 B per site-update in FP32): CIL in the
         # three storages and MIPS at 4096^2, one launch per step
         q9c = [SI.q9_cil_4096()]

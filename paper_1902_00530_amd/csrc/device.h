@@ -492,17 +492,18 @@ struct BufIO<_Float16> {
 // the batched MIPS kernels both run this body.
 // ---------------------------------------------------------------------------
 constexpr int kMipsRows = 16;
+constexpr int kMipsWaves = 8;
 constexpr int mips_tile_lds(int rows) { return (rows + 2) * 66; }
 
-template <int S, int F, int ROWS = kMipsRows>
+template <int S, int F, int ROWS = kMipsRows, int NW = 4>
 __device__ __forceinline__ void mips_tile_step(__amdgpu_buffer_rsrc_t rs, __amdgpu_buffer_rsrc_t rd,
                                                const StepArgs &a, int x0, int y0, uint32_t t_lo, uint32_t t_hi,
                                                float *srho)
 {
     using T = typename Store<S>::T;
-    static_assert(ROWS == 4 || ROWS == 16, "four waves own the rows; waves 0-2 cover the ring");
-    constexpr int W = 66, H = ROWS + 2, RW = ROWS / 4;  // RW rows per wave
-    constexpr int kRing = 2 * W + 2 * ROWS;             // 164 or 140
+    constexpr int W = 66, H = ROWS + 2, RW = ROWS / NW;  // RW rows per wave
+    constexpr int kRing = 2 * W + 2 * ROWS;
+    static_assert(NW % 2 == 0 && ROWS % NW == 0 && kRing <= 64 * NW, "NW waves own the rows and cover the ring");
     const uint32_t plane = (uint32_t)a.plane, P = (uint32_t)a.pitch, nx = (uint32_t)a.nx;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -517,7 +518,7 @@ __device__ __forceinline__ void mips_tile_step(__amdgpu_buffer_rsrc_t rs, __amdg
     float f[RW][7];
 #pragma unroll
     for (int k = 0; k < RW; ++k) {
-        const int y = y0 + wv + 4 * k;
+        const int y = y0 + wv + NW * k;
         if (interior) {
             const uint32_t p = (uint32_t)y & 1u;
             const uint32_t c = (uint32_t)y * P + (uint32_t)x0;  // offset of (x0, y)
@@ -552,7 +553,7 @@ __device__ __forceinline__ void mips_tile_step(__amdgpu_buffer_rsrc_t rs, __amdg
     for (int k = 0; k < RW; ++k) {
         float jx, jy;
         site_moments(f[k], rho[k], jx, jy);
-        srho[(wv + 4 * k + 1) * W + lane + 1] = rho[k];
+        srho[(wv + NW * k + 1) * W + lane + 1] = rho[k];
     }
     __syncthreads();
     // collisions; row r of the tile has parity r & 1 = wv & 1 (y0 is even)
@@ -560,7 +561,7 @@ __device__ __forceinline__ void mips_tile_step(__amdgpu_buffer_rsrc_t rs, __amdg
     const int x = x0 + lane;
 #pragma unroll
     for (int k = 0; k < RW; ++k) {
-        const int r = wv + 4 * k, y = y0 + r;
+        const int r = wv + NW * k, y = y0 + r;
         if (x >= a.nx || y >= a.ny)
             continue;
         const int cx = lane + 1, cy = r + 1;

@@ -181,8 +181,8 @@ __global__ __launch_bounds__(256) void k_step_mips64(const typename Store<S>::T 
 // arithmetic is the same).  Offsets are 32-bit (7 planes below 2^30
 // elements); larger lattices take k_step_mips64.
 // ---------------------------------------------------------------------------
-template <int S, int F, int ROWS>
-__global__ __launch_bounds__(256) void k_step_mips(const typename Store<S>::T *__restrict__ src,
+template <int S, int F, int ROWS, int NW = 4>
+__global__ __launch_bounds__(64 * NW) void k_step_mips(const typename Store<S>::T *__restrict__ src,
                                                    typename Store<S>::T *__restrict__ dst, StepArgs a,
                                                    StepClock *__restrict__ clk, int slot)
 {
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256) void k_step_mips(const typename Store<S>::T *_
     if (y0 >= a.ny)  // padding tile rows of the last group: the whole block
         return;
     const uint32_t bytes = 7u * (uint32_t)a.plane * (uint32_t)sizeof(T);  // < 2^32: 7 planes < 2^30 elements
-    mips_tile_step<S, F, ROWS>(buffer_rsrc(src, bytes), buffer_rsrc(dst, bytes), a, x0, y0, t_lo, t_hi, srho);
+    mips_tile_step<S, F, ROWS, NW>(buffer_rsrc(src, bytes), buffer_rsrc(dst, bytes), a, x0, y0, t_lo, t_hi, srho);
     clock_advance(clk, slot, tt);
 }
 
@@ -230,7 +230,8 @@ static hipError_t launch_step_sf(const lbm_params &p, const StepArgs &a, const v
                 hipLaunchKernelGGL((k_step_mips<S, F, 4>), grd, dim3(256), 0, s, in, out, a, clk, slot);
             } else {
                 dim3 grd(8u * (unsigned)ntx, (unsigned)((nty + 7) / 8));
-                hipLaunchKernelGGL((k_step_mips<S, F, kMipsRows>), grd, dim3(256), 0, s, in, out, a, clk, slot);
+                hipLaunchKernelGGL((k_step_mips<S, F, kMipsRows, kMipsWaves>), grd, dim3(64 * kMipsWaves), 0, s, in,
+                                   out, a, clk, slot);
             }
         } else {
             dim3 blk(kMipsTX, kMipsTY), grd((p.nx + kMipsTX - 1) / kMipsTX, (p.ny + kMipsTY - 1) / kMipsTY);
