@@ -22,7 +22,8 @@
  *    e_3: (x-1+p, y+1); e_4: (x-1, y); e_5: (x-1+p, y-1); e_6: (x+p, y-1),
  *    p = y mod 2, all indices periodic.
  *  - A population buffer is [7][ny][pitch] elements of the storage type
- *    (plane i, row y, column x), pitch >= nx elements.  The state kept
+ *    (plane i, row y, column x), pitch >= nx elements (LBM_BF16_DEV_R32: a
+ *    float32 plane, then six 16-bit planes).  The state kept
  *    between steps is the population after the last step of the algorithm
  *    (the negative correction); a step streams it (population i of site r
  *    comes from r - e_i), then collides.  An initial state f^SS is therefore
@@ -101,10 +102,19 @@ extern "C" {
 #define LBM_F32 0      /* float32 populations */
 #define LBM_BF16_DEV 1 /* bfloat16 deviations d_i = f_i - r_i (round to nearest even) */
 #define LBM_F16_DEV 2  /* IEEE half deviations d_i = f_i - r_i (round to nearest even) */
+#define LBM_BF16_DEV_R32 3 /* bfloat16 deviations of the six moving populations, float32 rest population */
 /* The reference r_i of plane i is w_i rho_ref rounded to float, then to the
  * storage format, so that f_i = 0 is stored exactly (lbm_deviation_reference
  * returns the values); a population is read back as float(d_i) + r_i in
- * float32. */
+ * float32.
+ * LBM_BF16_DEV_R32 (D2Q7 only): the buffer is the float32 rest plane
+ * [ny][pitch] followed by the six bfloat16 deviation planes [6][ny][pitch],
+ * 16 bytes per site (the size of [8][ny][pitch] 16-bit elements, the rest
+ * plane taking the room of two); r_0 = 0 and f_0 is stored as is.  Each
+ * step stores the rest population as the site's density minus its six
+ * moving populations as they are stored (kept >= 0), so a site keeps its
+ * mass to one float32 rounding, where the bfloat16 rest deviation of
+ * LBM_BF16_DEV rounds it at every step. */
 
 /* Initial states (appendix "CIL Model: General notes"). */
 #define LBM_INIT_NONE 0        /* caller has filled the first buffer */
@@ -114,7 +124,7 @@ extern "C" {
 typedef struct lbm_params {
     int32_t nx, ny;    /* lattice size; ny <= 65535; nx * ny < 2^32; ny even on D2Q7 */
     int32_t model;     /* LBM_PASSIVE / LBM_MIPS / LBM_CIL */
-    int32_t storage;   /* LBM_F32 / LBM_BF16_DEV / LBM_F16_DEV */
+    int32_t storage;   /* LBM_F32 / LBM_BF16_DEV / LBM_F16_DEV / LBM_BF16_DEV_R32 */
     double tau;        /* relaxation time, >= 1 (appendix "Negative Correction"); +inf = streaming only */
     double sigma;      /* noise half-width, >= 0 */
     double A, B;       /* CIL speed law */
@@ -335,7 +345,7 @@ int32_t lbm_sweep_groups(const lbm_params *ps, int32_t n);
 
 /* Run a batch.  ps[n]: per-lattice parameters; every lattice uses the same
  * velocity set (D2Q7 or D2Q9), the same storage (F32; on D2Q7 also
- * BF16_DEV or F16_DEV, each step rounding its results into the storage as
+ * BF16_DEV, F16_DEV or BF16_DEV_R32, each step rounding its results into the storage as
  * lbm_step does), the same model (CIL, MIPS or passive), and agrees on
  * tau == 1 and on sigma == 0; nx*ny*Q < 2^30 (Q = 7 or 9 populations),
  * ny <= 32760.  bufs[2n]: caller-owned device buffers [Q][ny][nx] of the

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ENONFINITE, LBM_EUNSUPPORTED, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_PASSIVE, LBM_MIPS, LBM_CIL = 0, 1, 2
-LBM_F32, LBM_BF16_DEV, LBM_F16_DEV = 0, 1, 2
+LBM_F32, LBM_BF16_DEV, LBM_F16_DEV, LBM_BF16_DEV_R32 = 0, 1, 2, 3
 LBM_D2Q7, LBM_D2Q9 = 0, 1
 LBM_TILE_RESIDENT = 1024  # tile_rows of the LDS-resident batch form (<= 4096 sites on D2Q7, 3072 on D2Q9)
 LBM_INIT_NONE, LBM_INIT_UNIFORM_DIR, LBM_INIT_GAUSS_DIR = 0, 1, 2
@@ -368,7 +368,7 @@ class Batch:
         import torch
         self.n = len(params_list)
         self.params = (lbm_params * self.n)(*params_list)
-        self.buffers = [torch.zeros((n_populations(p), p.ny, p.nx), dtype=storage_dtype(p.storage), device=device)
+        self.buffers = [torch.zeros((storage_planes(p), p.ny, p.nx), dtype=storage_dtype(p.storage), device=device)
                         for p in params_list for _ in range(2)]
         self.bufs = (ctypes.c_void_p * (2 * self.n))(*[b.data_ptr() for b in self.buffers])
         # device arrays of the n buffer pointers of each parity (for the
@@ -517,7 +517,17 @@ def make_init(mode=LBM_INIT_UNIFORM_DIR, rho_mean=1.0, rho_spread=0.1, angle_std
 
 def storage_dtype(storage):
     import torch
-    return {LBM_F32: torch.float32, LBM_BF16_DEV: torch.bfloat16, LBM_F16_DEV: torch.float16}[storage]
+    # LBM_BF16_DEV_R32 buffers mix a float32 plane and bfloat16 planes: held
+    # as raw 16-bit words (int16), so that comparisons are bitwise
+    return {LBM_F32: torch.float32, LBM_BF16_DEV: torch.bfloat16, LBM_F16_DEV: torch.float16,
+            LBM_BF16_DEV_R32: torch.int16}[storage]
+
+
+def storage_planes(params):
+    """Planes of storage_dtype in a population buffer: Q, or 8 for
+    LBM_BF16_DEV_R32 (its float32 rest plane takes the room of planes 0 and 1
+    as one [ny][pitch] float32 array, the six bfloat16 planes follow)."""
+    return 8 if params.storage == LBM_BF16_DEV_R32 else n_populations(params)
 
 
 class Lattice:
@@ -529,8 +539,11 @@ class Lattice:
         import torch
         self.params = params
         self.pitch = int(pitch or params.nx)
+        if params.storage == LBM_BF16_DEV_R32 and self.pitch != params.nx:
+            # state views slice planes by column, which the float32 rest plane's bytes do not follow
+            raise ValueError("LBM_BF16_DEV_R32 lattices take pitch == nx in this binding")
         dt = storage_dtype(params.storage)
-        q = n_populations(params)
+        q = storage_planes(params)
         self.buffers = [torch.zeros((q, params.ny, self.pitch), dtype=dt, device=device) for _ in range(2)]
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         nws = lbm_workspace_bytes(params, self.pitch)

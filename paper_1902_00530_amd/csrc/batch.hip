@@ -93,15 +93,14 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchTile *__restrict_
     const int y = tl.ty * blockDim.y + threadIdx.y;
     if (x >= a.nx || y >= a.ny)
         return;
-    using T = typename Store<ST>::T;
     const uint32_t plane = (uint32_t)a.plane;
-    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], 7u * plane * (uint32_t)sizeof(T));
-    const __amdgpu_buffer_rsrc_t dst = buffer_rsrc(L.buf[par ^ 1], 7u * plane * (uint32_t)sizeof(T));
+    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], (uint32_t)Planes<ST>::bytes(plane));
+    const __amdgpu_buffer_rsrc_t dst = buffer_rsrc(L.buf[par ^ 1], (uint32_t)Planes<ST>::bytes(plane));
     const PullSources32 g_src = pull_sources32(a, x, y);
     float f[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        f[i] = Store<ST>::widen(BufIO<T>::load(src, g_src.idx[i], i * plane), i == 0 ? a.wr0 : a.wr1);
+        f[i] = Planes<ST>::load(src, g_src.idx[i], 0u, i, plane, a);
     float rho, jx, jy, ux, uy;
     site_moments(f, rho, jx, jy);
     local_ustar<M>(a, rho, jx, jy, ux, uy);
@@ -110,7 +109,7 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchTile *__restrict_
     site_collide<F, ST>(a, f, rho, ux, uy, own, (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32));
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        BufIO<T>::store(dst, own, i * plane, Store<ST>::narrow(f[i], i == 0 ? a.wr0 : a.wr1));
+        Planes<ST>::store(dst, own, 0u, i, plane, f[i], a);
 }
 
 // MIPS over a list of 64 x ROWS tiles (the tile body of the single-lattice
@@ -129,7 +128,7 @@ __global__ __launch_bounds__(256) void k_batch_step_mips(const BatchTile *__rest
     const int x0 = tl.tx * 64, y0 = tl.ty * ROWS;
     if (x0 >= a.nx || y0 >= a.ny)  // whole-block exit, before the barrier
         return;
-    const uint32_t bytes = 7u * (uint32_t)a.plane * (uint32_t)sizeof(typename Store<ST>::T);
+    const uint32_t bytes = (uint32_t)Planes<ST>::bytes(a.plane);
     mips_tile_step<ST, F, ROWS>(buffer_rsrc(L.buf[par], bytes), buffer_rsrc(L.buf[par ^ 1], bytes), a, x0, y0,
                             (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32), srho);
 }
@@ -163,12 +162,19 @@ __global__ __launch_bounds__(kResidentLanes) void k_batch_resident(const LatDesc
     const int tid = threadIdx.x;
     float *rho_l = st + 7 * S;
     // the state is kept in LDS as stored (16-bit storages: the stored bits),
-    // so every step rounds and widens exactly as lbm_step's loads and stores
+    // so every step rounds and widens exactly as lbm_step's loads and stores;
+    // with a float32 rest plane (kBf16R32) as the values the storage gives
+    // back, in float32
+    constexpr bool kFloatLds = ST == kBf16R32;
     T *sv = (T *)st;
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        for (int e = tid; e < S; e += kResidentLanes)
-            sv[i * S + e] = src[(int64_t)i * a.plane + e];
+        for (int e = tid; e < S; e += kResidentLanes) {
+            if constexpr (kFloatLds)
+                st[i * S + e] = Planes<ST>::ld(src, e, i, a.plane, a);
+            else
+                sv[i * S + e] = src[(int64_t)i * a.plane + e];
+        }
     // this lane's sites s = tid + j * 1024 and their coordinates
     int sx[kResidentPer], sy[kResidentPer];
 #pragma unroll
@@ -189,8 +195,12 @@ __global__ __launch_bounds__(kResidentLanes) void k_batch_resident(const LatDesc
             if (s < S) {
                 const PullSources32 q = pull_sources32(a, sx[j], sy[j]);
 #pragma unroll
-                for (int i = 0; i < 7; ++i)
-                    f[j][i] = Store<ST>::widen(sv[i * S + (int)q.idx[i]], i == 0 ? a.wr0 : a.wr1);
+                for (int i = 0; i < 7; ++i) {
+                    if constexpr (kFloatLds)
+                        f[j][i] = st[i * S + (int)q.idx[i]];
+                    else
+                        f[j][i] = Store<ST>::widen(sv[i * S + (int)q.idx[i]], i == 0 ? a.wr0 : a.wr1);
+                }
                 site_moments(f[j], rho[j], jx[j], jy[j]);
                 if (M == kMips)
                     rho_l[s] = rho[j];
@@ -219,16 +229,24 @@ __global__ __launch_bounds__(kResidentLanes) void k_batch_resident(const LatDesc
                 }
                 site_collide<F, ST>(a, f[j], rho[j], ux, uy, (uint32_t)s, tlo, thi);
 #pragma unroll
-                for (int i = 0; i < 7; ++i)
-                    sv[i * S + s] = Store<ST>::narrow(f[j][i], i == 0 ? a.wr0 : a.wr1);
+                for (int i = 0; i < 7; ++i) {
+                    if constexpr (kFloatLds)
+                        st[i * S + s] = Planes<ST>::round(f[j][i], i, a);
+                    else
+                        sv[i * S + s] = Store<ST>::narrow(f[j][i], i == 0 ? a.wr0 : a.wr1);
+                }
             }
         }
         __syncthreads();  // the step's writes precede the next step's pulls
     }
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        for (int e = tid; e < S; e += kResidentLanes)
-            dst[(int64_t)i * a.plane + e] = sv[i * S + e];
+        for (int e = tid; e < S; e += kResidentLanes) {
+            if constexpr (kFloatLds)
+                Planes<ST>::st(dst, e, i, a.plane, st[i * S + e], a);
+            else
+                dst[(int64_t)i * a.plane + e] = sv[i * S + e];
+        }
 }
 
 // The same for the square lattice (D2Q9): nine planes and the densities, at
@@ -552,13 +570,10 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
     const int x0 = tl.tx * 64, y0 = tl.ty * TY;
     if (x0 >= a.nx || y0 >= a.ny)  // whole-block exit, before the barrier
         return;
-    using T = typename Store<ST>::T;
     const uint32_t plane = (uint32_t)a.plane;
-    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], 7u * plane * (uint32_t)sizeof(T));
-    const __amdgpu_buffer_rsrc_t dst = buffer_rsrc(L.buf[par ^ 1], 7u * plane * (uint32_t)sizeof(T));
-    auto ld = [&](uint32_t elem, uint32_t first, int i) {
-        return Store<ST>::widen(BufIO<T>::load(src, elem, first), i == 0 ? a.wr0 : a.wr1);
-    };
+    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], (uint32_t)Planes<ST>::bytes(plane));
+    const __amdgpu_buffer_rsrc_t dst = buffer_rsrc(L.buf[par ^ 1], (uint32_t)Planes<ST>::bytes(plane));
+    auto ld = [&](uint32_t elem, uint32_t first, int i) { return Planes<ST>::load(src, elem, first, i, plane, a); };
     const uint32_t nx = (uint32_t)a.nx;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
@@ -581,19 +596,19 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
             const uint32_t p = (uint32_t)yg & 1u;
             const uint32_t c = (uint32_t)yg * nx + (uint32_t)x0;  // offset of (x0, yg)
             g[0] = ld(lane, c, 0);
-            g[1] = ld(lane, plane + c - 1u, 1);
-            g[2] = ld(lane, 2u * plane + c - nx - 1u + p, 2);
-            g[3] = ld(lane, 3u * plane + c - nx + p, 3);
-            g[4] = ld(lane, 4u * plane + c + 1u, 4);
-            g[5] = ld(lane, 5u * plane + c + nx + p, 5);
-            g[6] = ld(lane, 6u * plane + c + nx - 1u + p, 6);
+            g[1] = ld(lane, c - 1u, 1);
+            g[2] = ld(lane, c - nx - 1u + p, 2);
+            g[3] = ld(lane, c - nx + p, 3);
+            g[4] = ld(lane, c + 1u, 4);
+            g[5] = ld(lane, c + nx + p, 5);
+            g[6] = ld(lane, c + nx - 1u + p, 6);
             st = c + (uint32_t)lane;
         } else {
             const int xg = wrap_coord(x0 + lane, a.nx), yg = wrap_coord(y0 - 1 + ly, a.ny);
             const PullSources32 q = pull_sources32(a, xg, yg);
 #pragma unroll
             for (int i = 0; i < 7; ++i)
-                g[i] = ld(q.idx[i], i * plane, i);
+                g[i] = ld(q.idx[i], 0u, i);
             st = q.idx[0];  // pitch nx: own offset = site index
         }
     };
@@ -605,7 +620,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
 #pragma unroll
         for (int i = 0; i < 7; ++i)
             if (ML::kept(i, lx, ly))  // the value a store and the next step's load would give
-                mid[ML::at(i, lx, ly)] = Store<ST>::round(g[i], i == 0 ? a.wr0 : a.wr1);
+                mid[ML::at(i, lx, ly)] = Planes<ST>::round(g[i], i, a);
     };
     // slots 0 .. NR-2: rows of every wave
     if (interior) {
@@ -632,7 +647,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
             const PullSources32 q = pull_sources32(a, xg, yg);
 #pragma unroll
             for (int i = 0; i < 7; ++i)
-                f[NR - 1][i] = ld(q.idx[i], i * plane, i);
+                f[NR - 1][i] = ld(q.idx[i], 0u, i);
             site[NR - 1] = q.idx[0];
         }
     }
@@ -663,7 +678,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
         site_collide<F, ST>(a, f, rho, ux, uy, row + (uint32_t)lane, tb_lo, tb_hi);
 #pragma unroll
         for (int i = 0; i < 7; ++i)
-            BufIO<T>::store(dst, lane, i * plane + row, Store<ST>::narrow(f[i], i == 0 ? a.wr0 : a.wr1));
+            Planes<ST>::store(dst, lane, row, i, plane, f[i], a);
     };
     if (interior) {
         for (int r = wv; r < TY; r += NW)
@@ -711,12 +726,11 @@ __global__ __launch_bounds__(256) void k_batch_moments(const MomTile *__restrict
             bool finite = true;
             float rho, jx, jy;
             if constexpr (Q == 7) {
-                using T = typename Store<ST>::T;
-                const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], 7u * plane * (uint32_t)sizeof(T));
+                const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], (uint32_t)Planes<ST>::bytes(plane));
                 const PullSources32 g = pull_sources32(a, x, y);
 #pragma unroll
                 for (int i = 0; i < 7; ++i)
-                    f[i] = Store<ST>::widen(BufIO<T>::load(src, g.idx[i], i * plane), i == 0 ? a.wr0 : a.wr1);
+                    f[i] = Planes<ST>::load(src, g.idx[i], 0u, i, plane, a);
                 site_moments(f, rho, jx, jy);
             } else {
                 const float *src = (const float *)L.buf[par];
@@ -856,9 +870,13 @@ __global__ __launch_bounds__(256) void k_batch_add_density(const MomTile *__rest
     for (int y = m.cy * kMomRows; y < ye; ++y)
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const float wr = Q == 7 ? (i == 0 ? a.wr0 : a.wr1) : 0.0f;
-            T *p = f + (size_t)i * (size_t)a.plane + (size_t)y * (size_t)a.pitch + x;
-            *p = Store<ST>::narrow(Store<ST>::widen(*p, wr) + add, wr);
+            const int64_t e = (int64_t)y * a.pitch + x;
+            if constexpr (Q == 7) {
+                Planes<ST>::st(f, e, i, a.plane, Planes<ST>::ld(f, e, i, a.plane, a) + add, a);
+            } else {
+                T *p = f + (size_t)i * (size_t)a.plane + (size_t)e;
+                *p = Store<ST>::narrow(Store<ST>::widen(*p, 0.0f) + add, 0.0f);
+            }
         }
 }
 
@@ -941,8 +959,11 @@ static std::vector<int> cache_groups(const lbm_params *ps, int n)
     std::vector<uint64_t> b(n);
     uint64_t total = 0;
     for (int l = 0; l < n; ++l) {
-        b[l] = 2ull * (ps[l].lattice == LBM_D2Q9 ? 9ull : 7ull) * (ps[l].storage == LBM_F32 ? 4ull : 2ull) *
-               (uint64_t)ps[l].nx * ps[l].ny;
+        const uint64_t per_site = ps[l].lattice == LBM_D2Q9 ? (ps[l].storage == LBM_F32 ? 36ull : 18ull)
+                                  : ps[l].storage == LBM_F32        ? 28ull
+                                  : ps[l].storage == LBM_BF16_DEV_R32 ? 16ull
+                                                                      : 14ull;
+        b[l] = 2ull * per_site * (uint64_t)ps[l].nx * ps[l].ny;
         total += b[l];
     }
     const uint64_t ng = (total + kCacheGroupBytes - 1) / kCacheGroupBytes;
@@ -1052,6 +1073,7 @@ static hipError_t with_storage(int storage, Fn &&fn)
     case kF32: return fn(IntTag<kF32>{});
     case kBf16Dev: return fn(IntTag<kBf16Dev>{});
     case kF16Dev: return fn(IntTag<kF16Dev>{});
+    case kBf16R32: return fn(IntTag<kBf16R32>{});
     }
     return hipErrorInvalidValue;
 }

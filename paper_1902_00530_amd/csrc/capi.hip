@@ -46,8 +46,10 @@ int32_t validate_params(const lbm_params *p, int64_t pitch)
         return fail(LBM_EINVAL, "pitch must be >= nx");
     if (p->model < LBM_PASSIVE || p->model > LBM_CIL)
         return fail(LBM_EINVAL, "unknown model");
-    if (p->storage < LBM_F32 || p->storage > LBM_F16_DEV)
+    if (p->storage < LBM_F32 || p->storage > LBM_BF16_DEV_R32)
         return fail(LBM_EINVAL, "unknown storage");
+    if (p->storage == LBM_BF16_DEV_R32 && p->lattice == LBM_D2Q9)
+        return fail(LBM_EUNSUPPORTED, "the float32 rest plane storage takes D2Q7 lattices");
     if (!(p->tau >= 1.0))
         return fail(LBM_EINVAL, "tau must be >= 1 (or +inf for streaming only)");
     if (!finite_nonneg(p->sigma))
@@ -99,9 +101,11 @@ StepArgs make_step_args(const lbm_params &p, int64_t pitch)
     a.inv_rho_star = p.model == LBM_MIPS ? (float)(1.0 / p.rho_star) : 1.0f;
     a.u_max = (float)p.u_max;
     const double rr = p.storage == LBM_F32 ? 0.0 : p.rho_ref;
-    a.wr0 = storage_reference(q9 ? 4.0 * rr / 9.0 : 0.5 * rr, p.storage);
-    a.wr1 = storage_reference(q9 ? rr / 9.0 : rr / 12.0, p.storage);
-    a.wr2 = storage_reference(q9 ? rr / 36.0 : rr / 12.0, p.storage);
+    // the float32 rest plane of LBM_BF16_DEV_R32 holds f_0 itself
+    const int moving = p.storage == LBM_BF16_DEV_R32 ? LBM_BF16_DEV : p.storage;
+    a.wr0 = p.storage == LBM_BF16_DEV_R32 ? 0.0f : storage_reference(q9 ? 4.0 * rr / 9.0 : 0.5 * rr, p.storage);
+    a.wr1 = storage_reference(q9 ? rr / 9.0 : rr / 12.0, moving);
+    a.wr2 = storage_reference(q9 ? rr / 36.0 : rr / 12.0, moving);
     a.key0 = (uint32_t)(p.seed & 0xffffffffu);
     a.key1 = (uint32_t)(p.seed >> 32);
     a.noisy = p.sigma != 0.0;

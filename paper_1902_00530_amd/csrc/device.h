@@ -11,7 +11,7 @@
 namespace lbm {
 
 enum Model : int { kPassive = 0, kMips = 1, kCil = 2 };
-enum Storage : int { kF32 = 0, kBf16Dev = 1, kF16Dev = 2 };
+enum Storage : int { kF32 = 0, kBf16Dev = 1, kF16Dev = 2, kBf16R32 = 3 };
 
 // Kernel-side copy of the parameters, with derived constants precomputed on
 // the host in double and rounded once to float.
@@ -154,6 +154,14 @@ struct Store<kF16Dev> {
     __device__ __forceinline__ static float round(float v, float wr) { return widen(narrow(v, wr), wr); }
 };
 
+// bfloat16 deviations of the six moving populations with the rest population
+// in float32: the buffer is the float32 rest plane followed by six bfloat16
+// planes; every access goes through Planes<kBf16R32> (below).
+template <>
+struct Store<kBf16R32> {
+    using T = uint16_t;
+};
+
 // ---------------------------------------------------------------------------
 // Per-site arithmetic.
 // ---------------------------------------------------------------------------
@@ -262,7 +270,8 @@ enum StepFlags : int { kUnitTau = 1, kNoisy = 2 };
 // every site.  In float32 storage that value enters the correction as the
 // rest population; in the 16-bit storages (S) it is taken from the moving
 // populations as they will be stored, at sites where no rule fired (where
-// one fires, the rescale to rho sets the mass).  tau = +inf keeps the
+// one fires, the rescale to rho sets the mass); with a float32 rest plane
+// (kBf16R32) at every site, after the correction.  tau = +inf keeps the
 // populations as they are.
 template <int F, int S = kF32>
 __device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], float rho, float ux, float uy,
@@ -283,7 +292,7 @@ __device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], floa
     if (F & kNoisy)
         site_add_noise(a, site, t_lo, t_hi, f);
     const bool absorb = (F & kUnitTau) || a.omega != 0.0f;
-    if constexpr (S == kF32) {
+    if constexpr (S == kF32 || S == kBf16R32) {
         if (absorb)
             f[0] = rho - ((f[1] + f[4]) + ((f[2] + f[5]) + (f[3] + f[6])));
     }
@@ -306,7 +315,7 @@ __device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], floa
             fired = true;
         }
     }
-    if constexpr (S != kF32) {
+    if constexpr (S == kBf16Dev || S == kF16Dev) {
         if (!fired && absorb) {
             float g[7];
 #pragma unroll
@@ -328,6 +337,21 @@ __device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], floa
 #pragma unroll
         for (int i = 0; i < 7; ++i)
             f[i] *= r;
+    }
+    if constexpr (S == kBf16R32) {
+        // bfloat16 moving populations, float32 rest population: the rest
+        // population takes rho minus the moving ones as they will be stored,
+        // at every site (corrected ones included), so the stored site holds
+        // its mass to one float32 rounding; it stays >= 0 (where the moving
+        // roundings exceed a corrected rest population of ~0, that excess is
+        // the only mass the step does not keep)
+        if (absorb) {
+            float g[7];
+#pragma unroll
+            for (int i = 1; i < 7; ++i)
+                g[i] = Store<kBf16Dev>::round(f[i], a.wr1);
+            f[0] = fmaxf(rho - ((g[1] + g[4]) + ((g[2] + g[5]) + (g[3] + g[6]))), 0.0f);
+        }
     }
 }
 
@@ -476,6 +500,76 @@ struct BufIO<_Float16> {
     }
 };
 
+// Population planes of a buffer in storage S, plane i of `plane` elements:
+// load / store of element v + s of plane i through a buffer resource (v the
+// per-lane part, s the wave-uniform part), the same through a plain pointer
+// (ld / st), the value a store and a later load give back (round), and the
+// buffer's size in bytes.  One type per buffer except kBf16R32, whose rest
+// plane is float32 (two 16-bit planes of room) before six bfloat16 planes.
+template <int S>
+struct Planes {
+    using T = typename Store<S>::T;
+    __host__ __device__ static constexpr uint64_t bytes(uint64_t plane) { return 7u * plane * sizeof(T); }
+    __device__ __forceinline__ static float wr(int i, const StepArgs &a) { return i == 0 ? a.wr0 : a.wr1; }
+    __device__ __forceinline__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, int i,
+                                                 uint32_t plane, const StepArgs &a)
+    {
+        return Store<S>::widen(BufIO<T>::load(r, v, (uint32_t)i * plane + s), wr(i, a));
+    }
+    __device__ __forceinline__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, int i,
+                                                 uint32_t plane, float x, const StepArgs &a)
+    {
+        BufIO<T>::store(r, v, (uint32_t)i * plane + s, Store<S>::narrow(x, wr(i, a)));
+    }
+    __device__ __forceinline__ static float ld(const T *p, int64_t e, int i, int64_t plane, const StepArgs &a)
+    {
+        return Store<S>::load(p, i * plane + e, wr(i, a));
+    }
+    __device__ __forceinline__ static void st(T *p, int64_t e, int i, int64_t plane, float x, const StepArgs &a)
+    {
+        Store<S>::store(p, i * plane + e, x, wr(i, a));
+    }
+    __device__ __forceinline__ static float round(float x, int i, const StepArgs &a) { return Store<S>::round(x, wr(i, a)); }
+};
+
+template <>
+struct Planes<kBf16R32> {
+    using T = uint16_t;
+    __host__ __device__ static constexpr uint64_t bytes(uint64_t plane) { return 16u * plane; }
+    __device__ __forceinline__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, int i,
+                                                 uint32_t plane, const StepArgs &a)
+    {
+        if (i == 0)
+            return BufIO<float>::load(r, v, s);
+        return Store<kBf16Dev>::widen(BufIO<uint16_t>::load(r, v, (uint32_t)(i + 1) * plane + s), a.wr1);
+    }
+    __device__ __forceinline__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s, int i,
+                                                 uint32_t plane, float x, const StepArgs &a)
+    {
+        if (i == 0)
+            BufIO<float>::store(r, v, s, x);
+        else
+            BufIO<uint16_t>::store(r, v, (uint32_t)(i + 1) * plane + s, Store<kBf16Dev>::narrow(x, a.wr1));
+    }
+    __device__ __forceinline__ static float ld(const T *p, int64_t e, int i, int64_t plane, const StepArgs &a)
+    {
+        if (i == 0)
+            return ((const float *)p)[e];
+        return Store<kBf16Dev>::load(p, (i + 1) * plane + e, a.wr1);
+    }
+    __device__ __forceinline__ static void st(T *p, int64_t e, int i, int64_t plane, float x, const StepArgs &a)
+    {
+        if (i == 0)
+            ((float *)p)[e] = x;
+        else
+            Store<kBf16Dev>::store(p, (i + 1) * plane + e, x, a.wr1);
+    }
+    __device__ __forceinline__ static float round(float x, int i, const StepArgs &a)
+    {
+        return i == 0 ? x : Store<kBf16Dev>::round(x, a.wr1);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // MIPS step of one 64 x ROWS tile at (x0, y0), ROWS = 4 or 16 (u* needs the
 // streamed density of the six neighbours).  256 threads: wave w owns rows w,
@@ -500,7 +594,6 @@ __device__ __forceinline__ void mips_tile_step(__amdgpu_buffer_rsrc_t rs, __amdg
                                                const StepArgs &a, int x0, int y0, uint32_t t_lo, uint32_t t_hi,
                                                float *srho)
 {
-    using T = typename Store<S>::T;
     constexpr int W = 66, H = ROWS + 2, RW = ROWS / NW;  // RW rows per wave
     constexpr int kRing = 2 * W + 2 * ROWS;
     static_assert(NW % 2 == 0 && ROWS % NW == 0 && kRing <= 64 * NW, "NW waves own the rows and cover the ring");
@@ -513,7 +606,7 @@ __device__ __forceinline__ void mips_tile_step(__amdgpu_buffer_rsrc_t rs, __amdg
         const PullSources32 q = pull_sources32(a, wrap_coord(x, a.nx), wrap_coord(y, a.ny));
 #pragma unroll
         for (int i = 0; i < 7; ++i)
-            g[i] = Store<S>::widen(BufIO<T>::load(rs, q.idx[i], i * plane), i == 0 ? a.wr0 : a.wr1);
+            g[i] = Planes<S>::load(rs, q.idx[i], 0u, i, plane, a);
     };
     float f[RW][7];
 #pragma unroll
@@ -522,11 +615,10 @@ __device__ __forceinline__ void mips_tile_step(__amdgpu_buffer_rsrc_t rs, __amdg
         if (interior) {
             const uint32_t p = (uint32_t)y & 1u;
             const uint32_t c = (uint32_t)y * P + (uint32_t)x0;  // offset of (x0, y)
-            const uint32_t e[7] = {c, plane + c - 1u, 2u * plane + c - P - 1u + p, 3u * plane + c - P + p,
-                                   4u * plane + c + 1u, 5u * plane + c + P + p, 6u * plane + c + P - 1u + p};
+            const uint32_t e[7] = {c, c - 1u, c - P - 1u + p, c - P + p, c + 1u, c + P + p, c + P - 1u + p};
 #pragma unroll
             for (int i = 0; i < 7; ++i)
-                f[k][i] = Store<S>::widen(BufIO<T>::load(rs, lane, e[i]), i == 0 ? a.wr0 : a.wr1);
+                f[k][i] = Planes<S>::load(rs, lane, e[i], i, plane, a);
         } else {
             load_wrapped(f[k], x0 + lane, y);
         }
@@ -579,7 +671,7 @@ __device__ __forceinline__ void mips_tile_step(__amdgpu_buffer_rsrc_t rs, __amdg
         const uint32_t own = (uint32_t)y * P + (uint32_t)x;
 #pragma unroll
         for (int i = 0; i < 7; ++i)
-            BufIO<T>::store(rd, own, i * plane, Store<S>::narrow(f[k][i], i == 0 ? a.wr0 : a.wr1));
+            Planes<S>::store(rd, own, 0u, i, plane, f[k][i], a);
     }
 }
 

@@ -73,7 +73,7 @@ __device__ __forceinline__ void gathered_moments(const typename Store<S>::T *src
         const PullSources g_src = pull_sources(a, x, y);
 #pragma unroll
         for (int i = 0; i < 7; ++i)
-            f[i] = Store<S>::load(src, i * a.plane + g_src.idx[i], i == 0 ? a.wr0 : a.wr1);
+            f[i] = Planes<S>::ld(src, g_src.idx[i], i, a.plane, a);
         site_moments(f, rho, jx, jy);
     } else {
         const Q9Sources g_src = q9_sources(a, x, y);
@@ -212,6 +212,12 @@ hipError_t launch_moments(const lbm_params &p, const StepArgs &a, const void *sr
         else
             hipLaunchKernelGGL((k_moments<kF16Dev, 7>), grd, blk, 0, s, (const _Float16 *)src, a, rho, ux, uy, part,
                                colpart);
+        break;
+    case kBf16R32:
+        if (q9)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_moments<kBf16R32, 7>), grd, blk, 0, s, (const uint16_t *)src, a, rho, ux, uy, part,
+                           colpart);
         break;
     default: return hipErrorInvalidValue;
     }

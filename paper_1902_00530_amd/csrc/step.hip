@@ -34,15 +34,14 @@ __global__ __launch_bounds__(256) void k_step_local(const typename Store<S>::T *
     const int y = tyi * blockDim.y + threadIdx.y;
     if (x >= a.nx || y >= a.ny)
         return;
-    using T = typename Store<S>::T;
     const uint32_t plane = (uint32_t)a.plane;
-    const uint32_t bytes = 7u * plane * (uint32_t)sizeof(T);  // < 2^32: 7 plane < 2^30
+    const uint32_t bytes = (uint32_t)Planes<S>::bytes(plane);  // < 2^32: 7 planes < 2^30 elements
     const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(src, bytes), rd = buffer_rsrc(dst, bytes);
     const PullSources32 g_src = pull_sources32(a, x, y);
     float f[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        f[i] = Store<S>::widen(BufIO<T>::load(rs, g_src.idx[i], i * plane), i == 0 ? a.wr0 : a.wr1);
+        f[i] = Planes<S>::load(rs, g_src.idx[i], 0u, i, plane, a);
     float rho, jx, jy, ux, uy;
     site_moments(f, rho, jx, jy);
     local_ustar<M>(a, rho, jx, jy, ux, uy);
@@ -50,7 +49,7 @@ __global__ __launch_bounds__(256) void k_step_local(const typename Store<S>::T *
     const uint32_t own = g_src.idx[0];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        BufIO<T>::store(rd, own, i * plane, Store<S>::narrow(f[i], i == 0 ? a.wr0 : a.wr1));
+        Planes<S>::store(rd, own, 0u, i, plane, f[i], a);
     clock_advance(clk, slot, tt);
 }
 
@@ -71,7 +70,7 @@ __global__ __launch_bounds__(256) void k_step_local64(const typename Store<S>::T
     float f[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        f[i] = Store<S>::load(src, i * a.plane + g_src.idx[i], i == 0 ? a.wr0 : a.wr1);
+        f[i] = Planes<S>::ld(src, g_src.idx[i], i, a.plane, a);
     float rho, jx, jy, ux, uy;
     site_moments(f, rho, jx, jy);
     local_ustar<M>(a, rho, jx, jy, ux, uy);
@@ -79,7 +78,7 @@ __global__ __launch_bounds__(256) void k_step_local64(const typename Store<S>::T
     const int64_t own = g_src.idx[0];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        Store<S>::store(dst, i * a.plane + own, f[i], i == 0 ? a.wr0 : a.wr1);
+        Planes<S>::st(dst, own, i, a.plane, f[i], a);
     clock_advance(clk, slot, tt);
 }
 
@@ -98,7 +97,7 @@ __device__ __forceinline__ float rho_at(const typename Store<S>::T *src, const S
     float f[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        f[i] = Store<S>::load(src, i * a.plane + g_src.idx[i], i == 0 ? a.wr0 : a.wr1);
+        f[i] = Planes<S>::ld(src, g_src.idx[i], i, a.plane, a);
     return f[0] + ((f[1] + f[4]) + ((f[2] + f[5]) + (f[3] + f[6])));
 }
 
@@ -127,7 +126,7 @@ __global__ __launch_bounds__(256) void k_step_mips64(const typename Store<S>::T 
     float f[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        f[i] = Store<S>::load(src, i * a.plane + g_src.idx[i], i == 0 ? a.wr0 : a.wr1);
+        f[i] = Planes<S>::ld(src, g_src.idx[i], i, a.plane, a);
     float rho, jx, jy;
     site_moments(f, rho, jx, jy);
     srho[ty + 1][tx + 1] = rho;
@@ -170,7 +169,7 @@ __global__ __launch_bounds__(256) void k_step_mips64(const typename Store<S>::T 
     const int64_t own = g_src.idx[0];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        Store<S>::store(dst, i * a.plane + own, f[i], i == 0 ? a.wr0 : a.wr1);
+        Planes<S>::st(dst, own, i, a.plane, f[i], a);
     clock_advance(clk, slot, tt);
 }
 
@@ -188,14 +187,13 @@ __global__ __launch_bounds__(64 * NW) void k_step_mips(const typename Store<S>::
 {
     const uint64_t tt = clock_read(clk, slot);
     const uint32_t t_lo = (uint32_t)(tt & 0xffffffffu), t_hi = (uint32_t)(tt >> 32);
-    using T = typename Store<S>::T;
     __shared__ float srho[mips_tile_lds(ROWS)];
     int txi, tyi;
     row_group_tile(txi, tyi);
     const int x0 = txi * 64, y0 = tyi * ROWS;
     if (y0 >= a.ny)  // padding tile rows of the last group: the whole block
         return;
-    const uint32_t bytes = 7u * (uint32_t)a.plane * (uint32_t)sizeof(T);  // < 2^32: 7 planes < 2^30 elements
+    const uint32_t bytes = (uint32_t)Planes<S>::bytes(a.plane);  // < 2^32: 7 planes < 2^30 elements
     mips_tile_step<S, F, ROWS, NW>(buffer_rsrc(src, bytes), buffer_rsrc(dst, bytes), a, x0, y0, t_lo, t_hi, srho);
     clock_advance(clk, slot, tt);
 }
@@ -278,6 +276,7 @@ hipError_t launch_step(const lbm_params &p, const StepArgs &a, const void *src, 
     case kF32: return launch_step_s<kF32>(p, a, src, dst, clk, slot, s);
     case kBf16Dev: return launch_step_s<kBf16Dev>(p, a, src, dst, clk, slot, s);
     case kF16Dev: return launch_step_s<kF16Dev>(p, a, src, dst, clk, slot, s);
+    case kBf16R32: return launch_step_s<kBf16R32>(p, a, src, dst, clk, slot, s);
     }
     return hipErrorInvalidValue;
 }
@@ -342,7 +341,7 @@ __global__ __launch_bounds__(256) void k_init(typename Store<S>::T *__restrict__
     }
     const int64_t own = (int64_t)y * a.pitch + x;
     for (int i = 0; i < 7; ++i)
-        Store<S>::store(dst, i * a.plane + own, (float)g[i], i == 0 ? a.wr0 : a.wr1);
+        Planes<S>::st(dst, own, i, a.plane, (float)g[i], a);
 }
 
 template <int S>
@@ -354,9 +353,8 @@ __global__ __launch_bounds__(256) void k_add_density(typename Store<S>::T *__res
         return;
     const int64_t own = (int64_t)y * a.pitch + x;
     for (int i = 0; i < 7; ++i) {
-        const float wr = i == 0 ? a.wr0 : a.wr1;
-        const float v = Store<S>::load(buf, i * a.plane + own, wr);
-        Store<S>::store(buf, i * a.plane + own, v + add, wr);
+        const float v = Planes<S>::ld(buf, own, i, a.plane, a);
+        Planes<S>::st(buf, own, i, a.plane, v + add, a);
     }
 }
 
@@ -368,6 +366,7 @@ hipError_t launch_init(const lbm_params &p, const lbm_init &in, const StepArgs &
     case kF32: hipLaunchKernelGGL(k_init<kF32>, grd, blk, 0, s, (float *)dst, a, ia); break;
     case kBf16Dev: hipLaunchKernelGGL(k_init<kBf16Dev>, grd, blk, 0, s, (uint16_t *)dst, a, ia); break;
     case kF16Dev: hipLaunchKernelGGL(k_init<kF16Dev>, grd, blk, 0, s, (_Float16 *)dst, a, ia); break;
+    case kBf16R32: hipLaunchKernelGGL(k_init<kBf16R32>, grd, blk, 0, s, (uint16_t *)dst, a, ia); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -381,6 +380,7 @@ hipError_t launch_add_density(const lbm_params &p, const StepArgs &a, void *buf,
     case kF32: hipLaunchKernelGGL(k_add_density<kF32>, grd, blk, 0, s, (float *)buf, a, add); break;
     case kBf16Dev: hipLaunchKernelGGL(k_add_density<kBf16Dev>, grd, blk, 0, s, (uint16_t *)buf, a, add); break;
     case kF16Dev: hipLaunchKernelGGL(k_add_density<kF16Dev>, grd, blk, 0, s, (_Float16 *)buf, a, add); break;
+    case kBf16R32: hipLaunchKernelGGL(k_add_density<kBf16R32>, grd, blk, 0, s, (uint16_t *)buf, a, add); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

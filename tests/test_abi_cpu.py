@@ -255,3 +255,24 @@ def test_surrogate_descriptions_and_create_validation():
                   ctypes.byref(h)) == L.LBM_EINVAL and "workspace" in L.lbm_last_error()
     assert L._lib.lbm_surrogate_train_step(None, None, None, None, 1, ctypes.c_float(1e-3), None) == L.LBM_ESTATE
     assert L._lib.lbm_surrogate_predict(None, None, 1, None) == L.LBM_ESTATE
+
+
+def test_float32_rest_plane_storage_references_and_validation():
+    """LBM_BF16_DEV_R32: the rest population is stored as is (r_0 = 0), the
+    moving ones as bfloat16 deviations from w_i rho_ref rounded to bfloat16
+    (the references of LBM_BF16_DEV); D2Q7 only; storages past it are
+    unknown."""
+    import numpy as np
+    import paper_1902_00530_amd as L
+    p = L.make_params(64, 64, L.LBM_CIL, storage=L.LBM_BF16_DEV_R32, rho_ref=0.74)
+    wr = L.lbm_deviation_reference(p)
+    wb = L.lbm_deviation_reference(L.make_params(64, 64, L.LBM_CIL, storage=L.LBM_BF16_DEV, rho_ref=0.74))
+    assert wr[0] == 0.0 and (wr[1:] == wb[1:]).all()
+    # bfloat16-representable: the low 16 bits of the float32 pattern are zero
+    assert (wr[1:].view(np.uint32) & 0xFFFF == 0).all() and abs(wr[1] - 0.74 / 12) < 2 ** -8 * 0.74 / 12
+    assert L.storage_planes(p) == 8
+    q9 = L.make_params(64, 64, L.LBM_CIL, storage=L.LBM_BF16_DEV_R32, rho_ref=0.74, lattice=L.LBM_D2Q9)
+    assert L._lib.lbm_deviation_reference(ctypes.byref(q9), (ctypes.c_float * 9)()) == L.LBM_EUNSUPPORTED
+    bad = L.make_params(64, 64, L.LBM_CIL, storage=4, rho_ref=0.74)
+    assert L._lib.lbm_deviation_reference(ctypes.byref(bad), (ctypes.c_float * 9)()) == L.LBM_EINVAL
+    assert "storage" in L.lbm_last_error()

@@ -503,13 +503,14 @@ def test_enqueue_only_sweep_and_later_samples(L):
         assert torch.equal(a, b_)
 
 
-@pytest.mark.parametrize("storage", [1, 2])
+@pytest.mark.parametrize("storage", [1, 2, 3])
 @pytest.mark.parametrize("tile_rows,use_graph", [(1, 1), (16, 1), (0, 1), (8, 0)])
 def test_16bit_batch_member_equals_single_run(L, storage, tile_rows, use_graph):
-    """BF16 / FP16 deviation storage in batched sweeps: every step rounds its
-    results into the storage as lbm_step's store does (the two-step kernel
-    rounds its first step's results in LDS the same way), so members equal
-    lbm_step runs bit for bit, samples and density ramp included."""
+    """BF16 / FP16 deviation storage (and BF16 with the float32 rest plane,
+    storage 3) in batched sweeps: every step rounds its results into the
+    storage as lbm_step's store does (the two-step kernel rounds its first
+    step's results in LDS the same way), so members equal lbm_step runs bit
+    for bit, samples and density ramp included."""
     cfgs = small_batch()[:4]
     rr = [0.3 + 0.3 * l for l in range(len(cfgs))]
     gp = [L.make_params(c["nx"], c["ny"], c["model"], c["tau"], c["sigma"], c["A"], c["B"], c["C"], c["rho_star"],
@@ -546,10 +547,11 @@ def test_16bit_batch_member_equals_single_run(L, storage, tile_rows, use_graph):
             assert abs(s_b["phi"] - s_l["phi"]) <= 1e-12
 
 
-@pytest.mark.parametrize("storage", [1, 2])
+@pytest.mark.parametrize("storage", [1, 2, 3])
 def test_16bit_mips_and_resident_batches(L, storage):
     """MIPS (64 x 16 and 64 x 4 tiles) and the LDS-resident form in 16-bit
-    storage equal lbm_step runs bit for bit."""
+    storage (the resident form keeps storage 3 as the float32 values the
+    storage gives back) equal lbm_step runs bit for bit."""
     import synth_inputs as SI_
     cfgs = [dict(nx=90, ny=30, model=SI_.MIPS, tau=2.0, sigma=1.0 / 70.0, A=0.0, B=0.0, C=50.0, rho_star=0.2,
                  u_max=0.3, seed=SI_.seed_for(9, l)) for l in range(3)]

@@ -63,13 +63,14 @@ def dev_ref(L, params):
     return L.lbm_deviation_reference(params).astype(np.float64)[:, None, None]
 
 
-def storage_bound(ref, wr, u):
+def storage_bound(ref, wr, u, rest32=False):
     """One rounding (unit roundoff u) of each stored deviation |ref - r_i|; the
     rest population is rho minus the moving populations as stored, so it
-    also carries their roundings."""
+    also carries their roundings.  rest32: the rest population is stored in
+    float32 (its own rounding is left to the caller's float32 term)."""
     d = np.abs(ref - wr)
     b = u * d
-    b[0] = b[0] + u * d[1:].sum(axis=0)
+    b[0] = (0.0 if rest32 else b[0]) + u * d[1:].sum(axis=0)
     return b
 
 
