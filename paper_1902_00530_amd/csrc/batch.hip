@@ -703,14 +703,16 @@ __device__ __forceinline__ double bwave_sum(double v)
     return v;
 }
 
-// Q = 7 (triangular) or 9 (square lattice, F32 storage only).
+// Q = 7 (triangular) or 9 (square lattice, F32 storage only).  Block b
+// takes moments tile base + b (a launch may cover one lattice group).
 template <int Q, int ST>
 __global__ __launch_bounds__(256) void k_batch_moments(const MomTile *__restrict__ mt, const LatDesc *__restrict__ lats,
-                                                       const Ctrl *__restrict__ ctrl, int node,
+                                                       const Ctrl *__restrict__ ctrl, int node, int base,
                                                        double *__restrict__ part, double *__restrict__ colpart)
 {
     __shared__ double lds[4][5];
-    const MomTile m = mt[blockIdx.x];
+    const int tile = base + (int)blockIdx.x;
+    const MomTile m = mt[tile];
     const LatDesc &L = lats[m.lat];
     const StepArgs a = L.a;
     const int par = (int)((ctrl->k0 + node) & 1);
@@ -765,7 +767,7 @@ __global__ __launch_bounds__(256) void k_batch_moments(const MomTile *__restrict
     if (threadIdx.x == 0)
 #pragma unroll
         for (int k = 0; k < 5; ++k)
-            part[(int64_t)blockIdx.x * 5 + k] = ((lds[0][k] + lds[1][k]) + lds[2][k]) + lds[3][k];
+            part[(int64_t)tile * 5 + k] = ((lds[0][k] + lds[1][k]) + lds[2][k]) + lds[3][k];
 }
 
 // Column means rho_y(x) of every lattice: one thread per column (grid y =
@@ -1240,10 +1242,30 @@ struct GraphKey {
 
 // An executable graph, destroyed when the last holder lets go (the cache or
 // a call still running it).
+// An instantiated graph and an event recorded after its latest launch: a
+// sweep returns without waiting for its graphs, so an exec evicted from the
+// cache (or released at the end of a call) waits for that launch to finish
+// before it is destroyed.
 struct GraphExec {
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    hipError_t launched(hipStream_t s)
+    {
+        if (!done) {
+            hipError_t e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                done = nullptr;
+                return e;
+            }
+        }
+        return hipEventRecord(done, s);
+    }
     ~GraphExec()
     {
+        if (done) {
+            (void)hipEventSynchronize(done);
+            (void)hipEventDestroy(done);
+        }
         if (exec)
             (void)hipGraphExecDestroy(exec);
     }
@@ -1654,6 +1676,31 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     std::vector<int64_t> gkey(g_main);
     gkey.insert(gkey.end(), g_one.begin(), g_one.end());
 
+    // moments tiles of each lattice group ([begin, end) in the lattice-ordered list)
+    std::vector<int> gmt(gfirst.size(), 0);
+    {
+        std::vector<int> first_mt(n + 1, 0);
+        for (int l = 0; l < n; ++l)
+            first_mt[l + 1] = first_mt[l] + ((ps[l].nx + 255) / 256) * ((ps[l].ny + kMomRows - 1) / kMomRows);
+        for (size_t g = 0; g < gfirst.size(); ++g)
+            gmt[g] = first_mt[gfirst[g]];
+    }
+    // the sample's moments of lattice group g: right after the group's last
+    // launch, while its state is still in the Infinity Cache
+    auto group_moments = [&](size_t g, int64_t steps) {
+        const int base = gmt[g], cnt = gmt[g + 1] - gmt[g];
+        if (cnt <= 0)
+            return;
+        if (q9)
+            hipLaunchKernelGGL((k_batch_moments<9, kF32>), dim3((unsigned)cnt), dim3(256), 0, s, d_mt, d_lat, d_ctrl,
+                               (int)steps, base, d_part, d_colpart);
+        else
+            (void)with_storage(ps[0].storage, [&](auto st) {
+                hipLaunchKernelGGL((k_batch_moments<7, decltype(st)::value>), dim3((unsigned)cnt), dim3(256), 0, s,
+                                   d_mt, d_lat, d_ctrl, (int)steps, base, d_part, d_colpart);
+                return hipSuccess;
+            });
+    };
     // `steps` steps, then the sample if asked, then the counter update
     auto enqueue = [&](int64_t steps, bool sample) -> hipError_t {
         int64_t done = 0, launches = 0;
@@ -1663,6 +1710,8 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
                 return e;
             done = steps;
         }
+        if (resident && sample)
+            group_moments(0, steps);
         // every launch of the chunk for one lattice group, then the next
         const int64_t d0 = done, l0 = launches;
         for (size_t g = 0; g + 1 < gfirst.size() && !resident; ++g) {
@@ -1686,18 +1735,11 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
                 if (e != hipSuccess)
                     return e;
             }
+            if (sample)
+                group_moments(g, steps);
         }
         if (sample) {
             const int sto = ps[0].storage;
-            if (q9)
-                hipLaunchKernelGGL((k_batch_moments<9, kF32>), dim3((unsigned)nmt), dim3(256), 0, s, d_mt, d_lat,
-                                   d_ctrl, (int)steps, d_part, d_colpart);
-            else
-                (void)with_storage(sto, [&](auto st) {
-                    hipLaunchKernelGGL((k_batch_moments<7, decltype(st)::value>), dim3((unsigned)nmt), dim3(256), 0,
-                                       s, d_mt, d_lat, d_ctrl, (int)steps, d_part, d_colpart);
-                    return hipSuccess;
-                });
             hipLaunchKernelGGL(k_batch_colmeans, dim3((unsigned)((max_nx + 255) / 256), (unsigned)n), dim3(256), 0, s,
                                d_lat, d_colpart, d_colmean);
             hipLaunchKernelGGL(k_batch_final, dim3((unsigned)n), dim3(256), 0, s, d_lat, d_ctrl, (int)steps, d_part,
@@ -1781,8 +1823,11 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
             if (e == hipSuccess)
                 e = hipGraphLaunch(g_tail->exec, s);
         }
+        // no wait here: each exec remembers its latest launch (GraphExec)
+        if (e == hipSuccess && g_chunk && reps > 0 && n_periods > 0)
+            e = g_chunk->launched(s);
         if (e == hipSuccess)
-            e = hipStreamSynchronize(s);
+            e = g_tail->launched(s);
         if (e != hipSuccess)
             return hip_fail(e, "lbm_sweep_batch graph");
     } else {
