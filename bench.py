@@ -646,6 +646,14 @@ def main():
         for c in (8, 16, 32):
             fl[f"{c}x{c}_sites_per_cell"] = round(S.noise_floor(SI.surrogate_grid(256, 21000), c, 50, 2000), 5)
         var["surrogate_noise_floor_by_cell"] = fl
+        # where the floor drops below the fixed bound of 1e-2 (32 x 32 sites
+        # per cell) and just above it (16 x 16): the same recipe and sweeps
+        for c in (16, 32):
+            r = S.recipe(SI.surrogate_grid(256, 11000), SI.surrogate_grid(256, 21000), SI.surrogate_grid(256, 31000),
+                         coarse=c, k=50, warmup=2000, rounds=320, epochs=30, batch=64, lr=1e-3, jumps=20,
+                         check_every=4)
+            r.pop("network")
+            var[f"surrogate_256_k50_cell{c}"] = r
         # the paper's measurement protocol (180 x 60 lattices, its CIL
         # parameters): the hysteresis ramps at A = 2 (50 increasing and 50
         # decreasing runs) and a (rho, A) phase diagram (9 A values x 10
