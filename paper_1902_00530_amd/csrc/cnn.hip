@@ -8,11 +8,10 @@
 // Layout: activations NCHW float32; weights stored as bfloat16 (the Adam
 // step keeps float32 master copies) and widened once per pass to float32, so
 // every product is a bf16 x f32 -> f32 product with float32 accumulation.
-// Convolutions: one block = one sample x a 16 x 16 pixel tile x all output
-// channels; the input tile with its one-pixel halo sits in LDS, weights are
-// read with wave-uniform addresses (scalar loads), each thread keeps one
-// pixel's output channels in registers.  Reductions (weight gradients, loss)
-// use fixed partitions and orders, so results are deterministic.
+// Convolutions and weight gradients are matrix products on the matrix cores
+// (FP32 operands) over 16 x 8 pixel tiles staged in LDS with their halo.
+// Reductions (weight gradients, loss) use fixed partitions and orders, so
+// results are deterministic.
 #include <math.h>
 
 #include <algorithm>
@@ -22,103 +21,252 @@
 
 namespace lbm {
 
-constexpr int kTile = 16;
-
 // ---------------------------------------------------------------------------
-// 3x3 convolution.  TR = 0: y[n,o,i,j] = b[o] + sum_c sum_k w[o,c,k]
-// x[n,c,i+ky-1,j+kx-1].  TR = 1 (input gradient of a convolution with
-// weights w[Cin_orig=co][Cout_orig=ci]): y[n,c,..] = sum_o sum_k
-// w[o,c,8-k] x[n,o,..], i.e. the same sum with transposed, flipped weights.
-// Epilogue in order: bias, ReLU, + resid[n, o] (first co channels of a
-// tensor with resid_c channels), * (mask[n, o] > 0).
+// 3x3 convolutions on the matrix cores (v_mfma_f32_32x32x2_f32: FP32
+// operands, FP32 accumulation, so every product is exact and only the order
+// of the sums differs from the definition).  The weights are the bf16 values
+// the network stores, widened; the activations stay FP32.  A 16 x 8 pixel
+// tile of one sample per block (four waves, one 32-pixel slab each: two
+// image rows of 16), its input with the one-pixel circular halo staged in
+// LDS, every channel at once (ci, co <= 32).
 //
-// One block = one sample x a 16 x 16 pixel tile x OG of the co_n output
-// channels (blockIdx.z = sample * groups + group), so small batches of small
-// fields still give several blocks per CU; the input tile with its halo is
-// staged in LDS kChunk channels at a time.  Every output sums over c and k in
-// increasing order, as the definition reads.
+// Convolution as a matrix product per slab: D[pixel][o] = sum_k A[pixel][k]
+// B[k][o], k = c * 9 + tap (tap = 3 ky + kx), A the input at the pixel
+// shifted by the tap, B[k][o] = wb[o][k].  TR = 0: y[n,o,i,j] = b[o] +
+// sum_c sum_tap w[o,c,tap] x[n,c,i+ky-1,j+kx-1] (wb = w).  TR = 1 (input
+// gradient of a convolution whose weights are w[c][o][tap]): the same sum
+// with wb[o][c*9+tap] = w[c][o][8-tap], the transposed, flipped weights
+// (written by k_widen_tr).  Epilogue in order: bias, ReLU, + resid[n, o]
+// (first co channels of a tensor with resid_c channels), * (mask[n, o] > 0).
+//
+// MFMA 32x32x2 operand layout (per lane l of the wave): A row l mod 32,
+// k = l / 32; B column l mod 32, k = l / 32; result register r holds row
+// 8 (r / 4) + 4 (l / 32) + r mod 4 of column l mod 32.  The reduction runs
+// in the order (channel pair, tap): lanes with k = 0 take channel c, lanes
+// with k = 1 channel c + ceil(ci / 2) (a zero channel when ci is odd), so
+// each step's LDS offsets differ from the lane's base by a constant.
 // ---------------------------------------------------------------------------
-constexpr int kChunk = 8;
+constexpr int kTW = 16, kTH = 8;                   // pixel tile
+constexpr int kHW_ = kTW + 2, kHH = kTH + 2;       // with the halo
+constexpr int kHalo = kHW_ * kHH;                  // 180 pixels
+constexpr int kMaxC = 32, kMaxK = kMaxC * 9;       // channels, reduction length
 
-template <int OG, int TR>
-__global__ __launch_bounds__(256) void k_conv3x3(const float *__restrict__ x, int ci_n, const float *__restrict__ w,
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// v in [-1, n + kHW_ - 2] wrapped into [0, n); SMALL: n may be smaller than
+// the halo tile, so v may wrap more than once
+template <bool SMALL>
+__device__ __forceinline__ int wrap_index(int v, int n)
+{
+    if (SMALL)
+        return (v + n) % n;
+    return v < 0 ? v + n : (v >= n ? v - n : v);
+}
+
+// LDS staging with every global load of a thread in flight before the first
+// LDS write: element e < count of the block's copy is get(e) (a load from an
+// address that is valid for every e < count) stored at put(e).
+template <int NT, int MAXE, class Get, class Put>
+__device__ __forceinline__ void stage(int count, Get get, Put put)
+{
+    constexpr int U = (MAXE + NT - 1) / NT;
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        v[u] = get(min((int)threadIdx.x + u * NT, count - 1));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int e = threadIdx.x + u * NT;
+        if (e < count)
+            put(e, v[u]);
+    }
+}
+
+// the input tile of sample n with its circular halo: s[c][hy][hx], c < cpad
+// <= MAXC (channels ci_n .. cpad-1 zero); halo values of pixels outside the
+// field feed no output.  Offsets within a sample fit 32 bits (ci h w < 2^31).
+template <int NT, int MAXC, bool SMALL>
+__device__ __forceinline__ void stage_halo_(const float *__restrict__ xn, int ci_n, int cpad, int H, int W, int i0,
+                                            int j0, float *s)
+{
+    const unsigned HW = (unsigned)H * (unsigned)W;
+    stage<NT, MAXC * kHalo>(
+        cpad * kHalo,
+        [&](int e) {
+            const int c = e / kHalo, r = e - c * kHalo, hy = r / kHW_, hx = r - hy * kHW_;
+            const int gi = wrap_index<SMALL>(i0 + hy - 1, H), gj = wrap_index<SMALL>(j0 + hx - 1, W);
+            const float v = xn[(unsigned)min(c, ci_n - 1) * HW + (unsigned)gi * (unsigned)W + (unsigned)gj];
+            return c < ci_n ? v : 0.0f;
+        },
+        [&](int e, float v) { s[e] = v; });
+}
+
+template <int NT, int MAXC>
+__device__ __forceinline__ void stage_halo(const float *__restrict__ x, int n, int ci_n, int cpad, int H, int W, int i0,
+                                           int j0, float *s)
+{
+    const float *xn = x + (size_t)n * ci_n * H * W;
+    if (H >= kHH && W >= kHW_)
+        stage_halo_<NT, MAXC, false>(xn, ci_n, cpad, H, W, i0, j0, s);
+    else
+        stage_halo_<NT, MAXC, true>(xn, ci_n, cpad, H, W, i0, j0, s);
+}
+
+__device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// CHT > 0: ceil(ci / 2) fixed at compile time (the channel loop unrolls
+// completely, so the operand loads run ahead of the products); 0: any ci.
+template <int CHT>
+__global__ __launch_bounds__(256) void k_conv3x3(const float *__restrict__ x, int ci_n, const float *__restrict__ wb,
                                                  int co_n, const float *__restrict__ bias,
                                                  const float *__restrict__ resid, int resid_c,
                                                  const float *__restrict__ mask, int relu, float *__restrict__ y,
                                                  int H, int W)
 {
-    constexpr int L = kTile + 2;
-    __shared__ float s_in[kChunk * L * L];
-    const int groups = co_n / OG;
-    const int n = blockIdx.z / groups, o0 = (blockIdx.z - n * groups) * OG;
-    const int i0 = blockIdx.y * kTile, j0 = blockIdx.x * kTile;
-    const int tid = threadIdx.x;
-    const size_t HW = (size_t)H * W;
-    const float *xn = x + (size_t)n * ci_n * HW;
-    const int pi = tid >> 4, pj = tid & 15;
-    const int i = i0 + pi, j = j0 + pj;
-    float acc[OG];
+    constexpr int KS = kMaxK + 1;  // weight row stride (odd: the 32 columns of a read hit distinct banks)
+    // one channel / one channel's taps of slack: the loop reads the operands
+    // of the step after the last one, and discards them
+    __shared__ float s_in[(kMaxC + 1) * kHalo];
+    __shared__ float s_w[kMaxC * KS + 9];
+    const int n = blockIdx.z, i0 = blockIdx.y * kTH, j0 = blockIdx.x * kTW;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int CH = CHT > 0 ? CHT : (ci_n + 1) >> 1, K = ci_n * 9, Kp = 2 * CH * 9;
+    stage_halo<256, kMaxC>(x, n, ci_n, 2 * CH, H, W, i0, j0, s_in);
+    // B: s_w[o][k] = wb[o][k]; rows o >= co_n and the padding channel zero
+    stage<256, kMaxC * KS>(
+        kMaxC * KS,
+        [&](int e) {
+            const int o = e / KS, k = e - o * KS;
+            const bool ok = o < co_n && k < K;
+            const float v = wb[ok ? o * K + k : 0];
+            return ok ? v : 0.0f;
+        },
+        [&](int e, float v) { s_w[e] = v; });
+    __syncthreads();
+    const int m = lane & 31, hk = lane >> 5;        // A row (pixel of the slab) / B column, k within the pair
+    const int pr = 2 * wv + (m >> 4), pc = m & 15;  // tile row and column of the A row's pixel
+    const float *pa = s_in + hk * CH * kHalo + pr * kHW_ + pc;
+    const float *pb = s_w + m * KS + hk * CH * 9;
+    f32x16 acc;
 #pragma unroll
-    for (int o = 0; o < OG; ++o)
-        acc[o] = bias ? bias[o0 + o] : 0.0f;
-    for (int c0 = 0; c0 < ci_n; c0 += kChunk) {
-        const int cc = min(kChunk, ci_n - c0);
-        __syncthreads();  // the previous chunk is no longer read
-        for (int e = tid; e < cc * L * L; e += 256) {
-            const int c = e / (L * L), r = e - c * (L * L), li = r / L, lj = r - li * L;
-            int gi = i0 + li - 1, gj = j0 + lj - 1;
-            gi = gi < 0 ? gi + H : (gi >= H ? gi - H : gi);
-            gj = gj < 0 ? gj + W : (gj >= W ? gj - W : gj);
-            s_in[e] = xn[(size_t)(c0 + c) * HW + (size_t)gi * W + gj];
+    for (int r = 0; r < 16; ++r)
+        acc[r] = 0.0f;
+    // channel step c's operands load while step c - 1 multiplies
+    float av[9], bv[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        av[t] = pa[(t / 3) * kHW_ + t % 3];
+        bv[t] = pb[t];
+    }
+#pragma unroll(CHT > 0 ? CHT : 1)
+    for (int c = 0; c < CH; ++c) {
+        pa += kHalo;
+        pb += 9;
+        float an[9], bn[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            an[t] = pa[(t / 3) * kHW_ + t % 3];
+            bn[t] = pb[t];
         }
-        __syncthreads();
-        for (int c = 0; c < cc; ++c) {
-            const float *t = s_in + c * L * L + pi * L + pj;
-            float v[9];
 #pragma unroll
-            for (int ky = 0; ky < 3; ++ky)
-#pragma unroll
-                for (int kx = 0; kx < 3; ++kx)
-                    v[ky * 3 + kx] = t[ky * L + kx];
-            const int cg = c0 + c;
-#pragma unroll
-            for (int o = 0; o < OG; ++o) {
-                float sum = acc[o];
-#pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    const float wk = TR ? w[((size_t)cg * co_n + o0 + o) * 9 + (8 - k)]
-                                        : w[((size_t)(o0 + o) * ci_n + cg) * 9 + k];
-                    sum = fmaf(wk, v[k], sum);
-                }
-                acc[o] = sum;
-            }
+        for (int t = 0; t < 9; ++t) {
+            acc = mfma32(av[t], bv[t], acc);
+            av[t] = an[t];
+            bv[t] = bn[t];
         }
     }
-    if (i >= H || j >= W)
+    // lane: output channel o = m; register group g holds the four pixels
+    // 8 g + 4 hk .. + 3 of the slab, one image row, consecutive columns
+    const int o = m;
+    if (o >= co_n)
         return;
-    const size_t pix = (size_t)i * W + j;
+    const size_t HW = (size_t)H * W;
+    const float bo = bias ? bias[o] : 0.0f;
+    float *yo = y + ((size_t)n * co_n + o) * HW;
+    const float *ro = resid ? resid + ((size_t)n * resid_c + o) * HW : nullptr;
+    const float *mo = mask ? mask + ((size_t)n * co_n + o) * HW : nullptr;
+    if ((W & 3) == 0) {
+        // four 16-byte groups (j + 3 < W whenever j < W); the residual and
+        // mask loads of all groups are issued before the first use
+        size_t pix[4];
+        bool ok[4];
+        float4 rq[4], mq[4];
 #pragma unroll
-    for (int o = 0; o < OG; ++o) {
-        const int og = o0 + o;
-        float r = acc[o];
-        if (relu)
-            r = fmaxf(r, 0.0f);
-        if (resid)
-            r += resid[((size_t)n * resid_c + og) * HW + pix];
-        if (mask)
-            r = mask[((size_t)n * co_n + og) * HW + pix] > 0.0f ? r : 0.0f;
-        y[((size_t)n * co_n + og) * HW + pix] = r;
+        for (int g = 0; g < 4; ++g) {
+            const int i = i0 + 2 * wv + (g >> 1), j = j0 + 8 * (g & 1) + 4 * hk;
+            ok[g] = i < H && j < W;
+            pix[g] = ok[g] ? (size_t)i * W + j : 0;
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            rq[g] = ro ? *(const float4 *)(ro + pix[g]) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            mq[g] = mo ? *(const float4 *)(mo + pix[g]) : make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                v[u] = acc[4 * g + u] + bo;
+                if (relu)
+                    v[u] = fmaxf(v[u], 0.0f);
+            }
+            if (ro)
+                v[0] += rq[g].x, v[1] += rq[g].y, v[2] += rq[g].z, v[3] += rq[g].w;
+            if (mo) {
+                v[0] = mq[g].x > 0.0f ? v[0] : 0.0f, v[1] = mq[g].y > 0.0f ? v[1] : 0.0f;
+                v[2] = mq[g].z > 0.0f ? v[2] : 0.0f, v[3] = mq[g].w > 0.0f ? v[3] : 0.0f;
+            }
+            if (ok[g])
+                *(float4 *)(yo + pix[g]) = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        return;
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int i = i0 + 2 * wv + (g >> 1), j = j0 + 8 * (g & 1) + 4 * hk;
+        if (i >= H || j >= W)
+            continue;
+        const size_t pix = (size_t)i * W + j;
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v[u] = acc[4 * g + u] + bo;
+            if (relu)
+                v[u] = fmaxf(v[u], 0.0f);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (j + u >= W)
+                break;
+            float w = v[u];
+            if (ro)
+                w += ro[pix + u];
+            if (mo)
+                w = mo[pix + u] > 0.0f ? w : 0.0f;
+            yo[pix + u] = w;
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Weight and bias gradients: dw[o,c,k] = sum_{n,i,j} dy[n,o,i,j]
+// Weight and bias gradients: dw[o,c,tap] = sum_{n,i,j} dy[n,o,i,j]
 // x[n,c,i+ky-1,j+kx-1], db[o] = sum dy[n,o,i,j].  One block per (sample,
-// 16 x 16 tile) writes its partial sums (float, in pixel order) to
-// part[block][co_n ci_n 9 + co_n]; k_grad_reduce adds the blocks in order in
-// float64.  Per chunk of kChunk input channels, thread t takes the pair
-// (OG output channels, one input channel) t mod pairs and the pixel group
-// t / pairs; the pixel groups of a pair are then added in order through LDS.
+// 16 x 8 tile) writes its partial sums to part[block][co_n ci_n 9 + co_n];
+// k_grad_reduce adds the blocks in order in float64.  Per block a matrix
+// product on the matrix cores (v_mfma_f32_16x16x4_f32): D[o][k] = sum_p
+// A[o][p] B[p][k], p the tile's 128 pixels in groups of four neighbours
+// (lane group q = l / 16 takes pixel 4 s + q of step s), k = c * 9 + tap.
+// The output is cut into 16 x 16 blocks (rows o, columns k), dealt to the
+// four waves in turn; the bias sums are per-row wave reductions of the dy
+// tile in a fixed order.
+//
+// 16x16x4 operand layout (lane l): A row l mod 16, k = l / 16; B column
+// l mod 16, k = l / 16; result register r holds row 4 (l / 16) + r of
+// column l mod 16.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double cwave_sum(double v)
 {
@@ -128,114 +276,113 @@ __device__ __forceinline__ double cwave_sum(double v)
     return v;
 }
 
-template <int OG>
-__global__ __launch_bounds__(256) void k_conv3x3_wgrad(const float *__restrict__ dy, int co_n,
-                                                       const float *__restrict__ x, int ci_n, int H, int W,
-                                                       float *__restrict__ part)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWgWaves = 4;
+
+__global__ __launch_bounds__(64 * kWgWaves) void k_conv3x3_wgrad(const float *__restrict__ dy, int co_n,
+                                                                 const float *__restrict__ x, int ci_n, int H, int W,
+                                                                 float *__restrict__ part)
 {
-    constexpr int L = kTile + 2;
-    __shared__ float s_x[kChunk * L * L];      // x tile, kChunk input channels
-    __shared__ float s_d[32 * kTile * kTile];  // dy tile, all (<= 32) output channels
-    __shared__ float s_red[256 * 9];           // pixel-group partials
-    const int tiles_j = (W + kTile - 1) / kTile, tiles_i = (H + kTile - 1) / kTile;
+    constexpr int NT = 64 * kWgWaves, NP = kTW * kTH, DS = NP + 1;  // threads, pixels, dy row stride
+    __shared__ float s_x[kMaxC * kHalo];
+    __shared__ float s_d[kMaxC * DS];  // dy tile [o][p] (rows o >= co_n zero; pixels outside the field zero)
+    const int tiles_j = (W + kTW - 1) / kTW, tiles_i = (H + kTH - 1) / kTH;
     const int n = blockIdx.x / (tiles_i * tiles_j), tt = blockIdx.x - n * (tiles_i * tiles_j);
     const int ti = tt / tiles_j;
-    const int i0 = ti * kTile, j0 = (tt - ti * tiles_j) * kTile;
-    const int tid = threadIdx.x;
+    const int i0 = ti * kTH, j0 = (tt - ti * tiles_j) * kTW;
     const size_t HW = (size_t)H * W;
-    const int pairs = (co_n / OG) * kChunk;  // divides 256 (checked on the host)
-    const int pg = 256 / pairs;              // pixel groups
-    const int pair = tid % pairs, grp = tid / pairs;
-    const int og = pair / kChunk, cl = pair - og * kChunk;
-    const int nw = co_n * ci_n * 9;
+    stage_halo<NT, kMaxC>(x, n, ci_n, ci_n, H, W, i0, j0, s_x);
+    const float *dyn = dy + (size_t)n * co_n * HW;
+    stage<NT, kMaxC * NP>(
+        kMaxC * NP,
+        [&](int e) {
+            const int o = e / NP, pq = e - o * NP, gi = i0 + pq / kTW, gj = j0 + pq % kTW;
+            const bool ok = o < co_n && gi < H && gj < W;
+            const float v = dyn[ok ? (size_t)o * HW + (size_t)gi * W + gj : 0];
+            return ok ? v : 0.0f;
+        },
+        [&](int e, float v) { s_d[(e / NP) * DS + e % NP] = v; });
+    __syncthreads();
+    const int K = ci_n * 9, nw = co_n * K;
     float *out = part + (size_t)blockIdx.x * (nw + co_n);
-    // dy tile (zero outside the field)
-    for (int e = tid; e < co_n * kTile * kTile; e += 256) {
-        const int o = e / (kTile * kTile), r = e - o * (kTile * kTile), li = r / kTile, lj = r - li * kTile;
-        const int gi = i0 + li, gj = j0 + lj;
-        s_d[e] = (gi < H && gj < W) ? dy[((size_t)n * co_n + o) * HW + (size_t)gi * W + gj] : 0.0f;
-    }
-    for (int c0 = 0; c0 < ci_n; c0 += kChunk) {
-        __syncthreads();
-        for (int e = tid; e < kChunk * L * L; e += 256) {
-            const int c = e / (L * L), r = e - c * (L * L), li = r / L, lj = r - li * L;
-            int gi = i0 + li - 1, gj = j0 + lj - 1;
-            gi = gi < 0 ? gi + H : (gi >= H ? gi - H : gi);
-            gj = gj < 0 ? gj + W : (gj >= W ? gj - W : gj);
-            s_x[e] = c0 + c < ci_n ? x[((size_t)n * ci_n + c0 + c) * HW + (size_t)gi * W + gj] : 0.0f;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int l16 = lane & 15, q = lane >> 4;
+    const int nrb = (co_n + 15) >> 4, ncb = (K + 15) >> 4;
+    for (int tb = wv; tb < nrb * ncb; tb += kWgWaves) {
+        const int rb = tb / ncb, cb = tb - rb * ncb;
+        const int col = cb * 16 + l16;  // this lane's B column k
+        const int cc = col < K ? col / 9 : 0, t = col < K ? col - cc * 9 : 0, ty = t / 3, tx = t - ty * 3;
+        const float *pa = s_d + (rb * 16 + l16) * DS + q;
+        const float *pb = s_x + cc * kHalo + ty * kHW_ + tx + q;
+        // all of the block's operands first, then the products
+        float av[NP / 4], bv[NP / 4];
+#pragma unroll
+        for (int s4 = 0; s4 < NP / 4; ++s4) {  // pixel 4 s4 + q: row s4 / 4, column 4 s4 mod 16 + q
+            av[s4] = pa[4 * s4];
+            bv[s4] = pb[(s4 >> 2) * kHW_ + ((4 * s4) & 15)];
         }
-        __syncthreads();
-        float acc[OG][9];
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int o = 0; o < OG; ++o)
+        for (int s4 = 0; s4 < NP / 4; ++s4)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s4], bv[s4], acc, 0, 0, 0);
+        if (col < K) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k)
-                acc[o][k] = 0.0f;
-        for (int p = grp; p < kTile * kTile; p += pg) {
-            const int pi = p >> 4, pj = p & 15;
-            const float *t = s_x + cl * L * L + pi * L + pj;
-            float v[9];
-#pragma unroll
-            for (int ky = 0; ky < 3; ++ky)
-#pragma unroll
-                for (int kx = 0; kx < 3; ++kx)
-                    v[ky * 3 + kx] = t[ky * L + kx];
-#pragma unroll
-            for (int o = 0; o < OG; ++o) {
-                const float d = s_d[(og * OG + o) * kTile * kTile + p];
-#pragma unroll
-                for (int k = 0; k < 9; ++k)
-                    acc[o][k] = fmaf(d, v[k], acc[o][k]);
-            }
-        }
-        // the pixel groups of one (pair, tap), added in group order, one
-        // (pair, tap) per thread
-#pragma unroll
-        for (int o = 0; o < OG; ++o) {
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < 9; ++k)
-                s_red[tid * 9 + k] = acc[o][k];
-            __syncthreads();
-            for (int q = tid; q < pairs * 9; q += 256) {
-                const int qp = q / 9, k = q - qp * 9;
-                const int qog = qp / kChunk, qcl = qp - qog * kChunk;
-                if (c0 + qcl < ci_n) {
-                    float sum = 0.0f;
-                    for (int g = 0; g < pg; ++g)
-                        sum += s_red[(g * pairs + qp) * 9 + k];
-                    out[((size_t)(qog * OG + o) * ci_n + c0 + qcl) * 9 + k] = sum;
-                }
+            for (int r = 0; r < 4; ++r) {
+                const int o = rb * 16 + 4 * q + r;
+                if (o < co_n)
+                    out[(size_t)o * K + col] = acc[r];
             }
         }
     }
-    // bias: thread o adds its dy tile in pixel order
-    if (tid < co_n) {
-        float sum = 0.0f;
-        for (int p = 0; p < kTile * kTile; ++p)
-            sum += s_d[tid * kTile * kTile + p];
-        out[nw + tid] = sum;
+    // bias: wave w takes rows w, w + 4, ...; lane l adds pixels l and l + 64,
+    // then a fixed butterfly over the wave
+    for (int o = wv; o < co_n; o += kWgWaves) {
+        float v = s_d[o * DS + lane] + s_d[o * DS + lane + 64];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            v += __shfl_xor(v, off, 64);
+        if (lane == 0)
+            out[nw + o] = v;
     }
 }
 
 // g[e] = the sum over blocks b of part[b][e] (float64); e < nw goes to the
-// weight gradient, e >= nw to the bias gradient.  A block takes 64 entries
-// with 4 threads each: thread slice s adds blocks s, s + 4, ... in order, then
-// the four slices are added in order.
+// weight gradient, e >= nw to the bias gradient.  A block takes kReduceCols
+// entries with 256 / kReduceCols threads each: thread slice s adds blocks s,
+// s + slices, ... in order, then the slices are added in order.
+constexpr int kReduceCols = 16, kReduceSlices = 256 / kReduceCols;
+
 __global__ __launch_bounds__(256) void k_grad_reduce(const float *__restrict__ part, int nblocks, int nw, int nb,
                                                      float *__restrict__ gw, float *__restrict__ gb)
 {
-    __shared__ double s_sum[4][64];
-    const int col = threadIdx.x & 63, slice = threadIdx.x >> 6;
-    const int e = blockIdx.x * 64 + col;
+    __shared__ double s_sum[kReduceSlices][kReduceCols];
+    const int col = threadIdx.x % kReduceCols, slice = threadIdx.x / kReduceCols;
+    const int e = blockIdx.x * kReduceCols + col;
+    const size_t stride = (size_t)(nw + nb);
     double sum = 0.0;
-    if (e < nw + nb)
-        for (int b = slice; b < nblocks; b += 4)
-            sum += (double)part[(size_t)b * (nw + nb) + e];
+    if (e < nw + nb) {
+        const float *p = part + e;
+        int b = slice;
+        constexpr int U = 8;  // loads in flight per thread; the additions stay in block order
+        for (; b + (U - 1) * kReduceSlices < nblocks; b += U * kReduceSlices) {
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                v[u] = p[(size_t)(b + u * kReduceSlices) * stride];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                sum += (double)v[u];
+        }
+        for (; b < nblocks; b += kReduceSlices)
+            sum += (double)p[(size_t)b * stride];
+    }
     s_sum[slice][col] = sum;
     __syncthreads();
     if (slice == 0 && e < nw + nb) {
-        const double t = ((s_sum[0][col] + s_sum[1][col]) + s_sum[2][col]) + s_sum[3][col];
+        double t = s_sum[0][col];
+        for (int k = 1; k < kReduceSlices; ++k)
+            t += s_sum[k][col];
         if (e < nw)
             gw[e] = (float)t;
         else
@@ -281,32 +428,62 @@ __global__ __launch_bounds__(256) void k_mse_final(const double *__restrict__ pa
         *loss = (float)((((s_red[0] + s_red[1]) + s_red[2]) + s_red[3]) / (double)count);
 }
 
-// bf16 weights -> float32 working copy.
-__global__ void k_widen_bf16(const uint16_t *__restrict__ w, int64_t count, float *__restrict__ out)
+// bf16 weights w[co][ci][9] -> float32 working copies, up to three tensors
+// per launch (blockIdx.y): tr = 0 copies, tr = 1 writes the weights of the
+// input-gradient convolution, out[i][o * 9 + t] = w[o][i][8 - t].
+struct WidenJobs {
+    const uint16_t *w[3];
+    float *out[3];
+    int co[3], ci[3], tr[3];
+};
+
+__global__ void k_widen(WidenJobs j)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < count)
-        out[e] = bf16_bits_to_float(w[e]);
+    const int q = blockIdx.y, co = j.co[q], ci = j.ci[q];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= co * ci * 9)
+        return;
+    int src = e;
+    if (j.tr[q]) {
+        const int i = e / (co * 9), r = e - i * (co * 9), o = r / 9, t = r - o * 9;
+        src = (o * ci + i) * 9 + (8 - t);
+    }
+    j.out[q][e] = bf16_bits_to_float(j.w[q][src]);
 }
 
-// Adam (Kingma & Ba, algorithm 1) on a float32 master tensor; writes the
-// bf16 copy when bf16_out is given.
-__global__ void k_adam(float *__restrict__ theta, float *__restrict__ m, float *__restrict__ v,
-                       const float *__restrict__ g, int64_t count, float lr, float beta1, float beta2, float eps,
-                       float bc1, float bc2, uint16_t *__restrict__ bf16_out)
+// Adam (Kingma & Ba, algorithm 1) on float32 master tensors, up to kAdamMax
+// of them in one launch (blockIdx.y selects the tensor; every tensor has its
+// own moments and gradient); writes the bf16 copy where one is given.
+__global__ void k_adam_many(AdamJobs j, float lr, float beta1, float beta2, float eps, float bc1, float bc2)
 {
+    const int q = blockIdx.y;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= count)
+    if (e >= j.count[q])
         return;
-    const float gi = g[e];
+    float *theta = j.theta[q], *m = j.m[q], *v = j.v[q];
+    const float gi = j.g[q][e];
     const float mi = beta1 * m[e] + (1.0f - beta1) * gi;
     const float vi = beta2 * v[e] + (1.0f - beta2) * gi * gi;
     m[e] = mi;
     v[e] = vi;
     const float th = theta[e] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
     theta[e] = th;
-    if (bf16_out)
-        bf16_out[e] = float_to_bf16_rne(th);
+    if (j.bf16[q])
+        j.bf16[q][e] = float_to_bf16_rne(th);
+}
+
+hipError_t launch_adam_many(const AdamJobs &j, int n, float lr, float beta1, float beta2, float eps, int64_t t,
+                            hipStream_t s)
+{
+    const float bc1 = (float)(1.0 - pow((double)beta1, (double)t));
+    const float bc2 = (float)(1.0 - pow((double)beta2, (double)t));
+    int64_t most = 0;
+    for (int q = 0; q < n; ++q)
+        most = std::max(most, j.count[q]);
+    if (n > 0 && most > 0)
+        hipLaunchKernelGGL(k_adam_many, dim3((unsigned)((most + 255) / 256), n), dim3(256), 0, s, j, lr, beta1, beta2,
+                           eps, bc1, bc2);
+    return hipGetLastError();
 }
 
 // x[n, c, p] = x[n, c, p] * scale[c] + shift[c] for c < nc (in place).
@@ -528,35 +705,40 @@ static bool shape_ok(const lbm_cnn_shape *s)
            s->cin <= 32 && (int64_t)s->h * s->w <= (1 << 26) && s->n <= 65535;
 }
 
-// co output channels in groups of OG (co % OG == 0)
-template <int OG, int TR>
-static hipError_t conv(const float *x, int ci, const float *w, int co, const float *b, const float *resid,
+// wb in the B layout [co][ci * 9] (the weights, or k_widen_tr's transposed
+// flipped weights for an input gradient)
+static hipError_t conv(const float *x, int ci, const float *wb, int co, const float *b, const float *resid,
                        int resid_c, const float *mask, int relu, float *y, int N, int H, int W, hipStream_t s)
 {
-    dim3 grd((W + kTile - 1) / kTile, (H + kTile - 1) / kTile, N * (co / OG));
-    hipLaunchKernelGGL((k_conv3x3<OG, TR>), grd, dim3(256), 0, s, x, ci, w, co, b, resid, resid_c, mask, relu, y, H,
-                       W);
+    dim3 grd((W + kTW - 1) / kTW, (H + kTH - 1) / kTH, N);
+    const int ch = (ci + 1) / 2;
+    if (ch == 16)
+        hipLaunchKernelGGL(k_conv3x3<16>, grd, dim3(256), 0, s, x, ci, wb, co, b, resid, resid_c, mask, relu, y, H, W);
+    else if (ch == 2)
+        hipLaunchKernelGGL(k_conv3x3<2>, grd, dim3(256), 0, s, x, ci, wb, co, b, resid, resid_c, mask, relu, y, H, W);
+    else
+        hipLaunchKernelGGL(k_conv3x3<0>, grd, dim3(256), 0, s, x, ci, wb, co, b, resid, resid_c, mask, relu, y, H, W);
     return hipGetLastError();
 }
 
-static int conv_tiles(int H, int W) { return ((H + kTile - 1) / kTile) * ((W + kTile - 1) / kTile); }
+static int conv_tiles(int H, int W) { return ((H + kTH - 1) / kTH) * ((W + kTW - 1) / kTW); }
 
 // Weight and bias gradients of one layer (co output, ci input channels):
 // per-tile partials, then their ordered sum.
-template <int OG>
 static hipError_t wgrad(const float *dy, int co, const float *x, int ci, int N, int H, int W, float *part, float *gw,
                         float *gb, hipStream_t s)
 {
     const int blocks = N * conv_tiles(H, W);
-    hipLaunchKernelGGL((k_conv3x3_wgrad<OG>), dim3(blocks), dim3(256), 0, s, dy, co, x, ci, H, W, part);
+    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(blocks), dim3(64 * kWgWaves), 0, s, dy, co, x, ci, H, W, part);
     const int total = co * ci * 9 + co;
-    hipLaunchKernelGGL(k_grad_reduce, dim3((total + 63) / 64), dim3(256), 0, s, part, blocks, co * ci * 9, co, gw,
-                       gb);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((total + kReduceCols - 1) / kReduceCols), dim3(256), 0, s, part, blocks,
+                       co * ci * 9, co, gw, gb);
     return hipGetLastError();
 }
 
 struct CnnWs {
-    float *w[3];     // widened weights
+    float *w[3];     // widened weights [co][ci * 9]
+    float *wt[3];    // the input-gradient convolutions' weights (layers 2 and 3)
     double *part;    // loss partials
     float *gpart;    // per-tile gradient partials
     float *dy;       // dL/dy [n][cout][hw]
@@ -574,43 +756,46 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 static CnnWs cnn_layout(const lbm_cnn_shape *s, char *base)
 {
     CnnWs L{};
-    size_t off = 0, o[7];
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return base ? base + o : nullptr;
+    };
     const int64_t hw = (int64_t)s->h * s->w;
     const int64_t sizes[3] = {n_w(s->hidden, s->cin), n_w(s->hidden, s->hidden), n_w(s->cout, s->hidden)};
-    for (int k = 0; k < 3; ++k) {
-        o[k] = off;
-        off = align256(off + sizes[k] * sizeof(float));
-    }
-    o[3] = off;
-    off = align256(off + kMseBlocks * sizeof(double));
-    const size_t gpart = off;  // the largest layer: hidden x hidden weights
-    off = align256(off + (size_t)s->n * conv_tiles(s->h, s->w) *
-                             (size_t)(s->hidden * std::max(s->hidden, s->cin) * 9 + s->hidden) * sizeof(float));
-    o[4] = off;
-    off = align256(off + (size_t)s->n * s->cout * hw * sizeof(float));
-    o[5] = off;
-    off = align256(off + (size_t)s->n * s->hidden * hw * sizeof(float));
-    o[6] = off;
-    off = align256(off + (size_t)s->n * s->hidden * hw * sizeof(float));
+    for (int k = 0; k < 3; ++k)
+        L.w[k] = (float *)take(sizes[k] * sizeof(float));
+    for (int k = 1; k < 3; ++k)
+        L.wt[k] = (float *)take(sizes[k] * sizeof(float));
+    L.part = (double *)take(kMseBlocks * sizeof(double));
+    // per-tile partials of the largest layer (hidden x max(hidden, cin) weights)
+    L.gpart = (float *)take((size_t)s->n * conv_tiles(s->h, s->w) *
+                            (size_t)(s->hidden * std::max(s->hidden, s->cin) * 9 + s->hidden) * sizeof(float));
+    L.dy = (float *)take((size_t)s->n * s->cout * hw * sizeof(float));
+    L.dz2 = (float *)take((size_t)s->n * s->hidden * hw * sizeof(float));
+    L.dz1 = (float *)take((size_t)s->n * s->hidden * hw * sizeof(float));
     L.total = off;
-    if (base) {
-        for (int k = 0; k < 3; ++k)
-            L.w[k] = (float *)(base + o[k]);
-        L.part = (double *)(base + o[3]);
-        L.gpart = (float *)(base + gpart);
-        L.dy = (float *)(base + o[4]);
-        L.dz2 = (float *)(base + o[5]);
-        L.dz1 = (float *)(base + o[6]);
-    }
     return L;
 }
 
-static hipError_t widen(const lbm_cnn_shape *s, const lbm_cnn_params *p, const CnnWs &L, hipStream_t st)
+// forward: the three weight tensors as they are; backward: the transposed,
+// flipped weights of layers 2 and 3
+static hipError_t widen(const lbm_cnn_shape *s, const lbm_cnn_params *p, const CnnWs &L, bool backward,
+                        hipStream_t st)
 {
-    const int64_t sizes[3] = {n_w(s->hidden, s->cin), n_w(s->hidden, s->hidden), n_w(s->cout, s->hidden)};
-    for (int k = 0; k < 3; ++k)
-        hipLaunchKernelGGL(k_widen_bf16, dim3((unsigned)((sizes[k] + 255) / 256)), dim3(256), 0, st, p->w[k], sizes[k],
-                           L.w[k]);
+    const int co[3] = {s->hidden, s->hidden, s->cout}, ci[3] = {s->cin, s->hidden, s->hidden};
+    WidenJobs j{};
+    int nj = 0, most = 0;
+    for (int k = backward ? 1 : 0; k < 3; ++k, ++nj) {
+        j.w[nj] = p->w[k];
+        j.out[nj] = backward ? L.wt[k] : L.w[k];
+        j.co[nj] = co[k];
+        j.ci[nj] = ci[k];
+        j.tr[nj] = backward;
+        most = std::max(most, co[k] * ci[k] * 9);
+    }
+    hipLaunchKernelGGL(k_widen, dim3((most + 255) / 256, nj), dim3(256), 0, st, j);
     return hipGetLastError();
 }
 
@@ -641,10 +826,10 @@ int32_t lbm_cnn_forward(const lbm_cnn_shape *s, const lbm_cnn_params *p, const f
     if (ws_bytes < L.total)
         return fail(LBM_EINVAL, "workspace smaller than lbm_cnn_workspace_bytes()");
     hipStream_t st = (hipStream_t)stream;
-    LBM_HIP_TRY(widen(s, p, L, st));
-    LBM_HIP_TRY((conv<8, 0>(x, s->cin, L.w[0], 32, p->b[0], nullptr, 0, nullptr, 1, a1, s->n, s->h, s->w, st)));
-    LBM_HIP_TRY((conv<8, 0>(a1, 32, L.w[1], 32, p->b[1], nullptr, 0, nullptr, 1, a2, s->n, s->h, s->w, st)));
-    LBM_HIP_TRY((conv<3, 0>(a2, 32, L.w[2], 3, p->b[2], x, s->cin, nullptr, 0, y, s->n, s->h, s->w, st)));
+    LBM_HIP_TRY(widen(s, p, L, false, st));
+    LBM_HIP_TRY(conv(x, s->cin, L.w[0], 32, p->b[0], nullptr, 0, nullptr, 1, a1, s->n, s->h, s->w, st));
+    LBM_HIP_TRY(conv(a1, 32, L.w[1], 32, p->b[1], nullptr, 0, nullptr, 1, a2, s->n, s->h, s->w, st));
+    LBM_HIP_TRY(conv(a2, 32, L.w[2], 3, p->b[2], x, s->cin, nullptr, 0, y, s->n, s->h, s->w, st));
     return LBM_OK;
 }
 
@@ -665,17 +850,17 @@ int32_t lbm_cnn_backward(const lbm_cnn_shape *s, const lbm_cnn_params *p, const 
     hipStream_t st = (hipStream_t)stream;
     const int N = s->n, H = s->h, W = s->w;
     const int64_t hw = (int64_t)H * W, count = (int64_t)N * s->cout * hw;
-    LBM_HIP_TRY(widen(s, p, L, st));
+    LBM_HIP_TRY(widen(s, p, L, true, st));
     hipLaunchKernelGGL(k_mse, dim3(kMseBlocks), dim3(256), 0, st, y, target, count, L.dy, L.part);
     hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(256), 0, st, L.part, kMseBlocks, count, loss);
     // layer 3: y = x[:cout] + conv(a2, w2) + b2
-    LBM_HIP_TRY(wgrad<3>(L.dy, s->cout, a2, 32, N, H, W, L.gpart, g->w[2], g->b[2], st));
-    LBM_HIP_TRY((conv<8, 1>(L.dy, s->cout, L.w[2], 32, nullptr, nullptr, 0, a2, 0, L.dz2, N, H, W, st)));
+    LBM_HIP_TRY(wgrad(L.dy, s->cout, a2, 32, N, H, W, L.gpart, g->w[2], g->b[2], st));
+    LBM_HIP_TRY(conv(L.dy, s->cout, L.wt[2], 32, nullptr, nullptr, 0, a2, 0, L.dz2, N, H, W, st));
     // layer 2: a2 = relu(conv(a1, w1) + b1)
-    LBM_HIP_TRY(wgrad<4>(L.dz2, 32, a1, 32, N, H, W, L.gpart, g->w[1], g->b[1], st));
-    LBM_HIP_TRY((conv<8, 1>(L.dz2, 32, L.w[1], 32, nullptr, nullptr, 0, a1, 0, L.dz1, N, H, W, st)));
+    LBM_HIP_TRY(wgrad(L.dz2, 32, a1, 32, N, H, W, L.gpart, g->w[1], g->b[1], st));
+    LBM_HIP_TRY(conv(L.dz2, 32, L.wt[1], 32, nullptr, nullptr, 0, a1, 0, L.dz1, N, H, W, st));
     // layer 1: a1 = relu(conv(x, w0) + b0)
-    LBM_HIP_TRY(wgrad<4>(L.dz1, 32, x, s->cin, N, H, W, L.gpart, g->w[0], g->b[0], st));
+    LBM_HIP_TRY(wgrad(L.dz1, 32, x, s->cin, N, H, W, L.gpart, g->w[0], g->b[0], st));
     LBM_HIP_TRY(hipGetLastError());
     return LBM_OK;
 }
@@ -687,11 +872,14 @@ int32_t lbm_cnn_adam(float *theta, float *m, float *v, const float *grad, int64_
         return fail(LBM_EINVAL, "invalid Adam arguments");
     if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
         return fail(LBM_EINVAL, "invalid Adam hyper-parameters");
-    const float bc1 = (float)(1.0 - pow((double)beta1, (double)t));
-    const float bc2 = (float)(1.0 - pow((double)beta2, (double)t));
-    if (count > 0)
-        hipLaunchKernelGGL(k_adam, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, (hipStream_t)stream, theta, m,
-                           v, grad, count, lr, beta1, beta2, eps, bc1, bc2, bf16_out);
+    AdamJobs j{};
+    j.theta[0] = theta;
+    j.m[0] = m;
+    j.v[0] = v;
+    j.g[0] = grad;
+    j.count[0] = count;
+    j.bf16[0] = bf16_out;
+    LBM_HIP_TRY(launch_adam_many(j, 1, lr, beta1, beta2, eps, t, (hipStream_t)stream));
     LBM_HIP_TRY(hipGetLastError());
     return LBM_OK;
 }

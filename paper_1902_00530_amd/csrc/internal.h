@@ -53,6 +53,17 @@ hipError_t launch_moments(const lbm_params &p, const StepArgs &a, const void *sr
                           float *uy, double *scratch, double *result, hipStream_t s);
 // The surrogate form of lbm_sweep_batch (opts->surrogate set; arguments
 // validated as for a plain sweep).
+// Adam (as lbm_cnn_adam) on up to kAdamMax tensors in one launch.
+constexpr int kAdamMax = 6;
+struct AdamJobs {
+    float *theta[kAdamMax], *m[kAdamMax], *v[kAdamMax];
+    const float *g[kAdamMax];
+    int64_t count[kAdamMax];
+    uint16_t *bf16[kAdamMax];  // bf16 copies of theta, or null
+};
+hipError_t launch_adam_many(const AdamJobs &j, int n, float lr, float beta1, float beta2, float eps, int64_t t,
+                            hipStream_t s);
+
 int32_t surrogate_sweep(const lbm_params *ps, int n, const lbm_sweep_opts *o, void *const *bufs, void *ws,
                         size_t ws_bytes, hipStream_t st, lbm_obs *out);
 // Turn the 8 reduced doubles into an lbm_obs (host).

@@ -570,14 +570,16 @@ int32_t lbm_surrogate_train_step(lbm_surrogate *s, const float *x, const float *
     if (rc)
         return rc;
     s->t += 1;
+    AdamJobs aj{};
     for (int k = 0; k < 6; ++k) {
-        rc = lbm_cnn_adam((float *)(s->params + s->P.theta[k]), (float *)(s->params + s->P.m[k]),
-                          (float *)(s->params + s->P.v[k]), (const float *)(s->ws + s->W.grad[k]), s->P.count[k], lr,
-                          0.9f, 0.999f, 1e-8f, s->t, k % 2 == 0 ? (uint16_t *)(s->params + s->P.wb[k / 2]) : nullptr,
-                          s->stream);
-        if (rc)
-            return rc;
+        aj.theta[k] = (float *)(s->params + s->P.theta[k]);
+        aj.m[k] = (float *)(s->params + s->P.m[k]);
+        aj.v[k] = (float *)(s->params + s->P.v[k]);
+        aj.g[k] = (const float *)(s->ws + s->W.grad[k]);
+        aj.count[k] = s->P.count[k];
+        aj.bf16[k] = k % 2 == 0 ? (uint16_t *)(s->params + s->P.wb[k / 2]) : nullptr;
     }
+    LBM_HIP_TRY(launch_adam_many(aj, 6, lr, 0.9f, 0.999f, 1e-8f, s->t, s->stream));
     if (loss)
         LBM_HIP_TRY(hipMemcpyAsync(loss, d_loss, sizeof(float), hipMemcpyDeviceToDevice, s->stream));
     return LBM_OK;

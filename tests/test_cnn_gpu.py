@@ -58,8 +58,16 @@ def rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
 
 
-def test_forward_matches_oracle(L):
-    x, t, p, g, shape, params, ws = setup(L)
+# (n, cin, h, w): ragged 16 x 8 tiles; an odd reduction length (cin 3);
+# fields smaller than a tile, whose halo wraps more than once; every input
+# channel the kernels take (cin 32)
+SHAPES = [(2, 4, 20, 24), (3, 3, 9, 17), (1, 5, 5, 7), (2, 32, 16, 32)]
+
+
+@pytest.mark.parametrize("shp", SHAPES)
+def test_forward_matches_oracle(L, shp):
+    n, cin, h, w = shp
+    x, t, p, g, shape, params, ws = setup(L, n=n, cin=cin, h=h, w=w)
     n, h, w = shape.n, shape.h, shape.w
     a1 = torch.empty((n, 32, h, w), device="cuda")
     a2 = torch.empty_like(a1)
@@ -73,8 +81,10 @@ def test_forward_matches_oracle(L):
     assert rel(y.double().cpu().numpy(), ry) < 1e-5
 
 
-def test_backward_matches_oracle(L):
-    x, t, p, g, shape, params, ws = setup(L, seed=1)
+@pytest.mark.parametrize("shp", SHAPES)
+def test_backward_matches_oracle(L, shp):
+    n, cin, h, w = shp
+    x, t, p, g, shape, params, ws = setup(L, n=n, cin=cin, h=h, w=w, seed=1)
     n, h, w = shape.n, shape.h, shape.w
     a1 = torch.empty((n, 32, h, w), device="cuda")
     a2 = torch.empty_like(a1)
