@@ -8,8 +8,9 @@
 // Layout: activations NCHW float32; weights stored as bfloat16 (the Adam
 // step keeps float32 master copies) and widened once per pass to float32, so
 // every product is a bf16 x f32 -> f32 product with float32 accumulation.
-// Convolutions and weight gradients are matrix products on the matrix cores
-// (FP32 operands) over 16 x 8 pixel tiles staged in LDS with their halo.
+// Convolutions (bf16 operands: the weights, and each activation split into
+// three bf16 parts) and weight gradients (FP32 operands) are matrix products
+// on the matrix cores over 16 x 8 pixel tiles staged in LDS with their halo.
 // Reductions (weight gradients, loss) use fixed partitions and orders, so
 // results are deterministic.
 #include <math.h>
@@ -22,36 +23,40 @@
 namespace lbm {
 
 // ---------------------------------------------------------------------------
-// 3x3 convolutions on the matrix cores (v_mfma_f32_32x32x2_f32: FP32
-// operands, FP32 accumulation, so every product is exact and only the order
-// of the sums differs from the definition).  The weights are the bf16 values
-// the network stores, widened; the activations stay FP32.  A 16 x 8 pixel
-// tile of one sample per block (four waves, one 32-pixel slab each: two
-// image rows of 16), its input with the one-pixel circular halo staged in
-// LDS, every channel at once (ci, co <= 32).
+// 3x3 convolutions on the matrix cores, bf16 operands with float32
+// accumulation (v_mfma_f32_32x32x16_bf16).  The weights are bf16 values
+// already; each float32 activation x is split into three bf16 parts, x = h +
+// m + l + r with |r| < 2^-24 |x| (h: x with its low 16 bits cleared, m and l
+// the same of the exact remainders), and the product of each part with the
+// weight is exact, so the three products together give the float32 product
+// and only the order of the float32 sums differs from the definition.  A
+// 16 x 8 pixel tile of one sample per block (four waves, one 32-pixel slab
+// each: two image rows of 16), its input split and stored channel-last in
+// LDS with the one-pixel circular halo, every channel at once (ci, co <= 32).
 //
 // Convolution as a matrix product per slab: D[pixel][o] = sum_k A[pixel][k]
-// B[k][o], k = c * 9 + tap (tap = 3 ky + kx), A the input at the pixel
-// shifted by the tap, B[k][o] = wb[o][k].  TR = 0: y[n,o,i,j] = b[o] +
-// sum_c sum_tap w[o,c,tap] x[n,c,i+ky-1,j+kx-1] (wb = w).  TR = 1 (input
-// gradient of a convolution whose weights are w[c][o][tap]): the same sum
-// with wb[o][c*9+tap] = w[c][o][8-tap], the transposed, flipped weights
-// (written by k_widen_tr).  Epilogue in order: bias, ReLU, + resid[n, o]
-// (first co channels of a tensor with resid_c channels), * (mask[n, o] > 0).
+// B[k][o], k = tap * CP + c (tap = 3 ky + kx, c < CP = ci rounded up to 16
+// with zero channels), A the input at the pixel shifted by the tap, B[k][o]
+// = wb[o][tap][c] (bf16).  TR = 0 weights: wb[o][tap][c] = w[o][c][tap]: y =
+// b[o] + sum_c sum_tap w[o,c,tap] x[n,c,i+ky-1,j+kx-1].  The input gradient
+// of a convolution whose weights are w[c][o][tap] takes wb[o][tap][c] =
+// w[c][o][8 - tap], the transposed, flipped weights (both written by
+// k_widen).  Epilogue in order: bias, ReLU, + resid[n, o] (first co channels
+// of a tensor with resid_c channels), * (mask[n, o] > 0).
 //
-// MFMA 32x32x2 operand layout (per lane l of the wave): A row l mod 32,
-// k = l / 32; B column l mod 32, k = l / 32; result register r holds row
-// 8 (r / 4) + 4 (l / 32) + r mod 4 of column l mod 32.  The reduction runs
-// in the order (channel pair, tap): lanes with k = 0 take channel c, lanes
-// with k = 1 channel c + ceil(ci / 2) (a zero channel when ci is odd), so
-// each step's LDS offsets differ from the lane's base by a constant.
+// MFMA 32x32x16 operand layout (per lane l of the wave): A row l mod 32 with
+// k = 8 (l / 32) + j, j < 8; B column l mod 32, the same k; result register r
+// holds row 8 (r / 4) + 4 (l / 32) + r mod 4 of column l mod 32.  Each step
+// takes one tap and 16 channels, so a lane's eight A values (channels c0 +
+// 8 (l / 32) ..) and eight B values are 16 contiguous bytes of LDS.
 // ---------------------------------------------------------------------------
 constexpr int kTW = 16, kTH = 8;                   // pixel tile
 constexpr int kHW_ = kTW + 2, kHH = kTH + 2;       // with the halo
 constexpr int kHalo = kHW_ * kHH;                  // 180 pixels
-constexpr int kMaxC = 32, kMaxK = kMaxC * 9;       // channels, reduction length
+constexpr int kMaxC = 32;                          // channels
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // v in [-1, n + kHW_ - 2] wrapped into [0, n); SMALL: n may be smaller than
 // the halo tile, so v may wrap more than once
@@ -64,8 +69,8 @@ __device__ __forceinline__ int wrap_index(int v, int n)
 }
 
 // LDS staging with every global load of a thread in flight before the first
-// LDS write: element e < count of the block's copy is get(e) (a load from an
-// address that is valid for every e < count) stored at put(e).
+// LDS write: element e < count (count > 0) of the block's copy is get(e) (a
+// load from an address that is valid for every e < count) stored by put(e).
 template <int NT, int MAXE, class Get, class Put>
 __device__ __forceinline__ void stage(int count, Get get, Put put)
 {
@@ -82,100 +87,109 @@ __device__ __forceinline__ void stage(int count, Get get, Put put)
     }
 }
 
-// the input tile of sample n with its circular halo: s[c][hy][hx], c < cpad
-// <= MAXC (channels ci_n .. cpad-1 zero); halo values of pixels outside the
-// field feed no output.  Offsets within a sample fit 32 bits (ci h w < 2^31).
-template <int NT, int MAXC, bool SMALL>
-__device__ __forceinline__ void stage_halo_(const float *__restrict__ xn, int ci_n, int cpad, int H, int W, int i0,
-                                            int j0, float *s)
+// element e = c * kHalo + hy * kHW_ + hx of the input tile of sample n with
+// its circular halo (0 for c >= ci_n); offsets within a sample fit 32 bits
+// (ci h w < 2^31)
+template <bool SMALL>
+__device__ __forceinline__ float halo_value(const float *__restrict__ xn, int ci_n, int H, int W, int i0, int j0, int e)
 {
-    const unsigned HW = (unsigned)H * (unsigned)W;
-    stage<NT, MAXC * kHalo>(
-        cpad * kHalo,
-        [&](int e) {
-            const int c = e / kHalo, r = e - c * kHalo, hy = r / kHW_, hx = r - hy * kHW_;
-            const int gi = wrap_index<SMALL>(i0 + hy - 1, H), gj = wrap_index<SMALL>(j0 + hx - 1, W);
-            const float v = xn[(unsigned)min(c, ci_n - 1) * HW + (unsigned)gi * (unsigned)W + (unsigned)gj];
-            return c < ci_n ? v : 0.0f;
-        },
-        [&](int e, float v) { s[e] = v; });
+    const int c = e / kHalo, r = e - c * kHalo, hy = r / kHW_, hx = r - hy * kHW_;
+    const int gi = wrap_index<SMALL>(i0 + hy - 1, H), gj = wrap_index<SMALL>(j0 + hx - 1, W);
+    const float v = xn[(unsigned)min(c, ci_n - 1) * (unsigned)H * (unsigned)W + (unsigned)gi * (unsigned)W + (unsigned)gj];
+    return c < ci_n ? v : 0.0f;
 }
 
+// the input tile as float32, s[c][hy][hx], c < cpad <= MAXC (halo values of
+// pixels outside the field feed no output)
 template <int NT, int MAXC>
 __device__ __forceinline__ void stage_halo(const float *__restrict__ x, int n, int ci_n, int cpad, int H, int W, int i0,
                                            int j0, float *s)
 {
     const float *xn = x + (size_t)n * ci_n * H * W;
+    auto put = [&](int e, float v) { s[e] = v; };
     if (H >= kHH && W >= kHW_)
-        stage_halo_<NT, MAXC, false>(xn, ci_n, cpad, H, W, i0, j0, s);
+        stage<NT, MAXC * kHalo>(cpad * kHalo, [&](int e) { return halo_value<false>(xn, ci_n, H, W, i0, j0, e); }, put);
     else
-        stage_halo_<NT, MAXC, true>(xn, ci_n, cpad, H, W, i0, j0, s);
+        stage<NT, MAXC * kHalo>(cpad * kHalo, [&](int e) { return halo_value<true>(xn, ci_n, H, W, i0, j0, e); }, put);
 }
 
-__device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c)
+// the three bf16 parts of x (bit patterns): x = h + m + l + r, |r| < 2^-24 |x|
+__device__ __forceinline__ void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l)
 {
-    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+    const uint32_t hb = __float_as_uint(x) & 0xffff0000u;
+    const float r1 = x - __uint_as_float(hb);  // exact: the low 16 bits of x
+    const uint32_t mb = __float_as_uint(r1) & 0xffff0000u;
+    const float r2 = r1 - __uint_as_float(mb);  // exact
+    h = (uint16_t)(hb >> 16);
+    m = (uint16_t)(mb >> 16);
+    l = (uint16_t)(__float_as_uint(r2) >> 16);
 }
 
-// CHT > 0: ceil(ci / 2) fixed at compile time (the channel loop unrolls
-// completely, so the operand loads run ahead of the products); 0: any ci.
-template <int CHT>
-__global__ __launch_bounds__(256) void k_conv3x3(const float *__restrict__ x, int ci_n, const float *__restrict__ wb,
+__device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// CP: input channels rounded up to 16 (16 or 32).
+template <int CP>
+__global__ __launch_bounds__(256) void k_conv3x3(const float *__restrict__ x, int ci_n, const uint16_t *__restrict__ wb,
                                                  int co_n, const float *__restrict__ bias,
                                                  const float *__restrict__ resid, int resid_c,
                                                  const float *__restrict__ mask, int relu, float *__restrict__ y,
                                                  int H, int W)
 {
-    constexpr int KS = kMaxK + 1;  // weight row stride (odd: the 32 columns of a read hit distinct banks)
-    // one channel / one channel's taps of slack: the loop reads the operands
-    // of the step after the last one, and discards them
-    __shared__ float s_in[(kMaxC + 1) * kHalo];
-    __shared__ float s_w[kMaxC * KS + 9];
+    // strides (bf16 elements) padded so that eight consecutive lanes' 16-byte
+    // reads fall in distinct banks
+    constexpr int CPS = CP + 8, WS = 9 * CP + 8;
+    __shared__ __attribute__((aligned(16))) uint16_t s_x[3 * kHalo * CPS];  // [part][pixel][channel]
+    __shared__ __attribute__((aligned(16))) uint16_t s_w[kMaxC * WS];      // [out][tap][channel]
     const int n = blockIdx.z, i0 = blockIdx.y * kTH, j0 = blockIdx.x * kTW;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int CH = CHT > 0 ? CHT : (ci_n + 1) >> 1, K = ci_n * 9, Kp = 2 * CH * 9;
-    stage_halo<256, kMaxC>(x, n, ci_n, 2 * CH, H, W, i0, j0, s_in);
-    // B: s_w[o][k] = wb[o][k]; rows o >= co_n and the padding channel zero
-    stage<256, kMaxC * KS>(
-        kMaxC * KS,
-        [&](int e) {
-            const int o = e / KS, k = e - o * KS;
-            const bool ok = o < co_n && k < K;
-            const float v = wb[ok ? o * K + k : 0];
-            return ok ? v : 0.0f;
-        },
-        [&](int e, float v) { s_w[e] = v; });
+    {
+        const float *xn = x + (size_t)n * ci_n * H * W;
+        auto put = [&](int e, float v) {
+            const int c = e / kHalo, pix = e - c * kHalo;
+            uint16_t h, m, l;
+            split3(v, h, m, l);
+            s_x[pix * CPS + c] = h;
+            s_x[(kHalo + pix) * CPS + c] = m;
+            s_x[(2 * kHalo + pix) * CPS + c] = l;
+        };
+        if (H >= kHH && W >= kHW_)
+            stage<256, CP * kHalo>(CP * kHalo, [&](int e) { return halo_value<false>(xn, ci_n, H, W, i0, j0, e); },
+                                   put);
+        else
+            stage<256, CP * kHalo>(CP * kHalo, [&](int e) { return halo_value<true>(xn, ci_n, H, W, i0, j0, e); },
+                                   put);
+    }
+    // B: rows o < co_n of wb (9 CP bf16 each, 16-byte pieces), zero rows after
+    {
+        constexpr int RQ = 9 * CP / 8;  // 16-byte pieces per row
+        const uint4 *src = (const uint4 *)wb;
+        for (int e = threadIdx.x; e < kMaxC * RQ; e += 256) {
+            const int o = e / RQ, q = e - o * RQ;
+            const uint4 v = o < co_n ? src[(size_t)o * RQ + q] : make_uint4(0u, 0u, 0u, 0u);
+            *(uint4 *)(s_w + o * WS + q * 8) = v;
+        }
+    }
     __syncthreads();
-    const int m = lane & 31, hk = lane >> 5;        // A row (pixel of the slab) / B column, k within the pair
+    const int m = lane & 31, hk = lane >> 5;        // A row (pixel of the slab) / B column, k half
     const int pr = 2 * wv + (m >> 4), pc = m & 15;  // tile row and column of the A row's pixel
-    const float *pa = s_in + hk * CH * kHalo + pr * kHW_ + pc;
-    const float *pb = s_w + m * KS + hk * CH * 9;
+    const uint16_t *pa = s_x + (pr * kHW_ + pc) * CPS + 8 * hk;
+    const uint16_t *pb = s_w + m * WS + 8 * hk;
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r)
         acc[r] = 0.0f;
-    // channel step c's operands load while step c - 1 multiplies
-    float av[9], bv[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-        av[t] = pa[(t / 3) * kHW_ + t % 3];
-        bv[t] = pb[t];
-    }
-#pragma unroll(CHT > 0 ? CHT : 1)
-    for (int c = 0; c < CH; ++c) {
-        pa += kHalo;
-        pb += 9;
-        float an[9], bn[9];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            an[t] = pa[(t / 3) * kHW_ + t % 3];
-            bn[t] = pb[t];
-        }
+        for (int c0 = 0; c0 < CP; c0 += 16) {
+            const bf16x8 b = *(const bf16x8 *)(pb + t * CP + c0);
+            const int off = ((t / 3) * kHW_ + t % 3) * CPS + c0;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            acc = mfma32(av[t], bv[t], acc);
-            av[t] = an[t];
-            bv[t] = bn[t];
+            for (int part = 0; part < 3; ++part)
+                acc = mfma_bf16(*(const bf16x8 *)(pa + part * kHalo * CPS + off), b, acc);
         }
     }
     // lane: output channel o = m; register group g holds the four pixels
@@ -428,27 +442,28 @@ __global__ __launch_bounds__(256) void k_mse_final(const double *__restrict__ pa
         *loss = (float)((((s_red[0] + s_red[1]) + s_red[2]) + s_red[3]) / (double)count);
 }
 
-// bf16 weights w[co][ci][9] -> float32 working copies, up to three tensors
-// per launch (blockIdx.y): tr = 0 copies, tr = 1 writes the weights of the
-// input-gradient convolution, out[i][o * 9 + t] = w[o][i][8 - t].
+// bf16 weights -> the B layout of a convolution, out[o][tap][c] (c < cp, zero
+// for c >= ci), up to three tensors per launch (blockIdx.y).  tr = 0: the
+// convolution's own weights w[o][c][tap]; tr = 1: the input gradient of a
+// convolution whose weights are w[c][o][tap], out[o][tap][c] = w[c][o][8 -
+// tap].
 struct WidenJobs {
     const uint16_t *w[3];
-    float *out[3];
-    int co[3], ci[3], tr[3];
+    uint16_t *out[3];
+    int co[3], ci[3], cp[3], tr[3];
 };
 
 __global__ void k_widen(WidenJobs j)
 {
-    const int q = blockIdx.y, co = j.co[q], ci = j.ci[q];
+    const int q = blockIdx.y, co = j.co[q], ci = j.ci[q], cp = j.cp[q];
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= co * ci * 9)
+    if (e >= co * 9 * cp)
         return;
-    int src = e;
-    if (j.tr[q]) {
-        const int i = e / (co * 9), r = e - i * (co * 9), o = r / 9, t = r - o * 9;
-        src = (o * ci + i) * 9 + (8 - t);
-    }
-    j.out[q][e] = bf16_bits_to_float(j.w[q][src]);
+    const int o = e / (9 * cp), r = e - o * (9 * cp), t = r / cp, c = r - t * cp;
+    uint16_t v = 0;
+    if (c < ci)
+        v = j.tr[q] ? j.w[q][(c * co + o) * 9 + (8 - t)] : j.w[q][(o * ci + c) * 9 + t];
+    j.out[q][e] = v;
 }
 
 // Adam (Kingma & Ba, algorithm 1) on float32 master tensors, up to kAdamMax
@@ -697,27 +712,23 @@ __global__ __launch_bounds__(256) void k_lift(const float *__restrict__ coarse, 
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-static int64_t n_w(int a, int b) { return (int64_t)a * b * 9; }
-
 static bool shape_ok(const lbm_cnn_shape *s)
 {
     return s && s->n > 0 && s->h > 0 && s->w > 0 && s->hidden == 32 && s->cout == 3 && s->cin >= 3 &&
            s->cin <= 32 && (int64_t)s->h * s->w <= (1 << 26) && s->n <= 65535;
 }
 
-// wb in the B layout [co][ci * 9] (the weights, or k_widen_tr's transposed
-// flipped weights for an input gradient)
-static hipError_t conv(const float *x, int ci, const float *wb, int co, const float *b, const float *resid,
+static int pad16(int c) { return c <= 16 ? 16 : 32; }
+
+// wb: bf16 weights in the B layout [co][9][pad16(ci)] (k_widen)
+static hipError_t conv(const float *x, int ci, const uint16_t *wb, int co, const float *b, const float *resid,
                        int resid_c, const float *mask, int relu, float *y, int N, int H, int W, hipStream_t s)
 {
     dim3 grd((W + kTW - 1) / kTW, (H + kTH - 1) / kTH, N);
-    const int ch = (ci + 1) / 2;
-    if (ch == 16)
+    if (pad16(ci) == 16)
         hipLaunchKernelGGL(k_conv3x3<16>, grd, dim3(256), 0, s, x, ci, wb, co, b, resid, resid_c, mask, relu, y, H, W);
-    else if (ch == 2)
-        hipLaunchKernelGGL(k_conv3x3<2>, grd, dim3(256), 0, s, x, ci, wb, co, b, resid, resid_c, mask, relu, y, H, W);
     else
-        hipLaunchKernelGGL(k_conv3x3<0>, grd, dim3(256), 0, s, x, ci, wb, co, b, resid, resid_c, mask, relu, y, H, W);
+        hipLaunchKernelGGL(k_conv3x3<32>, grd, dim3(256), 0, s, x, ci, wb, co, b, resid, resid_c, mask, relu, y, H, W);
     return hipGetLastError();
 }
 
@@ -737,13 +748,13 @@ static hipError_t wgrad(const float *dy, int co, const float *x, int ci, int N, 
 }
 
 struct CnnWs {
-    float *w[3];     // widened weights [co][ci * 9]
-    float *wt[3];    // the input-gradient convolutions' weights (layers 2 and 3)
-    double *part;    // loss partials
-    float *gpart;    // per-tile gradient partials
-    float *dy;       // dL/dy [n][cout][hw]
-    float *dz2;      // [n][hidden][hw]
-    float *dz1;      // [n][hidden][hw]
+    uint16_t *wb[3];   // the layers' weights in the convolutions' B layout [co][9][pad16(ci)]
+    uint16_t *wbt[3];  // the input-gradient convolutions' weights (layers 2 and 3)
+    double *part;      // loss partials
+    float *gpart;      // per-tile gradient partials
+    float *dy;         // dL/dy [n][cout][hw]
+    float *dz2;        // [n][hidden][hw]
+    float *dz1;        // [n][hidden][hw]
     size_t total;
 };
 
@@ -751,8 +762,8 @@ static const int kMseBlocks = 1024;
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Workspace: widened weights, loss partials and the backward pass's
-// intermediate gradients.  base == nullptr only measures the size.
+// Workspace: the weights in the B layout, loss partials and the backward
+// pass's intermediate gradients.  base == nullptr only measures the size.
 static CnnWs cnn_layout(const lbm_cnn_shape *s, char *base)
 {
     CnnWs L{};
@@ -763,11 +774,11 @@ static CnnWs cnn_layout(const lbm_cnn_shape *s, char *base)
         return base ? base + o : nullptr;
     };
     const int64_t hw = (int64_t)s->h * s->w;
-    const int64_t sizes[3] = {n_w(s->hidden, s->cin), n_w(s->hidden, s->hidden), n_w(s->cout, s->hidden)};
+    const int co[3] = {s->hidden, s->hidden, s->cout}, ci[3] = {s->cin, s->hidden, s->hidden};
     for (int k = 0; k < 3; ++k)
-        L.w[k] = (float *)take(sizes[k] * sizeof(float));
+        L.wb[k] = (uint16_t *)take((size_t)co[k] * 9 * pad16(ci[k]) * sizeof(uint16_t));
     for (int k = 1; k < 3; ++k)
-        L.wt[k] = (float *)take(sizes[k] * sizeof(float));
+        L.wbt[k] = (uint16_t *)take((size_t)ci[k] * 9 * pad16(co[k]) * sizeof(uint16_t));
     L.part = (double *)take(kMseBlocks * sizeof(double));
     // per-tile partials of the largest layer (hidden x max(hidden, cin) weights)
     L.gpart = (float *)take((size_t)s->n * conv_tiles(s->h, s->w) *
@@ -779,8 +790,9 @@ static CnnWs cnn_layout(const lbm_cnn_shape *s, char *base)
     return L;
 }
 
-// forward: the three weight tensors as they are; backward: the transposed,
-// flipped weights of layers 2 and 3
+// forward: the three layers' convolutions; backward: the input-gradient
+// convolutions of layers 2 and 3 (their output channels are the layer's
+// inputs)
 static hipError_t widen(const lbm_cnn_shape *s, const lbm_cnn_params *p, const CnnWs &L, bool backward,
                         hipStream_t st)
 {
@@ -789,11 +801,12 @@ static hipError_t widen(const lbm_cnn_shape *s, const lbm_cnn_params *p, const C
     int nj = 0, most = 0;
     for (int k = backward ? 1 : 0; k < 3; ++k, ++nj) {
         j.w[nj] = p->w[k];
-        j.out[nj] = backward ? L.wt[k] : L.w[k];
-        j.co[nj] = co[k];
-        j.ci[nj] = ci[k];
+        j.out[nj] = backward ? L.wbt[k] : L.wb[k];
+        j.co[nj] = backward ? ci[k] : co[k];
+        j.ci[nj] = backward ? co[k] : ci[k];
+        j.cp[nj] = pad16(j.ci[nj]);
         j.tr[nj] = backward;
-        most = std::max(most, co[k] * ci[k] * 9);
+        most = std::max(most, j.co[nj] * 9 * j.cp[nj]);
     }
     hipLaunchKernelGGL(k_widen, dim3((most + 255) / 256, nj), dim3(256), 0, st, j);
     return hipGetLastError();
@@ -827,9 +840,9 @@ int32_t lbm_cnn_forward(const lbm_cnn_shape *s, const lbm_cnn_params *p, const f
         return fail(LBM_EINVAL, "workspace smaller than lbm_cnn_workspace_bytes()");
     hipStream_t st = (hipStream_t)stream;
     LBM_HIP_TRY(widen(s, p, L, false, st));
-    LBM_HIP_TRY(conv(x, s->cin, L.w[0], 32, p->b[0], nullptr, 0, nullptr, 1, a1, s->n, s->h, s->w, st));
-    LBM_HIP_TRY(conv(a1, 32, L.w[1], 32, p->b[1], nullptr, 0, nullptr, 1, a2, s->n, s->h, s->w, st));
-    LBM_HIP_TRY(conv(a2, 32, L.w[2], 3, p->b[2], x, s->cin, nullptr, 0, y, s->n, s->h, s->w, st));
+    LBM_HIP_TRY(conv(x, s->cin, L.wb[0], 32, p->b[0], nullptr, 0, nullptr, 1, a1, s->n, s->h, s->w, st));
+    LBM_HIP_TRY(conv(a1, 32, L.wb[1], 32, p->b[1], nullptr, 0, nullptr, 1, a2, s->n, s->h, s->w, st));
+    LBM_HIP_TRY(conv(a2, 32, L.wb[2], 3, p->b[2], x, s->cin, nullptr, 0, y, s->n, s->h, s->w, st));
     return LBM_OK;
 }
 
@@ -855,10 +868,10 @@ int32_t lbm_cnn_backward(const lbm_cnn_shape *s, const lbm_cnn_params *p, const 
     hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(256), 0, st, L.part, kMseBlocks, count, loss);
     // layer 3: y = x[:cout] + conv(a2, w2) + b2
     LBM_HIP_TRY(wgrad(L.dy, s->cout, a2, 32, N, H, W, L.gpart, g->w[2], g->b[2], st));
-    LBM_HIP_TRY(conv(L.dy, s->cout, L.wt[2], 32, nullptr, nullptr, 0, a2, 0, L.dz2, N, H, W, st));
+    LBM_HIP_TRY(conv(L.dy, s->cout, L.wbt[2], 32, nullptr, nullptr, 0, a2, 0, L.dz2, N, H, W, st));
     // layer 2: a2 = relu(conv(a1, w1) + b1)
     LBM_HIP_TRY(wgrad(L.dz2, 32, a1, 32, N, H, W, L.gpart, g->w[1], g->b[1], st));
-    LBM_HIP_TRY(conv(L.dz2, 32, L.wt[1], 32, nullptr, nullptr, 0, a1, 0, L.dz1, N, H, W, st));
+    LBM_HIP_TRY(conv(L.dz2, 32, L.wbt[1], 32, nullptr, nullptr, 0, a1, 0, L.dz1, N, H, W, st));
     // layer 1: a1 = relu(conv(x, w0) + b0)
     LBM_HIP_TRY(wgrad(L.dz1, 32, x, s->cin, N, H, W, L.gpart, g->w[0], g->b[0], st));
     LBM_HIP_TRY(hipGetLastError());
