@@ -1321,7 +1321,7 @@ static auto &g_ws = *new std::map<std::pair<int, const void *>, WsTables>();
 static bool same_args(const StepArgs &x, const StepArgs &y)
 {
     return LBM_SAME(nx) && LBM_SAME(ny) && LBM_SAME(pitch) && LBM_SAME(plane) && LBM_SAME(omega) &&
-           LBM_SAME(noise_scale) && LBM_SAME(A16) && LBM_SAME(B16) && LBM_SAME(C) && LBM_SAME(rho_star) &&
+           LBM_SAME(noise_scale) && LBM_SAME(noise_h) && LBM_SAME(A16) && LBM_SAME(B16) && LBM_SAME(C) && LBM_SAME(rho_star) &&
            LBM_SAME(inv_rho_star) && LBM_SAME(u_max) && LBM_SAME(wr0) && LBM_SAME(wr1) && LBM_SAME(wr2) &&
            LBM_SAME(key0) && LBM_SAME(key1) && LBM_SAME(noisy);
 }

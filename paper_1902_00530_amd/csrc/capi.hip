@@ -94,6 +94,7 @@ StepArgs make_step_args(const lbm_params &p, int64_t pitch)
     a.omega = (float)(1.0 / p.tau);
     const bool q9 = p.lattice == LBM_D2Q9;
     a.noise_scale = (float)(q9 ? p.sigma / 73728.0 : p.sigma / 229376.0);
+    a.noise_h = (float)(q9 ? p.sigma / 8192.0 : p.sigma / 32768.0);
     a.A16 = (float)p.A * 65536.0f;
     a.B16 = (float)p.B * 65536.0f;
     a.C = (float)p.C;

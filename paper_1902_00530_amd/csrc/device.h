@@ -22,6 +22,7 @@ struct StepArgs {
     float omega;        // 1 / tau (0 for tau = +inf)
     float noise_scale;  // D2Q7: sigma / 229376, eta_i = (7 h_i - sum h) * noise_scale;
                         // D2Q9: sigma / 73728, eta_i = (9 h_i - sum h) * noise_scale
+    float noise_h;      // D2Q7: sigma / 32768 = 7 noise_scale, the factor of h_i alone
     float A16, B16;     // CIL A and B times 2^16 (exact), see local_ustar
     float C, rho_star, inv_rho_star, u_max;  // MIPS
     float wr0, wr1, wr2;  // w_i rho_ref (deviation storages): D2Q7 rest, moving;
@@ -86,14 +87,13 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 }
 
 // Zero-sum noise of one site and step (eq. noiseDensityConservation with
-// uniform raw draws), added to f.  With 16-bit draws h_i the raw value is
-// sigma (2 h_i - 65535) / 65536; subtracting the mean over the seven
-// directions leaves sigma (7 h_i - H) / 229376 with H = sum h_i.  The h_i, H
-// and 7 h_i - H are integers below 2^20 in magnitude, exact in float; one fma
-// then scales and adds each.  The halves are taken as 16-bit values so that
-// each becomes one convert with a word select (SDWA), no mask or shift.
-__device__ __forceinline__ void site_add_noise(const StepArgs &a, uint32_t site, uint32_t t_lo, uint32_t t_hi,
-                                               float f[7])
+// uniform raw draws).  With 16-bit draws h_i the raw value is sigma (2 h_i -
+// 65535) / 65536; subtracting the mean over the seven directions leaves
+// sigma (7 h_i - H) / 229376 with H = sum h_i, taken as h_i sigma / 32768 -
+// H sigma / 229376 (one product for the site, one fma per direction).  The
+// halves are taken as 16-bit values so that each becomes one convert with a
+// word select (SDWA), no mask or shift.
+__device__ __forceinline__ void site_noise(const StepArgs &a, uint32_t site, uint32_t t_lo, uint32_t t_hi, float nz[7])
 {
     const Philox4 w = philox4x32_10(site, t_lo, t_hi, 0u, a.key0, a.key1);
     float h[7];
@@ -105,9 +105,10 @@ __device__ __forceinline__ void site_add_noise(const StepArgs &a, uint32_t site,
     h[5] = (float)(uint16_t)(w.v[2] >> 16);
     h[6] = (float)(uint16_t)w.v[3];
     const float H = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + h[6]);
+    const float hs = H * a.noise_scale;
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        f[i] = fmaf(fmaf(h[i], 7.0f, -H), a.noise_scale, f[i]);
+        nz[i] = fmaf(h[i], a.noise_h, -hs);
 }
 
 // ---------------------------------------------------------------------------
@@ -240,7 +241,10 @@ __device__ __forceinline__ void mips_ustar(const StepArgs &a, float rho, const f
 // Steady state xi(rho, u) of eq. fssD2Q7 in pair form: a_k = e_k.u,
 // base = 1 - 2|u|^2, xi_{k, k+3} = (rho/12)(base + 8 a_k^2 +- 4 a_k),
 // xi_0 = (rho/2) base.
-__device__ __forceinline__ void site_equilibrium(float rho, float ux, float uy, float eq[7])
+// ADD: eq_i + add_i, each with one rounding of the last product.
+template <bool ADD = false>
+__device__ __forceinline__ void site_equilibrium(float rho, float ux, float uy, float eq[7],
+                                                 const float *add = nullptr)
 {
     const float usq = ux * ux + uy * uy;
     const float a1 = ux;
@@ -248,14 +252,15 @@ __device__ __forceinline__ void site_equilibrium(float rho, float ux, float uy, 
     const float a3 = fmaf(kHalfSqrt3Lo, uy, fmaf(kHalfSqrt3, uy, -0.5f * ux));
     const float r12 = fmaf(rho, kTwelfthHi, rho * kTwelfthLo);
     const float base = 1.0f - 2.0f * usq;
-    eq[0] = 0.5f * rho * base;
     const float b1 = base + 8.0f * a1 * a1, b2 = base + 8.0f * a2 * a2, b3 = base + 8.0f * a3 * a3;
-    eq[1] = r12 * (b1 + 4.0f * a1);
-    eq[4] = r12 * (b1 - 4.0f * a1);
-    eq[2] = r12 * (b2 + 4.0f * a2);
-    eq[5] = r12 * (b2 - 4.0f * a2);
-    eq[3] = r12 * (b3 + 4.0f * a3);
-    eq[6] = r12 * (b3 - 4.0f * a3);
+    const float q[7] = {base,           b1 + 4.0f * a1, b2 + 4.0f * a2, b3 + 4.0f * a3,
+                        b1 - 4.0f * a1, b2 - 4.0f * a2, b3 - 4.0f * a3};
+    const float r0 = 0.5f * rho;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        const float r = i == 0 ? r0 : r12;
+        eq[i] = ADD ? fmaf(r, q[i], add[i]) : r * q[i];
+    }
 }
 
 // Compile-time variants (no uniform branches inside the site body).
@@ -277,20 +282,26 @@ template <int F, int S = kF32>
 __device__ __forceinline__ void site_collide(const StepArgs &a, float f[7], float rho, float ux, float uy,
                                              uint32_t site, uint32_t t_lo, uint32_t t_hi)
 {
-    float eq[7];
-    site_equilibrium(rho, ux, uy, eq);
-    if (F & kUnitTau) {
-        // tau = 1 (the paper's CIL runs): the relaxation lands on xi exactly
-#pragma unroll
-        for (int i = 0; i < 7; ++i)
-            f[i] = eq[i];
-    } else {
-#pragma unroll
-        for (int i = 0; i < 7; ++i)
-            f[i] = f[i] - (f[i] - eq[i]) * a.omega;
-    }
+    float nz[7];
     if (F & kNoisy)
-        site_add_noise(a, site, t_lo, t_hi, f);
+        site_noise(a, site, t_lo, t_hi, nz);
+    if (F & kUnitTau) {
+        // tau = 1 (the paper's CIL runs): the relaxation lands on xi exactly,
+        // and the noise is added by the last product of xi
+        if (F & kNoisy)
+            site_equilibrium<true>(rho, ux, uy, f, nz);
+        else
+            site_equilibrium(rho, ux, uy, f);
+    } else {
+        float eq[7];
+        site_equilibrium(rho, ux, uy, eq);
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+            f[i] = f[i] - (f[i] - eq[i]) * a.omega;
+            if (F & kNoisy)
+                f[i] += nz[i];
+        }
+    }
     const bool absorb = (F & kUnitTau) || a.omega != 0.0f;
     if constexpr (S == kF32 || S == kBf16R32) {
         if (absorb)
