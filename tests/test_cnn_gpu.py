@@ -31,9 +31,11 @@ def bf16_round(a):
     return torch.from_numpy(a).float().to(torch.bfloat16).double().numpy()
 
 
-def setup(L, n=2, cin=4, h=20, w=24, seed=0):
+def setup(L, n=2, cin=4, h=20, w=24, seed=0, spread=0.0):
     r = np.random.default_rng(seed)
     x = r.normal(size=(n, cin, h, w))
+    if spread:  # magnitudes over 10^-spread .. 10^spread
+        x *= 10.0 ** r.uniform(-spread, spread, size=x.shape)
     t = r.normal(size=(n, 3, h, w))
     p = list(ocnn.init_params(cin, 32, 3, r))
     p[1] = r.normal(size=32) * 0.1
@@ -67,7 +69,27 @@ SHAPES = [(2, 4, 20, 24), (3, 3, 9, 17), (1, 5, 5, 7), (2, 32, 16, 32)]
 @pytest.mark.parametrize("shp", SHAPES)
 def test_forward_matches_oracle(L, shp):
     n, cin, h, w = shp
-    x, t, p, g, shape, params, ws = setup(L, n=n, cin=cin, h=h, w=w)
+    _forward_case(L, setup(L, n=n, cin=cin, h=h, w=w))
+
+
+def test_forward_inputs_over_six_decades(L):
+    """The convolutions split each float32 activation into three bf16 parts
+    (what is left is below 2^-24 of the value): with input magnitudes spread
+    over six decades, every first-layer output is within float32 rounding of
+    the FP64 value relative to the sum of the magnitudes of its terms (4e-6:
+    a few dozen float32 accumulations; a split that dropped its third part
+    would err by ~2^-16, its second by ~2^-8), and the tensors keep the 1e-5
+    agreement."""
+    case = setup(L, n=2, cin=5, h=12, w=20, seed=3, spread=3.0)
+    a1 = _forward_case(L, case)
+    x, p = case[0], case[2]
+    ra1 = ocnn.forward(x, p)[0]
+    scale = ocnn.forward(np.abs(x), tuple(np.abs(q) for q in p))[0]  # sum of |term|, per output
+    assert (np.abs(a1 - ra1) <= 4e-6 * scale + 1e-30).all()
+
+
+def _forward_case(L, case):
+    x, t, p, g, shape, params, ws = case
     n, h, w = shape.n, shape.h, shape.w
     a1 = torch.empty((n, 32, h, w), device="cuda")
     a2 = torch.empty_like(a1)
@@ -79,6 +101,7 @@ def test_forward_matches_oracle(L, shp):
     assert rel(a1.double().cpu().numpy(), ra1) < 1e-5
     assert rel(a2.double().cpu().numpy(), ra2) < 1e-5
     assert rel(y.double().cpu().numpy(), ry) < 1e-5
+    return a1.double().cpu().numpy()
 
 
 @pytest.mark.parametrize("shp", SHAPES)
