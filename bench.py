@@ -64,6 +64,9 @@ def parse():
                     help="oracle steps of the 1024^2 single-thread baseline run x 6 (default: 4 steps)")
     ap.add_argument("--tile-rows", type=int, default=0,
                     help="batch work tile: 0 tuned, 1/2/4 one step per launch, 8/16 two steps per launch, 1024 lattices resident in LDS")
+    ap.add_argument("--launch", default="direct", choices=["direct", "graph"],
+                    help="batch mode: launch every kernel of the timed sweep directly (default) or replay "
+                         "captured graphs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 7 x 1024 x 1024 float buffer --steps times (counter calibration)")
     return ap.parse_args()
@@ -199,17 +202,22 @@ def time_single(L, torch, cfgs, steps, warmup, storage=0, lattice=0):
     return ms, obs
 
 
-def time_batch(L, torch, cfgs, steps, warmup, tile_rows=0, lattice=0, storage=0):
+def time_batch(L, torch, cfgs, steps, warmup, tile_rows=0, lattice=0, storage=0, use_graph=1):
     """All lattices advanced by lbm_sweep_batch (one launch per step, or per
-    two steps for the two-step tiles)."""
+    two steps for the two-step tiles), replaying captured graphs (use_graph
+    1) or launching every kernel directly (0)."""
     lats = make_lattices(L, cfgs, storage, lattice)
     b = L.Batch([lat.params for lat in lats])
     for l, lat in enumerate(lats):
         b.set_state(l, lat.state)
         lat.close()
-    b.run(warmup, tile_rows=tile_rows)
     # build the launch plan (tile-shape tuning and the captured graphs for
-    # `steps` steps) before timing; no step runs here
+    # `steps` steps; no step runs), warm up, then prepare again: that only
+    # moves each state into the first buffer of its pair, where a sweep
+    # starts (after an odd warm-up it sits in the second), so the GPU idles
+    # only briefly before the timed sweep
+    b.run(steps, tile_rows=tile_rows, use_graph=2)
+    b.run(warmup, tile_rows=tile_rows, use_graph=use_graph)
     b.run(steps, tile_rows=tile_rows, use_graph=2)
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
@@ -217,7 +225,7 @@ def time_batch(L, torch, cfgs, steps, warmup, tile_rows=0, lattice=0, storage=0)
     # the sweep is enqueued (its FP64 sample is computed on the GPU inside the
     # timed region) and its samples are read back after the timed region
     e0.record(s)
-    b.run(steps, tile_rows=tile_rows, fetch=False)
+    b.run(steps, tile_rows=tile_rows, fetch=False, use_graph=use_graph)
     e1.record(s)
     torch.cuda.synchronize()
     out = b.samples()
@@ -419,7 +427,12 @@ def main():
     t_wall = time.perf_counter()
     rows, ngr = 0, 1
     if mode == "batch":
-        ms, obs = time_batch(L, torch, cfgs, args.steps, args.warmup, args.tile_rows, lattice, args.storage)
+        # Each step launch of these batches carries 25-45 us of GPU work, far
+        # more than the host needs to issue it, and replaying a graph of the
+        # same launches took 14-28 us more GPU time per 20-step call on this
+        # ROCm: the timed sweep launches its kernels directly by default.
+        ms, obs = time_batch(L, torch, cfgs, args.steps, args.warmup, args.tile_rows, lattice, args.storage,
+                             use_graph=1 if args.launch == "graph" else 0)
         rows = time_batch.tile_rows
         ngr = time_batch.groups
         two, one = batch_launches(args.steps, rows)
@@ -433,7 +446,8 @@ def main():
             # and does half the site work: count it as half a launch
             launches = (two + 0.5 * one) * ngr
             kernel = (f"k_batch_step2<CIL,unit-tau,noisy,{rows}> (64x{rows} tiles, two steps per launch; "
-                      f"{two * ngr} launches + {one * ngr} one-step launches + 1 FP64 sample{gtxt})")
+                      f"{two * ngr} launches + {one * ngr} one-step launches + 1 FP64 sample{gtxt}; "
+                      f"{'launched directly' if args.launch == 'direct' else 'captured graphs'})")
         else:
             launches = args.steps * ngr
             tile = {1: "256x1", 2: "128x2", 4: "64x4"}.get(rows, "?")
@@ -466,7 +480,8 @@ def main():
                   3: "bf16 storage with f32 rest population, f32 math"}[args.storage],
         "data": "synthetic",
         "config": {"workload": wname, "lattices": len(cfgs), "sites": sites, "storage": args.storage,
-                   "mode": mode, **({"tile_rows": rows, "lattice_groups": ngr} if mode == "batch" else {})},
+                   "mode": mode, **({"tile_rows": rows, "lattice_groups": ngr, "launch": args.launch}
+                                    if mode == "batch" else {})},
         "roofline": (roofline_two_step(sites / ngr, per_launch, kernel, rows, sites) if rows >= 8 and not lattice
                      else roofline(args.storage, sites / (launches / args.steps), per_launch, kernel, q)
                      if rows < 8 else roofline_q9_two_step(sites / ngr, per_launch, kernel)),
@@ -496,6 +511,13 @@ def main():
 
     if not args.quick and args.workload == "cil1024x5" and args.storage == 0:
         var = {}
+        # the headline's timed sweep in the other launch form, same steps
+        other = "graph" if args.launch == "direct" else "direct"
+        mso, _ = time_batch(L, torch, cfgs, args.steps, args.warmup, args.tile_rows, lattice, args.storage,
+                            use_graph=1 if other == "graph" else 0)
+        var[f"cil1024x5_{other}_launches" if other == "direct" else "cil1024x5_graph_replay"] = {
+            "MLUPS": round(sites * args.steps / (mso / 1e3) / 1e6, 1), "ms": round(mso, 4),
+            "vs_headline": round(ms / mso, 4)}
         k = max(200, args.steps // 4)
         # the same batch with one step per launch (256 x 1 tiles): the plain
         # fused step against the HBM roofline

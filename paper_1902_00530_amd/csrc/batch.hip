@@ -1230,12 +1230,13 @@ struct GraphKey {
     const void *tiles_main, *tiles_one, *lat, *ctrl, *mt, *part, *colpart, *colmean, *results;
     int lattice, model, storage, flags, shape;
     int64_t ntiles_main, ntiles_one, nmt, n, n_samples, steps;
-    int sample, add;
+    int sample, add, rev;
     std::vector<int64_t> groups;  // tile ranges of the lattice groups
     auto tie() const
     {
         return std::tie(device, tiles_main, tiles_one, lat, ctrl, mt, part, colpart, colmean, results, lattice, model,
-                        storage, flags, shape, ntiles_main, ntiles_one, nmt, n, n_samples, steps, sample, add, groups);
+                        storage, flags, shape, ntiles_main, ntiles_one, nmt, n, n_samples, steps, sample, add, rev,
+                        groups);
     }
     bool operator==(const GraphKey &o) const { return tie() == o.tie(); }
 };
@@ -1310,6 +1311,10 @@ struct WsTables {
     std::vector<std::pair<int32_t, int32_t>> sizes;  // (nx, ny) of each lattice, in batch order
     std::vector<LatDesc> lat;
     int region[2] = {-1, -1};  // shape whose list is in the one-step / two-step region
+    // lattice groups in reverse order in the next call: each call starts with
+    // the group the previous one ended with, whose state is still in the
+    // Infinity Cache
+    bool rev_next = false;
 };
 constexpr size_t kWsRecords = 64;
 static std::mutex g_ws_mu;
@@ -1676,6 +1681,9 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     std::vector<int64_t> gkey(g_main);
     gkey.insert(gkey.end(), g_one.begin(), g_one.end());
 
+    // the order of the lattice groups in this call, and in the next one
+    const bool rev = !resident && gfirst.size() > 2 && rec.rev_next;
+    rec.rev_next = o->use_graph == 2 ? rev : (!resident && gfirst.size() > 2 && !rev);
     // moments tiles of each lattice group ([begin, end) in the lattice-ordered list)
     std::vector<int> gmt(gfirst.size(), 0);
     {
@@ -1714,7 +1722,8 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
             group_moments(0, steps);
         // every launch of the chunk for one lattice group, then the next
         const int64_t d0 = done, l0 = launches;
-        for (size_t g = 0; g + 1 < gfirst.size() && !resident; ++g) {
+        for (size_t k = 0; k + 1 < gfirst.size() && !resident; ++k) {
+            const size_t g = rev ? gfirst.size() - 2 - k : k;
             done = d0;
             launches = l0;
             if (two) {
@@ -1776,7 +1785,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
                            ps[0].storage, flags,
                            shape,
                            main_list.second, one_list.second, nmt, (int64_t)n, n_samples, steps, sample ? 1 : 0,
-                           o->drho ? 1 : 0, gkey};
+                           o->drho ? 1 : 0, rev ? 1 : 0, gkey};
         if ((*ge = graph_cache_get(key)))
             return hipSuccess;
         hipGraph_t g;

@@ -395,7 +395,9 @@ def test_lattice_groups_with_samples_and_density_ramp(L):
     """The benchmark's five 1024 x 1024 lattices run as two lattice groups
     (each group's state sized for the Infinity Cache): samples every 10 steps
     with a density change after each, two steps per launch, equal to
-    single-lattice runs with lbm_add_density bit for bit."""
+    single-lattice runs with lbm_add_density bit for bit; then three more
+    calls (the groups' order alternates from call to call), with graphs and
+    with direct launches, still equal to the single runs."""
     cfgs = [SI.cil_1024(r, l) for l, r in enumerate(SI.CIL_DENSITIES)]
     inits = [c.pop("init") for c in cfgs]
     params = [_gparams(L, c) for c in cfgs]
@@ -425,6 +427,19 @@ def test_lattice_groups_with_samples_and_density_ramp(L):
         for o, s in zip(out[l], obs):
             for k in ("M", "phi", "drho"):
                 assert abs(o[k] - s[k]) <= 1e-12 * max(1.0, abs(s[k])), (l, k)
+    finals = [b.state(l).clone() for l in range(len(params))]
+    b.run(20, tile_rows=16)
+    b.run(20, tile_rows=16, use_graph=0)
+    out = b.run(20, tile_rows=16)
+    for l, p in enumerate(params):
+        lat = L.Lattice(p)
+        lat.set_state(finals[l])
+        lat.set_step(40)
+        lat.step(60)
+        assert torch.equal(b.state(l), lat.state), l
+        o, s = out[l][0], lat.observables()
+        assert abs(o["M"] - s["M"]) <= 1e-12 * max(1.0, abs(s["M"])), l
+        lat.close()
 
 
 def _raw_sweep(L, params, bufs, ws, steps, keep, tile_rows=16, sample_every=0):
