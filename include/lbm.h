@@ -339,8 +339,11 @@ int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n);
  * group of consecutive lattices, then for the next, each group's two buffers
  * (about equal shares, at most 240 MiB where one lattice is not larger) kept
  * in the 256 MiB Infinity Cache across those launches.  A chunk of s steps
- * therefore makes groups times the launches of one group.  LBM_EINVAL on
- * invalid arguments. */
+ * therefore makes groups times the launches of one group.  Successive calls on
+ * one workspace take the groups in alternating order (last group first on
+ * every other call; a prepare-only call keeps the order), so a call starts
+ * with the state the previous one left in the cache; results do not depend on
+ * the order.  LBM_EINVAL on invalid arguments. */
 int32_t lbm_sweep_groups(const lbm_params *ps, int32_t n);
 
 /* Run a batch.  ps[n]: per-lattice parameters; every lattice uses the same
