@@ -43,6 +43,10 @@ VALU_PER_SITE_UPDATE = 185
 # the same for the square lattice (D2Q9): the one-step batch kernel with one
 # site per lane (256 x 1 tiles), CIL, FP32, tau 1, noise on
 Q9_VALU_PER_SITE_UPDATE = 223
+# MIPS, two steps per launch on 64 x 16 tiles (4096^2, FP32, tau 2, noise
+# on): every VALU instruction of the launch (both rings included) per
+# site-update of the tile
+MIPS2_VALU_PER_SITE_UPDATE = 267
 
 
 def parse():
@@ -53,7 +57,8 @@ def parse():
     ap.add_argument("--workload", default="cil1024x5",
                     choices=["cil1024x5", "cil4096", "mips4096", "q9_cil4096", "q9_mips4096"],
                     help="mips4096: the 64 x 64 MIPS workload's parameters on 4096 x 4096; q9_*: the "
-                         "square-lattice (D2Q9) variant (lbm_step; --mode batch: the batched path)")
+                         "square-lattice (D2Q9) variant; lbm_step unless --mode batch (the batched path, "
+                         "two steps per launch where tuned)")
     ap.add_argument("--storage", type=int, default=0,
                     help="0 f32, 1 bf16 deviations, 2 fp16 deviations, 3 bf16 deviations with a float32 rest plane")
     ap.add_argument("--mode", default=None, choices=["batch", "single"],
@@ -354,6 +359,31 @@ def roofline_two_step(sites, per_launch_s, kernel, rows, total_sites=None):
     return r
 
 
+def roofline_mips_two_step(sites, per_launch_s, kernel):
+    """MIPS, two steps per launch (64 x 16 tiles): 2 x sites site-updates of
+    VALU work at the kernel's own count per update (from its counter summary
+    when taken on the current sources) against the VALU issue peak; the HBM
+    side is the state read and written once per launch (56 B per site)."""
+    c = measured_traffic("counters_k_batch_step2_mips_16_4096.json")
+    if c is not None and c.get("sites") == sites and c.get("valu_lane_instructions_per_site_update"):
+        vpu, vsrc = float(c["valu_lane_instructions_per_site_update"]), "counters_k_batch_step2_mips_16_4096.json"
+    else:
+        vpu, vsrc = float(MIPS2_VALU_PER_SITE_UPDATE), "stated (counter summary taken on other kernel sources)"
+    tops = vpu * 2 * sites / per_launch_s / 1e12
+    hbm = BYTES_PER_SITE[0] * sites / per_launch_s / 1e9
+    r = {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+         "unit": "T VALU lane-instructions/s", "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": None,
+         "kernel": kernel, "avg_launch_us": round(per_launch_s * 1e6, 3),
+         "valu_per_site_update": vpu, "valu_per_site_update_source": vsrc, "site_updates_per_launch": round(2 * sites),
+         "hbm": {"achieved": round(hbm, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                 "frac": round(hbm / HBM_PEAK_GBPS, 4), "bytes_per_launch": BYTES_PER_SITE[0] * sites}}
+    if c is not None and c.get("sites") == sites and c.get("traffic_bytes_per_launch"):
+        r["traffic"] = round(c["traffic_bytes_per_launch"] / per_launch_s / 1e9, 1)
+        r["traffic_bytes_per_launch"] = c["traffic_bytes_per_launch"]
+        r["traffic_vs_algorithmic"] = round(c["traffic_bytes_per_launch"] / c["algorithmic_bytes_per_launch"], 4)
+    return r
+
+
 def q9_valu_per_site_update():
     """valu_per_site_update() of the D2Q9 one-step batch kernel (256 x 1
     tiles), from its counter summary when taken on the current sources."""
@@ -421,8 +451,6 @@ def main():
         wname = "MIPS 4096x4096 periodic D2Q9, mean density 1.0 (x8 scaled), sigma 8/70, tau 2"
     sites = sum(c["nx"] * c["ny"] for c in cfgs)
     mode = args.mode or ("batch" if args.workload in ("cil1024x5", "cil4096") else "single")
-    if args.workload == "mips4096":  # lbm_step only
-        mode = "single"
 
     t_wall = time.perf_counter()
     rows, ngr = 0, 1
@@ -437,7 +465,12 @@ def main():
         ngr = time_batch.groups
         two, one = batch_launches(args.steps, rows)
         gtxt = f"; {ngr} lattice groups per pass" if ngr > 1 else ""
-        if lattice:
+        if args.workload == "mips4096":
+            launches = (two + 0.5 * one if two else args.steps) * ngr
+            kernel = (f"k_batch_step2_mips<F32,noisy,{rows}> (64x{rows} tiles, two steps per launch; {two} launches "
+                      f"+ {one} one-step launches + 1 FP64 sample)" if two else
+                      f"k_batch_step_mips<F32,noisy,{rows}> (one step per launch, +1 FP64 sample)")
+        elif lattice:
             launches = (two + 0.5 * one if two else args.steps) * ngr
             kernel = (f"k_batch_q9_step2<CIL,unit-tau,noisy,{rows}> (64x{rows} tiles, two steps per launch{gtxt})"
                       if two else f"k_batch_q9_step (one step per launch, tile rows {rows}{gtxt})")
@@ -482,7 +515,8 @@ def main():
         "config": {"workload": wname, "lattices": len(cfgs), "sites": sites, "storage": args.storage,
                    "mode": mode, **({"tile_rows": rows, "lattice_groups": ngr, "launch": args.launch}
                                     if mode == "batch" else {})},
-        "roofline": (roofline_two_step(sites / ngr, per_launch, kernel, rows, sites) if rows >= 8 and not lattice
+        "roofline": (roofline_mips_two_step(sites, per_launch, kernel) if rows >= 8 and args.workload == "mips4096"
+                     else roofline_two_step(sites / ngr, per_launch, kernel, rows, sites) if rows >= 8 and not lattice
                      else roofline(args.storage, sites / (launches / args.steps), per_launch, kernel, q)
                      if rows < 8 else roofline_q9_two_step(sites / ngr, per_launch, kernel)),
         "phi": [round(o["phi"], 6) for o in obs],
@@ -496,7 +530,7 @@ def main():
             attach_traffic(line["roofline"], f"counters_k_batch_q9_step2_{rows}_cil_4096.json", KERNEL_SOURCES_Q9B,
                            sites, per_launch)
 
-    if args.workload == "mips4096" and args.storage == 0:
+    if args.workload == "mips4096" and args.storage == 0 and mode == "single":
         attach_traffic(line["roofline"], "counters_k_step_mips_4096.json", STEP_SOURCES, sites, per_launch)
     if args.workload == "cil4096" and args.storage == 0 and mode == "single":
         attach_traffic(line["roofline"], "counters_k_step_local_cil_4096.json", STEP_SOURCES, sites, per_launch)
@@ -578,6 +612,13 @@ def main():
         var["mips4096_f32"] = {"MLUPS": round(4096 * 4096 * 100 / (msb / 1e3) / 1e6, 1), "GBps": rm["achieved"],
                                "frac_hbm": rm["frac"], "avg_launch_us": rm["avg_launch_us"],
                                "traffic_GBps": rm["traffic"], "traffic_vs_algorithmic": rm.get("traffic_vs_algorithmic")}
+        # the same lattice through the batched path: two steps per launch
+        # (k_batch_step2_mips, tuned among 64x4 one-step and 64x8 / 64x16
+        # two-step tiles)
+        msb2, _ = time_batch(L, torch, [mbig], 100, 10)
+        var["mips4096_f32_two_step"] = {"MLUPS": round(4096 * 4096 * 100 / (msb2 / 1e3) / 1e6, 1),
+                                        "tile_rows": time_batch.tile_rows,
+                                        "speedup_vs_f32_one_step": round(msb / msb2, 3)}
         # the square lattice (D2Q9, 72 B per site-update in FP32): CIL in the
         # three storages and MIPS at 4096^2, one launch per step
         q9c = [SI.q9_cil_4096()]
@@ -650,7 +691,7 @@ def main():
                     init=dict(mode=1, rho_mean=r, rho_spread=0.0, angle_std=0.0, u_mag=0.1, pop_noise=1e-3))
                for l, r in enumerate((0.06, 0.08, 0.10, 0.125, 0.15, 0.18) * 2)]
         forms = {}
-        for name, rows in (("64x16", 16), ("64x4", 4), ("resident", L.LBM_TILE_RESIDENT), ("tuned", 0)):
+        for name, rows in (("64x16_two_step", 16), ("64x4", 4), ("resident", L.LBM_TILE_RESIDENT), ("tuned", 0)):
             msr, _ = time_batch(L, torch, mcf, 20000, 1000, rows)
             forms[name] = {"us_per_step": round(msr * 1e3 / 20000, 3),
                            "MLUPS": round(12 * 2700 * 20000 / (msr / 1e3) / 1e6, 1)}

@@ -273,8 +273,10 @@ typedef struct lbm_sweep_opts {
                              launch; 8, 16 = 64x8, 64x16 sites, two steps per launch
                              (the second from LDS); 0 = tuned (every shape timed on the
                              batch itself, cached per batch signature).  MIPS batches
-                             take 0 (tuned), 4 or 16: 64x4 or 64x16 tiles, one step per
-                             launch, neighbour densities in LDS.  LBM_TILE_RESIDENT (1024):
+                             take 0 (tuned), 4: 64x4 tiles, one step per launch, or 8,
+                             16: 64x8, 64x16 tiles, two steps per launch (the first on
+                             a two-site ring, from densities of a three-site ring,
+                             all in LDS).  LBM_TILE_RESIDENT (1024):
                              whole lattices in LDS (every lattice at most 4096 sites
                              on D2Q7, 3072 on D2Q9, any model; tuned among the others
                              when the batch qualifies).  D2Q9 batches take 0, 1, 2, 4, 8
@@ -329,8 +331,8 @@ size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samp
 
 /* Work-tile rows (1, 2, 4, 8 or 16, as in lbm_sweep_opts.tile_rows, or
  * LBM_TILE_RESIDENT) the tuning chose for a batch with these lattices' sizes,
- * model and step variant (MIPS: 4, 16 or LBM_TILE_RESIDENT), 0 if not tuned
- * yet in this process; negative on invalid arguments. */
+ * model and step variant (D2Q7 MIPS: 4, 8, 16 or LBM_TILE_RESIDENT), 0 if not
+ * tuned yet in this process; negative on invalid arguments. */
 int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n);
 
 /* Lattice groups a sweep of these n lattices runs each captured chunk in

@@ -691,6 +691,235 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
 }
 
 // ---------------------------------------------------------------------------
+// MIPS, steps t and t+1 on a 64 x TY tile.  u* at a site needs the streamed
+// density of its six neighbours (eq. bu_mips with the isotropic stencil), so
+// the second step on the tile reads the first step's populations on a ring of
+// two sites around it (region B) and its densities on a ring of one (C), and
+// the first step on B reads densities on a ring of three (A), which gather
+// from the stored state on a ring of four.  Four phases, a barrier after each
+// of the first three:
+//  1. every site of A: its seven streamed populations from HBM and their
+//     density into LDS; B's sites come first and keep their populations in
+//     registers, the ring A \ B follows in one more slot, so the collisions
+//     of phase 2 fill whole waves;
+//  2. every site of B: u* from the densities, collision of step t, the
+//     populations into LDS as a store and a later load give them back;
+//  3. every site of C: the streamed density of step t+1 from LDS;
+//  4. every site of the tile: its streamed populations from LDS, u* from the
+//     densities of phase 3, collision of step t+1, store.
+// Ring sites are computed at their periodic images with the one-step site
+// body, so every site gets the values two one-step launches give it, bit for
+// bit.  Row parity follows the global row (y0 is even, ny is even).
+// ---------------------------------------------------------------------------
+template <int TY>
+struct Mips2Layout {
+    static constexpr int WA = 70, HA = TY + 6;  // A: x0-3 .. x0+66, y0-3 .. y0+TY+2
+    static constexpr int WB = 68, HB = TY + 4;  // B: x0-2 .. x0+65, y0-2 .. y0+TY+1
+    static constexpr int WC = 66, HC = TY + 2;  // C: x0-1 .. x0+64, y0-1 .. y0+TY
+    static constexpr int NA = WA * HA, NB = WB * HB, NC = WC * HC;
+    static constexpr int kRing = NA - NB;           // A outside B: 2 WA + 2 (HA - 2) sites
+    static constexpr int kMid = 7 * NB;             // step-t populations on B, plane by plane
+    static constexpr int kRho = NA > NC ? NA : NC;  // densities on A (phases 1-2), then on C (3-4)
+    static constexpr int kSize = kMid + kRho;
+    // A-local position of ring site e (0 <= e < kRing): the row above B, the
+    // row below, then the left and the right column between them
+    __device__ static void ring(int e, int &ax, int &ay)
+    {
+        if (e < WA) {
+            ax = e;
+            ay = 0;
+        } else if (e < 2 * WA) {
+            ax = e - WA;
+            ay = HA - 1;
+        } else {
+            const int c = e - 2 * WA;
+            ax = c < HA - 2 ? 0 : WA - 1;
+            ay = 1 + (c < HA - 2 ? c : c - (HA - 2));
+        }
+    }
+};
+
+template <int ST, int F, int TY, int NW>
+__global__ __launch_bounds__(64 * NW) void k_batch_step2_mips(const BatchTile *__restrict__ tiles,
+                                                          const LatDesc *__restrict__ lats,
+                                                          const Ctrl *__restrict__ ctrl, int step_off, int launch_off)
+{
+    using ML = Mips2Layout<TY>;
+    constexpr int NT = 64 * NW;
+    constexpr int KB = (ML::NB + NT - 1) / NT, KR = (ML::kRing + NT - 1) / NT, KC = (ML::NC + NT - 1) / NT;
+    static_assert(TY % NW == 0 && TY % 2 == 0, "rows per wave split evenly; tile rows start even");
+    __shared__ float lds[ML::kSize];
+    float *const mid = lds;            // [7][HB][WB]
+    float *const rs = lds + ML::kMid;  // [HA][WA], then [HC][WC]
+    const BatchTile tl = tiles[blockIdx.x];
+    const LatDesc &L = lats[tl.lat];
+    const StepArgs a = L.a;
+    const int64_t t = ctrl->t0 + step_off;
+    const int64_t t1 = t + 1;
+    const int par = (int)((ctrl->k0 + launch_off) & 1);
+    const int x0 = tl.tx * 64, y0 = tl.ty * TY;
+    if (x0 >= a.nx || y0 >= a.ny)  // whole-block exit, before the barrier
+        return;
+    const uint32_t plane = (uint32_t)a.plane, nx = (uint32_t)a.nx;
+    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], (uint32_t)Planes<ST>::bytes(plane));
+    const __amdgpu_buffer_rsrc_t dst = buffer_rsrc(L.buf[par ^ 1], (uint32_t)Planes<ST>::bytes(plane));
+    auto ld = [&](uint32_t elem, int i) { return Planes<ST>::load(src, elem, 0u, i, plane, a); };
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+    const uint32_t ta_lo = (uint32_t)((uint64_t)t & 0xffffffffu), ta_hi = (uint32_t)((uint64_t)t >> 32);
+    const uint32_t tb_lo = (uint32_t)((uint64_t)t1 & 0xffffffffu), tb_hi = (uint32_t)((uint64_t)t1 >> 32);
+    // sources four sites around the tile inside the lattice: no wrap at all
+    const bool interior = x0 >= 4 && x0 + 68 <= a.nx && y0 >= 4 && y0 + TY + 4 <= a.ny;
+    // A's coordinates lie in [-3, n + 65] (x) and [-3, n + TY + 1] (y): one
+    // period brings them into the lattice unless it is that small
+    const bool once = a.nx >= 66 && a.ny >= TY + 2;
+    auto wrap = [&](int c, int n) {
+        if (once) {
+            c = c < 0 ? c + n : c;
+            return c >= n ? c - n : c;
+        }
+        c %= n;
+        return c < 0 ? c + n : c;
+    };
+    // the seven streamed populations of global site (x, y), unwrapped
+    // coordinates; `own` its offset (pitch nx: the site index of the noise)
+    auto gather = [&](float *g, uint32_t &own, int x, int y) {
+        if (interior) {
+            const uint32_t p = (uint32_t)y & 1u;
+            const uint32_t c = (uint32_t)y * nx + (uint32_t)x;
+            g[0] = ld(c, 0);
+            g[1] = ld(c - 1u, 1);
+            g[2] = ld(c - nx - 1u + p, 2);
+            g[3] = ld(c - nx + p, 3);
+            g[4] = ld(c + 1u, 4);
+            g[5] = ld(c + nx + p, 5);
+            g[6] = ld(c + nx - 1u + p, 6);
+            own = c;
+        } else {
+            const PullSources32 q = pull_sources32(a, wrap(x, a.nx), wrap(y, a.ny));
+#pragma unroll
+            for (int i = 0; i < 7; ++i)
+                g[i] = ld(q.idx[i], i);
+            own = q.idx[0];
+        }
+    };
+    auto density = [](const float *g) { return g[0] + ((g[1] + g[4]) + ((g[2] + g[5]) + (g[3] + g[6]))); };
+
+    // phase 1: every load of the block's sites of A is issued first
+    float f[KB][7], fr[KR][7];
+    uint32_t own[KB], ownr[KR];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const int s = tid + k * NT;
+        if ((k + 1) * NT <= ML::NB || s < ML::NB)
+            gather(f[k], own[k], x0 - 2 + s % ML::WB, y0 - 2 + s / ML::WB);
+    }
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int e = tid + k * NT;
+        if (e < ML::kRing) {
+            int ax, ay;
+            ML::ring(e, ax, ay);
+            gather(fr[k], ownr[k], x0 - 3 + ax, y0 - 3 + ay);
+        }
+    }
+    float rho[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const int s = tid + k * NT;
+        if ((k + 1) * NT <= ML::NB || s < ML::NB) {
+            rho[k] = density(f[k]);
+            rs[(s / ML::WB + 1) * ML::WA + s % ML::WB + 1] = rho[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int e = tid + k * NT;
+        if (e < ML::kRing) {
+            int ax, ay;
+            ML::ring(e, ax, ay);
+            rs[ay * ML::WA + ax] = density(fr[k]);
+        }
+    }
+    __syncthreads();
+
+    // phase 2: step t on B
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const int s = tid + k * NT;
+        if ((k + 1) * NT <= ML::NB || s < ML::NB) {
+            const int by = s / ML::WB, ax = s % ML::WB + 1, ay = by + 1;
+            const int p = by & 1;  // parity of row y0 - 2 + by
+            float nb[7];
+            nb[0] = rho[k];
+            nb[1] = rs[ay * ML::WA + ax + 1];
+            nb[2] = rs[(ay + 1) * ML::WA + ax + p];
+            nb[3] = rs[(ay + 1) * ML::WA + ax - 1 + p];
+            nb[4] = rs[ay * ML::WA + ax - 1];
+            nb[5] = rs[(ay - 1) * ML::WA + ax - 1 + p];
+            nb[6] = rs[(ay - 1) * ML::WA + ax + p];
+            float ux, uy;
+            mips_ustar(a, rho[k], nb, ux, uy);
+            site_collide<F, ST>(a, f[k], rho[k], ux, uy, own[k], ta_lo, ta_hi);
+#pragma unroll
+            for (int i = 0; i < 7; ++i)
+                mid[i * ML::NB + s] = Planes<ST>::round(f[k][i], i, a);
+        }
+    }
+    __syncthreads();
+
+    // phase 3: densities of step t+1 on C (row cy has parity (cy + 1) & 1);
+    // the streamed populations of B-local site (bx, by) with parity p
+    auto pull_mid = [&](float *g, int bx, int by, int p) {
+        g[0] = mid[0 * ML::NB + by * ML::WB + bx];
+        g[1] = mid[1 * ML::NB + by * ML::WB + bx - 1];
+        g[2] = mid[2 * ML::NB + (by - 1) * ML::WB + bx - 1 + p];
+        g[3] = mid[3 * ML::NB + (by - 1) * ML::WB + bx + p];
+        g[4] = mid[4 * ML::NB + by * ML::WB + bx + 1];
+        g[5] = mid[5 * ML::NB + (by + 1) * ML::WB + bx + p];
+        g[6] = mid[6 * ML::NB + (by + 1) * ML::WB + bx - 1 + p];
+    };
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const int s = tid + k * NT;
+        if ((k + 1) * NT <= ML::NC || s < ML::NC) {
+            const int cx = s % ML::WC, cy = s / ML::WC;
+            float g[7];
+            pull_mid(g, cx + 1, cy + 1, (cy + 1) & 1);
+            rs[s] = density(g);
+        }
+    }
+    __syncthreads();
+
+    // phase 4: step t+1 on the tile; wave w takes rows w, w + NW, ...
+    for (int r = wv; r < TY; r += NW) {
+        const int x = x0 + lane, y = y0 + r;
+        if (!interior && (x >= a.nx || y >= a.ny))
+            continue;
+        const int p = r & 1, cx = lane + 1, cy = r + 1;
+        float g[7];
+        pull_mid(g, lane + 2, r + 2, p);
+        float rh, jx, jy;
+        site_moments(g, rh, jx, jy);
+        float nb[7];
+        nb[0] = rh;
+        nb[1] = rs[cy * ML::WC + cx + 1];
+        nb[2] = rs[(cy + 1) * ML::WC + cx + p];
+        nb[3] = rs[(cy + 1) * ML::WC + cx - 1 + p];
+        nb[4] = rs[cy * ML::WC + cx - 1];
+        nb[5] = rs[(cy - 1) * ML::WC + cx - 1 + p];
+        nb[6] = rs[(cy - 1) * ML::WC + cx + p];
+        float ux, uy;
+        mips_ustar(a, rh, nb, ux, uy);
+        const uint32_t row = (uint32_t)y * nx + (uint32_t)x0;  // pitch nx
+        site_collide<F, ST>(a, g, rh, ux, uy, row + (uint32_t)lane, tb_lo, tb_hi);
+#pragma unroll
+        for (int i = 0; i < 7; ++i)
+            Planes<ST>::store(dst, lane, row, i, plane, g[i], a);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Sampling: per moments tile (256 columns x 16 rows of one lattice) FP64
 // partial sums of M, Jx, Jy, sum |j|, nonfinite and per-column density sums
 // of the streamed populations; then per lattice the fixed-order totals.
@@ -912,8 +1141,10 @@ struct Layout {
 };
 
 // Work-tile shapes: sites across, rows, steps per launch.  Shapes 0..4 serve
-// the local models (CIL, passive), shapes 5 and 6 MIPS (64 x 16 and 64 x 4,
-// one step per launch); each model's shapes are tuned among themselves.
+// the local models (CIL, passive); D2Q7 MIPS takes shape 6 (64 x 4, one step
+// per launch) and the two-step shapes 3 and 4 (64 x 8, 64 x 16), D2Q9 MIPS
+// shape 5 (64 x 16, one step); each model's shapes are tuned among
+// themselves.
 struct Shape {
     int tx, ty, steps;
 };
@@ -1112,7 +1343,13 @@ template <int ST, int F>
 static hipError_t launch_batch_mips_f(int shape, int64_t ntiles, const BatchTile *tiles, const LatDesc *lats,
                                       const Ctrl *ctrl, int step_off, int launch_off, hipStream_t s)
 {
-    if (shape == kMipsShape4)
+    if (kShapes[shape].steps == 2 && kShapes[shape].ty == 8)
+        hipLaunchKernelGGL((k_batch_step2_mips<ST, F, 8, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats,
+                           ctrl, step_off, launch_off);
+    else if (kShapes[shape].steps == 2)
+        hipLaunchKernelGGL((k_batch_step2_mips<ST, F, 16, 8>), dim3((unsigned)ntiles), dim3(512), 0, s, tiles, lats,
+                           ctrl, step_off, launch_off);
+    else if (shape == kMipsShape4)
         hipLaunchKernelGGL((k_batch_step_mips<ST, F, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
                            step_off, launch_off);
     else
@@ -1438,18 +1675,19 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         return surrogate_sweep(ps, n, o, bufs, ws, ws_bytes, (hipStream_t)stream, out);
     // tile shape: caller's choice (tile_rows 1, 2, 4: 256x1, 128x2, 64x4
     // sites, one step per launch; 8, 16: 64x8, 64x16 sites, two steps per
-    // launch; MIPS always 64x16, one step per launch), else the tuned one for
+    // launch; D2Q7 MIPS 4, 8, 16, D2Q9 MIPS 16 with one step per launch),
+    // else the tuned one for
     // this signature, else tuned below: every tuning launch reads the state
     // in the first buffer of each lattice and writes the second (free until
     // the sweep starts), so the state is unchanged.
     int shape = -1;
     const bool mips = ps[0].model == LBM_MIPS, q9 = ps[0].lattice == LBM_D2Q9;
     // the shapes this model and lattice may take (tuned among themselves):
-    // MIPS one step per launch (D2Q7 64x16 or 64x4, D2Q9 64x16), the local
-    // models every shape
+    // D2Q7 MIPS 64x4 with one step per launch, 64x8 and 64x16 with two; D2Q9
+    // MIPS 64x16 with one; the local models shapes 0..4
     std::vector<int> cands;
     if (mips)
-        cands = q9 ? std::vector<int>{kMipsShape} : std::vector<int>{kMipsShape, kMipsShape4};
+        cands = q9 ? std::vector<int>{kMipsShape} : std::vector<int>{kMipsShape4, 3, 4};
     else
         for (int k = 0; k < kNumTuned; ++k)
             cands.push_back(k);
@@ -1468,7 +1706,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     }
     if (shape < 0 && o->tile_rows != 0)
         return fail(LBM_EINVAL, mips ? (q9 ? "D2Q9 MIPS batches take tile_rows 0, 16 or LBM_TILE_RESIDENT"
-                                          : "MIPS batches take tile_rows 0, 4, 16 or LBM_TILE_RESIDENT")
+                                          : "MIPS batches take tile_rows 0, 4, 8, 16 or LBM_TILE_RESIDENT")
                                      : "tile_rows must be 0, 1, 2, 4, 8, 16 or LBM_TILE_RESIDENT");
     const std::string sig = signature(ps, n, flags);
     if (shape < 0) {
@@ -1652,11 +1890,13 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tuned[sig] = shape;
     }
-    // the chosen list, and for a two-step shape the 256x1 list for the
-    // single steps that keep the launch count's parity equal to the step
-    // count's (so the state ends in bufs[2l + (n_steps & 1)])
+    // the chosen list, and for a two-step shape the list of a one-step shape
+    // (256x1, MIPS 64x4) for the single steps that keep the launch count's
+    // parity equal to the step count's (so the state ends in
+    // bufs[2l + (n_steps & 1)])
     const bool resident = shape == kResident;
     const bool two = !resident && kShapes[shape].steps == 2;
+    const int one_shape = two ? (mips ? kMipsShape4 : 0) : shape;
     std::pair<BatchTile *, int64_t> main_list{d_tiles1, 0};
     if (!resident) {
         main_list = upload(shape);
@@ -1665,7 +1905,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     }
     std::pair<BatchTile *, int64_t> one_list = main_list;
     if (two) {
-        one_list = upload(0);
+        one_list = upload(one_shape);
         if (!one_list.first)
             return hip_fail(up_err, "tile list upload");
     }
@@ -1677,7 +1917,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     // lattice groups that fit the Infinity Cache (one group when resident)
     const std::vector<int> gfirst = resident ? std::vector<int>{0, n} : cache_groups(ps, n);
     const std::vector<int64_t> g_main = resident ? std::vector<int64_t>{0, 0} : group_ranges(ps, gfirst, shape);
-    const std::vector<int64_t> g_one = two ? group_ranges(ps, gfirst, 0) : g_main;
+    const std::vector<int64_t> g_one = two ? group_ranges(ps, gfirst, one_shape) : g_main;
     std::vector<int64_t> gkey(g_main);
     gkey.insert(gkey.end(), g_one.begin(), g_one.end());
 
@@ -1738,7 +1978,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
                 }
             }
             for (; done < steps; ++launches, ++done) {
-                hipError_t e = launch_batch_step(ps[0].lattice, ps[0].model, ps[0].storage, flags, two ? 0 : shape, g_one[2 * g + 1],
+                hipError_t e = launch_batch_step(ps[0].lattice, ps[0].model, ps[0].storage, flags, one_shape, g_one[2 * g + 1],
                                                  one_list.first + g_one[2 * g], d_lat, d_ctrl, (int)done,
                                                  (int)launches, s);
                 if (e != hipSuccess)

@@ -206,7 +206,9 @@ def test_sweep_batch_rejects_invalid_batches():
     assert "tau" in L.lbm_last_error()
     assert _sweep(L, [good, L.make_params(64, 64, L.LBM_CIL, tau=1.0, sigma=0.0)]) == L.LBM_EINVAL
     mips = L.make_params(128, 128, L.LBM_MIPS, tau=2.0, rho_star=1.0)
-    assert _sweep(L, [mips], tile_rows=8) == L.LBM_EINVAL and "MIPS" in L.lbm_last_error()
+    assert _sweep(L, [mips], tile_rows=2) == L.LBM_EINVAL and "MIPS" in L.lbm_last_error()
+    mips9 = L.make_params(128, 128, L.LBM_MIPS, tau=2.0, rho_star=1.0, lattice=L.LBM_D2Q9)
+    assert _sweep(L, [mips9], tile_rows=8) == L.LBM_EINVAL and "D2Q9 MIPS" in L.lbm_last_error()
     assert _sweep(L, [mips, good]) == L.LBM_EINVAL   # one model per batch
     # 16-bit storages: D2Q7 only, one storage per batch
     assert _sweep(L, [L.make_params(128, 128, L.LBM_CIL, storage=L.LBM_BF16_DEV, lattice=L.LBM_D2Q9)]) == \

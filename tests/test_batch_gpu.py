@@ -229,12 +229,15 @@ def mips_states(L, cfgs):
     return states
 
 
-@pytest.mark.parametrize("tile_rows,use_graph,steps", [(16, 1, 37), (4, 0, 37), (0, 1, 1100), (4, 1, 1100)])
+@pytest.mark.parametrize("tile_rows,use_graph,steps", [(16, 1, 37), (16, 0, 38), (8, 1, 37), (8, 0, 2),
+                                                      (4, 0, 37), (0, 1, 1100), (4, 1, 1100), (16, 1, 1100)])
 def test_mips_batch_member_equals_single_run(L, tile_rows, use_graph, steps):
-    """The batched MIPS kernel runs the single-lattice MIPS tile body (on
-    64 x 16 or 64 x 4 tiles): every member equals its lbm_step run (64 x 16
-    tiles) bit for bit (1100 steps cross a captured chunk), and the tuned
-    shape is one of the two MIPS tiles."""
+    """The batched MIPS kernels (one step per launch on 64 x 4 tiles with the
+    single-lattice MIPS tile body; two steps per launch on 64 x 8 and 64 x 16
+    tiles, odd step counts ending with a one-step launch): every member,
+    lattices smaller than a tile and ragged ones included, equals its
+    lbm_step run bit for bit (1100 steps cross a captured chunk), and the
+    tuned shape is one of the three."""
     cfgs = mips_batch()
     states = mips_states(L, cfgs)
     finals, samples = single_runs(L, cfgs, states, steps)
@@ -249,7 +252,7 @@ def test_mips_batch_member_equals_single_run(L, tile_rows, use_graph, steps):
         for k in ("M", "phi", "drho"):
             assert abs(o[k] - s[k]) <= 1e-12 * max(1.0, abs(s[k])), (l, k)
     if tile_rows == 0:
-        assert L.lbm_sweep_tile_rows(b.params, b.n) in (4, 16)
+        assert L.lbm_sweep_tile_rows(b.params, b.n) in (4, 8, 16)
 
 
 def test_mips_batch_samples_density_ramp_and_oracle(L, orc):
@@ -375,8 +378,8 @@ def test_resident_samples_density_ramp_and_oracle(L, orc):
 
 def test_resident_is_tuned_for_paper_sized_lattices(L):
     """Twelve 90 x 30 MIPS lattices (the paper's noise-ramp batch): the tuning
-    picks among the 64 x 16, 64 x 4 and LDS-resident forms, and the tuned run
-    equals single runs bit for bit."""
+    picks among the two-step 64 x 16 and 64 x 8, the one-step 64 x 4 and the
+    LDS-resident forms, and the tuned run equals single runs bit for bit."""
     model, kw = RESIDENT_KW["mips"]
     cfgs = [_cfg(model, 90, 30, seed=SI.seed_for(10, l), **kw) for l in range(12)]
     states = resident_states(L, cfgs)
@@ -386,7 +389,7 @@ def test_resident_is_tuned_for_paper_sized_lattices(L):
         b.set_state(l, f0)
     b.run(200)
     torch.cuda.synchronize()
-    assert L.lbm_sweep_tile_rows(b.params, b.n) in (4, 16, L.LBM_TILE_RESIDENT)
+    assert L.lbm_sweep_tile_rows(b.params, b.n) in (4, 8, 16, L.LBM_TILE_RESIDENT)
     for l in range(len(cfgs)):
         assert torch.equal(b.state(l), finals[l]), l
 
@@ -564,8 +567,8 @@ def test_16bit_batch_member_equals_single_run(L, storage, tile_rows, use_graph):
 
 @pytest.mark.parametrize("storage", [1, 2, 3])
 def test_16bit_mips_and_resident_batches(L, storage):
-    """MIPS (64 x 16 and 64 x 4 tiles) and the LDS-resident form in 16-bit
-    storage (the resident form keeps storage 3 as the float32 values the
+    """MIPS (two steps per launch on 64 x 16 and 64 x 8 tiles, one on 64 x 4)
+    and the LDS-resident form in 16-bit storage (the resident form keeps storage 3 as the float32 values the
     storage gives back) equal lbm_step runs bit for bit."""
     import synth_inputs as SI_
     cfgs = [dict(nx=90, ny=30, model=SI_.MIPS, tau=2.0, sigma=1.0 / 70.0, A=0.0, B=0.0, C=50.0, rho_star=0.2,
@@ -587,7 +590,7 @@ def test_16bit_mips_and_resident_batches(L, storage):
         lat.step(steps)
         finals.append(lat.state.clone())
         lat.close()
-    for rows in (16, 4, L.LBM_TILE_RESIDENT):
+    for rows in (16, 8, 4, L.LBM_TILE_RESIDENT):
         b = L.Batch(gp)
         for l, f0 in enumerate(states):
             b.set_state(l, f0)

@@ -150,3 +150,26 @@ def test_cil_4096_two_step_batch_equals_single(L, tile_rows):
     b.run(4, tile_rows=tile_rows)
     torch.cuda.synchronize()
     assert torch.equal(b.state(0), single)
+
+
+@pytest.mark.parametrize("tile_rows", [16, 8])
+def test_mips_4096_two_step_batch_equals_single(L, tile_rows):
+    """MIPS at 4096^2 with two steps per launch (64 x 16 and 64 x 8 tiles,
+    densities of a three-site ring recomputed in LDS): five steps, two
+    two-step launches and one one-step launch, equal bit for bit to five
+    lbm_step launches, whose one-step parity with the oracle is checked
+    above."""
+    cfg = dict(SI.mips_small(), nx=4096, ny=4096)
+    ini = cfg.pop("init")
+    lat = L.Lattice(_gparams(L, cfg), init=L.make_init(**ini))
+    torch.cuda.synchronize()
+    s0 = lat.state[:, :, : cfg["nx"]].clone()
+    lat.step(5)
+    torch.cuda.synchronize()
+    single = lat.state[:, :, : cfg["nx"]].clone()
+    lat.close()
+    b = L.Batch([_gparams(L, cfg)])
+    b.set_state(0, s0)
+    b.run(5, tile_rows=tile_rows)
+    torch.cuda.synchronize()
+    assert torch.equal(b.state(0), single)
