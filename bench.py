@@ -47,6 +47,8 @@ Q9_VALU_PER_SITE_UPDATE = 223
 # on): every VALU instruction of the launch (both rings included) per
 # site-update of the tile
 MIPS2_VALU_PER_SITE_UPDATE = 267
+# the same on the square lattice (D2Q9)
+MIPS2_Q9_VALU_PER_SITE_UPDATE = 308
 
 
 def parse():
@@ -359,24 +361,28 @@ def roofline_two_step(sites, per_launch_s, kernel, rows, total_sites=None):
     return r
 
 
-def roofline_mips_two_step(sites, per_launch_s, kernel):
-    """MIPS, two steps per launch (64 x 16 tiles): 2 x sites site-updates of
-    VALU work at the kernel's own count per update (from its counter summary
-    when taken on the current sources) against the VALU issue peak; the HBM
-    side is the state read and written once per launch (56 B per site)."""
-    c = measured_traffic("counters_k_batch_step2_mips_16_4096.json")
+def roofline_mips_two_step(sites, per_launch_s, kernel, q=7):
+    """MIPS, two steps per launch (64 x 16 tiles; q = 7 triangular, 9 square
+    lattice): 2 x sites site-updates of VALU work at the kernel's own count
+    per update (from its counter summary when taken on the current sources)
+    against the VALU issue peak; the HBM side is the state read and written
+    once per launch (56 or 72 B per site)."""
+    name = "counters_k_batch_step2_mips_16_4096.json" if q == 7 else "counters_k_batch_step2_mips_q9_16_4096.json"
+    c = measured_traffic(name, KERNEL_SOURCES if q == 7 else KERNEL_SOURCES_Q9B)
     if c is not None and c.get("sites") == sites and c.get("valu_lane_instructions_per_site_update"):
-        vpu, vsrc = float(c["valu_lane_instructions_per_site_update"]), "counters_k_batch_step2_mips_16_4096.json"
+        vpu, vsrc = float(c["valu_lane_instructions_per_site_update"]), name
     else:
-        vpu, vsrc = float(MIPS2_VALU_PER_SITE_UPDATE), "stated (counter summary taken on other kernel sources)"
+        vpu = float(MIPS2_VALU_PER_SITE_UPDATE if q == 7 else MIPS2_Q9_VALU_PER_SITE_UPDATE)
+        vsrc = "stated (counter summary taken on other kernel sources)"
     tops = vpu * 2 * sites / per_launch_s / 1e12
-    hbm = BYTES_PER_SITE[0] * sites / per_launch_s / 1e9
+    per_site = BYTES_PER_SITE[0] * q // 7
+    hbm = per_site * sites / per_launch_s / 1e9
     r = {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
          "unit": "T VALU lane-instructions/s", "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": None,
          "kernel": kernel, "avg_launch_us": round(per_launch_s * 1e6, 3),
          "valu_per_site_update": vpu, "valu_per_site_update_source": vsrc, "site_updates_per_launch": round(2 * sites),
          "hbm": {"achieved": round(hbm, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                 "frac": round(hbm / HBM_PEAK_GBPS, 4), "bytes_per_launch": BYTES_PER_SITE[0] * sites}}
+                 "frac": round(hbm / HBM_PEAK_GBPS, 4), "bytes_per_launch": per_site * sites}}
     if c is not None and c.get("sites") == sites and c.get("traffic_bytes_per_launch"):
         r["traffic"] = round(c["traffic_bytes_per_launch"] / per_launch_s / 1e9, 1)
         r["traffic_bytes_per_launch"] = c["traffic_bytes_per_launch"]
@@ -465,11 +471,13 @@ def main():
         ngr = time_batch.groups
         two, one = batch_launches(args.steps, rows)
         gtxt = f"; {ngr} lattice groups per pass" if ngr > 1 else ""
-        if args.workload == "mips4096":
+        if args.workload in ("mips4096", "q9_mips4096"):
             launches = (two + 0.5 * one if two else args.steps) * ngr
-            kernel = (f"k_batch_step2_mips<F32,noisy,{rows}> (64x{rows} tiles, two steps per launch; {two} launches "
-                      f"+ {one} one-step launches + 1 FP64 sample)" if two else
-                      f"k_batch_step_mips<F32,noisy,{rows}> (one step per launch, +1 FP64 sample)")
+            lat_name = "D2Q9" if lattice else "D2Q7"
+            kernel = (f"k_batch_step2_mips<{lat_name},F32,noisy,{rows}> (64x{rows} tiles, two steps per launch; "
+                      f"{two} launches + {one} one-step launches + 1 FP64 sample)" if two else
+                      f"{'k_batch_q9_step_mips' if lattice else 'k_batch_step_mips'}<F32,noisy> (one step per launch, "
+                      f"+1 FP64 sample)")
         elif lattice:
             launches = (two + 0.5 * one if two else args.steps) * ngr
             kernel = (f"k_batch_q9_step2<CIL,unit-tau,noisy,{rows}> (64x{rows} tiles, two steps per launch{gtxt})"
@@ -515,7 +523,8 @@ def main():
         "config": {"workload": wname, "lattices": len(cfgs), "sites": sites, "storage": args.storage,
                    "mode": mode, **({"tile_rows": rows, "lattice_groups": ngr, "launch": args.launch}
                                     if mode == "batch" else {})},
-        "roofline": (roofline_mips_two_step(sites, per_launch, kernel) if rows >= 8 and args.workload == "mips4096"
+        "roofline": (roofline_mips_two_step(sites, per_launch, kernel, q)
+                     if rows >= 8 and args.workload in ("mips4096", "q9_mips4096")
                      else roofline_two_step(sites / ngr, per_launch, kernel, rows, sites) if rows >= 8 and not lattice
                      else roofline(args.storage, sites / (launches / args.steps), per_launch, kernel, q)
                      if rows < 8 else roofline_q9_two_step(sites / ngr, per_launch, kernel)),
@@ -648,6 +657,10 @@ def main():
         rq = roofline(0, nbig, msq / 1e3 / 100, "k_q9_step_mips<F32,noisy>", q=9)
         var["q9_mips4096_f32"] = {"MLUPS": round(nbig * 100 / (msq / 1e3) / 1e6, 1), "GBps": rq["achieved"],
                                   "frac_hbm": rq["frac"], "avg_launch_us": rq["avg_launch_us"]}
+        msq2m, _ = time_batch(L, torch, [SI.q9_mips_4096()], 100, 10, lattice=L.LBM_D2Q9)
+        var["q9_mips4096_f32_two_step"] = {"MLUPS": round(nbig * 100 / (msq2m / 1e3) / 1e6, 1),
+                                           "tile_rows": time_batch.tile_rows,
+                                           "speedup_vs_f32_one_step": round(msq / msq2m, 3)}
         # FP32 at 4096^2 through the batched path (two steps per launch)
         ms2, _ = time_batch(L, torch, big, 200, 10)
         rows2 = time_batch.tile_rows

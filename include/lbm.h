@@ -280,7 +280,8 @@ typedef struct lbm_sweep_opts {
                              whole lattices in LDS (every lattice at most 4096 sites
                              on D2Q7, 3072 on D2Q9, any model; tuned among the others
                              when the batch qualifies).  D2Q9 batches take 0, 1, 2, 4, 8
-                             or 16 (MIPS: 0 or 16), and LBM_TILE_RESIDENT */
+                             or 16 (MIPS: 0, 8 or 16, two steps per launch), and
+                             LBM_TILE_RESIDENT */
     int32_t use_graph;    /* 0: launch every kernel directly; 1: run each sample period
                              as captured HIP graphs of at most 1024 steps, kept (16 most
                              recent) and replayed by later calls with the same batch,
@@ -331,8 +332,8 @@ size_t lbm_sweep_workspace_bytes(const lbm_params *ps, int32_t n, int64_t n_samp
 
 /* Work-tile rows (1, 2, 4, 8 or 16, as in lbm_sweep_opts.tile_rows, or
  * LBM_TILE_RESIDENT) the tuning chose for a batch with these lattices' sizes,
- * model and step variant (D2Q7 MIPS: 4, 8, 16 or LBM_TILE_RESIDENT), 0 if not
- * tuned yet in this process; negative on invalid arguments. */
+ * model and step variant (MIPS: 4 (D2Q7 only), 8, 16 or LBM_TILE_RESIDENT), 0
+ * if not tuned yet in this process; negative on invalid arguments. */
 int32_t lbm_sweep_tile_rows(const lbm_params *ps, int32_t n);
 
 /* Lattice groups a sweep of these n lattices runs each captured chunk in

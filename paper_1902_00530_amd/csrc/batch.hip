@@ -691,15 +691,16 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
 }
 
 // ---------------------------------------------------------------------------
-// MIPS, steps t and t+1 on a 64 x TY tile.  u* at a site needs the streamed
-// density of its six neighbours (eq. bu_mips with the isotropic stencil), so
+// MIPS, steps t and t+1 on a 64 x TY tile, on either lattice.  u* at a site
+// needs the streamed density of its neighbours (eq. bu_mips with the
+// isotropic stencil: six on the triangular lattice, eight on the square), so
 // the second step on the tile reads the first step's populations on a ring of
 // two sites around it (region B) and its densities on a ring of one (C), and
 // the first step on B reads densities on a ring of three (A), which gather
 // from the stored state on a ring of four.  Four phases, a barrier after each
 // of the first three:
-//  1. every site of A: its seven streamed populations from HBM and their
-//     density into LDS; B's sites come first and keep their populations in
+//  1. every site of A: its streamed populations from HBM and their density
+//     into LDS; B's sites come first and keep their populations in
 //     registers, the ring A \ B follows in one more slot, so the collisions
 //     of phase 2 fill whole waves;
 //  2. every site of B: u* from the densities, collision of step t, the
@@ -709,7 +710,8 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
 //     densities of phase 3, collision of step t+1, store.
 // Ring sites are computed at their periodic images with the one-step site
 // body, so every site gets the values two one-step launches give it, bit for
-// bit.  Row parity follows the global row (y0 is even, ny is even).
+// bit.  On the triangular lattice row parity follows the global row (y0 and
+// ny are even).
 // ---------------------------------------------------------------------------
 template <int TY>
 struct Mips2Layout {
@@ -718,9 +720,7 @@ struct Mips2Layout {
     static constexpr int WC = 66, HC = TY + 2;  // C: x0-1 .. x0+64, y0-1 .. y0+TY
     static constexpr int NA = WA * HA, NB = WB * HB, NC = WC * HC;
     static constexpr int kRing = NA - NB;           // A outside B: 2 WA + 2 (HA - 2) sites
-    static constexpr int kMid = 7 * NB;             // step-t populations on B, plane by plane
     static constexpr int kRho = NA > NC ? NA : NC;  // densities on A (phases 1-2), then on C (3-4)
-    static constexpr int kSize = kMid + kRho;
     // A-local position of ring site e (0 <= e < kRing): the row above B, the
     // row below, then the left and the right column between them
     __device__ static void ring(int e, int &ax, int &ay)
@@ -739,18 +739,172 @@ struct Mips2Layout {
     }
 };
 
-template <int ST, int F, int TY, int NW>
+// Lattice policies of the two-step MIPS kernel: the streamed populations of a
+// global site from the stored state (sources inside the lattice, or at the
+// periodic images of a wrapped site), the density, u* from the densities
+// around position c of an LDS map of row width W, the collision, the value a
+// store and a later load give back, the streamed populations of a site of
+// the step-t map (nb sites per plane, row width wb), and the store.
+template <int ST>
+struct Mips2Q7 {  // offset-row triangular lattice, any storage
+    static constexpr int Q = 7;
+    const StepArgs &a;
+    const __amdgpu_buffer_rsrc_t src, dst;
+    const uint32_t plane, nx;
+    __device__ Mips2Q7(const StepArgs &a_, const void *s, void *d)
+        : a(a_), src(buffer_rsrc(s, (uint32_t)Planes<ST>::bytes(a_.plane))),
+          dst(buffer_rsrc(d, (uint32_t)Planes<ST>::bytes(a_.plane))), plane((uint32_t)a_.plane), nx((uint32_t)a_.nx)
+    {
+    }
+    __device__ float ld(uint32_t e, int i) const { return Planes<ST>::load(src, e, 0u, i, plane, a); }
+    __device__ void gather_in(float *g, uint32_t &own, int x, int y) const
+    {
+        const uint32_t p = (uint32_t)y & 1u;
+        const uint32_t c = (uint32_t)y * nx + (uint32_t)x;
+        g[0] = ld(c, 0);
+        g[1] = ld(c - 1u, 1);
+        g[2] = ld(c - nx - 1u + p, 2);
+        g[3] = ld(c - nx + p, 3);
+        g[4] = ld(c + 1u, 4);
+        g[5] = ld(c + nx + p, 5);
+        g[6] = ld(c + nx - 1u + p, 6);
+        own = c;
+    }
+    __device__ void gather_wrapped(float *g, uint32_t &own, int xg, int yg) const
+    {
+        const PullSources32 q = pull_sources32(a, xg, yg);
+#pragma unroll
+        for (int i = 0; i < 7; ++i)
+            g[i] = ld(q.idx[i], i);
+        own = q.idx[0];
+    }
+    __device__ static float density(const float *g) { return g[0] + ((g[1] + g[4]) + ((g[2] + g[5]) + (g[3] + g[6]))); }
+    template <int W>
+    __device__ void ustar(const float *rs, int c, int p, float rho, float &ux, float &uy) const
+    {
+        float nb[7];
+        nb[0] = rho;
+        nb[1] = rs[c + 1];
+        nb[2] = rs[c + W + p];
+        nb[3] = rs[c + W - 1 + p];
+        nb[4] = rs[c - 1];
+        nb[5] = rs[c - W - 1 + p];
+        nb[6] = rs[c - W + p];
+        mips_ustar(a, rho, nb, ux, uy);
+    }
+    template <int F>
+    __device__ void collide(float *f, float rho, float ux, float uy, uint32_t site, uint32_t lo, uint32_t hi) const
+    {
+        site_collide<F, ST>(a, f, rho, ux, uy, site, lo, hi);
+    }
+    __device__ float round(float v, int i) const { return Planes<ST>::round(v, i, a); }
+    template <int NB, int WB>
+    __device__ static void pull_mid(float *g, const float *mid, int bx, int by, int p)
+    {
+        const int m = by * WB + bx;
+        g[0] = mid[0 * NB + m];
+        g[1] = mid[1 * NB + m - 1];
+        g[2] = mid[2 * NB + m - WB - 1 + p];
+        g[3] = mid[3 * NB + m - WB + p];
+        g[4] = mid[4 * NB + m + 1];
+        g[5] = mid[5 * NB + m + WB + p];
+        g[6] = mid[6 * NB + m + WB - 1 + p];
+    }
+    __device__ void store(uint32_t row, int lane, const float *g) const
+    {
+#pragma unroll
+        for (int i = 0; i < 7; ++i)
+            Planes<ST>::store(dst, (uint32_t)lane, row, i, plane, g[i], a);
+    }
+};
+
+struct Mips2Q9 {  // square lattice, float32 storage; one buffer resource per plane
+    static constexpr int Q = 9;
+    const StepArgs &a;
+    const float *const srcp;
+    float *const dstp;
+    const uint32_t plane, nx;
+    __device__ Mips2Q9(const StepArgs &a_, const void *s, void *d)
+        : a(a_), srcp((const float *)s), dstp((float *)d), plane((uint32_t)a_.plane), nx((uint32_t)a_.nx)
+    {
+    }
+    __device__ float ld(uint32_t e, int i) const { return BufIO<float>::load(q9_plane_rsrc(srcp, i, plane), e, 0u); }
+    __device__ void gather_in(float *g, uint32_t &own, int x, int y) const
+    {
+        const uint32_t c = (uint32_t)y * nx + (uint32_t)x;
+        const uint32_t e[9] = {c, c - 1u, c - nx, c + 1u, c + nx, c - nx - 1u, c - nx + 1u, c + nx + 1u, c + nx - 1u};
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            g[i] = ld(e[i], i);
+        own = c;
+    }
+    __device__ void gather_wrapped(float *g, uint32_t &own, int xg, int yg) const
+    {
+        const Q9Sources q = q9_sources(a, xg, yg);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            g[i] = ld(q.idx[i], i);
+        own = q.idx[0];
+    }
+    __device__ static float density(const float *g)
+    {
+        return g[0] + (((g[1] + g[3]) + (g[2] + g[4])) + ((g[5] + g[7]) + (g[6] + g[8])));
+    }
+    template <int W>
+    __device__ void ustar(const float *rs, int c, int, float rho, float &ux, float &uy) const
+    {
+        float nb[9];
+        nb[0] = rho;
+        nb[1] = rs[c + 1];
+        nb[2] = rs[c + W];
+        nb[3] = rs[c - 1];
+        nb[4] = rs[c - W];
+        nb[5] = rs[c + W + 1];
+        nb[6] = rs[c + W - 1];
+        nb[7] = rs[c - W - 1];
+        nb[8] = rs[c - W + 1];
+        q9_mips_ustar(a, rho, nb, ux, uy);
+    }
+    template <int F>
+    __device__ void collide(float *f, float rho, float ux, float uy, uint32_t site, uint32_t lo, uint32_t hi) const
+    {
+        q9_collide<F, kF32>(a, f, rho, ux, uy, site, lo, hi);
+    }
+    __device__ float round(float v, int) const { return v; }
+    template <int NB, int WB>
+    __device__ static void pull_mid(float *g, const float *mid, int bx, int by, int)
+    {
+        const int m = by * WB + bx;
+        g[0] = mid[0 * NB + m];
+        g[1] = mid[1 * NB + m - 1];
+        g[2] = mid[2 * NB + m - WB];
+        g[3] = mid[3 * NB + m + 1];
+        g[4] = mid[4 * NB + m + WB];
+        g[5] = mid[5 * NB + m - WB - 1];
+        g[6] = mid[6 * NB + m - WB + 1];
+        g[7] = mid[7 * NB + m + WB + 1];
+        g[8] = mid[8 * NB + m + WB - 1];
+    }
+    __device__ void store(uint32_t row, int lane, const float *g) const
+    {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            BufIO<float>::store(q9_plane_rsrc(dstp, i, plane), (uint32_t)lane, row, g[i]);
+    }
+};
+
+template <class LP, int F, int TY, int NW>
 __global__ __launch_bounds__(64 * NW) void k_batch_step2_mips(const BatchTile *__restrict__ tiles,
                                                           const LatDesc *__restrict__ lats,
                                                           const Ctrl *__restrict__ ctrl, int step_off, int launch_off)
 {
     using ML = Mips2Layout<TY>;
-    constexpr int NT = 64 * NW;
+    constexpr int Q = LP::Q, NT = 64 * NW;
     constexpr int KB = (ML::NB + NT - 1) / NT, KR = (ML::kRing + NT - 1) / NT, KC = (ML::NC + NT - 1) / NT;
     static_assert(TY % NW == 0 && TY % 2 == 0, "rows per wave split evenly; tile rows start even");
-    __shared__ float lds[ML::kSize];
-    float *const mid = lds;            // [7][HB][WB]
-    float *const rs = lds + ML::kMid;  // [HA][WA], then [HC][WC]
+    __shared__ float lds[Q * ML::NB + ML::kRho];
+    float *const mid = lds;               // [Q][HB][WB]
+    float *const rs = lds + Q * ML::NB;  // [HA][WA], then [HC][WC]
     const BatchTile tl = tiles[blockIdx.x];
     const LatDesc &L = lats[tl.lat];
     const StepArgs a = L.a;
@@ -760,10 +914,8 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2_mips(const BatchTile *_
     const int x0 = tl.tx * 64, y0 = tl.ty * TY;
     if (x0 >= a.nx || y0 >= a.ny)  // whole-block exit, before the barrier
         return;
-    const uint32_t plane = (uint32_t)a.plane, nx = (uint32_t)a.nx;
-    const __amdgpu_buffer_rsrc_t src = buffer_rsrc(L.buf[par], (uint32_t)Planes<ST>::bytes(plane));
-    const __amdgpu_buffer_rsrc_t dst = buffer_rsrc(L.buf[par ^ 1], (uint32_t)Planes<ST>::bytes(plane));
-    auto ld = [&](uint32_t elem, int i) { return Planes<ST>::load(src, elem, 0u, i, plane, a); };
+    const LP lp(a, L.buf[par], L.buf[par ^ 1]);
+    const uint32_t nx = (uint32_t)a.nx;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     const uint32_t ta_lo = (uint32_t)((uint64_t)t & 0xffffffffu), ta_hi = (uint32_t)((uint64_t)t >> 32);
@@ -781,32 +933,17 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2_mips(const BatchTile *_
         c %= n;
         return c < 0 ? c + n : c;
     };
-    // the seven streamed populations of global site (x, y), unwrapped
+    // the Q streamed populations of global site (x, y), unwrapped
     // coordinates; `own` its offset (pitch nx: the site index of the noise)
     auto gather = [&](float *g, uint32_t &own, int x, int y) {
-        if (interior) {
-            const uint32_t p = (uint32_t)y & 1u;
-            const uint32_t c = (uint32_t)y * nx + (uint32_t)x;
-            g[0] = ld(c, 0);
-            g[1] = ld(c - 1u, 1);
-            g[2] = ld(c - nx - 1u + p, 2);
-            g[3] = ld(c - nx + p, 3);
-            g[4] = ld(c + 1u, 4);
-            g[5] = ld(c + nx + p, 5);
-            g[6] = ld(c + nx - 1u + p, 6);
-            own = c;
-        } else {
-            const PullSources32 q = pull_sources32(a, wrap(x, a.nx), wrap(y, a.ny));
-#pragma unroll
-            for (int i = 0; i < 7; ++i)
-                g[i] = ld(q.idx[i], i);
-            own = q.idx[0];
-        }
+        if (interior)
+            lp.gather_in(g, own, x, y);
+        else
+            lp.gather_wrapped(g, own, wrap(x, a.nx), wrap(y, a.ny));
     };
-    auto density = [](const float *g) { return g[0] + ((g[1] + g[4]) + ((g[2] + g[5]) + (g[3] + g[6]))); };
 
     // phase 1: every load of the block's sites of A is issued first
-    float f[KB][7], fr[KR][7];
+    float f[KB][Q], fr[KR][Q];
     uint32_t own[KB], ownr[KR];
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
@@ -828,7 +965,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2_mips(const BatchTile *_
     for (int k = 0; k < KB; ++k) {
         const int s = tid + k * NT;
         if ((k + 1) * NT <= ML::NB || s < ML::NB) {
-            rho[k] = density(f[k]);
+            rho[k] = LP::density(f[k]);
             rs[(s / ML::WB + 1) * ML::WA + s % ML::WB + 1] = rho[k];
         }
     }
@@ -838,55 +975,36 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2_mips(const BatchTile *_
         if (e < ML::kRing) {
             int ax, ay;
             ML::ring(e, ax, ay);
-            rs[ay * ML::WA + ax] = density(fr[k]);
+            rs[ay * ML::WA + ax] = LP::density(fr[k]);
         }
     }
     __syncthreads();
 
-    // phase 2: step t on B
+    // phase 2: step t on B (row by has parity by & 1: y0 is even)
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
         const int s = tid + k * NT;
         if ((k + 1) * NT <= ML::NB || s < ML::NB) {
             const int by = s / ML::WB, ax = s % ML::WB + 1, ay = by + 1;
-            const int p = by & 1;  // parity of row y0 - 2 + by
-            float nb[7];
-            nb[0] = rho[k];
-            nb[1] = rs[ay * ML::WA + ax + 1];
-            nb[2] = rs[(ay + 1) * ML::WA + ax + p];
-            nb[3] = rs[(ay + 1) * ML::WA + ax - 1 + p];
-            nb[4] = rs[ay * ML::WA + ax - 1];
-            nb[5] = rs[(ay - 1) * ML::WA + ax - 1 + p];
-            nb[6] = rs[(ay - 1) * ML::WA + ax + p];
             float ux, uy;
-            mips_ustar(a, rho[k], nb, ux, uy);
-            site_collide<F, ST>(a, f[k], rho[k], ux, uy, own[k], ta_lo, ta_hi);
+            lp.template ustar<ML::WA>(rs, ay * ML::WA + ax, by & 1, rho[k], ux, uy);
+            lp.template collide<F>(f[k], rho[k], ux, uy, own[k], ta_lo, ta_hi);
 #pragma unroll
-            for (int i = 0; i < 7; ++i)
-                mid[i * ML::NB + s] = Planes<ST>::round(f[k][i], i, a);
+            for (int i = 0; i < Q; ++i)
+                mid[i * ML::NB + s] = lp.round(f[k][i], i);
         }
     }
     __syncthreads();
 
-    // phase 3: densities of step t+1 on C (row cy has parity (cy + 1) & 1);
-    // the streamed populations of B-local site (bx, by) with parity p
-    auto pull_mid = [&](float *g, int bx, int by, int p) {
-        g[0] = mid[0 * ML::NB + by * ML::WB + bx];
-        g[1] = mid[1 * ML::NB + by * ML::WB + bx - 1];
-        g[2] = mid[2 * ML::NB + (by - 1) * ML::WB + bx - 1 + p];
-        g[3] = mid[3 * ML::NB + (by - 1) * ML::WB + bx + p];
-        g[4] = mid[4 * ML::NB + by * ML::WB + bx + 1];
-        g[5] = mid[5 * ML::NB + (by + 1) * ML::WB + bx + p];
-        g[6] = mid[6 * ML::NB + (by + 1) * ML::WB + bx - 1 + p];
-    };
+    // phase 3: densities of step t+1 on C (row cy has parity (cy + 1) & 1)
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
         const int s = tid + k * NT;
         if ((k + 1) * NT <= ML::NC || s < ML::NC) {
             const int cx = s % ML::WC, cy = s / ML::WC;
-            float g[7];
-            pull_mid(g, cx + 1, cy + 1, (cy + 1) & 1);
-            rs[s] = density(g);
+            float g[Q];
+            LP::template pull_mid<ML::NB, ML::WB>(g, mid, cx + 1, cy + 1, (cy + 1) & 1);
+            rs[s] = LP::density(g);
         }
     }
     __syncthreads();
@@ -896,26 +1014,14 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2_mips(const BatchTile *_
         const int x = x0 + lane, y = y0 + r;
         if (!interior && (x >= a.nx || y >= a.ny))
             continue;
-        const int p = r & 1, cx = lane + 1, cy = r + 1;
-        float g[7];
-        pull_mid(g, lane + 2, r + 2, p);
-        float rh, jx, jy;
-        site_moments(g, rh, jx, jy);
-        float nb[7];
-        nb[0] = rh;
-        nb[1] = rs[cy * ML::WC + cx + 1];
-        nb[2] = rs[(cy + 1) * ML::WC + cx + p];
-        nb[3] = rs[(cy + 1) * ML::WC + cx - 1 + p];
-        nb[4] = rs[cy * ML::WC + cx - 1];
-        nb[5] = rs[(cy - 1) * ML::WC + cx - 1 + p];
-        nb[6] = rs[(cy - 1) * ML::WC + cx + p];
+        float g[Q];
+        LP::template pull_mid<ML::NB, ML::WB>(g, mid, lane + 2, r + 2, r & 1);
+        const float rh = LP::density(g);
         float ux, uy;
-        mips_ustar(a, rh, nb, ux, uy);
+        lp.template ustar<ML::WC>(rs, (r + 1) * ML::WC + lane + 1, r & 1, rh, ux, uy);
         const uint32_t row = (uint32_t)y * nx + (uint32_t)x0;  // pitch nx
-        site_collide<F, ST>(a, g, rh, ux, uy, row + (uint32_t)lane, tb_lo, tb_hi);
-#pragma unroll
-        for (int i = 0; i < 7; ++i)
-            Planes<ST>::store(dst, lane, row, i, plane, g[i], a);
+        lp.template collide<F>(g, rh, ux, uy, row + (uint32_t)lane, tb_lo, tb_hi);
+        lp.store(row, lane, g);
     }
 }
 
@@ -1141,10 +1247,9 @@ struct Layout {
 };
 
 // Work-tile shapes: sites across, rows, steps per launch.  Shapes 0..4 serve
-// the local models (CIL, passive); D2Q7 MIPS takes shape 6 (64 x 4, one step
-// per launch) and the two-step shapes 3 and 4 (64 x 8, 64 x 16), D2Q9 MIPS
-// shape 5 (64 x 16, one step); each model's shapes are tuned among
-// themselves.
+// the local models (CIL, passive); MIPS takes the two-step shapes 3 and 4
+// (64 x 8, 64 x 16) and, for single steps, shape 6 (D2Q7, 64 x 4) or 5
+// (D2Q9, 64 x 16); each model's shapes are tuned among themselves.
 struct Shape {
     int tx, ty, steps;
 };
@@ -1344,11 +1449,11 @@ static hipError_t launch_batch_mips_f(int shape, int64_t ntiles, const BatchTile
                                       const Ctrl *ctrl, int step_off, int launch_off, hipStream_t s)
 {
     if (kShapes[shape].steps == 2 && kShapes[shape].ty == 8)
-        hipLaunchKernelGGL((k_batch_step2_mips<ST, F, 8, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats,
-                           ctrl, step_off, launch_off);
+        hipLaunchKernelGGL((k_batch_step2_mips<Mips2Q7<ST>, F, 8, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles,
+                           lats, ctrl, step_off, launch_off);
     else if (kShapes[shape].steps == 2)
-        hipLaunchKernelGGL((k_batch_step2_mips<ST, F, 16, 8>), dim3((unsigned)ntiles), dim3(512), 0, s, tiles, lats,
-                           ctrl, step_off, launch_off);
+        hipLaunchKernelGGL((k_batch_step2_mips<Mips2Q7<ST>, F, 16, 8>), dim3((unsigned)ntiles), dim3(512), 0, s,
+                           tiles, lats, ctrl, step_off, launch_off);
     else if (shape == kMipsShape4)
         hipLaunchKernelGGL((k_batch_step_mips<ST, F, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
                            step_off, launch_off);
@@ -1405,7 +1510,13 @@ static hipError_t launch_batch_q9_f(int model, int shape, int64_t ntiles, const 
                                     const Ctrl *ctrl, int step_off, int launch_off, hipStream_t s)
 {
     const Shape &sh = kShapes[shape];
-    if (model == kMips)
+    if (model == kMips && sh.steps == 2 && sh.ty == 8)
+        hipLaunchKernelGGL((k_batch_step2_mips<Mips2Q9, F, 8, 4>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles,
+                           lats, ctrl, step_off, launch_off);
+    else if (model == kMips && sh.steps == 2)
+        hipLaunchKernelGGL((k_batch_step2_mips<Mips2Q9, F, 16, 8>), dim3((unsigned)ntiles), dim3(512), 0, s, tiles,
+                           lats, ctrl, step_off, launch_off);
+    else if (model == kMips)
         hipLaunchKernelGGL((k_batch_q9_step_mips<F>), dim3((unsigned)ntiles), dim3(256), 0, s, tiles, lats, ctrl,
                            step_off, launch_off);
     else if (sh.steps == 2 && model == kCil)
@@ -1675,7 +1786,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         return surrogate_sweep(ps, n, o, bufs, ws, ws_bytes, (hipStream_t)stream, out);
     // tile shape: caller's choice (tile_rows 1, 2, 4: 256x1, 128x2, 64x4
     // sites, one step per launch; 8, 16: 64x8, 64x16 sites, two steps per
-    // launch; D2Q7 MIPS 4, 8, 16, D2Q9 MIPS 16 with one step per launch),
+    // launch; MIPS 8, 16 and, D2Q7 only, 4 with one step per launch),
     // else the tuned one for
     // this signature, else tuned below: every tuning launch reads the state
     // in the first buffer of each lattice and writes the second (free until
@@ -1683,11 +1794,11 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
     int shape = -1;
     const bool mips = ps[0].model == LBM_MIPS, q9 = ps[0].lattice == LBM_D2Q9;
     // the shapes this model and lattice may take (tuned among themselves):
-    // D2Q7 MIPS 64x4 with one step per launch, 64x8 and 64x16 with two; D2Q9
-    // MIPS 64x16 with one; the local models shapes 0..4
+    // MIPS 64x8 and 64x16 with two steps per launch and, D2Q7 only, 64x4
+    // with one; the local models shapes 0..4
     std::vector<int> cands;
     if (mips)
-        cands = q9 ? std::vector<int>{kMipsShape} : std::vector<int>{kMipsShape4, 3, 4};
+        cands = q9 ? std::vector<int>{3, 4} : std::vector<int>{kMipsShape4, 3, 4};
     else
         for (int k = 0; k < kNumTuned; ++k)
             cands.push_back(k);
@@ -1705,7 +1816,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         shape = kResident;
     }
     if (shape < 0 && o->tile_rows != 0)
-        return fail(LBM_EINVAL, mips ? (q9 ? "D2Q9 MIPS batches take tile_rows 0, 16 or LBM_TILE_RESIDENT"
+        return fail(LBM_EINVAL, mips ? (q9 ? "D2Q9 MIPS batches take tile_rows 0, 8, 16 or LBM_TILE_RESIDENT"
                                           : "MIPS batches take tile_rows 0, 4, 8, 16 or LBM_TILE_RESIDENT")
                                      : "tile_rows must be 0, 1, 2, 4, 8, 16 or LBM_TILE_RESIDENT");
     const std::string sig = signature(ps, n, flags);
@@ -1891,12 +2002,12 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         g_tuned[sig] = shape;
     }
     // the chosen list, and for a two-step shape the list of a one-step shape
-    // (256x1, MIPS 64x4) for the single steps that keep the launch count's
+    // (256x1; MIPS 64x4, D2Q9 MIPS 64x16) for the single steps that keep the launch count's
     // parity equal to the step count's (so the state ends in
     // bufs[2l + (n_steps & 1)])
     const bool resident = shape == kResident;
     const bool two = !resident && kShapes[shape].steps == 2;
-    const int one_shape = two ? (mips ? kMipsShape4 : 0) : shape;
+    const int one_shape = two ? (mips ? (q9 ? kMipsShape : kMipsShape4) : 0) : shape;
     std::pair<BatchTile *, int64_t> main_list{d_tiles1, 0};
     if (!resident) {
         main_list = upload(shape);

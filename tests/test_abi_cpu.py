@@ -127,7 +127,7 @@ def test_square_lattice_validation():
         assert _sweep(L, [q9], tile_rows=rows) in (L.LBM_OK, L.LBM_EHIP)
     assert _sweep(L, [q9], tile_rows=32) == L.LBM_EINVAL
     q9m = L.make_params(128, 128, L.LBM_MIPS, tau=2.0, rho_star=1.0, lattice=L.LBM_D2Q9)
-    for rows in (4, 8):
+    for rows in (1, 2, 4):  # D2Q9 MIPS: 8, 16 (two steps per launch) or resident
         assert _sweep(L, [q9m], tile_rows=rows) == L.LBM_EINVAL and "D2Q9" in L.lbm_last_error()
     assert _sweep(L, [q9], tile_rows=L.LBM_TILE_RESIDENT) == L.LBM_EINVAL  # 16384 sites: too large for LDS
     q9h = L.make_params(128, 128, L.LBM_CIL, storage=L.LBM_BF16_DEV, rho_ref=1.0, lattice=L.LBM_D2Q9)
@@ -208,7 +208,7 @@ def test_sweep_batch_rejects_invalid_batches():
     mips = L.make_params(128, 128, L.LBM_MIPS, tau=2.0, rho_star=1.0)
     assert _sweep(L, [mips], tile_rows=2) == L.LBM_EINVAL and "MIPS" in L.lbm_last_error()
     mips9 = L.make_params(128, 128, L.LBM_MIPS, tau=2.0, rho_star=1.0, lattice=L.LBM_D2Q9)
-    assert _sweep(L, [mips9], tile_rows=8) == L.LBM_EINVAL and "D2Q9 MIPS" in L.lbm_last_error()
+    assert _sweep(L, [mips9], tile_rows=4) == L.LBM_EINVAL and "D2Q9 MIPS" in L.lbm_last_error()
     assert _sweep(L, [mips, good]) == L.LBM_EINVAL   # one model per batch
     # 16-bit storages: D2Q7 only, one storage per batch
     assert _sweep(L, [L.make_params(128, 128, L.LBM_CIL, storage=L.LBM_BF16_DEV, lattice=L.LBM_D2Q9)]) == \

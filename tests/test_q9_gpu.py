@@ -394,6 +394,28 @@ def test_full_size_4096(L, q9, orc, which):
     assert rel_err(got, ref) < 1e-6
 
 
+@pytest.mark.parametrize("tile_rows", [16, 8])
+def test_mips_4096_two_step_batch_equals_single(L, tile_rows):
+    """The square-lattice MIPS workload at 4096^2 through the batched path
+    with two steps per launch: five steps (two two-step launches, one
+    one-step launch) equal five lbm_step launches bit for bit, whose one-step
+    parity with the oracle is checked above."""
+    c = SI.q9_mips_4096()
+    ini = c.pop("init")
+    lat = L.Lattice(_gp(L, c), init=L.make_init(**ini))
+    torch.cuda.synchronize()
+    s0 = lat.state[:, :, : c["nx"]].clone()
+    lat.step(5)
+    torch.cuda.synchronize()
+    single = lat.state[:, :, : c["nx"]].clone()
+    lat.close()
+    b = L.Batch([_gp(L, c)])
+    b.set_state(0, s0)
+    b.run(5, tile_rows=tile_rows)
+    torch.cuda.synchronize()
+    assert torch.equal(b.state(0), single)
+
+
 # ---------------------------------------------------------------- batched sweeps
 
 def _q9_batch(model):
@@ -420,13 +442,16 @@ def _q9_states(L, cfgs):
 @pytest.mark.parametrize("model,tile_rows,use_graph,steps", [
     (SI.CIL, 1, 1, 37), (SI.CIL, 2, 0, 37), (SI.CIL, 4, 1, 37), (SI.CIL, 0, 1, 1100), (SI.PASSIVE, 0, 1, 37),
     (SI.CIL, 16, 1, 37), (SI.CIL, 8, 0, 38), (SI.PASSIVE, 16, 1, 39), (SI.CIL, 16, 1, 1100),
-    (SI.MIPS, 16, 1, 37), (SI.MIPS, 0, 0, 1100)])
+    (SI.MIPS, 16, 1, 37), (SI.MIPS, 16, 0, 38), (SI.MIPS, 8, 1, 37), (SI.MIPS, 8, 0, 2), (SI.MIPS, 0, 0, 1100),
+    (SI.MIPS, 16, 1, 1100)])
 def test_batch_member_equals_single_run(L, model, tile_rows, use_graph, steps):
     """D2Q9 batches run the single-lattice site and tile bodies: every member
     of lattices of uneven sizes (odd ny, narrower than a tile) equals its
     lbm_step run bit for bit, for every tile shape (one step per launch, or
-    two on 64 x 8 and 64 x 16 tiles with the first step widened into LDS),
-    with and without graphs, across a captured chunk (1100 steps)."""
+    two on 64 x 8 and 64 x 16 tiles with the first step widened into LDS: by
+    one site for the local models, by two, from densities on a ring of three,
+    for MIPS; odd step counts end with a one-step launch), with and without
+    graphs, across a captured chunk (1100 steps)."""
     cfgs = _q9_batch(model)
     states = _q9_states(L, cfgs)
     b = L.Batch([_gp(L, c) for c in cfgs])
@@ -573,7 +598,7 @@ def test_resident_samples_density_ramp_and_tuning(L):
     for l, f0 in enumerate(states):
         b.set_state(l, f0)
     b.run(200)
-    assert L.lbm_sweep_tile_rows(b.params, b.n) in (16, L.LBM_TILE_RESIDENT)
+    assert L.lbm_sweep_tile_rows(b.params, b.n) in (8, 16, L.LBM_TILE_RESIDENT)
     for l, c in enumerate(cfgs):
         lat = L.Lattice(_gp(L, c))
         lat.set_state(states[l])
