@@ -258,6 +258,7 @@ def test_mips_batch_member_equals_single_run(L, tile_rows, use_graph, steps):
 def test_mips_batch_samples_density_ramp_and_oracle(L, orc):
     """Samples every 10 steps with the protocol's density change after each,
     against single runs with lbm_add_density (bit for bit), and three steps
+    (one two-step launch and one one-step launch where the tile takes two)
     against the oracle."""
     cfgs = mips_batch()[2:5]
     states = mips_states(L, cfgs)
@@ -278,13 +279,14 @@ def test_mips_batch_samples_density_ramp_and_oracle(L, orc):
         lat.close()
         for o, s in zip(out[l], obs):
             assert abs(o["M"] - s["M"]) <= 1e-12 * s["M"] and abs(o["drho"] - s["drho"]) <= 1e-12
-    b2 = L.Batch([_gparams(L, c) for c in cfgs[:2]])
-    for l in range(2):
-        b2.set_state(l, states[l])
-    b2.run(3)
-    for l, c in enumerate(cfgs[:2]):
-        ref = orc.run(_oparams(orc, c), states[l].double().cpu().numpy(), 3)
-        assert rel_err(b2.state(l).double().cpu().numpy(), ref) < 3e-6
+    for rows in (0, 8, 16):  # tuned, and both two-step MIPS tiles against the oracle directly
+        b2 = L.Batch([_gparams(L, c) for c in cfgs[:2]])
+        for l in range(2):
+            b2.set_state(l, states[l])
+        b2.run(3, tile_rows=rows)
+        for l, c in enumerate(cfgs[:2]):
+            ref = orc.run(_oparams(orc, c), states[l].double().cpu().numpy(), 3)
+            assert rel_err(b2.state(l).double().cpu().numpy(), ref) < 3e-6, (rows, l)
 
 
 # ---------------------------------------------------------------- lattices resident in LDS

@@ -502,6 +502,22 @@ def test_batch_samples_density_ramp_and_oracle(L, q9, orc):
         assert rel_err(b2.state(l).double().cpu().numpy(), ref) < 3e-6
 
 
+@pytest.mark.parametrize("tile_rows", [8, 16])
+def test_mips_two_step_batch_against_oracle(L, q9, orc, tile_rows):
+    """The two-step MIPS kernel on the square lattice (lattices with odd ny,
+    narrower than a tile, and one with interior tiles): three steps (one
+    two-step launch, one one-step launch) against the D2Q9 oracle."""
+    cfgs = _q9_batch(SI.MIPS)[1:5]
+    states = _q9_states(L, cfgs)
+    b = L.Batch([_gp(L, c) for c in cfgs])
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    b.run(3, tile_rows=tile_rows)
+    for l, c in enumerate(cfgs):
+        ref = q9.run(_op(orc, c), states[l].double().cpu().numpy(), 3)
+        assert rel_err(b.state(l).double().cpu().numpy(), ref) < 3e-6, l
+
+
 @pytest.mark.parametrize("tile_rows", [16, 1])
 def test_batch_lattice_groups(L, tile_rows):
     """Five 1024 x 1024 square lattices (377 MB of state) run as two lattice
