@@ -198,7 +198,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t q9_plane_rsrc(const T *base, i
 // One site-update of the local models (passive, CIL) at (x, y): the nine
 // streamed populations gathered from their periodic sources, collided, and
 // stored at (x, y) in dst.  src and dst are [9][ny][pitch] population buffers.
-template <int M, int S, int F>
+template <int M, int S, int F, int CP = kStoreCached>
 __device__ __forceinline__ void q9_site_step(const typename Store<S>::T *src, typename Store<S>::T *dst,
                                              const StepArgs &a, int x, int y, uint32_t t_lo, uint32_t t_hi)
 {
@@ -215,7 +215,7 @@ __device__ __forceinline__ void q9_site_step(const typename Store<S>::T *src, ty
     q9_collide<F, S>(a, f, rho, ux, uy, (uint32_t)y * (uint32_t)a.nx + (uint32_t)x, t_lo, t_hi);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        BufIO<T>::store(q9_plane_rsrc(dst, i, plane), g.idx[0], 0u, Store<S>::narrow(f[i], q9_wr(a, i)));
+        BufIO<T>::template store<CP>(q9_plane_rsrc(dst, i, plane), g.idx[0], 0u, Store<S>::narrow(f[i], q9_wr(a, i)));
 }
 
 // ---------------------------------------------------------------------------
@@ -233,7 +233,7 @@ __device__ __forceinline__ void q9_site_step(const typename Store<S>::T *src, ty
 // ---------------------------------------------------------------------------
 constexpr int kQ9MipsRows = 16;
 
-template <int S, int F>
+template <int S, int F, int CP = kStoreCached>
 __device__ __forceinline__ void q9_mips_tile_step(const typename Store<S>::T *src, typename Store<S>::T *dst,
                                                   const StepArgs &a, int x0, int y0, uint32_t t_lo, uint32_t t_hi,
                                                   float *srho)
@@ -313,7 +313,7 @@ __device__ __forceinline__ void q9_mips_tile_step(const typename Store<S>::T *sr
         const uint32_t own = (uint32_t)y * P + (uint32_t)x;
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            BufIO<T>::store(q9_plane_rsrc(dst, i, plane), own, 0u, Store<S>::narrow(f[k][i], q9_wr(a, i)));
+            BufIO<T>::template store<CP>(q9_plane_rsrc(dst, i, plane), own, 0u, Store<S>::narrow(f[k][i], q9_wr(a, i)));
     }
 }
 

@@ -18,7 +18,7 @@ namespace lbm {
 // BX a multiple of 64, laid out in row groups so each row of tiles runs on
 // one XCD.
 // ---------------------------------------------------------------------------
-template <int M, int S, int F>
+template <int M, int S, int F, int CP>
 __global__ __launch_bounds__(256) void k_q9_step_local(const typename Store<S>::T *__restrict__ src,
                                                        typename Store<S>::T *__restrict__ dst, StepArgs a,
                                                        StepClock *__restrict__ clk, int slot)
@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void k_q9_step_local(const typename Store<S>::
     const int y = tyi * blockDim.y + threadIdx.y;
     if (x >= a.nx || y >= a.ny)
         return;
-    q9_site_step<M, S, F>(src, dst, a, x, y, t_lo, t_hi);
+    q9_site_step<M, S, F, CP>(src, dst, a, x, y, t_lo, t_hi);
     clock_advance(clk, slot, tt);
 }
 
@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_q9_step_local(const typename Store<S>::
 // MIPS: the 64 x 16 tile body (q9_mips_tile_step in device_q9.h) on a grid
 // in row groups.
 // ---------------------------------------------------------------------------
-template <int S, int F>
+template <int S, int F, int CP>
 __global__ __launch_bounds__(256) void k_q9_step_mips(const typename Store<S>::T *__restrict__ src,
                                                       typename Store<S>::T *__restrict__ dst, StepArgs a,
                                                       StepClock *__restrict__ clk, int slot)
@@ -52,16 +52,16 @@ __global__ __launch_bounds__(256) void k_q9_step_mips(const typename Store<S>::T
     const int x0 = txi * 64, y0 = tyi * kQ9MipsRows;
     if (y0 >= a.ny)  // padding tile rows of the last group: the whole block
         return;
-    q9_mips_tile_step<S, F>(src, dst, a, x0, y0, t_lo, t_hi, srho);
+    q9_mips_tile_step<S, F, CP>(src, dst, a, x0, y0, t_lo, t_hi, srho);
     clock_advance(clk, slot, tt);
 }
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int S, int F>
-static hipError_t launch_q9_sf(const lbm_params &p, const StepArgs &a, const void *src, void *dst, StepClock *clk, int slot,
-                               hipStream_t s)
+template <int S, int F, int CP>
+static hipError_t launch_q9_sfc(const lbm_params &p, const StepArgs &a, const void *src, void *dst, StepClock *clk,
+                                int slot, hipStream_t s)
 {
     using T = typename Store<S>::T;
     const T *in = (const T *)src;
@@ -69,7 +69,7 @@ static hipError_t launch_q9_sf(const lbm_params &p, const StepArgs &a, const voi
     if (p.model == kMips) {
         const int ntx = (p.nx + 63) / 64, nty = (p.ny + kQ9MipsRows - 1) / kQ9MipsRows;
         dim3 grd(8u * (unsigned)ntx, (unsigned)((nty + 7) / 8));
-        hipLaunchKernelGGL((k_q9_step_mips<S, F>), grd, dim3(256), 0, s, in, out, a, clk, slot);
+        hipLaunchKernelGGL((k_q9_step_mips<S, F, CP>), grd, dim3(256), 0, s, in, out, a, clk, slot);
         return hipGetLastError();
     }
     const int bx = p.nx >= 256 ? 256 : ((p.nx + 63) / 64) * 64;
@@ -77,10 +77,21 @@ static hipError_t launch_q9_sf(const lbm_params &p, const StepArgs &a, const voi
     const int ntx = (p.nx + blk.x - 1) / blk.x, nty = (p.ny + blk.y - 1) / blk.y;
     dim3 grd(8u * (unsigned)ntx, (unsigned)((nty + 7) / 8));
     if (p.model == kCil)
-        hipLaunchKernelGGL((k_q9_step_local<kCil, S, F>), grd, blk, 0, s, in, out, a, clk, slot);
+        hipLaunchKernelGGL((k_q9_step_local<kCil, S, F, CP>), grd, blk, 0, s, in, out, a, clk, slot);
     else
-        hipLaunchKernelGGL((k_q9_step_local<kPassive, S, F>), grd, blk, 0, s, in, out, a, clk, slot);
+        hipLaunchKernelGGL((k_q9_step_local<kPassive, S, F, CP>), grd, blk, 0, s, in, out, a, clk, slot);
     return hipGetLastError();
+}
+
+// stores stream past the caches when the two buffers cannot stay in the
+// Infinity Cache
+template <int S, int F>
+static hipError_t launch_q9_sf(const lbm_params &p, const StepArgs &a, const void *src, void *dst, StepClock *clk, int slot,
+                               hipStream_t s)
+{
+    if (2ull * 9ull * (uint64_t)a.plane * sizeof(typename Store<S>::T) > kStreamStateBytes)
+        return launch_q9_sfc<S, F, kStoreStream>(p, a, src, dst, clk, slot, s);
+    return launch_q9_sfc<S, F, kStoreCached>(p, a, src, dst, clk, slot, s);
 }
 
 template <int S>

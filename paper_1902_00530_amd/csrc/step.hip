@@ -21,7 +21,7 @@ namespace lbm {
 // the grid is laid out in row groups so each row of tiles runs on one XCD.
 // Offsets are 32-bit element indices from per-plane base pointers.
 // ---------------------------------------------------------------------------
-template <int M, int S, int F>
+template <int M, int S, int F, int CP>
 __global__ __launch_bounds__(256) void k_step_local(const typename Store<S>::T *__restrict__ src,
                                                     typename Store<S>::T *__restrict__ dst, StepArgs a,
                                                     StepClock *__restrict__ clk, int slot)
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_step_local(const typename Store<S>::T *
     const uint32_t own = g_src.idx[0];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        Planes<S>::store(rd, own, 0u, i, plane, f[i], a);
+        Planes<S>::template store<CP>(rd, own, 0u, i, plane, f[i], a);
     clock_advance(clk, slot, tt);
 }
 
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_step_mips64(const typename Store<S>::T 
 // arithmetic is the same).  Offsets are 32-bit (7 planes below 2^30
 // elements); larger lattices take k_step_mips64.
 // ---------------------------------------------------------------------------
-template <int S, int F, int ROWS, int NW = 4>
+template <int S, int F, int ROWS, int NW, int CP>
 __global__ __launch_bounds__(64 * NW) void k_step_mips(const typename Store<S>::T *__restrict__ src,
                                                    typename Store<S>::T *__restrict__ dst, StepArgs a,
                                                    StepClock *__restrict__ clk, int slot)
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(64 * NW) void k_step_mips(const typename Store<S>::
     if (y0 >= a.ny)  // padding tile rows of the last group: the whole block
         return;
     const uint32_t bytes = (uint32_t)Planes<S>::bytes(a.plane);  // < 2^32: 7 planes < 2^30 elements
-    mips_tile_step<S, F, ROWS, NW>(buffer_rsrc(src, bytes), buffer_rsrc(dst, bytes), a, x0, y0, t_lo, t_hi, srho);
+    mips_tile_step<S, F, ROWS, NW, CP>(buffer_rsrc(src, bytes), buffer_rsrc(dst, bytes), a, x0, y0, t_lo, t_hi, srho);
     clock_advance(clk, slot, tt);
 }
 
@@ -212,9 +212,9 @@ static dim3 local_block(int nx)
 
 static bool fits32(const StepArgs &a) { return (uint64_t)a.plane * 7ull < (1ull << 30); }
 
-template <int S, int F>
-static hipError_t launch_step_sf(const lbm_params &p, const StepArgs &a, const void *src, void *dst, StepClock *clk, int slot,
-                                 hipStream_t s)
+template <int S, int F, int CP>
+static hipError_t launch_step_sfc(const lbm_params &p, const StepArgs &a, const void *src, void *dst, StepClock *clk,
+                                  int slot, hipStream_t s)
 {
     using T = typename Store<S>::T;
     const T *in = (const T *)src;
@@ -225,11 +225,11 @@ static hipError_t launch_step_sf(const lbm_params &p, const StepArgs &a, const v
             if ((int64_t)ntx * nty < kMipsSmallTiles) {
                 const int nty4 = (p.ny + 3) / 4;
                 dim3 grd(8u * (unsigned)ntx, (unsigned)((nty4 + 7) / 8));
-                hipLaunchKernelGGL((k_step_mips<S, F, 4>), grd, dim3(256), 0, s, in, out, a, clk, slot);
+                hipLaunchKernelGGL((k_step_mips<S, F, 4, 4, CP>), grd, dim3(256), 0, s, in, out, a, clk, slot);
             } else {
                 dim3 grd(8u * (unsigned)ntx, (unsigned)((nty + 7) / 8));
-                hipLaunchKernelGGL((k_step_mips<S, F, kMipsRows, kMipsWaves>), grd, dim3(64 * kMipsWaves), 0, s, in,
-                                   out, a, clk, slot);
+                hipLaunchKernelGGL((k_step_mips<S, F, kMipsRows, kMipsWaves, CP>), grd, dim3(64 * kMipsWaves), 0, s,
+                                   in, out, a, clk, slot);
             }
         } else {
             dim3 blk(kMipsTX, kMipsTY), grd((p.nx + kMipsTX - 1) / kMipsTX, (p.ny + kMipsTY - 1) / kMipsTY);
@@ -242,9 +242,9 @@ static hipError_t launch_step_sf(const lbm_params &p, const StepArgs &a, const v
     if (fits32(a)) {
         dim3 grd(8u * (unsigned)ntx, (unsigned)((nty + 7) / 8));
         if (p.model == kCil)
-            hipLaunchKernelGGL((k_step_local<kCil, S, F>), grd, blk, 0, s, in, out, a, clk, slot);
+            hipLaunchKernelGGL((k_step_local<kCil, S, F, CP>), grd, blk, 0, s, in, out, a, clk, slot);
         else
-            hipLaunchKernelGGL((k_step_local<kPassive, S, F>), grd, blk, 0, s, in, out, a, clk, slot);
+            hipLaunchKernelGGL((k_step_local<kPassive, S, F, CP>), grd, blk, 0, s, in, out, a, clk, slot);
     } else {
         dim3 grd(ntx, nty);
         if (p.model == kCil)
@@ -253,6 +253,18 @@ static hipError_t launch_step_sf(const lbm_params &p, const StepArgs &a, const v
             hipLaunchKernelGGL((k_step_local64<kPassive, S, F>), grd, blk, 0, s, in, out, a, clk, slot);
     }
     return hipGetLastError();
+}
+
+// stores stream past the caches when the two buffers cannot stay in the
+// Infinity Cache (the lattices beyond 2^30 elements take the 64-bit kernels,
+// whose stores stay cached)
+template <int S, int F>
+static hipError_t launch_step_sf(const lbm_params &p, const StepArgs &a, const void *src, void *dst, StepClock *clk, int slot,
+                                 hipStream_t s)
+{
+    if (2ull * Planes<S>::bytes(a.plane) > kStreamStateBytes)
+        return launch_step_sfc<S, F, kStoreStream>(p, a, src, dst, clk, slot, s);
+    return launch_step_sfc<S, F, kStoreCached>(p, a, src, dst, clk, slot, s);
 }
 
 int step_flags(const StepArgs &a) { return (a.omega == 1.0f ? kUnitTau : 0) | (a.noisy ? kNoisy : 0); }
