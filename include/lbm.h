@@ -194,7 +194,9 @@ int32_t lbm_create(const lbm_params *p, void *f_a, void *f_b, int64_t pitch, con
  * launch reads its step index (the noise counter) from the workspace's step
  * clock, so graphs replay with unchanged arguments.  The state alternates
  * between the two buffers; lbm_current_buffer() tells which holds it
- * afterwards. */
+ * afterwards.  Where the two buffers together exceed 240 MiB (more than the
+ * 256 MB Infinity Cache keeps) the steps' stores are non-temporal; the values
+ * are the same either way. */
 int32_t lbm_step(lbm_ctx *c, int64_t n);
 
 /* Fields and observables of the stored state.  rho, ux, uy: caller-owned
