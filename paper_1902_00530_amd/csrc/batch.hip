@@ -59,7 +59,42 @@ struct LatDesc {
     int64_t col_off;    // offset of this lattice's column partials
     int64_t cm_off;     // offset of this lattice's column means
     float add;          // added to every population after each sample (drho / Q)
+    int32_t stream;     // 1: stores streamed past the caches (two buffers beyond the
+                        // Infinity Cache budget: the lattice is a group of its own)
 };
+
+// A batch kernel's population stores at element v + s of each plane:
+// streamed past the caches for a lattice flagged LatDesc::stream (uniform per
+// block), cached otherwise, where the next launch or a later lattice group
+// reads them from the Infinity Cache.
+template <int ST>
+__device__ __forceinline__ void batch_store7(bool stream, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s,
+                                             uint32_t plane, const float f[7], const StepArgs &a)
+{
+    if (stream) {
+#pragma unroll
+        for (int i = 0; i < 7; ++i)
+            Planes<ST>::template store<kStoreStream>(r, v, s, i, plane, f[i], a);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 7; ++i)
+            Planes<ST>::store(r, v, s, i, plane, f[i], a);
+    }
+}
+
+__device__ __forceinline__ void batch_store9(bool stream, float *dst, uint32_t plane, uint32_t v, uint32_t s,
+                                             const float f[9])
+{
+    if (stream) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            BufIO<float>::store<kStoreStream>(q9_plane_rsrc(dst, i, plane), v, s, f[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            BufIO<float>::store(q9_plane_rsrc(dst, i, plane), v, s, f[i]);
+    }
+}
 
 struct MomTile {
     int32_t lat;
@@ -107,9 +142,7 @@ __global__ __launch_bounds__(256) void k_batch_step(const BatchTile *__restrict_
     // batch buffers have pitch nx, so the own offset is the site index
     const uint32_t own = g_src.idx[0];
     site_collide<F, ST>(a, f, rho, ux, uy, own, (uint32_t)((uint64_t)t & 0xffffffffu), (uint32_t)((uint64_t)t >> 32));
-#pragma unroll
-    for (int i = 0; i < 7; ++i)
-        Planes<ST>::store(dst, own, 0u, i, plane, f[i], a);
+    batch_store7<ST>(L.stream != 0, dst, own, 0u, plane, f, a);
 }
 
 // MIPS over a list of 64 x ROWS tiles (the tile body of the single-lattice
@@ -424,6 +457,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_q9_step2(const BatchTile *__r
     const uint32_t tb_lo = (uint32_t)((uint64_t)t1 & 0xffffffffu), tb_hi = (uint32_t)((uint64_t)t1 >> 32);
     // sources two sites around the tile do not wrap: wave-uniform row bases
     const bool interior = x0 >= 2 && x0 + 66 <= a.nx && y0 >= 2 && y0 + TY + 2 <= a.ny;
+    const bool stream = L.stream != 0;
 
     // first step on the widened tile, from HBM into LDS (wave w: rows w,
     // w+NW, ...; waves 2 and up take the two edge columns in their last slot)
@@ -508,9 +542,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_q9_step2(const BatchTile *__r
         local_ustar<M>(a, rho, jx, jy, ux, uy);
         const uint32_t row = (uint32_t)(y0 + r) * nx + (uint32_t)x0;  // pitch nx
         q9_collide<F>(a, g, rho, ux, uy, row + (uint32_t)lane, tb_lo, tb_hi);
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            BufIO<float>::store(q9_plane_rsrc(dst, i, plane), lane, row, g[i]);
+        batch_store9(stream, dst, plane, (uint32_t)lane, row, g);
     };
     if (interior) {
         for (int r = wv; r < TY; r += NW)
@@ -582,6 +614,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
     // A tile whose sources (two sites around it) do not wrap: every offset is
     // a wave-uniform row base plus the lane.
     const bool interior = x0 >= 2 && x0 + 66 <= a.nx && y0 >= 2 && y0 + TY + 2 <= a.ny;
+    const bool stream = L.stream != 0;
 
     // First step on the widened tile, from HBM into LDS.  Wave w takes rows
     // w, w+NW, ... of the H rows; waves 2 and up own one row fewer (H = 2 mod
@@ -676,9 +709,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2(const BatchTile *__rest
         local_ustar<M>(a, rho, jx, jy, ux, uy);
         const uint32_t row = (uint32_t)(y0 + r) * nx + (uint32_t)x0;  // pitch nx
         site_collide<F, ST>(a, f, rho, ux, uy, row + (uint32_t)lane, tb_lo, tb_hi);
-#pragma unroll
-        for (int i = 0; i < 7; ++i)
-            Planes<ST>::store(dst, lane, row, i, plane, f[i], a);
+        batch_store7<ST>(stream, dst, (uint32_t)lane, row, plane, f, a);
     };
     if (interior) {
         for (int r = wv; r < TY; r += NW)
@@ -810,11 +841,9 @@ struct Mips2Q7 {  // offset-row triangular lattice, any storage
         g[5] = mid[5 * NB + m + WB + p];
         g[6] = mid[6 * NB + m + WB - 1 + p];
     }
-    __device__ void store(uint32_t row, int lane, const float *g) const
+    __device__ void store(bool stream, uint32_t row, int lane, const float *g) const
     {
-#pragma unroll
-        for (int i = 0; i < 7; ++i)
-            Planes<ST>::store(dst, (uint32_t)lane, row, i, plane, g[i], a);
+        batch_store7<ST>(stream, dst, (uint32_t)lane, row, plane, g, a);
     }
 };
 
@@ -885,11 +914,9 @@ struct Mips2Q9 {  // square lattice, float32 storage; one buffer resource per pl
         g[7] = mid[7 * NB + m + WB + 1];
         g[8] = mid[8 * NB + m + WB - 1];
     }
-    __device__ void store(uint32_t row, int lane, const float *g) const
+    __device__ void store(bool stream, uint32_t row, int lane, const float *g) const
     {
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            BufIO<float>::store(q9_plane_rsrc(dstp, i, plane), (uint32_t)lane, row, g[i]);
+        batch_store9(stream, dstp, plane, (uint32_t)lane, row, g);
     }
 };
 
@@ -1021,7 +1048,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_step2_mips(const BatchTile *_
         lp.template ustar<ML::WC>(rs, (r + 1) * ML::WC + lane + 1, r & 1, rh, ux, uy);
         const uint32_t row = (uint32_t)y * nx + (uint32_t)x0;  // pitch nx
         lp.template collide<F>(g, rh, ux, uy, row + (uint32_t)lane, tb_lo, tb_hi);
-        lp.store(row, lane, g);
+        lp.store(L.stream != 0, row, lane, g);
     }
 }
 
@@ -1292,16 +1319,22 @@ static int64_t count_tiles(const lbm_params *ps, int n, int tx, int ty)
 // consecutive lattices of about equal bytes.
 constexpr uint64_t kCacheGroupBytes = 240ull << 20;
 
+// bytes of a lattice's two population buffers (pitch nx)
+static uint64_t state_bytes(const lbm_params &p)
+{
+    const uint64_t per_site = p.lattice == LBM_D2Q9 ? (p.storage == LBM_F32 ? 36ull : 18ull)
+                              : p.storage == LBM_F32        ? 28ull
+                              : p.storage == LBM_BF16_DEV_R32 ? 16ull
+                                                              : 14ull;
+    return 2ull * per_site * (uint64_t)p.nx * p.ny;
+}
+
 static std::vector<int> cache_groups(const lbm_params *ps, int n)
 {
     std::vector<uint64_t> b(n);
     uint64_t total = 0;
     for (int l = 0; l < n; ++l) {
-        const uint64_t per_site = ps[l].lattice == LBM_D2Q9 ? (ps[l].storage == LBM_F32 ? 36ull : 18ull)
-                                  : ps[l].storage == LBM_F32        ? 28ull
-                                  : ps[l].storage == LBM_BF16_DEV_R32 ? 16ull
-                                                                      : 14ull;
-        b[l] = 2ull * per_site * (uint64_t)ps[l].nx * ps[l].ny;
+        b[l] = state_bytes(ps[l]);
         total += b[l];
     }
     const uint64_t ng = (total + kCacheGroupBytes - 1) / kCacheGroupBytes;
@@ -1681,7 +1714,7 @@ static bool same_args(const StepArgs &x, const StepArgs &y)
 static bool same_desc(const LatDesc &x, const LatDesc &y)
 {
     return same_args(x.a, y.a) && LBM_SAME(buf) && LBM_SAME(B) && LBM_SAME(mt_begin) && LBM_SAME(mt_count) &&
-           LBM_SAME(nrb) && LBM_SAME(col_off) && LBM_SAME(cm_off) && LBM_SAME(add);
+           LBM_SAME(nrb) && LBM_SAME(col_off) && LBM_SAME(cm_off) && LBM_SAME(add) && LBM_SAME(stream);
 }
 #undef LBM_SAME
 
@@ -1849,6 +1882,7 @@ int32_t lbm_sweep_batch(const lbm_params *ps, int32_t n, const lbm_sweep_opts *o
         D.buf[1] = bufs[2 * l + 1];
         D.B = (float)ps[l].B;
         D.add = o->drho ? (float)(o->drho[l] / (ps[l].lattice == LBM_D2Q9 ? 9.0 : 7.0)) : 0.0f;
+        D.stream = state_bytes(ps[l]) > kCacheGroupBytes ? 1 : 0;
         const int cx = (ps[l].nx + 255) / 256, cy = (ps[l].ny + kMomRows - 1) / kMomRows;
         D.mt_begin = (int32_t)nmt;
         D.mt_count = cx * cy;
