@@ -497,10 +497,10 @@ def main():
         ms, obs = time_single(L, torch, cfgs, args.steps, args.warmup, args.storage, lattice)
         st = {0: "F32", 1: "BF16dev", 2: "F16dev", 3: "BF16devR32"}[args.storage]
         launches = args.steps * len(cfgs)
-        kernel = {"q9_cil4096": f"k_q9_step_local<CIL,{st},unit-tau,noisy>",
-                  "q9_mips4096": f"k_q9_step_mips<{st},noisy>",
-                  "mips4096": f"k_step_mips<{st},noisy,16,8>"}.get(args.workload,
-                                                                     f"k_step_local<CIL,{st},unit-tau,noisy>")
+        kernel = {"q9_cil4096": f"k_q9_step_local<CIL,{st},unit-tau,noisy,streamed stores>",
+                  "q9_mips4096": f"k_q9_step_mips<{st},noisy,streamed stores>",
+                  "mips4096": f"k_step_mips<{st},noisy,16,8,streamed stores>"}.get(
+                      args.workload, f"k_step_local<CIL,{st},unit-tau,noisy,streamed stores>")
     wall = time.perf_counter() - t_wall
     per_launch = ms / 1e3 / launches
     mlups = sites * args.steps / (ms / 1e3) / 1e6
@@ -584,7 +584,7 @@ def main():
         for st, name in ((0, "f32"), (1, "bf16_dev"), (2, "f16_dev"), (3, "bf16_dev_r32")):
             msb, _ = time_single(L, torch, big, 200, 10, st)
             per = msb / 1e3 / 200
-            r = roofline(st, nbig, per, f"k_step_local<CIL,{name}>")
+            r = roofline(st, nbig, per, f"k_step_local<CIL,{name},streamed stores>")
             v = {"MLUPS": round(nbig / per / 1e6, 1), "GBps": r["achieved"], "frac_hbm": r["frac"],
                  "avg_launch_us": r["avg_launch_us"]}
             if st == 0:
@@ -616,7 +616,7 @@ def main():
                                     "note": "4,096 sites: one launch per step, launch-bound"}
         mbig = dict(mcfg, nx=4096, ny=4096)
         msb, _ = time_single(L, torch, [mbig], 100, 10)
-        rm = roofline(0, 4096 * 4096, msb / 1e3 / 100, "k_step_mips<F32,noisy,16,8>")
+        rm = roofline(0, 4096 * 4096, msb / 1e3 / 100, "k_step_mips<F32,noisy,16,8,streamed stores>")
         attach_traffic(rm, "counters_k_step_mips_4096.json", STEP_SOURCES, 4096 * 4096, msb / 1e3 / 100)
         var["mips4096_f32"] = {"MLUPS": round(4096 * 4096 * 100 / (msb / 1e3) / 1e6, 1), "GBps": rm["achieved"],
                                "frac_hbm": rm["frac"], "avg_launch_us": rm["avg_launch_us"],
@@ -635,7 +635,7 @@ def main():
         for st, name in ((0, "f32"), (1, "bf16_dev"), (2, "f16_dev")):
             msq, _ = time_single(L, torch, q9c, 200, 10, st, lattice=L.LBM_D2Q9)
             per = msq / 1e3 / 200
-            r = roofline(st, nbig, per, f"k_q9_step_local<CIL,{name}>", q=9)
+            r = roofline(st, nbig, per, f"k_q9_step_local<CIL,{name},streamed stores>", q=9)
             v = {"MLUPS": round(nbig / per / 1e6, 1), "GBps": r["achieved"], "frac_hbm": r["frac"],
                  "avg_launch_us": r["avg_launch_us"], "bytes_per_site": r["bytes_per_site"]}
             if st == 0:
@@ -654,7 +654,7 @@ def main():
                                           "tile_rows": time_batch.tile_rows,
                                           "speedup_vs_f32_one_step": round(q9f32 / (msq2 / 1e3 / 200), 3)}
         msq, _ = time_single(L, torch, [SI.q9_mips_4096()], 100, 10, lattice=L.LBM_D2Q9)
-        rq = roofline(0, nbig, msq / 1e3 / 100, "k_q9_step_mips<F32,noisy>", q=9)
+        rq = roofline(0, nbig, msq / 1e3 / 100, "k_q9_step_mips<F32,noisy,streamed stores>", q=9)
         var["q9_mips4096_f32"] = {"MLUPS": round(nbig * 100 / (msq / 1e3) / 1e6, 1), "GBps": rq["achieved"],
                                   "frac_hbm": rq["frac"], "avg_launch_us": rq["avg_launch_us"]}
         msq2m, _ = time_batch(L, torch, [SI.q9_mips_4096()], 100, 10, lattice=L.LBM_D2Q9)
