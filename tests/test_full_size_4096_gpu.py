@@ -173,3 +173,32 @@ def test_mips_4096_two_step_batch_equals_single(L, tile_rows):
     b.run(5, tile_rows=tile_rows)
     torch.cuda.synchronize()
     assert torch.equal(b.state(0), single)
+
+
+def test_batch_mixing_streamed_and_cached_stores(L):
+    """One 4096^2 lattice (its two buffers exceed the Infinity Cache budget:
+    a lattice group of its own, stores streamed past the caches) batched with
+    two small lattices (cached stores): five steps with two steps
+    per launch, each member equal bit for bit to its lbm_step run."""
+    big = SI.cil_4096()
+    cfgs = [big, dict(big, nx=200, ny=70, seed=SI.seed_for(21)), dict(big, nx=130, ny=34, seed=SI.seed_for(22))]
+    inits = [c.pop("init") for c in cfgs]
+    params = [_gparams(L, c) for c in cfgs]
+    arr = (L.lbm_params * 3)(*params)
+    assert L.lbm_sweep_groups(arr, 3) >= 2  # the big lattice in a group of its own
+    states, singles = [], []
+    for c, p, ini in zip(cfgs, params, inits):
+        lat = L.Lattice(p, init=L.make_init(**ini))
+        torch.cuda.synchronize()
+        states.append(lat.state[:, :, : c["nx"]].clone())
+        lat.step(5)
+        torch.cuda.synchronize()
+        singles.append(lat.state[:, :, : c["nx"]].clone())
+        lat.close()
+    b = L.Batch(params)
+    for l, f0 in enumerate(states):
+        b.set_state(l, f0)
+    b.run(5, tile_rows=16)
+    torch.cuda.synchronize()
+    for l in range(3):
+        assert torch.equal(b.state(l), singles[l]), l
